@@ -1,0 +1,153 @@
+/*
+ * hbi.h -- C ABI of the butterfly-compressed Hadamard-Babich (HB) volume
+ * integrator on AMD Instinct MI355X (gfx950).
+ *
+ * The library applies the discretised HB integrator U = K^{v2v} I of the
+ * paper's Sec. 3.1 (eq. m_v2v): N_v cells of size h on a regular grid, the
+ * source vector I_j = s(r_j) h^d, and the operator entries
+ *   K_ij = v0 f_{-(d-2)/2}(omega, tau) + v1 f_{1-(d-2)/2}(omega, tau),  i != j
+ * (eq. babich with N = 1 and the terms of eq. termf), with tau^2, v0, v1
+ * taken from Chebyshev-interpolated tables (eq. chebinterp,
+ * eq. chebinterpblock) and K_ii the cell integral of the leading HB term
+ * (Appendix A).  K is compressed as a hierarchically off-diagonal butterfly
+ * (HODBF) matrix (Sec. 3.2): a K-D cluster tree, one column-wise butterfly
+ * per pair of sibling clusters (eq. butterfly_mat, eq. butterfly_factors)
+ * built level by level from interpolative decompositions of proxy-row
+ * blocks (eq. ID, eq. proxy, eq. proxyv2v), and dense diagonal leaf blocks.
+ *
+ * Conventions shared by every call:
+ *  * Every function returns hbi_status; nothing throws across the ABI.  On
+ *    failure hbi_last_error(ctx) (or hbi_last_error(NULL) when no context
+ *    exists) gives a human-readable reason.
+ *  * Cells are numbered naturally: i = x + ncell[0] * (y + ncell[1] * z).
+ *    Cell (x, y, z) has centre origin + (idx + 0.5) * h.
+ *  * Complex arrays are interleaved (re, im): complex128 for HBI_F64,
+ *    complex64 for HBI_F32.
+ *  * Device arrays are HIP device pointers on the context's device (for
+ *    instance torch.Tensor.data_ptr()).  Host arrays are ordinary memory.
+ */
+#ifndef HBI_H
+#define HBI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hbi_ctx hbi_ctx;
+
+typedef enum {
+  HBI_OK = 0,
+  HBI_ERR_ARG = 1,      /* bad shape, null pointer, out-of-range value   */
+  HBI_ERR_STATE = 2,    /* call out of order (apply before build, ...)   */
+  HBI_ERR_OOM = 3,      /* device or host allocation failed              */
+  HBI_ERR_HIP = 4,      /* a HIP runtime call failed (text in last_error) */
+  HBI_ERR_NUMERIC = 5   /* non-finite value met where one is not allowed  */
+} hbi_status;
+
+typedef enum { HBI_F64 = 0, HBI_F32 = 1 } hbi_prec;
+
+/* Problem statement and tabulated HB ingredients (Sec. 3.1 and the
+ * tabulation of eq. chebinterp).
+ *
+ * Table layout: the table region is nbox[0] x nbox[1] (x nbox[2]) cubic
+ * boxes of side box_size from box_origin; box b = bx + nbox0*(by + nbox1*bz).
+ * Each box carries nI first-kind Chebyshev nodes per axis at
+ * lo + box_size*(1 + cos((2k+1)pi/(2 nI)))/2, k = 0..nI-1, node multi-index
+ * a = k1 + nI*(k2 + nI*k3); global node A = b*nI^d + a, NT = nboxes*nI^d.
+ * tau2, v0, v1 are NT x NT row-major: F[A*NT + B] = f(node A as observation
+ * point, node B as source).  A point is interpolated with the nodes of the
+ * box floor((x - box_origin)/box_size) (clamped), so cells must lie inside
+ * the table region.  With nbox = {1,1,1} this is the paper's global table. */
+typedef struct {
+  int32_t dim;            /* 2 or 3                                        */
+  int32_t ncell[3];       /* cells per axis (unused axes ignored)          */
+  double origin[3];       /* lower corner of the cell grid                 */
+  double h;               /* cell size (> 0)                               */
+  double omega;           /* angular frequency (> 0)                       */
+  int32_t nterms;         /* 1 (N = 0: v0 only) or 2 (N = 1: v0 and v1)    */
+  int32_t nI;             /* Chebyshev nodes per axis per box, 2..16       */
+  int32_t nbox[3];        /* table boxes per axis (>= 1)                   */
+  double box_origin[3];
+  double box_size;        /* > 0                                           */
+  const double *tau2;     /* host [NT*NT]                                  */
+  const double *v0;       /* host [NT*NT]                                  */
+  const double *v1;       /* host [NT*NT]; may be NULL iff nterms == 1     */
+  const double *slowness; /* host [N_v], n(r_i) at cell centres, natural
+                             order (used by the self terms, Appendix A)    */
+} hbi_tables;
+
+/* Compression parameters (Sec. 3.2.2 and the parameter choices of
+ * Sec. 5.1).  Zero / negative fields select the default in brackets. */
+typedef struct {
+  double chi;               /* proxy oversampling factor chi of eq. proxyv2v
+                               [20 in 2D, 4 in 3D]                          */
+  int32_t leaf_size;        /* max cells per leaf cluster [64]               */
+  double neighbor_radius;   /* radius of the neighbour proxy rows n_i, in
+                               cells [10 in 2D, 3 in 3D]                    */
+  int32_t band_width;       /* width in cells of the boundary band that the
+                               uniform proxy rows f_tau are drawn from [2]   */
+  int64_t workspace_bytes;  /* device workspace per build batch [2 GiB]      */
+} hbi_build_opts;
+
+/* Create a context on HIP device `device`; all work is queued on
+ * `hip_stream` (a hipStream_t, NULL = the null stream).  *out receives the
+ * context, owned by the caller until hbi_destroy. */
+hbi_status hbi_create(int device, void *hip_stream, hbi_ctx **out);
+
+/* Free the context and every device allocation it owns.  NULL is a no-op. */
+hbi_status hbi_destroy(hbi_ctx *ctx);
+
+/* Change the stream later applies are queued on. */
+hbi_status hbi_set_stream(hbi_ctx *ctx, void *hip_stream);
+
+/* Deep-copy the problem statement and the tables to the device and build the
+ * cluster tree.  The caller keeps ownership of t and its arrays.  Drops any
+ * earlier factors.  Synchronous. */
+hbi_status hbi_load_tables(hbi_ctx *ctx, const hbi_tables *t);
+
+/* Override compression parameters for later builds (NULL restores the
+ * defaults). */
+hbi_status hbi_set_build_opts(hbi_ctx *ctx, const hbi_build_opts *opts);
+
+/* Build the HODBF factors (Sec. 3.2): interpolative decompositions by
+ * column-pivoted QR with relative tolerance `tol` (eq. ID: a pivot is kept
+ * while |R_kk| > tol |R_11|), in FP64.  `prec` selects the precision the
+ * factors are stored and applied in (HBI_F32 rounds the FP64 factors).
+ * Needs loaded tables; replaces earlier factors.  Synchronous. */
+hbi_status hbi_build(hbi_ctx *ctx, double tol, hbi_prec prec);
+
+/* u = K (h^d s) (eq. m_v2v) for nrhs right-hand sides.  s and u are device
+ * arrays, column-major N_v x nrhs with leading dimension ld >= N_v, natural
+ * cell order, complex128 (HBI_F64 build) or complex64 (HBI_F32 build); they
+ * must not overlap.  Asynchronous on the context's stream. */
+hbi_status hbi_apply(hbi_ctx *ctx, const void *s, void *u, int32_t nrhs,
+                     int64_t ld);
+
+/* u = h^d K^H s: the exact conjugate transpose of the compressed operator
+ * applied by hbi_apply (same layout rules).  With L(s) = ||P K h^d s - d||^2
+ * the gradient with respect to conj(s) is h^d K^H P^T (P K h^d s - d). */
+hbi_status hbi_apply_adjoint(hbi_ctx *ctx, const void *s, void *u,
+                             int32_t nrhs, int64_t ld);
+
+/* hb_entry on its own: out[i + m*j] = K[rows[i], cols[j]] (natural cell
+ * indices, host int32 arrays) as complex128 into the device array `out`
+ * (column-major m x n), including the self term where rows[i] == cols[j].
+ * Needs loaded tables.  Synchronous. */
+hbi_status hbi_entries(hbi_ctx *ctx, const int32_t *rows, int32_t m,
+                       const int32_t *cols, int32_t n, void *out);
+
+/* JSON description of the context into json[0..cap): sizes, ranks, stored
+ * factor entries and bytes, build timings.  Fails with HBI_ERR_ARG when cap
+ * is too small. */
+hbi_status hbi_get_info(const hbi_ctx *ctx, char *json, int64_t cap);
+
+/* Text of the last error on ctx (or of the last context-free error when ctx
+ * is NULL).  Valid until the next call on the same context. */
+const char *hbi_last_error(const hbi_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HBI_H */

@@ -1,0 +1,203 @@
+"""MI355X-native butterfly-compressed Hadamard-Babich (HB) integrator.
+
+Python face of libhbi.so (include/hbi.h).  PyTorch provides device memory and
+streams; every step of entry evaluation, compression and application runs in
+the library's HIP kernels.
+
+    op = Operator(problem, device=0)          # problem statement + tables
+    op.build(tol=1e-7, prec="f64")            # HODBF factors (Sec. 3.2)
+    u = op.apply(s)                           # u = K (h^d s)    (eq. m_v2v)
+    g = op.apply_adjoint(r)                   # g = h^d K^H r
+    u = HBApply.apply(op, s)                  # differentiable in s
+
+``problem`` is any object with the attributes dim, ncell, origin, h, omega,
+nterms, nI, nbox, box_origin, box_size, tau2, v0, v1, slowness (see
+hbi_tables in include/hbi.h for their meaning and layout).
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+
+import numpy as np
+
+from . import _lib
+from ._lib import HBIError, HBI_F32, HBI_F64
+
+__all__ = ["Operator", "HBApply", "HBIError", "load_library"]
+
+
+def load_library():
+    return _lib.load()
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Operator:
+    def __init__(self, problem, device: int = 0, stream=None):
+        import torch
+        self._lib = _lib.load()
+        self.device = torch.device("cuda", device)
+        self.dim = int(problem.dim)
+        self.ncell = tuple(int(c) for c in problem.ncell[: self.dim])
+        self.Nv = int(np.prod(self.ncell))
+        self.h = float(problem.h)
+        self.prec = None
+        ctx = ctypes.c_void_p()
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        _lib.check(self._lib.hbi_create(device, ctypes.c_void_p(st), ctypes.byref(ctx)))
+        self._ctx = ctx
+        self._keep = []
+        self.load(problem)
+
+    # -- marshalling helpers -------------------------------------------------
+    def _check(self, status):
+        _lib.check(status, self._ctx)
+
+    def load(self, p):
+        t = _lib.hbi_tables()
+        t.dim = self.dim
+        for a in range(3):
+            t.ncell[a] = int(p.ncell[a]) if a < self.dim else 1
+            t.origin[a] = float(p.origin[a]) if a < self.dim else 0.0
+            t.nbox[a] = int(p.nbox[a]) if a < self.dim else 1
+            t.box_origin[a] = float(p.box_origin[a]) if a < self.dim else 0.0
+        t.h = float(p.h)
+        t.omega = float(p.omega)
+        t.nterms = int(p.nterms)
+        t.nI = int(p.nI)
+        t.box_size = float(p.box_size)
+        arrs = [np.ascontiguousarray(p.tau2, dtype=np.float64),
+                np.ascontiguousarray(p.v0, dtype=np.float64),
+                None if p.v1 is None else np.ascontiguousarray(p.v1, dtype=np.float64),
+                np.ascontiguousarray(p.slowness, dtype=np.float64)]
+        t.tau2 = _dptr(arrs[0])
+        t.v0 = _dptr(arrs[1])
+        t.v1 = _dptr(arrs[2]) if arrs[2] is not None else ctypes.POINTER(ctypes.c_double)()
+        t.slowness = _dptr(arrs[3])
+        self._check(self._lib.hbi_load_tables(self._ctx, ctypes.byref(t)))
+        self.prec = None
+
+    def set_stream(self, stream=None):
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        self._check(self._lib.hbi_set_stream(self._ctx, ctypes.c_void_p(st)))
+
+    def build(self, tol: float = 1e-7, prec: str = "f64", chi=None, leaf_size=None,
+              neighbor_radius=None, band_width=None, workspace_bytes=None):
+        o = _lib.hbi_build_opts()
+        o.chi = float(chi or 0.0)
+        o.leaf_size = int(leaf_size or 0)
+        o.neighbor_radius = float(neighbor_radius or 0.0)
+        o.band_width = int(band_width or 0)
+        o.workspace_bytes = int(workspace_bytes or 0)
+        self._check(self._lib.hbi_set_build_opts(self._ctx, ctypes.byref(o)))
+        p = {"f64": HBI_F64, "f32": HBI_F32}[prec]
+        self.set_stream()
+        self._check(self._lib.hbi_build(self._ctx, float(tol), p))
+        self.prec = prec
+        return self
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.complex128 if self.prec == "f64" else torch.complex64
+
+    def _prep(self, s):
+        import torch
+        if self.prec is None:
+            raise HBIError(_lib.HBI_ERR_STATE, "apply before build")
+        if s.device != self.device:
+            raise ValueError(f"input on {s.device}, operator on {self.device}")
+        if s.dtype != self.dtype:
+            raise TypeError(f"expected {self.dtype}, got {s.dtype}")
+        vec = s.dim() == 1
+        S = s.reshape(self.Nv, -1) if vec else s
+        if S.shape[0] != self.Nv:
+            raise ValueError(f"expected {self.Nv} rows, got {S.shape[0]}")
+        # column-major N_v x nrhs: a row-major (nrhs, N_v) buffer transposed
+        if not (S.stride(0) == 1 and (S.shape[1] == 1 or S.stride(1) >= self.Nv)):
+            S = S.t().contiguous().t()
+        return S, vec
+
+    def _run(self, fn, s, out=None):
+        import torch
+        S, vec = self._prep(s)
+        nrhs = S.shape[1]
+        ld = S.stride(1) if nrhs > 1 else self.Nv
+        U = torch.empty((nrhs, self.Nv), dtype=self.dtype, device=self.device).t() \
+            if out is None else out.reshape(self.Nv, -1)
+        self.set_stream()
+        self._check(fn(self._ctx, ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(U.data_ptr()),
+                       nrhs, ld))
+        return U.reshape(-1) if vec else U
+
+    def apply(self, s, out=None):
+        """u = K (h^d s) (eq. m_v2v)."""
+        return self._run(self._lib.hbi_apply, s, out)
+
+    def apply_adjoint(self, s, out=None):
+        """u = h^d K^H s."""
+        return self._run(self._lib.hbi_apply_adjoint, s, out)
+
+    def entries(self, rows, cols):
+        """K[rows][:, cols] (natural indices) as a complex128 device tensor."""
+        import torch
+        r = np.ascontiguousarray(rows, dtype=np.int32)
+        c = np.ascontiguousarray(cols, dtype=np.int32)
+        out = torch.empty((c.size, r.size), dtype=torch.complex128, device=self.device)
+        self.set_stream()
+        self._check(self._lib.hbi_entries(
+            self._ctx, r.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), r.size,
+            c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), c.size,
+            ctypes.c_void_p(out.data_ptr())))
+        return out.t()
+
+    def info(self) -> dict:
+        buf = ctypes.create_string_buffer(8192)
+        self._check(self._lib.hbi_get_info(self._ctx, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.hbi_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _autograd_function():
+    import torch
+
+    class HBApply(torch.autograd.Function):
+        """u = K (h^d s), differentiable in s; backward is the hand-written
+        conjugate-transpose apply (grad_s = h^d K^H grad_u)."""
+
+        @staticmethod
+        def forward(ctx, op, s):
+            ctx.op = op
+            return op.apply(s)
+
+        @staticmethod
+        def backward(ctx, grad_u):
+            return None, ctx.op.apply_adjoint(grad_u.contiguous() if grad_u.dim() == 1 else grad_u)
+
+    return HBApply
+
+
+class _LazyHBApply:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _LazyHBApply._cls is None:
+            _LazyHBApply._cls = _autograd_function()
+        return getattr(_LazyHBApply._cls, name)
+
+
+HBApply = _LazyHBApply()

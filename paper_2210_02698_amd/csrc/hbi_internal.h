@@ -1,0 +1,60 @@
+// Internal structures shared by the host driver and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define HBI_MAX_NI 16
+#define HBI_MAX_LEAF 64
+#define HBI_ID_THREADS 256
+#define HBI_ID_NMAX 4096   // largest candidate-column count an ID accepts
+
+// Problem constants visible to the kernels.
+struct DevProblem {
+  int dim, nI, NT, NTb, nterms;
+  int nbox[3];
+  double box_origin[3], box_size;
+  double omega, h, hd;   // hd = h^dim
+};
+
+// Per-cell data, in tree order (position p of the K-D permutation).
+struct DevCells {
+  const double *xyz;     // [Nv*3] centre coordinates
+  const double *lw;      // [Nv*dim*nI] 1D Lagrange weights in the cell's box
+  const int32_t *box;    // [Nv] table box of the cell
+  const double2 *self;   // [Nv] self term K_ii
+  const double *slow;    // [Nv] slowness
+  const int32_t *perm;   // [Nv] tree position -> natural index
+};
+
+struct DevTables {
+  const double *FT[3];   // transposed tables FT[t][B*NT + A] = F_t[A*NT + B]
+};
+
+// hb_entry work description for one block K(rows, cols).
+struct EntryBlock {
+  int64_t row_off;   // into rows[] / rowslot[]
+  int64_t col_off;   // into cols[]
+  int64_t slot_off;  // into slotbox[]
+  int64_t hc_off;    // into the Hc workspace (doubles)
+  double2 *out;      // column-major m x n output, leading dimension m
+  int32_t m, n, nslot, pad;
+};
+
+// One interpolative decomposition on a block already in the workspace.
+struct IdBlock {
+  double2 *A;        // m x n column-major (overwritten)
+  double2 *X;        // output r x n column-major (capacity min(m,n)*n)
+  int32_t *piv;      // output, n entries (first r are the skeleton)
+  int32_t m, n;
+};
+
+// Apply descriptors (element offsets into the factor store / z workspace).
+struct VDesc { int64_t foff; int64_t zout; int32_t r; int32_t pad; };
+struct KDesc { int64_t foff; int64_t zin; int32_t r; int32_t pad; };
+struct WUnit {
+  int64_t foff;      // [X_a (ra x c) | X_b (rb x c)], each column-major
+  int64_t zin;       // c inputs (skeletons of nu_1 then nu_2)
+  int64_t zouta, zoutb;
+  int32_t ra, rb, c, pad;
+};
+struct LeafInfo { int32_t start, size; int64_t dense_off; };

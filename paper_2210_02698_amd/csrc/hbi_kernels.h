@@ -1,0 +1,46 @@
+// Launchers of the HIP kernels (defined in hbi_kernels.hip).
+#pragma once
+#include <vector>
+
+#include "hbi_internal.h"
+
+namespace hbi {
+
+struct CopyDesc { const double2 *src; double2 *dst; int64_t count; };
+
+// Device-side apply plan (all pointers are device pointers).
+struct ApplyPlan {
+  int Lv = 0, Lmax = 0;
+  int64_t nleaf = 0;
+  const LeafInfo *leaves = nullptr;
+  const int32_t *perm = nullptr;
+  const VDesc *vd = nullptr;
+  const KDesc *kd = nullptr;
+  std::vector<const WUnit *> units;   // index k = 1..Lmax
+  std::vector<int64_t> nunits;
+};
+
+hipError_t launch_cell_setup(const DevProblem &P, const int32_t *perm, int64_t Nv,
+                             const int32_t ncell[3], const double origin[3],
+                             double *xyz, double *lw, int32_t *box, hipStream_t st);
+hipError_t launch_self_terms(const DevProblem &P, const double *slow, int64_t Nv,
+                             const double *gx, const double *gw, int ng,
+                             double2 *self, hipStream_t st);
+hipError_t launch_colside(const DevProblem &P, const DevCells &C, const DevTables &T,
+                          const EntryBlock *blks, const int32_t *work, int64_t nwork,
+                          const int32_t *cols, const int32_t *slotbox, double *Hc,
+                          hipStream_t st);
+hipError_t launch_entries(const DevProblem &P, const DevCells &C, const EntryBlock *blks,
+                          const int32_t *work, int64_t nwork, const int32_t *rows,
+                          const uint16_t *rowslot, const int32_t *cols, const double *Hc,
+                          hipStream_t st);
+hipError_t launch_cpqr(const IdBlock *blks, int64_t nb, double tol, int32_t *rank,
+                       hipStream_t st);
+hipError_t launch_copy_blocks(const CopyDesc *d, int64_t nb, hipStream_t st);
+hipError_t launch_to_f32(const double2 *src, float2 *dst, int64_t n, hipStream_t st);
+
+template <typename R>
+hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
+                        const void *F, R hd, bool adjoint, hipStream_t st);
+
+}  // namespace hbi

@@ -1,0 +1,731 @@
+// HIP kernels of the HB integrator for gfx950 (wave64).
+//
+//   hb_entry  k_cell_setup, k_self_terms, k_colside, k_entries
+//   bf_build  k_cpqr (column-pivoted Householder QR + interpolation matrix),
+//             k_copy_blocks
+//   bf_apply  k_vstage, k_wstage, k_final           (u = K h^d s)
+//   adjoint   k_final_adj, k_wstage_adj, k_vstage_adj (u = h^d K^H s)
+#include "hbi_kernels.h"
+#include "hbi_device.h"
+#include "hbi_hankel.h"
+
+namespace hbi {
+
+// ---------------------------------------------------------------------------
+// Per-cell setup: centre, table box and 1D barycentric Lagrange weights.
+// First-kind Chebyshev nodes u_k = (1 + cos((2k+1)pi/(2nI)))/2 on [0,1]
+// have barycentric weights (-1)^k sin((2k+1)pi/(2nI)) (Berrut & Trefethen,
+// SIAM Rev. 2004); l_k(t) = (w_k/(t-u_k)) / sum_j w_j/(t-u_j).
+// ---------------------------------------------------------------------------
+__global__ void k_cell_setup(DevProblem P, const int32_t *perm, int64_t Nv,
+                             int32_t ncx, int32_t ncy, double ox, double oy,
+                             double oz, double *xyz, double *lw, int32_t *box) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= Nv) return;
+  const int64_t nat = perm[p];
+  const int64_t ix = nat % ncx, iy = (nat / ncx) % ncy, iz = nat / ((int64_t)ncx * ncy);
+  double c[3];
+  c[0] = ox + (ix + 0.5) * P.h;
+  c[1] = oy + (iy + 0.5) * P.h;
+  c[2] = oz + (iz + 0.5) * P.h;
+  int32_t b = 0, stride = 1;
+  const int nI = P.nI;
+  for (int ax = 0; ax < P.dim; ++ax) {
+    xyz[p * 3 + ax] = c[ax];
+    const double rel = (c[ax] - P.box_origin[ax]) / P.box_size;
+    int bi = (int)floor(rel);
+    bi = bi < 0 ? 0 : (bi >= P.nbox[ax] ? P.nbox[ax] - 1 : bi);
+    b += bi * stride;
+    stride *= P.nbox[ax];
+    const double t = rel - bi;
+    double *w = lw + (p * P.dim + ax) * nI;
+    int hit = -1;
+    double den = 0.0;
+    for (int k = 0; k < nI; ++k) {
+      const double ang = (2.0 * k + 1.0) * kPi / (2.0 * nI);
+      const double u = 0.5 * (1.0 + cos(ang));
+      const double d = t - u;
+      if (d == 0.0) { hit = k; break; }
+      const double q = ((k & 1) ? -sin(ang) : sin(ang)) / d;
+      w[k] = q;
+      den += q;
+    }
+    if (hit >= 0) {
+      for (int k = 0; k < nI; ++k) w[k] = (k == hit) ? 1.0 : 0.0;
+    } else {
+      const double inv = 1.0 / den;
+      for (int k = 0; k < nI; ++k) w[k] *= inv;
+    }
+  }
+  if (P.dim == 2) xyz[p * 3 + 2] = 0.0;
+  box[p] = b;
+}
+
+// ---------------------------------------------------------------------------
+// Self terms K_ii = h^-d x (cell integral of the leading HB term), Appendix A.
+// 2D: (i/4) (n w)^-2 [8 int_0^{pi/4} X H1(X) dtheta + 4i] / h^2,
+//     X = h n w / (2 cos theta).
+// 3D: i Q_s / (4 pi w^2 n^2 h^3), Q_s = -48i int_0^{pi/4} dphi int_0^1 drho'
+//     [e^{i r1}(1 - i r1) - 1] rho / (1 + rho^2)^{3/2} / cos phi,
+//     rho = rho'/cos phi, r1 = w n (h/2) sqrt(1 + rho^2).
+// Both integrands are smooth; Gauss-Legendre with `ng` nodes (gx, gw on
+// [0,1]) converges to machine precision.
+// ---------------------------------------------------------------------------
+__global__ void k_self_terms(DevProblem P, const double *slow, int64_t Nv,
+                             const double *gx, const double *gw, int ng,
+                             double2 *self) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= Nv) return;
+  const double n = slow[p], w = P.omega, h = P.h;
+  double2 out;
+  if (P.dim == 2) {
+    const double a = 0.5 * h * n * w;
+    double sr = 0.0, si = 0.0;
+    for (int q = 0; q < ng; ++q) {
+      const double th = 0.25 * kPi * gx[q];
+      const double X = a / cos(th);
+      const Hankel01 H = hankel01(X);
+      sr += gw[q] * X * H.j1;
+      si += gw[q] * X * H.y1;
+    }
+    sr *= 0.25 * kPi;
+    si *= 0.25 * kPi;
+    // (i/4)(8 s + 4i) = 2 i s - 1
+    const double sc = 1.0 / ((n * w) * (n * w) * h * h);
+    out.x = (-2.0 * si - 1.0) * sc;
+    out.y = (2.0 * sr) * sc;
+  } else {
+    double qr = 0.0, qi = 0.0;
+    for (int a = 0; a < ng; ++a) {
+      const double phi = 0.25 * kPi * gx[a];
+      const double cph = cos(phi);
+      double ir = 0.0, ii = 0.0;
+      for (int b = 0; b < ng; ++b) {
+        const double rho = gx[b] / cph;
+        const double s2 = 1.0 + rho * rho;
+        const double r1 = w * n * 0.5 * h * sqrt(s2);
+        double sn, cs;
+        sincos(r1, &sn, &cs);
+        // e^{i r1}(1 - i r1) - 1
+        const double er = cs + r1 * sn - 1.0;
+        const double ei = sn - r1 * cs;
+        const double g = rho / (s2 * sqrt(s2)) / cph;
+        ir += gw[b] * er * g;
+        ii += gw[b] * ei * g;
+      }
+      qr += gw[a] * ir;
+      qi += gw[a] * ii;
+    }
+    qr *= 0.25 * kPi;
+    qi *= 0.25 * kPi;
+    // Q_s = -48 i (qr + i qi) = 48 qi - 48 i qr ; I = i Q_s / (4 pi w^2 n^2)
+    const double Qr = 48.0 * qi, Qi = -48.0 * qr;
+    const double sc = 1.0 / (4.0 * kPi * w * w * n * n * h * h * h);
+    out.x = -Qi * sc;
+    out.y = Qr * sc;
+  }
+  self[p] = out;
+}
+
+// ---------------------------------------------------------------------------
+// hb_entry, column side of eq. chebinterpblock: for block column j (source
+// cell in table box beta) and row box alpha,
+//   Hc[t][a] = sum_b F_t[alpha*NTb + a, beta*NTb + b] T_b(r_j).
+// One wave per (block, column, row-box slot); lanes run over a, reading the
+// transposed table so that the loads are contiguous.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_colside(
+    DevProblem P, DevCells C, DevTables T, const EntryBlock *blks,
+    const int32_t *work, int64_t nwork, const int32_t *cols,
+    const int32_t *slotbox, double *Hc) {
+  extern __shared__ double sT[];
+  const int64_t w = blockIdx.x;
+  if (w >= nwork) return;
+  const int blk = work[2 * w], js = work[2 * w + 1];
+  const EntryBlock B = blks[blk];
+  const int j = js / B.nslot, slot = js % B.nslot;
+  const int32_t cp = cols[B.col_off + j];
+  const int beta = C.box[cp];
+  const int alpha = slotbox[B.slot_off + slot];
+  const int nI = P.nI, NTb = P.NTb, NT = P.NT, D = P.dim;
+  const double *lwc = C.lw + (int64_t)cp * D * nI;
+  for (int b = threadIdx.x; b < NTb; b += 64) {
+    int r = b;
+    double v = 1.0;
+    for (int ax = 0; ax < D; ++ax) {
+      v *= lwc[ax * nI + r % nI];
+      r /= nI;
+    }
+    sT[b] = v;
+  }
+  __syncthreads();
+  const int ntab = P.nterms == 2 ? 3 : 2;
+  double *out = Hc + B.hc_off + ((int64_t)j * B.nslot + slot) * 3 * NTb;
+  for (int a = threadIdx.x; a < NTb; a += 64) {
+    const int64_t col = (int64_t)alpha * NTb + a;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < NTb; ++b) {
+      const double tb = sT[b];
+      const int64_t rowB = ((int64_t)beta * NTb + b) * NT + col;
+      acc[0] = fma(tb, T.FT[0][rowB], acc[0]);
+      acc[1] = fma(tb, T.FT[1][rowB], acc[1]);
+      if (ntab == 3) acc[2] = fma(tb, T.FT[2][rowB], acc[2]);
+    }
+    out[a] = acc[0];
+    out[NTb + a] = acc[1];
+    out[2 * NTb + a] = acc[2];
+  }
+}
+
+// sum_a T_a(r_i) H_t[a] for the ntab tables at once, T_a = prod_s l_{a_s}(r_s).
+// The x-axis weights sit in registers; y and z weights are read from the
+// (cached) per-cell array.
+template <int D, int NI>
+__device__ __forceinline__ void contract3(const double *lw, const double *H, int NTb,
+                                          int ntab, double out[3]) {
+  double lx[NI];
+#pragma unroll
+  for (int a1 = 0; a1 < NI; ++a1) lx[a1] = lw[a1];
+  out[0] = out[1] = out[2] = 0.0;
+  const int n3 = D == 3 ? NI : 1;
+  for (int a3 = 0; a3 < n3; ++a3) {
+    double s3[3] = {0.0, 0.0, 0.0};
+    for (int a2 = 0; a2 < NI; ++a2) {
+      const double *Hp = H + NI * (a2 + NI * a3);
+      double s[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int a1 = 0; a1 < NI; ++a1) {
+        s[0] = fma(lx[a1], Hp[a1], s[0]);
+        s[1] = fma(lx[a1], Hp[NTb + a1], s[1]);
+        if (ntab == 3) s[2] = fma(lx[a1], Hp[2 * NTb + a1], s[2]);
+      }
+      const double wy = lw[NI + a2];
+      s3[0] = fma(wy, s[0], s3[0]);
+      s3[1] = fma(wy, s[1], s3[1]);
+      s3[2] = fma(wy, s[2], s3[2]);
+    }
+    const double wz = D == 3 ? lw[2 * NI + a3] : 1.0;
+    out[0] = fma(wz, s3[0], out[0]);
+    out[1] = fma(wz, s3[1], out[1]);
+    out[2] = fma(wz, s3[2], out[2]);
+  }
+}
+
+// HB entry from interpolated tau^2, v0, v1 (eq. babich, eq. termf).
+__device__ __forceinline__ double2 hb_value(int D, int nterms, double omega,
+                                            double tau2, double v0, double v1) {
+  const double tau = sqrt(fmax(tau2, 0.0));
+  const double x = omega * tau;
+  double2 K;
+  if (D == 2) {
+    // f0 = i sqrt(pi)/2 H0 = (sqrt(pi)/2)(-Y0 + i J0)
+    // f1 = -i sqrt(pi) (tau/omega) H1 = sqrt(pi)(tau/omega)(Y1 - i J1)
+    const Hankel01 H = hankel01(x);
+    const double c0 = 0.88622692545275801365 * v0;   // sqrt(pi)/2
+    K.x = -c0 * H.y0;
+    K.y = c0 * H.j0;
+    if (nterms == 2) {
+      const double c1 = 1.77245385090551602730 * (tau / omega) * v1;
+      K.x += c1 * H.y1;
+      K.y -= c1 * H.j1;
+    }
+  } else {
+    // e^{i x} (v0/(2 tau) + i v1/omega)
+    double sn, cs;
+    sincos(x, &sn, &cs);
+    const double A = v0 / (2.0 * tau);
+    const double B = nterms == 2 ? v1 / omega : 0.0;
+    K.x = cs * A - sn * B;
+    K.y = sn * A + cs * B;
+  }
+  return K;
+}
+
+template <int D, int NI>
+__global__ __launch_bounds__(256) void k_entries(
+    DevProblem P, DevCells C, const EntryBlock *blks, const int32_t *work,
+    int64_t nwork, const int32_t *rows, const uint16_t *rowslot,
+    const int32_t *cols, const double *Hc) {
+  const int64_t w = blockIdx.x;
+  if (w >= nwork) return;
+  const int blk = work[2 * w], j = work[2 * w + 1];
+  const EntryBlock B = blks[blk];
+  const int32_t cp = cols[B.col_off + j];
+  const int NTb = P.NTb;
+  const double *Hcol = Hc + B.hc_off + (int64_t)j * B.nslot * 3 * NTb;
+  double2 *out = B.out + (int64_t)j * B.m;
+  for (int i = threadIdx.x; i < B.m; i += 256) {
+    const int32_t rp = rows[B.row_off + i];
+    double2 K;
+    if (rp == cp) {
+      K = C.self[rp];
+    } else {
+      const int slot = rowslot[B.row_off + i];
+      const double *H = Hcol + (int64_t)slot * 3 * NTb;
+      double tv[3];
+      contract3<D, NI>(C.lw + (int64_t)rp * D * NI, H, NTb, P.nterms == 2 ? 3 : 2, tv);
+      const double t2 = tv[0], v0 = tv[1], v1 = tv[2];
+      K = hb_value(D, P.nterms, P.omega, t2, v0, v1);
+    }
+    out[i] = K;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Interpolative decomposition of one block (eq. ID): Householder QR with
+// column pivoting on the largest remaining column norm (ties: first in
+// pivot order), stopped at the first k with |R_kk| <= tol |R_11|; rank
+// r = k (at least 1).  Then X = [I, R11^-1 R12] Pi^T (r x n) so that
+// A ~ A(:, skel) X.  Column norms are recomputed exactly from the updated
+// entries at every step.  One workgroup (4 waves) per block; the block lives
+// in global memory and waves split the trailing columns.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(HBI_ID_THREADS) void k_cpqr(const IdBlock *blks,
+                                                          double tol,
+                                                          int32_t *rank_out) {
+  __shared__ double nrm2[HBI_ID_NMAX];
+  __shared__ int colmap[HBI_ID_NMAX];
+  __shared__ double red_v[HBI_ID_THREADS / 64];
+  __shared__ int red_i[HBI_ID_THREADS / 64];
+  __shared__ double2 sh_tau, sh_scale;
+  __shared__ int sh_stop, sh_rank, sh_c;
+  __shared__ double sh_r11;
+
+  const IdBlock B = blks[blockIdx.x];
+  const int m = B.m, n = B.n;
+  double2 *A = B.A;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = HBI_ID_THREADS / 64;
+
+  for (int j = wave; j < n; j += NW) {
+    const double2 *a = A + (int64_t)j * m;
+    double s = 0.0;
+    for (int i = lane; i < m; i += 64) s += a[i].x * a[i].x + a[i].y * a[i].y;
+    s = wave_sum(s);
+    if (lane == 0) nrm2[j] = s;
+  }
+  for (int j = tid; j < n; j += HBI_ID_THREADS) colmap[j] = j;
+  if (tid == 0) { sh_rank = m < n ? m : n; sh_r11 = 0.0; }
+  __syncthreads();
+
+  const int kmax = m < n ? m : n;
+  for (int k = 0; k < kmax; ++k) {
+    // pivot search over q in [k, n)
+    double bv = -1.0;
+    int bq = n;
+    for (int q = k + tid; q < n; q += HBI_ID_THREADS) {
+      const double v = nrm2[colmap[q]];
+      if (v > bv) { bv = v; bq = q; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o, 64);
+      const int oq = __shfl_xor(bq, o, 64);
+      if (ov > bv || (ov == bv && oq < bq)) { bv = ov; bq = oq; }
+    }
+    if (lane == 0) { red_v[wave] = bv; red_i[wave] = bq; }
+    __syncthreads();
+    if (tid == 0) {
+      for (int w2 = 1; w2 < NW; ++w2)
+        if (red_v[w2] > bv || (red_v[w2] == bv && red_i[w2] < bq)) {
+          bv = red_v[w2];
+          bq = red_i[w2];
+        }
+      const double nrm = sqrt(fmax(bv, 0.0));
+      if (k == 0) sh_r11 = nrm;
+      int stop = (nrm == 0.0) || (k > 0 && nrm <= tol * sh_r11);
+      sh_stop = stop;
+      if (stop) {
+        sh_rank = k > 0 ? k : 1;
+      } else {
+        const int t = colmap[k];
+        colmap[k] = colmap[bq];
+        colmap[bq] = t;
+        const int c = colmap[k];
+        double2 *ac = A + (int64_t)c * m;
+        const double2 al = ac[k];
+        const double beta = al.x >= 0.0 ? -nrm : nrm;
+        // tau = (beta - alpha)/beta ; scale = 1/(alpha - beta)
+        sh_tau = double2{(beta - al.x) / beta, -al.y / beta};
+        const double dr = al.x - beta, di = al.y;
+        const double dd = dr * dr + di * di;
+        sh_scale = double2{dr / dd, -di / dd};
+        ac[k] = double2{beta, 0.0};
+        sh_c = c;
+      }
+    }
+    __syncthreads();
+    if (sh_stop) break;
+    const int c = sh_c;
+    const double2 scale = sh_scale, tau = sh_tau;
+    double2 *v = A + (int64_t)c * m;
+    for (int i = k + 1 + tid; i < m; i += HBI_ID_THREADS) v[i] = cmul(v[i], scale);
+    __syncthreads();
+    const double2 ctau = double2{tau.x, -tau.y};
+    for (int q = k + 1 + wave; q < n; q += NW) {
+      const int j = colmap[q];
+      double2 *a = A + (int64_t)j * m;
+      double2 wv = double2{0.0, 0.0};
+      for (int i = k + lane; i < m; i += 64) {
+        const double2 vi = (i == k) ? double2{1.0, 0.0} : v[i];
+        cfmac(wv, vi, a[i]);
+      }
+      wv.x = wave_sum(wv.x);
+      wv.y = wave_sum(wv.y);
+      const double2 f = cmul(ctau, wv);
+      double s = 0.0;
+      for (int i = k + lane; i < m; i += 64) {
+        const double2 vi = (i == k) ? double2{1.0, 0.0} : v[i];
+        double2 ai = a[i];
+        ai.x -= f.x * vi.x - f.y * vi.y;
+        ai.y -= f.x * vi.y + f.y * vi.x;
+        a[i] = ai;
+        if (i > k) s += ai.x * ai.x + ai.y * ai.y;
+      }
+      s = wave_sum(s);
+      if (lane == 0) nrm2[j] = s;
+    }
+    __syncthreads();
+  }
+
+  const int r = sh_rank;
+  const bool zero = !(sh_r11 > 0.0);
+  double2 *X = B.X;
+  for (int idx = tid; idx < r * r; idx += HBI_ID_THREADS) {
+    const int q = idx / r, i = idx % r;
+    X[i + (int64_t)colmap[q] * r] = double2{i == q ? 1.0 : 0.0, 0.0};
+  }
+  for (int q = tid; q < r; q += HBI_ID_THREADS) B.piv[q] = colmap[q];
+  // T = R11^-1 R12 by back substitution, one column per thread
+  for (int q = r + tid; q < n; q += HBI_ID_THREADS) {
+    const int col = colmap[q];
+    const double2 *rc = A + (int64_t)col * m;
+    double2 *x = X + (int64_t)col * r;
+    for (int i = r - 1; i >= 0; --i) {
+      double2 acc = rc[i];
+      for (int l = i + 1; l < r; ++l) {
+        const double2 ril = A[i + (int64_t)colmap[l] * m];
+        const double2 xl = x[l];
+        acc.x -= ril.x * xl.x - ril.y * xl.y;
+        acc.y -= ril.x * xl.y + ril.y * xl.x;
+      }
+      const double2 d = A[i + (int64_t)colmap[i] * m];
+      const double dd = d.x * d.x + d.y * d.y;
+      if (zero || dd == 0.0) {
+        x[i] = double2{0.0, 0.0};
+      } else {
+        x[i] = double2{(acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd};
+      }
+    }
+  }
+  if (tid == 0) rank_out[blockIdx.x] = r;
+}
+
+// Contiguous copies src[b] -> dst[b] of cnt[b] complex values.
+__global__ void k_copy_blocks(const CopyDesc *d, int64_t nb) {
+  const int64_t b = blockIdx.x;
+  if (b >= nb) return;
+  const CopyDesc c = d[b];
+  for (int64_t i = threadIdx.x; i < c.count; i += blockDim.x) c.dst[i] = c.src[i];
+}
+
+__global__ void k_to_f32(const double2 *src, float2 *dst, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = float2{(float)src[i].x, (float)src[i].y};
+}
+
+// ---------------------------------------------------------------------------
+// bf_apply (eq. butterfly_mat): V^0 per column leaf, transfer stages W^k,
+// skeleton factor K^L plus the dense diagonal leaf per row leaf.  Gathers
+// only: every output element is written by exactly one lane.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(64) void k_vstage(const cplx_t<R> *s,
+                                               const LeafInfo *leaves,
+                                               const int32_t *perm,
+                                               const VDesc *vd, int Lv,
+                                               const cplx_t<R> *F,
+                                               cplx_t<R> *z, R hd) {
+  using C = cplx_t<R>;
+  __shared__ C xs[HBI_MAX_LEAF];
+  const int g = blockIdx.x, lane = threadIdx.x;
+  const LeafInfo lf = leaves[g];
+  if (lane < lf.size) {
+    const C v = s[perm[lf.start + lane]];
+    xs[lane] = C{v.x * hd, v.y * hd};
+  }
+  __syncthreads();
+  for (int l = 0; l < Lv; ++l) {
+    const VDesc d = vd[(int64_t)g * Lv + l];
+    if (lane < d.r) {
+      const C *f = F + d.foff + lane;
+      C acc{0, 0};
+      for (int col = 0; col < lf.size; ++col) cfma(acc, f[(int64_t)col * d.r], xs[col]);
+      z[d.zout + lane] = acc;
+    }
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_wstage(const WUnit *units,
+                                                int64_t nunits,
+                                                const cplx_t<R> *F,
+                                                cplx_t<R> *z) {
+  using C = cplx_t<R>;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t u = (int64_t)blockIdx.x * 4 + wave;
+  if (u >= nunits) return;
+  const WUnit U = units[u];
+  const int Rt = U.ra + U.rb;
+  const C *zin = z + U.zin;
+  for (int s = lane; s < Rt; s += 64) {
+    const bool first = s < U.ra;
+    const int row = first ? s : s - U.ra;
+    const int ld = first ? U.ra : U.rb;
+    const C *M = F + U.foff + (first ? 0 : (int64_t)U.ra * U.c) + row;
+    C acc{0, 0};
+    for (int col = 0; col < U.c; ++col) cfma(acc, M[(int64_t)col * ld], zin[col]);
+    z[(first ? U.zouta : U.zoutb) + row] = acc;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(64) void k_final(const cplx_t<R> *s,
+                                              const LeafInfo *leaves,
+                                              const int32_t *perm,
+                                              const KDesc *kd, int Lv,
+                                              const cplx_t<R> *F,
+                                              const cplx_t<R> *z,
+                                              cplx_t<R> *u, R hd) {
+  using C = cplx_t<R>;
+  __shared__ C xs[HBI_MAX_LEAF];
+  const int g = blockIdx.x, lane = threadIdx.x;
+  const LeafInfo lf = leaves[g];
+  const int sz = lf.size;
+  if (lane < sz) {
+    const C v = s[perm[lf.start + lane]];
+    xs[lane] = C{v.x * hd, v.y * hd};
+  }
+  __syncthreads();
+  if (lane >= sz) return;
+  C acc{0, 0};
+  const C *Dm = F + lf.dense_off + lane;
+  for (int col = 0; col < sz; ++col) cfma(acc, Dm[(int64_t)col * sz], xs[col]);
+  for (int l = 0; l < Lv; ++l) {
+    const KDesc d = kd[(int64_t)g * Lv + l];
+    const C *K = F + d.foff + lane;
+    const C *zz = z + d.zin;
+    for (int q = 0; q < d.r; ++q) cfma(acc, K[(int64_t)q * sz], zz[q]);
+  }
+  u[perm[lf.start + lane]] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint: the same factors read as conjugate transposes, stages reversed.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(64) void k_final_adj(const cplx_t<R> *y,
+                                                  const LeafInfo *leaves,
+                                                  const int32_t *perm,
+                                                  const KDesc *kd, int Lv,
+                                                  const cplx_t<R> *F,
+                                                  cplx_t<R> *z) {
+  using C = cplx_t<R>;
+  __shared__ C ys[HBI_MAX_LEAF];
+  const int g = blockIdx.x, lane = threadIdx.x;
+  const LeafInfo lf = leaves[g];
+  const int sz = lf.size;
+  if (lane < sz) ys[lane] = y[perm[lf.start + lane]];
+  __syncthreads();
+  for (int l = 0; l < Lv; ++l) {
+    const KDesc d = kd[(int64_t)g * Lv + l];
+    if (lane < d.r) {
+      const C *K = F + d.foff + (int64_t)lane * sz;
+      C acc{0, 0};
+      for (int row = 0; row < sz; ++row) cfmac(acc, K[row], ys[row]);
+      z[d.zin + lane] = acc;
+    }
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_wstage_adj(const WUnit *units,
+                                                    int64_t nunits,
+                                                    const cplx_t<R> *F,
+                                                    cplx_t<R> *z) {
+  using C = cplx_t<R>;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t u = (int64_t)blockIdx.x * 4 + wave;
+  if (u >= nunits) return;
+  const WUnit U = units[u];
+  const C *wa = z + U.zouta, *wb = z + U.zoutb;
+  const C *Ma = F + U.foff, *Mb = F + U.foff + (int64_t)U.ra * U.c;
+  for (int col = lane; col < U.c; col += 64) {
+    C acc{0, 0};
+    const C *ca = Ma + (int64_t)col * U.ra;
+    for (int i = 0; i < U.ra; ++i) cfmac(acc, ca[i], wa[i]);
+    const C *cb = Mb + (int64_t)col * U.rb;
+    for (int i = 0; i < U.rb; ++i) cfmac(acc, cb[i], wb[i]);
+    z[U.zin + col] = acc;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(64) void k_vstage_adj(const cplx_t<R> *y,
+                                                   const LeafInfo *leaves,
+                                                   const int32_t *perm,
+                                                   const VDesc *vd, int Lv,
+                                                   const cplx_t<R> *F,
+                                                   const cplx_t<R> *z,
+                                                   cplx_t<R> *u, R hd) {
+  using C = cplx_t<R>;
+  __shared__ C ys[HBI_MAX_LEAF];
+  const int g = blockIdx.x, lane = threadIdx.x;
+  const LeafInfo lf = leaves[g];
+  const int sz = lf.size;
+  if (lane < sz) ys[lane] = y[perm[lf.start + lane]];
+  __syncthreads();
+  if (lane >= sz) return;
+  C acc{0, 0};
+  // dense leaf: (D^H y)[col], column `lane` of D is contiguous
+  const C *Dc = F + lf.dense_off + (int64_t)lane * sz;
+  for (int row = 0; row < sz; ++row) cfmac(acc, Dc[row], ys[row]);
+  for (int l = 0; l < Lv; ++l) {
+    const VDesc d = vd[(int64_t)g * Lv + l];
+    const C *V = F + d.foff + (int64_t)lane * d.r;
+    const C *w = z + d.zout;
+    for (int row = 0; row < d.r; ++row) cfmac(acc, V[row], w[row]);
+  }
+  u[perm[lf.start + lane]] = C{acc.x * hd, acc.y * hd};
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_cell_setup(const DevProblem &P, const int32_t *perm, int64_t Nv,
+                             const int32_t ncell[3], const double origin[3],
+                             double *xyz, double *lw, int32_t *box, hipStream_t st) {
+  const int T = 256;
+  hipLaunchKernelGGL(k_cell_setup, dim3((Nv + T - 1) / T), dim3(T), 0, st, P, perm, Nv,
+                     ncell[0], ncell[1], origin[0], origin[1], origin[2], xyz, lw, box);
+  return hipGetLastError();
+}
+
+hipError_t launch_self_terms(const DevProblem &P, const double *slow, int64_t Nv,
+                             const double *gx, const double *gw, int ng,
+                             double2 *self, hipStream_t st) {
+  const int T = 128;
+  hipLaunchKernelGGL(k_self_terms, dim3((Nv + T - 1) / T), dim3(T), 0, st, P, slow, Nv,
+                     gx, gw, ng, self);
+  return hipGetLastError();
+}
+
+hipError_t launch_colside(const DevProblem &P, const DevCells &C, const DevTables &T,
+                          const EntryBlock *blks, const int32_t *work, int64_t nwork,
+                          const int32_t *cols, const int32_t *slotbox, double *Hc,
+                          hipStream_t st) {
+  if (nwork == 0) return hipSuccess;
+  const size_t lds = sizeof(double) * (size_t)P.NTb;
+  hipLaunchKernelGGL(k_colside, dim3(nwork), dim3(64), lds, st, P, C, T, blks, work, nwork,
+                     cols, slotbox, Hc);
+  return hipGetLastError();
+}
+
+template <int D, int NI>
+static void entries_launch(const DevProblem &P, const DevCells &C, const EntryBlock *blks,
+                           const int32_t *work, int64_t nwork, const int32_t *rows,
+                           const uint16_t *rowslot, const int32_t *cols, const double *Hc,
+                           hipStream_t st) {
+  hipLaunchKernelGGL((k_entries<D, NI>), dim3(nwork), dim3(256), 0, st, P, C, blks, work,
+                     nwork, rows, rowslot, cols, Hc);
+}
+
+hipError_t launch_entries(const DevProblem &P, const DevCells &C, const EntryBlock *blks,
+                          const int32_t *work, int64_t nwork, const int32_t *rows,
+                          const uint16_t *rowslot, const int32_t *cols, const double *Hc,
+                          hipStream_t st) {
+  if (nwork == 0) return hipSuccess;
+#define HBI_NI_CASE(D, NI) \
+  case NI: entries_launch<D, NI>(P, C, blks, work, nwork, rows, rowslot, cols, Hc, st); break;
+#define HBI_NI_SWITCH(D)                                                              \
+  switch (P.nI) {                                                                     \
+    HBI_NI_CASE(D, 2) HBI_NI_CASE(D, 3) HBI_NI_CASE(D, 4) HBI_NI_CASE(D, 5)           \
+    HBI_NI_CASE(D, 6) HBI_NI_CASE(D, 7) HBI_NI_CASE(D, 8) HBI_NI_CASE(D, 9)           \
+    HBI_NI_CASE(D, 10) HBI_NI_CASE(D, 11) HBI_NI_CASE(D, 12) HBI_NI_CASE(D, 13)       \
+    HBI_NI_CASE(D, 14) HBI_NI_CASE(D, 15) HBI_NI_CASE(D, 16)                          \
+    default: return hipErrorInvalidValue;                                            \
+  }
+  if (P.dim == 2) {
+    HBI_NI_SWITCH(2)
+  } else {
+    HBI_NI_SWITCH(3)
+  }
+#undef HBI_NI_SWITCH
+#undef HBI_NI_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_cpqr(const IdBlock *blks, int64_t nb, double tol, int32_t *rank,
+                       hipStream_t st) {
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cpqr, dim3(nb), dim3(HBI_ID_THREADS), 0, st, blks, tol, rank);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_blocks(const CopyDesc *d, int64_t nb, hipStream_t st) {
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_blocks, dim3(nb), dim3(256), 0, st, d, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const double2 *src, float2 *dst, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int T = 256;
+  hipLaunchKernelGGL(k_to_f32, dim3((n + T - 1) / T), dim3(T), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
+                        const void *F, R hd, bool adjoint, hipStream_t st) {
+  using C = cplx_t<R>;
+  const C *sc = (const C *)s;
+  C *uc = (C *)u;
+  C *zc = (C *)z;
+  const C *Fc = (const C *)F;
+  if (!adjoint) {
+    if (ap.Lv > 0)
+      hipLaunchKernelGGL((k_vstage<R>), dim3(ap.nleaf), dim3(64), 0, st, sc, ap.leaves,
+                         ap.perm, ap.vd, ap.Lv, Fc, zc, hd);
+    for (int k = 1; k <= ap.Lmax; ++k) {
+      const int64_t nu = ap.nunits[k];
+      if (nu == 0) continue;
+      hipLaunchKernelGGL((k_wstage<R>), dim3((nu + 3) / 4), dim3(256), 0, st,
+                         ap.units[k], nu, Fc, zc);
+    }
+    hipLaunchKernelGGL((k_final<R>), dim3(ap.nleaf), dim3(64), 0, st, sc, ap.leaves,
+                       ap.perm, ap.kd, ap.Lv, Fc, (const C *)zc, uc, hd);
+  } else {
+    if (ap.Lv > 0)
+      hipLaunchKernelGGL((k_final_adj<R>), dim3(ap.nleaf), dim3(64), 0, st, sc, ap.leaves,
+                         ap.perm, ap.kd, ap.Lv, Fc, zc);
+    for (int k = ap.Lmax; k >= 1; --k) {
+      const int64_t nu = ap.nunits[k];
+      if (nu == 0) continue;
+      hipLaunchKernelGGL((k_wstage_adj<R>), dim3((nu + 3) / 4), dim3(256), 0, st,
+                         ap.units[k], nu, Fc, zc);
+    }
+    hipLaunchKernelGGL((k_vstage_adj<R>), dim3(ap.nleaf), dim3(64), 0, st, sc, ap.leaves,
+                       ap.perm, ap.vd, ap.Lv, Fc, (const C *)zc, uc, hd);
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_apply<double>(const ApplyPlan &, const void *, void *, void *,
+                                         const void *, double, bool, hipStream_t);
+template hipError_t launch_apply<float>(const ApplyPlan &, const void *, void *, void *,
+                                        const void *, float, bool, hipStream_t);
+
+}  // namespace hbi

@@ -1,0 +1,982 @@
+// C ABI, context and the level-synchronous HODBF build driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/hbi.h"
+#include "hbi_geometry.h"
+#include "hbi_internal.h"
+#include "hbi_kernels.h"
+
+using namespace hbi;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf &operator=(DevBuf &&o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  hipError_t alloc(size_t bytes) {
+    release();
+    if (bytes == 0) return hipSuccess;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) { p = nullptr; (void)hipGetLastError(); return e; }
+    n = bytes;
+    return hipSuccess;
+  }
+  // grow-only reuse
+  hipError_t reserve(size_t bytes) { return bytes <= n ? hipSuccess : alloc(bytes); }
+  template <class T> T *as() const { return (T *)p; }
+};
+
+struct Status {
+  hbi_status code;
+  std::string msg;
+};
+
+struct Error {
+  hbi_status code;
+  std::string msg;
+};
+
+#define HBI_HIP(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      throw Error{e_ == hipErrorOutOfMemory ? HBI_ERR_OOM : HBI_ERR_HIP,               \
+                  std::string(#expr) + ": " + hipGetErrorString(e_)};                  \
+    }                                                                                  \
+  } while (0)
+
+#define HBI_REQUIRE(cond, code, msg) \
+  do {                               \
+    if (!(cond)) throw Error{code, msg}; \
+  } while (0)
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Gauss-Legendre nodes/weights on [0,1] by Newton iteration on P_n.
+void gauss_legendre01(int n, std::vector<double> &x, std::vector<double> &w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = 0.5 * (1.0 - z);
+    w[i] = 1.0 / ((1.0 - z * z) * dp * dp);   // = 0.5 * 2/((1-z^2) P'^2)
+  }
+}
+
+struct Chunk {
+  DevBuf buf;
+  int64_t goff;     // global element offset in the final factor store
+  int64_t count;    // complex elements
+};
+
+}  // namespace
+
+struct hbi_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int state = 0;   // 0 created, 1 tables, 2 built
+  // problem
+  int dim = 2, nterms = 2, nI = 3, NTb = 0, NT = 0;
+  int32_t ncell[3] = {1, 1, 1}, nbox[3] = {1, 1, 1};
+  double origin[3] = {0, 0, 0}, h = 1, omega = 1, box_origin[3] = {0, 0, 0}, box_size = 1;
+  std::vector<double> slow_nat;
+  hbi_build_opts opts{};
+  int geo_leaf = -1;
+  Geometry geo;
+  std::vector<int32_t> box_h;   // table box per tree position (host copy)
+  // device cell data
+  DevBuf perm_d, xyz_d, lw_d, box_d, self_d, slow_d, FT_d[3];
+  // build workspace
+  DevBuf ws, idx_d;
+  // factors and plan
+  hbi_prec prec = HBI_F64;
+  DevBuf F;
+  int64_t Felems = 0;
+  DevBuf leaves_d, vd_d, kd_d;
+  std::vector<DevBuf> units_d;
+  ApplyPlan plan;
+  int64_t ztotal = 0;
+  DevBuf z_d;
+  // statistics
+  double t_build = 0, t_geo = 0, t_host = 0, t_gpu = 0, t_final = 0;
+  int64_t nnz_v = 0, nnz_w = 0, nnz_k = 0, nnz_d = 0, entries_eval = 0, nid = 0;
+  int32_t rank_max = 0;
+  double rank_sum = 0;
+  double tol = 0;
+
+  DevProblem devprob() const {
+    DevProblem P{};
+    P.dim = dim; P.nI = nI; P.NT = NT; P.NTb = NTb; P.nterms = nterms;
+    for (int a = 0; a < 3; ++a) { P.nbox[a] = nbox[a]; P.box_origin[a] = box_origin[a]; }
+    P.box_size = box_size; P.omega = omega; P.h = h; P.hd = std::pow(h, dim);
+    return P;
+  }
+  DevCells devcells() const {
+    DevCells C{};
+    C.xyz = xyz_d.as<double>(); C.lw = lw_d.as<double>(); C.box = box_d.as<int32_t>();
+    C.self = self_d.as<double2>(); C.slow = slow_d.as<double>(); C.perm = perm_d.as<int32_t>();
+    return C;
+  }
+  DevTables devtables() const {
+    DevTables T{};
+    for (int t = 0; t < 3; ++t) T.FT[t] = FT_d[t].as<double>();
+    return T;
+  }
+  double chi() const { return opts.chi > 0 ? opts.chi : (dim == 2 ? 20.0 : 4.0); }
+  int leaf() const { return opts.leaf_size > 0 ? std::min(opts.leaf_size, HBI_MAX_LEAF) : 64; }
+  double radius() const { return opts.neighbor_radius > 0 ? opts.neighbor_radius : (dim == 2 ? 10.0 : 3.0); }
+  int band() const { return opts.band_width > 0 ? opts.band_width : 2; }
+  int64_t wsbytes() const { return opts.workspace_bytes > 0 ? opts.workspace_bytes : (int64_t)2 << 30; }
+  void drop_factors() {
+    F.release(); Felems = 0; leaves_d.release(); vd_d.release(); kd_d.release();
+    units_d.clear(); plan = ApplyPlan(); ztotal = 0; z_d.release();
+    nnz_v = nnz_w = nnz_k = nnz_d = entries_eval = nid = 0; rank_max = 0; rank_sum = 0;
+    if (state > 1) state = 1;
+  }
+};
+
+namespace {
+
+hbi_status fail(hbi_ctx *ctx, const Error &e) {
+  if (ctx) ctx->err = e.msg; else g_err = e.msg;
+  return e.code;
+}
+
+template <class F> hbi_status guarded(hbi_ctx *ctx, F &&f) {
+  try {
+    if (ctx) {
+      ctx->err.clear();
+      HBI_HIP(hipSetDevice(ctx->device));
+    }
+    f();
+    return HBI_OK;
+  } catch (const Error &e) {
+    return fail(ctx, e);
+  } catch (const std::bad_alloc &) {
+    return fail(ctx, Error{HBI_ERR_OOM, "host allocation failed"});
+  } catch (const std::exception &e) {
+    return fail(ctx, Error{HBI_ERR_HIP, e.what()});
+  }
+}
+
+template <class T> void upload(DevBuf &d, const std::vector<T> &h) {
+  HBI_HIP(d.alloc(h.size() * sizeof(T)));
+  if (!h.empty()) HBI_HIP(hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// Geometry + per-cell device arrays for the current leaf size.
+void setup_cells(hbi_ctx *c) {
+  const double t0 = now_s();
+  c->geo.build(c->dim, c->ncell, c->leaf());
+  c->geo.build_bands(c->band());
+  c->geo_leaf = c->leaf();
+  const int64_t Nv = c->geo.Nv;
+  upload(c->perm_d, c->geo.perm);
+  std::vector<double> slow_t(Nv);
+  for (int64_t p = 0; p < Nv; ++p) slow_t[p] = c->slow_nat[c->geo.perm[p]];
+  upload(c->slow_d, slow_t);
+  HBI_HIP(c->xyz_d.alloc(sizeof(double) * 3 * Nv));
+  HBI_HIP(c->lw_d.alloc(sizeof(double) * c->dim * c->nI * Nv));
+  HBI_HIP(c->box_d.alloc(sizeof(int32_t) * Nv));
+  HBI_HIP(c->self_d.alloc(sizeof(double2) * Nv));
+  const DevProblem P = c->devprob();
+  HBI_HIP(launch_cell_setup(P, c->perm_d.as<int32_t>(), Nv, c->ncell, c->origin,
+                            c->xyz_d.as<double>(), c->lw_d.as<double>(), c->box_d.as<int32_t>(),
+                            c->stream));
+  std::vector<double> gx, gw;
+  gauss_legendre01(32, gx, gw);
+  DevBuf gx_d, gw_d;
+  upload(gx_d, gx);
+  upload(gw_d, gw);
+  HBI_HIP(launch_self_terms(P, c->slow_d.as<double>(), Nv, gx_d.as<double>(), gw_d.as<double>(),
+                            32, c->self_d.as<double2>(), c->stream));
+  c->box_h.resize(Nv);
+  HBI_HIP(hipMemcpyAsync(c->box_h.data(), c->box_d.p, sizeof(int32_t) * Nv,
+                         hipMemcpyDeviceToHost, c->stream));
+  HBI_HIP(hipStreamSynchronize(c->stream));
+  c->t_geo = now_s() - t0;
+}
+
+// ---------------------------------------------------------------------------
+// Batched hb_entry (+ optional interpolative decomposition) on the GPU.
+// ---------------------------------------------------------------------------
+struct BlockIn {
+  const int32_t *rows; int32_t m;
+  const int32_t *cols; int32_t n;
+  double2 *out;        // entry-only blocks: destination (column-major, ld m)
+};
+
+struct BlockOut {
+  int32_t rank = 0;
+  std::vector<int32_t> piv;   // first `rank` pivots
+  const double2 *X = nullptr; // device, rank x n (valid until the next batch)
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Batcher {
+  hbi_ctx *c;
+  explicit Batcher(hbi_ctx *ctx) : c(ctx) {}
+
+  // bytes of workspace a block needs
+  size_t ws_need(int32_t m, int32_t n, int nslot, bool id) const {
+    size_t b = align256((size_t)n * nslot * 3 * c->NTb * sizeof(double));
+    if (id) b += align256((size_t)m * n * sizeof(double2)) +
+                 align256((size_t)std::min(m, n) * n * sizeof(double2));
+    return b;
+  }
+
+  int count_slots(const BlockIn &b, std::vector<int32_t> &slotbox) const {
+    slotbox.clear();
+    for (int32_t i = 0; i < b.m; ++i) {
+      const int32_t bx = c->box_h[b.rows[i]];
+      if (std::find(slotbox.begin(), slotbox.end(), bx) == slotbox.end()) slotbox.push_back(bx);
+    }
+    return (int)slotbox.size();
+  }
+
+  // Process blocks [0, nb) in as many GPU batches as the workspace needs.
+  // id = true: evaluate into the workspace and run the ID, fill outs.
+  // id = false: evaluate straight into blocks[i].out.
+  // `on_batch(first, count)` is called after each ID batch while its X
+  // matrices are still in the workspace.
+  template <class CB>
+  void run(const std::vector<BlockIn> &blocks, bool id, double tol, std::vector<BlockOut> *outs,
+           CB &&on_batch) {
+    const int64_t nb = (int64_t)blocks.size();
+    const size_t budget = (size_t)c->wsbytes();
+    HBI_HIP(c->ws.reserve(budget));
+    std::vector<std::vector<int32_t>> slots(nb);
+    std::vector<int> nslot(nb);
+    parallel_for(nb, [&](int64_t a, int64_t b) {
+      for (int64_t i = a; i < b; ++i) nslot[i] = count_slots(blocks[i], slots[i]);
+    });
+    int64_t i0 = 0;
+    while (i0 < nb) {
+      size_t used = 0;
+      int64_t i1 = i0;
+      while (i1 < nb) {
+        const size_t need = ws_need(blocks[i1].m, blocks[i1].n, nslot[i1], id);
+        if (need > budget)
+          throw Error{HBI_ERR_OOM, "a single block (m=" + std::to_string(blocks[i1].m) + ", n=" +
+                                       std::to_string(blocks[i1].n) + ") exceeds the workspace"};
+        if (used + need > budget) break;
+        used += need;
+        ++i1;
+      }
+      run_batch(blocks, slots, nslot, i0, i1, id, tol, outs);
+      if (id) on_batch(i0, i1 - i0);
+      i0 = i1;
+    }
+  }
+
+  void run_batch(const std::vector<BlockIn> &blocks, const std::vector<std::vector<int32_t>> &slots,
+                 const std::vector<int> &nslot, int64_t i0, int64_t i1, bool id, double tol,
+                 std::vector<BlockOut> *outs) {
+    const int64_t nb = i1 - i0;
+    std::vector<EntryBlock> eb(nb);
+    std::vector<IdBlock> ib(id ? nb : 0);
+    int64_t nrows = 0, ncols = 0, nsl = 0, ncw = 0, new_ = 0;
+    for (int64_t q = 0; q < nb; ++q) {
+      const BlockIn &b = blocks[i0 + q];
+      nrows += b.m; ncols += b.n; nsl += nslot[i0 + q];
+      ncw += (int64_t)b.n * nslot[i0 + q];
+      new_ += b.n;
+    }
+    std::vector<int32_t> rows(nrows), cols(ncols), slotbox(nsl), workc(2 * ncw), worke(2 * new_);
+    std::vector<uint16_t> rowslot(nrows);
+    std::vector<int64_t> pivoff(nb, 0);
+    char *ws = c->ws.as<char>();
+    size_t wso = 0;
+    int64_t ro = 0, co = 0, so = 0, wc = 0, we = 0, po = 0;
+    for (int64_t q = 0; q < nb; ++q) {
+      const BlockIn &b = blocks[i0 + q];
+      const std::vector<int32_t> &sl = slots[i0 + q];
+      const int ns = nslot[i0 + q];
+      EntryBlock &e = eb[q];
+      e.row_off = ro; e.col_off = co; e.slot_off = so; e.m = b.m; e.n = b.n; e.nslot = ns;
+      e.hc_off = (int64_t)(wso / sizeof(double));
+      wso += align256((size_t)b.n * ns * 3 * c->NTb * sizeof(double));
+      if (id) {
+        IdBlock &d = ib[q];
+        d.A = (double2 *)(ws + wso);
+        wso += align256((size_t)b.m * b.n * sizeof(double2));
+        d.X = (double2 *)(ws + wso);
+        wso += align256((size_t)std::min(b.m, b.n) * b.n * sizeof(double2));
+        d.m = b.m; d.n = b.n;
+        d.piv = nullptr;   // set after the index buffer is placed
+        pivoff[q] = po;
+        po += b.n;
+        e.out = d.A;
+      } else {
+        e.out = b.out;
+      }
+      for (int32_t i = 0; i < b.m; ++i) {
+        rows[ro + i] = b.rows[i];
+        const int32_t bx = c->box_h[b.rows[i]];
+        rowslot[ro + i] = (uint16_t)(std::find(sl.begin(), sl.end(), bx) - sl.begin());
+      }
+      std::copy(b.cols, b.cols + b.n, cols.begin() + co);
+      std::copy(sl.begin(), sl.end(), slotbox.begin() + so);
+      for (int32_t j = 0; j < b.n; ++j) {
+        for (int s = 0; s < ns; ++s) {
+          workc[2 * wc] = (int32_t)q;
+          workc[2 * wc + 1] = j * ns + s;
+          ++wc;
+        }
+        worke[2 * we] = (int32_t)q;
+        worke[2 * we + 1] = j;
+        ++we;
+      }
+      ro += b.m; co += b.n; so += ns;
+    }
+    // one index upload: rows, cols, slotbox, workc, worke, rowslot, eb, ib, piv, rank
+    size_t off = 0;
+    auto place = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    const size_t o_rows = place(rows.size() * 4), o_cols = place(cols.size() * 4),
+                 o_slot = place(slotbox.size() * 4), o_wc = place(workc.size() * 4),
+                 o_we = place(worke.size() * 4), o_rs = place(rowslot.size() * 2),
+                 o_eb = place(eb.size() * sizeof(EntryBlock)),
+                 o_ib = place(ib.size() * sizeof(IdBlock)), o_piv = place((size_t)po * 4),
+                 o_rank = place((size_t)nb * 4);
+    HBI_HIP(c->idx_d.reserve(off));
+    char *ix = c->idx_d.as<char>();
+    for (int64_t q = 0; q < (int64_t)ib.size(); ++q) ib[q].piv = (int32_t *)(ix + o_piv) + pivoff[q];
+    std::vector<char> stage(off);
+    auto put = [&](size_t o, const void *src, size_t bytes) { if (bytes) std::memcpy(stage.data() + o, src, bytes); };
+    put(o_rows, rows.data(), rows.size() * 4);
+    put(o_cols, cols.data(), cols.size() * 4);
+    put(o_slot, slotbox.data(), slotbox.size() * 4);
+    put(o_wc, workc.data(), workc.size() * 4);
+    put(o_we, worke.data(), worke.size() * 4);
+    put(o_rs, rowslot.data(), rowslot.size() * 2);
+    put(o_eb, eb.data(), eb.size() * sizeof(EntryBlock));
+    put(o_ib, ib.data(), ib.size() * sizeof(IdBlock));
+    HBI_HIP(hipMemcpyAsync(ix, stage.data(), o_piv, hipMemcpyHostToDevice, c->stream));
+    const DevProblem P = c->devprob();
+    const DevCells C = c->devcells();
+    const DevTables T = c->devtables();
+    HBI_HIP(launch_colside(P, C, T, (const EntryBlock *)(ix + o_eb), (const int32_t *)(ix + o_wc),
+                           ncw, (const int32_t *)(ix + o_cols), (const int32_t *)(ix + o_slot),
+                           c->ws.as<double>(), c->stream));
+    HBI_HIP(launch_entries(P, C, (const EntryBlock *)(ix + o_eb), (const int32_t *)(ix + o_we),
+                           new_, (const int32_t *)(ix + o_rows), (const uint16_t *)(ix + o_rs),
+                           (const int32_t *)(ix + o_cols), c->ws.as<double>(), c->stream));
+    for (int64_t q = 0; q < nb; ++q) c->entries_eval += (int64_t)blocks[i0 + q].m * blocks[i0 + q].n;
+    if (id) {
+      HBI_HIP(launch_cpqr((const IdBlock *)(ix + o_ib), nb, tol, (int32_t *)(ix + o_rank), c->stream));
+      std::vector<int32_t> rank(nb), piv(po);
+      HBI_HIP(hipMemcpyAsync(rank.data(), ix + o_rank, nb * 4, hipMemcpyDeviceToHost, c->stream));
+      if (po) HBI_HIP(hipMemcpyAsync(piv.data(), ix + o_piv, po * 4, hipMemcpyDeviceToHost, c->stream));
+      HBI_HIP(hipStreamSynchronize(c->stream));
+      int64_t pp = 0;
+      for (int64_t q = 0; q < nb; ++q) {
+        BlockOut &o = (*outs)[i0 + q];
+        o.rank = rank[q];
+        if (o.rank < 1 || o.rank > std::min(ib[q].m, ib[q].n))
+          throw Error{HBI_ERR_NUMERIC, "interpolative decomposition returned an invalid rank"};
+        o.piv.assign(piv.begin() + pp, piv.begin() + pp + o.rank);
+        o.X = ib[q].X;
+        pp += ib[q].n;
+        c->nid += 1;
+        c->rank_max = std::max(c->rank_max, o.rank);
+        c->rank_sum += o.rank;
+      }
+    } else {
+      HBI_HIP(hipStreamSynchronize(c->stream));
+    }
+  }
+};
+
+struct BF { int lev; int64_t oi, si; int L; };
+
+struct LevelState {
+  std::vector<int32_t> rank;
+  std::vector<int64_t> skel_off;   // into skel, size nblk+1
+  std::vector<int32_t> skel;       // tree positions
+  std::vector<int64_t> foff;
+  std::vector<int64_t> zoff;
+  void reset(int64_t nblk) {
+    rank.assign(nblk, 0); skel_off.assign(nblk + 1, 0); skel.clear();
+    foff.assign(nblk, 0); zoff.assign(nblk, 0);
+  }
+};
+
+void build_factors(hbi_ctx *c, double tol) {
+  const double tb0 = now_s();
+  if (c->geo_leaf != c->leaf()) setup_cells(c);
+  Geometry &G = c->geo;
+  const int Lv = G.Lv;
+  const int64_t nleaf = (int64_t)1 << Lv;
+  std::vector<BF> bfs;
+  for (int lev = 1; lev <= Lv; ++lev)
+    for (int64_t p = 0; p < ((int64_t)1 << (lev - 1)); ++p) {
+      bfs.push_back({lev, 2 * p, 2 * p + 1, Lv - lev});
+      bfs.push_back({lev, 2 * p + 1, 2 * p, Lv - lev});
+    }
+  const int64_t nbf = (int64_t)bfs.size();
+  const int Lmax = Lv >= 1 ? Lv - 1 : 0;
+  std::vector<LevelState> prev(nbf), cur(nbf);
+  std::vector<Chunk> chunks;
+  int64_t Fg = 0;   // running global element offset
+  std::vector<VDesc> vd((size_t)nleaf * Lv);
+  std::vector<KDesc> kd((size_t)nleaf * Lv);
+  std::vector<std::vector<WUnit>> units(Lmax + 1);
+  ProxyParams pp;
+  pp.chi = c->chi();
+  pp.radius = c->radius();
+  Batcher B(c);
+  c->ztotal = 0;
+  double t_host = 0, t_gpu = 0;
+
+  // Compact the X matrices of an ID batch into a new chunk.
+  auto compact = [&](std::vector<BlockOut> &outs, int64_t first, int64_t cnt,
+                     const std::vector<int32_t> &ncols, std::vector<int64_t> &foff_out) {
+    int64_t tot = 0;
+    for (int64_t q = 0; q < cnt; ++q) tot += (int64_t)outs[first + q].rank * ncols[first + q];
+    Chunk ch;
+    HBI_HIP(ch.buf.alloc(sizeof(double2) * tot));
+    ch.goff = Fg;
+    ch.count = tot;
+    std::vector<CopyDesc> cd(cnt);
+    int64_t o = 0;
+    for (int64_t q = 0; q < cnt; ++q) {
+      const int64_t e = (int64_t)outs[first + q].rank * ncols[first + q];
+      cd[q] = CopyDesc{outs[first + q].X, ch.buf.as<double2>() + o, e};
+      foff_out[first + q] = Fg + o;
+      o += e;
+    }
+    DevBuf cd_d;
+    upload(cd_d, cd);
+    HBI_HIP(launch_copy_blocks(cd_d.as<CopyDesc>(), cnt, c->stream));
+    HBI_HIP(hipStreamSynchronize(c->stream));
+    Fg += tot;
+    chunks.push_back(std::move(ch));
+  };
+
+  for (int k = 0; k <= Lmax && Lv >= 1; ++k) {
+    // enumerate blocks of level k in processing order
+    struct Blk { int32_t b; int32_t t; int64_t j; };
+    std::vector<Blk> blks;
+    for (int64_t b = 0; b < nbf; ++b) {
+      const int L = bfs[b].L;
+      if (L < k) continue;
+      cur[b].reset((int64_t)1 << L);
+      if (k == 0) {
+        for (int64_t j = 0; j < ((int64_t)1 << L); ++j) blks.push_back({(int32_t)b, 0, j});
+      } else {
+        for (int64_t tp = 0; tp < ((int64_t)1 << (k - 1)); ++tp)
+          for (int64_t j = 0; j < ((int64_t)1 << (L - k)); ++j)
+            for (int cc = 0; cc < 2; ++cc) blks.push_back({(int32_t)b, (int32_t)(2 * tp + cc), j});
+      }
+    }
+    const int64_t nblk = (int64_t)blks.size();
+    // per-block skeleton staging (filled as batches finish)
+    std::vector<std::vector<int32_t>> skel_tmp(nblk);
+    std::vector<int32_t> rank_tmp(nblk);
+    std::vector<int64_t> foff_tmp(nblk);
+    const int64_t CH = 16384;
+    for (int64_t c0 = 0; c0 < nblk; c0 += CH) {
+      const int64_t c1 = std::min(nblk, c0 + CH);
+      const double th = now_s();
+      std::vector<std::vector<int32_t>> rows(c1 - c0), cands(c1 - c0);
+      parallel_for(c1 - c0, [&](int64_t a, int64_t e) {
+        std::vector<int32_t> stamp(G.Nv, 0);
+        int32_t tag = 0;
+        for (int64_t q = a; q < e; ++q) {
+          const Blk &bk = blks[c0 + q];
+          const BF &bf = bfs[bk.b];
+          const int L = bf.L;
+          std::vector<int32_t> &cd = cands[q];
+          if (k == 0) {
+            const int64_t nd = Geometry::node(bf.lev + L, (bf.si << L) + bk.j);
+            for (int32_t p = G.nstart[nd]; p < G.nend[nd]; ++p) cd.push_back(p);
+          } else {
+            const LevelState &ps = prev[bk.b];
+            const int64_t in = (int64_t)(bk.t >> 1) * ((int64_t)1 << (L - k + 1)) + 2 * bk.j;
+            cd.insert(cd.end(), ps.skel.begin() + ps.skel_off[in], ps.skel.begin() + ps.skel_off[in + 2]);
+          }
+          const int64_t tnode = Geometry::node(bf.lev + k, (bf.oi << k) + bk.t);
+          if (k == L) {
+            rows[q].resize(G.nend[tnode] - G.nstart[tnode]);
+            for (size_t i = 0; i < rows[q].size(); ++i) rows[q][i] = G.nstart[tnode] + (int32_t)i;
+          } else {
+            proxy_rows(G, tnode, cd.data(), (int)cd.size(), pp, rows[q], stamp, ++tag);
+          }
+        }
+      });
+      t_host += now_s() - th;
+      const double tg = now_s();
+      std::vector<BlockIn> bin(c1 - c0);
+      std::vector<int32_t> ncols(c1 - c0);
+      for (int64_t q = 0; q < c1 - c0; ++q) {
+        bin[q] = BlockIn{rows[q].data(), (int32_t)rows[q].size(), cands[q].data(),
+                         (int32_t)cands[q].size(), nullptr};
+        ncols[q] = (int32_t)cands[q].size();
+        if (ncols[q] > HBI_ID_NMAX)
+          throw Error{HBI_ERR_NUMERIC, "candidate set larger than the ID kernel supports"};
+      }
+      std::vector<BlockOut> outs(c1 - c0);
+      std::vector<int64_t> foff_local(c1 - c0);
+      B.run(bin, true, tol, &outs, [&](int64_t first, int64_t cnt) {
+        compact(outs, first, cnt, ncols, foff_local);
+      });
+      for (int64_t q = 0; q < c1 - c0; ++q) {
+        skel_tmp[c0 + q].resize(outs[q].rank);
+        for (int32_t r = 0; r < outs[q].rank; ++r) skel_tmp[c0 + q][r] = cands[q][outs[q].piv[r]];
+        rank_tmp[c0 + q] = outs[q].rank;
+        foff_tmp[c0 + q] = foff_local[q];
+        const int64_t e = (int64_t)outs[q].rank * ncols[q];
+        if (k == 0) c->nnz_v += e; else c->nnz_w += e;
+      }
+      t_gpu += now_s() - tg;
+    }
+    // scatter into per-butterfly state (block index t * 2^(L-k) + j)
+    for (int64_t q = 0; q < nblk; ++q) {
+      const Blk &bk = blks[q];
+      const int L = bfs[bk.b].L;
+      const int64_t bi = (int64_t)bk.t * ((int64_t)1 << (L - k)) + bk.j;
+      cur[bk.b].rank[bi] = rank_tmp[q];
+      cur[bk.b].foff[bi] = foff_tmp[q];
+    }
+    for (int64_t b = 0; b < nbf; ++b) {
+      if (bfs[b].L < k) continue;
+      LevelState &cs = cur[b];
+      const int64_t n = (int64_t)cs.rank.size();
+      for (int64_t bi = 0; bi < n; ++bi) cs.skel_off[bi + 1] = cs.skel_off[bi] + cs.rank[bi];
+      cs.skel.resize(cs.skel_off[n]);
+    }
+    for (int64_t q = 0; q < nblk; ++q) {
+      const Blk &bk = blks[q];
+      const int L = bfs[bk.b].L;
+      const int64_t bi = (int64_t)bk.t * ((int64_t)1 << (L - k)) + bk.j;
+      std::copy(skel_tmp[q].begin(), skel_tmp[q].end(), cur[bk.b].skel.begin() + cur[bk.b].skel_off[bi]);
+    }
+    // z offsets in (t, j) order, then descriptors
+    for (int64_t b = 0; b < nbf; ++b) {
+      const BF &bf = bfs[b];
+      if (bf.L < k) continue;
+      LevelState &cs = cur[b];
+      for (size_t bi = 0; bi < cs.rank.size(); ++bi) { cs.zoff[bi] = c->ztotal; c->ztotal += cs.rank[bi]; }
+      const int L = bf.L;
+      if (k == 0) {
+        for (int64_t j = 0; j < ((int64_t)1 << L); ++j) {
+          const int64_t g = (bf.si << L) + j;
+          vd[g * Lv + (bf.lev - 1)] = VDesc{cs.foff[j], cs.zoff[j], cs.rank[j], 0};
+        }
+      } else {
+        const LevelState &ps = prev[b];
+        for (int64_t tp = 0; tp < ((int64_t)1 << (k - 1)); ++tp)
+          for (int64_t j = 0; j < ((int64_t)1 << (L - k)); ++j) {
+            const int64_t a = (2 * tp) * ((int64_t)1 << (L - k)) + j;
+            const int64_t bb = (2 * tp + 1) * ((int64_t)1 << (L - k)) + j;
+            const int64_t in = tp * ((int64_t)1 << (L - k + 1)) + 2 * j;
+            WUnit U{};
+            U.ra = cs.rank[a]; U.rb = cs.rank[bb];
+            U.c = ps.rank[in] + ps.rank[in + 1];
+            U.foff = cs.foff[a];
+            U.zin = ps.zoff[in];
+            U.zouta = cs.zoff[a];
+            U.zoutb = cs.zoff[bb];
+            if (ps.zoff[in + 1] != ps.zoff[in] + ps.rank[in] ||
+                cs.foff[bb] != cs.foff[a] + (int64_t)U.ra * U.c)
+              throw Error{HBI_ERR_NUMERIC, "internal layout error in the transfer stage"};
+            units[k].push_back(U);
+          }
+      }
+    }
+    // skeleton factors K^L for butterflies ending at this level
+    {
+      std::vector<std::pair<int64_t, int64_t>> kl;   // (butterfly, t)
+      int64_t tot = 0;
+      for (int64_t b = 0; b < nbf; ++b) {
+        if (bfs[b].L != k) continue;
+        for (int64_t t = 0; t < ((int64_t)1 << k); ++t) {
+          const int64_t nd = Geometry::node(bfs[b].lev + k, (bfs[b].oi << k) + t);
+          tot += (int64_t)(G.nend[nd] - G.nstart[nd]) * cur[b].rank[t];
+          kl.push_back({b, t});
+        }
+      }
+      if (!kl.empty()) {
+        const double tg = now_s();
+        Chunk ch;
+        HBI_HIP(ch.buf.alloc(sizeof(double2) * tot));
+        ch.goff = Fg;
+        ch.count = tot;
+        std::vector<BlockIn> bin;
+        std::vector<std::vector<int32_t>> rws(kl.size());
+        int64_t o = 0;
+        for (size_t q = 0; q < kl.size(); ++q) {
+          const auto [b, t] = kl[q];
+          const BF &bf = bfs[b];
+          const int64_t nd = Geometry::node(bf.lev + k, (bf.oi << k) + t);
+          const int32_t sz = G.nend[nd] - G.nstart[nd];
+          rws[q].resize(sz);
+          for (int32_t i = 0; i < sz; ++i) rws[q][i] = G.nstart[nd] + i;
+          const LevelState &cs = cur[b];
+          bin.push_back(BlockIn{rws[q].data(), sz, cs.skel.data() + cs.skel_off[t], cs.rank[t],
+                                ch.buf.as<double2>() + o});
+          const int64_t g = (bf.oi << k) + t;
+          kd[g * Lv + (bf.lev - 1)] = KDesc{Fg + o, cs.zoff[t], cs.rank[t], 0};
+          o += (int64_t)sz * cs.rank[t];
+        }
+        B.run(bin, false, tol, nullptr, [](int64_t, int64_t) {});
+        Fg += tot;
+        c->nnz_k += tot;
+        chunks.push_back(std::move(ch));
+        t_gpu += now_s() - tg;
+      }
+    }
+    std::swap(prev, cur);
+  }
+
+  // dense diagonal leaves
+  std::vector<LeafInfo> leaves(nleaf);
+  {
+    const double tg = now_s();
+    int64_t tot = 0;
+    for (int64_t g = 0; g < nleaf; ++g) {
+      const int64_t nd = Geometry::node(Lv, g);
+      const int64_t sz = G.nend[nd] - G.nstart[nd];
+      tot += sz * sz;
+    }
+    Chunk ch;
+    HBI_HIP(ch.buf.alloc(sizeof(double2) * tot));
+    ch.goff = Fg;
+    ch.count = tot;
+    std::vector<std::vector<int32_t>> rws(nleaf);
+    std::vector<BlockIn> bin(nleaf);
+    int64_t o = 0;
+    for (int64_t g = 0; g < nleaf; ++g) {
+      const int64_t nd = Geometry::node(Lv, g);
+      const int32_t sz = G.nend[nd] - G.nstart[nd];
+      rws[g].resize(sz);
+      for (int32_t i = 0; i < sz; ++i) rws[g][i] = G.nstart[nd] + i;
+      bin[g] = BlockIn{rws[g].data(), sz, rws[g].data(), sz, ch.buf.as<double2>() + o};
+      leaves[g] = LeafInfo{G.nstart[nd], sz, Fg + o};
+      o += (int64_t)sz * sz;
+    }
+    B.run(bin, false, tol, nullptr, [](int64_t, int64_t) {});
+    Fg += tot;
+    c->nnz_d += tot;
+    chunks.push_back(std::move(ch));
+    t_gpu += now_s() - tg;
+  }
+
+  // final factor store (FP64 or rounded to FP32)
+  const double tf = now_s();
+  c->Felems = Fg;
+  const size_t esz = c->prec == HBI_F64 ? sizeof(double2) : sizeof(float2);
+  HBI_HIP(c->F.alloc(esz * std::max<int64_t>(Fg, 1)));
+  for (auto &ch : chunks) {
+    if (ch.count == 0) continue;
+    if (c->prec == HBI_F64) {
+      HBI_HIP(hipMemcpyAsync(c->F.as<double2>() + ch.goff, ch.buf.p, sizeof(double2) * ch.count,
+                             hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      HBI_HIP(launch_to_f32(ch.buf.as<double2>(), c->F.as<float2>() + ch.goff, ch.count, c->stream));
+    }
+  }
+  HBI_HIP(hipStreamSynchronize(c->stream));
+  chunks.clear();
+  upload(c->leaves_d, leaves);
+  upload(c->vd_d, vd);
+  upload(c->kd_d, kd);
+  c->units_d.clear();
+  c->units_d.resize(Lmax + 1);
+  c->plan = ApplyPlan();
+  c->plan.Lv = Lv;
+  c->plan.Lmax = Lv >= 1 ? Lmax : 0;
+  c->plan.nleaf = nleaf;
+  c->plan.leaves = c->leaves_d.as<LeafInfo>();
+  c->plan.perm = c->perm_d.as<int32_t>();
+  c->plan.vd = c->vd_d.as<VDesc>();
+  c->plan.kd = c->kd_d.as<KDesc>();
+  c->plan.units.assign(Lmax + 1, nullptr);
+  c->plan.nunits.assign(Lmax + 1, 0);
+  for (int k = 1; k <= Lmax; ++k) {
+    upload(c->units_d[k], units[k]);
+    c->plan.units[k] = c->units_d[k].as<WUnit>();
+    c->plan.nunits[k] = (int64_t)units[k].size();
+  }
+  HBI_HIP(c->z_d.alloc(esz * std::max<int64_t>(c->ztotal, 1)));
+  c->t_final = now_s() - tf;
+  c->t_host = t_host;
+  c->t_gpu = t_gpu;
+  c->t_build = now_s() - tb0;
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+  const char *x = (const char *)a, *y = (const char *)b;
+  return x < y + nb && y < x + na;
+}
+
+void check_apply_args(hbi_ctx *c, const void *s, void *u, int32_t nrhs, int64_t ld) {
+  HBI_REQUIRE(c->state == 2, HBI_ERR_STATE, "apply before build");
+  HBI_REQUIRE(s && u, HBI_ERR_ARG, "null s or u");
+  HBI_REQUIRE(nrhs >= 1, HBI_ERR_ARG, "nrhs must be >= 1");
+  HBI_REQUIRE(ld >= c->geo.Nv, HBI_ERR_ARG, "ld must be >= N_v");
+  const size_t esz = c->prec == HBI_F64 ? 16 : 8;
+  const size_t span = esz * ((size_t)ld * (nrhs - 1) + c->geo.Nv);
+  HBI_REQUIRE(!overlap(s, span, u, span), HBI_ERR_ARG, "s and u overlap");
+}
+
+void do_apply(hbi_ctx *c, const void *s, void *u, int32_t nrhs, int64_t ld, bool adj) {
+  check_apply_args(c, s, u, nrhs, ld);
+  const size_t esz = c->prec == HBI_F64 ? 16 : 8;
+  for (int32_t r = 0; r < nrhs; ++r) {
+    const char *sc = (const char *)s + esz * (size_t)ld * r;
+    char *uc = (char *)u + esz * (size_t)ld * r;
+    if (c->prec == HBI_F64) {
+      HBI_HIP(launch_apply<double>(c->plan, sc, uc, c->z_d.p, c->F.p, std::pow(c->h, c->dim), adj,
+                                   c->stream));
+    } else {
+      HBI_HIP(launch_apply<float>(c->plan, sc, uc, c->z_d.p, c->F.p, (float)std::pow(c->h, c->dim),
+                                  adj, c->stream));
+    }
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+hbi_status hbi_create(int device, void *hip_stream, hbi_ctx **out) {
+  return guarded(nullptr, [&]() {
+    HBI_REQUIRE(out, HBI_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HBI_HIP(hipGetDeviceCount(&n));
+    HBI_REQUIRE(device >= 0 && device < n, HBI_ERR_ARG, "device index out of range");
+    HBI_HIP(hipSetDevice(device));
+    auto c = std::make_unique<hbi_ctx>();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c.release();
+  });
+}
+
+hbi_status hbi_destroy(hbi_ctx *ctx) {
+  if (!ctx) return HBI_OK;
+  (void)hipSetDevice(ctx->device);
+  delete ctx;
+  return HBI_OK;
+}
+
+hbi_status hbi_set_stream(hbi_ctx *ctx, void *hip_stream) {
+  if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
+  ctx->stream = (hipStream_t)hip_stream;
+  return HBI_OK;
+}
+
+hbi_status hbi_load_tables(hbi_ctx *ctx, const hbi_tables *t) {
+  if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
+  return guarded(ctx, [&]() {
+    HBI_REQUIRE(t, HBI_ERR_ARG, "tables is NULL");
+    HBI_REQUIRE(t->dim == 2 || t->dim == 3, HBI_ERR_ARG, "dim must be 2 or 3");
+    const int d = t->dim;
+    int64_t Nv = 1;
+    for (int a = 0; a < d; ++a) {
+      HBI_REQUIRE(t->ncell[a] >= 1, HBI_ERR_ARG, "ncell must be >= 1");
+      HBI_REQUIRE(t->nbox[a] >= 1, HBI_ERR_ARG, "nbox must be >= 1");
+      Nv *= t->ncell[a];
+    }
+    HBI_REQUIRE(Nv <= ((int64_t)1 << 30), HBI_ERR_ARG, "N_v too large");
+    HBI_REQUIRE(t->h > 0 && std::isfinite(t->h), HBI_ERR_ARG, "h must be > 0");
+    HBI_REQUIRE(t->omega > 0 && std::isfinite(t->omega), HBI_ERR_ARG, "omega must be > 0");
+    HBI_REQUIRE(t->nterms == 1 || t->nterms == 2, HBI_ERR_ARG, "nterms must be 1 or 2");
+    HBI_REQUIRE(t->nI >= 2 && t->nI <= HBI_MAX_NI, HBI_ERR_ARG, "nI must be in [2, 16]");
+    HBI_REQUIRE(t->box_size > 0, HBI_ERR_ARG, "box_size must be > 0");
+    HBI_REQUIRE(t->tau2 && t->v0 && t->slowness, HBI_ERR_ARG, "null table or slowness");
+    HBI_REQUIRE(t->nterms == 1 || t->v1, HBI_ERR_ARG, "v1 is NULL but nterms == 2");
+    for (int a = 0; a < d; ++a) {
+      const double lo = t->origin[a], hi = t->origin[a] + t->ncell[a] * t->h;
+      const double blo = t->box_origin[a], bhi = t->box_origin[a] + t->nbox[a] * t->box_size;
+      const double eps = 1e-12 * std::max(1.0, std::fabs(bhi - blo));
+      HBI_REQUIRE(lo + 0.5 * t->h >= blo - eps && hi - 0.5 * t->h <= bhi + eps, HBI_ERR_ARG,
+                  "cell centres lie outside the table region");
+    }
+    hbi_ctx *c = ctx;
+    c->drop_factors();
+    c->state = 0;
+    c->dim = d;
+    c->nterms = t->nterms;
+    c->nI = t->nI;
+    c->NTb = 1;
+    int64_t nboxes = 1;
+    for (int a = 0; a < 3; ++a) {
+      c->ncell[a] = a < d ? t->ncell[a] : 1;
+      c->nbox[a] = a < d ? t->nbox[a] : 1;
+      c->origin[a] = a < d ? t->origin[a] : 0.0;
+      c->box_origin[a] = a < d ? t->box_origin[a] : 0.0;
+    }
+    for (int a = 0; a < d; ++a) { c->NTb *= t->nI; nboxes *= t->nbox[a]; }
+    HBI_REQUIRE(nboxes * c->NTb <= (1 << 16), HBI_ERR_ARG, "table too large");
+    c->NT = (int)(nboxes * c->NTb);
+    c->h = t->h;
+    c->omega = t->omega;
+    c->box_size = t->box_size;
+    c->slow_nat.assign(t->slowness, t->slowness + Nv);
+    for (double v : c->slow_nat)
+      HBI_REQUIRE(std::isfinite(v) && v > 0, HBI_ERR_ARG, "slowness must be finite and > 0");
+    // transposed tables (FT[B*NT + A] = F[A*NT + B]) so the kernels read them contiguously
+    const int64_t NT = c->NT;
+    const double *src[3] = {t->tau2, t->v0, t->nterms == 2 ? t->v1 : nullptr};
+    std::vector<double> tr((size_t)NT * NT);
+    for (int k = 0; k < 3; ++k) {
+      if (!src[k]) { std::fill(tr.begin(), tr.end(), 0.0); }
+      else {
+        const double *F = src[k];
+        parallel_for(NT, [&](int64_t b0, int64_t b1) {
+          for (int64_t B = b0; B < b1; ++B)
+            for (int64_t A = 0; A < NT; ++A) tr[B * NT + A] = F[A * NT + B];
+        });
+      }
+      upload(c->FT_d[k], tr);
+    }
+    setup_cells(c);
+    c->state = 1;
+  });
+}
+
+hbi_status hbi_set_build_opts(hbi_ctx *ctx, const hbi_build_opts *opts) {
+  if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
+  return guarded(ctx, [&]() {
+    if (!opts) { ctx->opts = hbi_build_opts{}; return; }
+    HBI_REQUIRE(opts->leaf_size <= HBI_MAX_LEAF, HBI_ERR_ARG, "leaf_size must be <= 64");
+    HBI_REQUIRE(std::isfinite(opts->chi) && std::isfinite(opts->neighbor_radius), HBI_ERR_ARG,
+                "non-finite option");
+    ctx->opts = *opts;
+  });
+}
+
+hbi_status hbi_build(hbi_ctx *ctx, double tol, hbi_prec prec) {
+  if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
+  return guarded(ctx, [&]() {
+    HBI_REQUIRE(ctx->state >= 1, HBI_ERR_STATE, "build before tables");
+    HBI_REQUIRE(tol > 0 && tol < 1, HBI_ERR_ARG, "tol must be in (0, 1)");
+    HBI_REQUIRE(prec == HBI_F64 || prec == HBI_F32, HBI_ERR_ARG, "bad precision");
+    ctx->drop_factors();
+    ctx->prec = prec;
+    ctx->tol = tol;
+    build_factors(ctx, tol);
+    ctx->state = 2;
+  });
+}
+
+hbi_status hbi_apply(hbi_ctx *ctx, const void *s, void *u, int32_t nrhs, int64_t ld) {
+  if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
+  return guarded(ctx, [&]() { do_apply(ctx, s, u, nrhs, ld, false); });
+}
+
+hbi_status hbi_apply_adjoint(hbi_ctx *ctx, const void *s, void *u, int32_t nrhs, int64_t ld) {
+  if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
+  return guarded(ctx, [&]() { do_apply(ctx, s, u, nrhs, ld, true); });
+}
+
+hbi_status hbi_entries(hbi_ctx *ctx, const int32_t *rows, int32_t m, const int32_t *cols,
+                       int32_t n, void *out) {
+  if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
+  return guarded(ctx, [&]() {
+    HBI_REQUIRE(ctx->state >= 1, HBI_ERR_STATE, "entries before tables");
+    HBI_REQUIRE(m >= 0 && n >= 0, HBI_ERR_ARG, "negative size");
+    if (m == 0 || n == 0) return;
+    HBI_REQUIRE(rows && cols && out, HBI_ERR_ARG, "null pointer");
+    const int64_t Nv = ctx->geo.Nv;
+    std::vector<int32_t> rp(m), cp(n);
+    for (int32_t i = 0; i < m; ++i) {
+      HBI_REQUIRE(rows[i] >= 0 && rows[i] < Nv, HBI_ERR_ARG, "row index out of range");
+      rp[i] = ctx->geo.ipos[rows[i]];
+    }
+    for (int32_t j = 0; j < n; ++j) {
+      HBI_REQUIRE(cols[j] >= 0 && cols[j] < Nv, HBI_ERR_ARG, "column index out of range");
+      cp[j] = ctx->geo.ipos[cols[j]];
+    }
+    std::vector<BlockIn> bin;
+    const int32_t CW = 256;
+    for (int32_t j0 = 0; j0 < n; j0 += CW) {
+      const int32_t nn = std::min(CW, n - j0);
+      bin.push_back(BlockIn{rp.data(), m, cp.data() + j0, nn, (double2 *)out + (int64_t)j0 * m});
+    }
+    Batcher B(ctx);
+    B.run(bin, false, 0.0, nullptr, [](int64_t, int64_t) {});
+  });
+}
+
+hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
+  hbi_ctx *ctx = const_cast<hbi_ctx *>(cctx);
+  if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
+  if (!json || cap <= 0) { ctx->err = "null or empty output buffer"; return HBI_ERR_ARG; }
+  const int64_t Nv = ctx->geo.Nv;
+  const size_t esz = ctx->prec == HBI_F64 ? 16 : 8;
+  char buf[2048];
+  const int len = std::snprintf(
+      buf, sizeof buf,
+      "{\"state\": %d, \"dim\": %d, \"N_v\": %lld, \"L_v\": %d, \"NT\": %d, \"nI\": %d, "
+      "\"prec\": \"%s\", \"tol\": %.3e, \"chi\": %.3f, \"leaf_size\": %d, "
+      "\"nnz_v\": %lld, \"nnz_w\": %lld, \"nnz_k\": %lld, \"nnz_dense\": %lld, "
+      "\"nnz_total\": %lld, \"factor_bytes\": %lld, \"z_entries\": %lld, "
+      "\"n_id\": %lld, \"rank_max\": %d, \"rank_mean\": %.3f, \"entries_evaluated\": %lld, "
+      "\"build_s\": %.6f, \"build_geometry_s\": %.6f, \"build_proxy_host_s\": %.6f, "
+      "\"build_gpu_s\": %.6f, \"build_finalize_s\": %.6f}",
+      ctx->state, ctx->dim, (long long)Nv, ctx->geo.Lv, ctx->NT, ctx->nI,
+      ctx->prec == HBI_F64 ? "f64" : "f32", ctx->tol, ctx->chi(), ctx->leaf(),
+      (long long)ctx->nnz_v, (long long)ctx->nnz_w, (long long)ctx->nnz_k, (long long)ctx->nnz_d,
+      (long long)ctx->Felems, (long long)(ctx->Felems * (int64_t)esz), (long long)ctx->ztotal,
+      (long long)ctx->nid, ctx->rank_max, ctx->nid ? ctx->rank_sum / ctx->nid : 0.0,
+      (long long)ctx->entries_eval, ctx->t_build, ctx->t_geo, ctx->t_host, ctx->t_gpu,
+      ctx->t_final);
+  if (len < 0 || len >= cap) { ctx->err = "output buffer too small"; return HBI_ERR_ARG; }
+  std::memcpy(json, buf, len + 1);
+  return HBI_OK;
+}
+
+const char *hbi_last_error(const hbi_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_err.c_str();
+}
+
+}  // extern "C"
