@@ -1,0 +1,202 @@
+"""Benchmark of the HB integrator apply on one MI355X.
+
+Workload (default): 2D Gaussian-bump medium n = 1 + 0.3 exp(-|r-(1/2,1/2)|^2
+/ (2 * 0.1^2)) on the unit square, 1024 x 1024 cells (128 wavelengths at
+n = 1, omega = 256 pi), piecewise Chebyshev tables (8 x 8 boxes x 8 x 8
+nodes), one seeded complex N(0,1) right-hand side.
+
+Per run:
+  1. FP64 build at tol 1e-7 and FP32 build (FP64 QR/ID, factors rounded to
+     complex64) at tol 1e-6; build seconds are wall time of hbi_build.
+  2. Parity: relative L2 error of each apply against the FP64 CPU oracle on
+     seeded sampled rows.
+  3. Timed applies u = K (h^d s) with the input resident in HBM: W warm-up
+     steps, then K timed steps between device synchronisations.  `value`
+     is the FP32 apply throughput in Gcell*RHS/s (the metric's rel. error
+     bound is 1e-4); the FP64 figures are reported beside it.
+  4. Roofline: per-kernel HIP-event durations recorded by the library on
+     its stream during the timed steps; algorithmic bytes from the factor
+     layout.
+  5. CPU baseline: the oracle (as is) on a bounded sample of rows on the
+     host, scaled to Gcell*RHS/s.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "HB butterfly apply Gcell·RHS/s at rel err ≤1e-4; build s; % HBM/MFMA peak"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n-side", type=int, default=1024)
+    ap.add_argument("--tol64", type=float, default=1e-7)
+    ap.add_argument("--tol32", type=float, default=1e-6)
+    ap.add_argument("--chi", type=float, default=0.0, help="proxy oversampling (0 = library default)")
+    ap.add_argument("--oracle-rows", type=int, default=24)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one device copy of this many MiB first (HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import hb_inputs
+    import paper_2210_02698_amd as hbi
+
+    if not os.path.exists(os.path.join(ROOT, "paper_2210_02698_amd", "libhbi.so")):
+        from paper_2210_02698_amd import build as _b
+        _b.build()
+
+    dev = torch.device("cuda:0")
+    if args.calib_copy_mb:
+        n = args.calib_copy_mb << 20
+        a = torch.empty(n, dtype=torch.uint8, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {n} bytes done")
+        del a, b
+    t0 = time.time()
+    prob = hb_inputs.configs.c2(args.n_side)
+    log(f"problem {prob.name}: N_v={prob.Nv} NT={prob.NT} tables {time.time() - t0:.1f}s")
+    s_h = hb_inputs.complex_normal(prob.Nv, [hb_inputs.configs.CFG_SEED["c2"], 0])
+    rows = np.sort(np.random.default_rng([2, 7]).choice(prob.Nv, args.oracle_rows, replace=False))
+
+    # oracle on the sampled rows: parity reference and CPU baseline
+    cpu = None
+    ref = None
+    if not args.no_cpu:
+        import oracle
+        try:
+            from threadpoolctl import threadpool_limits
+            limiter = threadpool_limits(1)
+        except Exception:
+            limiter = None
+        t0 = time.perf_counter()
+        ref = oracle.apply(prob, s_h, rows)
+        t_or = time.perf_counter() - t0
+        if limiter is not None:
+            limiter.restore_original_limits()
+        cpu = {"value": args.oracle_rows / t_or / 1e9, "unit": "Gcell·RHS/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{args.oracle_rows} seeded rows of the dense FP64 oracle u = K h^d s "
+                         f"(each row: {prob.Nv} HB entries from the tables), single thread, "
+                         f"{t_or:.1f} s; full-apply time extrapolates to "
+                         f"{t_or * prob.Nv / args.oracle_rows / 3600:.1f} h"}
+        log(f"oracle {args.oracle_rows} rows in {t_or:.1f}s")
+
+    def timed(op, s):
+        for _ in range(args.warmup):
+            op.apply(s)
+        torch.cuda.synchronize()
+        op.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            op.apply(s)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        prof = op.profile(False)
+        return dt, prof
+
+    results = {}
+    for prec, tol in (("f64", args.tol64), ("f32", args.tol32)):
+        if prec == "f64" and args.no_fp64:
+            continue
+        op = hbi.Operator(prob, device=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op.build(tol=tol, prec=prec, chi=args.chi or None)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        info = op.info()
+        log(f"{prec} build {build_s:.2f}s info {info}")
+        dt = torch.complex128 if prec == "f64" else torch.complex64
+        s = torch.from_numpy(s_h).to(dev).to(dt)
+        u = op.apply(s)
+        torch.cuda.synchronize()
+        err = None
+        if ref is not None:
+            ug = u.cpu().numpy().astype(np.complex128)[rows]
+            err = float(np.linalg.norm(ug - ref) / np.linalg.norm(ref))
+        t_apply, prof = timed(op, s)
+        esz = 16 if prec == "f64" else 8
+        fbytes = info["nnz_total"] * esz
+        vec_bytes = (2 * prob.Nv + 2 * info["z_entries"]) * esz
+        results[prec] = dict(build_s=build_s, err=err, ms=t_apply * 1e3, info=info, prof=prof,
+                             gcells=prob.Nv / t_apply / 1e9,
+                             apply_gbs=(fbytes + vec_bytes) / t_apply / 1e9,
+                             factor_bytes=fbytes)
+        log(f"{prec} apply {t_apply * 1e3:.3f} ms  err {err}  prof {prof}")
+        op.close()
+        del op
+        torch.cuda.empty_cache()
+
+    head = results["f32"]
+    # dominant kernel roofline from the library's per-kernel event timings
+    prof = head["prof"]
+    dom = max(prof["kernels"], key=lambda k: prof["kernels"][k]["ms"])
+    kd = prof["kernels"][dom]
+    achieved = kd["bytes"] / (kd["ms"] / kd["launches"] * 1e-3) / kd["launches"] / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(head["gcells"], 6),
+        "unit": "Gcell·RHS/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 (fp32 factors and accumulation; fp64 phase, weights and QR in the build)",
+        "data": "synthetic (seeded inputs; straight-ray stand-in tables)",
+        "config": {"workload": f"2D Gaussian-bump medium, {args.n_side}x{args.n_side} cells, "
+                               f"omega={2 * args.n_side / 8:.0f}pi, 1 RHS",
+                   "N_v": prob.Nv, "nrhs": 1, "tol_fp32_build": args.tol32,
+                   "tol_fp64_build": args.tol64, "parallelism": "single GPU"},
+        "rel_err_vs_oracle": head["err"],
+        "build_s": round(head["build_s"], 3),
+        "apply_achieved_GBs": round(head["apply_gbs"], 1),
+        "apply_hbm_frac": round(head["apply_gbs"] / HBM_PEAK_GBS, 4),
+        "factor_bytes": head["factor_bytes"],
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    if "f64" in results:
+        r = results["f64"]
+        line["fp64"] = {"value": round(r["gcells"], 6), "ms_per_step": round(r["ms"], 4),
+                        "rel_err_vs_oracle": r["err"], "build_s": round(r["build_s"], 3),
+                        "apply_achieved_GBs": round(r["apply_gbs"], 1),
+                        "factor_bytes": r["factor_bytes"]}
+        line["fp32_speedup_over_fp64"] = round(r["ms"] / head["ms"], 3)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -138,6 +138,19 @@ hbi_status hbi_apply_adjoint(hbi_ctx *ctx, const void *s, void *u,
 hbi_status hbi_entries(hbi_ctx *ctx, const int32_t *rows, int32_t m,
                        const int32_t *cols, int32_t n, void *out);
 
+/* Per-kernel timing of applies.  While enabled (enable != 0), every
+ * hbi_apply / hbi_apply_adjoint records a HIP event pair on the context's
+ * stream around each of its kernel launches.  Used to report achieved
+ * bandwidth against the HBM roofline; costs a few microseconds per launch. */
+hbi_status hbi_set_profiling(hbi_ctx *ctx, int32_t enable);
+
+/* Synchronise the context's stream and write JSON
+ * {"kernels": {name: {"launches": n, "ms": total, "bytes": total}}} for
+ * the launches recorded since profiling was enabled (bytes are the
+ * algorithmic HBM bytes of each launch: factor entries streamed, vector
+ * entries read and written, descriptors), then clear the record. */
+hbi_status hbi_get_profile(hbi_ctx *ctx, char *json, int64_t cap);
+
 /* JSON description of the context into json[0..cap): sizes, ranks, stored
  * factor entries and bytes, build timings.  Fails with HBI_ERR_ARG when cap
  * is too small. */

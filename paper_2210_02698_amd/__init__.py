@@ -118,7 +118,7 @@ class Operator:
         if S.shape[0] != self.Nv:
             raise ValueError(f"expected {self.Nv} rows, got {S.shape[0]}")
         # column-major N_v x nrhs: a row-major (nrhs, N_v) buffer transposed
-        if not (S.stride(0) == 1 and (S.shape[1] == 1 or S.stride(1) >= self.Nv)):
+        if not (S.stride(0) == 1 and (S.shape[1] == 1 or S.stride(1) == self.Nv)):
             S = S.t().contiguous().t()
         return S, vec
 
@@ -158,6 +158,17 @@ class Operator:
     def info(self) -> dict:
         buf = ctypes.create_string_buffer(8192)
         self._check(self._lib.hbi_get_info(self._ctx, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    def profile(self, enable: bool):
+        """Turn per-kernel event timing of applies on (returns None) or off
+        (returns the recorded {"kernels": {name: {launches, ms, bytes}}})."""
+        if enable:
+            self._check(self._lib.hbi_set_profiling(self._ctx, 1))
+            return None
+        buf = ctypes.create_string_buffer(1 << 16)
+        self._check(self._lib.hbi_get_profile(self._ctx, buf, len(buf)))
+        self._check(self._lib.hbi_set_profiling(self._ctx, 0))
         return json.loads(buf.value.decode())
 
     def close(self):

@@ -64,6 +64,8 @@ SIGNATURES = [
                                          ctypes.c_int32, ctypes.c_int64]),
     ("hbi_entries", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_void_p]),
+    ("hbi_set_profiling", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    ("hbi_get_profile", ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]),
     ("hbi_get_info", ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]),
     ("hbi_last_error", ctypes.c_char_p, [ctypes.c_void_p]),
 ]

@@ -52,7 +52,7 @@ struct IdBlock {
 struct VDesc { int64_t foff; int64_t zout; int32_t r; int32_t pad; };
 struct KDesc { int64_t foff; int64_t zin; int32_t r; int32_t pad; };
 struct WUnit {
-  int64_t foff;      // [X_a (ra x c) | X_b (rb x c)], each column-major
+  int64_t foff;      // stacked [X_a; X_b], column-major (ra + rb) x c
   int64_t zin;       // c inputs (skeletons of nu_1 then nu_2)
   int64_t zouta, zoutb;
   int32_t ra, rb, c, pad;

@@ -7,6 +7,14 @@
 namespace hbi {
 
 struct CopyDesc { const double2 *src; double2 *dst; int64_t count; };
+struct PairDesc { const double2 *xa, *xb; double2 *dst; int32_t ra, rb, c, pad; };
+
+// Optional observer of apply launches (per-kernel event timing).
+struct LaunchHook {
+  virtual void before(const char *name, double bytes) = 0;
+  virtual void after() = 0;
+  virtual ~LaunchHook() = default;
+};
 
 // Device-side apply plan (all pointers are device pointers).
 struct ApplyPlan {
@@ -18,6 +26,9 @@ struct ApplyPlan {
   const KDesc *kd = nullptr;
   std::vector<const WUnit *> units;   // index k = 1..Lmax
   std::vector<int64_t> nunits;
+  // algorithmic traffic per launch, in complex elements and index bytes
+  double v_elems = 0, v_idx = 0, f_elems = 0, f_idx = 0;
+  std::vector<double> w_elems, w_idx;   // index k
 };
 
 hipError_t launch_cell_setup(const DevProblem &P, const int32_t *perm, int64_t Nv,
@@ -37,10 +48,12 @@ hipError_t launch_entries(const DevProblem &P, const DevCells &C, const EntryBlo
 hipError_t launch_cpqr(const IdBlock *blks, int64_t nb, double tol, int32_t *rank,
                        hipStream_t st);
 hipError_t launch_copy_blocks(const CopyDesc *d, int64_t nb, hipStream_t st);
+hipError_t launch_pack_pairs(const PairDesc *d, int64_t np, hipStream_t st);
 hipError_t launch_to_f32(const double2 *src, float2 *dst, int64_t n, hipStream_t st);
 
 template <typename R>
 hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
-                        const void *F, R hd, bool adjoint, hipStream_t st);
+                        const void *F, R hd, bool adjoint, hipStream_t st,
+                        LaunchHook *hook = nullptr);
 
 }  // namespace hbi

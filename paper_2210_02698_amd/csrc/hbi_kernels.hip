@@ -429,6 +429,21 @@ __global__ void k_copy_blocks(const CopyDesc *d, int64_t nb) {
   for (int64_t i = threadIdx.x; i < c.count; i += blockDim.x) c.dst[i] = c.src[i];
 }
 
+// Stack the interpolation matrices of a sibling pair, X_a (ra x c) and X_b
+// (rb x c), into one column-major (ra + rb) x c transfer block.
+__global__ void k_pack_pairs(const PairDesc *d, int64_t np) {
+  const int64_t b = blockIdx.x;
+  if (b >= np) return;
+  const PairDesc p = d[b];
+  const int R = p.ra + p.rb;
+  const int64_t n = (int64_t)R * p.c;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const int col = (int)(i / R), row = (int)(i % R);
+    p.dst[i] = row < p.ra ? p.xa[row + (int64_t)col * p.ra]
+                          : p.xb[row - p.ra + (int64_t)col * p.rb];
+  }
+}
+
 __global__ void k_to_f32(const double2 *src, float2 *dst, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) dst[i] = float2{(float)src[i].x, (float)src[i].y};
@@ -439,6 +454,51 @@ __global__ void k_to_f32(const double2 *src, float2 *dst, int64_t n) {
 // skeleton factor K^L plus the dense diagonal leaf per row leaf.  Gathers
 // only: every output element is written by exactly one lane.
 // ---------------------------------------------------------------------------
+// y[0..R) = M x for a column-major R x c matrix M streamed by one wave.
+// Lane l works on row l % R of column group l / R (G = 64 / R groups when
+// R <= 32), so every load instruction of the wave reads one contiguous span
+// of G*R entries; partial sums of a row are combined with lane permutes in a
+// fixed order.  For R > 32 lanes take rows (64 at a time) and columns are
+// walked in order.  Returns the result for row `lane` (lane < R, R <= 64) or
+// writes through `store` for larger R.
+template <typename C, typename XF, typename ST>
+__device__ __forceinline__ void wave_gemv(const C *__restrict__ M, int Rt, int c, int lane,
+                                          XF xat, ST store) {
+  if (Rt <= 32) {
+    const int G = 64 / Rt;
+    const int grp = lane / Rt;
+    const bool act = grp < G;
+    C acc{0, 0};
+    if (act) {
+      const C *p = M + lane;
+      const int step = G * Rt;
+      int col = grp;
+#pragma unroll 8
+      for (; col < c; col += G, p += step) cfma(acc, *p, xat(col));
+    }
+    // combine the G partial sums of each row (lanes row, row+Rt, ...)
+    C tot = acc;
+    for (int g = 1; g < G; ++g) {
+      const int src = lane + g * Rt;
+      const auto re = __shfl(acc.x, src < 64 ? src : lane, 64);
+      const auto im = __shfl(acc.y, src < 64 ? src : lane, 64);
+      if (src < 64) { tot.x += re; tot.y += im; }
+    }
+    if (lane < Rt) store(lane, tot);
+  } else {
+    for (int r0 = 0; r0 < Rt; r0 += 64) {
+      const int row = r0 + lane;
+      if (row < Rt) {
+        C acc{0, 0};
+        const C *p = M + row;
+#pragma unroll 8
+        for (int col = 0; col < c; ++col, p += Rt) cfma(acc, *p, xat(col));
+        store(row, acc);
+      }
+    }
+  }
+}
+
 template <typename R>
 __global__ __launch_bounds__(64) void k_vstage(const cplx_t<R> *s,
                                                const LeafInfo *leaves,
@@ -457,12 +517,9 @@ __global__ __launch_bounds__(64) void k_vstage(const cplx_t<R> *s,
   __syncthreads();
   for (int l = 0; l < Lv; ++l) {
     const VDesc d = vd[(int64_t)g * Lv + l];
-    if (lane < d.r) {
-      const C *f = F + d.foff + lane;
-      C acc{0, 0};
-      for (int col = 0; col < lf.size; ++col) cfma(acc, f[(int64_t)col * d.r], xs[col]);
-      z[d.zout + lane] = acc;
-    }
+    C *zo = z + d.zout;
+    wave_gemv<C>(F + d.foff, d.r, lf.size, lane, [&](int col) { return xs[col]; },
+                 [&](int row, C v) { zo[row] = v; });
   }
 }
 
@@ -477,17 +534,14 @@ __global__ __launch_bounds__(256) void k_wstage(const WUnit *units,
   const int64_t u = (int64_t)blockIdx.x * 4 + wave;
   if (u >= nunits) return;
   const WUnit U = units[u];
-  const int Rt = U.ra + U.rb;
   const C *zin = z + U.zin;
-  for (int s = lane; s < Rt; s += 64) {
-    const bool first = s < U.ra;
-    const int row = first ? s : s - U.ra;
-    const int ld = first ? U.ra : U.rb;
-    const C *M = F + U.foff + (first ? 0 : (int64_t)U.ra * U.c) + row;
-    C acc{0, 0};
-    for (int col = 0; col < U.c; ++col) cfma(acc, M[(int64_t)col * ld], zin[col]);
-    z[(first ? U.zouta : U.zoutb) + row] = acc;
-  }
+  C *za = z + U.zouta;
+  C *zb = z + U.zoutb;
+  const int ra = U.ra;
+  wave_gemv<C>(F + U.foff, ra + U.rb, U.c, lane, [&](int col) { return zin[col]; },
+               [&](int row, C v) {
+                 if (row < ra) za[row] = v; else zb[row - ra] = v;
+               });
 }
 
 template <typename R>
@@ -511,11 +565,13 @@ __global__ __launch_bounds__(64) void k_final(const cplx_t<R> *s,
   if (lane >= sz) return;
   C acc{0, 0};
   const C *Dm = F + lf.dense_off + lane;
+#pragma unroll 8
   for (int col = 0; col < sz; ++col) cfma(acc, Dm[(int64_t)col * sz], xs[col]);
   for (int l = 0; l < Lv; ++l) {
     const KDesc d = kd[(int64_t)g * Lv + l];
     const C *K = F + d.foff + lane;
     const C *zz = z + d.zin;
+#pragma unroll 8
     for (int q = 0; q < d.r; ++q) cfma(acc, K[(int64_t)q * sz], zz[q]);
   }
   u[perm[lf.start + lane]] = acc;
@@ -560,14 +616,14 @@ __global__ __launch_bounds__(256) void k_wstage_adj(const WUnit *units,
   const int64_t u = (int64_t)blockIdx.x * 4 + wave;
   if (u >= nunits) return;
   const WUnit U = units[u];
+  const int ra = U.ra, Rt = U.ra + U.rb;
   const C *wa = z + U.zouta, *wb = z + U.zoutb;
-  const C *Ma = F + U.foff, *Mb = F + U.foff + (int64_t)U.ra * U.c;
+  const C *M = F + U.foff;
   for (int col = lane; col < U.c; col += 64) {
     C acc{0, 0};
-    const C *ca = Ma + (int64_t)col * U.ra;
-    for (int i = 0; i < U.ra; ++i) cfmac(acc, ca[i], wa[i]);
-    const C *cb = Mb + (int64_t)col * U.rb;
-    for (int i = 0; i < U.rb; ++i) cfmac(acc, cb[i], wb[i]);
+    const C *cm = M + (int64_t)col * Rt;
+    for (int i = 0; i < ra; ++i) cfmac(acc, cm[i], wa[i]);
+    for (int i = ra; i < Rt; ++i) cfmac(acc, cm[i], wb[i - ra]);
     z[U.zin + col] = acc;
   }
 }
@@ -680,6 +736,12 @@ hipError_t launch_copy_blocks(const CopyDesc *d, int64_t nb, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_pack_pairs(const PairDesc *d, int64_t np, hipStream_t st) {
+  if (np == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_pairs, dim3(np), dim3(256), 0, st, d, np);
+  return hipGetLastError();
+}
+
 hipError_t launch_to_f32(const double2 *src, float2 *dst, int64_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const int T = 256;
@@ -689,43 +751,64 @@ hipError_t launch_to_f32(const double2 *src, float2 *dst, int64_t n, hipStream_t
 
 template <typename R>
 hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
-                        const void *F, R hd, bool adjoint, hipStream_t st) {
+                        const void *F, R hd, bool adjoint, hipStream_t st, LaunchHook *hook) {
   using C = cplx_t<R>;
   const C *sc = (const C *)s;
   C *uc = (C *)u;
   C *zc = (C *)z;
   const C *Fc = (const C *)F;
+  const double esz = sizeof(C);
+  auto pre = [&](const char *name, double elems, double idx) {
+    if (hook) hook->before(name, elems * esz + idx);
+  };
+  auto post = [&]() { if (hook) hook->after(); };
   if (!adjoint) {
-    if (ap.Lv > 0)
+    if (ap.Lv > 0) {
+      pre("k_vstage", ap.v_elems, ap.v_idx);
       hipLaunchKernelGGL((k_vstage<R>), dim3(ap.nleaf), dim3(64), 0, st, sc, ap.leaves,
                          ap.perm, ap.vd, ap.Lv, Fc, zc, hd);
+      post();
+    }
     for (int k = 1; k <= ap.Lmax; ++k) {
       const int64_t nu = ap.nunits[k];
       if (nu == 0) continue;
+      pre("k_wstage", ap.w_elems[k], ap.w_idx[k]);
       hipLaunchKernelGGL((k_wstage<R>), dim3((nu + 3) / 4), dim3(256), 0, st,
                          ap.units[k], nu, Fc, zc);
+      post();
     }
+    pre("k_final", ap.f_elems, ap.f_idx);
     hipLaunchKernelGGL((k_final<R>), dim3(ap.nleaf), dim3(64), 0, st, sc, ap.leaves,
                        ap.perm, ap.kd, ap.Lv, Fc, (const C *)zc, uc, hd);
+    post();
   } else {
-    if (ap.Lv > 0)
+    // the adjoint streams the same factors; its K^L part is the K^L share of
+    // the final stage and its dense part rides with the V^H stage
+    if (ap.Lv > 0) {
+      pre("k_final_adj", ap.f_elems, ap.f_idx);
       hipLaunchKernelGGL((k_final_adj<R>), dim3(ap.nleaf), dim3(64), 0, st, sc, ap.leaves,
                          ap.perm, ap.kd, ap.Lv, Fc, zc);
+      post();
+    }
     for (int k = ap.Lmax; k >= 1; --k) {
       const int64_t nu = ap.nunits[k];
       if (nu == 0) continue;
+      pre("k_wstage_adj", ap.w_elems[k], ap.w_idx[k]);
       hipLaunchKernelGGL((k_wstage_adj<R>), dim3((nu + 3) / 4), dim3(256), 0, st,
                          ap.units[k], nu, Fc, zc);
+      post();
     }
+    pre("k_vstage_adj", ap.v_elems, ap.v_idx);
     hipLaunchKernelGGL((k_vstage_adj<R>), dim3(ap.nleaf), dim3(64), 0, st, sc, ap.leaves,
                        ap.perm, ap.vd, ap.Lv, Fc, (const C *)zc, uc, hd);
+    post();
   }
   return hipGetLastError();
 }
 
 template hipError_t launch_apply<double>(const ApplyPlan &, const void *, void *, void *,
-                                         const void *, double, bool, hipStream_t);
+                                         const void *, double, bool, hipStream_t, LaunchHook *);
 template hipError_t launch_apply<float>(const ApplyPlan &, const void *, void *, void *,
-                                        const void *, float, bool, hipStream_t);
+                                        const void *, float, bool, hipStream_t, LaunchHook *);
 
 }  // namespace hbi

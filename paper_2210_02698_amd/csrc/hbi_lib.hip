@@ -109,6 +109,27 @@ struct Chunk {
   int64_t count;    // complex elements
 };
 
+// Records an event pair around every apply launch while enabled.
+struct Profiler : LaunchHook {
+  hipStream_t st = nullptr;
+  struct Rec { const char *name; hipEvent_t a, b; double bytes; };
+  std::vector<Rec> recs;
+  void before(const char *name, double bytes) override {
+    Rec r{name, nullptr, nullptr, bytes};
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+    (void)hipEventRecord(r.a, st);
+    recs.push_back(r);
+  }
+  void after() override {
+    if (!recs.empty()) (void)hipEventRecord(recs.back().b, st);
+  }
+  void clear() {
+    for (auto &r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    recs.clear();
+  }
+  ~Profiler() override { clear(); }
+};
+
 }  // namespace
 
 struct hbi_ctx {
@@ -138,6 +159,8 @@ struct hbi_ctx {
   ApplyPlan plan;
   int64_t ztotal = 0;
   DevBuf z_d;
+  bool profiling = false;
+  Profiler prof;
   // statistics
   double t_build = 0, t_geo = 0, t_host = 0, t_gpu = 0, t_final = 0;
   int64_t nnz_v = 0, nnz_w = 0, nnz_k = 0, nnz_d = 0, entries_eval = 0, nid = 0;
@@ -283,7 +306,7 @@ struct Batcher {
   // matrices are still in the workspace.
   template <class CB>
   void run(const std::vector<BlockIn> &blocks, bool id, double tol, std::vector<BlockOut> *outs,
-           CB &&on_batch) {
+           CB &&on_batch, bool pairs = false) {
     const int64_t nb = (int64_t)blocks.size();
     const size_t budget = (size_t)c->wsbytes();
     HBI_HIP(c->ws.reserve(budget));
@@ -296,14 +319,18 @@ struct Batcher {
     while (i0 < nb) {
       size_t used = 0;
       int64_t i1 = i0;
+      // with `pairs`, blocks 2q and 2q+1 always go to the same batch
+      const int step = pairs ? 2 : 1;
       while (i1 < nb) {
-        const size_t need = ws_need(blocks[i1].m, blocks[i1].n, nslot[i1], id);
+        size_t need = 0;
+        for (int q = 0; q < step && i1 + q < nb; ++q)
+          need += ws_need(blocks[i1 + q].m, blocks[i1 + q].n, nslot[i1 + q], id);
         if (need > budget)
           throw Error{HBI_ERR_OOM, "a single block (m=" + std::to_string(blocks[i1].m) + ", n=" +
                                        std::to_string(blocks[i1].n) + ") exceeds the workspace"};
         if (used + need > budget) break;
         used += need;
-        ++i1;
+        i1 = std::min<int64_t>(nb, i1 + step);
       }
       run_batch(blocks, slots, nslot, i0, i1, id, tol, outs);
       if (id) on_batch(i0, i1 - i0);
@@ -470,26 +497,45 @@ void build_factors(hbi_ctx *c, double tol) {
   c->ztotal = 0;
   double t_host = 0, t_gpu = 0;
 
-  // Compact the X matrices of an ID batch into a new chunk.
+  // Compact the X matrices of an ID batch into a new chunk.  Level 0 keeps
+  // each V_{tau,nu} (r x |nu|); higher levels stack the sibling pair
+  // (2t', j), (2t'+1, j) into one column-major transfer block [X_a; X_b].
   auto compact = [&](std::vector<BlockOut> &outs, int64_t first, int64_t cnt,
-                     const std::vector<int32_t> &ncols, std::vector<int64_t> &foff_out) {
+                     const std::vector<int32_t> &ncols, std::vector<int64_t> &foff_out,
+                     bool pairs) {
     int64_t tot = 0;
     for (int64_t q = 0; q < cnt; ++q) tot += (int64_t)outs[first + q].rank * ncols[first + q];
     Chunk ch;
     HBI_HIP(ch.buf.alloc(sizeof(double2) * tot));
     ch.goff = Fg;
     ch.count = tot;
-    std::vector<CopyDesc> cd(cnt);
+    DevBuf d_d;
     int64_t o = 0;
-    for (int64_t q = 0; q < cnt; ++q) {
-      const int64_t e = (int64_t)outs[first + q].rank * ncols[first + q];
-      cd[q] = CopyDesc{outs[first + q].X, ch.buf.as<double2>() + o, e};
-      foff_out[first + q] = Fg + o;
-      o += e;
+    if (!pairs) {
+      std::vector<CopyDesc> cd(cnt);
+      for (int64_t q = 0; q < cnt; ++q) {
+        const int64_t e = (int64_t)outs[first + q].rank * ncols[first + q];
+        cd[q] = CopyDesc{outs[first + q].X, ch.buf.as<double2>() + o, e};
+        foff_out[first + q] = Fg + o;
+        o += e;
+      }
+      upload(d_d, cd);
+      HBI_HIP(launch_copy_blocks(d_d.as<CopyDesc>(), cnt, c->stream));
+    } else {
+      if (cnt % 2 != 0) throw Error{HBI_ERR_NUMERIC, "internal error: unpaired transfer block"};
+      std::vector<PairDesc> pd(cnt / 2);
+      for (int64_t q = 0; q < cnt; q += 2) {
+        const BlockOut &a = outs[first + q], &b = outs[first + q + 1];
+        const int32_t cc = ncols[first + q];
+        if (ncols[first + q + 1] != cc) throw Error{HBI_ERR_NUMERIC, "internal error: pair width"};
+        pd[q / 2] = PairDesc{a.X, b.X, ch.buf.as<double2>() + o, a.rank, b.rank, cc, 0};
+        foff_out[first + q] = Fg + o;
+        foff_out[first + q + 1] = Fg + o + (int64_t)a.rank * cc;
+        o += (int64_t)(a.rank + b.rank) * cc;
+      }
+      upload(d_d, pd);
+      HBI_HIP(launch_pack_pairs(d_d.as<PairDesc>(), cnt / 2, c->stream));
     }
-    DevBuf cd_d;
-    upload(cd_d, cd);
-    HBI_HIP(launch_copy_blocks(cd_d.as<CopyDesc>(), cnt, c->stream));
     HBI_HIP(hipStreamSynchronize(c->stream));
     Fg += tot;
     chunks.push_back(std::move(ch));
@@ -560,8 +606,8 @@ void build_factors(hbi_ctx *c, double tol) {
       std::vector<BlockOut> outs(c1 - c0);
       std::vector<int64_t> foff_local(c1 - c0);
       B.run(bin, true, tol, &outs, [&](int64_t first, int64_t cnt) {
-        compact(outs, first, cnt, ncols, foff_local);
-      });
+        compact(outs, first, cnt, ncols, foff_local, k > 0);
+      }, k > 0);
       for (int64_t q = 0; q < c1 - c0; ++q) {
         skel_tmp[c0 + q].resize(outs[q].rank);
         for (int32_t r = 0; r < outs[q].rank; ++r) skel_tmp[c0 + q][r] = cands[q][outs[q].piv[r]];
@@ -740,6 +786,34 @@ void build_factors(hbi_ctx *c, double tol) {
     c->plan.units[k] = c->units_d[k].as<WUnit>();
     c->plan.nunits[k] = (int64_t)units[k].size();
   }
+  // algorithmic traffic per launch (complex elements + index bytes)
+  {
+    ApplyPlan &ap = c->plan;
+    ap.w_elems.assign(Lmax + 1, 0.0);
+    ap.w_idx.assign(Lmax + 1, 0.0);
+    double ve = 0, vi = 0, fe = 0, fi = 0;
+    for (int64_t g = 0; g < nleaf; ++g) {
+      const double sz = leaves[g].size;
+      vi += sizeof(LeafInfo) + 4.0 * sz;
+      fi += sizeof(LeafInfo) + 4.0 * sz;
+      if (Lv > 0) ve += sz;                 // s read by the V stage
+      fe += sz * sz + 2.0 * sz;             // dense leaf, s read, u written
+      for (int l = 0; l < Lv; ++l) {
+        const VDesc &v = vd[g * Lv + l];
+        const KDesc &q = kd[g * Lv + l];
+        ve += (double)v.r * sz + v.r;
+        fe += (double)q.r * sz + q.r;
+        vi += sizeof(VDesc);
+        fi += sizeof(KDesc);
+      }
+    }
+    ap.v_elems = ve; ap.v_idx = vi; ap.f_elems = fe; ap.f_idx = fi;
+    for (int k = 1; k <= Lmax; ++k)
+      for (const WUnit &U : units[k]) {
+        ap.w_elems[k] += (double)(U.ra + U.rb) * U.c + U.c + U.ra + U.rb;
+        ap.w_idx[k] += sizeof(WUnit);
+      }
+  }
   HBI_HIP(c->z_d.alloc(esz * std::max<int64_t>(c->ztotal, 1)));
   c->t_final = now_s() - tf;
   c->t_host = t_host;
@@ -765,15 +839,17 @@ void check_apply_args(hbi_ctx *c, const void *s, void *u, int32_t nrhs, int64_t 
 void do_apply(hbi_ctx *c, const void *s, void *u, int32_t nrhs, int64_t ld, bool adj) {
   check_apply_args(c, s, u, nrhs, ld);
   const size_t esz = c->prec == HBI_F64 ? 16 : 8;
+  c->prof.st = c->stream;
+  LaunchHook *hook = c->profiling ? &c->prof : nullptr;
   for (int32_t r = 0; r < nrhs; ++r) {
     const char *sc = (const char *)s + esz * (size_t)ld * r;
     char *uc = (char *)u + esz * (size_t)ld * r;
     if (c->prec == HBI_F64) {
       HBI_HIP(launch_apply<double>(c->plan, sc, uc, c->z_d.p, c->F.p, std::pow(c->h, c->dim), adj,
-                                   c->stream));
+                                   c->stream, hook));
     } else {
       HBI_HIP(launch_apply<float>(c->plan, sc, uc, c->z_d.p, c->F.p, (float)std::pow(c->h, c->dim),
-                                  adj, c->stream));
+                                  adj, c->stream, hook));
     }
   }
 }
@@ -944,6 +1020,47 @@ hbi_status hbi_entries(hbi_ctx *ctx, const int32_t *rows, int32_t m, const int32
     }
     Batcher B(ctx);
     B.run(bin, false, 0.0, nullptr, [](int64_t, int64_t) {});
+  });
+}
+
+hbi_status hbi_set_profiling(hbi_ctx *ctx, int32_t enable) {
+  if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
+  return guarded(ctx, [&]() {
+    ctx->profiling = enable != 0;
+    if (ctx->profiling) {
+      HBI_HIP(hipStreamSynchronize(ctx->stream));
+      ctx->prof.clear();
+    }
+  });
+}
+
+hbi_status hbi_get_profile(hbi_ctx *ctx, char *json, int64_t cap) {
+  if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
+  return guarded(ctx, [&]() {
+    HBI_REQUIRE(json && cap > 0, HBI_ERR_ARG, "null or empty output buffer");
+    HBI_HIP(hipStreamSynchronize(ctx->stream));
+    struct Agg { std::string name; int64_t n = 0; double ms = 0, bytes = 0; };
+    std::vector<Agg> agg;
+    for (auto &r : ctx->prof.recs) {
+      float ms = 0.f;
+      HBI_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      auto it = std::find_if(agg.begin(), agg.end(), [&](const Agg &a) { return a.name == r.name; });
+      if (it == agg.end()) { agg.push_back(Agg{r.name}); it = agg.end() - 1; }
+      it->n += 1;
+      it->ms += ms;
+      it->bytes += r.bytes;
+    }
+    ctx->prof.clear();
+    std::string out = "{\"kernels\": {";
+    char buf[256];
+    for (size_t i = 0; i < agg.size(); ++i) {
+      std::snprintf(buf, sizeof buf, "%s\"%s\": {\"launches\": %lld, \"ms\": %.6f, \"bytes\": %.0f}",
+                    i ? ", " : "", agg[i].name.c_str(), (long long)agg[i].n, agg[i].ms, agg[i].bytes);
+      out += buf;
+    }
+    out += "}}";
+    HBI_REQUIRE((int64_t)out.size() < cap, HBI_ERR_ARG, "output buffer too small");
+    std::memcpy(json, out.c_str(), out.size() + 1);
   });
 }
 

@@ -42,6 +42,8 @@ def test_null_context_is_an_argument_error(lib):
     assert lib.hbi_entries(null, None, 0, None, 0, None) == _lib.HBI_ERR_ARG
     assert lib.hbi_get_info(null, None, 0) == _lib.HBI_ERR_ARG
     assert lib.hbi_set_stream(null, None) == _lib.HBI_ERR_ARG
+    assert lib.hbi_set_profiling(null, 1) == _lib.HBI_ERR_ARG
+    assert lib.hbi_get_profile(null, None, 0) == _lib.HBI_ERR_ARG
     assert lib.hbi_last_error(null) == b"ctx is NULL"
     assert lib.hbi_destroy(null) == _lib.HBI_OK
 
