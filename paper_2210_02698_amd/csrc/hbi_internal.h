@@ -5,7 +5,7 @@
 
 #define HBI_MAX_NI 16
 #define HBI_MAX_LEAF 64
-#define HBI_ID_THREADS 256
+#define HBI_ID_THREADS 1024
 #define HBI_ID_NMAX 4096   // largest candidate-column count an ID accepts
 
 // Problem constants visible to the kernels.
@@ -57,4 +57,7 @@ struct WUnit {
   int64_t zouta, zoutb;
   int32_t ra, rb, c, pad;
 };
+// Work item of a transfer stage: rows (forward) or columns (adjoint)
+// [off, off + 64) of unit `unit`.
+struct WItem { int32_t unit; int32_t off; };
 struct LeafInfo { int32_t start, size; int64_t dense_off; };

@@ -26,6 +26,8 @@ struct ApplyPlan {
   const KDesc *kd = nullptr;
   std::vector<const WUnit *> units;   // index k = 1..Lmax
   std::vector<int64_t> nunits;
+  std::vector<const WItem *> items, items_adj;   // index k
+  std::vector<int64_t> nitems, nitems_adj;
   // algorithmic traffic per launch, in complex elements and index bytes
   double v_elems = 0, v_idx = 0, f_elems = 0, f_idx = 0;
   std::vector<double> w_elems, w_idx;   // index k
@@ -45,7 +47,7 @@ hipError_t launch_entries(const DevProblem &P, const DevCells &C, const EntryBlo
                           const int32_t *work, int64_t nwork, const int32_t *rows,
                           const uint16_t *rowslot, const int32_t *cols, const double *Hc,
                           hipStream_t st);
-hipError_t launch_cpqr(const IdBlock *blks, int64_t nb, double tol, int32_t *rank,
+hipError_t launch_cpqr(const IdBlock *blks, int64_t nb, int nmax, double tol, int32_t *rank,
                        hipStream_t st);
 hipError_t launch_copy_blocks(const CopyDesc *d, int64_t nb, hipStream_t st);
 hipError_t launch_pack_pairs(const PairDesc *d, int64_t np, hipStream_t st);

@@ -278,74 +278,69 @@ __global__ __launch_bounds__(256) void k_entries(
 // r = k (at least 1).  Then X = [I, R11^-1 R12] Pi^T (r x n) so that
 // A ~ A(:, skel) X.  Column norms are recomputed exactly from the updated
 // entries at every step.  One workgroup (4 waves) per block; the block lives
-// in global memory and waves split the trailing columns.
+// in global memory and waves split the trailing columns.  Each step: thread
+// 0 picks the pivot from the waves' candidates and forms the reflector
+// (beta, tau and the scale of x below the diagonal); the waves then apply
+// it to their columns with the reflector vector formed on the fly (the
+// pivot column below the diagonal is not needed afterwards) and report
+// their best next pivot.  LDS: norms and column map, 12 bytes per column.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(HBI_ID_THREADS) void k_cpqr(const IdBlock *blks,
                                                           double tol,
                                                           int32_t *rank_out) {
-  __shared__ double nrm2[HBI_ID_NMAX];
-  __shared__ int colmap[HBI_ID_NMAX];
-  __shared__ double red_v[HBI_ID_THREADS / 64];
-  __shared__ int red_i[HBI_ID_THREADS / 64];
+  extern __shared__ double lds_id[];
+  constexpr int NW = HBI_ID_THREADS / 64;
+  __shared__ double red_v[NW];
+  __shared__ int red_i[NW];
   __shared__ double2 sh_tau, sh_scale;
   __shared__ int sh_stop, sh_rank, sh_c;
   __shared__ double sh_r11;
 
   const IdBlock B = blks[blockIdx.x];
   const int m = B.m, n = B.n;
+  double *nrm2 = lds_id;
+  int *colmap = (int *)(lds_id + n);
   double2 *A = B.A;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int NW = HBI_ID_THREADS / 64;
 
+  // initial norms; each wave also tracks its best candidate
+  double bv = -1.0;
+  int bq = n;
   for (int j = wave; j < n; j += NW) {
     const double2 *a = A + (int64_t)j * m;
     double s = 0.0;
     for (int i = lane; i < m; i += 64) s += a[i].x * a[i].x + a[i].y * a[i].y;
     s = wave_sum(s);
     if (lane == 0) nrm2[j] = s;
+    if (s > bv) { bv = s; bq = j; }
   }
+  if (lane == 0) { red_v[wave] = bv; red_i[wave] = bq; }
   for (int j = tid; j < n; j += HBI_ID_THREADS) colmap[j] = j;
   if (tid == 0) { sh_rank = m < n ? m : n; sh_r11 = 0.0; }
   __syncthreads();
 
   const int kmax = m < n ? m : n;
   for (int k = 0; k < kmax; ++k) {
-    // pivot search over q in [k, n)
-    double bv = -1.0;
-    int bq = n;
-    for (int q = k + tid; q < n; q += HBI_ID_THREADS) {
-      const double v = nrm2[colmap[q]];
-      if (v > bv) { bv = v; bq = q; }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(bv, o, 64);
-      const int oq = __shfl_xor(bq, o, 64);
-      if (ov > bv || (ov == bv && oq < bq)) { bv = ov; bq = oq; }
-    }
-    if (lane == 0) { red_v[wave] = bv; red_i[wave] = bq; }
-    __syncthreads();
     if (tid == 0) {
+      double v = red_v[0];
+      int q = red_i[0];
       for (int w2 = 1; w2 < NW; ++w2)
-        if (red_v[w2] > bv || (red_v[w2] == bv && red_i[w2] < bq)) {
-          bv = red_v[w2];
-          bq = red_i[w2];
-        }
-      const double nrm = sqrt(fmax(bv, 0.0));
+        if (red_v[w2] > v || (red_v[w2] == v && red_i[w2] < q)) { v = red_v[w2]; q = red_i[w2]; }
+      const double nrm = sqrt(fmax(v, 0.0));
       if (k == 0) sh_r11 = nrm;
-      int stop = (nrm == 0.0) || (k > 0 && nrm <= tol * sh_r11);
+      const int stop = (q >= n) || (nrm == 0.0) || (k > 0 && nrm <= tol * sh_r11);
       sh_stop = stop;
       if (stop) {
         sh_rank = k > 0 ? k : 1;
       } else {
         const int t = colmap[k];
-        colmap[k] = colmap[bq];
-        colmap[bq] = t;
+        colmap[k] = colmap[q];
+        colmap[q] = t;
         const int c = colmap[k];
         double2 *ac = A + (int64_t)c * m;
         const double2 al = ac[k];
         const double beta = al.x >= 0.0 ? -nrm : nrm;
-        // tau = (beta - alpha)/beta ; scale = 1/(alpha - beta)
+        // H = I - tau v v^H with v = (1, x_{k+1:}/(alpha - beta)), H^H x = beta e_k
         sh_tau = double2{(beta - al.x) / beta, -al.y / beta};
         const double dr = al.x - beta, di = al.y;
         const double dd = dr * dr + di * di;
@@ -358,16 +353,16 @@ __global__ __launch_bounds__(HBI_ID_THREADS) void k_cpqr(const IdBlock *blks,
     if (sh_stop) break;
     const int c = sh_c;
     const double2 scale = sh_scale, tau = sh_tau;
-    double2 *v = A + (int64_t)c * m;
-    for (int i = k + 1 + tid; i < m; i += HBI_ID_THREADS) v[i] = cmul(v[i], scale);
-    __syncthreads();
+    const double2 *x = A + (int64_t)c * m;
     const double2 ctau = double2{tau.x, -tau.y};
+    bv = -1.0;
+    bq = n;
     for (int q = k + 1 + wave; q < n; q += NW) {
       const int j = colmap[q];
       double2 *a = A + (int64_t)j * m;
       double2 wv = double2{0.0, 0.0};
       for (int i = k + lane; i < m; i += 64) {
-        const double2 vi = (i == k) ? double2{1.0, 0.0} : v[i];
+        const double2 vi = (i == k) ? double2{1.0, 0.0} : cmul(x[i], scale);
         cfmac(wv, vi, a[i]);
       }
       wv.x = wave_sum(wv.x);
@@ -375,7 +370,7 @@ __global__ __launch_bounds__(HBI_ID_THREADS) void k_cpqr(const IdBlock *blks,
       const double2 f = cmul(ctau, wv);
       double s = 0.0;
       for (int i = k + lane; i < m; i += 64) {
-        const double2 vi = (i == k) ? double2{1.0, 0.0} : v[i];
+        const double2 vi = (i == k) ? double2{1.0, 0.0} : cmul(x[i], scale);
         double2 ai = a[i];
         ai.x -= f.x * vi.x - f.y * vi.y;
         ai.y -= f.x * vi.y + f.y * vi.x;
@@ -384,7 +379,9 @@ __global__ __launch_bounds__(HBI_ID_THREADS) void k_cpqr(const IdBlock *blks,
       }
       s = wave_sum(s);
       if (lane == 0) nrm2[j] = s;
+      if (s > bv) { bv = s; bq = q; }
     }
+    if (lane == 0) { red_v[wave] = bv; red_i[wave] = bq; }
     __syncthreads();
   }
 
@@ -400,21 +397,21 @@ __global__ __launch_bounds__(HBI_ID_THREADS) void k_cpqr(const IdBlock *blks,
   for (int q = r + tid; q < n; q += HBI_ID_THREADS) {
     const int col = colmap[q];
     const double2 *rc = A + (int64_t)col * m;
-    double2 *x = X + (int64_t)col * r;
+    double2 *xo = X + (int64_t)col * r;
     for (int i = r - 1; i >= 0; --i) {
       double2 acc = rc[i];
       for (int l = i + 1; l < r; ++l) {
         const double2 ril = A[i + (int64_t)colmap[l] * m];
-        const double2 xl = x[l];
+        const double2 xl = xo[l];
         acc.x -= ril.x * xl.x - ril.y * xl.y;
         acc.y -= ril.x * xl.y + ril.y * xl.x;
       }
       const double2 d = A[i + (int64_t)colmap[i] * m];
       const double dd = d.x * d.x + d.y * d.y;
       if (zero || dd == 0.0) {
-        x[i] = double2{0.0, 0.0};
+        xo[i] = double2{0.0, 0.0};
       } else {
-        x[i] = double2{(acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd};
+        xo[i] = double2{(acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd};
       }
     }
   }
@@ -463,7 +460,7 @@ __global__ void k_to_f32(const double2 *src, float2 *dst, int64_t n) {
 // writes through `store` for larger R.
 template <typename C, typename XF, typename ST>
 __device__ __forceinline__ void wave_gemv(const C *__restrict__ M, int Rt, int c, int lane,
-                                          XF xat, ST store) {
+                                          XF xat, ST store, int r0 = 0, int r1 = 1 << 30) {
   if (Rt <= 32) {
     const int G = 64 / Rt;
     const int grp = lane / Rt;
@@ -473,7 +470,7 @@ __device__ __forceinline__ void wave_gemv(const C *__restrict__ M, int Rt, int c
       const C *p = M + lane;
       const int step = G * Rt;
       int col = grp;
-#pragma unroll 8
+#pragma unroll 16
       for (; col < c; col += G, p += step) cfma(acc, *p, xat(col));
     }
     // combine the G partial sums of each row (lanes row, row+Rt, ...)
@@ -486,12 +483,13 @@ __device__ __forceinline__ void wave_gemv(const C *__restrict__ M, int Rt, int c
     }
     if (lane < Rt) store(lane, tot);
   } else {
-    for (int r0 = 0; r0 < Rt; r0 += 64) {
-      const int row = r0 + lane;
-      if (row < Rt) {
+    const int re_ = r1 < Rt ? r1 : Rt;
+    for (int rb = r0; rb < re_; rb += 64) {
+      const int row = rb + lane;
+      if (row < re_) {
         C acc{0, 0};
         const C *p = M + row;
-#pragma unroll 8
+#pragma unroll 16
         for (int col = 0; col < c; ++col, p += Rt) cfma(acc, *p, xat(col));
         store(row, acc);
       }
@@ -499,23 +497,27 @@ __device__ __forceinline__ void wave_gemv(const C *__restrict__ M, int Rt, int c
   }
 }
 
+// One workgroup (4 waves) per leaf; wave w handles the HODBF levels
+// l = w, w + 4, ... of the leaf.
 template <typename R>
-__global__ __launch_bounds__(64) void k_vstage(const cplx_t<R> *s,
-                                               const LeafInfo *leaves,
-                                               const int32_t *perm,
-                                               const VDesc *vd, int Lv,
-                                               const cplx_t<R> *F,
-                                               cplx_t<R> *z, R hd) {
+__global__ __launch_bounds__(256) void k_vstage(const cplx_t<R> *s,
+                                                const LeafInfo *leaves,
+                                                const int32_t *perm,
+                                                const VDesc *vd, int Lv,
+                                                const cplx_t<R> *F,
+                                                cplx_t<R> *z, R hd) {
   using C = cplx_t<R>;
   __shared__ C xs[HBI_MAX_LEAF];
-  const int g = blockIdx.x, lane = threadIdx.x;
+  const int g = blockIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const LeafInfo lf = leaves[g];
-  if (lane < lf.size) {
-    const C v = s[perm[lf.start + lane]];
-    xs[lane] = C{v.x * hd, v.y * hd};
+  if (threadIdx.x < lf.size) {
+    const C v = s[perm[lf.start + threadIdx.x]];
+    xs[threadIdx.x] = C{v.x * hd, v.y * hd};
   }
   __syncthreads();
-  for (int l = 0; l < Lv; ++l) {
+  for (int l = wave; l < Lv; l += 4) {
     const VDesc d = vd[(int64_t)g * Lv + l];
     C *zo = z + d.zout;
     wave_gemv<C>(F + d.foff, d.r, lf.size, lane, [&](int col) { return xs[col]; },
@@ -523,17 +525,19 @@ __global__ __launch_bounds__(64) void k_vstage(const cplx_t<R> *s,
   }
 }
 
+// One wave per work item: rows [r0, r0 + 64) of a transfer unit (whole unit
+// when it has <= 64 rows).  Items are ordered by decreasing cost.
 template <typename R>
-__global__ __launch_bounds__(256) void k_wstage(const WUnit *units,
-                                                int64_t nunits,
-                                                const cplx_t<R> *F,
+__global__ __launch_bounds__(256) void k_wstage(const WUnit *units, const WItem *items,
+                                                int64_t nitems, const cplx_t<R> *F,
                                                 cplx_t<R> *z) {
   using C = cplx_t<R>;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t u = (int64_t)blockIdx.x * 4 + wave;
-  if (u >= nunits) return;
-  const WUnit U = units[u];
+  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+  if (it >= nitems) return;
+  const WItem W = items[it];
+  const WUnit U = units[W.unit];
   const C *zin = z + U.zin;
   C *za = z + U.zouta;
   C *zb = z + U.zoutb;
@@ -541,60 +545,78 @@ __global__ __launch_bounds__(256) void k_wstage(const WUnit *units,
   wave_gemv<C>(F + U.foff, ra + U.rb, U.c, lane, [&](int col) { return zin[col]; },
                [&](int row, C v) {
                  if (row < ra) za[row] = v; else zb[row - ra] = v;
-               });
+               },
+               W.off, W.off + 64);
 }
 
+// One workgroup (4 waves) per row leaf: wave w accumulates the K^L blocks
+// of levels l = w, w + 4, ... (wave 0 also the dense block); the four
+// partial results are added in a fixed order.
 template <typename R>
-__global__ __launch_bounds__(64) void k_final(const cplx_t<R> *s,
-                                              const LeafInfo *leaves,
-                                              const int32_t *perm,
-                                              const KDesc *kd, int Lv,
-                                              const cplx_t<R> *F,
-                                              const cplx_t<R> *z,
-                                              cplx_t<R> *u, R hd) {
+__global__ __launch_bounds__(256) void k_final(const cplx_t<R> *s,
+                                               const LeafInfo *leaves,
+                                               const int32_t *perm,
+                                               const KDesc *kd, int Lv,
+                                               const cplx_t<R> *F,
+                                               const cplx_t<R> *z,
+                                               cplx_t<R> *u, R hd) {
   using C = cplx_t<R>;
   __shared__ C xs[HBI_MAX_LEAF];
-  const int g = blockIdx.x, lane = threadIdx.x;
+  __shared__ C part[4][HBI_MAX_LEAF];
+  const int g = blockIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const LeafInfo lf = leaves[g];
   const int sz = lf.size;
-  if (lane < sz) {
-    const C v = s[perm[lf.start + lane]];
-    xs[lane] = C{v.x * hd, v.y * hd};
+  if (threadIdx.x < sz) {
+    const C v = s[perm[lf.start + threadIdx.x]];
+    xs[threadIdx.x] = C{v.x * hd, v.y * hd};
   }
   __syncthreads();
-  if (lane >= sz) return;
   C acc{0, 0};
-  const C *Dm = F + lf.dense_off + lane;
-#pragma unroll 8
-  for (int col = 0; col < sz; ++col) cfma(acc, Dm[(int64_t)col * sz], xs[col]);
-  for (int l = 0; l < Lv; ++l) {
-    const KDesc d = kd[(int64_t)g * Lv + l];
-    const C *K = F + d.foff + lane;
-    const C *zz = z + d.zin;
-#pragma unroll 8
-    for (int q = 0; q < d.r; ++q) cfma(acc, K[(int64_t)q * sz], zz[q]);
+  if (lane < sz) {
+    if (wave == 0) {
+      const C *Dm = F + lf.dense_off + lane;
+#pragma unroll 16
+      for (int col = 0; col < sz; ++col) cfma(acc, Dm[(int64_t)col * sz], xs[col]);
+    }
+    for (int l = wave; l < Lv; l += 4) {
+      const KDesc d = kd[(int64_t)g * Lv + l];
+      const C *K = F + d.foff + lane;
+      const C *zz = z + d.zin;
+#pragma unroll 16
+      for (int q = 0; q < d.r; ++q) cfma(acc, K[(int64_t)q * sz], zz[q]);
+    }
   }
-  u[perm[lf.start + lane]] = acc;
+  part[wave][lane] = acc;
+  __syncthreads();
+  if (threadIdx.x < sz) {
+    C t = part[0][threadIdx.x];
+    for (int w = 1; w < 4; ++w) { t.x += part[w][threadIdx.x].x; t.y += part[w][threadIdx.x].y; }
+    u[perm[lf.start + threadIdx.x]] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Adjoint: the same factors read as conjugate transposes, stages reversed.
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(64) void k_final_adj(const cplx_t<R> *y,
-                                                  const LeafInfo *leaves,
-                                                  const int32_t *perm,
-                                                  const KDesc *kd, int Lv,
-                                                  const cplx_t<R> *F,
-                                                  cplx_t<R> *z) {
+__global__ __launch_bounds__(256) void k_final_adj(const cplx_t<R> *y,
+                                                   const LeafInfo *leaves,
+                                                   const int32_t *perm,
+                                                   const KDesc *kd, int Lv,
+                                                   const cplx_t<R> *F,
+                                                   cplx_t<R> *z) {
   using C = cplx_t<R>;
   __shared__ C ys[HBI_MAX_LEAF];
-  const int g = blockIdx.x, lane = threadIdx.x;
+  const int g = blockIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const LeafInfo lf = leaves[g];
   const int sz = lf.size;
-  if (lane < sz) ys[lane] = y[perm[lf.start + lane]];
+  if (threadIdx.x < sz) ys[threadIdx.x] = y[perm[lf.start + threadIdx.x]];
   __syncthreads();
-  for (int l = 0; l < Lv; ++l) {
+  for (int l = wave; l < Lv; l += 4) {
     const KDesc d = kd[(int64_t)g * Lv + l];
     if (lane < d.r) {
       const C *K = F + d.foff + (int64_t)lane * sz;
@@ -606,20 +628,22 @@ __global__ __launch_bounds__(64) void k_final_adj(const cplx_t<R> *y,
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_wstage_adj(const WUnit *units,
-                                                    int64_t nunits,
-                                                    const cplx_t<R> *F,
+__global__ __launch_bounds__(256) void k_wstage_adj(const WUnit *units, const WItem *items,
+                                                    int64_t nitems, const cplx_t<R> *F,
                                                     cplx_t<R> *z) {
   using C = cplx_t<R>;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t u = (int64_t)blockIdx.x * 4 + wave;
-  if (u >= nunits) return;
-  const WUnit U = units[u];
+  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+  if (it >= nitems) return;
+  const WItem W = items[it];
+  const WUnit U = units[W.unit];
   const int ra = U.ra, Rt = U.ra + U.rb;
   const C *wa = z + U.zouta, *wb = z + U.zoutb;
   const C *M = F + U.foff;
-  for (int col = lane; col < U.c; col += 64) {
+  const int c1 = W.off + 64 < U.c ? W.off + 64 : U.c;
+  const int col = W.off + lane;
+  if (col < c1) {
     C acc{0, 0};
     const C *cm = M + (int64_t)col * Rt;
     for (int i = 0; i < ra; ++i) cfmac(acc, cm[i], wa[i]);
@@ -629,32 +653,44 @@ __global__ __launch_bounds__(256) void k_wstage_adj(const WUnit *units,
 }
 
 template <typename R>
-__global__ __launch_bounds__(64) void k_vstage_adj(const cplx_t<R> *y,
-                                                   const LeafInfo *leaves,
-                                                   const int32_t *perm,
-                                                   const VDesc *vd, int Lv,
-                                                   const cplx_t<R> *F,
-                                                   const cplx_t<R> *z,
-                                                   cplx_t<R> *u, R hd) {
+__global__ __launch_bounds__(256) void k_vstage_adj(const cplx_t<R> *y,
+                                                    const LeafInfo *leaves,
+                                                    const int32_t *perm,
+                                                    const VDesc *vd, int Lv,
+                                                    const cplx_t<R> *F,
+                                                    const cplx_t<R> *z,
+                                                    cplx_t<R> *u, R hd) {
   using C = cplx_t<R>;
   __shared__ C ys[HBI_MAX_LEAF];
-  const int g = blockIdx.x, lane = threadIdx.x;
+  __shared__ C part[4][HBI_MAX_LEAF];
+  const int g = blockIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const LeafInfo lf = leaves[g];
   const int sz = lf.size;
-  if (lane < sz) ys[lane] = y[perm[lf.start + lane]];
+  if (threadIdx.x < sz) ys[threadIdx.x] = y[perm[lf.start + threadIdx.x]];
   __syncthreads();
-  if (lane >= sz) return;
   C acc{0, 0};
-  // dense leaf: (D^H y)[col], column `lane` of D is contiguous
-  const C *Dc = F + lf.dense_off + (int64_t)lane * sz;
-  for (int row = 0; row < sz; ++row) cfmac(acc, Dc[row], ys[row]);
-  for (int l = 0; l < Lv; ++l) {
-    const VDesc d = vd[(int64_t)g * Lv + l];
-    const C *V = F + d.foff + (int64_t)lane * d.r;
-    const C *w = z + d.zout;
-    for (int row = 0; row < d.r; ++row) cfmac(acc, V[row], w[row]);
+  if (lane < sz) {
+    if (wave == 0) {
+      // dense leaf: (D^H y)[col], column `lane` of D is contiguous
+      const C *Dc = F + lf.dense_off + (int64_t)lane * sz;
+      for (int row = 0; row < sz; ++row) cfmac(acc, Dc[row], ys[row]);
+    }
+    for (int l = wave; l < Lv; l += 4) {
+      const VDesc d = vd[(int64_t)g * Lv + l];
+      const C *V = F + d.foff + (int64_t)lane * d.r;
+      const C *w = z + d.zout;
+      for (int row = 0; row < d.r; ++row) cfmac(acc, V[row], w[row]);
+    }
   }
-  u[perm[lf.start + lane]] = C{acc.x * hd, acc.y * hd};
+  part[wave][lane] = acc;
+  __syncthreads();
+  if (threadIdx.x < sz) {
+    C t = part[0][threadIdx.x];
+    for (int w = 1; w < 4; ++w) { t.x += part[w][threadIdx.x].x; t.y += part[w][threadIdx.x].y; }
+    u[perm[lf.start + threadIdx.x]] = C{t.x * hd, t.y * hd};
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -723,10 +759,11 @@ hipError_t launch_entries(const DevProblem &P, const DevCells &C, const EntryBlo
   return hipGetLastError();
 }
 
-hipError_t launch_cpqr(const IdBlock *blks, int64_t nb, double tol, int32_t *rank,
+hipError_t launch_cpqr(const IdBlock *blks, int64_t nb, int nmax, double tol, int32_t *rank,
                        hipStream_t st) {
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cpqr, dim3(nb), dim3(HBI_ID_THREADS), 0, st, blks, tol, rank);
+  const size_t lds = (size_t)nmax * (sizeof(double) + sizeof(int)) + 16;
+  hipLaunchKernelGGL(k_cpqr, dim3(nb), dim3(HBI_ID_THREADS), lds, st, blks, tol, rank);
   return hipGetLastError();
 }
 
@@ -765,20 +802,21 @@ hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
   if (!adjoint) {
     if (ap.Lv > 0) {
       pre("k_vstage", ap.v_elems, ap.v_idx);
-      hipLaunchKernelGGL((k_vstage<R>), dim3(ap.nleaf), dim3(64), 0, st, sc, ap.leaves,
+      hipLaunchKernelGGL((k_vstage<R>), dim3(ap.nleaf), dim3(256), 0, st, sc, ap.leaves,
                          ap.perm, ap.vd, ap.Lv, Fc, zc, hd);
       post();
     }
     for (int k = 1; k <= ap.Lmax; ++k) {
       const int64_t nu = ap.nunits[k];
       if (nu == 0) continue;
+      const int64_t ni = ap.nitems[k];
       pre("k_wstage", ap.w_elems[k], ap.w_idx[k]);
-      hipLaunchKernelGGL((k_wstage<R>), dim3((nu + 3) / 4), dim3(256), 0, st,
-                         ap.units[k], nu, Fc, zc);
+      hipLaunchKernelGGL((k_wstage<R>), dim3((ni + 3) / 4), dim3(256), 0, st,
+                         ap.units[k], ap.items[k], ni, Fc, zc);
       post();
     }
     pre("k_final", ap.f_elems, ap.f_idx);
-    hipLaunchKernelGGL((k_final<R>), dim3(ap.nleaf), dim3(64), 0, st, sc, ap.leaves,
+    hipLaunchKernelGGL((k_final<R>), dim3(ap.nleaf), dim3(256), 0, st, sc, ap.leaves,
                        ap.perm, ap.kd, ap.Lv, Fc, (const C *)zc, uc, hd);
     post();
   } else {
@@ -786,20 +824,21 @@ hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
     // the final stage and its dense part rides with the V^H stage
     if (ap.Lv > 0) {
       pre("k_final_adj", ap.f_elems, ap.f_idx);
-      hipLaunchKernelGGL((k_final_adj<R>), dim3(ap.nleaf), dim3(64), 0, st, sc, ap.leaves,
+      hipLaunchKernelGGL((k_final_adj<R>), dim3(ap.nleaf), dim3(256), 0, st, sc, ap.leaves,
                          ap.perm, ap.kd, ap.Lv, Fc, zc);
       post();
     }
     for (int k = ap.Lmax; k >= 1; --k) {
       const int64_t nu = ap.nunits[k];
       if (nu == 0) continue;
+      const int64_t ni = ap.nitems_adj[k];
       pre("k_wstage_adj", ap.w_elems[k], ap.w_idx[k]);
-      hipLaunchKernelGGL((k_wstage_adj<R>), dim3((nu + 3) / 4), dim3(256), 0, st,
-                         ap.units[k], nu, Fc, zc);
+      hipLaunchKernelGGL((k_wstage_adj<R>), dim3((ni + 3) / 4), dim3(256), 0, st,
+                         ap.units[k], ap.items_adj[k], ni, Fc, zc);
       post();
     }
     pre("k_vstage_adj", ap.v_elems, ap.v_idx);
-    hipLaunchKernelGGL((k_vstage_adj<R>), dim3(ap.nleaf), dim3(64), 0, st, sc, ap.leaves,
+    hipLaunchKernelGGL((k_vstage_adj<R>), dim3(ap.nleaf), dim3(256), 0, st, sc, ap.leaves,
                        ap.perm, ap.vd, ap.Lv, Fc, (const C *)zc, uc, hd);
     post();
   }

@@ -155,7 +155,7 @@ struct hbi_ctx {
   DevBuf F;
   int64_t Felems = 0;
   DevBuf leaves_d, vd_d, kd_d;
-  std::vector<DevBuf> units_d;
+  std::vector<DevBuf> units_d, items_d, items_adj_d;
   ApplyPlan plan;
   int64_t ztotal = 0;
   DevBuf z_d;
@@ -193,7 +193,7 @@ struct hbi_ctx {
   int64_t wsbytes() const { return opts.workspace_bytes > 0 ? opts.workspace_bytes : (int64_t)2 << 30; }
   void drop_factors() {
     F.release(); Felems = 0; leaves_d.release(); vd_d.release(); kd_d.release();
-    units_d.clear(); plan = ApplyPlan(); ztotal = 0; z_d.release();
+    units_d.clear(); items_d.clear(); items_adj_d.clear(); plan = ApplyPlan(); ztotal = 0; z_d.release();
     nnz_v = nnz_w = nnz_k = nnz_d = entries_eval = nid = 0; rank_max = 0; rank_sum = 0;
     if (state > 1) state = 1;
   }
@@ -432,7 +432,10 @@ struct Batcher {
                            (const int32_t *)(ix + o_cols), c->ws.as<double>(), c->stream));
     for (int64_t q = 0; q < nb; ++q) c->entries_eval += (int64_t)blocks[i0 + q].m * blocks[i0 + q].n;
     if (id) {
-      HBI_HIP(launch_cpqr((const IdBlock *)(ix + o_ib), nb, tol, (int32_t *)(ix + o_rank), c->stream));
+      int nmax = 1;
+      for (int64_t q = 0; q < nb; ++q) nmax = std::max(nmax, (int)blocks[i0 + q].n);
+      HBI_HIP(launch_cpqr((const IdBlock *)(ix + o_ib), nb, nmax, tol, (int32_t *)(ix + o_rank),
+                          c->stream));
       std::vector<int32_t> rank(nb), piv(po);
       HBI_HIP(hipMemcpyAsync(rank.data(), ix + o_rank, nb * 4, hipMemcpyDeviceToHost, c->stream));
       if (po) HBI_HIP(hipMemcpyAsync(piv.data(), ix + o_piv, po * 4, hipMemcpyDeviceToHost, c->stream));
@@ -781,10 +784,48 @@ void build_factors(hbi_ctx *c, double tol) {
   c->plan.kd = c->kd_d.as<KDesc>();
   c->plan.units.assign(Lmax + 1, nullptr);
   c->plan.nunits.assign(Lmax + 1, 0);
+  c->items_d.clear();
+  c->items_d.resize(Lmax + 1);
+  c->items_adj_d.clear();
+  c->items_adj_d.resize(Lmax + 1);
+  c->plan.items.assign(Lmax + 1, nullptr);
+  c->plan.items_adj.assign(Lmax + 1, nullptr);
+  c->plan.nitems.assign(Lmax + 1, 0);
+  c->plan.nitems_adj.assign(Lmax + 1, 0);
   for (int k = 1; k <= Lmax; ++k) {
     upload(c->units_d[k], units[k]);
     c->plan.units[k] = c->units_d[k].as<WUnit>();
     c->plan.nunits[k] = (int64_t)units[k].size();
+    // work items: 64-row (forward) / 64-column (adjoint) windows of every
+    // unit, heaviest first so the long items do not form the tail
+    std::vector<std::pair<int64_t, WItem>> fw, bw;
+    for (int32_t u = 0; u < (int32_t)units[k].size(); ++u) {
+      const WUnit &U = units[k][u];
+      const int Rt = U.ra + U.rb;
+      if (Rt <= 64) {
+        fw.push_back({(int64_t)Rt * U.c, WItem{u, 0}});
+      } else {
+        for (int r0 = 0; r0 < Rt; r0 += 64)
+          fw.push_back({(int64_t)std::min(64, Rt - r0) * U.c, WItem{u, r0}});
+      }
+      for (int c0 = 0; c0 < U.c; c0 += 64)
+        bw.push_back({(int64_t)std::min(64, U.c - c0) * Rt, WItem{u, c0}});
+    }
+    auto order = [](std::vector<std::pair<int64_t, WItem>> &v) {
+      std::stable_sort(v.begin(), v.end(), [](const std::pair<int64_t, WItem> &a,
+                                              const std::pair<int64_t, WItem> &b) {
+        return a.first > b.first;
+      });
+      std::vector<WItem> out(v.size());
+      for (size_t q = 0; q < v.size(); ++q) out[q] = v[q].second;
+      return out;
+    };
+    upload(c->items_d[k], order(fw));
+    upload(c->items_adj_d[k], order(bw));
+    c->plan.items[k] = c->items_d[k].as<WItem>();
+    c->plan.items_adj[k] = c->items_adj_d[k].as<WItem>();
+    c->plan.nitems[k] = (int64_t)fw.size();
+    c->plan.nitems_adj[k] = (int64_t)bw.size();
   }
   // algorithmic traffic per launch (complex elements + index bytes)
   {
