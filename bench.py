@@ -36,6 +36,22 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "HB butterfly apply Gcell·RHS/s at rel err ≤1e-4; build s; % HBM/MFMA peak"
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_wstage_f32_bump1024_traffic.json")
+    src = os.path.join(ROOT, "paper_2210_02698_amd", "csrc", "hbi_kernels.hip")
+    try:
+        rec = json.load(open(path))
+        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_source_sha256") != cur or not rec.get("kernel", "").startswith(kernel):
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -185,7 +201,9 @@ def main():
         "factor_bytes": head["factor_bytes"],
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom) if args.n_side == 1024 else None,
+                     "algorithmic_bytes_per_launch": round(kd["bytes"] / kd["launches"])},
         "cpu_baseline": cpu,
     }
     if "f64" in results:
