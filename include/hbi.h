@@ -131,6 +131,24 @@ hbi_status hbi_apply(hbi_ctx *ctx, const void *s, void *u, int32_t nrhs,
 hbi_status hbi_apply_adjoint(hbi_ctx *ctx, const void *s, void *u,
                              int32_t nrhs, int64_t ld);
 
+/* The batched workload: for p = 0..nprob-1, u[p] = K_p (h^d s[p]) with
+ * nrhs[p] right-hand sides (column-major N_v,p x nrhs[p], leading dimension
+ * ld[p], same element type and rules as hbi_apply).  All contexts must be
+ * built, in the same precision and on the same device; the work is queued
+ * on ctx[0]'s stream.  The factor products of all problems become complex
+ * GEMM tiles over the right-hand sides (16x16x4 MFMA), each stage of every
+ * problem in one launch, and the whole call is captured once into a HIP
+ * graph that later calls with the same contexts and nrhs replay (new
+ * vector pointers are patched in).  On the first call the column-tile
+ * width is chosen by timing the candidates on the batch itself; choices are
+ * kept for the process and in the JSON file named by HBI_TUNE_CACHE when
+ * set.  Vector workspace is bounded by HBI_MULTI_BYTES (default 8 GiB);
+ * larger batches run as several passes inside the same graph.  hbi_apply
+ * with nrhs >= 2 uses the same path for one problem. */
+hbi_status hbi_apply_batched(hbi_ctx *const *ctx, int32_t nprob,
+                             const void *const *s, void *const *u,
+                             const int32_t *nrhs, const int64_t *ld);
+
 /* hb_entry on its own: out[i + m*j] = K[rows[i], cols[j]] (natural cell
  * indices, host int32 arrays) as complex128 into the device array `out`
  * (column-major m x n), including the self term where rows[i] == cols[j].

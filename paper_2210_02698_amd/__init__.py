@@ -24,7 +24,7 @@ import numpy as np
 from . import _lib
 from ._lib import HBIError, HBI_F32, HBI_F64
 
-__all__ = ["Operator", "HBApply", "HBIError", "load_library"]
+__all__ = ["Operator", "HBApply", "HBIError", "load_library", "apply_batched"]
 
 
 def load_library():
@@ -181,6 +181,34 @@ class Operator:
             self.close()
         except Exception:
             pass
+
+
+def apply_batched(ops, S, out=None):
+    """u_p = K_p (h^d s_p) for every operator in `ops` in one library call
+    (hbi_apply_batched): all problems' stages share launches and the call is
+    replayed from a captured HIP graph.  S[p] is an (N_v,p x nrhs_p) device
+    tensor of the operator's dtype; returns column-major outputs."""
+    import torch
+    lib = _lib.load()
+    n = len(ops)
+    if n == 0:
+        return []
+    Sc = [s.reshape(s.shape[0], -1) for s in S]
+    Sc = [s if (s.stride(0) == 1 and (s.shape[1] == 1 or s.stride(1) == s.shape[0]))
+          else s.t().contiguous().t() for s in Sc]
+    for op, s in zip(ops, Sc):
+        if s.dtype != op.dtype or s.shape[0] != op.Nv or s.device != op.device:
+            raise ValueError("right-hand side does not match its operator")
+    U = out if out is not None else [
+        torch.empty((s.shape[1], s.shape[0]), dtype=s.dtype, device=s.device).t() for s in Sc]
+    ctxs = (ctypes.c_void_p * n)(*[o._ctx.value for o in ops])
+    sp = (ctypes.c_void_p * n)(*[s.data_ptr() for s in Sc])
+    up = (ctypes.c_void_p * n)(*[u.data_ptr() for u in U])
+    nr = (ctypes.c_int32 * n)(*[s.shape[1] for s in Sc])
+    ld = (ctypes.c_int64 * n)(*[s.shape[0] for s in Sc])
+    ops[0].set_stream()
+    _lib.check(lib.hbi_apply_batched(ctxs, n, sp, up, nr, ld), ops[0]._ctx)
+    return U
 
 
 def _autograd_function():

@@ -62,6 +62,11 @@ SIGNATURES = [
                                  ctypes.c_int32, ctypes.c_int64]),
     ("hbi_apply_adjoint", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_int32, ctypes.c_int64]),
+    ("hbi_apply_batched", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_void_p),
+                                         ctypes.POINTER(ctypes.c_void_p),
+                                         ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int64)]),
     ("hbi_entries", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_void_p]),
     ("hbi_set_profiling", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),

@@ -14,6 +14,12 @@
 #include "hbi_geometry.h"
 #include "hbi_internal.h"
 #include "hbi_kernels.h"
+#include "hbi_multi.h"
+
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <sstream>
 
 using namespace hbi;
 
@@ -132,6 +138,8 @@ struct Profiler : LaunchHook {
 
 }  // namespace
 
+struct BatchCache;
+
 struct hbi_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -161,6 +169,12 @@ struct hbi_ctx {
   DevBuf z_d;
   bool profiling = false;
   Profiler prof;
+  // host copies of the apply plan (used to assemble batched work items)
+  std::vector<LeafInfo> leaves_h;
+  std::vector<VDesc> vd_h;
+  std::vector<KDesc> kd_h;
+  std::vector<std::vector<WUnit>> units_h;
+  std::shared_ptr<BatchCache> batch;
   // statistics
   double t_build = 0, t_geo = 0, t_host = 0, t_gpu = 0, t_final = 0;
   int64_t nnz_v = 0, nnz_w = 0, nnz_k = 0, nnz_d = 0, entries_eval = 0, nid = 0;
@@ -193,7 +207,8 @@ struct hbi_ctx {
   int64_t wsbytes() const { return opts.workspace_bytes > 0 ? opts.workspace_bytes : (int64_t)2 << 30; }
   void drop_factors() {
     F.release(); Felems = 0; leaves_d.release(); vd_d.release(); kd_d.release();
-    units_d.clear(); items_d.clear(); items_adj_d.clear(); plan = ApplyPlan(); ztotal = 0; z_d.release();
+    units_d.clear(); items_d.clear(); items_adj_d.clear(); plan = ApplyPlan();
+    leaves_h.clear(); vd_h.clear(); kd_h.clear(); units_h.clear(); batch.reset(); ztotal = 0; z_d.release();
     nnz_v = nnz_w = nnz_k = nnz_d = entries_eval = nid = 0; rank_max = 0; rank_sum = 0;
     if (state > 1) state = 1;
   }
@@ -772,6 +787,10 @@ void build_factors(hbi_ctx *c, double tol) {
   upload(c->leaves_d, leaves);
   upload(c->vd_d, vd);
   upload(c->kd_d, kd);
+  c->leaves_h = leaves;
+  c->vd_h = vd;
+  c->kd_h = kd;
+  c->units_h = units;
   c->units_d.clear();
   c->units_d.resize(Lmax + 1);
   c->plan = ApplyPlan();
@@ -893,6 +912,343 @@ void do_apply(hbi_ctx *c, const void *s, void *u, int32_t nrhs, int64_t ld, bool
                                   adj, c->stream, hook));
     }
   }
+}
+
+}  // namespace
+
+// ===========================================================================
+// Many right-hand sides / many problems (MFMA tiles, one HIP graph)
+// ===========================================================================
+struct MultiJob {
+  hbi_ctx *c;
+  int32_t j0, nrhs, Np;     // right-hand-side columns [j0, j0 + nrhs) of problem p
+  int prob;
+  int64_t xt_off = 0, yt_off = 0, z_off = 0;   // element offsets in the pass workspace
+};
+
+struct MultiPass {
+  std::vector<int> jobs;
+  std::vector<MStagePlan> stages;
+  std::vector<DevBuf> bufs;
+  std::vector<MTrans> jin, jout;
+  DevBuf jin_d, jout_d;
+  int64_t maxNv = 0;
+  int maxjt = 0;
+  size_t bytes = 0;
+};
+
+struct BatchCache {
+  std::vector<hbi_ctx *> ctxs;
+  std::vector<int32_t> nrhs;
+  std::vector<const void *> s_ptr;
+  std::vector<void *> u_ptr;
+  std::vector<int64_t> ld;
+  int prec = 0, nb = 4;
+  std::vector<MultiJob> jobs;
+  std::vector<MultiPass> passes;
+  DevBuf ws;
+  hipStream_t gst = nullptr;
+  hipEvent_t e_in = nullptr, e_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double tuned_ms = 0;
+  ~BatchCache() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e_in) (void)hipEventDestroy(e_in);
+    if (e_out) (void)hipEventDestroy(e_out);
+    if (gst) (void)hipStreamDestroy(gst);
+  }
+};
+
+namespace {
+
+size_t multi_budget() {
+  const char *e = std::getenv("HBI_MULTI_BYTES");
+  if (e && *e) return (size_t)std::strtoull(e, nullptr, 10);
+  return (size_t)8 << 30;
+}
+
+int round16(int n) { return (n + 15) & ~15; }
+
+// Split the problems' right-hand sides into jobs and pack them into passes
+// whose vector workspace (x, y and all butterfly vectors, Np wide) fits.
+void plan_passes(BatchCache &B, const std::vector<int32_t> &nrhs) {
+  const size_t budget = multi_budget();
+  const size_t esz = B.prec == HBI_F64 ? 16 : 8;
+  B.jobs.clear();
+  B.passes.clear();
+  for (size_t p = 0; p < B.ctxs.size(); ++p) {
+    hbi_ctx *c = B.ctxs[p];
+    const size_t per_col = (size_t)(2 * c->geo.Nv + c->ztotal) * esz;
+    int cmax = (int)std::min<size_t>(256, (budget / per_col) & ~(size_t)15);
+    if (cmax < 16) throw Error{HBI_ERR_OOM, "batched apply workspace too small for a problem"};
+    for (int j0 = 0; j0 < nrhs[p]; j0 += cmax) {
+      MultiJob J{};
+      J.c = c;
+      J.prob = (int)p;
+      J.j0 = j0;
+      J.nrhs = std::min(cmax, nrhs[p] - j0);
+      J.Np = round16(J.nrhs);
+      B.jobs.push_back(J);
+    }
+  }
+  MultiPass cur;
+  for (int q = 0; q < (int)B.jobs.size(); ++q) {
+    MultiJob &J = B.jobs[q];
+    const size_t b = (size_t)(2 * J.c->geo.Nv + J.c->ztotal) * J.Np * esz;
+    if (!cur.jobs.empty() && cur.bytes + b > budget) {
+      B.passes.push_back(std::move(cur));
+      cur = MultiPass();
+    }
+    cur.jobs.push_back(q);
+    cur.bytes += b;
+  }
+  if (!cur.jobs.empty()) B.passes.push_back(std::move(cur));
+  size_t wsmax = 0;
+  for (auto &P : B.passes) {
+    int64_t o = 0;
+    for (int q : P.jobs) { B.jobs[q].xt_off = o; o += B.jobs[q].c->geo.Nv * B.jobs[q].Np; }
+    for (int q : P.jobs) { B.jobs[q].yt_off = o; o += B.jobs[q].c->geo.Nv * B.jobs[q].Np; }
+    for (int q : P.jobs) { B.jobs[q].z_off = o; o += std::max<int64_t>(B.jobs[q].c->ztotal, 1) * B.jobs[q].Np; }
+    wsmax = std::max(wsmax, (size_t)o * esz);
+  }
+  HBI_HIP(B.ws.reserve(std::max<size_t>(wsmax, 256)));
+}
+
+// Work items of every stage of every pass for `nb` column tiles per wave.
+void build_items(BatchCache &B, int nb) {
+  const size_t esz = B.prec == HBI_F64 ? 16 : 8;
+  char *ws = B.ws.as<char>();
+  for (auto &P : B.passes) {
+    P.stages.clear();
+    P.bufs.clear();
+    P.jin.clear();
+    P.jout.clear();
+    P.maxNv = 0;
+    P.maxjt = 0;
+    int Lmax = 0;
+    std::vector<MVItem> vi;
+    std::vector<MFItem> fi;
+    for (int q : P.jobs) {
+      const MultiJob &J = B.jobs[q];
+      hbi_ctx *c = J.c;
+      const char *F = c->F.as<char>();
+      char *xt = ws + J.xt_off * esz, *yt = ws + J.yt_off * esz, *zb = ws + J.z_off * esz;
+      const int Lv = c->geo.Lv;
+      Lmax = std::max(Lmax, c->plan.Lmax);
+      P.maxNv = std::max(P.maxNv, c->geo.Nv);
+      P.maxjt = std::max(P.maxjt, J.Np / 16);
+      const int ngrp = (J.Np / 16 + nb - 1) / nb;
+      for (int64_t g = 0; g < (int64_t)c->leaves_h.size(); ++g) {
+        const LeafInfo &lf = c->leaves_h[g];
+        const char *x = xt + (int64_t)lf.start * J.Np * esz;
+        for (int l = 0; l < Lv; ++l) {
+          const VDesc &d = c->vd_h[g * Lv + l];
+          for (int r0 = 0; r0 < d.r; r0 += 16)
+            for (int gq = 0; gq < ngrp; ++gq)
+              vi.push_back(MVItem{F + d.foff * esz, x, zb + d.zout * J.Np * esz, d.r, lf.size, r0,
+                                  gq * nb, J.Np, 0});
+        }
+        for (int r0 = 0; r0 < lf.size; r0 += 16)
+          for (int gq = 0; gq < ngrp; ++gq)
+            fi.push_back(MFItem{F, zb, x, yt + (int64_t)lf.start * J.Np * esz,
+                                c->kd_d.as<KDesc>() + g * Lv, lf.dense_off, lf.size, Lv, r0,
+                                gq * nb, J.Np, 0});
+      }
+      const size_t cofs = (size_t)J.j0 * esz;
+      P.jin.push_back(MTrans{(const char *)B.s_ptr[J.prob] + cofs * B.ld[J.prob], xt,
+                             c->perm_d.as<int32_t>(), c->geo.Nv, B.ld[J.prob], J.nrhs, J.Np,
+                             std::pow(c->h, c->dim)});
+      P.jout.push_back(MTrans{yt, (char *)B.u_ptr[J.prob] + cofs * B.ld[J.prob],
+                              c->perm_d.as<int32_t>(), c->geo.Nv, B.ld[J.prob], J.nrhs, J.Np, 1.0});
+    }
+    auto add_stage = [&](int kind, const void *data, size_t bytes, int64_t n) {
+      DevBuf d;
+      HBI_HIP(d.alloc(bytes));
+      if (bytes) HBI_HIP(hipMemcpy(d.p, data, bytes, hipMemcpyHostToDevice));
+      P.stages.push_back(MStagePlan{kind, nb, d.p, n});
+      P.bufs.push_back(std::move(d));
+    };
+    add_stage(0, vi.data(), vi.size() * sizeof(MVItem), (int64_t)vi.size());
+    for (int k = 1; k <= Lmax; ++k) {
+      std::vector<std::pair<int64_t, MWItem>> wi;
+      for (int q : P.jobs) {
+        const MultiJob &J = B.jobs[q];
+        hbi_ctx *c = J.c;
+        if (k > c->plan.Lmax) continue;
+        const char *F = c->F.as<char>();
+        char *zb = ws + J.z_off * esz;
+        const int ngrp = (J.Np / 16 + nb - 1) / nb;
+        for (const WUnit &U : c->units_h[k]) {
+          const int Rt = U.ra + U.rb;
+          for (int r0 = 0; r0 < Rt; r0 += 16)
+            for (int gq = 0; gq < ngrp; ++gq)
+              wi.push_back({(int64_t)U.c, MWItem{F + U.foff * esz, zb + U.zin * J.Np * esz,
+                                                 zb + U.zouta * J.Np * esz,
+                                                 zb + U.zoutb * J.Np * esz, U.ra, U.rb, U.c, r0,
+                                                 gq * nb, J.Np}});
+        }
+      }
+      std::stable_sort(wi.begin(), wi.end(), [](const std::pair<int64_t, MWItem> &a,
+                                                const std::pair<int64_t, MWItem> &b) {
+        return a.first > b.first;
+      });
+      std::vector<MWItem> w(wi.size());
+      for (size_t q = 0; q < wi.size(); ++q) w[q] = wi[q].second;
+      add_stage(1, w.data(), w.size() * sizeof(MWItem), (int64_t)w.size());
+    }
+    add_stage(2, fi.data(), fi.size() * sizeof(MFItem), (int64_t)fi.size());
+    upload(P.jin_d, P.jin);
+    upload(P.jout_d, P.jout);
+  }
+  B.nb = nb;
+}
+
+void launch_passes(BatchCache &B, hipStream_t st) {
+  for (auto &P : B.passes) {
+    if (B.prec == HBI_F64) {
+      HBI_HIP(launch_gather_in<double>(P.jin_d.as<MTrans>(), (int64_t)P.jin.size(), P.maxNv,
+                                       P.maxjt, st));
+      for (auto &sp : P.stages) HBI_HIP(launch_multi_stage<double>(sp, st));
+      HBI_HIP(launch_scatter_out<double>(P.jout_d.as<MTrans>(), (int64_t)P.jout.size(), P.maxNv,
+                                         P.maxjt, st));
+    } else {
+      HBI_HIP(launch_gather_in<float>(P.jin_d.as<MTrans>(), (int64_t)P.jin.size(), P.maxNv,
+                                      P.maxjt, st));
+      for (auto &sp : P.stages) HBI_HIP(launch_multi_stage<float>(sp, st));
+      HBI_HIP(launch_scatter_out<float>(P.jout_d.as<MTrans>(), (int64_t)P.jout.size(), P.maxNv,
+                                        P.maxjt, st));
+    }
+  }
+}
+
+// Tuned column-tile width per (precision, widest column-tile count),
+// shared by every batch of the process and optionally kept in the JSON
+// file named by HBI_TUNE_CACHE.
+std::map<std::string, int> &tune_table() {
+  static std::map<std::string, int> t;
+  static bool loaded = false;
+  if (!loaded) {
+    loaded = true;
+    const char *path = std::getenv("HBI_TUNE_CACHE");
+    if (path && *path) {
+      std::ifstream f(path);
+      std::string line;
+      while (std::getline(f, line)) {
+        const auto q1 = line.find('"'), q2 = line.find('"', q1 + 1), colon = line.find(':', q2);
+        if (q1 == std::string::npos || q2 == std::string::npos || colon == std::string::npos) continue;
+        t[line.substr(q1 + 1, q2 - q1 - 1)] = std::atoi(line.c_str() + colon + 1);
+      }
+    }
+  }
+  return t;
+}
+
+void save_tune_table() {
+  const char *path = std::getenv("HBI_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::ofstream f(path);
+  f << "{\n";
+  size_t i = 0;
+  for (auto &kv : tune_table())
+    f << "  \"" << kv.first << "\": " << kv.second << (++i < tune_table().size() ? ",\n" : "\n");
+  f << "}\n";
+}
+
+double time_passes(BatchCache &B, int reps) {
+  hipEvent_t a, b;
+  HBI_HIP(hipEventCreate(&a));
+  HBI_HIP(hipEventCreate(&b));
+  launch_passes(B, B.gst);   // warm
+  HBI_HIP(hipEventRecord(a, B.gst));
+  for (int r = 0; r < reps; ++r) launch_passes(B, B.gst);
+  HBI_HIP(hipEventRecord(b, B.gst));
+  HBI_HIP(hipEventSynchronize(b));
+  float ms = 0;
+  HBI_HIP(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms / reps;
+}
+
+void multi_apply(hbi_ctx *c0, const std::vector<hbi_ctx *> &ctxs, const std::vector<const void *> &s,
+                 const std::vector<void *> &u, const std::vector<int32_t> &nrhs,
+                 const std::vector<int64_t> &ld) {
+  const int prec = ctxs[0]->prec;
+  for (size_t p = 0; p < ctxs.size(); ++p) {
+    HBI_REQUIRE(ctxs[p] && ctxs[p]->state == 2, HBI_ERR_STATE, "batched apply before build");
+    HBI_REQUIRE(ctxs[p]->prec == prec, HBI_ERR_ARG, "batched problems differ in precision");
+    HBI_REQUIRE(ctxs[p]->device == c0->device, HBI_ERR_ARG, "batched problems on different devices");
+    check_apply_args(ctxs[p], s[p], u[p], nrhs[p], ld[p]);
+  }
+  std::shared_ptr<BatchCache> B = c0->batch;
+  const bool same = B && B->ctxs == ctxs && B->nrhs == nrhs && B->prec == prec;
+  if (!same) {
+    B = std::make_shared<BatchCache>();
+    B->ctxs = ctxs;
+    B->nrhs = nrhs;
+    B->prec = prec;
+    B->s_ptr = s;
+    B->u_ptr = u;
+    B->ld = ld;
+    HBI_HIP(hipStreamCreateWithFlags(&B->gst, hipStreamNonBlocking));
+    HBI_HIP(hipEventCreateWithFlags(&B->e_in, hipEventDisableTiming));
+    HBI_HIP(hipEventCreateWithFlags(&B->e_out, hipEventDisableTiming));
+    HBI_HIP(hipEventRecord(B->e_in, c0->stream));
+    HBI_HIP(hipStreamWaitEvent(B->gst, B->e_in, 0));
+    plan_passes(*B, nrhs);
+    // autotune the column-tile width on this batch (cached per process)
+    int maxjt = 1;
+    for (auto &J : B->jobs) maxjt = std::max(maxjt, J.Np / 16);
+    const std::string key = std::string(prec == HBI_F64 ? "f64" : "f32") + ":jt" + std::to_string(maxjt);
+    auto &tt = tune_table();
+    int best = -1;
+    if (tt.count(key)) {
+      best = tt[key];
+    } else {
+      double bt = 1e300;
+      for (int nb : {1, 2, 4, 8}) {
+        if (nb > 1 && nb > maxjt) break;
+        build_items(*B, nb);
+        const double t = time_passes(*B, 2);
+        if (t < bt) { bt = t; best = nb; }
+      }
+      B->tuned_ms = bt;
+      tt[key] = best;
+      save_tune_table();
+    }
+    build_items(*B, best);
+    HBI_HIP(hipStreamBeginCapture(B->gst, hipStreamCaptureModeRelaxed));
+    launch_passes(*B, B->gst);
+    HBI_HIP(hipStreamEndCapture(B->gst, &B->graph));
+    HBI_HIP(hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0));
+    c0->batch = B;
+  } else if (B->s_ptr != s || B->u_ptr != u || B->ld != ld) {
+    // new vector pointers: refresh the gather/scatter job tables
+    HBI_HIP(hipStreamSynchronize(B->gst));
+    B->s_ptr = s;
+    B->u_ptr = u;
+    B->ld = ld;
+    const size_t esz = prec == HBI_F64 ? 16 : 8;
+    for (auto &P : B->passes) {
+      for (size_t q = 0; q < P.jobs.size(); ++q) {
+        const MultiJob &J = B->jobs[P.jobs[q]];
+        const size_t cofs = (size_t)J.j0 * esz * ld[J.prob];
+        P.jin[q].src = (const char *)s[J.prob] + cofs;
+        P.jin[q].ld = ld[J.prob];
+        P.jout[q].dst = (char *)u[J.prob] + cofs;
+        P.jout[q].ld = ld[J.prob];
+      }
+      HBI_HIP(hipMemcpy(P.jin_d.p, P.jin.data(), P.jin.size() * sizeof(MTrans), hipMemcpyHostToDevice));
+      HBI_HIP(hipMemcpy(P.jout_d.p, P.jout.data(), P.jout.size() * sizeof(MTrans), hipMemcpyHostToDevice));
+    }
+  }
+  HBI_HIP(hipEventRecord(B->e_in, c0->stream));
+  HBI_HIP(hipStreamWaitEvent(B->gst, B->e_in, 0));
+  HBI_HIP(hipGraphLaunch(B->gexec, B->gst));
+  HBI_HIP(hipEventRecord(B->e_out, B->gst));
+  HBI_HIP(hipStreamWaitEvent(c0->stream, B->e_out, 0));
 }
 
 }  // namespace
@@ -1027,7 +1383,26 @@ hbi_status hbi_build(hbi_ctx *ctx, double tol, hbi_prec prec) {
 
 hbi_status hbi_apply(hbi_ctx *ctx, const void *s, void *u, int32_t nrhs, int64_t ld) {
   if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
-  return guarded(ctx, [&]() { do_apply(ctx, s, u, nrhs, ld, false); });
+  return guarded(ctx, [&]() {
+    if (nrhs >= 2 && !ctx->profiling)
+      multi_apply(ctx, {ctx}, {s}, {u}, {nrhs}, {ld});
+    else
+      do_apply(ctx, s, u, nrhs, ld, false);
+  });
+}
+
+hbi_status hbi_apply_batched(hbi_ctx *const *ctx, int32_t nprob, const void *const *s,
+                             void *const *u, const int32_t *nrhs, const int64_t *ld) {
+  if (!ctx || nprob < 1 || !ctx[0]) { g_err = "ctx is NULL or nprob < 1"; return HBI_ERR_ARG; }
+  return guarded(ctx[0], [&]() {
+    HBI_REQUIRE(s && u && nrhs && ld, HBI_ERR_ARG, "null argument array");
+    std::vector<hbi_ctx *> cs(ctx, ctx + nprob);
+    std::vector<const void *> sv(s, s + nprob);
+    std::vector<void *> uv(u, u + nprob);
+    std::vector<int32_t> nv(nrhs, nrhs + nprob);
+    std::vector<int64_t> lv(ld, ld + nprob);
+    multi_apply(ctx[0], cs, sv, uv, nv, lv);
+  });
 }
 
 hbi_status hbi_apply_adjoint(hbi_ctx *ctx, const void *s, void *u, int32_t nrhs, int64_t ld) {

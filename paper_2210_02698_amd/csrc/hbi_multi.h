@@ -1,0 +1,63 @@
+// Work items and launchers of the multi-right-hand-side (MFMA) apply.
+#pragma once
+#include "hbi_internal.h"
+
+namespace hbi {
+
+// Transfer-stage item: rows [r0, r0+16) x column tiles [jt, jt+NB) of the
+// stacked unit M ((ra+rb) x c, column-major).  Vector pointers are absolute.
+struct MWItem {
+  const void *M;
+  const void *zin;     // c x Np
+  void *za, *zb;       // ra x Np, rb x Np
+  int32_t ra, rb, c, r0, jt, Np;
+};
+
+// V^0 item: rows [r0, r0+16) of V (r x sz) times the leaf's inputs.
+struct MVItem {
+  const void *V;
+  const void *x;       // sz x Np (tree-ordered input rows of the leaf)
+  void *z;             // r x Np
+  int32_t r, sz, r0, jt, Np, pad;
+};
+
+// Final item: rows [r0, r0+16) of one leaf: dense block plus the K^L of
+// every HODBF level.
+struct MFItem {
+  const void *F;       // factor store (element offsets below)
+  const void *z;       // z base of the problem (offsets in kd are rows)
+  const void *x;       // sz x Np leaf inputs
+  void *y;             // sz x Np leaf outputs
+  const KDesc *kd;     // Lv descriptors of this leaf
+  int64_t dense_off;
+  int32_t sz, Lv, r0, jt, Np, pad;
+};
+
+// Gather / scatter between natural column-major vectors and tree-ordered
+// row-major blocks.
+struct MTrans {
+  const void *src;
+  void *dst;
+  const int32_t *perm;
+  int64_t Nv, ld;
+  int32_t nrhs, Np;
+  double scale;
+};
+
+struct MStagePlan {
+  int kind;            // 0 V, 1 W, 2 final
+  int nb;              // column tiles per wave
+  const void *items;
+  int64_t n;
+};
+
+template <typename R> hipError_t launch_multi_stage(const MStagePlan &sp, hipStream_t st);
+template <typename R>
+hipError_t launch_gather_in(const MTrans *jobs, int64_t njobs, int64_t maxNv, int maxjt,
+                            hipStream_t st);
+template <typename R>
+hipError_t launch_scatter_out(const MTrans *jobs, int64_t njobs, int64_t maxNv, int maxjt,
+                              hipStream_t st);
+hipError_t launch_mfma_probe(const float *A, const float *B, float *D, hipStream_t st);
+
+}  // namespace hbi

@@ -1,0 +1,289 @@
+// Many right-hand sides (and many problems) per launch: the factor
+// products become small complex GEMMs Y = M Z, computed with 16x16x4 MFMA
+// tiles (FP32: v_mfma_f32_16x16x4_f32, FP64: v_mfma_f64_16x16x4_f64).
+//
+// A complex GEMM step is four real MFMAs on the same operands:
+//   Yr += Mr Zr - Mi Zi,   Yi += Mr Zi + Mi Zr.
+// Operand layout of the 16x16x4 MFMA (one wave): lane l holds A[l%16][l/16]
+// and B[l/16][l%16].  Accumulator v = 0..3 of lane l holds D[4*(l/16) + v]
+// [l%16] for the FP32 instruction and D[l/16 + 4*v][l%16] for the FP64 one
+// (checked on gfx950 with a probe of both builtins).
+//
+// Vectors are in tree order with the right-hand sides contiguous:
+// element (row, j) of a block with offset zoff is z[(zoff + row) * Np + j],
+// Np = nrhs rounded up to 16.  Factor blocks keep their single-RHS
+// column-major layout, so every factor entry is loaded once per 16-row
+// tile and reused for all Np right-hand sides.
+#include "hbi_device.h"
+#include "hbi_multi.h"
+
+namespace hbi {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <typename R> struct Mfma;
+template <> struct Mfma<float> {
+  using acc = v4f;
+  static __device__ __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ acc op(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // row of the result held by accumulator v of a lane in group g = l/16
+  static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
+};
+template <> struct Mfma<double> {
+  using acc = v4d;
+  static __device__ __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ acc op(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int g, int v) { return g + 4 * v; }
+};
+
+// Accumulate a 16-row tile of M (rows r0.., column-major, leading dimension
+// ldm, `rows` valid rows, `k` columns) times Z (k x Np, row stride Np),
+// for column tiles [jt0, jt0 + NB) of 16 columns each.
+template <typename R, int NB>
+__device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int ldm, int r0,
+                                          int rows, int k, const cplx_t<R> *__restrict__ Z,
+                                          int Np, int jt0, int lane,
+                                          typename Mfma<R>::acc (&ar)[NB],
+                                          typename Mfma<R>::acc (&ai)[NB]) {
+  using C = cplx_t<R>;
+  const int li = lane & 15, lk = lane >> 4;
+  const int row = r0 + li;
+  const bool rok = row < rows;
+  for (int k0 = 0; k0 < k; k0 += 4) {
+    const int kk = k0 + lk;
+    C a{0, 0};
+    if (rok && kk < k) a = M[row + (int64_t)kk * ldm];
+    const R nai = -a.y;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      C b{0, 0};
+      if (kk < k) b = Z[(int64_t)kk * Np + (jt0 + nb) * 16 + li];
+      ar[nb] = Mfma<R>::op(a.x, b.x, ar[nb]);
+      ar[nb] = Mfma<R>::op(nai, b.y, ar[nb]);
+      ai[nb] = Mfma<R>::op(a.x, b.y, ai[nb]);
+      ai[nb] = Mfma<R>::op(a.y, b.x, ai[nb]);
+    }
+  }
+}
+
+// Transfer stage: one wave per (unit, 16-row tile, group of NB column tiles).
+template <typename R, int NB>
+__global__ __launch_bounds__(256) void k_wstage_mr(const MWItem *items, int64_t nitems) {
+  using C = cplx_t<R>;
+  using A = typename Mfma<R>::acc;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+  if (it >= nitems) return;
+  const MWItem W = items[it];
+  A ar[NB], ai[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) { ar[nb] = Mfma<R>::zero(); ai[nb] = Mfma<R>::zero(); }
+  const int Rt = W.ra + W.rb;
+  const int jt0 = W.jt;
+  const int nbv = (W.Np >> 4) - jt0 < NB ? (W.Np >> 4) - jt0 : NB;
+  tile_gemm<R, NB>((const C *)W.M, Rt, W.r0, Rt, W.c, (const C *)W.zin, W.Np, jt0, lane, ar, ai);
+  const int li = lane & 15, lg = lane >> 4;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = W.r0 + Mfma<R>::row(lg, v);
+    if (row >= Rt) continue;
+    C *dst = row < W.ra ? (C *)W.za + (int64_t)row * W.Np : (C *)W.zb + (int64_t)(row - W.ra) * W.Np;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      if (nb < nbv) dst[(jt0 + nb) * 16 + li] = C{ar[nb][v], ai[nb][v]};
+  }
+}
+
+// V^0 stage: one wave per (leaf, level, 16-row tile, column-tile group).
+template <typename R, int NB>
+__global__ __launch_bounds__(256) void k_vstage_mr(const MVItem *items, int64_t nitems) {
+  using C = cplx_t<R>;
+  using A = typename Mfma<R>::acc;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+  if (it >= nitems) return;
+  const MVItem W = items[it];
+  A ar[NB], ai[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) { ar[nb] = Mfma<R>::zero(); ai[nb] = Mfma<R>::zero(); }
+  const int nbv = (W.Np >> 4) - W.jt < NB ? (W.Np >> 4) - W.jt : NB;
+  tile_gemm<R, NB>((const C *)W.V, W.r, W.r0, W.r, W.sz, (const C *)W.x, W.Np, W.jt, lane, ar, ai);
+  const int li = lane & 15, lg = lane >> 4;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = W.r0 + Mfma<R>::row(lg, v);
+    if (row >= W.r) continue;
+    C *dst = (C *)W.z + (int64_t)row * W.Np;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      if (nb < nbv) dst[(W.jt + nb) * 16 + li] = C{ar[nb][v], ai[nb][v]};
+  }
+}
+
+// Final stage: one wave per (leaf, 16-row tile, column-tile group); the
+// dense leaf block and every level's K^L accumulate into the same tiles in
+// a fixed order.
+template <typename R, int NB>
+__global__ __launch_bounds__(256) void k_final_mr(const MFItem *items, int64_t nitems) {
+  using C = cplx_t<R>;
+  using A = typename Mfma<R>::acc;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+  if (it >= nitems) return;
+  const MFItem W = items[it];
+  A ar[NB], ai[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) { ar[nb] = Mfma<R>::zero(); ai[nb] = Mfma<R>::zero(); }
+  const C *F = (const C *)W.F;
+  const C *z = (const C *)W.z;
+  const int sz = W.sz;
+  tile_gemm<R, NB>(F + W.dense_off, sz, W.r0, sz, sz, (const C *)W.x, W.Np, W.jt, lane, ar, ai);
+  for (int l = 0; l < W.Lv; ++l) {
+    const KDesc d = W.kd[l];
+    tile_gemm<R, NB>(F + d.foff, sz, W.r0, sz, d.r, z + d.zin * W.Np, W.Np, W.jt, lane, ar, ai);
+  }
+  const int nbv = (W.Np >> 4) - W.jt < NB ? (W.Np >> 4) - W.jt : NB;
+  const int li = lane & 15, lg = lane >> 4;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = W.r0 + Mfma<R>::row(lg, v);
+    if (row >= sz) continue;
+    C *dst = (C *)W.y + (int64_t)row * W.Np;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      if (nb < nbv) dst[(W.jt + nb) * 16 + li] = C{ar[nb][v], ai[nb][v]};
+  }
+}
+
+// s (natural order, column-major N_v x nrhs, leading dimension ld) ->
+// x (tree order, row stride Np), scaled by h^d; columns nrhs..Np-1 zeroed.
+// 64 tree positions x 16 columns per workgroup through LDS.
+template <typename R>
+__global__ __launch_bounds__(256) void k_gather_in(const MTrans *jobs, int64_t njobs) {
+  using C = cplx_t<R>;
+  __shared__ C tile[64][17];
+  const MTrans J = jobs[blockIdx.y];
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int jt = blockIdx.z;
+  if (p0 >= J.Nv || jt * 16 >= J.Np) return;
+  const int t = threadIdx.x;
+  // read: column j fastest-varying over threads' positions
+  for (int q = t; q < 64 * 16; q += 256) {
+    const int pl = q & 63, j = q >> 6;
+    const int64_t p = p0 + pl;
+    const int col = jt * 16 + j;
+    C v{0, 0};
+    if (p < J.Nv && col < J.nrhs) {
+      const C s = ((const C *)J.src)[J.perm[p] + (int64_t)col * J.ld];
+      v = C{s.x * (R)J.scale, s.y * (R)J.scale};
+    }
+    tile[pl][j] = v;
+  }
+  __syncthreads();
+  for (int q = t; q < 64 * 16; q += 256) {
+    const int j = q & 15, pl = q >> 4;
+    const int64_t p = p0 + pl;
+    if (p < J.Nv) ((C *)J.dst)[p * J.Np + jt * 16 + j] = tile[pl][j];
+  }
+}
+
+// y (tree order, row stride Np) -> u (natural order, column-major, ld).
+template <typename R>
+__global__ __launch_bounds__(256) void k_scatter_out(const MTrans *jobs, int64_t njobs) {
+  using C = cplx_t<R>;
+  __shared__ C tile[64][17];
+  const MTrans J = jobs[blockIdx.y];
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int jt = blockIdx.z;
+  if (p0 >= J.Nv || jt * 16 >= J.Np) return;
+  const int t = threadIdx.x;
+  for (int q = t; q < 64 * 16; q += 256) {
+    const int j = q & 15, pl = q >> 4;
+    const int64_t p = p0 + pl;
+    if (p < J.Nv) tile[pl][j] = ((const C *)J.src)[p * J.Np + jt * 16 + j];
+  }
+  __syncthreads();
+  for (int q = t; q < 64 * 16; q += 256) {
+    const int pl = q & 63, j = q >> 6;
+    const int64_t p = p0 + pl;
+    const int col = jt * 16 + j;
+    if (p < J.Nv && col < J.nrhs) ((C *)J.dst)[J.perm[p] + (int64_t)col * J.ld] = tile[pl][j];
+  }
+}
+
+// MFMA operand-layout check: D = A B for one 16x16x4 tile (A row-major
+// 16x4, B row-major 4x16, D row-major 16x16), exactly as the GEMM kernels
+// use the instruction.
+__global__ void k_mfma_probe(const float *A, const float *B, float *D) {
+  const int l = threadIdx.x;
+  v4f acc = {0.f, 0.f, 0.f, 0.f};
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[(l & 15) * 4 + (l >> 4)], B[(l >> 4) * 16 + (l & 15)],
+                                             acc, 0, 0, 0);
+  for (int v = 0; v < 4; ++v) D[(4 * (l >> 4) + v) * 16 + (l & 15)] = acc[v];
+}
+
+// ---------------------------------------------------------------------------
+template <typename R, int NB>
+static void launch_stage_nb(const MStagePlan &sp, hipStream_t st) {
+  if (sp.kind == 0 && sp.n)
+    hipLaunchKernelGGL((k_vstage_mr<R, NB>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
+                       (const MVItem *)sp.items, sp.n);
+  if (sp.kind == 1 && sp.n)
+    hipLaunchKernelGGL((k_wstage_mr<R, NB>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
+                       (const MWItem *)sp.items, sp.n);
+  if (sp.kind == 2 && sp.n)
+    hipLaunchKernelGGL((k_final_mr<R, NB>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
+                       (const MFItem *)sp.items, sp.n);
+}
+
+template <typename R>
+hipError_t launch_multi_stage(const MStagePlan &sp, hipStream_t st) {
+  switch (sp.nb) {
+    case 1: launch_stage_nb<R, 1>(sp, st); break;
+    case 2: launch_stage_nb<R, 2>(sp, st); break;
+    case 4: launch_stage_nb<R, 4>(sp, st); break;
+    case 8: launch_stage_nb<R, 8>(sp, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_gather_in(const MTrans *jobs, int64_t njobs, int64_t maxNv, int maxjt,
+                            hipStream_t st) {
+  if (njobs == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_gather_in<R>), dim3((maxNv + 63) / 64, njobs, maxjt), dim3(256), 0, st,
+                     jobs, njobs);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_scatter_out(const MTrans *jobs, int64_t njobs, int64_t maxNv, int maxjt,
+                              hipStream_t st) {
+  if (njobs == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_scatter_out<R>), dim3((maxNv + 63) / 64, njobs, maxjt), dim3(256), 0, st,
+                     jobs, njobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_mfma_probe(const float *A, const float *B, float *D, hipStream_t st) {
+  hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, st, A, B, D);
+  return hipGetLastError();
+}
+
+template hipError_t launch_multi_stage<float>(const MStagePlan &, hipStream_t);
+template hipError_t launch_multi_stage<double>(const MStagePlan &, hipStream_t);
+template hipError_t launch_gather_in<float>(const MTrans *, int64_t, int64_t, int, hipStream_t);
+template hipError_t launch_gather_in<double>(const MTrans *, int64_t, int64_t, int, hipStream_t);
+template hipError_t launch_scatter_out<float>(const MTrans *, int64_t, int64_t, int, hipStream_t);
+template hipError_t launch_scatter_out<double>(const MTrans *, int64_t, int64_t, int, hipStream_t);
+
+}  // namespace hbi
