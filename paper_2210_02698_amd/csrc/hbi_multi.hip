@@ -43,7 +43,9 @@ template <> struct Mfma<double> {
 
 // Accumulate a 16-row tile of M (rows r0.., column-major, leading dimension
 // ldm, `rows` valid rows, `k` columns) times Z (k x Np, row stride Np),
-// for column tiles [jt0, jt0 + NB) of 16 columns each.
+// for column tiles [jt0, jt0 + NB) of 16 columns each.  Four k-steps (16
+// columns of M) are loaded before their MFMAs are issued, so each wave keeps
+// 4 (1 + NB) loads in flight.
 template <typename R, int NB>
 __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int ldm, int r0,
                                           int rows, int k, const cplx_t<R> *__restrict__ Z,
@@ -51,22 +53,32 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
                                           typename Mfma<R>::acc (&ar)[NB],
                                           typename Mfma<R>::acc (&ai)[NB]) {
   using C = cplx_t<R>;
+  constexpr int KU = 4;
   const int li = lane & 15, lk = lane >> 4;
   const int row = r0 + li;
   const bool rok = row < rows;
-  for (int k0 = 0; k0 < k; k0 += 4) {
-    const int kk = k0 + lk;
-    C a{0, 0};
-    if (rok && kk < k) a = M[row + (int64_t)kk * ldm];
-    const R nai = -a.y;
+  const C *Mp = M + row;
+  const C *Zp = Z + jt0 * 16 + li;
+  for (int k0 = 0; k0 < k; k0 += 4 * KU) {
+    C a[KU], b[KU][NB];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      C b{0, 0};
-      if (kk < k) b = Z[(int64_t)kk * Np + (jt0 + nb) * 16 + li];
-      ar[nb] = Mfma<R>::op(a.x, b.x, ar[nb]);
-      ar[nb] = Mfma<R>::op(nai, b.y, ar[nb]);
-      ai[nb] = Mfma<R>::op(a.x, b.y, ai[nb]);
-      ai[nb] = Mfma<R>::op(a.y, b.x, ai[nb]);
+    for (int u = 0; u < KU; ++u) {
+      const int kk = k0 + 4 * u + lk;
+      const bool kok = kk < k;
+      a[u] = (rok && kok) ? Mp[(int64_t)kk * ldm] : C{0, 0};
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) b[u][nb] = kok ? Zp[(int64_t)kk * Np + nb * 16] : C{0, 0};
+    }
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const R nai = -a[u].y;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        ar[nb] = Mfma<R>::op(a[u].x, b[u][nb].x, ar[nb]);
+        ar[nb] = Mfma<R>::op(nai, b[u][nb].y, ar[nb]);
+        ai[nb] = Mfma<R>::op(a[u].x, b[u][nb].y, ai[nb]);
+        ai[nb] = Mfma<R>::op(a[u].y, b[u][nb].x, ai[nb]);
+      }
     }
   }
 }
