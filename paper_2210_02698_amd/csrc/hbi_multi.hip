@@ -59,6 +59,8 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
   const bool rok = row < rows;
   const C *Mp = M + row;
   const C *Zp = Z + jt0 * 16 + li;
+  // column tiles past Np (last group of a row) are never read
+  const int nbv = (Np >> 4) - jt0 < NB ? (Np >> 4) - jt0 : NB;
   for (int k0 = 0; k0 < k; k0 += 4 * KU) {
     C a[KU], b[KU][NB];
 #pragma unroll
@@ -67,7 +69,8 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
       const bool kok = kk < k;
       a[u] = (rok && kok) ? Mp[(int64_t)kk * ldm] : C{0, 0};
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) b[u][nb] = kok ? Zp[(int64_t)kk * Np + nb * 16] : C{0, 0};
+      for (int nb = 0; nb < NB; ++nb)
+        b[u][nb] = (kok && nb < nbv) ? Zp[(int64_t)kk * Np + nb * 16] : C{0, 0};
     }
 #pragma unroll
     for (int u = 0; u < KU; ++u) {
