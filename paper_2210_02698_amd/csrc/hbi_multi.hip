@@ -77,6 +77,7 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
       const R nai = -a[u].y;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
+        if (nb >= nbv) break;   // wave-uniform: no MFMAs on padding tiles
         ar[nb] = Mfma<R>::op(a[u].x, b[u][nb].x, ar[nb]);
         ar[nb] = Mfma<R>::op(nai, b[u][nb].y, ar[nb]);
         ai[nb] = Mfma<R>::op(a[u].x, b[u][nb].y, ai[nb]);

@@ -298,3 +298,52 @@ def test_autograd_gradient(torch_mod):
             an = (np.conj(unit) * grad[j]).real
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd))
     op.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_inverse_source_gradient_bump256(torch_mod, prec):
+    """Differentiation workload: Gaussian bump on 256^2 cells, P = 512 seeded
+    receivers, d = P K s_true from 20 seeded point sources (FP64 oracle),
+    loss ||P K h^d s - d||^2 at a seeded complex64 s.  The gradient through
+    HBApply (hand-written adjoint) matches the dense FP64 adjoint
+    2 h^d K[P]^H (K[P] h^d s - d) and central finite differences (step 1e-3)
+    of the dense FP64 loss, which is exactly quadratic."""
+    torch = torch_mod
+    import paper_2210_02698_amd as hbi
+    prob = hb_inputs.configs.c4()
+    say(f"gradient bump256 {prec}")
+    op = make_op(prob, tol=1e-7 if prec == "f64" else 1e-6, prec=prec)
+    seed = hb_inputs.configs.CFG_SEED["c4"]
+    g = np.random.default_rng([seed, 0])
+    P = np.sort(g.choice(prob.Nv, 512, replace=False))
+    cells, s_true = hb_inputs.point_sources(prob, 20, [seed, 1])
+    KP = oracle.entries(prob, P, np.arange(prob.Nv))          # dense FP64 rows
+    hd = prob.h ** 2
+    d = KP @ (s_true * hd)
+    s0 = hb_inputs.complex_normal(prob.Nv, [seed, 2], dtype=np.complex64).astype(np.complex128)
+    dt = torch.complex64 if prec == "f32" else torch.complex128
+    s = to_dev(torch, s0, dt).requires_grad_(True)
+    Pd = torch.from_numpy(P).to("cuda:0")
+    dd = to_dev(torch, d, dt)
+    u = hbi.HBApply.apply(op, s)
+    loss = (u[Pd] - dd).abs().pow(2).sum()
+    loss.backward()
+    grad = s.grad.cpu().numpy().astype(np.complex128)
+    r = KP @ (s0 * hd) - d
+    ref = 2 * hd * (KP.conj().T @ r)
+    e = rel(grad, ref)
+    say(f"gradient rel err vs dense adjoint {e:.2e}")
+    assert e < (1e-4 if prec == "f32" else 1e-6), e
+
+    def L(x):
+        return float(np.sum(np.abs(KP @ (x * hd) - d) ** 2))
+
+    scale = np.linalg.norm(ref) / np.sqrt(prob.Nv)
+    for j in g.choice(prob.Nv, 16, replace=False):
+        for unit in (1.0, 1j):
+            ej = np.zeros(prob.Nv, complex)
+            ej[j] = unit * 1e-3
+            fd = (L(s0 + ej) - L(s0 - ej)) / 2e-3
+            an = (np.conj(unit) * grad[j]).real
+            assert abs(fd - an) <= 1e-3 * scale + 1e-4 * abs(fd), (j, unit, fd, an)
+    op.close()
