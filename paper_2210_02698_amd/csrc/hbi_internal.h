@@ -7,6 +7,7 @@
 #define HBI_MAX_LEAF 64
 #define HBI_ID_THREADS 1024
 #define HBI_ID_NMAX 4096   // largest candidate-column count an ID accepts
+#define HBI_ID_ONCHIP_NMAX 64   // largest column count of the on-chip ID kernel
 
 // Problem constants visible to the kernels.
 struct DevProblem {

@@ -47,8 +47,13 @@ hipError_t launch_entries(const DevProblem &P, const DevCells &C, const EntryBlo
                           const int32_t *work, int64_t nwork, const int32_t *rows,
                           const uint16_t *rowslot, const int32_t *cols, const double *Hc,
                           hipStream_t st);
-hipError_t launch_cpqr(const IdBlock *blks, int64_t nb, int nmax, double tol, int32_t *rank,
-                       hipStream_t st);
+// Interpolative decompositions of the blocks blks[sel[0..nb)]: k_cpqr works
+// on the block in global memory (any n); launch_id_onchip handles blocks of
+// at most HBI_ID_ONCHIP_NMAX columns on chip (nmax = their largest n).
+hipError_t launch_cpqr(const IdBlock *blks, const int32_t *sel, int64_t nb, int nmax, int mmax,
+                       double tol, int32_t *rank, hipStream_t st);
+hipError_t launch_id_onchip(const IdBlock *blks, const int32_t *sel, int64_t nb, int nmax,
+                            double tol, int32_t *rank, hipStream_t st);
 hipError_t launch_copy_blocks(const CopyDesc *d, int64_t nb, hipStream_t st);
 hipError_t launch_pack_pairs(const PairDesc *d, int64_t np, hipStream_t st);
 hipError_t launch_to_f32(const double2 *src, float2 *dst, int64_t n, hipStream_t st);

@@ -277,17 +277,135 @@ __global__ __launch_bounds__(256) void k_entries(
 // pivot order), stopped at the first k with |R_kk| <= tol |R_11|; rank
 // r = k (at least 1).  Then X = [I, R11^-1 R12] Pi^T (r x n) so that
 // A ~ A(:, skel) X.  Column norms are recomputed exactly from the updated
-// entries at every step.  One workgroup (4 waves) per block; the block lives
-// in global memory and waves split the trailing columns.  Each step: thread
-// 0 picks the pivot from the waves' candidates and forms the reflector
-// (beta, tau and the scale of x below the diagonal); the waves then apply
-// it to their columns with the reflector vector formed on the fly (the
-// pivot column below the diagonal is not needed afterwards) and report
-// their best next pivot.  LDS: norms and column map, 12 bytes per column.
+// entries at every step.
+//
+// One 1024-thread workgroup (16 waves) per block; the block stays in global
+// memory and the waves split the trailing columns.  Each step: thread 0
+// picks the pivot from the waves' candidates and forms the reflector
+// H = I - tau v v^H (beta, tau and the scale of x below the diagonal); the
+// workgroup writes v into LDS; each wave applies H^H to its columns
+// (w = v^H a, a -= conj(tau) w v) and reports its best next pivot.  Rows
+// [k, k + 64 kCpqrRPL) of a column stay in registers between the dot product
+// and the update, so they are read once; rows past that are streamed twice
+// with kCpqrCH loads in flight per lane.  After the last step the top r rows
+// of R (pivoted order) are staged in LDS and R11^-1 R12 is solved there by
+// back substitution, one column per thread.
+//
+// LDS: norms (8 B per column) and column map (4 B per column), then a region
+// of `cap` complex entries that holds v during the factorisation and R's top
+// rows during the solve.  A block whose m (or r n) exceeds `cap` uses the
+// global-memory forms of those two parts instead.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(HBI_ID_THREADS) void k_cpqr(const IdBlock *blks,
-                                                          double tol,
-                                                          int32_t *rank_out) {
+constexpr int kCpqrRPL = 8;
+constexpr int kCpqrCH = 2;
+
+// Reflector entries read from LDS, or formed from the pivot column.
+struct ReflLds {
+  const double2 *v;
+  __device__ __forceinline__ double2 operator()(int i) const { return v[i]; }
+};
+struct ReflGlobal {
+  const double2 *x;
+  double2 scale;
+  int k;
+  __device__ __forceinline__ double2 operator()(int i) const {
+    return i == k ? double2{1.0, 0.0} : cmul(x[i], scale);
+  }
+};
+
+// Apply H^H to column a (rows [k, m)) by one wave; returns the new squared
+// norm of a below row k.
+template <class Refl>
+__device__ __forceinline__ double apply_reflector(double2 *a, const Refl &v, int k, int m,
+                                                  int lane, double2 ctau) {
+  double2 seg[kCpqrRPL];
+  double2 wv = double2{0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < kCpqrRPL; ++t) {
+    const int i = k + lane + 64 * t;
+    seg[t] = i < m ? a[i] : double2{0.0, 0.0};
+  }
+#pragma unroll
+  for (int t = 0; t < kCpqrRPL; ++t) {
+    const int i = k + lane + 64 * t;
+    if (i < m) cfmac(wv, v(i), seg[t]);
+  }
+  const int kr = k + 64 * kCpqrRPL;
+  for (int b = kr; b < m; b += 64 * kCpqrCH) {
+    double2 t2[kCpqrCH];
+#pragma unroll
+    for (int u = 0; u < kCpqrCH; ++u) {
+      const int i = b + lane + 64 * u;
+      t2[u] = i < m ? a[i] : double2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < kCpqrCH; ++u) {
+      const int i = b + lane + 64 * u;
+      if (i < m) cfmac(wv, v(i), t2[u]);
+    }
+  }
+  wv.x = wave_sum(wv.x);
+  wv.y = wave_sum(wv.y);
+  const double2 f = cmul(ctau, wv);
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < kCpqrRPL; ++t) {
+    const int i = k + lane + 64 * t;
+    if (i < m) {
+      const double2 vi = v(i);
+      double2 ai = seg[t];
+      ai.x -= f.x * vi.x - f.y * vi.y;
+      ai.y -= f.x * vi.y + f.y * vi.x;
+      a[i] = ai;
+      if (i > k) s += ai.x * ai.x + ai.y * ai.y;
+    }
+  }
+  for (int b = kr; b < m; b += 64 * kCpqrCH) {
+    double2 t2[kCpqrCH];
+#pragma unroll
+    for (int u = 0; u < kCpqrCH; ++u) {
+      const int i = b + lane + 64 * u;
+      t2[u] = i < m ? a[i] : double2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < kCpqrCH; ++u) {
+      const int i = b + lane + 64 * u;
+      if (i < m) {
+        const double2 vi = v(i);
+        double2 ai = t2[u];
+        ai.x -= f.x * vi.x - f.y * vi.y;
+        ai.y -= f.x * vi.y + f.y * vi.x;
+        a[i] = ai;
+        s += ai.x * ai.x + ai.y * ai.y;
+      }
+    }
+  }
+  return wave_sum(s);
+}
+
+// Back substitution x <- R11^-1 x for one column (x holds R12's column on
+// entry); R(i, l) at R[i + l * ldr].  A zero or singular diagonal gives 0.
+template <class RAt>
+__device__ __forceinline__ void solve_upper(const RAt &R, double2 *x, int r, bool zero) {
+  for (int i = r - 1; i >= 0; --i) {
+    double2 acc = x[i];
+    for (int l = i + 1; l < r; ++l) {
+      const double2 ril = R(i, l);
+      const double2 xl = x[l];
+      acc.x -= ril.x * xl.x - ril.y * xl.y;
+      acc.y -= ril.x * xl.y + ril.y * xl.x;
+    }
+    const double2 d = R(i, i);
+    const double dd = d.x * d.x + d.y * d.y;
+    x[i] = (zero || dd == 0.0)
+               ? double2{0.0, 0.0}
+               : double2{(acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd};
+  }
+}
+
+__global__ __launch_bounds__(HBI_ID_THREADS) void k_cpqr(const IdBlock *blks, const int32_t *sel,
+                                                          double tol, int32_t *rank_out, int nmax,
+                                                          int cap) {
   extern __shared__ double lds_id[];
   constexpr int NW = HBI_ID_THREADS / 64;
   __shared__ double red_v[NW];
@@ -296,10 +414,13 @@ __global__ __launch_bounds__(HBI_ID_THREADS) void k_cpqr(const IdBlock *blks,
   __shared__ int sh_stop, sh_rank, sh_c;
   __shared__ double sh_r11;
 
-  const IdBlock B = blks[blockIdx.x];
+  const int blk = sel[blockIdx.x];
+  const IdBlock B = blks[blk];
   const int m = B.m, n = B.n;
   double *nrm2 = lds_id;
-  int *colmap = (int *)(lds_id + n);
+  int *colmap = (int *)(lds_id + nmax);
+  double2 *shared_c = (double2 *)(lds_id + nmax + (nmax + 1) / 2 + 1);
+  const bool vlds = m <= cap;
   double2 *A = B.A;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
@@ -309,7 +430,16 @@ __global__ __launch_bounds__(HBI_ID_THREADS) void k_cpqr(const IdBlock *blks,
   for (int j = wave; j < n; j += NW) {
     const double2 *a = A + (int64_t)j * m;
     double s = 0.0;
-    for (int i = lane; i < m; i += 64) s += a[i].x * a[i].x + a[i].y * a[i].y;
+    for (int b = 0; b < m; b += 64 * kCpqrCH) {
+      double2 t2[kCpqrCH];
+#pragma unroll
+      for (int u = 0; u < kCpqrCH; ++u) {
+        const int i = b + lane + 64 * u;
+        t2[u] = i < m ? a[i] : double2{0.0, 0.0};
+      }
+#pragma unroll
+      for (int u = 0; u < kCpqrCH; ++u) s += t2[u].x * t2[u].x + t2[u].y * t2[u].y;
+    }
     s = wave_sum(s);
     if (lane == 0) nrm2[j] = s;
     if (s > bv) { bv = s; bq = j; }
@@ -351,35 +481,30 @@ __global__ __launch_bounds__(HBI_ID_THREADS) void k_cpqr(const IdBlock *blks,
     }
     __syncthreads();
     if (sh_stop) break;
-    const int c = sh_c;
-    const double2 scale = sh_scale, tau = sh_tau;
-    const double2 *x = A + (int64_t)c * m;
-    const double2 ctau = double2{tau.x, -tau.y};
+    const double2 *x = A + (int64_t)sh_c * m;
+    const double2 scale = sh_scale;
+    const double2 ctau = double2{sh_tau.x, -sh_tau.y};
     bv = -1.0;
     bq = n;
-    for (int q = k + 1 + wave; q < n; q += NW) {
-      const int j = colmap[q];
-      double2 *a = A + (int64_t)j * m;
-      double2 wv = double2{0.0, 0.0};
-      for (int i = k + lane; i < m; i += 64) {
-        const double2 vi = (i == k) ? double2{1.0, 0.0} : cmul(x[i], scale);
-        cfmac(wv, vi, a[i]);
+    if (vlds) {
+      for (int i = k + tid; i < m; i += HBI_ID_THREADS)
+        shared_c[i] = (i == k) ? double2{1.0, 0.0} : cmul(x[i], scale);
+      __syncthreads();
+      const ReflLds v{shared_c};
+      for (int q = k + 1 + wave; q < n; q += NW) {
+        const int j = colmap[q];
+        const double s = apply_reflector(A + (int64_t)j * m, v, k, m, lane, ctau);
+        if (lane == 0) nrm2[j] = s;
+        if (s > bv) { bv = s; bq = q; }
       }
-      wv.x = wave_sum(wv.x);
-      wv.y = wave_sum(wv.y);
-      const double2 f = cmul(ctau, wv);
-      double s = 0.0;
-      for (int i = k + lane; i < m; i += 64) {
-        const double2 vi = (i == k) ? double2{1.0, 0.0} : cmul(x[i], scale);
-        double2 ai = a[i];
-        ai.x -= f.x * vi.x - f.y * vi.y;
-        ai.y -= f.x * vi.y + f.y * vi.x;
-        a[i] = ai;
-        if (i > k) s += ai.x * ai.x + ai.y * ai.y;
+    } else {
+      const ReflGlobal v{x, scale, k};
+      for (int q = k + 1 + wave; q < n; q += NW) {
+        const int j = colmap[q];
+        const double s = apply_reflector(A + (int64_t)j * m, v, k, m, lane, ctau);
+        if (lane == 0) nrm2[j] = s;
+        if (s > bv) { bv = s; bq = q; }
       }
-      s = wave_sum(s);
-      if (lane == 0) nrm2[j] = s;
-      if (s > bv) { bv = s; bq = q; }
     }
     if (lane == 0) { red_v[wave] = bv; red_i[wave] = bq; }
     __syncthreads();
@@ -393,29 +518,361 @@ __global__ __launch_bounds__(HBI_ID_THREADS) void k_cpqr(const IdBlock *blks,
     X[i + (int64_t)colmap[q] * r] = double2{i == q ? 1.0 : 0.0, 0.0};
   }
   for (int q = tid; q < r; q += HBI_ID_THREADS) B.piv[q] = colmap[q];
-  // T = R11^-1 R12 by back substitution, one column per thread
-  for (int q = r + tid; q < n; q += HBI_ID_THREADS) {
-    const int col = colmap[q];
-    const double2 *rc = A + (int64_t)col * m;
-    double2 *xo = X + (int64_t)col * r;
-    for (int i = r - 1; i >= 0; --i) {
-      double2 acc = rc[i];
-      for (int l = i + 1; l < r; ++l) {
-        const double2 ril = A[i + (int64_t)colmap[l] * m];
-        const double2 xl = xo[l];
-        acc.x -= ril.x * xl.x - ril.y * xl.y;
-        acc.y -= ril.x * xl.y + ril.y * xl.x;
+  if ((int64_t)r * n <= cap) {
+    // top r rows of R in pivoted column order, column q at shared_c[q r]
+    for (int idx = tid; idx < r * n; idx += HBI_ID_THREADS) {
+      const int q = idx / r, i = idx % r;
+      shared_c[idx] = A[i + (int64_t)colmap[q] * m];
+    }
+    __syncthreads();
+    const double2 *Rs = shared_c;
+    auto R = [Rs, r](int i, int l) { return Rs[i + l * r]; };
+    for (int q = r + tid; q < n; q += HBI_ID_THREADS) solve_upper(R, shared_c + q * r, r, zero);
+    __syncthreads();
+    for (int idx = tid; idx < r * (n - r); idx += HBI_ID_THREADS) {
+      const int q = r + idx / r, i = idx % r;
+      X[i + (int64_t)colmap[q] * r] = shared_c[i + q * r];
+    }
+  } else {
+    // in global memory: R12's column is copied into X's and solved there
+    auto R = [A, colmap, m](int i, int l) { return A[i + (int64_t)colmap[l] * m]; };
+    for (int q = r + tid; q < n; q += HBI_ID_THREADS) {
+      const int col = colmap[q];
+      double2 *xo = X + (int64_t)col * r;
+      for (int i = 0; i < r; ++i) xo[i] = A[i + (int64_t)col * m];
+      solve_upper(R, xo, r, zero);
+    }
+  }
+  if (tid == 0) rank_out[blk] = r;
+}
+
+// ---------------------------------------------------------------------------
+// Interpolative decomposition of a block with at most NW NS columns, done on
+// chip.  The pivoted QR of A (m x n) is taken as the pivoted QR of the n x n
+// triangular factor R0 of an unpivoted Householder QR A = Q0 R0: Q0 has
+// orthonormal columns, so every column norm, pivot choice and R factor of
+// the pivoted QR is the same for A and for R0, and A is read once.
+//   Phase 1 streams A in panels of 64 PR rows and folds each panel P into
+//   R0 with Householder reflections of the stacked matrix [R0; P].
+//   Phase 2 is the column-pivoted QR of R0 with the rule and stopping test
+//   of k_cpqr (norms recomputed exactly at each step).
+//   Phase 3 stages the top r rows of R in LDS (or, when r n exceeds `cap`,
+//   in A's storage) and solves R11 T = R12 one column per thread.
+// Layout: wave w owns columns c = w + NW s (s < NS); lane l holds rows
+// l + 64 u of R0 (u < RR = NW NS / 64) and rows l + 64 t of the panel
+// (t < PR).  Launched as 8 waves x 8 slots with 128-row panels (n <= 64):
+// within 128 VGPRs, so two workgroups share a CU.
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, true);
+  return v + __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+// Sum over the wave's 64 lanes, the same value in every lane: DPP row
+// shifts by 1, 2, 4, 8 leave each row's sum in its lane 15; row broadcasts
+// of lanes 15 and 31 then carry the total to lane 63, which is read out.
+__device__ __forceinline__ double wave_sum_u(double v) {
+  v = dpp_add<0x111, 0xf>(v);   // row_shr:1
+  v = dpp_add<0x112, 0xf>(v);   // row_shr:2
+  v = dpp_add<0x114, 0xf>(v);   // row_shr:4
+  v = dpp_add<0x118, 0xf>(v);   // row_shr:8
+  v = dpp_add<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return readlane_d(v, 63);
+}
+
+// A value the whole wave holds alike (read from LDS), made wave-uniform so
+// that branches on it are scalar.
+__device__ __forceinline__ double uniform_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)b);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+__device__ __forceinline__ double2 uniform_c(double2 v) {
+  return double2{uniform_d(v.x), uniform_d(v.y)};
+}
+
+__device__ __forceinline__ double2 readlane_c(double2 v, int l) {
+  return double2{readlane_d(v.x, l), readlane_d(v.y, l)};
+}
+
+template <int NW, int NS, int PR, int WPE>
+__global__ __launch_bounds__(NW * 64, WPE) void k_id_onchip(
+    const IdBlock *blks, const int32_t *sel, double tol, int32_t *rank_out, int cap) {
+  constexpr int NC = NS * NW;      // column capacity
+  constexpr int RR = NC / 64;      // R0 rows per lane
+  constexpr int T = NW * 64;
+  static_assert(NC % 64 == 0, "column capacity must be a multiple of 64");
+  extern __shared__ double2 lds_rs[];
+  __shared__ double2 v_sh[2][NC > 64 * PR ? NC : 64 * PR];
+  __shared__ double2 tau_sh[2];
+  __shared__ int colmap[NC], pos[NC];
+  __shared__ double red_v[NW];
+  __shared__ int red_q[NW], red_c[NW];
+
+  const int blk = sel[blockIdx.x];
+  const IdBlock B = blks[blk];
+  const int m = B.m, n = B.n;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
+  const double2 *A = B.A;
+  const double2 zero2 = double2{0.0, 0.0};
+
+  double2 R[RR][NS];
+#pragma unroll
+  for (int u = 0; u < RR; ++u)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) R[u][s] = zero2;
+
+  // ---- phase 1: R0 of A, one panel of 64 PR rows at a time
+  int buf = 0;
+  for (int p0 = 0; p0 < m; p0 += 64 * PR) {
+    double2 P[PR][NS];
+#pragma unroll
+    for (int t = 0; t < PR; ++t)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int c = w + NW * s, i = p0 + lane + 64 * t;
+        P[t][s] = (c < n && i < m) ? A[i + (int64_t)c * m] : zero2;
       }
-      const double2 d = A[i + (int64_t)colmap[i] * m];
-      const double dd = d.x * d.x + d.y * d.y;
-      if (zero || dd == 0.0) {
-        xo[i] = double2{0.0, 0.0};
-      } else {
-        xo[i] = double2{(acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd};
+    for (int j = 0; j < n; ++j) {
+      const int sj = j / NW, uj = j >> 6, lj = j & 63;
+      if (w == j % NW) {
+        double2 x[PR], rj = zero2;
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          if (s == sj) {
+#pragma unroll
+            for (int t = 0; t < PR; ++t) x[t] = P[t][s];
+#pragma unroll
+            for (int u = 0; u < RR; ++u)
+              if (u == uj) rj = R[u][s];
+          }
+        double xn = 0.0;
+#pragma unroll
+        for (int t = 0; t < PR; ++t) xn += x[t].x * x[t].x + x[t].y * x[t].y;
+        xn = wave_sum_u(xn);
+        const double2 al = readlane_c(rj, lj);
+        double2 tau = zero2;
+        if (xn != 0.0 || al.y != 0.0) {
+          const double nrm = sqrt(al.x * al.x + al.y * al.y + xn);
+          const double beta = al.x >= 0.0 ? -nrm : nrm;
+          tau = double2{(beta - al.x) / beta, -al.y / beta};
+          const double dr = al.x - beta, di = al.y, dd = dr * dr + di * di;
+          const double2 scale = double2{dr / dd, -di / dd};
+#pragma unroll
+          for (int t = 0; t < PR; ++t) v_sh[buf][lane + 64 * t] = cmul(x[t], scale);
+#pragma unroll
+          for (int s = 0; s < NS; ++s)
+            if (s == sj) {
+#pragma unroll
+              for (int t = 0; t < PR; ++t) P[t][s] = zero2;
+#pragma unroll
+              for (int u = 0; u < RR; ++u)
+                if (u == uj && lane == lj) R[u][s] = double2{beta, 0.0};
+            }
+        }
+        if (lane == 0) tau_sh[buf] = tau;
+      }
+      __syncthreads();
+      const double2 tau = uniform_c(tau_sh[buf]);
+      if (tau.x != 0.0 || tau.y != 0.0) {
+        double2 v[PR];
+#pragma unroll
+        for (int t = 0; t < PR; ++t) v[t] = v_sh[buf][lane + 64 * t];
+        const double2 ctau = double2{tau.x, -tau.y};
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int c = w + NW * s;
+          if (c > j && c < n) {
+            double2 d = zero2;
+#pragma unroll
+            for (int t = 0; t < PR; ++t) cfmac(d, v[t], P[t][s]);
+            d.x = wave_sum_u(d.x);
+            d.y = wave_sum_u(d.y);
+            double2 rl = R[0][s];
+#pragma unroll
+            for (int u = 1; u < RR; ++u)
+              if (u == uj) rl = R[u][s];
+            const double2 rjc = readlane_c(rl, lj);
+            const double2 f = cmul(ctau, double2{rjc.x + d.x, rjc.y + d.y});
+#pragma unroll
+            for (int t = 0; t < PR; ++t) {
+              P[t][s].x -= f.x * v[t].x - f.y * v[t].y;
+              P[t][s].y -= f.x * v[t].y + f.y * v[t].x;
+            }
+#pragma unroll
+            for (int u = 0; u < RR; ++u)
+              if (u == uj && lane == lj) { R[u][s].x -= f.x; R[u][s].y -= f.y; }
+          }
+        }
+      }
+      buf ^= 1;
+    }
+  }
+
+  // ---- phase 2: column-pivoted QR of R0
+  for (int c = tid; c < NC; c += T) { colmap[c] = c; pos[c] = c; }
+  {
+    double bv = -1.0;
+    int bq = n, bc = -1;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int c = w + NW * s;
+      if (c < n) {
+        double sn = 0.0;
+#pragma unroll
+        for (int u = 0; u < RR; ++u) sn += R[u][s].x * R[u][s].x + R[u][s].y * R[u][s].y;
+        sn = wave_sum_u(sn);
+        if (sn > bv || (sn == bv && c < bq)) { bv = sn; bq = c; bc = c; }
+      }
+    }
+    if (lane == 0) { red_v[w] = bv; red_q[w] = bq; red_c[w] = bc; }
+  }
+  __syncthreads();
+  const int kmax = m < n ? m : n;
+  int rank = kmax;
+  double r11 = 0.0;
+  for (int k = 0; k < kmax; ++k) {
+    double best = uniform_d(red_v[0]);
+    int q = __builtin_amdgcn_readfirstlane(red_q[0]), p = __builtin_amdgcn_readfirstlane(red_c[0]);
+    for (int w2 = 1; w2 < NW; ++w2) {
+      const double bw = uniform_d(red_v[w2]);
+      const int qw = __builtin_amdgcn_readfirstlane(red_q[w2]);
+      if (bw > best || (bw == best && qw < q)) {
+        best = bw; q = qw; p = __builtin_amdgcn_readfirstlane(red_c[w2]);
+      }
+    }
+    const double nrm = sqrt(fmax(best, 0.0));
+    if (k == 0) r11 = nrm;
+    if (q >= n || nrm == 0.0 || (k > 0 && nrm <= tol * r11)) {
+      rank = k > 0 ? k : 1;
+      break;
+    }
+    const int uk = k >> 6, lk = k & 63;
+    if (w == p % NW) {
+      const int sp = p / NW;
+      double2 col[RR];
+#pragma unroll
+      for (int u = 0; u < RR; ++u) col[u] = zero2;
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (s == sp) {
+#pragma unroll
+          for (int u = 0; u < RR; ++u) col[u] = R[u][s];
+        }
+      double2 al = col[0];
+#pragma unroll
+      for (int u = 1; u < RR; ++u)
+        if (u == uk) al = col[u];
+      al = readlane_c(al, lk);
+      const double beta = al.x >= 0.0 ? -nrm : nrm;
+      const double dr = al.x - beta, di = al.y, dd = dr * dr + di * di;
+      const double2 scale = double2{dr / dd, -di / dd};
+#pragma unroll
+      for (int u = 0; u < RR; ++u) {
+        const int row = lane + 64 * u;
+        v_sh[buf][row] = row < k ? zero2 : (row == k ? double2{1.0, 0.0} : cmul(col[u], scale));
+      }
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (s == sp) {
+#pragma unroll
+          for (int u = 0; u < RR; ++u) {
+            const int row = lane + 64 * u;
+            if (row == k) R[u][s] = double2{beta, 0.0};
+            else if (row > k) R[u][s] = zero2;
+          }
+        }
+      if (lane == 0) tau_sh[buf] = double2{(beta - al.x) / beta, -al.y / beta};
+    }
+    if (tid == 0) {
+      const int ck = colmap[k];
+      colmap[k] = p;
+      colmap[q] = ck;
+      pos[p] = k;
+      pos[ck] = q;
+    }
+    __syncthreads();
+    const double2 tau = uniform_c(tau_sh[buf]);
+    const double2 ctau = double2{tau.x, -tau.y};
+    double2 v[RR];
+#pragma unroll
+    for (int u = 0; u < RR; ++u) v[u] = v_sh[buf][lane + 64 * u];
+    double bv = -1.0;
+    int bq = n, bc = -1;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int c = w + NW * s;
+      if (c < n) {
+        const int pc = __builtin_amdgcn_readfirstlane(pos[c]);
+        if (pc > k) {
+          double2 d = zero2;
+#pragma unroll
+          for (int u = 0; u < RR; ++u) cfmac(d, v[u], R[u][s]);
+          d.x = wave_sum_u(d.x);
+          d.y = wave_sum_u(d.y);
+          const double2 f = cmul(ctau, d);
+          double sn = 0.0;
+#pragma unroll
+          for (int u = 0; u < RR; ++u) {
+            R[u][s].x -= f.x * v[u].x - f.y * v[u].y;
+            R[u][s].y -= f.x * v[u].y + f.y * v[u].x;
+            if (lane + 64 * u > k) sn += R[u][s].x * R[u][s].x + R[u][s].y * R[u][s].y;
+          }
+          sn = wave_sum_u(sn);
+          if (sn > bv || (sn == bv && pc < bq)) { bv = sn; bq = pc; bc = c; }
+        }
+      }
+    }
+    if (lane == 0) { red_v[w] = bv; red_q[w] = bq; red_c[w] = bc; }
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  // ---- phase 3: X = [I, R11^-1 R12] Pi^T
+  const int r = rank;
+  const bool zero = !(r11 > 0.0);
+  double2 *Rs = (int64_t)r * n <= cap ? lds_rs : (double2 *)B.A;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int c = w + NW * s;
+    if (c < n) {
+      const int q = __builtin_amdgcn_readfirstlane(pos[c]);
+#pragma unroll
+      for (int u = 0; u < RR; ++u) {
+        const int row = lane + 64 * u;
+        if (row < r) Rs[row + q * r] = R[u][s];
       }
     }
   }
-  if (tid == 0) rank_out[blockIdx.x] = r;
+  __syncthreads();
+  double2 *X = B.X;
+  for (int idx = tid; idx < r * r; idx += T) {
+    const int q = idx / r, i = idx % r;
+    X[i + (int64_t)colmap[q] * r] = double2{i == q ? 1.0 : 0.0, 0.0};
+  }
+  for (int q = tid; q < r; q += T) B.piv[q] = colmap[q];
+  const double2 *Rc = Rs;
+  auto Rat = [Rc, r](int i, int l) { return Rc[i + l * r]; };
+  for (int q = r + tid; q < n; q += T) solve_upper(Rat, Rs + q * r, r, zero);
+  __syncthreads();
+  for (int idx = tid; idx < r * (n - r); idx += T) {
+    const int q = r + idx / r, i = idx % r;
+    X[i + (int64_t)colmap[q] * r] = Rs[i + q * r];
+  }
+  if (tid == 0) rank_out[blk] = r;
 }
 
 // Contiguous copies src[b] -> dst[b] of cnt[b] complex values.
@@ -759,11 +1216,52 @@ hipError_t launch_entries(const DevProblem &P, const DevCells &C, const EntryBlo
   return hipGetLastError();
 }
 
-hipError_t launch_cpqr(const IdBlock *blks, int64_t nb, int nmax, double tol, int32_t *rank,
-                       hipStream_t st) {
+static hipError_t lds_limit(int *ldsmax) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  return hipDeviceGetAttribute(ldsmax, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+}
+
+hipError_t launch_cpqr(const IdBlock *blks, const int32_t *sel, int64_t nb, int nmax, int mmax,
+                       double tol, int32_t *rank, hipStream_t st) {
   if (nb == 0) return hipSuccess;
-  const size_t lds = (size_t)nmax * (sizeof(double) + sizeof(int)) + 16;
-  hipLaunchKernelGGL(k_cpqr, dim3(nb), dim3(HBI_ID_THREADS), lds, st, blks, tol, rank);
+  int ldsmax = 65536;
+  hipError_t e = lds_limit(&ldsmax);
+  if (e != hipSuccess) return e;
+  // norms + column map, then the region for v (m entries) and R's top rows
+  // (r n <= min(m, n) n entries), as far as the device's LDS allows
+  const size_t head = sizeof(double) * ((size_t)nmax + (nmax + 1) / 2 + 1);
+  const size_t want = std::max<size_t>((size_t)mmax, (size_t)std::min(mmax, nmax) * nmax);
+  const size_t avail = (size_t)ldsmax > head + 1024 ? ((size_t)ldsmax - head - 1024) / 16 : 0;
+  const int cap = (int)std::min(want, avail);
+  const size_t lds = head + sizeof(double2) * (size_t)cap;
+  if (lds > 65536) {
+    e = hipFuncSetAttribute((const void *)k_cpqr, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_cpqr, dim3(nb), dim3(HBI_ID_THREADS), lds, st, blks, sel, tol, rank, nmax,
+                     cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_id_onchip(const IdBlock *blks, const int32_t *sel, int64_t nb, int nmax,
+                            double tol, int32_t *rank, hipStream_t st) {
+  if (nb == 0) return hipSuccess;
+  if (nmax > HBI_ID_ONCHIP_NMAX) return hipErrorInvalidValue;
+  int ldsmax = 65536;
+  hipError_t e = lds_limit(&ldsmax);
+  if (e != hipSuccess) return e;
+  // R's top rows: 64 KiB (two workgroups share a CU), within what the
+  // device allows
+  const size_t lds = std::min((size_t)64 << 10, ldsmax > 8192 ? (size_t)ldsmax - 8192 : (size_t)0);
+  const int cap = (int)(lds / sizeof(double2));
+  e = hipFuncSetAttribute((const void *)k_id_onchip<8, 8, 2, 4>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_id_onchip<8, 8, 2, 4>), dim3(nb), dim3(512), lds, st, blks, sel, tol, rank,
+                     cap);
   return hipGetLastError();
 }
 

@@ -178,8 +178,9 @@ struct hbi_ctx {
   // statistics
   double t_build = 0, t_geo = 0, t_host = 0, t_gpu = 0, t_final = 0;
   int64_t nnz_v = 0, nnz_w = 0, nnz_k = 0, nnz_d = 0, entries_eval = 0, nid = 0;
-  int32_t rank_max = 0;
-  double rank_sum = 0;
+  int32_t rank_max = 0, id_m_max = 0;
+  double rank_sum = 0, id_m_sum = 0, id_n_sum = 0, id_work = 0, id_work_wide = 0;
+  int64_t nid_wide = 0;
   double tol = 0;
 
   DevProblem devprob() const {
@@ -210,6 +211,7 @@ struct hbi_ctx {
     units_d.clear(); items_d.clear(); items_adj_d.clear(); plan = ApplyPlan();
     leaves_h.clear(); vd_h.clear(); kd_h.clear(); units_h.clear(); batch.reset(); ztotal = 0; z_d.release();
     nnz_v = nnz_w = nnz_k = nnz_d = entries_eval = nid = 0; rank_max = 0; rank_sum = 0;
+    id_m_max = 0; id_m_sum = id_n_sum = id_work = id_work_wide = 0; nid_wide = 0;
     if (state > 1) state = 1;
   }
 };
@@ -292,6 +294,14 @@ struct BlockOut {
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// HBI_ID_KERNEL=global sends every interpolative decomposition to the
+// global-memory pivoted QR (for comparisons); by default blocks of at most
+// HBI_ID_ONCHIP_NMAX columns are decomposed on chip.
+static bool id_onchip_enabled() {
+  const char *e = std::getenv("HBI_ID_KERNEL");
+  return !(e && std::strcmp(e, "global") == 0);
+}
 
 struct Batcher {
   hbi_ctx *c;
@@ -420,8 +430,25 @@ struct Batcher {
                  o_slot = place(slotbox.size() * 4), o_wc = place(workc.size() * 4),
                  o_we = place(worke.size() * 4), o_rs = place(rowslot.size() * 2),
                  o_eb = place(eb.size() * sizeof(EntryBlock)),
-                 o_ib = place(ib.size() * sizeof(IdBlock)), o_piv = place((size_t)po * 4),
-                 o_rank = place((size_t)nb * 4);
+                 o_ib = place(ib.size() * sizeof(IdBlock)), o_sel = place(id ? (size_t)nb * 4 : 0),
+                 o_piv = place((size_t)po * 4), o_rank = place((size_t)nb * 4);
+    // ID kernel per block: on chip up to HBI_ID_ONCHIP_NMAX columns, the
+    // global-memory pivoted QR beyond; sel lists the groups
+    std::vector<int32_t> sel;
+    int64_t nsel[3] = {0, 0, 0};
+    int nmax_g[3] = {1, 1, 1}, mmax_w = 1;
+    if (id) {
+      const bool onchip = id_onchip_enabled();
+      std::vector<int32_t> g[3];
+      for (int64_t q = 0; q < nb; ++q) {
+        const int n = ib[q].n;
+        const int k = !onchip || n > HBI_ID_ONCHIP_NMAX ? 2 : 0;
+        g[k].push_back((int32_t)q);
+        nmax_g[k] = std::max(nmax_g[k], n);
+        if (k == 2) mmax_w = std::max(mmax_w, (int)ib[q].m);
+      }
+      for (int k = 0; k < 3; ++k) { nsel[k] = (int64_t)g[k].size(); sel.insert(sel.end(), g[k].begin(), g[k].end()); }
+    }
     HBI_HIP(c->idx_d.reserve(off));
     char *ix = c->idx_d.as<char>();
     for (int64_t q = 0; q < (int64_t)ib.size(); ++q) ib[q].piv = (int32_t *)(ix + o_piv) + pivoff[q];
@@ -435,6 +462,7 @@ struct Batcher {
     put(o_rs, rowslot.data(), rowslot.size() * 2);
     put(o_eb, eb.data(), eb.size() * sizeof(EntryBlock));
     put(o_ib, ib.data(), ib.size() * sizeof(IdBlock));
+    put(o_sel, sel.data(), sel.size() * 4);
     HBI_HIP(hipMemcpyAsync(ix, stage.data(), o_piv, hipMemcpyHostToDevice, c->stream));
     const DevProblem P = c->devprob();
     const DevCells C = c->devcells();
@@ -447,9 +475,12 @@ struct Batcher {
                            (const int32_t *)(ix + o_cols), c->ws.as<double>(), c->stream));
     for (int64_t q = 0; q < nb; ++q) c->entries_eval += (int64_t)blocks[i0 + q].m * blocks[i0 + q].n;
     if (id) {
-      int nmax = 1;
-      for (int64_t q = 0; q < nb; ++q) nmax = std::max(nmax, (int)blocks[i0 + q].n);
-      HBI_HIP(launch_cpqr((const IdBlock *)(ix + o_ib), nb, nmax, tol, (int32_t *)(ix + o_rank),
+      const IdBlock *ibd = (const IdBlock *)(ix + o_ib);
+      const int32_t *seld = (const int32_t *)(ix + o_sel);
+      int32_t *rankd = (int32_t *)(ix + o_rank);
+      HBI_HIP(launch_id_onchip(ibd, seld, nsel[0], nmax_g[0], tol, rankd, c->stream));
+      HBI_HIP(launch_id_onchip(ibd, seld + nsel[0], nsel[1], nmax_g[1], tol, rankd, c->stream));
+      HBI_HIP(launch_cpqr(ibd, seld + nsel[0] + nsel[1], nsel[2], nmax_g[2], mmax_w, tol, rankd,
                           c->stream));
       std::vector<int32_t> rank(nb), piv(po);
       HBI_HIP(hipMemcpyAsync(rank.data(), ix + o_rank, nb * 4, hipMemcpyDeviceToHost, c->stream));
@@ -467,6 +498,15 @@ struct Batcher {
         c->nid += 1;
         c->rank_max = std::max(c->rank_max, o.rank);
         c->rank_sum += o.rank;
+        c->id_m_max = std::max(c->id_m_max, ib[q].m);
+        c->id_m_sum += ib[q].m;
+        c->id_n_sum += ib[q].n;
+        // complex multiply-adds of the Householder steps actually taken
+        double wk = 0.0;
+        for (int32_t k = 0; k < o.rank; ++k)
+          wk += 2.0 * (double)(ib[q].m - k) * (double)(ib[q].n - k - 1);
+        c->id_work += wk;
+        if (ib[q].n > 64) { c->id_work_wide += wk; c->nid_wide += 1; }
       }
     } else {
       HBI_HIP(hipStreamSynchronize(c->stream));
@@ -1494,6 +1534,8 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       "\"nnz_v\": %lld, \"nnz_w\": %lld, \"nnz_k\": %lld, \"nnz_dense\": %lld, "
       "\"nnz_total\": %lld, \"factor_bytes\": %lld, \"z_entries\": %lld, "
       "\"n_id\": %lld, \"rank_max\": %d, \"rank_mean\": %.3f, \"entries_evaluated\": %lld, "
+      "\"id_rows_mean\": %.1f, \"id_rows_max\": %d, \"id_cols_mean\": %.1f, \"id_cmac\": %.6e, "
+      "\"n_id_cols_gt64\": %lld, \"id_cmac_cols_gt64\": %.6e, "
       "\"build_s\": %.6f, \"build_geometry_s\": %.6f, \"build_proxy_host_s\": %.6f, "
       "\"build_gpu_s\": %.6f, \"build_finalize_s\": %.6f}",
       ctx->state, ctx->dim, (long long)Nv, ctx->geo.Lv, ctx->NT, ctx->nI,
@@ -1501,7 +1543,9 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       (long long)ctx->nnz_v, (long long)ctx->nnz_w, (long long)ctx->nnz_k, (long long)ctx->nnz_d,
       (long long)ctx->Felems, (long long)(ctx->Felems * (int64_t)esz), (long long)ctx->ztotal,
       (long long)ctx->nid, ctx->rank_max, ctx->nid ? ctx->rank_sum / ctx->nid : 0.0,
-      (long long)ctx->entries_eval, ctx->t_build, ctx->t_geo, ctx->t_host, ctx->t_gpu,
+      (long long)ctx->entries_eval, ctx->nid ? ctx->id_m_sum / ctx->nid : 0.0, ctx->id_m_max,
+      ctx->nid ? ctx->id_n_sum / ctx->nid : 0.0, ctx->id_work, (long long)ctx->nid_wide,
+      ctx->id_work_wide, ctx->t_build, ctx->t_geo, ctx->t_host, ctx->t_gpu,
       ctx->t_final);
   if (len < 0 || len >= cap) { ctx->err = "output buffer too small"; return HBI_ERR_ARG; }
   std::memcpy(json, buf, len + 1);

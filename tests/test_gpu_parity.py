@@ -260,6 +260,38 @@ def test_3d_apply_sampled_rows(torch_mod):
     op.close()
 
 
+@pytest.mark.parametrize("prec,tol,bound", [("f64", 1e-7, 1e-6), ("f32", 1e-5, 1e-4)])
+def test_id_onchip_matches_global(torch_mod, monkeypatch, prec, tol, bound):
+    """Blocks of at most 64 candidate columns are decomposed on chip (pivoted
+    QR of the triangular factor of the block); HBI_ID_KERNEL=global sends them
+    to the global-memory pivoted QR of the block itself.  Both operators agree
+    with the oracle and with each other to the compression tolerance, with
+    nearly the same ranks."""
+    torch = torch_mod
+    prob = hb_inputs.configs.c2(128)
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    s = hb_inputs.complex_normal(prob.Nv, [11, 4])
+    rows = np.random.default_rng(6).choice(prob.Nv, 64, replace=False)
+    ref = oracle.apply(prob, s, rows)
+    out = {}
+    for kind in ("onchip", "global"):
+        if kind == "global":
+            monkeypatch.setenv("HBI_ID_KERNEL", "global")
+        say(f"id kernel {kind} {prec} tol {tol}")
+        op = make_op(prob, tol=tol, prec=prec)
+        u = op.apply(to_dev(torch, s, dt)).cpu().numpy().astype(np.complex128)
+        out[kind] = (u, op.info())
+        e = rel(u[rows], ref)
+        say(f"{kind} rel err {e:.3e} rank mean {out[kind][1]['rank_mean']:.3f}")
+        assert e < bound, (kind, e)
+        op.close()
+    d = rel(out["onchip"][0], out["global"][0])
+    say(f"onchip vs global {d:.3e}")
+    assert d < bound, d
+    r1, r2 = out["onchip"][1]["rank_mean"], out["global"][1]["rank_mean"]
+    assert abs(r1 - r2) <= 0.02 * r2, (r1, r2)
+
+
 def test_autograd_gradient(torch_mod):
     """Loss ||P K h^d s - d||^2: gradient from HBApply.backward equals the
     dense adjoint and central finite differences (the loss is quadratic, so
