@@ -43,9 +43,16 @@ hipError_t launch_colside(const DevProblem &P, const DevCells &C, const DevTable
                           const EntryBlock *blks, const int32_t *work, int64_t nwork,
                           const int32_t *cols, const int32_t *slotbox, double *Hc,
                           hipStream_t st);
+// Column-side contractions of every (cell, box) pair into Hcache
+// (Nv * nbox * 3 * NTb doubles).
+hipError_t launch_colside_cells(const DevProblem &P, const DevCells &C, const DevTables &T,
+                                int64_t Nv, int nbox, double *Hcache, hipStream_t st);
+// Entries of the blocks; the column side comes from the batch workspace Hc,
+// or from Hcache (nbox boxes per cell) when that is non-null.
 hipError_t launch_entries(const DevProblem &P, const DevCells &C, const EntryBlock *blks,
                           const int32_t *work, int64_t nwork, const int32_t *rows,
                           const uint16_t *rowslot, const int32_t *cols, const double *Hc,
+                          const int32_t *slotbox, const double *Hcache, int nbox,
                           hipStream_t st);
 // Interpolative decompositions of the blocks blks[sel[0..nb)]: k_cpqr works
 // on the block in global memory (any n); launch_id_onchip handles blocks of

@@ -128,25 +128,18 @@ __global__ void k_self_terms(DevProblem P, const double *slow, int64_t Nv,
 }
 
 // ---------------------------------------------------------------------------
-// hb_entry, column side of eq. chebinterpblock: for block column j (source
-// cell in table box beta) and row box alpha,
+// hb_entry, column side of eq. chebinterpblock: for a source cell in table
+// box beta and a row box alpha,
 //   Hc[t][a] = sum_b F_t[alpha*NTb + a, beta*NTb + b] T_b(r_j).
-// One wave per (block, column, row-box slot); lanes run over a, reading the
-// transposed table so that the loads are contiguous.
+// One wave per (source cell, row box); lanes run over a, reading the
+// transposed table so that the loads are contiguous.  k_colside does this
+// per (block, column, row-box slot) into the batch workspace; k_colside_cells
+// fills a cache for every (cell, box) pair once per build when it fits in
+// memory, which the entry kernel then reads instead.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_colside(
-    DevProblem P, DevCells C, DevTables T, const EntryBlock *blks,
-    const int32_t *work, int64_t nwork, const int32_t *cols,
-    const int32_t *slotbox, double *Hc) {
-  extern __shared__ double sT[];
-  const int64_t w = blockIdx.x;
-  if (w >= nwork) return;
-  const int blk = work[2 * w], js = work[2 * w + 1];
-  const EntryBlock B = blks[blk];
-  const int j = js / B.nslot, slot = js % B.nslot;
-  const int32_t cp = cols[B.col_off + j];
-  const int beta = C.box[cp];
-  const int alpha = slotbox[B.slot_off + slot];
+__device__ __forceinline__ void colside_item(const DevProblem &P, const DevCells &C,
+                                             const DevTables &T, int32_t cp, int beta, int alpha,
+                                             double *out, double *sT) {
   const int nI = P.nI, NTb = P.NTb, NT = P.NT, D = P.dim;
   const double *lwc = C.lw + (int64_t)cp * D * nI;
   for (int b = threadIdx.x; b < NTb; b += 64) {
@@ -160,7 +153,6 @@ __global__ __launch_bounds__(64) void k_colside(
   }
   __syncthreads();
   const int ntab = P.nterms == 2 ? 3 : 2;
-  double *out = Hc + B.hc_off + ((int64_t)j * B.nslot + slot) * 3 * NTb;
   for (int a = threadIdx.x; a < NTb; a += 64) {
     const int64_t col = (int64_t)alpha * NTb + a;
     double acc[3] = {0.0, 0.0, 0.0};
@@ -175,6 +167,32 @@ __global__ __launch_bounds__(64) void k_colside(
     out[NTb + a] = acc[1];
     out[2 * NTb + a] = acc[2];
   }
+}
+
+__global__ __launch_bounds__(64) void k_colside(
+    DevProblem P, DevCells C, DevTables T, const EntryBlock *blks,
+    const int32_t *work, int64_t nwork, const int32_t *cols,
+    const int32_t *slotbox, double *Hc) {
+  extern __shared__ double sT[];
+  const int64_t w = blockIdx.x;
+  if (w >= nwork) return;
+  const int blk = work[2 * w], js = work[2 * w + 1];
+  const EntryBlock B = blks[blk];
+  const int j = js / B.nslot, slot = js % B.nslot;
+  const int32_t cp = cols[B.col_off + j];
+  double *out = Hc + B.hc_off + ((int64_t)j * B.nslot + slot) * 3 * P.NTb;
+  colside_item(P, C, T, cp, C.box[cp], slotbox[B.slot_off + slot], out, sT);
+}
+
+// Cache entry (cell p, box alpha) at Hcache[(p * nbox + alpha) * 3 NTb].
+__global__ __launch_bounds__(64) void k_colside_cells(DevProblem P, DevCells C, DevTables T,
+                                                      int64_t Nv, int nbox, double *Hcache) {
+  extern __shared__ double sT[];
+  const int64_t w = blockIdx.x;
+  if (w >= Nv * nbox) return;
+  const int32_t p = (int32_t)(w / nbox);
+  const int alpha = (int)(w % nbox);
+  colside_item(P, C, T, p, C.box[p], alpha, Hcache + w * 3 * P.NTb, sT);
 }
 
 // sum_a T_a(r_i) H_t[a] for the ntab tables at once, T_a = prod_s l_{a_s}(r_s).
@@ -245,14 +263,16 @@ template <int D, int NI>
 __global__ __launch_bounds__(256) void k_entries(
     DevProblem P, DevCells C, const EntryBlock *blks, const int32_t *work,
     int64_t nwork, const int32_t *rows, const uint16_t *rowslot,
-    const int32_t *cols, const double *Hc) {
+    const int32_t *cols, const double *Hc, const int32_t *slotbox, const double *Hcache,
+    int nbox) {
   const int64_t w = blockIdx.x;
   if (w >= nwork) return;
   const int blk = work[2 * w], j = work[2 * w + 1];
   const EntryBlock B = blks[blk];
   const int32_t cp = cols[B.col_off + j];
   const int NTb = P.NTb;
-  const double *Hcol = Hc + B.hc_off + (int64_t)j * B.nslot * 3 * NTb;
+  const double *Hcol = Hcache ? Hcache + (int64_t)cp * nbox * 3 * NTb
+                              : Hc + B.hc_off + (int64_t)j * B.nslot * 3 * NTb;
   double2 *out = B.out + (int64_t)j * B.m;
   for (int i = threadIdx.x; i < B.m; i += 256) {
     const int32_t rp = rows[B.row_off + i];
@@ -261,7 +281,8 @@ __global__ __launch_bounds__(256) void k_entries(
       K = C.self[rp];
     } else {
       const int slot = rowslot[B.row_off + i];
-      const double *H = Hcol + (int64_t)slot * 3 * NTb;
+      const int hs = Hcache ? slotbox[B.slot_off + slot] : slot;
+      const double *H = Hcol + (int64_t)hs * 3 * NTb;
       double tv[3];
       contract3<D, NI>(C.lw + (int64_t)rp * D * NI, H, NTb, P.nterms == 2 ? 3 : 2, tv);
       const double t2 = tv[0], v0 = tv[1], v1 = tv[2];
@@ -744,7 +765,9 @@ __global__ __launch_bounds__(NW * 64, WPE) void k_id_onchip(
   const int kmax = m < n ? m : n;
   int rank = kmax;
   double r11 = 0.0;
-  for (int k = 0; k < kmax; ++k) {
+  // single-exit loop (a break would make the compiler copy R at the exit)
+  bool go = kmax > 0;
+  for (int k = 0; go; ++k) {
     double best = uniform_d(red_v[0]);
     int q = __builtin_amdgcn_readfirstlane(red_q[0]), p = __builtin_amdgcn_readfirstlane(red_c[0]);
     for (int w2 = 1; w2 < NW; ++w2) {
@@ -758,8 +781,10 @@ __global__ __launch_bounds__(NW * 64, WPE) void k_id_onchip(
     if (k == 0) r11 = nrm;
     if (q >= n || nrm == 0.0 || (k > 0 && nrm <= tol * r11)) {
       rank = k > 0 ? k : 1;
-      break;
+      go = false;
+      continue;
     }
+    go = k + 1 < kmax;
     const int uk = k >> 6, lk = k & 63;
     if (w == p % NW) {
       const int sp = p / NW;
@@ -1182,22 +1207,36 @@ hipError_t launch_colside(const DevProblem &P, const DevCells &C, const DevTable
   return hipGetLastError();
 }
 
+hipError_t launch_colside_cells(const DevProblem &P, const DevCells &C, const DevTables &T,
+                                int64_t Nv, int nbox, double *Hcache, hipStream_t st) {
+  const int64_t n = Nv * nbox;
+  if (n == 0) return hipSuccess;
+  const size_t lds = sizeof(double) * (size_t)P.NTb;
+  hipLaunchKernelGGL(k_colside_cells, dim3(n), dim3(64), lds, st, P, C, T, Nv, nbox, Hcache);
+  return hipGetLastError();
+}
+
 template <int D, int NI>
 static void entries_launch(const DevProblem &P, const DevCells &C, const EntryBlock *blks,
                            const int32_t *work, int64_t nwork, const int32_t *rows,
                            const uint16_t *rowslot, const int32_t *cols, const double *Hc,
+                           const int32_t *slotbox, const double *Hcache, int nbox,
                            hipStream_t st) {
   hipLaunchKernelGGL((k_entries<D, NI>), dim3(nwork), dim3(256), 0, st, P, C, blks, work,
-                     nwork, rows, rowslot, cols, Hc);
+                     nwork, rows, rowslot, cols, Hc, slotbox, Hcache, nbox);
 }
 
 hipError_t launch_entries(const DevProblem &P, const DevCells &C, const EntryBlock *blks,
                           const int32_t *work, int64_t nwork, const int32_t *rows,
                           const uint16_t *rowslot, const int32_t *cols, const double *Hc,
+                          const int32_t *slotbox, const double *Hcache, int nbox,
                           hipStream_t st) {
   if (nwork == 0) return hipSuccess;
-#define HBI_NI_CASE(D, NI) \
-  case NI: entries_launch<D, NI>(P, C, blks, work, nwork, rows, rowslot, cols, Hc, st); break;
+#define HBI_NI_CASE(D, NI)                                                                 \
+  case NI:                                                                                 \
+    entries_launch<D, NI>(P, C, blks, work, nwork, rows, rowslot, cols, Hc, slotbox, Hcache, \
+                          nbox, st);                                                       \
+    break;
 #define HBI_NI_SWITCH(D)                                                              \
   switch (P.nI) {                                                                     \
     HBI_NI_CASE(D, 2) HBI_NI_CASE(D, 3) HBI_NI_CASE(D, 4) HBI_NI_CASE(D, 5)           \

@@ -156,8 +156,10 @@ struct hbi_ctx {
   std::vector<int32_t> box_h;   // table box per tree position (host copy)
   // device cell data
   DevBuf perm_d, xyz_d, lw_d, box_d, self_d, slow_d, FT_d[3];
-  // build workspace
-  DevBuf ws, idx_d;
+  // build workspace; hc_cache holds the column side of every (cell, box)
+  // pair during a build when it fits (hc_nbox boxes per cell, else empty)
+  DevBuf ws, idx_d, hc_cache;
+  int hc_nbox = 0;
   // factors and plan
   hbi_prec prec = HBI_F64;
   DevBuf F;
@@ -309,7 +311,7 @@ struct Batcher {
 
   // bytes of workspace a block needs
   size_t ws_need(int32_t m, int32_t n, int nslot, bool id) const {
-    size_t b = align256((size_t)n * nslot * 3 * c->NTb * sizeof(double));
+    size_t b = c->hc_cache.p ? 0 : align256((size_t)n * nslot * 3 * c->NTb * sizeof(double));
     if (id) b += align256((size_t)m * n * sizeof(double2)) +
                  align256((size_t)std::min(m, n) * n * sizeof(double2));
     return b;
@@ -389,7 +391,7 @@ struct Batcher {
       EntryBlock &e = eb[q];
       e.row_off = ro; e.col_off = co; e.slot_off = so; e.m = b.m; e.n = b.n; e.nslot = ns;
       e.hc_off = (int64_t)(wso / sizeof(double));
-      wso += align256((size_t)b.n * ns * 3 * c->NTb * sizeof(double));
+      if (!c->hc_cache.p) wso += align256((size_t)b.n * ns * 3 * c->NTb * sizeof(double));
       if (id) {
         IdBlock &d = ib[q];
         d.A = (double2 *)(ws + wso);
@@ -467,12 +469,15 @@ struct Batcher {
     const DevProblem P = c->devprob();
     const DevCells C = c->devcells();
     const DevTables T = c->devtables();
-    HBI_HIP(launch_colside(P, C, T, (const EntryBlock *)(ix + o_eb), (const int32_t *)(ix + o_wc),
-                           ncw, (const int32_t *)(ix + o_cols), (const int32_t *)(ix + o_slot),
-                           c->ws.as<double>(), c->stream));
+    const double *hcache = c->hc_cache.as<double>();
+    if (!hcache)
+      HBI_HIP(launch_colside(P, C, T, (const EntryBlock *)(ix + o_eb),
+                             (const int32_t *)(ix + o_wc), ncw, (const int32_t *)(ix + o_cols),
+                             (const int32_t *)(ix + o_slot), c->ws.as<double>(), c->stream));
     HBI_HIP(launch_entries(P, C, (const EntryBlock *)(ix + o_eb), (const int32_t *)(ix + o_we),
                            new_, (const int32_t *)(ix + o_rows), (const uint16_t *)(ix + o_rs),
-                           (const int32_t *)(ix + o_cols), c->ws.as<double>(), c->stream));
+                           (const int32_t *)(ix + o_cols), c->ws.as<double>(),
+                           (const int32_t *)(ix + o_slot), hcache, c->hc_nbox, c->stream));
     for (int64_t q = 0; q < nb; ++q) c->entries_eval += (int64_t)blocks[i0 + q].m * blocks[i0 + q].n;
     if (id) {
       const IdBlock *ibd = (const IdBlock *)(ix + o_ib);
@@ -528,9 +533,36 @@ struct LevelState {
   }
 };
 
+// The column-side cache: Nv * nbox * 3 * NTb doubles, used when at most
+// HBI_HC_CACHE_BYTES (default 16 GiB) and a quarter of the free device memory.
+// Each cell then gets its column side once instead of once per block.
+static void fill_hc_cache(hbi_ctx *c) {
+  c->hc_cache.release();
+  c->hc_nbox = 0;
+  const int nbox = c->NT / c->NTb;
+  const int64_t Nv = c->geo.Nv;
+  const size_t bytes = (size_t)Nv * nbox * 3 * c->NTb * sizeof(double);
+  size_t cap = (size_t)16 << 30;
+  if (const char *e = std::getenv("HBI_HC_CACHE_BYTES")) cap = (size_t)std::strtoull(e, nullptr, 10);
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) { (void)hipGetLastError(); return; }
+  if (bytes == 0 || bytes > cap || bytes > fr / 4) return;
+  if (c->hc_cache.alloc(bytes) != hipSuccess) return;   // not fatal: per-block path
+  HBI_HIP(launch_colside_cells(c->devprob(), c->devcells(), c->devtables(), Nv, nbox,
+                               c->hc_cache.as<double>(), c->stream));
+  c->hc_nbox = nbox;
+}
+
+struct HcCacheScope {
+  hbi_ctx *c;
+  ~HcCacheScope() { c->hc_cache.release(); c->hc_nbox = 0; }
+};
+
 void build_factors(hbi_ctx *c, double tol) {
   const double tb0 = now_s();
   if (c->geo_leaf != c->leaf()) setup_cells(c);
+  HcCacheScope hc_scope{c};
+  fill_hc_cache(c);
   Geometry &G = c->geo;
   const int Lv = G.Lv;
   const int64_t nleaf = (int64_t)1 << Lv;

@@ -264,9 +264,11 @@ def test_3d_apply_sampled_rows(torch_mod):
 def test_id_onchip_matches_global(torch_mod, monkeypatch, prec, tol, bound):
     """Blocks of at most 64 candidate columns are decomposed on chip (pivoted
     QR of the triangular factor of the block); HBI_ID_KERNEL=global sends them
-    to the global-memory pivoted QR of the block itself.  Both operators agree
-    with the oracle and with each other to the compression tolerance, with
-    nearly the same ranks."""
+    to the global-memory pivoted QR of the block itself.  The second build
+    also turns the per-cell column-side cache off (HBI_HC_CACHE_BYTES=0), so
+    entries come from the per-block column side.  Both operators agree with
+    the oracle and with each other to the compression tolerance, with nearly
+    the same ranks."""
     torch = torch_mod
     prob = hb_inputs.configs.c2(128)
     dt = torch.complex128 if prec == "f64" else torch.complex64
@@ -277,6 +279,7 @@ def test_id_onchip_matches_global(torch_mod, monkeypatch, prec, tol, bound):
     for kind in ("onchip", "global"):
         if kind == "global":
             monkeypatch.setenv("HBI_ID_KERNEL", "global")
+            monkeypatch.setenv("HBI_HC_CACHE_BYTES", "0")
         say(f"id kernel {kind} {prec} tol {tol}")
         op = make_op(prob, tol=tol, prec=prec)
         u = op.apply(to_dev(torch, s, dt)).cpu().numpy().astype(np.complex128)
