@@ -41,6 +41,10 @@ struct EntryBlock {
   int32_t m, n, nslot, pad;
 };
 
+// Entry tile: sorted rows [r0, r0 + nr) of block blk (all in row-box slot
+// `slot`) x columns [j0, j0 + nj).
+struct ETile { int32_t blk, r0, nr, j0, nj, slot; };
+
 // One interpolative decomposition on a block already in the workspace.
 struct IdBlock {
   double2 *A;        // m x n column-major (overwritten)

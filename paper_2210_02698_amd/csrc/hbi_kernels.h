@@ -50,8 +50,8 @@ hipError_t launch_colside_cells(const DevProblem &P, const DevCells &C, const De
 // Entries of the blocks; the column side comes from the batch workspace Hc,
 // or from Hcache (nbox boxes per cell) when that is non-null.
 hipError_t launch_entries(const DevProblem &P, const DevCells &C, const EntryBlock *blks,
-                          const int32_t *work, int64_t nwork, const int32_t *rows,
-                          const uint16_t *rowslot, const int32_t *cols, const double *Hc,
+                          const ETile *tiles, int64_t ntiles, const int32_t *rows,
+                          const int32_t *rord, const int32_t *cols, const double *Hc,
                           const int32_t *slotbox, const double *Hcache, int nbox,
                           hipStream_t st);
 // Interpolative decompositions of the blocks blks[sel[0..nb)]: k_cpqr works

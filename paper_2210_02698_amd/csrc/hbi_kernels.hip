@@ -195,40 +195,6 @@ __global__ __launch_bounds__(64) void k_colside_cells(DevProblem P, DevCells C, 
   colside_item(P, C, T, p, C.box[p], alpha, Hcache + w * 3 * P.NTb, sT);
 }
 
-// sum_a T_a(r_i) H_t[a] for the ntab tables at once, T_a = prod_s l_{a_s}(r_s).
-// The x-axis weights sit in registers; y and z weights are read from the
-// (cached) per-cell array.
-template <int D, int NI>
-__device__ __forceinline__ void contract3(const double *lw, const double *H, int NTb,
-                                          int ntab, double out[3]) {
-  double lx[NI];
-#pragma unroll
-  for (int a1 = 0; a1 < NI; ++a1) lx[a1] = lw[a1];
-  out[0] = out[1] = out[2] = 0.0;
-  const int n3 = D == 3 ? NI : 1;
-  for (int a3 = 0; a3 < n3; ++a3) {
-    double s3[3] = {0.0, 0.0, 0.0};
-    for (int a2 = 0; a2 < NI; ++a2) {
-      const double *Hp = H + NI * (a2 + NI * a3);
-      double s[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-      for (int a1 = 0; a1 < NI; ++a1) {
-        s[0] = fma(lx[a1], Hp[a1], s[0]);
-        s[1] = fma(lx[a1], Hp[NTb + a1], s[1]);
-        if (ntab == 3) s[2] = fma(lx[a1], Hp[2 * NTb + a1], s[2]);
-      }
-      const double wy = lw[NI + a2];
-      s3[0] = fma(wy, s[0], s3[0]);
-      s3[1] = fma(wy, s[1], s3[1]);
-      s3[2] = fma(wy, s[2], s3[2]);
-    }
-    const double wz = D == 3 ? lw[2 * NI + a3] : 1.0;
-    out[0] = fma(wz, s3[0], out[0]);
-    out[1] = fma(wz, s3[1], out[1]);
-    out[2] = fma(wz, s3[2], out[2]);
-  }
-}
-
 // HB entry from interpolated tau^2, v0, v1 (eq. babich, eq. termf).
 __device__ __forceinline__ double2 hb_value(int D, int nterms, double omega,
                                             double tau2, double v0, double v1) {
@@ -259,36 +225,109 @@ __device__ __forceinline__ double2 hb_value(int D, int nterms, double omega,
   return K;
 }
 
+// ---------------------------------------------------------------------------
+// hb_entry, row side of eq. chebinterpblock as a tiled product: for a tile of
+// up to kET_I rows (all in one table box) and kET_J columns of a block,
+//   g_t(i, j) = sum_A T_A(r_i) Hc_t(j, box)[A],   T_A = prod_s l_{a_s}(r_i),
+// for t = tau^2, v0, v1.  T and Hc pass through LDS in chunks of kET_K nodes;
+// each thread keeps a 4 x 4 x 3 register tile.  Then the HB value of
+// (tau^2, v0, v1) (eq. babich, eq. termf), or the self term on the diagonal,
+// goes to out(i, j).  Rows are visited in slot order through `rord`.
+// ---------------------------------------------------------------------------
+constexpr int kET_I = 128, kET_J = 32, kET_K = 32;
+
 template <int D, int NI>
-__global__ __launch_bounds__(256) void k_entries(
-    DevProblem P, DevCells C, const EntryBlock *blks, const int32_t *work,
-    int64_t nwork, const int32_t *rows, const uint16_t *rowslot,
-    const int32_t *cols, const double *Hc, const int32_t *slotbox, const double *Hcache,
-    int nbox) {
-  const int64_t w = blockIdx.x;
-  if (w >= nwork) return;
-  const int blk = work[2 * w], j = work[2 * w + 1];
-  const EntryBlock B = blks[blk];
-  const int32_t cp = cols[B.col_off + j];
+__global__ __launch_bounds__(256, 2) void k_entries(
+    DevProblem P, DevCells C, const EntryBlock *blks, const ETile *tiles, int64_t ntiles,
+    const int32_t *rows, const int32_t *rord, const int32_t *cols, const double *Hc,
+    const int32_t *slotbox, const double *Hcache, int nbox) {
+  __shared__ double sW[kET_K][kET_I];
+  __shared__ double sH[3][kET_K][kET_J];
+  __shared__ int32_t srp[kET_I];
+  __shared__ const double *shp[kET_J];
+  const int64_t tb = blockIdx.x;
+  if (tb >= ntiles) return;
+  const ETile T = tiles[tb];
+  const EntryBlock B = blks[T.blk];
   const int NTb = P.NTb;
-  const double *Hcol = Hcache ? Hcache + (int64_t)cp * nbox * 3 * NTb
-                              : Hc + B.hc_off + (int64_t)j * B.nslot * 3 * NTb;
-  double2 *out = B.out + (int64_t)j * B.m;
-  for (int i = threadIdx.x; i < B.m; i += 256) {
-    const int32_t rp = rows[B.row_off + i];
-    double2 K;
-    if (rp == cp) {
-      K = C.self[rp];
-    } else {
-      const int slot = rowslot[B.row_off + i];
-      const int hs = Hcache ? slotbox[B.slot_off + slot] : slot;
-      const double *H = Hcol + (int64_t)hs * 3 * NTb;
-      double tv[3];
-      contract3<D, NI>(C.lw + (int64_t)rp * D * NI, H, NTb, P.nterms == 2 ? 3 : 2, tv);
-      const double t2 = tv[0], v0 = tv[1], v1 = tv[2];
-      K = hb_value(D, P.nterms, P.omega, t2, v0, v1);
+  const int ntab = P.nterms == 2 ? 3 : 2;
+  const int tid = threadIdx.x;
+  const int box = slotbox[B.slot_off + T.slot];
+  for (int r = tid; r < kET_I; r += 256)
+    srp[r] = r < T.nr ? rows[B.row_off + rord[B.row_off + T.r0 + r]] : -1;
+  for (int c = tid; c < kET_J; c += 256) {
+    const double *h = nullptr;
+    if (c < T.nj) {
+      const int j = T.j0 + c;
+      h = Hcache ? Hcache + ((int64_t)cols[B.col_off + j] * nbox + box) * 3 * NTb
+                 : Hc + B.hc_off + ((int64_t)j * B.nslot + T.slot) * 3 * NTb;
     }
-    out[i] = K;
+    shp[c] = h;
+  }
+  __syncthreads();
+  const int ty = tid >> 3, tx = tid & 7;
+  double acc[4][4][3];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int t = 0; t < 3; ++t) acc[r][c][t] = 0.0;
+  for (int a0 = 0; a0 < NTb; a0 += kET_K) {
+    for (int e = tid; e < kET_K * kET_I; e += 256) {
+      const int k = e / kET_I, r = e % kET_I;
+      const int A = a0 + k, rp = srp[r];
+      double w = 0.0;
+      if (rp >= 0 && A < NTb) {
+        const double *lw = C.lw + (int64_t)rp * D * NI;
+        const int a1 = A % NI, a23 = A / NI;
+        w = lw[a1] * lw[NI + a23 % NI];
+        if (D == 3) w *= lw[2 * NI + a23 / NI];
+      }
+      sW[k][r] = w;
+    }
+    for (int e = tid; e < 3 * kET_K * kET_J; e += 256) {
+      const int k = e % kET_K, cr = e / kET_K, c = cr % kET_J, t = cr / kET_J;
+      const double *h = shp[c];
+      const int A = a0 + k;
+      sH[t][k][c] = (h && A < NTb && t < ntab) ? h[(int64_t)t * NTb + A] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int k = 0; k < kET_K; ++k) {
+      double w[4], h[3][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) w[r] = sW[k][ty * 4 + r];
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) h[t][c] = sH[t][k][tx * 4 + c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int t = 0; t < 3; ++t) acc[r][c][t] = fma(w[r], h[t][c], acc[r][c][t]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int rr = ty * 4 + r;
+    if (rr >= T.nr) continue;
+    const int i = rord[B.row_off + T.r0 + rr];
+    const int32_t rp = srp[rr];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int cc = tx * 4 + c;
+      if (cc >= T.nj) continue;
+      const int j = T.j0 + cc;
+      const int32_t cp = cols[B.col_off + j];
+      const double2 K = rp == cp ? C.self[rp]
+                                 : hb_value(D, P.nterms, P.omega, acc[r][c][0], acc[r][c][1],
+                                            acc[r][c][2]);
+      B.out[i + (int64_t)j * B.m] = K;
+    }
   }
 }
 
@@ -1218,24 +1257,24 @@ hipError_t launch_colside_cells(const DevProblem &P, const DevCells &C, const De
 
 template <int D, int NI>
 static void entries_launch(const DevProblem &P, const DevCells &C, const EntryBlock *blks,
-                           const int32_t *work, int64_t nwork, const int32_t *rows,
-                           const uint16_t *rowslot, const int32_t *cols, const double *Hc,
+                           const ETile *tiles, int64_t ntiles, const int32_t *rows,
+                           const int32_t *rord, const int32_t *cols, const double *Hc,
                            const int32_t *slotbox, const double *Hcache, int nbox,
                            hipStream_t st) {
-  hipLaunchKernelGGL((k_entries<D, NI>), dim3(nwork), dim3(256), 0, st, P, C, blks, work,
-                     nwork, rows, rowslot, cols, Hc, slotbox, Hcache, nbox);
+  hipLaunchKernelGGL((k_entries<D, NI>), dim3(ntiles), dim3(256), 0, st, P, C, blks, tiles,
+                     ntiles, rows, rord, cols, Hc, slotbox, Hcache, nbox);
 }
 
 hipError_t launch_entries(const DevProblem &P, const DevCells &C, const EntryBlock *blks,
-                          const int32_t *work, int64_t nwork, const int32_t *rows,
-                          const uint16_t *rowslot, const int32_t *cols, const double *Hc,
+                          const ETile *tiles, int64_t ntiles, const int32_t *rows,
+                          const int32_t *rord, const int32_t *cols, const double *Hc,
                           const int32_t *slotbox, const double *Hcache, int nbox,
                           hipStream_t st) {
-  if (nwork == 0) return hipSuccess;
-#define HBI_NI_CASE(D, NI)                                                                 \
-  case NI:                                                                                 \
-    entries_launch<D, NI>(P, C, blks, work, nwork, rows, rowslot, cols, Hc, slotbox, Hcache, \
-                          nbox, st);                                                       \
+  if (ntiles == 0) return hipSuccess;
+#define HBI_NI_CASE(D, NI)                                                                  \
+  case NI:                                                                                  \
+    entries_launch<D, NI>(P, C, blks, tiles, ntiles, rows, rord, cols, Hc, slotbox, Hcache, \
+                          nbox, st);                                                        \
     break;
 #define HBI_NI_SWITCH(D)                                                              \
   switch (P.nI) {                                                                     \

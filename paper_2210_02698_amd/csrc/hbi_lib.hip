@@ -305,6 +305,9 @@ static bool id_onchip_enabled() {
   return !(e && std::strcmp(e, "global") == 0);
 }
 
+// entry tile shape (rows of one table box x columns), as k_entries takes it
+constexpr int32_t kEntryTileRows = 128, kEntryTileCols = 32;
+
 struct Batcher {
   hbi_ctx *c;
   explicit Batcher(hbi_ctx *ctx) : c(ctx) {}
@@ -371,19 +374,19 @@ struct Batcher {
     const int64_t nb = i1 - i0;
     std::vector<EntryBlock> eb(nb);
     std::vector<IdBlock> ib(id ? nb : 0);
-    int64_t nrows = 0, ncols = 0, nsl = 0, ncw = 0, new_ = 0;
+    int64_t nrows = 0, ncols = 0, nsl = 0, ncw = 0;
     for (int64_t q = 0; q < nb; ++q) {
       const BlockIn &b = blocks[i0 + q];
       nrows += b.m; ncols += b.n; nsl += nslot[i0 + q];
       ncw += (int64_t)b.n * nslot[i0 + q];
-      new_ += b.n;
     }
-    std::vector<int32_t> rows(nrows), cols(ncols), slotbox(nsl), workc(2 * ncw), worke(2 * new_);
-    std::vector<uint16_t> rowslot(nrows);
+    std::vector<int32_t> rows(nrows), cols(ncols), slotbox(nsl), workc(2 * ncw), rord(nrows);
+    std::vector<ETile> tiles;
+    std::vector<int32_t> scount;
     std::vector<int64_t> pivoff(nb, 0);
     char *ws = c->ws.as<char>();
     size_t wso = 0;
-    int64_t ro = 0, co = 0, so = 0, wc = 0, we = 0, po = 0;
+    int64_t ro = 0, co = 0, so = 0, wc = 0, po = 0;
     for (int64_t q = 0; q < nb; ++q) {
       const BlockIn &b = blocks[i0 + q];
       const std::vector<int32_t> &sl = slots[i0 + q];
@@ -406,11 +409,28 @@ struct Batcher {
       } else {
         e.out = b.out;
       }
+      // rows in slot order (counting sort), then tiles of kEntryTileRows rows
+      // of one slot x kEntryTileCols columns
+      scount.assign(ns + 1, 0);
       for (int32_t i = 0; i < b.m; ++i) {
         rows[ro + i] = b.rows[i];
         const int32_t bx = c->box_h[b.rows[i]];
-        rowslot[ro + i] = (uint16_t)(std::find(sl.begin(), sl.end(), bx) - sl.begin());
+        scount[(std::find(sl.begin(), sl.end(), bx) - sl.begin()) + 1] += 1;
       }
+      for (int s2 = 0; s2 < ns; ++s2) scount[s2 + 1] += scount[s2];
+      {
+        std::vector<int32_t> fill(scount.begin(), scount.end() - 1);
+        for (int32_t i = 0; i < b.m; ++i) {
+          const int32_t bx = c->box_h[b.rows[i]];
+          const int s2 = (int)(std::find(sl.begin(), sl.end(), bx) - sl.begin());
+          rord[ro + fill[s2]++] = i;
+        }
+      }
+      for (int s2 = 0; s2 < ns; ++s2)
+        for (int32_t r0 = scount[s2]; r0 < scount[s2 + 1]; r0 += kEntryTileRows)
+          for (int32_t j0 = 0; j0 < b.n; j0 += kEntryTileCols)
+            tiles.push_back(ETile{(int32_t)q, r0, std::min(kEntryTileRows, scount[s2 + 1] - r0), j0,
+                                  std::min(kEntryTileCols, b.n - j0), s2});
       std::copy(b.cols, b.cols + b.n, cols.begin() + co);
       std::copy(sl.begin(), sl.end(), slotbox.begin() + so);
       for (int32_t j = 0; j < b.n; ++j) {
@@ -419,18 +439,15 @@ struct Batcher {
           workc[2 * wc + 1] = j * ns + s;
           ++wc;
         }
-        worke[2 * we] = (int32_t)q;
-        worke[2 * we + 1] = j;
-        ++we;
       }
       ro += b.m; co += b.n; so += ns;
     }
-    // one index upload: rows, cols, slotbox, workc, worke, rowslot, eb, ib, piv, rank
+    // one index upload: rows, cols, slotbox, workc, tiles, rord, eb, ib, sel, piv, rank
     size_t off = 0;
     auto place = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     const size_t o_rows = place(rows.size() * 4), o_cols = place(cols.size() * 4),
                  o_slot = place(slotbox.size() * 4), o_wc = place(workc.size() * 4),
-                 o_we = place(worke.size() * 4), o_rs = place(rowslot.size() * 2),
+                 o_tl = place(tiles.size() * sizeof(ETile)), o_ro = place(rord.size() * 4),
                  o_eb = place(eb.size() * sizeof(EntryBlock)),
                  o_ib = place(ib.size() * sizeof(IdBlock)), o_sel = place(id ? (size_t)nb * 4 : 0),
                  o_piv = place((size_t)po * 4), o_rank = place((size_t)nb * 4);
@@ -460,8 +477,8 @@ struct Batcher {
     put(o_cols, cols.data(), cols.size() * 4);
     put(o_slot, slotbox.data(), slotbox.size() * 4);
     put(o_wc, workc.data(), workc.size() * 4);
-    put(o_we, worke.data(), worke.size() * 4);
-    put(o_rs, rowslot.data(), rowslot.size() * 2);
+    put(o_tl, tiles.data(), tiles.size() * sizeof(ETile));
+    put(o_ro, rord.data(), rord.size() * 4);
     put(o_eb, eb.data(), eb.size() * sizeof(EntryBlock));
     put(o_ib, ib.data(), ib.size() * sizeof(IdBlock));
     put(o_sel, sel.data(), sel.size() * 4);
@@ -474,10 +491,11 @@ struct Batcher {
       HBI_HIP(launch_colside(P, C, T, (const EntryBlock *)(ix + o_eb),
                              (const int32_t *)(ix + o_wc), ncw, (const int32_t *)(ix + o_cols),
                              (const int32_t *)(ix + o_slot), c->ws.as<double>(), c->stream));
-    HBI_HIP(launch_entries(P, C, (const EntryBlock *)(ix + o_eb), (const int32_t *)(ix + o_we),
-                           new_, (const int32_t *)(ix + o_rows), (const uint16_t *)(ix + o_rs),
-                           (const int32_t *)(ix + o_cols), c->ws.as<double>(),
-                           (const int32_t *)(ix + o_slot), hcache, c->hc_nbox, c->stream));
+    HBI_HIP(launch_entries(P, C, (const EntryBlock *)(ix + o_eb), (const ETile *)(ix + o_tl),
+                           (int64_t)tiles.size(), (const int32_t *)(ix + o_rows),
+                           (const int32_t *)(ix + o_ro), (const int32_t *)(ix + o_cols),
+                           c->ws.as<double>(), (const int32_t *)(ix + o_slot), hcache,
+                           c->hc_nbox, c->stream));
     for (int64_t q = 0; q < nb; ++q) c->entries_eval += (int64_t)blocks[i0 + q].m * blocks[i0 + q].n;
     if (id) {
       const IdBlock *ibd = (const IdBlock *)(ix + o_ib);
