@@ -88,7 +88,9 @@ typedef struct {
                                cells [10 in 2D, 3 in 3D]                    */
   int32_t band_width;       /* width in cells of the boundary band that the
                                uniform proxy rows f_tau are drawn from [2]   */
-  int64_t workspace_bytes;  /* device workspace per build batch [2 GiB]      */
+  int64_t workspace_bytes;  /* device workspace budget per build batch
+                               [1/8 of free device memory, clamped to
+                               2..32 GiB]                                    */
 } hbi_build_opts;
 
 /* Create a context on HIP device `device`; all work is queued on

@@ -61,6 +61,10 @@ hipError_t launch_cpqr(const IdBlock *blks, const int32_t *sel, int64_t nb, int 
                        double tol, int32_t *rank, hipStream_t st);
 hipError_t launch_id_onchip(const IdBlock *blks, const int32_t *sel, int64_t nb, int nmax,
                             double tol, int32_t *rank, hipStream_t st);
+// Blocked (panel) form of k_cpqr for any n whose norms and panel fit in LDS
+// (falls back to launch_cpqr otherwise).
+hipError_t launch_cpqr_blocked(const IdBlock *blks, const int32_t *sel, int64_t nb, int nmax,
+                               int mmax, double tol, int32_t *rank, hipStream_t st);
 hipError_t launch_copy_blocks(const CopyDesc *d, int64_t nb, hipStream_t st);
 hipError_t launch_pack_pairs(const PairDesc *d, int64_t np, hipStream_t st);
 hipError_t launch_to_f32(const double2 *src, float2 *dst, int64_t n, hipStream_t st);

@@ -479,7 +479,7 @@ __global__ __launch_bounds__(HBI_ID_THREADS) void k_cpqr(const IdBlock *blks, co
   const int m = B.m, n = B.n;
   double *nrm2 = lds_id;
   int *colmap = (int *)(lds_id + nmax);
-  double2 *shared_c = (double2 *)(lds_id + nmax + (nmax + 1) / 2 + 1);
+  double2 *shared_c = (double2 *)(lds_id + ((nmax + (nmax + 1) / 2 + 2) & ~1));
   const bool vlds = m <= cap;
   double2 *A = B.A;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -939,6 +939,293 @@ __global__ __launch_bounds__(NW * 64, WPE) void k_id_onchip(
   if (tid == 0) rank_out[blk] = r;
 }
 
+// ---------------------------------------------------------------------------
+// Interpolative decomposition of a block in global memory with the
+// reflectors applied in panels of nb steps: the blocked form of column-
+// pivoted Householder QR (deferred trailing update with downdated column
+// norms, as in LAPACK's xGEQP3 / xLAQPS).  Same pivot rule, stopping test
+// and output as k_cpqr.  Inside a panel that starts at row k0 the trailing
+// block is A^(k) = A - V F^H, V holding the panel's reflectors (stored below
+// the diagonal of the pivot columns) and F = [f_0 ...], f_l = tau_l A^(l)^H v_l.
+// Step k, pivot p, trailing columns T:
+//   a_p    = A(k:, p) - V(k:, :) F(p, :)^H        (pivot column brought up to date)
+//   beta, tau, v from a_p (as in k_cpqr); v stored in A(k+1:, p)
+//   g      = A(k:, T)^H v,  y = V(k:, :)^H v       (one read of the trailing block)
+//   f      = tau (g - F(T, :) y)                    (new column of F)
+//   R(k,T) = A(k, T) - V(k, :) F(T, :)^H - conj(f)  (written to A(k, T))
+//   |a_j|^2 -= |R(k, j)|^2                          (norm downdate)
+// A downdated norm that falls below sqrt(eps) of its last exact value is
+// recomputed exactly; at the end of a panel A(k+1:, T) -= V F(T, :)^H is
+// applied explicitly and all norms are recomputed.  Per step the trailing
+// block is read once, against two reads and a write in k_cpqr.
+// LDS: norms, reference norms, column map and recompute list (24 B per
+// column), F (16 nb B per column), y and V(k, :) (nb entries each), then a
+// region holding v (m entries, when it fits; else v is read from A), the
+// panel-end chunk of V (64 nb entries) and, at the end, R's top rows.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(HBI_ID_THREADS) void k_cpqr_blocked(const IdBlock *blks,
+                                                                  const int32_t *sel, double tol,
+                                                                  int32_t *rank_out, int nmax,
+                                                                  int nb, int vcap, int rcap) {
+  extern __shared__ double lds_bq[];
+  constexpr int NW = HBI_ID_THREADS / 64;
+  constexpr double kTol3z = 1.4901161193847656e-08;   // sqrt(2^-52)
+  __shared__ double red_v[NW], red_s[NW];
+  __shared__ int red_q[NW], red_c[NW];
+  __shared__ double2 sh_alpha;
+  __shared__ int sh_nflag;
+
+  const int blk = sel[blockIdx.x];
+  const IdBlock B = blks[blk];
+  const int m = B.m, n = B.n;
+  double *nrm2 = lds_bq;
+  double *nref = nrm2 + nmax;
+  int *colmap = (int *)(nref + nmax);
+  int *flist = colmap + nmax;
+  double2 *F = (double2 *)(lds_bq + ((3 * nmax + 1) & ~1));   // nmax x nb, F(j, l) at F[j + l nmax]
+  double2 *yv = F + (int64_t)nmax * nb;
+  double2 *vr = yv + nb;
+  double2 *reg = vr + nb;                         // v / V chunk / R's top rows
+  const bool vlds = m <= vcap;
+  double2 *A = B.A;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  // exact initial norms; each wave reports its best candidate
+  {
+    double bv = -1.0;
+    int bq = n;
+    for (int j = wave; j < n; j += NW) {
+      const double2 *a = A + (int64_t)j * m;
+      double s = 0.0;
+      for (int r = lane; r < m; r += 64) s += a[r].x * a[r].x + a[r].y * a[r].y;
+      s = wave_sum(s);
+      if (lane == 0) { nrm2[j] = s; nref[j] = s; }
+      if (s > bv) { bv = s; bq = j; }
+    }
+    if (lane == 0) { red_v[wave] = bv; red_q[wave] = bq; red_c[wave] = bq < n ? bq : 0; }
+    for (int j = tid; j < n; j += HBI_ID_THREADS) colmap[j] = j;
+  }
+  __syncthreads();
+
+  const int kmax = m < n ? m : n;
+  int rank = kmax;
+  double r11 = 0.0;
+  int k0 = 0, i = 0;
+  for (int k = 0; k < kmax; ++k) {
+    // ---- pivot (every thread takes the same decision)
+    double best = red_v[0];
+    int q = red_q[0], p = red_c[0];
+    for (int w2 = 1; w2 < NW; ++w2)
+      if (red_v[w2] > best || (red_v[w2] == best && red_q[w2] < q)) {
+        best = red_v[w2]; q = red_q[w2]; p = red_c[w2];
+      }
+    if (q >= n) { rank = k > 0 ? k : 1; break; }
+    if (tid == 0) { colmap[q] = colmap[k]; colmap[k] = p; }
+    // ---- pivot column a_p(k:) = A(k:, p) - V(k:, :) F(p, :)^H, its norm
+    {
+      double sp = 0.0;
+      double2 *ap = A + (int64_t)p * m;
+      for (int r = k + tid; r < m; r += HBI_ID_THREADS) {
+        double2 a = ap[r];
+        for (int l = 0; l < i; ++l) {
+          const double2 vv = A[r + (int64_t)colmap[k0 + l] * m];
+          const double2 fl = F[p + l * nmax];
+          // a -= vv * conj(fl)
+          a.x -= vv.x * fl.x + vv.y * fl.y;
+          a.y -= vv.y * fl.x - vv.x * fl.y;
+        }
+        ap[r] = a;
+        if (r == k) sh_alpha = a;
+        else sp += a.x * a.x + a.y * a.y;
+      }
+      sp = wave_sum(sp);
+      if (lane == 0) red_s[wave] = sp;
+    }
+    __syncthreads();
+    // ---- reflector (every thread), v
+    double s = 0.0;
+    for (int w2 = 0; w2 < NW; ++w2) s += red_s[w2];
+    const double2 al = sh_alpha;
+    const double nrm = sqrt(al.x * al.x + al.y * al.y + s);
+    if (k == 0) r11 = nrm;
+    if (nrm == 0.0 || (k > 0 && nrm <= tol * r11)) { rank = k > 0 ? k : 1; break; }
+    const double beta = al.x >= 0.0 ? -nrm : nrm;
+    const double2 tau = double2{(beta - al.x) / beta, -al.y / beta};
+    const double dr = al.x - beta, di = al.y, dd = dr * dr + di * di;
+    const double2 scale = double2{dr / dd, -di / dd};
+    {
+      double2 *ap = A + (int64_t)p * m;
+      for (int r = k + 1 + tid; r < m; r += HBI_ID_THREADS) {
+        const double2 v = cmul(ap[r], scale);
+        ap[r] = v;
+        if (vlds) reg[r] = v;
+      }
+      if (tid == 0) {
+        ap[k] = double2{beta, 0.0};
+        if (vlds) reg[k] = double2{1.0, 0.0};
+        sh_nflag = 0;
+      }
+      if (tid < i) vr[tid] = A[k + (int64_t)colmap[k0 + tid] * m];
+    }
+    __syncthreads();
+    // ---- g = A(k:, T)^H v into F(:, i); y = V(k:, :)^H v
+    {
+      const double2 *pv = A + (int64_t)p * m;
+      const int items = i + (n - k - 1);
+      for (int it = wave; it < items; it += NW) {
+        const int col = it < i ? colmap[k0 + it] : colmap[k + 1 + (it - i)];
+        const double2 *a = A + (int64_t)col * m;
+        double2 d = double2{0.0, 0.0};
+        for (int r = k + lane; r < m; r += 64) {
+          const double2 v = r == k ? double2{1.0, 0.0} : (vlds ? reg[r] : pv[r]);
+          cfmac(d, a[r], v);   // d += conj(a) v
+        }
+        d.x = wave_sum(d.x);
+        d.y = wave_sum(d.y);
+        if (lane == 0) {
+          if (it < i) yv[it] = d;
+          else F[col + i * nmax] = d;
+        }
+      }
+    }
+    __syncthreads();
+    // ---- f, R(k, T), norm downdate (one thread per trailing column)
+    for (int qq = k + 1 + tid; qq < n; qq += HBI_ID_THREADS) {
+      const int j = colmap[qq];
+      const double2 g = F[j + i * nmax];
+      double2 fy = double2{0.0, 0.0};
+      double2 vf = double2{0.0, 0.0};
+      for (int l = 0; l < i; ++l) {
+        const double2 fl = F[j + l * nmax];
+        const double2 yl = yv[l], vl = vr[l];
+        fy.x += fl.x * yl.x - fl.y * yl.y;
+        fy.y += fl.x * yl.y + fl.y * yl.x;
+        vf.x += vl.x * fl.x + vl.y * fl.y;   // vl * conj(fl)
+        vf.y += vl.y * fl.x - vl.x * fl.y;
+      }
+      const double2 f = cmul(tau, double2{g.x - fy.x, g.y - fy.y});
+      F[j + i * nmax] = f;
+      double2 *akj = A + k + (int64_t)j * m;
+      const double2 a0 = *akj;
+      const double2 rk = double2{a0.x - vf.x - f.x, a0.y - vf.y + f.y};
+      *akj = rk;
+      const double nw = nrm2[j] - (rk.x * rk.x + rk.y * rk.y);
+      if (nw <= kTol3z * nref[j]) {
+        flist[atomicAdd(&sh_nflag, 1)] = j;
+      } else {
+        nrm2[j] = nw;
+      }
+    }
+    ++i;
+    const bool flush = i == nb && k + 1 < kmax;
+    __syncthreads();
+    if (flush) {
+      // ---- panel end: A(k+1:, T) -= V F(T, :)^H, exact norms
+      for (int qq = k + 1 + tid; qq < n; qq += HBI_ID_THREADS) nref[colmap[qq]] = 0.0;
+      __syncthreads();
+      for (int r0 = k + 1; r0 < m; r0 += 64) {
+        __syncthreads();
+        if (tid < 64 * nb) {
+          const int rr = tid / nb, l = tid % nb, r = r0 + rr;
+          reg[tid] = r < m ? A[r + (int64_t)colmap[k0 + l] * m] : double2{0.0, 0.0};
+        }
+        __syncthreads();
+        const int r = r0 + lane;
+        for (int qq = k + 1 + wave; qq < n; qq += NW) {
+          const int j = colmap[qq];
+          double sq = 0.0;
+          if (r < m) {
+            double2 a = A[r + (int64_t)j * m];
+            for (int l = 0; l < nb; ++l) {
+              const double2 vv = reg[lane * nb + l];
+              const double2 fl = F[j + l * nmax];
+              a.x -= vv.x * fl.x + vv.y * fl.y;
+              a.y -= vv.y * fl.x - vv.x * fl.y;
+            }
+            A[r + (int64_t)j * m] = a;
+            sq = a.x * a.x + a.y * a.y;
+          }
+          sq = wave_sum(sq);
+          if (lane == 0) nref[j] += sq;
+        }
+      }
+      // the same wave owns column j in the loop above and below
+      for (int qq = k + 1 + wave; qq < n; qq += NW)
+        if (lane == 0) nrm2[colmap[qq]] = nref[colmap[qq]];
+      k0 = k + 1;
+      i = 0;
+    } else if (sh_nflag > 0) {
+      // ---- exact norms of the flagged columns: rows k+1.., all panel terms
+      const int nf = sh_nflag;
+      for (int t = wave; t < nf; t += NW) {
+        const int j = flist[t];
+        double sq = 0.0;
+        for (int r = k + 1 + lane; r < m; r += 64) {
+          double2 a = A[r + (int64_t)j * m];
+          for (int l = 0; l < i; ++l) {
+            const double2 vv = A[r + (int64_t)colmap[k0 + l] * m];
+            const double2 fl = F[j + l * nmax];
+            a.x -= vv.x * fl.x + vv.y * fl.y;
+            a.y -= vv.y * fl.x - vv.x * fl.y;
+          }
+          sq += a.x * a.x + a.y * a.y;
+        }
+        sq = wave_sum(sq);
+        if (lane == 0) { nrm2[j] = sq; nref[j] = sq; }
+      }
+      __syncthreads();
+    }
+    // ---- next candidates (the flush owner of column j reads it back itself)
+    {
+      double bv = -1.0;
+      int bq = n, bc = 0;
+      for (int qq = k + 1 + wave; qq < n; qq += NW) {
+        const int j = colmap[qq];
+        const double v = nrm2[j];
+        if (v > bv) { bv = v; bq = qq; bc = j; }
+      }
+      if (lane == 0) { red_v[wave] = bv; red_q[wave] = bq; red_c[wave] = bc; }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+
+  // ---- X = [I, R11^-1 R12] Pi^T from the top rows of R (in A, pivot order)
+  const int r = rank;
+  const bool zero = !(r11 > 0.0);
+  double2 *X = B.X;
+  for (int idx = tid; idx < r * r; idx += HBI_ID_THREADS) {
+    const int qq = idx / r, ii = idx % r;
+    X[ii + (int64_t)colmap[qq] * r] = double2{ii == qq ? 1.0 : 0.0, 0.0};
+  }
+  for (int qq = tid; qq < r; qq += HBI_ID_THREADS) B.piv[qq] = colmap[qq];
+  double2 *Rs = F;   // F, y, V(k, :) and the region are free now
+  if ((int64_t)r * n <= rcap) {
+    for (int idx = tid; idx < r * n; idx += HBI_ID_THREADS) {
+      const int qq = idx / r, ii = idx % r;
+      Rs[idx] = A[ii + (int64_t)colmap[qq] * m];
+    }
+    __syncthreads();
+    const double2 *Rc = Rs;
+    auto Rat = [Rc, r](int a, int b) { return Rc[a + b * r]; };
+    for (int qq = r + tid; qq < n; qq += HBI_ID_THREADS) solve_upper(Rat, Rs + qq * r, r, zero);
+    __syncthreads();
+    for (int idx = tid; idx < r * (n - r); idx += HBI_ID_THREADS) {
+      const int qq = r + idx / r, ii = idx % r;
+      X[ii + (int64_t)colmap[qq] * r] = Rs[ii + qq * r];
+    }
+  } else {
+    auto Rat = [A, colmap, m](int a, int b) { return A[a + (int64_t)colmap[b] * m]; };
+    for (int qq = r + tid; qq < n; qq += HBI_ID_THREADS) {
+      const int col = colmap[qq];
+      double2 *xo = X + (int64_t)col * r;
+      for (int ii = 0; ii < r; ++ii) xo[ii] = A[ii + (int64_t)col * m];
+      solve_upper(Rat, xo, r, zero);
+    }
+  }
+  if (tid == 0) rank_out[blk] = r;
+}
+
 // Contiguous copies src[b] -> dst[b] of cnt[b] complex values.
 __global__ void k_copy_blocks(const CopyDesc *d, int64_t nb) {
   const int64_t b = blockIdx.x;
@@ -1309,7 +1596,7 @@ hipError_t launch_cpqr(const IdBlock *blks, const int32_t *sel, int64_t nb, int 
   if (e != hipSuccess) return e;
   // norms + column map, then the region for v (m entries) and R's top rows
   // (r n <= min(m, n) n entries), as far as the device's LDS allows
-  const size_t head = sizeof(double) * ((size_t)nmax + (nmax + 1) / 2 + 1);
+  const size_t head = sizeof(double) * (((size_t)nmax + (nmax + 1) / 2 + 2) & ~(size_t)1);
   const size_t want = std::max<size_t>((size_t)mmax, (size_t)std::min(mmax, nmax) * nmax);
   const size_t avail = (size_t)ldsmax > head + 1024 ? ((size_t)ldsmax - head - 1024) / 16 : 0;
   const int cap = (int)std::min(want, avail);
@@ -1321,6 +1608,38 @@ hipError_t launch_cpqr(const IdBlock *blks, const int32_t *sel, int64_t nb, int 
   }
   hipLaunchKernelGGL(k_cpqr, dim3(nb), dim3(HBI_ID_THREADS), lds, st, blks, sel, tol, rank, nmax,
                      cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_cpqr_blocked(const IdBlock *blks, const int32_t *sel, int64_t nb, int nmax,
+                               int mmax, double tol, int32_t *rank, hipStream_t st) {
+  if (nb == 0) return hipSuccess;
+  int ldsmax = 65536;
+  hipError_t e = lds_limit(&ldsmax);
+  if (e != hipSuccess) return e;
+  const size_t avail = ldsmax > 4096 ? (size_t)ldsmax - 4096 : 0;   // static LDS and slack
+  const size_t head = sizeof(double) * ((3 * (size_t)nmax + 1) & ~(size_t)1);
+  auto bytes = [&](int pw, size_t regcap) {
+    return head + sizeof(double2) * ((size_t)nmax * pw + 2 * pw + regcap);
+  };
+  int pw = 16;
+  while (pw >= 2 && bytes(pw, 64 * (size_t)pw) > avail) pw /= 2;
+  if (pw < 2) return launch_cpqr(blks, sel, nb, nmax, mmax, tol, rank, st);
+  size_t regcap = 64 * (size_t)pw;
+  int vcap = 0;
+  if (bytes(pw, std::max(regcap, (size_t)mmax)) <= avail) {
+    regcap = std::max(regcap, (size_t)mmax);
+    vcap = (int)regcap;
+  }
+  const int rcap = (int)((size_t)nmax * pw + 2 * pw + regcap);
+  const size_t lds = bytes(pw, regcap);
+  if (lds > 65536) {
+    e = hipFuncSetAttribute((const void *)k_cpqr_blocked,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_cpqr_blocked, dim3(nb), dim3(HBI_ID_THREADS), lds, st, blks, sel, tol,
+                     rank, nmax, pw, vcap, rcap);
   return hipGetLastError();
 }
 

@@ -207,7 +207,16 @@ struct hbi_ctx {
   int leaf() const { return opts.leaf_size > 0 ? std::min(opts.leaf_size, HBI_MAX_LEAF) : 64; }
   double radius() const { return opts.neighbor_radius > 0 ? opts.neighbor_radius : (dim == 2 ? 10.0 : 3.0); }
   int band() const { return opts.band_width > 0 ? opts.band_width : 2; }
-  int64_t wsbytes() const { return opts.workspace_bytes > 0 ? opts.workspace_bytes : (int64_t)2 << 30; }
+  // batch workspace budget: the option, else an eighth of the free device
+  // memory within [2 GiB, 32 GiB] (more blocks per batch keep more CUs busy
+  // while the largest decompositions run)
+  int64_t wsbytes() const {
+    if (opts.workspace_bytes > 0) return opts.workspace_bytes;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) { (void)hipGetLastError(); fr = 0; }
+    const int64_t lo = (int64_t)2 << 30, hi = (int64_t)32 << 30;
+    return std::min(hi, std::max(lo, (int64_t)(fr / 8)));
+  }
   void drop_factors() {
     F.release(); Felems = 0; leaves_d.release(); vd_d.release(); kd_d.release();
     units_d.clear(); items_d.clear(); items_adj_d.clear(); plan = ApplyPlan();
@@ -297,12 +306,17 @@ struct BlockOut {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// HBI_ID_KERNEL=global sends every interpolative decomposition to the
-// global-memory pivoted QR (for comparisons); by default blocks of at most
-// HBI_ID_ONCHIP_NMAX columns are decomposed on chip.
-static bool id_onchip_enabled() {
+// Which kernels decompose the blocks (HBI_ID_KERNEL, for comparisons):
+// by default blocks of at most HBI_ID_ONCHIP_NMAX columns on chip and wider
+// ones by the global-memory pivoted QR (k_cpqr); "global" sends every block
+// to k_cpqr, "blocked" every block to its panel form (k_cpqr_blocked, which
+// measured slower than k_cpqr on the 2D and 3D workloads).
+enum IdKernels { ID_AUTO = 0, ID_GLOBAL = 1, ID_BLOCKED = 2 };
+static IdKernels id_kernels() {
   const char *e = std::getenv("HBI_ID_KERNEL");
-  return !(e && std::strcmp(e, "global") == 0);
+  if (e && std::strcmp(e, "global") == 0) return ID_GLOBAL;
+  if (e && std::strcmp(e, "blocked") == 0) return ID_BLOCKED;
+  return ID_AUTO;
 }
 
 // entry tile shape (rows of one table box x columns), as k_entries takes it
@@ -339,7 +353,6 @@ struct Batcher {
            CB &&on_batch, bool pairs = false) {
     const int64_t nb = (int64_t)blocks.size();
     const size_t budget = (size_t)c->wsbytes();
-    HBI_HIP(c->ws.reserve(budget));
     std::vector<std::vector<int32_t>> slots(nb);
     std::vector<int> nslot(nb);
     parallel_for(nb, [&](int64_t a, int64_t b) {
@@ -362,6 +375,7 @@ struct Batcher {
         used += need;
         i1 = std::min<int64_t>(nb, i1 + step);
       }
+      HBI_HIP(c->ws.reserve(used));   // grow-only; the previous batch has finished
       run_batch(blocks, slots, nslot, i0, i1, id, tol, outs);
       if (id) on_batch(i0, i1 - i0);
       i0 = i1;
@@ -456,12 +470,12 @@ struct Batcher {
     std::vector<int32_t> sel;
     int64_t nsel[3] = {0, 0, 0};
     int nmax_g[3] = {1, 1, 1}, mmax_w = 1;
+    const IdKernels idk = id ? id_kernels() : ID_AUTO;
     if (id) {
-      const bool onchip = id_onchip_enabled();
       std::vector<int32_t> g[3];
       for (int64_t q = 0; q < nb; ++q) {
         const int n = ib[q].n;
-        const int k = !onchip || n > HBI_ID_ONCHIP_NMAX ? 2 : 0;
+        const int k = idk != ID_AUTO || n > HBI_ID_ONCHIP_NMAX ? 2 : 0;
         g[k].push_back((int32_t)q);
         nmax_g[k] = std::max(nmax_g[k], n);
         if (k == 2) mmax_w = std::max(mmax_w, (int)ib[q].m);
@@ -503,8 +517,12 @@ struct Batcher {
       int32_t *rankd = (int32_t *)(ix + o_rank);
       HBI_HIP(launch_id_onchip(ibd, seld, nsel[0], nmax_g[0], tol, rankd, c->stream));
       HBI_HIP(launch_id_onchip(ibd, seld + nsel[0], nsel[1], nmax_g[1], tol, rankd, c->stream));
-      HBI_HIP(launch_cpqr(ibd, seld + nsel[0] + nsel[1], nsel[2], nmax_g[2], mmax_w, tol, rankd,
-                          c->stream));
+      if (idk == ID_BLOCKED)
+        HBI_HIP(launch_cpqr_blocked(ibd, seld + nsel[0] + nsel[1], nsel[2], nmax_g[2], mmax_w,
+                                    tol, rankd, c->stream));
+      else
+        HBI_HIP(launch_cpqr(ibd, seld + nsel[0] + nsel[1], nsel[2], nmax_g[2], mmax_w, tol,
+                            rankd, c->stream));
       std::vector<int32_t> rank(nb), piv(po);
       HBI_HIP(hipMemcpyAsync(rank.data(), ix + o_rank, nb * 4, hipMemcpyDeviceToHost, c->stream));
       if (po) HBI_HIP(hipMemcpyAsync(piv.data(), ix + o_piv, po * 4, hipMemcpyDeviceToHost, c->stream));

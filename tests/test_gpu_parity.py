@@ -261,14 +261,15 @@ def test_3d_apply_sampled_rows(torch_mod):
 
 
 @pytest.mark.parametrize("prec,tol,bound", [("f64", 1e-7, 1e-6), ("f32", 1e-5, 1e-4)])
-def test_id_onchip_matches_global(torch_mod, monkeypatch, prec, tol, bound):
-    """Blocks of at most 64 candidate columns are decomposed on chip (pivoted
-    QR of the triangular factor of the block); HBI_ID_KERNEL=global sends them
-    to the global-memory pivoted QR of the block itself.  The second build
-    also turns the per-cell column-side cache off (HBI_HC_CACHE_BYTES=0), so
-    entries come from the per-block column side.  Both operators agree with
-    the oracle and with each other to the compression tolerance, with nearly
-    the same ranks."""
+def test_id_kernels_agree(torch_mod, monkeypatch, prec, tol, bound):
+    """By default blocks of at most 64 candidate columns are decomposed on
+    chip (pivoted QR of the triangular factor of the block) and wider ones by
+    the global-memory pivoted QR; HBI_ID_KERNEL=global sends every block to
+    the global-memory kernel and =blocked to its panel (deferred-update) form.  The
+    last two builds also turn the per-cell column-side cache off
+    (HBI_HC_CACHE_BYTES=0), so entries come from the per-block column side.
+    All three operators agree with the oracle and with each other to the
+    compression tolerance, with nearly the same ranks."""
     torch = torch_mod
     prob = hb_inputs.configs.c2(128)
     dt = torch.complex128 if prec == "f64" else torch.complex64
@@ -276,9 +277,9 @@ def test_id_onchip_matches_global(torch_mod, monkeypatch, prec, tol, bound):
     rows = np.random.default_rng(6).choice(prob.Nv, 64, replace=False)
     ref = oracle.apply(prob, s, rows)
     out = {}
-    for kind in ("onchip", "global"):
-        if kind == "global":
-            monkeypatch.setenv("HBI_ID_KERNEL", "global")
+    for kind in ("auto", "global", "blocked"):
+        if kind != "auto":
+            monkeypatch.setenv("HBI_ID_KERNEL", kind)
             monkeypatch.setenv("HBI_HC_CACHE_BYTES", "0")
         say(f"id kernel {kind} {prec} tol {tol}")
         op = make_op(prob, tol=tol, prec=prec)
@@ -288,11 +289,31 @@ def test_id_onchip_matches_global(torch_mod, monkeypatch, prec, tol, bound):
         say(f"{kind} rel err {e:.3e} rank mean {out[kind][1]['rank_mean']:.3f}")
         assert e < bound, (kind, e)
         op.close()
-    d = rel(out["onchip"][0], out["global"][0])
-    say(f"onchip vs global {d:.3e}")
-    assert d < bound, d
-    r1, r2 = out["onchip"][1]["rank_mean"], out["global"][1]["rank_mean"]
-    assert abs(r1 - r2) <= 0.02 * r2, (r1, r2)
+    for kind in ("global", "blocked"):
+        d = rel(out["auto"][0], out[kind][0])
+        say(f"auto vs {kind} {d:.3e}")
+        assert d < bound, (kind, d)
+        r1, r2 = out["auto"][1]["rank_mean"], out[kind][1]["rank_mean"]
+        assert abs(r1 - r2) <= 0.02 * r2, (kind, r1, r2)
+
+
+def test_small_build_workspace_many_batches(torch_mod):
+    """A 4 MiB build workspace splits every level into many batches (sibling
+    pairs kept together); the operator is the same as with the default
+    workspace, block for block."""
+    torch = torch_mod
+    prob = hb_inputs.configs.c2(96)
+    s = to_dev(torch, hb_inputs.complex_normal(prob.Nv, [12, 1]))
+    say("build workspace 4 MiB vs default")
+    u = {}
+    for ws in (None, 4 << 20):
+        op = make_op(prob, tol=1e-7, workspace_bytes=ws)
+        u[ws] = op.apply(s).cpu().numpy()
+        info = op.info()
+        op.close()
+    d = rel(u[4 << 20], u[None])
+    say(f"small vs default workspace {d:.3e}, nnz {info['nnz_total']}")
+    assert d < 1e-13, d
 
 
 def test_autograd_gradient(torch_mod):
