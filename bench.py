@@ -7,7 +7,9 @@ nodes), one seeded complex N(0,1) right-hand side.
 
 Per run:
   1. FP64 build at tol 1e-7 and FP32 build (FP64 QR/ID, factors rounded to
-     complex64) at tol 1e-6; build seconds are wall time of hbi_build.
+     complex64) at tol 1e-5, the loosest power of ten whose measured error
+     stays an order of magnitude inside the metric's 1e-4 bound; build
+     seconds are wall time of hbi_build.
   2. Parity: relative L2 error of each apply against the FP64 CPU oracle on
      seeded sampled rows.
   3. Timed applies u = K (h^d s) with the input resident in HBM: W warm-up
@@ -41,7 +43,7 @@ def measured_traffic(kernel):
     summary, or None when the kernel source changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_wstage_f32_bump1024_traffic.json")
-    src = os.path.join(ROOT, "paper_2210_02698_amd", "csrc", "hbi_kernels.hip")
+    src = os.path.join(ROOT, "paper_2210_02698_amd", "csrc", "hbi_apply.hip")
     try:
         rec = json.load(open(path))
         cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
@@ -63,7 +65,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n-side", type=int, default=1024)
     ap.add_argument("--tol64", type=float, default=1e-7)
-    ap.add_argument("--tol32", type=float, default=1e-6)
+    ap.add_argument("--tol32", type=float, default=None,
+                    help="FP32 build tolerance [1e-5 for the 2D workloads, 1e-6 for 3D]")
     ap.add_argument("--chi", type=float, default=0.0, help="proxy oversampling (0 = library default)")
     ap.add_argument("--oracle-rows", type=int, default=24)
     ap.add_argument("--no-fp64", action="store_true")
@@ -80,6 +83,8 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
+    if args.tol32 is None:
+        args.tol32 = 1e-6 if args.workload == "3d" else 1e-5
     if args.workload != "bump":
         return run_multi(args)
 
@@ -227,8 +232,9 @@ MFMA_F32_PEAK_TFLOPS = 157.3
 
 
 def run_multi(args):
-    """Many right-hand sides: the batched constant-gradient workload or the
-    3D sinusoid, FP32 factors (tol 1e-6), hbi_apply_batched under its graph."""
+    """Many right-hand sides: the batched constant-gradient workload (FP32
+    factors at tol 1e-5) or the 3D sinusoid (tol 1e-6), hbi_apply_batched
+    under its graph."""
     import numpy as np
     import torch
 

@@ -1,10 +1,11 @@
-// HIP kernels of the HB integrator for gfx950 (wave64).
+// HIP kernels of the HB integrator build for gfx950 (wave64).
 //
-//   hb_entry  k_cell_setup, k_self_terms, k_colside, k_entries
-//   bf_build  k_cpqr (column-pivoted Householder QR + interpolation matrix),
-//             k_copy_blocks
-//   bf_apply  k_vstage, k_wstage, k_final           (u = K h^d s)
-//   adjoint   k_final_adj, k_wstage_adj, k_vstage_adj (u = h^d K^H s)
+//   hb_entry  k_cell_setup, k_self_terms, k_colside, k_colside_cells,
+//             k_entries
+//   bf_build  k_id_onchip, k_cpqr, k_cpqr_blocked (column-pivoted Householder
+//             QR + interpolation matrix), k_copy_blocks, k_pack_pairs,
+//             k_to_f32
+// The apply kernels are in hbi_apply.hip, the multi-RHS ones in hbi_multi.hip.
 #include "hbi_kernels.h"
 #include "hbi_device.h"
 #include "hbi_hankel.h"
@@ -1255,253 +1256,6 @@ __global__ void k_to_f32(const double2 *src, float2 *dst, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// bf_apply (eq. butterfly_mat): V^0 per column leaf, transfer stages W^k,
-// skeleton factor K^L plus the dense diagonal leaf per row leaf.  Gathers
-// only: every output element is written by exactly one lane.
-// ---------------------------------------------------------------------------
-// y[0..R) = M x for a column-major R x c matrix M streamed by one wave.
-// Lane l works on row l % R of column group l / R (G = 64 / R groups when
-// R <= 32), so every load instruction of the wave reads one contiguous span
-// of G*R entries; partial sums of a row are combined with lane permutes in a
-// fixed order.  For R > 32 lanes take rows (64 at a time) and columns are
-// walked in order.  Returns the result for row `lane` (lane < R, R <= 64) or
-// writes through `store` for larger R.
-template <typename C, typename XF, typename ST>
-__device__ __forceinline__ void wave_gemv(const C *__restrict__ M, int Rt, int c, int lane,
-                                          XF xat, ST store, int r0 = 0, int r1 = 1 << 30) {
-  if (Rt <= 32) {
-    const int G = 64 / Rt;
-    const int grp = lane / Rt;
-    const bool act = grp < G;
-    C acc{0, 0};
-    if (act) {
-      const C *p = M + lane;
-      const int step = G * Rt;
-      int col = grp;
-#pragma unroll 16
-      for (; col < c; col += G, p += step) cfma(acc, *p, xat(col));
-    }
-    // combine the G partial sums of each row (lanes row, row+Rt, ...)
-    C tot = acc;
-    for (int g = 1; g < G; ++g) {
-      const int src = lane + g * Rt;
-      const auto re = __shfl(acc.x, src < 64 ? src : lane, 64);
-      const auto im = __shfl(acc.y, src < 64 ? src : lane, 64);
-      if (src < 64) { tot.x += re; tot.y += im; }
-    }
-    if (lane < Rt) store(lane, tot);
-  } else {
-    const int re_ = r1 < Rt ? r1 : Rt;
-    for (int rb = r0; rb < re_; rb += 64) {
-      const int row = rb + lane;
-      if (row < re_) {
-        C acc{0, 0};
-        const C *p = M + row;
-#pragma unroll 16
-        for (int col = 0; col < c; ++col, p += Rt) cfma(acc, *p, xat(col));
-        store(row, acc);
-      }
-    }
-  }
-}
-
-// One workgroup (4 waves) per leaf; wave w handles the HODBF levels
-// l = w, w + 4, ... of the leaf.
-template <typename R>
-__global__ __launch_bounds__(256) void k_vstage(const cplx_t<R> *s,
-                                                const LeafInfo *leaves,
-                                                const int32_t *perm,
-                                                const VDesc *vd, int Lv,
-                                                const cplx_t<R> *F,
-                                                cplx_t<R> *z, R hd) {
-  using C = cplx_t<R>;
-  __shared__ C xs[HBI_MAX_LEAF];
-  const int g = blockIdx.x;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const LeafInfo lf = leaves[g];
-  if (threadIdx.x < lf.size) {
-    const C v = s[perm[lf.start + threadIdx.x]];
-    xs[threadIdx.x] = C{v.x * hd, v.y * hd};
-  }
-  __syncthreads();
-  for (int l = wave; l < Lv; l += 4) {
-    const VDesc d = vd[(int64_t)g * Lv + l];
-    C *zo = z + d.zout;
-    wave_gemv<C>(F + d.foff, d.r, lf.size, lane, [&](int col) { return xs[col]; },
-                 [&](int row, C v) { zo[row] = v; });
-  }
-}
-
-// One wave per work item: rows [r0, r0 + 64) of a transfer unit (whole unit
-// when it has <= 64 rows).  Items are ordered by decreasing cost.
-template <typename R>
-__global__ __launch_bounds__(256) void k_wstage(const WUnit *units, const WItem *items,
-                                                int64_t nitems, const cplx_t<R> *F,
-                                                cplx_t<R> *z) {
-  using C = cplx_t<R>;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
-  if (it >= nitems) return;
-  const WItem W = items[it];
-  const WUnit U = units[W.unit];
-  const C *zin = z + U.zin;
-  C *za = z + U.zouta;
-  C *zb = z + U.zoutb;
-  const int ra = U.ra;
-  wave_gemv<C>(F + U.foff, ra + U.rb, U.c, lane, [&](int col) { return zin[col]; },
-               [&](int row, C v) {
-                 if (row < ra) za[row] = v; else zb[row - ra] = v;
-               },
-               W.off, W.off + 64);
-}
-
-// One workgroup (4 waves) per row leaf: wave w accumulates the K^L blocks
-// of levels l = w, w + 4, ... (wave 0 also the dense block); the four
-// partial results are added in a fixed order.
-template <typename R>
-__global__ __launch_bounds__(256) void k_final(const cplx_t<R> *s,
-                                               const LeafInfo *leaves,
-                                               const int32_t *perm,
-                                               const KDesc *kd, int Lv,
-                                               const cplx_t<R> *F,
-                                               const cplx_t<R> *z,
-                                               cplx_t<R> *u, R hd) {
-  using C = cplx_t<R>;
-  __shared__ C xs[HBI_MAX_LEAF];
-  __shared__ C part[4][HBI_MAX_LEAF];
-  const int g = blockIdx.x;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const LeafInfo lf = leaves[g];
-  const int sz = lf.size;
-  if (threadIdx.x < sz) {
-    const C v = s[perm[lf.start + threadIdx.x]];
-    xs[threadIdx.x] = C{v.x * hd, v.y * hd};
-  }
-  __syncthreads();
-  C acc{0, 0};
-  if (lane < sz) {
-    if (wave == 0) {
-      const C *Dm = F + lf.dense_off + lane;
-#pragma unroll 16
-      for (int col = 0; col < sz; ++col) cfma(acc, Dm[(int64_t)col * sz], xs[col]);
-    }
-    for (int l = wave; l < Lv; l += 4) {
-      const KDesc d = kd[(int64_t)g * Lv + l];
-      const C *K = F + d.foff + lane;
-      const C *zz = z + d.zin;
-#pragma unroll 16
-      for (int q = 0; q < d.r; ++q) cfma(acc, K[(int64_t)q * sz], zz[q]);
-    }
-  }
-  part[wave][lane] = acc;
-  __syncthreads();
-  if (threadIdx.x < sz) {
-    C t = part[0][threadIdx.x];
-    for (int w = 1; w < 4; ++w) { t.x += part[w][threadIdx.x].x; t.y += part[w][threadIdx.x].y; }
-    u[perm[lf.start + threadIdx.x]] = t;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Adjoint: the same factors read as conjugate transposes, stages reversed.
-// ---------------------------------------------------------------------------
-template <typename R>
-__global__ __launch_bounds__(256) void k_final_adj(const cplx_t<R> *y,
-                                                   const LeafInfo *leaves,
-                                                   const int32_t *perm,
-                                                   const KDesc *kd, int Lv,
-                                                   const cplx_t<R> *F,
-                                                   cplx_t<R> *z) {
-  using C = cplx_t<R>;
-  __shared__ C ys[HBI_MAX_LEAF];
-  const int g = blockIdx.x;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const LeafInfo lf = leaves[g];
-  const int sz = lf.size;
-  if (threadIdx.x < sz) ys[threadIdx.x] = y[perm[lf.start + threadIdx.x]];
-  __syncthreads();
-  for (int l = wave; l < Lv; l += 4) {
-    const KDesc d = kd[(int64_t)g * Lv + l];
-    if (lane < d.r) {
-      const C *K = F + d.foff + (int64_t)lane * sz;
-      C acc{0, 0};
-      for (int row = 0; row < sz; ++row) cfmac(acc, K[row], ys[row]);
-      z[d.zin + lane] = acc;
-    }
-  }
-}
-
-template <typename R>
-__global__ __launch_bounds__(256) void k_wstage_adj(const WUnit *units, const WItem *items,
-                                                    int64_t nitems, const cplx_t<R> *F,
-                                                    cplx_t<R> *z) {
-  using C = cplx_t<R>;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
-  if (it >= nitems) return;
-  const WItem W = items[it];
-  const WUnit U = units[W.unit];
-  const int ra = U.ra, Rt = U.ra + U.rb;
-  const C *wa = z + U.zouta, *wb = z + U.zoutb;
-  const C *M = F + U.foff;
-  const int c1 = W.off + 64 < U.c ? W.off + 64 : U.c;
-  const int col = W.off + lane;
-  if (col < c1) {
-    C acc{0, 0};
-    const C *cm = M + (int64_t)col * Rt;
-    for (int i = 0; i < ra; ++i) cfmac(acc, cm[i], wa[i]);
-    for (int i = ra; i < Rt; ++i) cfmac(acc, cm[i], wb[i - ra]);
-    z[U.zin + col] = acc;
-  }
-}
-
-template <typename R>
-__global__ __launch_bounds__(256) void k_vstage_adj(const cplx_t<R> *y,
-                                                    const LeafInfo *leaves,
-                                                    const int32_t *perm,
-                                                    const VDesc *vd, int Lv,
-                                                    const cplx_t<R> *F,
-                                                    const cplx_t<R> *z,
-                                                    cplx_t<R> *u, R hd) {
-  using C = cplx_t<R>;
-  __shared__ C ys[HBI_MAX_LEAF];
-  __shared__ C part[4][HBI_MAX_LEAF];
-  const int g = blockIdx.x;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const LeafInfo lf = leaves[g];
-  const int sz = lf.size;
-  if (threadIdx.x < sz) ys[threadIdx.x] = y[perm[lf.start + threadIdx.x]];
-  __syncthreads();
-  C acc{0, 0};
-  if (lane < sz) {
-    if (wave == 0) {
-      // dense leaf: (D^H y)[col], column `lane` of D is contiguous
-      const C *Dc = F + lf.dense_off + (int64_t)lane * sz;
-      for (int row = 0; row < sz; ++row) cfmac(acc, Dc[row], ys[row]);
-    }
-    for (int l = wave; l < Lv; l += 4) {
-      const VDesc d = vd[(int64_t)g * Lv + l];
-      const C *V = F + d.foff + (int64_t)lane * d.r;
-      const C *w = z + d.zout;
-      for (int row = 0; row < d.r; ++row) cfmac(acc, V[row], w[row]);
-    }
-  }
-  part[wave][lane] = acc;
-  __syncthreads();
-  if (threadIdx.x < sz) {
-    C t = part[0][threadIdx.x];
-    for (int w = 1; w < 4; ++w) { t.x += part[w][threadIdx.x].x; t.y += part[w][threadIdx.x].y; }
-    u[perm[lf.start + threadIdx.x]] = C{t.x * hd, t.y * hd};
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Host-side launchers.
 // ---------------------------------------------------------------------------
 hipError_t launch_cell_setup(const DevProblem &P, const int32_t *perm, int64_t Nv,
@@ -1680,69 +1434,5 @@ hipError_t launch_to_f32(const double2 *src, float2 *dst, int64_t n, hipStream_t
   hipLaunchKernelGGL(k_to_f32, dim3((n + T - 1) / T), dim3(T), 0, st, src, dst, n);
   return hipGetLastError();
 }
-
-template <typename R>
-hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
-                        const void *F, R hd, bool adjoint, hipStream_t st, LaunchHook *hook) {
-  using C = cplx_t<R>;
-  const C *sc = (const C *)s;
-  C *uc = (C *)u;
-  C *zc = (C *)z;
-  const C *Fc = (const C *)F;
-  const double esz = sizeof(C);
-  auto pre = [&](const char *name, double elems, double idx) {
-    if (hook) hook->before(name, elems * esz + idx);
-  };
-  auto post = [&]() { if (hook) hook->after(); };
-  if (!adjoint) {
-    if (ap.Lv > 0) {
-      pre("k_vstage", ap.v_elems, ap.v_idx);
-      hipLaunchKernelGGL((k_vstage<R>), dim3(ap.nleaf), dim3(256), 0, st, sc, ap.leaves,
-                         ap.perm, ap.vd, ap.Lv, Fc, zc, hd);
-      post();
-    }
-    for (int k = 1; k <= ap.Lmax; ++k) {
-      const int64_t nu = ap.nunits[k];
-      if (nu == 0) continue;
-      const int64_t ni = ap.nitems[k];
-      pre("k_wstage", ap.w_elems[k], ap.w_idx[k]);
-      hipLaunchKernelGGL((k_wstage<R>), dim3((ni + 3) / 4), dim3(256), 0, st,
-                         ap.units[k], ap.items[k], ni, Fc, zc);
-      post();
-    }
-    pre("k_final", ap.f_elems, ap.f_idx);
-    hipLaunchKernelGGL((k_final<R>), dim3(ap.nleaf), dim3(256), 0, st, sc, ap.leaves,
-                       ap.perm, ap.kd, ap.Lv, Fc, (const C *)zc, uc, hd);
-    post();
-  } else {
-    // the adjoint streams the same factors; its K^L part is the K^L share of
-    // the final stage and its dense part rides with the V^H stage
-    if (ap.Lv > 0) {
-      pre("k_final_adj", ap.f_elems, ap.f_idx);
-      hipLaunchKernelGGL((k_final_adj<R>), dim3(ap.nleaf), dim3(256), 0, st, sc, ap.leaves,
-                         ap.perm, ap.kd, ap.Lv, Fc, zc);
-      post();
-    }
-    for (int k = ap.Lmax; k >= 1; --k) {
-      const int64_t nu = ap.nunits[k];
-      if (nu == 0) continue;
-      const int64_t ni = ap.nitems_adj[k];
-      pre("k_wstage_adj", ap.w_elems[k], ap.w_idx[k]);
-      hipLaunchKernelGGL((k_wstage_adj<R>), dim3((ni + 3) / 4), dim3(256), 0, st,
-                         ap.units[k], ap.items_adj[k], ni, Fc, zc);
-      post();
-    }
-    pre("k_vstage_adj", ap.v_elems, ap.v_idx);
-    hipLaunchKernelGGL((k_vstage_adj<R>), dim3(ap.nleaf), dim3(256), 0, st, sc, ap.leaves,
-                       ap.perm, ap.vd, ap.Lv, Fc, (const C *)zc, uc, hd);
-    post();
-  }
-  return hipGetLastError();
-}
-
-template hipError_t launch_apply<double>(const ApplyPlan &, const void *, void *, void *,
-                                         const void *, double, bool, hipStream_t, LaunchHook *);
-template hipError_t launch_apply<float>(const ApplyPlan &, const void *, void *, void *,
-                                        const void *, float, bool, hipStream_t, LaunchHook *);
 
 }  // namespace hbi

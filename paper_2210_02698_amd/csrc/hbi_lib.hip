@@ -876,8 +876,11 @@ void build_factors(hbi_ctx *c, double tol) {
     t_gpu += now_s() - tg;
   }
 
-  // final factor store (FP64 or rounded to FP32)
+  // final factor store (FP64 or rounded to FP32); the batch workspace is not
+  // needed any more
   const double tf = now_s();
+  c->ws.release();
+  c->idx_d.release();
   c->Felems = Fg;
   const size_t esz = c->prec == HBI_F64 ? sizeof(double2) : sizeof(float2);
   HBI_HIP(c->F.alloc(esz * std::max<int64_t>(Fg, 1)));
