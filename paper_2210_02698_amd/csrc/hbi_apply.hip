@@ -94,9 +94,8 @@ __global__ __launch_bounds__(256) void k_vstage(const cplx_t<R> *s,
 // (A persistent variant, each wave looping over items, measured slower: the
 // per-item wave-level fences serialise the streams.)
 template <typename R>
-__global__ __launch_bounds__(256) void k_wstage(const WUnit *units, const WItem *items,
-                                                int64_t nitems, const cplx_t<R> *F,
-                                                cplx_t<R> *z) {
+__global__ __launch_bounds__(256) void k_wstage(const WItem *items, int64_t nitems,
+                                                const cplx_t<R> *F, cplx_t<R> *z) {
   using C = cplx_t<R>;
   constexpr int WX = sizeof(R) == 4 ? 512 : 256;
   __shared__ C xs[4][WX];
@@ -104,12 +103,9 @@ __global__ __launch_bounds__(256) void k_wstage(const WUnit *units, const WItem 
   const int lane = threadIdx.x & 63;
   const int64_t it = (int64_t)blockIdx.x * 4 + wave;
   const bool active = it < nitems;
-  WUnit U{};
-  int off = 0;
+  WItem U{};
   if (active) {
-    const WItem W = items[it];
-    U = units[W.unit];
-    off = W.off;
+    U = items[it];
     if (U.c <= WX)
       for (int i = lane; i < U.c; i += 64) xs[wave][i] = z[U.zin + i];
   }
@@ -123,12 +119,12 @@ __global__ __launch_bounds__(256) void k_wstage(const WUnit *units, const WItem 
   };
   if (U.c <= WX) {
     const C *xw = xs[wave];
-    wave_gemv<C>(F + U.foff, ra + U.rb, U.c, lane, [&](int col) { return xw[col]; }, store, off,
-                 off + 64);
+    wave_gemv<C>(F + U.foff, ra + U.rb, U.c, lane, [&](int col) { return xw[col]; }, store, U.off,
+                 U.off + 64);
   } else {
     const C *zin = z + U.zin;
     wave_gemv<C>(F + U.foff, ra + U.rb, U.c, lane, [&](int col) { return zin[col]; }, store,
-                 off, off + 64);
+                 U.off, U.off + 64);
   }
 }
 
@@ -211,21 +207,19 @@ __global__ __launch_bounds__(256) void k_final_adj(const cplx_t<R> *y,
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_wstage_adj(const WUnit *units, const WItem *items,
-                                                    int64_t nitems, const cplx_t<R> *F,
-                                                    cplx_t<R> *z) {
+__global__ __launch_bounds__(256) void k_wstage_adj(const WItem *items, int64_t nitems,
+                                                    const cplx_t<R> *F, cplx_t<R> *z) {
   using C = cplx_t<R>;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t it = (int64_t)blockIdx.x * 4 + wave;
   if (it >= nitems) return;
-  const WItem W = items[it];
-  const WUnit U = units[W.unit];
+  const WItem U = items[it];
   const int ra = U.ra, Rt = U.ra + U.rb;
   const C *wa = z + U.zouta, *wb = z + U.zoutb;
   const C *M = F + U.foff;
-  const int c1 = W.off + 64 < U.c ? W.off + 64 : U.c;
-  const int col = W.off + lane;
+  const int c1 = U.off + 64 < U.c ? U.off + 64 : U.c;
+  const int col = U.off + lane;
   if (col < c1) {
     C acc{0, 0};
     const C *cm = M + (int64_t)col * Rt;
@@ -302,7 +296,7 @@ hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
       const int64_t ni = ap.nitems[k];
       pre("k_wstage", ap.w_elems[k], ap.w_idx[k]);
       hipLaunchKernelGGL((k_wstage<R>), dim3((ni + 3) / 4), dim3(256), 0, st,
-                         ap.units[k], ap.items[k], ni, Fc, zc);
+                         ap.items[k], ni, Fc, zc);
       post();
     }
     pre("k_final", ap.f_elems, ap.f_idx);
@@ -324,7 +318,7 @@ hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
       const int64_t ni = ap.nitems_adj[k];
       pre("k_wstage_adj", ap.w_elems[k], ap.w_idx[k]);
       hipLaunchKernelGGL((k_wstage_adj<R>), dim3((ni + 3) / 4), dim3(256), 0, st,
-                         ap.units[k], ap.items_adj[k], ni, Fc, zc);
+                         ap.items_adj[k], ni, Fc, zc);
       post();
     }
     pre("k_vstage_adj", ap.v_elems, ap.v_idx);

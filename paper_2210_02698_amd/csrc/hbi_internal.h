@@ -63,6 +63,10 @@ struct WUnit {
   int32_t ra, rb, c, pad;
 };
 // Work item of a transfer stage: rows (forward) or columns (adjoint)
-// [off, off + 64) of unit `unit`.
-struct WItem { int32_t unit; int32_t off; };
+// [off, off + 64) of a unit, with the unit's fields copied in so that a wave
+// needs one descriptor load.
+struct WItem {
+  int64_t foff, zin, zouta, zoutb;
+  int32_t ra, rb, c, off;
+};
 struct LeafInfo { int32_t start, size; int64_t dense_off; };

@@ -932,14 +932,17 @@ void build_factors(hbi_ctx *c, double tol) {
     for (int32_t u = 0; u < (int32_t)units[k].size(); ++u) {
       const WUnit &U = units[k][u];
       const int Rt = U.ra + U.rb;
+      auto item = [&U](int32_t off) {
+        return WItem{U.foff, U.zin, U.zouta, U.zoutb, U.ra, U.rb, U.c, off};
+      };
       if (Rt <= 64) {
-        fw.push_back({(int64_t)Rt * U.c, WItem{u, 0}});
+        fw.push_back({(int64_t)Rt * U.c, item(0)});
       } else {
         for (int r0 = 0; r0 < Rt; r0 += 64)
-          fw.push_back({(int64_t)std::min(64, Rt - r0) * U.c, WItem{u, r0}});
+          fw.push_back({(int64_t)std::min(64, Rt - r0) * U.c, item(r0)});
       }
       for (int c0 = 0; c0 < U.c; c0 += 64)
-        bw.push_back({(int64_t)std::min(64, U.c - c0) * Rt, WItem{u, c0}});
+        bw.push_back({(int64_t)std::min(64, U.c - c0) * Rt, item(c0)});
     }
     auto order = [](std::vector<std::pair<int64_t, WItem>> &v) {
       std::stable_sort(v.begin(), v.end(), [](const std::pair<int64_t, WItem> &a,
@@ -979,11 +982,11 @@ void build_factors(hbi_ctx *c, double tol) {
       }
     }
     ap.v_elems = ve; ap.v_idx = vi; ap.f_elems = fe; ap.f_idx = fi;
-    for (int k = 1; k <= Lmax; ++k)
-      for (const WUnit &U : units[k]) {
+    for (int k = 1; k <= Lmax; ++k) {
+      for (const WUnit &U : units[k])
         ap.w_elems[k] += (double)(U.ra + U.rb) * U.c + U.c + U.ra + U.rb;
-        ap.w_idx[k] += sizeof(WUnit);
-      }
+      ap.w_idx[k] = (double)sizeof(WItem) * ap.nitems[k];
+    }
   }
   HBI_HIP(c->z_d.alloc(esz * std::max<int64_t>(c->ztotal, 1)));
   c->t_final = now_s() - tf;
