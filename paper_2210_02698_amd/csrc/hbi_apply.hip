@@ -13,6 +13,33 @@ namespace hbi {
 // skeleton factor K^L plus the dense diagonal leaf per row leaf.  Gathers
 // only: every output element is written by exactly one lane.
 // ---------------------------------------------------------------------------
+// acc += sum_{i < n} op(m(i), x(i)) in order of i, with the loads issued B
+// at a time (predicated past n) before any of them is consumed: a plain
+// unrolled loop leaves a short trip count to a remainder loop that waits for
+// every load in turn.
+template <int B, bool CONJ, typename C, typename MF, typename XF>
+__device__ __forceinline__ void batched_dot(C &acc, int n, MF m, XF x) {
+  for (int b = 0; b < n; b += B) {
+    C mv[B], xv[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      if (b + u < n) {
+        mv[u] = m(b + u);
+        xv[u] = x(b + u);
+      } else {
+        mv[u] = C{0, 0};
+        xv[u] = C{0, 0};
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      if (CONJ) cfmac(acc, mv[u], xv[u]);
+      else cfma(acc, mv[u], xv[u]);
+    }
+  }
+}
+template <typename C> struct LoadBatch { static constexpr int value = sizeof(C) == 8 ? 16 : 8; };
+
 // y[0..R) = M x for a column-major R x c matrix M streamed by one wave.
 // Lane l works on row l % R of column group l / R (G = 64 / R groups when
 // R <= 32), so every load instruction of the wave reads one contiguous span
@@ -31,9 +58,10 @@ __device__ __forceinline__ void wave_gemv(const C *__restrict__ M, int Rt, int c
     if (act) {
       const C *p = M + lane;
       const int step = G * Rt;
-      int col = grp;
-#pragma unroll 16
-      for (; col < c; col += G, p += step) cfma(acc, *p, xat(col));
+      const int nt = (c - grp + G - 1) / G;   // columns grp, grp + G, ...
+      batched_dot<LoadBatch<C>::value, false>(
+          acc, nt, [&](int t) { return p[(int64_t)t * step]; },
+          [&](int t) { return xat(grp + t * G); });
     }
     // combine the G partial sums of each row (lanes row, row+Rt, ...)
     C tot = acc;
@@ -51,8 +79,8 @@ __device__ __forceinline__ void wave_gemv(const C *__restrict__ M, int Rt, int c
       if (row < re_) {
         C acc{0, 0};
         const C *p = M + row;
-#pragma unroll 16
-        for (int col = 0; col < c; ++col, p += Rt) cfma(acc, *p, xat(col));
+        batched_dot<LoadBatch<C>::value, false>(
+            acc, c, [&](int col) { return p[(int64_t)col * Rt]; }, [&](int col) { return xat(col); });
         store(row, acc);
       }
     }
@@ -156,15 +184,15 @@ __global__ __launch_bounds__(256) void k_final(const cplx_t<R> *s,
   if (lane < sz) {
     if (wave == 0) {
       const C *Dm = F + lf.dense_off + lane;
-#pragma unroll 16
-      for (int col = 0; col < sz; ++col) cfma(acc, Dm[(int64_t)col * sz], xs[col]);
+      batched_dot<LoadBatch<C>::value, false>(
+          acc, sz, [&](int col) { return Dm[(int64_t)col * sz]; }, [&](int col) { return xs[col]; });
     }
     for (int l = wave; l < Lv; l += 4) {
       const KDesc d = kd[(int64_t)g * Lv + l];
       const C *K = F + d.foff + lane;
       const C *zz = z + d.zin;
-#pragma unroll 16
-      for (int q = 0; q < d.r; ++q) cfma(acc, K[(int64_t)q * sz], zz[q]);
+      batched_dot<LoadBatch<C>::value, false>(
+          acc, d.r, [&](int q) { return K[(int64_t)q * sz]; }, [&](int q) { return zz[q]; });
     }
   }
   part[wave][lane] = acc;
@@ -200,7 +228,8 @@ __global__ __launch_bounds__(256) void k_final_adj(const cplx_t<R> *y,
     if (lane < d.r) {
       const C *K = F + d.foff + (int64_t)lane * sz;
       C acc{0, 0};
-      for (int row = 0; row < sz; ++row) cfmac(acc, K[row], ys[row]);
+      batched_dot<LoadBatch<C>::value, true>(
+          acc, sz, [&](int row) { return K[row]; }, [&](int row) { return ys[row]; });
       z[d.zin + lane] = acc;
     }
   }
@@ -223,8 +252,10 @@ __global__ __launch_bounds__(256) void k_wstage_adj(const WItem *items, int64_t 
   if (col < c1) {
     C acc{0, 0};
     const C *cm = M + (int64_t)col * Rt;
-    for (int i = 0; i < ra; ++i) cfmac(acc, cm[i], wa[i]);
-    for (int i = ra; i < Rt; ++i) cfmac(acc, cm[i], wb[i - ra]);
+    batched_dot<LoadBatch<C>::value, true>(
+        acc, ra, [&](int i) { return cm[i]; }, [&](int i) { return wa[i]; });
+    batched_dot<LoadBatch<C>::value, true>(
+        acc, Rt - ra, [&](int i) { return cm[ra + i]; }, [&](int i) { return wb[i]; });
     z[U.zin + col] = acc;
   }
 }
@@ -252,13 +283,15 @@ __global__ __launch_bounds__(256) void k_vstage_adj(const cplx_t<R> *y,
     if (wave == 0) {
       // dense leaf: (D^H y)[col], column `lane` of D is contiguous
       const C *Dc = F + lf.dense_off + (int64_t)lane * sz;
-      for (int row = 0; row < sz; ++row) cfmac(acc, Dc[row], ys[row]);
+      batched_dot<LoadBatch<C>::value, true>(
+          acc, sz, [&](int row) { return Dc[row]; }, [&](int row) { return ys[row]; });
     }
     for (int l = wave; l < Lv; l += 4) {
       const VDesc d = vd[(int64_t)g * Lv + l];
       const C *V = F + d.foff + (int64_t)lane * d.r;
       const C *w = z + d.zout;
-      for (int row = 0; row < d.r; ++row) cfmac(acc, V[row], w[row]);
+      batched_dot<LoadBatch<C>::value, true>(
+          acc, d.r, [&](int row) { return V[row]; }, [&](int row) { return w[row]; });
     }
   }
   part[wave][lane] = acc;
