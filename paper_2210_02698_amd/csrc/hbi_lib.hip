@@ -57,6 +57,30 @@ struct DevBuf {
   template <class T> T *as() const { return (T *)p; }
 };
 
+// Pinned (page-locked) host memory, grow-only.
+struct HostBuf {
+  void *p = nullptr;
+  size_t n = 0;
+  HostBuf() = default;
+  HostBuf(const HostBuf &) = delete;
+  HostBuf &operator=(const HostBuf &) = delete;
+  ~HostBuf() { release(); }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  hipError_t reserve(size_t bytes) {
+    if (bytes <= n) return hipSuccess;
+    release();
+    hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) { p = nullptr; (void)hipGetLastError(); return e; }
+    n = bytes;
+    return hipSuccess;
+  }
+  template <class T> T *as() const { return (T *)p; }
+};
+
 struct Status {
   hbi_status code;
   std::string msg;
@@ -159,6 +183,7 @@ struct hbi_ctx {
   // build workspace; hc_cache holds the column side of every (cell, box)
   // pair during a build when it fits (hc_nbox boxes per cell, else empty)
   DevBuf ws, idx_d, hc_cache;
+  HostBuf stage_h;   // pinned staging of a batch's index upload
   int hc_nbox = 0;
   // factors and plan
   hbi_prec prec = HBI_F64;
@@ -179,6 +204,7 @@ struct hbi_ctx {
   std::shared_ptr<BatchCache> batch;
   // statistics
   double t_build = 0, t_geo = 0, t_host = 0, t_gpu = 0, t_final = 0;
+  double t_prep = 0, t_wait = 0, t_compact = 0;   // inside t_gpu: batch host set-up, batch total, compaction
   int64_t nnz_v = 0, nnz_w = 0, nnz_k = 0, nnz_d = 0, entries_eval = 0, nid = 0;
   int32_t rank_max = 0, id_m_max = 0;
   double rank_sum = 0, id_m_sum = 0, id_n_sum = 0, id_work = 0, id_work_wide = 0;
@@ -222,6 +248,7 @@ struct hbi_ctx {
     units_d.clear(); items_d.clear(); items_adj_d.clear(); plan = ApplyPlan();
     leaves_h.clear(); vd_h.clear(); kd_h.clear(); units_h.clear(); batch.reset(); ztotal = 0; z_d.release();
     nnz_v = nnz_w = nnz_k = nnz_d = entries_eval = nid = 0; rank_max = 0; rank_sum = 0;
+    t_prep = t_wait = t_compact = 0;
     id_m_max = 0; id_m_sum = id_n_sum = id_work = id_work_wide = 0; nid_wide = 0;
     if (state > 1) state = 1;
   }
@@ -377,7 +404,9 @@ struct Batcher {
       }
       HBI_HIP(c->ws.reserve(used));   // grow-only; the previous batch has finished
       run_batch(blocks, slots, nslot, i0, i1, id, tol, outs);
+      const double tc = now_s();
       if (id) on_batch(i0, i1 - i0);
+      c->t_compact += now_s() - tc;
       i0 = i1;
     }
   }
@@ -385,86 +414,53 @@ struct Batcher {
   void run_batch(const std::vector<BlockIn> &blocks, const std::vector<std::vector<int32_t>> &slots,
                  const std::vector<int> &nslot, int64_t i0, int64_t i1, bool id, double tol,
                  std::vector<BlockOut> *outs) {
+    const double tb = now_s();
     const int64_t nb = i1 - i0;
-    std::vector<EntryBlock> eb(nb);
-    std::vector<IdBlock> ib(id ? nb : 0);
-    int64_t nrows = 0, ncols = 0, nsl = 0, ncw = 0;
+    // offsets of every block's rows, columns, slots and column-side work
+    std::vector<int64_t> ro(nb + 1, 0), co(nb + 1, 0), so(nb + 1, 0), wco(nb + 1, 0),
+        pivoff(nb + 1, 0), wsoff(nb + 1, 0), to(nb + 1, 0);
     for (int64_t q = 0; q < nb; ++q) {
       const BlockIn &b = blocks[i0 + q];
-      nrows += b.m; ncols += b.n; nsl += nslot[i0 + q];
-      ncw += (int64_t)b.n * nslot[i0 + q];
-    }
-    std::vector<int32_t> rows(nrows), cols(ncols), slotbox(nsl), workc(2 * ncw), rord(nrows);
-    std::vector<ETile> tiles;
-    std::vector<int32_t> scount;
-    std::vector<int64_t> pivoff(nb, 0);
-    char *ws = c->ws.as<char>();
-    size_t wso = 0;
-    int64_t ro = 0, co = 0, so = 0, wc = 0, po = 0;
-    for (int64_t q = 0; q < nb; ++q) {
-      const BlockIn &b = blocks[i0 + q];
-      const std::vector<int32_t> &sl = slots[i0 + q];
       const int ns = nslot[i0 + q];
-      EntryBlock &e = eb[q];
-      e.row_off = ro; e.col_off = co; e.slot_off = so; e.m = b.m; e.n = b.n; e.nslot = ns;
-      e.hc_off = (int64_t)(wso / sizeof(double));
-      if (!c->hc_cache.p) wso += align256((size_t)b.n * ns * 3 * c->NTb * sizeof(double));
-      if (id) {
-        IdBlock &d = ib[q];
-        d.A = (double2 *)(ws + wso);
-        wso += align256((size_t)b.m * b.n * sizeof(double2));
-        d.X = (double2 *)(ws + wso);
-        wso += align256((size_t)std::min(b.m, b.n) * b.n * sizeof(double2));
-        d.m = b.m; d.n = b.n;
-        d.piv = nullptr;   // set after the index buffer is placed
-        pivoff[q] = po;
-        po += b.n;
-        e.out = d.A;
-      } else {
-        e.out = b.out;
-      }
-      // rows in slot order (counting sort), then tiles of kEntryTileRows rows
-      // of one slot x kEntryTileCols columns
-      scount.assign(ns + 1, 0);
-      for (int32_t i = 0; i < b.m; ++i) {
-        rows[ro + i] = b.rows[i];
-        const int32_t bx = c->box_h[b.rows[i]];
-        scount[(std::find(sl.begin(), sl.end(), bx) - sl.begin()) + 1] += 1;
-      }
-      for (int s2 = 0; s2 < ns; ++s2) scount[s2 + 1] += scount[s2];
-      {
-        std::vector<int32_t> fill(scount.begin(), scount.end() - 1);
+      ro[q + 1] = ro[q] + b.m;
+      co[q + 1] = co[q] + b.n;
+      so[q + 1] = so[q] + ns;
+      wco[q + 1] = wco[q] + (int64_t)b.n * ns;
+      pivoff[q + 1] = pivoff[q] + (id ? b.n : 0);
+      size_t w = c->hc_cache.p ? 0 : align256((size_t)b.n * ns * 3 * c->NTb * sizeof(double));
+      if (id) w += align256((size_t)b.m * b.n * sizeof(double2)) +
+                   align256((size_t)std::min(b.m, b.n) * b.n * sizeof(double2));
+      wsoff[q + 1] = wsoff[q] + (int64_t)w;
+    }
+    const int64_t nrows = ro[nb], ncols = co[nb], nsl = so[nb], ncw = wco[nb], po = pivoff[nb];
+    // rows in slot order (counting sort) and the number of entry tiles
+    // (kEntryTileRows rows of one slot x kEntryTileCols columns) per block
+    std::vector<int32_t> rord(nrows), rslot(nrows);
+    std::vector<int64_t> ntile(nb);
+    parallel_for(nb, [&](int64_t qa, int64_t qb) {
+      std::vector<int32_t> cnt;
+      for (int64_t q = qa; q < qb; ++q) {
+        const BlockIn &b = blocks[i0 + q];
+        const std::vector<int32_t> &sl = slots[i0 + q];
+        const int ns = nslot[i0 + q];
+        cnt.assign(ns + 1, 0);
+        int32_t *rs = rslot.data() + ro[q];
         for (int32_t i = 0; i < b.m; ++i) {
           const int32_t bx = c->box_h[b.rows[i]];
-          const int s2 = (int)(std::find(sl.begin(), sl.end(), bx) - sl.begin());
-          rord[ro + fill[s2]++] = i;
+          rs[i] = (int32_t)(std::find(sl.begin(), sl.end(), bx) - sl.begin());
+          cnt[rs[i] + 1] += 1;
         }
+        for (int s2 = 0; s2 < ns; ++s2) cnt[s2 + 1] += cnt[s2];
+        int64_t nt = 0;
+        const int64_t cj = (b.n + kEntryTileCols - 1) / kEntryTileCols;
+        for (int s2 = 0; s2 < ns; ++s2)
+          nt += (cnt[s2 + 1] - cnt[s2] + kEntryTileRows - 1) / kEntryTileRows * cj;
+        ntile[q] = nt;
+        for (int32_t i = 0; i < b.m; ++i) rord[ro[q] + cnt[rs[i]]++] = i;
       }
-      for (int s2 = 0; s2 < ns; ++s2)
-        for (int32_t r0 = scount[s2]; r0 < scount[s2 + 1]; r0 += kEntryTileRows)
-          for (int32_t j0 = 0; j0 < b.n; j0 += kEntryTileCols)
-            tiles.push_back(ETile{(int32_t)q, r0, std::min(kEntryTileRows, scount[s2 + 1] - r0), j0,
-                                  std::min(kEntryTileCols, b.n - j0), s2});
-      std::copy(b.cols, b.cols + b.n, cols.begin() + co);
-      std::copy(sl.begin(), sl.end(), slotbox.begin() + so);
-      for (int32_t j = 0; j < b.n; ++j) {
-        for (int s = 0; s < ns; ++s) {
-          workc[2 * wc] = (int32_t)q;
-          workc[2 * wc + 1] = j * ns + s;
-          ++wc;
-        }
-      }
-      ro += b.m; co += b.n; so += ns;
-    }
-    // one index upload: rows, cols, slotbox, workc, tiles, rord, eb, ib, sel, piv, rank
-    size_t off = 0;
-    auto place = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
-    const size_t o_rows = place(rows.size() * 4), o_cols = place(cols.size() * 4),
-                 o_slot = place(slotbox.size() * 4), o_wc = place(workc.size() * 4),
-                 o_tl = place(tiles.size() * sizeof(ETile)), o_ro = place(rord.size() * 4),
-                 o_eb = place(eb.size() * sizeof(EntryBlock)),
-                 o_ib = place(ib.size() * sizeof(IdBlock)), o_sel = place(id ? (size_t)nb * 4 : 0),
-                 o_piv = place((size_t)po * 4), o_rank = place((size_t)nb * 4);
+    });
+    for (int64_t q = 0; q < nb; ++q) to[q + 1] = to[q] + ntile[q];
+    const int64_t ntiles = to[nb];
     // ID kernel per block: on chip up to HBI_ID_ONCHIP_NMAX columns, the
     // global-memory pivoted QR beyond; sel lists the groups
     std::vector<int32_t> sel;
@@ -474,29 +470,88 @@ struct Batcher {
     if (id) {
       std::vector<int32_t> g[3];
       for (int64_t q = 0; q < nb; ++q) {
-        const int n = ib[q].n;
-        const int k = idk != ID_AUTO || n > HBI_ID_ONCHIP_NMAX ? 2 : 0;
+        const BlockIn &b = blocks[i0 + q];
+        const int k = idk != ID_AUTO || b.n > HBI_ID_ONCHIP_NMAX ? 2 : 0;
         g[k].push_back((int32_t)q);
-        nmax_g[k] = std::max(nmax_g[k], n);
-        if (k == 2) mmax_w = std::max(mmax_w, (int)ib[q].m);
+        nmax_g[k] = std::max(nmax_g[k], (int)b.n);
+        if (k == 2) mmax_w = std::max(mmax_w, (int)b.m);
       }
       for (int k = 0; k < 3; ++k) { nsel[k] = (int64_t)g[k].size(); sel.insert(sel.end(), g[k].begin(), g[k].end()); }
     }
+    // one index upload from pinned host memory: rows, cols, slotbox, workc,
+    // tiles, rord, eb, ib, sel; then piv and rank come back
+    size_t off = 0;
+    auto place = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    const size_t o_rows = place(nrows * 4), o_cols = place(ncols * 4), o_slot = place(nsl * 4),
+                 o_wc = place(ncw * 8), o_tl = place(ntiles * sizeof(ETile)),
+                 o_ro = place(nrows * 4), o_eb = place(nb * sizeof(EntryBlock)),
+                 o_ib = place(id ? nb * sizeof(IdBlock) : 0),
+                 o_sel = place(id ? (size_t)nb * 4 : 0), o_piv = place((size_t)po * 4),
+                 o_rank = place((size_t)nb * 4);
     HBI_HIP(c->idx_d.reserve(off));
+    HBI_HIP(c->stage_h.reserve(o_piv));
     char *ix = c->idx_d.as<char>();
-    for (int64_t q = 0; q < (int64_t)ib.size(); ++q) ib[q].piv = (int32_t *)(ix + o_piv) + pivoff[q];
-    std::vector<char> stage(off);
-    auto put = [&](size_t o, const void *src, size_t bytes) { if (bytes) std::memcpy(stage.data() + o, src, bytes); };
-    put(o_rows, rows.data(), rows.size() * 4);
-    put(o_cols, cols.data(), cols.size() * 4);
-    put(o_slot, slotbox.data(), slotbox.size() * 4);
-    put(o_wc, workc.data(), workc.size() * 4);
-    put(o_tl, tiles.data(), tiles.size() * sizeof(ETile));
-    put(o_ro, rord.data(), rord.size() * 4);
-    put(o_eb, eb.data(), eb.size() * sizeof(EntryBlock));
-    put(o_ib, ib.data(), ib.size() * sizeof(IdBlock));
-    put(o_sel, sel.data(), sel.size() * 4);
-    HBI_HIP(hipMemcpyAsync(ix, stage.data(), o_piv, hipMemcpyHostToDevice, c->stream));
+    char *st = c->stage_h.as<char>();
+    int32_t *rows = (int32_t *)(st + o_rows), *cols = (int32_t *)(st + o_cols),
+            *slotbox = (int32_t *)(st + o_slot), *workc = (int32_t *)(st + o_wc);
+    ETile *tiles = (ETile *)(st + o_tl);
+    EntryBlock *eb = (EntryBlock *)(st + o_eb);
+    IdBlock *ib = (IdBlock *)(st + o_ib);
+    std::memcpy(st + o_ro, rord.data(), nrows * 4);
+    if (id) std::memcpy(st + o_sel, sel.data(), sel.size() * 4);
+    char *ws = c->ws.as<char>();
+    parallel_for(nb, [&](int64_t qa, int64_t qb) {
+      for (int64_t q = qa; q < qb; ++q) {
+        const BlockIn &b = blocks[i0 + q];
+        const std::vector<int32_t> &sl = slots[i0 + q];
+        const int ns = nslot[i0 + q];
+        EntryBlock e{};
+        e.row_off = ro[q]; e.col_off = co[q]; e.slot_off = so[q];
+        e.m = b.m; e.n = b.n; e.nslot = ns;
+        size_t wso = (size_t)wsoff[q];
+        e.hc_off = (int64_t)(wso / sizeof(double));
+        if (!c->hc_cache.p) wso += align256((size_t)b.n * ns * 3 * c->NTb * sizeof(double));
+        if (id) {
+          IdBlock d{};
+          d.A = (double2 *)(ws + wso);
+          wso += align256((size_t)b.m * b.n * sizeof(double2));
+          d.X = (double2 *)(ws + wso);
+          d.m = b.m; d.n = b.n;
+          d.piv = (int32_t *)(ix + o_piv) + pivoff[q];
+          ib[q] = d;
+          e.out = d.A;
+        } else {
+          e.out = b.out;
+        }
+        eb[q] = e;
+        std::copy(b.rows, b.rows + b.m, rows + ro[q]);
+        std::copy(b.cols, b.cols + b.n, cols + co[q]);
+        std::copy(sl.begin(), sl.end(), slotbox + so[q]);
+        int32_t *w = workc + 2 * wco[q];
+        for (int32_t j = 0; j < b.n; ++j)
+          for (int s2 = 0; s2 < ns; ++s2) {
+            *w++ = (int32_t)q;
+            *w++ = j * ns + s2;
+          }
+        // tiles: slot runs of the sorted rows
+        ETile *t = tiles + to[q];
+        const int32_t *rs = rslot.data() + ro[q];
+        const int32_t *rq = rord.data() + ro[q];
+        int32_t r0 = 0;
+        while (r0 < b.m) {
+          const int s2 = rs[rq[r0]];
+          int32_t r1 = r0;
+          while (r1 < b.m && rs[rq[r1]] == s2) ++r1;
+          for (int32_t a = r0; a < r1; a += kEntryTileRows)
+            for (int32_t j0 = 0; j0 < b.n; j0 += kEntryTileCols)
+              *t++ = ETile{(int32_t)q, a, std::min(kEntryTileRows, r1 - a), j0,
+                           std::min(kEntryTileCols, b.n - j0), s2};
+          r0 = r1;
+        }
+      }
+    });
+    c->t_prep += now_s() - tb;   // host-side set-up of the batch
+    HBI_HIP(hipMemcpyAsync(ix, st, o_piv, hipMemcpyHostToDevice, c->stream));
     const DevProblem P = c->devprob();
     const DevCells C = c->devcells();
     const DevTables T = c->devtables();
@@ -506,7 +561,7 @@ struct Batcher {
                              (const int32_t *)(ix + o_wc), ncw, (const int32_t *)(ix + o_cols),
                              (const int32_t *)(ix + o_slot), c->ws.as<double>(), c->stream));
     HBI_HIP(launch_entries(P, C, (const EntryBlock *)(ix + o_eb), (const ETile *)(ix + o_tl),
-                           (int64_t)tiles.size(), (const int32_t *)(ix + o_rows),
+                           ntiles, (const int32_t *)(ix + o_rows),
                            (const int32_t *)(ix + o_ro), (const int32_t *)(ix + o_cols),
                            c->ws.as<double>(), (const int32_t *)(ix + o_slot), hcache,
                            c->hc_nbox, c->stream));
@@ -527,6 +582,7 @@ struct Batcher {
       HBI_HIP(hipMemcpyAsync(rank.data(), ix + o_rank, nb * 4, hipMemcpyDeviceToHost, c->stream));
       if (po) HBI_HIP(hipMemcpyAsync(piv.data(), ix + o_piv, po * 4, hipMemcpyDeviceToHost, c->stream));
       HBI_HIP(hipStreamSynchronize(c->stream));
+      c->t_wait += now_s() - tb;
       int64_t pp = 0;
       for (int64_t q = 0; q < nb; ++q) {
         BlockOut &o = (*outs)[i0 + q];
@@ -551,6 +607,7 @@ struct Batcher {
       }
     } else {
       HBI_HIP(hipStreamSynchronize(c->stream));
+      c->t_wait += now_s() - tb;
     }
   }
 };
@@ -881,6 +938,7 @@ void build_factors(hbi_ctx *c, double tol) {
   const double tf = now_s();
   c->ws.release();
   c->idx_d.release();
+  c->stage_h.release();
   c->Felems = Fg;
   const size_t esz = c->prec == HBI_F64 ? sizeof(double2) : sizeof(float2);
   HBI_HIP(c->F.alloc(esz * std::max<int64_t>(Fg, 1)));
@@ -1600,7 +1658,7 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
   if (!json || cap <= 0) { ctx->err = "null or empty output buffer"; return HBI_ERR_ARG; }
   const int64_t Nv = ctx->geo.Nv;
   const size_t esz = ctx->prec == HBI_F64 ? 16 : 8;
-  char buf[2048];
+  char buf[4096];
   const int len = std::snprintf(
       buf, sizeof buf,
       "{\"state\": %d, \"dim\": %d, \"N_v\": %lld, \"L_v\": %d, \"NT\": %d, \"nI\": %d, "
@@ -1611,7 +1669,8 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       "\"id_rows_mean\": %.1f, \"id_rows_max\": %d, \"id_cols_mean\": %.1f, \"id_cmac\": %.6e, "
       "\"n_id_cols_gt64\": %lld, \"id_cmac_cols_gt64\": %.6e, "
       "\"build_s\": %.6f, \"build_geometry_s\": %.6f, \"build_proxy_host_s\": %.6f, "
-      "\"build_gpu_s\": %.6f, \"build_finalize_s\": %.6f}",
+      "\"build_gpu_s\": %.6f, \"build_batch_host_setup_s\": %.6f, \"build_batch_total_s\": %.6f, "
+      "\"build_compact_s\": %.6f, \"build_finalize_s\": %.6f}",
       ctx->state, ctx->dim, (long long)Nv, ctx->geo.Lv, ctx->NT, ctx->nI,
       ctx->prec == HBI_F64 ? "f64" : "f32", ctx->tol, ctx->chi(), ctx->leaf(),
       (long long)ctx->nnz_v, (long long)ctx->nnz_w, (long long)ctx->nnz_k, (long long)ctx->nnz_d,
@@ -1619,7 +1678,8 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       (long long)ctx->nid, ctx->rank_max, ctx->nid ? ctx->rank_sum / ctx->nid : 0.0,
       (long long)ctx->entries_eval, ctx->nid ? ctx->id_m_sum / ctx->nid : 0.0, ctx->id_m_max,
       ctx->nid ? ctx->id_n_sum / ctx->nid : 0.0, ctx->id_work, (long long)ctx->nid_wide,
-      ctx->id_work_wide, ctx->t_build, ctx->t_geo, ctx->t_host, ctx->t_gpu,
+      ctx->id_work_wide, ctx->t_build, ctx->t_geo, ctx->t_host, ctx->t_gpu, ctx->t_prep,
+      ctx->t_wait, ctx->t_compact,
       ctx->t_final);
   if (len < 0 || len >= cap) { ctx->err = "output buffer too small"; return HBI_ERR_ARG; }
   std::memcpy(json, buf, len + 1);
