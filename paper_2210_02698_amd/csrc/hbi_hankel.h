@@ -56,37 +56,37 @@ HBI_HD inline Hankel01 hankel01_series(double x) {
 }
 
 HBI_HD inline Hankel01 hankel01_miller(double x) {
-  // start index: even, comfortably above x so J_N(x) is negligible
-  int N = (int)(x + 12.0 + 6.0 * cbrt(x));
+  // even start index comfortably above x: x + 12 + 6 x^(1/3), with x^(1/3)
+  // bounded by its tangent at x = 3 (so the start is never lower)
+  int N = (int)(x + 12.0 + 6.0 * (1.4422495703074083 + 0.16025 * (x - 3.0)));
   N = (N / 2) * 2 + 2;
   const double inv = 2.0 / x;
-  double jp1 = 0.0, jk = 1e-30;        // J_{k+1}, J_k (unnormalised)
+  double jp1 = 0.0, jk = 1e-30;        // J_{k+1}, J_k (unnormalised), k = N
   double norm = 0.0, sy0 = 0.0, sy1 = 0.0, j1 = 0.0;
-  // walk k = N .. 1 producing J_{k-1}; accumulate the sums on the fly
-  for (int k = N; k >= 1; --k) {
-    // contributions of J_k (k >= 1)
-    if ((k & 1) == 0) {
-      const int m = k >> 1;
-      const double sg = (m & 1) ? -1.0 : 1.0;
-      norm += 2.0 * jk;
-      sy0 += sg * jk / m;
-    } else {
-      // odd k: + (-1)^m J_k / m with k = 2m-1, and - (-1)^m J_k / m with k = 2m+1
-      const int ma = (k + 1) >> 1;
-      sy1 += ((ma & 1) ? -1.0 : 1.0) * jk / ma;
-      if (k >= 3) {
-        const int mb = (k - 1) >> 1;
-        sy1 -= ((mb & 1) ? -1.0 : 1.0) * jk / mb;
-      }
-    }
-    if (k == 1) j1 = jk;
-    const double jm1 = k * inv * jk - jp1;
+  // pairs k = 2m (even), 2m - 1 (odd), m = N/2 .. 1; one reciprocal per pair
+  int m = N / 2;
+  double sg = (m & 1) ? -1.0 : 1.0;    // (-1)^m
+  double rm = 1.0 / m;
+  for (; m >= 1; --m) {
+    // J_{2m}: normalisation and Y0 sums
+    norm += 2.0 * jk;
+    sy0 += sg * jk * rm;
+    double jm1 = (2 * m) * inv * jk - jp1;   // J_{2m-1}
+    jp1 = jk;
+    jk = jm1;
+    // J_{2m-1} enters Y1 as (-1)^m / m and, for m >= 2, as (-1)^m / (m - 1)
+    const double rm1 = m >= 2 ? 1.0 / (m - 1) : 0.0;
+    sy1 += sg * jk * (rm + rm1);
+    if (m == 1) j1 = jk;
+    jm1 = (2 * m - 1) * inv * jk - jp1;       // J_{2m-2}
     jp1 = jk;
     jk = jm1;
     if (fabs(jk) > 1e250) {
       jk *= 1e-250; jp1 *= 1e-250; norm *= 1e-250; sy0 *= 1e-250;
       sy1 *= 1e-250; j1 *= 1e-250;
     }
+    sg = -sg;
+    rm = rm1;
   }
   norm += jk;                      // J_0
   const double s = 1.0 / norm;
