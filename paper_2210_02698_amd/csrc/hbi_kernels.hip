@@ -231,21 +231,37 @@ __device__ __forceinline__ double2 hb_value(int D, int nterms, double omega,
 // up to kET_I rows (all in one table box) and kET_J columns of a block,
 //   g_t(i, j) = sum_A T_A(r_i) Hc_t(j, box)[A],   T_A = prod_s l_{a_s}(r_i),
 // for t = tau^2, v0, v1.  T and Hc pass through LDS in chunks of kET_K nodes;
-// each thread keeps a 4 x 4 x 3 register tile.  Then the HB value of
+// each thread keeps a 4 x 2 x 3 register tile.  Then the HB value of
 // (tau^2, v0, v1) (eq. babich, eq. termf), or the self term on the diagonal,
 // goes to out(i, j).  Rows are visited in slot order through `rord`.
+// In 2D the Hankel pair H0, H1 of x = omega tau takes one of three branches
+// (series, Miller recurrence, asymptotic expansion); the tile's entries are
+// first sorted by branch through LDS so that every wave runs one branch at a
+// time over full lanes, then written out in place.
 // ---------------------------------------------------------------------------
-constexpr int kET_I = 128, kET_J = 32, kET_K = 32;
+constexpr int kET_I = 128, kET_J = 16, kET_K = 32;
+constexpr int kET_N = kET_I * kET_J;   // entries per tile
+
+// HB value from the Hankel pair: (sqrt(pi)/2) v0 i H0 - sqrt(pi) (tau/omega) v1 i H1
+__device__ __forceinline__ double2 hb2d(const Hankel01 &H, double c0, double c1) {
+  return double2{-c0 * H.y0 + c1 * H.y1, c0 * H.j0 - c1 * H.j1};
+}
 
 template <int D, int NI>
 __global__ __launch_bounds__(256, 2) void k_entries(
     DevProblem P, DevCells C, const EntryBlock *blks, const ETile *tiles, int64_t ntiles,
     const int32_t *rows, const int32_t *rord, const int32_t *cols, const double *Hc,
     const int32_t *slotbox, const double *Hcache, int nbox) {
-  __shared__ double sW[kET_K][kET_I];
-  __shared__ double sH[3][kET_K][kET_J];
+  // contraction staging (sW: kET_K x kET_I, sH: 3 x kET_K x kET_J), reused by
+  // the 2D epilogue as x, c0, c1 per entry plus the branch-sorted entry list
+  constexpr int kStage = kET_K * kET_I + 3 * kET_K * kET_J;
+  constexpr int kEpi = 3 * kET_N + kET_N / 4;
+  __shared__ double smem[kStage > kEpi ? kStage : kEpi];
   __shared__ int32_t srp[kET_I];
   __shared__ const double *shp[kET_J];
+  __shared__ int32_t cls_cnt[4][3];
+  double(*sW)[kET_I] = (double(*)[kET_I])smem;
+  double(*sH)[kET_K][kET_J] = (double(*)[kET_K][kET_J])(smem + kET_K * kET_I);
   const int64_t tb = blockIdx.x;
   if (tb >= ntiles) return;
   const ETile T = tiles[tb];
@@ -267,11 +283,11 @@ __global__ __launch_bounds__(256, 2) void k_entries(
   }
   __syncthreads();
   const int ty = tid >> 3, tx = tid & 7;
-  double acc[4][4][3];
+  double acc[4][2][3];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int t = 0; t < 3; ++t) acc[r][c][t] = 0.0;
   for (int a0 = 0; a0 < NTb; a0 += kET_K) {
@@ -294,40 +310,144 @@ __global__ __launch_bounds__(256, 2) void k_entries(
       sH[t][k][c] = (h && A < NTb && t < ntab) ? h[(int64_t)t * NTb + A] : 0.0;
     }
     __syncthreads();
-#pragma unroll 2
+#pragma unroll 4
     for (int k = 0; k < kET_K; ++k) {
-      double w[4], h[3][4];
+      double w[4], h[3][2];
 #pragma unroll
       for (int r = 0; r < 4; ++r) w[r] = sW[k][ty * 4 + r];
 #pragma unroll
       for (int t = 0; t < 3; ++t)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) h[t][c] = sH[t][k][tx * 4 + c];
+        for (int c = 0; c < 2; ++c) h[t][c] = sH[t][k][tx * 2 + c];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < 2; ++c)
 #pragma unroll
           for (int t = 0; t < 3; ++t) acc[r][c][t] = fma(w[r], h[t][c], acc[r][c][t]);
     }
     __syncthreads();
   }
+  if (D == 3) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = ty * 4 + r;
+      if (rr >= T.nr) continue;
+      const int i = rord[B.row_off + T.r0 + rr];
+      const int32_t rp = srp[rr];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int cc = tx * 2 + c;
+        if (cc >= T.nj) continue;
+        const int j = T.j0 + cc;
+        const int32_t cp = cols[B.col_off + j];
+        const double2 K = rp == cp ? C.self[rp]
+                                   : hb_value(D, P.nterms, P.omega, acc[r][c][0], acc[r][c][1],
+                                              acc[r][c][2]);
+        B.out[i + (int64_t)j * B.m] = K;
+      }
+    }
+    return;
+  }
+  // ---- 2D: x, c0, c1 per entry (entry e = rr * kET_J + cc), branch 0..2 or
+  // 3 (value already final: self term) or -1 (outside the tile)
+  double *ex = smem, *ec0 = smem + kET_N, *ec1 = smem + 2 * kET_N;
+  uint16_t *elist = (uint16_t *)(smem + 3 * kET_N);
+  const int lane = tid & 63, wave = tid >> 6;
+  int cls[4][2];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int rr = ty * 4 + r;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int cc = tx * 2 + c;
+      const int e = rr * kET_J + cc;
+      cls[r][c] = -1;
+      if (rr < T.nr && cc < T.nj) {
+        const int32_t rp = srp[rr];
+        const int32_t cp = cols[B.col_off + T.j0 + cc];
+        if (rp == cp) {
+          const double2 sf = C.self[rp];
+          ec0[e] = sf.x;
+          ec1[e] = sf.y;
+          cls[r][c] = 3;
+        } else {
+          const double tau = sqrt(fmax(acc[r][c][0], 0.0));
+          const double x = P.omega * tau;
+          ex[e] = x;
+          ec0[e] = 0.88622692545275801365 * acc[r][c][1];   // sqrt(pi)/2 v0
+          ec1[e] = P.nterms == 2 ? 1.77245385090551602730 * (tau / P.omega) * acc[r][c][2] : 0.0;
+          cls[r][c] = x < 3.0 ? 0 : (x < 20.0 ? 1 : 2);
+        }
+      }
+    }
+  }
+  // branch-sorted list: per-wave counts by ballot, then positions
+  int cnt[3] = {0, 0, 0};
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) cnt[q] += __popcll(__ballot(cls[r][c] == q));
+  if (lane == 0)
+    for (int q = 0; q < 3; ++q) cls_cnt[wave][q] = cnt[q];
+  __syncthreads();
+  int base[3], tot[3];
+  {
+    int run = 0;
+    for (int q = 0; q < 3; ++q) {
+      int before = 0, all = 0;
+      for (int w2 = 0; w2 < 4; ++w2) {
+        if (w2 < wave) before += cls_cnt[w2][q];
+        all += cls_cnt[w2][q];
+      }
+      base[q] = run + before;
+      tot[q] = all;
+      run += all;
+    }
+  }
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const uint64_t mk = __ballot(cls[r][c] == q);
+        if (cls[r][c] == q)
+          elist[base[q] + __popcll(mk & below)] = (uint16_t)((ty * 4 + r) * kET_J + tx * 2 + c);
+        base[q] += __popcll(mk);
+      }
+  __syncthreads();
+  // one branch at a time over full lanes; results overwrite c0, c1
+  {
+    int off = 0;
+    for (int q = 0; q < 3; ++q) {
+      for (int t = tid; t < tot[q]; t += 256) {
+        const int e = elist[off + t];
+        const double x = ex[e];
+        const Hankel01 H = q == 0 ? hankel01_series(x)
+                                  : (q == 1 ? hankel01_miller(x) : hankel01_asym(x));
+        const double2 K = hb2d(H, ec0[e], ec1[e]);
+        ec0[e] = K.x;
+        ec1[e] = K.y;
+      }
+      off += tot[q];
+    }
+  }
+  __syncthreads();
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int rr = ty * 4 + r;
     if (rr >= T.nr) continue;
     const int i = rord[B.row_off + T.r0 + rr];
-    const int32_t rp = srp[rr];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int cc = tx * 4 + c;
+    for (int c = 0; c < 2; ++c) {
+      const int cc = tx * 2 + c;
       if (cc >= T.nj) continue;
-      const int j = T.j0 + cc;
-      const int32_t cp = cols[B.col_off + j];
-      const double2 K = rp == cp ? C.self[rp]
-                                 : hb_value(D, P.nterms, P.omega, acc[r][c][0], acc[r][c][1],
-                                            acc[r][c][2]);
-      B.out[i + (int64_t)j * B.m] = K;
+      const int e = rr * kET_J + cc;
+      B.out[i + (int64_t)(T.j0 + cc) * B.m] = double2{ec0[e], ec1[e]};
     }
   }
 }
@@ -668,35 +788,21 @@ __device__ __forceinline__ double2 readlane_c(double2 v, int l) {
   return double2{readlane_d(v.x, l), readlane_d(v.y, l)};
 }
 
-template <int NW, int NS, int PR, int WPE>
-__global__ __launch_bounds__(NW * 64, WPE) void k_id_onchip(
-    const IdBlock *blks, const int32_t *sel, double tol, int32_t *rank_out, int cap) {
-  constexpr int NC = NS * NW;      // column capacity
-  constexpr int RR = NC / 64;      // R0 rows per lane
-  constexpr int T = NW * 64;
-  static_assert(NC % 64 == 0, "column capacity must be a multiple of 64");
-  extern __shared__ double2 lds_rs[];
-  __shared__ double2 v_sh[2][NC > 64 * PR ? NC : 64 * PR];
-  __shared__ double2 tau_sh[2];
-  __shared__ int colmap[NC], pos[NC];
-  __shared__ double red_v[NW];
-  __shared__ int red_q[NW], red_c[NW];
-
-  const int blk = sel[blockIdx.x];
-  const IdBlock B = blks[blk];
-  const int m = B.m, n = B.n;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
-  const double2 *A = B.A;
+// Phase 1 of the on-chip decomposition: R0 (the triangular factor of an
+// unpivoted Householder QR of the m x n block A, n <= NW NS) accumulated in
+// registers (lane l holds rows l + 64 u of R0 for its wave's columns) by
+// folding panels of 64 PR rows into [R0; P].  vsh holds two reflector
+// buffers of VS entries, tsh two reflector scalars (LDS).
+template <int NW, int NS, int PR, int VS>
+__device__ __forceinline__ void tsqr_panels(const double2 *A, int m, int n, int w, int lane,
+                                            double2 (&R)[NS * NW / 64][NS], double2 *vsh,
+                                            double2 *tsh) {
+  constexpr int RR = NS * NW / 64;
   const double2 zero2 = double2{0.0, 0.0};
-
-  double2 R[RR][NS];
 #pragma unroll
   for (int u = 0; u < RR; ++u)
 #pragma unroll
     for (int s = 0; s < NS; ++s) R[u][s] = zero2;
-
-  // ---- phase 1: R0 of A, one panel of 64 PR rows at a time
   int buf = 0;
   for (int p0 = 0; p0 < m; p0 += 64 * PR) {
     double2 P[PR][NS];
@@ -733,7 +839,7 @@ __global__ __launch_bounds__(NW * 64, WPE) void k_id_onchip(
           const double dr = al.x - beta, di = al.y, dd = dr * dr + di * di;
           const double2 scale = double2{dr / dd, -di / dd};
 #pragma unroll
-          for (int t = 0; t < PR; ++t) v_sh[buf][lane + 64 * t] = cmul(x[t], scale);
+          for (int t = 0; t < PR; ++t) vsh[buf * VS + (lane + 64 * t)] = cmul(x[t], scale);
 #pragma unroll
           for (int s = 0; s < NS; ++s)
             if (s == sj) {
@@ -744,14 +850,14 @@ __global__ __launch_bounds__(NW * 64, WPE) void k_id_onchip(
                 if (u == uj && lane == lj) R[u][s] = double2{beta, 0.0};
             }
         }
-        if (lane == 0) tau_sh[buf] = tau;
+        if (lane == 0) tsh[buf] = tau;
       }
       __syncthreads();
-      const double2 tau = uniform_c(tau_sh[buf]);
+      const double2 tau = uniform_c(tsh[buf]);
       if (tau.x != 0.0 || tau.y != 0.0) {
         double2 v[PR];
 #pragma unroll
-        for (int t = 0; t < PR; ++t) v[t] = v_sh[buf][lane + 64 * t];
+        for (int t = 0; t < PR; ++t) v[t] = vsh[buf * VS + (lane + 64 * t)];
         const double2 ctau = double2{tau.x, -tau.y};
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -782,6 +888,41 @@ __global__ __launch_bounds__(NW * 64, WPE) void k_id_onchip(
       buf ^= 1;
     }
   }
+
+}
+
+template <int NW, int NS, int PR, int WPE>
+__global__ __launch_bounds__(NW * 64, WPE) void k_id_onchip(
+    const IdBlock *blks, const int32_t *sel, double tol, int32_t *rank_out, int cap) {
+  constexpr int NC = NS * NW;      // column capacity
+  constexpr int RR = NC / 64;      // R0 rows per lane
+  constexpr int T = NW * 64;
+  static_assert(NC % 64 == 0, "column capacity must be a multiple of 64");
+  extern __shared__ double2 lds_rs[];
+  __shared__ double2 v_sh[2][NC > 64 * PR ? NC : 64 * PR];
+  __shared__ double2 tau_sh[2];
+  __shared__ int colmap[NC], pos[NC];
+  __shared__ double red_v[NW];
+  __shared__ int red_q[NW], red_c[NW];
+
+  const int blk = sel[blockIdx.x];
+  const IdBlock B = blks[blk];
+  const int m = B.m, n = B.n;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
+  const double2 *A = B.A;
+  const double2 zero2 = double2{0.0, 0.0};
+
+  double2 R[RR][NS];
+#pragma unroll
+  for (int u = 0; u < RR; ++u)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) R[u][s] = zero2;
+
+  // ---- phase 1: R0 of A, one panel of 64 PR rows at a time
+  constexpr int VS = NC > 64 * PR ? NC : 64 * PR;
+  tsqr_panels<NW, NS, PR, VS>(A, m, n, w, lane, R, &v_sh[0][0], tau_sh);
+  int buf = 0;
 
   // ---- phase 2: column-pivoted QR of R0
   for (int c = tid; c < NC; c += T) { colmap[c] = c; pos[c] = c; }

@@ -206,8 +206,10 @@ struct hbi_ctx {
   double t_build = 0, t_geo = 0, t_host = 0, t_gpu = 0, t_final = 0;
   double t_prep = 0, t_wait = 0, t_compact = 0;   // inside t_gpu: batch host set-up, batch total, compaction
   int64_t nnz_v = 0, nnz_w = 0, nnz_k = 0, nnz_d = 0, entries_eval = 0, nid = 0;
+  int64_t entry_slots = 0;   // entry-tile capacity launched (fill = entries_eval / entry_slots)
+  int64_t nid_path[3] = {0, 0, 0};   // IDs per kernel group (on chip, unused, global)
   int32_t rank_max = 0, id_m_max = 0;
-  double rank_sum = 0, id_m_sum = 0, id_n_sum = 0, id_work = 0, id_work_wide = 0;
+  double rank_sum = 0, id_m_sum = 0, id_n_sum = 0, id_work = 0, id_work_wide = 0, id_work_128 = 0;
   int64_t nid_wide = 0;
   double tol = 0;
 
@@ -248,8 +250,9 @@ struct hbi_ctx {
     units_d.clear(); items_d.clear(); items_adj_d.clear(); plan = ApplyPlan();
     leaves_h.clear(); vd_h.clear(); kd_h.clear(); units_h.clear(); batch.reset(); ztotal = 0; z_d.release();
     nnz_v = nnz_w = nnz_k = nnz_d = entries_eval = nid = 0; rank_max = 0; rank_sum = 0;
-    t_prep = t_wait = t_compact = 0;
-    id_m_max = 0; id_m_sum = id_n_sum = id_work = id_work_wide = 0; nid_wide = 0;
+    t_prep = t_wait = t_compact = 0; entry_slots = 0;
+    nid_path[0] = nid_path[1] = nid_path[2] = 0;
+    id_m_max = 0; id_m_sum = id_n_sum = id_work = id_work_wide = id_work_128 = 0; nid_wide = 0;
     if (state > 1) state = 1;
   }
 };
@@ -347,7 +350,7 @@ static IdKernels id_kernels() {
 }
 
 // entry tile shape (rows of one table box x columns), as k_entries takes it
-constexpr int32_t kEntryTileRows = 128, kEntryTileCols = 32;
+constexpr int32_t kEntryTileRows = 128, kEntryTileCols = 16;
 
 struct Batcher {
   hbi_ctx *c;
@@ -462,7 +465,9 @@ struct Batcher {
     for (int64_t q = 0; q < nb; ++q) to[q + 1] = to[q] + ntile[q];
     const int64_t ntiles = to[nb];
     // ID kernel per block: on chip up to HBI_ID_ONCHIP_NMAX columns, the
-    // global-memory pivoted QR beyond; sel lists the groups
+    // global-memory pivoted QR beyond; sel lists the groups.  (Group 1, the
+    // triangular factor on chip followed by the global pivoted QR of it for
+    // n <= 128, measured no faster than group 2 and is left empty.)
     std::vector<int32_t> sel;
     int64_t nsel[3] = {0, 0, 0};
     int nmax_g[3] = {1, 1, 1}, mmax_w = 1;
@@ -476,7 +481,11 @@ struct Batcher {
         nmax_g[k] = std::max(nmax_g[k], (int)b.n);
         if (k == 2) mmax_w = std::max(mmax_w, (int)b.m);
       }
-      for (int k = 0; k < 3; ++k) { nsel[k] = (int64_t)g[k].size(); sel.insert(sel.end(), g[k].begin(), g[k].end()); }
+      for (int k = 0; k < 3; ++k) {
+        nsel[k] = (int64_t)g[k].size();
+        sel.insert(sel.end(), g[k].begin(), g[k].end());
+        c->nid_path[k] += nsel[k];
+      }
     }
     // one index upload from pinned host memory: rows, cols, slotbox, workc,
     // tiles, rord, eb, ib, sel; then piv and rank come back
@@ -566,6 +575,7 @@ struct Batcher {
                            c->ws.as<double>(), (const int32_t *)(ix + o_slot), hcache,
                            c->hc_nbox, c->stream));
     for (int64_t q = 0; q < nb; ++q) c->entries_eval += (int64_t)blocks[i0 + q].m * blocks[i0 + q].n;
+    c->entry_slots += ntiles * kEntryTileRows * kEntryTileCols;
     if (id) {
       const IdBlock *ibd = (const IdBlock *)(ix + o_ib);
       const int32_t *seld = (const int32_t *)(ix + o_sel);
@@ -604,6 +614,7 @@ struct Batcher {
           wk += 2.0 * (double)(ib[q].m - k) * (double)(ib[q].n - k - 1);
         c->id_work += wk;
         if (ib[q].n > 64) { c->id_work_wide += wk; c->nid_wide += 1; }
+        if (ib[q].n > 128) c->id_work_128 += wk;
       }
     } else {
       HBI_HIP(hipStreamSynchronize(c->stream));
@@ -1666,8 +1677,9 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       "\"nnz_v\": %lld, \"nnz_w\": %lld, \"nnz_k\": %lld, \"nnz_dense\": %lld, "
       "\"nnz_total\": %lld, \"factor_bytes\": %lld, \"z_entries\": %lld, "
       "\"n_id\": %lld, \"rank_max\": %d, \"rank_mean\": %.3f, \"entries_evaluated\": %lld, "
+      "\"entry_tile_fill\": %.4f, \"n_id_onchip\": %lld, \"n_id_global\": %lld, "
       "\"id_rows_mean\": %.1f, \"id_rows_max\": %d, \"id_cols_mean\": %.1f, \"id_cmac\": %.6e, "
-      "\"n_id_cols_gt64\": %lld, \"id_cmac_cols_gt64\": %.6e, "
+      "\"n_id_cols_gt64\": %lld, \"id_cmac_cols_gt64\": %.6e, \"id_cmac_cols_gt128\": %.6e, "
       "\"build_s\": %.6f, \"build_geometry_s\": %.6f, \"build_proxy_host_s\": %.6f, "
       "\"build_gpu_s\": %.6f, \"build_batch_host_setup_s\": %.6f, \"build_batch_total_s\": %.6f, "
       "\"build_compact_s\": %.6f, \"build_finalize_s\": %.6f}",
@@ -1676,9 +1688,12 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       (long long)ctx->nnz_v, (long long)ctx->nnz_w, (long long)ctx->nnz_k, (long long)ctx->nnz_d,
       (long long)ctx->Felems, (long long)(ctx->Felems * (int64_t)esz), (long long)ctx->ztotal,
       (long long)ctx->nid, ctx->rank_max, ctx->nid ? ctx->rank_sum / ctx->nid : 0.0,
-      (long long)ctx->entries_eval, ctx->nid ? ctx->id_m_sum / ctx->nid : 0.0, ctx->id_m_max,
+      (long long)ctx->entries_eval,
+      ctx->entry_slots ? (double)ctx->entries_eval / (double)ctx->entry_slots : 0.0,
+      (long long)ctx->nid_path[0], (long long)ctx->nid_path[2],
+      ctx->nid ? ctx->id_m_sum / ctx->nid : 0.0, ctx->id_m_max,
       ctx->nid ? ctx->id_n_sum / ctx->nid : 0.0, ctx->id_work, (long long)ctx->nid_wide,
-      ctx->id_work_wide, ctx->t_build, ctx->t_geo, ctx->t_host, ctx->t_gpu, ctx->t_prep,
+      ctx->id_work_wide, ctx->id_work_128, ctx->t_build, ctx->t_geo, ctx->t_host, ctx->t_gpu, ctx->t_prep,
       ctx->t_wait, ctx->t_compact,
       ctx->t_final);
   if (len < 0 || len >= cap) { ctx->err = "output buffer too small"; return HBI_ERR_ARG; }

@@ -289,6 +289,10 @@ def test_id_kernels_agree(torch_mod, monkeypatch, prec, tol, bound):
         say(f"{kind} rel err {e:.3e} rank mean {out[kind][1]['rank_mean']:.3f}")
         assert e < bound, (kind, e)
         op.close()
+    info = out["auto"][1]
+    say(f"auto paths: on chip {info['n_id_onchip']}, global {info['n_id_global']}")
+    assert info["n_id_onchip"] > 0 and info["n_id_global"] > 0, info
+    assert out["global"][1]["n_id_onchip"] == 0
     for kind in ("global", "blocked"):
         d = rel(out["auto"][0], out[kind][0])
         say(f"auto vs {kind} {d:.3e}")
