@@ -239,8 +239,10 @@ __device__ __forceinline__ double2 hb_value(int D, int nterms, double omega,
 // first sorted by branch through LDS so that every wave runs one branch at a
 // time over full lanes, then written out in place.
 // ---------------------------------------------------------------------------
-constexpr int kET_I = 128, kET_J = 16, kET_K = 32;
-constexpr int kET_N = kET_I * kET_J;   // entries per tile
+constexpr int kET_I = 128, kET_K = 32;
+// tile columns: 16 in 2D (entries are Hankel-heavy; the branch sort needs
+// the tile in LDS), 32 in 3D (entries are contraction-heavy)
+constexpr int et_cols(int D) { return D == 3 ? 32 : 16; }
 
 // HB value from the Hankel pair: (sqrt(pi)/2) v0 i H0 - sqrt(pi) (tau/omega) v1 i H1
 __device__ __forceinline__ double2 hb2d(const Hankel01 &H, double c0, double c1) {
@@ -254,8 +256,9 @@ __global__ __launch_bounds__(256, 2) void k_entries(
     const int32_t *slotbox, const double *Hcache, int nbox) {
   // contraction staging (sW: kET_K x kET_I, sH: 3 x kET_K x kET_J), reused by
   // the 2D epilogue as x, c0, c1 per entry plus the branch-sorted entry list
+  constexpr int kET_J = et_cols(D), CJ = kET_J / 8, kET_N = kET_I * kET_J;
   constexpr int kStage = kET_K * kET_I + 3 * kET_K * kET_J;
-  constexpr int kEpi = 3 * kET_N + kET_N / 4;
+  constexpr int kEpi = D == 2 ? 3 * kET_N + kET_N / 4 : 0;
   __shared__ double smem[kStage > kEpi ? kStage : kEpi];
   __shared__ int32_t srp[kET_I];
   __shared__ const double *shp[kET_J];
@@ -283,11 +286,11 @@ __global__ __launch_bounds__(256, 2) void k_entries(
   }
   __syncthreads();
   const int ty = tid >> 3, tx = tid & 7;
-  double acc[4][2][3];
+  double acc[4][CJ][3];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < CJ; ++c)
 #pragma unroll
       for (int t = 0; t < 3; ++t) acc[r][c][t] = 0.0;
   for (int a0 = 0; a0 < NTb; a0 += kET_K) {
@@ -312,23 +315,23 @@ __global__ __launch_bounds__(256, 2) void k_entries(
     __syncthreads();
 #pragma unroll 4
     for (int k = 0; k < kET_K; ++k) {
-      double w[4], h[3][2];
+      double w[4], h[3][CJ];
 #pragma unroll
       for (int r = 0; r < 4; ++r) w[r] = sW[k][ty * 4 + r];
 #pragma unroll
       for (int t = 0; t < 3; ++t)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) h[t][c] = sH[t][k][tx * 2 + c];
+        for (int c = 0; c < CJ; ++c) h[t][c] = sH[t][k][tx * CJ + c];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < CJ; ++c)
 #pragma unroll
           for (int t = 0; t < 3; ++t) acc[r][c][t] = fma(w[r], h[t][c], acc[r][c][t]);
     }
     __syncthreads();
   }
-  if (D == 3) {
+  if constexpr (D == 3) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int rr = ty * 4 + r;
@@ -336,8 +339,8 @@ __global__ __launch_bounds__(256, 2) void k_entries(
       const int i = rord[B.row_off + T.r0 + rr];
       const int32_t rp = srp[rr];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const int cc = tx * 2 + c;
+      for (int c = 0; c < CJ; ++c) {
+        const int cc = tx * CJ + c;
         if (cc >= T.nj) continue;
         const int j = T.j0 + cc;
         const int32_t cp = cols[B.col_off + j];
@@ -348,7 +351,7 @@ __global__ __launch_bounds__(256, 2) void k_entries(
       }
     }
     return;
-  }
+  } else {
   // ---- 2D: x, c0, c1 per entry (entry e = rr * kET_J + cc), branch 0..2 or
   // 3 (value already final: self term) or -1 (outside the tile)
   double *ex = smem, *ec0 = smem + kET_N, *ec1 = smem + 2 * kET_N;
@@ -449,6 +452,7 @@ __global__ __launch_bounds__(256, 2) void k_entries(
       const int e = rr * kET_J + cc;
       B.out[i + (int64_t)(T.j0 + cc) * B.m] = double2{ec0[e], ec1[e]};
     }
+  }
   }
 }
 

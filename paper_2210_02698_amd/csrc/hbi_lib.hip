@@ -349,8 +349,10 @@ static IdKernels id_kernels() {
   return ID_AUTO;
 }
 
-// entry tile shape (rows of one table box x columns), as k_entries takes it
-constexpr int32_t kEntryTileRows = 128, kEntryTileCols = 16;
+// entry tile shape (rows of one table box x columns), as k_entries takes it:
+// 16 columns in 2D, 32 in 3D
+constexpr int32_t kEntryTileRows = 128;
+static int32_t entry_tile_cols(int dim) { return dim == 3 ? 32 : 16; }
 
 struct Batcher {
   hbi_ctx *c;
@@ -437,7 +439,8 @@ struct Batcher {
     }
     const int64_t nrows = ro[nb], ncols = co[nb], nsl = so[nb], ncw = wco[nb], po = pivoff[nb];
     // rows in slot order (counting sort) and the number of entry tiles
-    // (kEntryTileRows rows of one slot x kEntryTileCols columns) per block
+    // (kEntryTileRows rows of one slot x tcols columns) per block
+    const int32_t tcols = entry_tile_cols(c->dim);
     std::vector<int32_t> rord(nrows), rslot(nrows);
     std::vector<int64_t> ntile(nb);
     parallel_for(nb, [&](int64_t qa, int64_t qb) {
@@ -455,7 +458,7 @@ struct Batcher {
         }
         for (int s2 = 0; s2 < ns; ++s2) cnt[s2 + 1] += cnt[s2];
         int64_t nt = 0;
-        const int64_t cj = (b.n + kEntryTileCols - 1) / kEntryTileCols;
+        const int64_t cj = (b.n + tcols - 1) / tcols;
         for (int s2 = 0; s2 < ns; ++s2)
           nt += (cnt[s2 + 1] - cnt[s2] + kEntryTileRows - 1) / kEntryTileRows * cj;
         ntile[q] = nt;
@@ -552,9 +555,9 @@ struct Batcher {
           int32_t r1 = r0;
           while (r1 < b.m && rs[rq[r1]] == s2) ++r1;
           for (int32_t a = r0; a < r1; a += kEntryTileRows)
-            for (int32_t j0 = 0; j0 < b.n; j0 += kEntryTileCols)
+            for (int32_t j0 = 0; j0 < b.n; j0 += tcols)
               *t++ = ETile{(int32_t)q, a, std::min(kEntryTileRows, r1 - a), j0,
-                           std::min(kEntryTileCols, b.n - j0), s2};
+                           std::min(tcols, b.n - j0), s2};
           r0 = r1;
         }
       }
@@ -575,7 +578,7 @@ struct Batcher {
                            c->ws.as<double>(), (const int32_t *)(ix + o_slot), hcache,
                            c->hc_nbox, c->stream));
     for (int64_t q = 0; q < nb; ++q) c->entries_eval += (int64_t)blocks[i0 + q].m * blocks[i0 + q].n;
-    c->entry_slots += ntiles * kEntryTileRows * kEntryTileCols;
+    c->entry_slots += ntiles * kEntryTileRows * tcols;
     if (id) {
       const IdBlock *ibd = (const IdBlock *)(ix + o_ib);
       const int32_t *seld = (const int32_t *)(ix + o_sel);
