@@ -1222,9 +1222,23 @@ __global__ __launch_bounds__(HBI_ID_THREADS) void k_cpqr_blocked(const IdBlock *
         const int col = it < i ? colmap[k0 + it] : colmap[k + 1 + (it - i)];
         const double2 *a = A + (int64_t)col * m;
         double2 d = double2{0.0, 0.0};
-        for (int r = k + lane; r < m; r += 64) {
-          const double2 v = r == k ? double2{1.0, 0.0} : (vlds ? reg[r] : pv[r]);
-          cfmac(d, a[r], v);   // d += conj(a) v
+        // rows k + lane + 64 t, kCpqrCB loads in flight per lane
+        constexpr int CB = 8;
+        for (int b = k; b < m; b += 64 * CB) {
+          double2 av[CB];
+#pragma unroll
+          for (int u = 0; u < CB; ++u) {
+            const int r = b + lane + 64 * u;
+            av[u] = r < m ? a[r] : double2{0.0, 0.0};
+          }
+#pragma unroll
+          for (int u = 0; u < CB; ++u) {
+            const int r = b + lane + 64 * u;
+            if (r < m) {
+              const double2 v = r == k ? double2{1.0, 0.0} : (vlds ? reg[r] : pv[r]);
+              cfmac(d, av[u], v);   // d += conj(a) v
+            }
+          }
         }
         d.x = wave_sum(d.x);
         d.y = wave_sum(d.y);
@@ -1272,7 +1286,7 @@ __global__ __launch_bounds__(HBI_ID_THREADS) void k_cpqr_blocked(const IdBlock *
       for (int r0 = k + 1; r0 < m; r0 += 64) {
         __syncthreads();
         if (tid < 64 * nb) {
-          const int rr = tid / nb, l = tid % nb, r = r0 + rr;
+          const int rr = tid & 63, l = tid >> 6, r = r0 + rr;   // V chunk, row fastest
           reg[tid] = r < m ? A[r + (int64_t)colmap[k0 + l] * m] : double2{0.0, 0.0};
         }
         __syncthreads();
@@ -1283,7 +1297,7 @@ __global__ __launch_bounds__(HBI_ID_THREADS) void k_cpqr_blocked(const IdBlock *
           if (r < m) {
             double2 a = A[r + (int64_t)j * m];
             for (int l = 0; l < nb; ++l) {
-              const double2 vv = reg[lane * nb + l];
+              const double2 vv = reg[l * 64 + lane];
               const double2 fl = F[j + l * nmax];
               a.x -= vv.x * fl.x + vv.y * fl.y;
               a.y -= vv.y * fl.x - vv.x * fl.y;
