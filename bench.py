@@ -141,12 +141,17 @@ def main():
         for _ in range(args.warmup):
             op.apply(s)
         torch.cuda.synchronize()
-        op.profile(True)
         t0 = time.perf_counter()
         for _ in range(args.steps):
             op.apply(s)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
+        # per-kernel HIP event timings: the same applies launched kernel by
+        # kernel with events between them (the timed loop replays a graph)
+        op.profile(True)
+        for _ in range(args.steps):
+            op.apply(s)
+        torch.cuda.synchronize()
         prof = op.profile(False)
         return dt, prof
 
