@@ -39,6 +39,14 @@ __device__ __forceinline__ void batched_dot(C &acc, int n, MF m, XF x) {
   }
 }
 template <typename C> struct LoadBatch { static constexpr int value = sizeof(C) == 8 ? 16 : 8; };
+// Factor entries are read once per product: non-temporal loads keep them
+// from displacing the skeleton vectors z in the caches.
+template <typename C> __device__ __forceinline__ C ldf(const C *p) {
+  using E = decltype(C{}.x);
+  typedef E V __attribute__((ext_vector_type(2)));
+  const V v = __builtin_nontemporal_load((const V *)p);
+  return C{v[0], v[1]};
+}
 
 // y[0..R) = M x for a column-major R x c matrix M streamed by one wave.
 // Lane l works on row l % R of column group l / R (G = 64 / R groups when
@@ -60,7 +68,7 @@ __device__ __forceinline__ void wave_gemv(const C *__restrict__ M, int Rt, int c
       const int step = G * Rt;
       const int nt = (c - grp + G - 1) / G;   // columns grp, grp + G, ...
       batched_dot<LoadBatch<C>::value, false>(
-          acc, nt, [&](int t) { return p[(int64_t)t * step]; },
+          acc, nt, [&](int t) { return ldf(p + (int64_t)t * step); },
           [&](int t) { return xat(grp + t * G); });
     }
     // combine the G partial sums of each row (lanes row, row+Rt, ...)
@@ -80,11 +88,19 @@ __device__ __forceinline__ void wave_gemv(const C *__restrict__ M, int Rt, int c
         C acc{0, 0};
         const C *p = M + row;
         batched_dot<LoadBatch<C>::value, false>(
-            acc, c, [&](int col) { return p[(int64_t)col * Rt]; }, [&](int col) { return xat(col); });
+            acc, c, [&](int col) { return ldf(p + (int64_t)col * Rt); }, [&](int col) { return xat(col); });
         store(row, acc);
       }
     }
   }
+}
+
+// Orders the LDS writes of a wave before its later LDS reads by other lanes
+// of the same wave (no other wave reads them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // One workgroup (4 waves) per leaf; wave w handles the HODBF levels
@@ -116,11 +132,12 @@ __global__ __launch_bounds__(256) void k_vstage(const cplx_t<R> *s,
 }
 
 // One wave per work item: rows [r0, r0 + 64) of a transfer unit (whole unit
-// when it has <= 64 rows).  Items are ordered by decreasing cost.  The unit's
-// input skeleton vector is staged in LDS when it has at most WX entries, so
-// the streamed factor block is the only vector-memory traffic of the loop.
-// (A persistent variant, each wave looping over items, measured slower: the
-// per-item wave-level fences serialise the streams.)
+// when it has <= 64 rows).  Items are ordered by decreasing cost, and the
+// factor store holds the units in that order.  The unit's input skeleton
+// vector is staged in the wave's own LDS slice when it has at most WX
+// entries, so the streamed factor block is the only vector-memory traffic
+// of the loop; the waves of a workgroup do not wait for each other.
+// (A persistent variant, each wave looping over items, measured slower.)
 template <typename R>
 __global__ __launch_bounds__(256) void k_wstage(const WItem *items, int64_t nitems,
                                                 const cplx_t<R> *F, cplx_t<R> *z) {
@@ -130,15 +147,8 @@ __global__ __launch_bounds__(256) void k_wstage(const WItem *items, int64_t nite
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t it = (int64_t)blockIdx.x * 4 + wave;
-  const bool active = it < nitems;
-  WItem U{};
-  if (active) {
-    U = items[it];
-    if (U.c <= WX)
-      for (int i = lane; i < U.c; i += 64) xs[wave][i] = z[U.zin + i];
-  }
-  __syncthreads();
-  if (!active) return;
+  if (it >= nitems) return;
+  const WItem U = items[it];
   C *za = z + U.zouta;
   C *zb = z + U.zoutb;
   const int ra = U.ra;
@@ -146,7 +156,9 @@ __global__ __launch_bounds__(256) void k_wstage(const WItem *items, int64_t nite
     if (row < ra) za[row] = v; else zb[row - ra] = v;
   };
   if (U.c <= WX) {
-    const C *xw = xs[wave];
+    C *xw = xs[wave];
+    for (int i = lane; i < U.c; i += 64) xw[i] = z[U.zin + i];
+    wave_lds_sync();
     wave_gemv<C>(F + U.foff, ra + U.rb, U.c, lane, [&](int col) { return xw[col]; }, store, U.off,
                  U.off + 64);
   } else {
@@ -185,14 +197,14 @@ __global__ __launch_bounds__(256) void k_final(const cplx_t<R> *s,
     if (wave == 0) {
       const C *Dm = F + lf.dense_off + lane;
       batched_dot<LoadBatch<C>::value, false>(
-          acc, sz, [&](int col) { return Dm[(int64_t)col * sz]; }, [&](int col) { return xs[col]; });
+          acc, sz, [&](int col) { return ldf(Dm + (int64_t)col * sz); }, [&](int col) { return xs[col]; });
     }
     for (int l = wave; l < Lv; l += 4) {
       const KDesc d = kd[(int64_t)g * Lv + l];
       const C *K = F + d.foff + lane;
       const C *zz = z + d.zin;
       batched_dot<LoadBatch<C>::value, false>(
-          acc, d.r, [&](int q) { return K[(int64_t)q * sz]; }, [&](int q) { return zz[q]; });
+          acc, d.r, [&](int q) { return ldf(K + (int64_t)q * sz); }, [&](int q) { return zz[q]; });
     }
   }
   part[wave][lane] = acc;
@@ -229,7 +241,7 @@ __global__ __launch_bounds__(256) void k_final_adj(const cplx_t<R> *y,
       const C *K = F + d.foff + (int64_t)lane * sz;
       C acc{0, 0};
       batched_dot<LoadBatch<C>::value, true>(
-          acc, sz, [&](int row) { return K[row]; }, [&](int row) { return ys[row]; });
+          acc, sz, [&](int row) { return ldf(K + row); }, [&](int row) { return ys[row]; });
       z[d.zin + lane] = acc;
     }
   }
@@ -253,9 +265,9 @@ __global__ __launch_bounds__(256) void k_wstage_adj(const WItem *items, int64_t 
     C acc{0, 0};
     const C *cm = M + (int64_t)col * Rt;
     batched_dot<LoadBatch<C>::value, true>(
-        acc, ra, [&](int i) { return cm[i]; }, [&](int i) { return wa[i]; });
+        acc, ra, [&](int i) { return ldf(cm + i); }, [&](int i) { return wa[i]; });
     batched_dot<LoadBatch<C>::value, true>(
-        acc, Rt - ra, [&](int i) { return cm[ra + i]; }, [&](int i) { return wb[i]; });
+        acc, Rt - ra, [&](int i) { return ldf(cm + ra + i); }, [&](int i) { return wb[i]; });
     z[U.zin + col] = acc;
   }
 }
@@ -284,14 +296,14 @@ __global__ __launch_bounds__(256) void k_vstage_adj(const cplx_t<R> *y,
       // dense leaf: (D^H y)[col], column `lane` of D is contiguous
       const C *Dc = F + lf.dense_off + (int64_t)lane * sz;
       batched_dot<LoadBatch<C>::value, true>(
-          acc, sz, [&](int row) { return Dc[row]; }, [&](int row) { return ys[row]; });
+          acc, sz, [&](int row) { return ldf(Dc + row); }, [&](int row) { return ys[row]; });
     }
     for (int l = wave; l < Lv; l += 4) {
       const VDesc d = vd[(int64_t)g * Lv + l];
       const C *V = F + d.foff + (int64_t)lane * d.r;
       const C *w = z + d.zout;
       batched_dot<LoadBatch<C>::value, true>(
-          acc, d.r, [&](int row) { return V[row]; }, [&](int row) { return w[row]; });
+          acc, d.r, [&](int row) { return ldf(V + row); }, [&](int row) { return w[row]; });
     }
   }
   part[wave][lane] = acc;

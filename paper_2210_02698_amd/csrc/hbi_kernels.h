@@ -8,6 +8,7 @@ namespace hbi {
 
 struct CopyDesc { const double2 *src; double2 *dst; int64_t count; };
 struct PairDesc { const double2 *xa, *xb; double2 *dst; int32_t ra, rb, c, pad; };
+struct PlaceDesc { const double2 *src; int64_t dst; int64_t count; };   // dst: element offset
 
 // Optional observer of apply launches (per-kernel event timing).
 struct LaunchHook {
@@ -67,7 +68,8 @@ hipError_t launch_cpqr_blocked(const IdBlock *blks, const int32_t *sel, int64_t 
                                int mmax, double tol, int32_t *rank, hipStream_t st);
 hipError_t launch_copy_blocks(const CopyDesc *d, int64_t nb, hipStream_t st);
 hipError_t launch_pack_pairs(const PairDesc *d, int64_t np, hipStream_t st);
-hipError_t launch_to_f32(const double2 *src, float2 *dst, int64_t n, hipStream_t st);
+hipError_t launch_place_blocks(const PlaceDesc *d, int64_t nb, void *F, bool f32,
+                               hipStream_t st);
 
 template <typename R>
 hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,

@@ -4,7 +4,7 @@
 //             k_entries
 //   bf_build  k_id_onchip, k_cpqr, k_cpqr_blocked (column-pivoted Householder
 //             QR + interpolation matrix), k_copy_blocks, k_pack_pairs,
-//             k_to_f32
+//             k_place_blocks
 // The apply kernels are in hbi_apply.hip, the multi-RHS ones in hbi_multi.hip.
 #include "hbi_kernels.h"
 #include "hbi_device.h"
@@ -1409,10 +1409,20 @@ __global__ void k_pack_pairs(const PairDesc *d, int64_t np) {
   }
 }
 
-__global__ void k_to_f32(const double2 *src, float2 *dst, int64_t n) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = float2{(float)src[i].x, (float)src[i].y};
+// Copy FP64 blocks to their places in the factor store (FP64 or rounded to
+// FP32), one workgroup per block.
+template <typename T>
+__global__ void k_place_blocks(const PlaceDesc *d, int64_t nb, T *F) {
+  const int64_t b = blockIdx.x;
+  if (b >= nb) return;
+  const PlaceDesc p = d[b];
+  T *dst = F + p.dst;
+  for (int64_t i = threadIdx.x; i < p.count; i += blockDim.x) {
+    const double2 v = p.src[i];
+    dst[i] = T{(decltype(T{}.x))v.x, (decltype(T{}.x))v.y};
+  }
 }
+
 
 // ---------------------------------------------------------------------------
 // Host-side launchers.
@@ -1587,11 +1597,15 @@ hipError_t launch_pack_pairs(const PairDesc *d, int64_t np, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_to_f32(const double2 *src, float2 *dst, int64_t n, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  const int T = 256;
-  hipLaunchKernelGGL(k_to_f32, dim3((n + T - 1) / T), dim3(T), 0, st, src, dst, n);
+hipError_t launch_place_blocks(const PlaceDesc *d, int64_t nb, void *F, bool f32,
+                               hipStream_t st) {
+  if (nb == 0) return hipSuccess;
+  if (f32)
+    hipLaunchKernelGGL(k_place_blocks<float2>, dim3(nb), dim3(256), 0, st, d, nb, (float2 *)F);
+  else
+    hipLaunchKernelGGL(k_place_blocks<double2>, dim3(nb), dim3(256), 0, st, d, nb, (double2 *)F);
   return hipGetLastError();
 }
+
 
 }  // namespace hbi

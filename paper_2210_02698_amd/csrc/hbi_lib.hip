@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <string>
 #include <vector>
@@ -665,6 +666,68 @@ struct HcCacheScope {
   ~HcCacheScope() { c->hc_cache.release(); c->hc_nbox = 0; }
 };
 
+// Final layout of the factor store.  The build leaves its blocks in chunks
+// in production order; the store places each block where its apply kernel
+// streams it, so that waves running at the same time read neighbouring
+// memory:
+//   V^0 blocks   leaf-major, level-minor (one workgroup per leaf);
+//   W^k units    per level, in the order of the forward stage's work items
+//                (heaviest first);
+//   leaf blocks  per leaf: the dense block, then its K^L blocks by level.
+// Every block offset (vd, units, leaves, kd) is rewritten to the new place;
+// the returned descriptors copy each block from its chunk.
+std::vector<PlaceDesc> layout_store(const std::vector<Chunk> &chunks, int Lv, int64_t nleaf,
+                                    std::vector<VDesc> &vd, std::vector<KDesc> &kd,
+                                    std::vector<LeafInfo> &leaves,
+                                    std::vector<std::vector<WUnit>> &units, int64_t Fg) {
+  // chunks are in store order (appended as the store grows)
+  auto src = [&](int64_t off, int64_t n) -> const double2 * {
+    auto it = std::upper_bound(chunks.begin(), chunks.end(), off,
+                               [](int64_t o, const Chunk &ch) { return o < ch.goff; });
+    if (it == chunks.begin() || off + n > (it - 1)->goff + (it - 1)->count)
+      throw Error{HBI_ERR_NUMERIC, "internal layout error in the factor store"};
+    return (it - 1)->buf.as<double2>() + (off - (it - 1)->goff);
+  };
+  std::vector<PlaceDesc> out;
+  int64_t cur = 0;
+  auto place = [&](int64_t &foff, int64_t n) {
+    if (n > 0) out.push_back(PlaceDesc{src(foff, n), cur, n});
+    foff = cur;
+    cur += n;
+  };
+  for (int64_t g = 0; g < nleaf; ++g)
+    for (int l = 0; l < Lv; ++l) {
+      VDesc &d = vd[g * Lv + l];
+      place(d.foff, (int64_t)d.r * leaves[g].size);
+    }
+  for (size_t k = 1; k < units.size(); ++k) {
+    std::vector<WUnit> &us = units[k];
+    // a unit's first forward item is its heaviest (64-row windows); items
+    // of equal weight keep the unit order
+    std::vector<std::pair<int64_t, int32_t>> ord(us.size());
+    for (size_t u = 0; u < us.size(); ++u)
+      ord[u] = {(int64_t)std::min(us[u].ra + us[u].rb, 64) * us[u].c, (int32_t)u};
+    std::stable_sort(ord.begin(), ord.end(), [](const std::pair<int64_t, int32_t> &a,
+                                                const std::pair<int64_t, int32_t> &b) {
+      return a.first > b.first;
+    });
+    for (const auto &o : ord) {
+      WUnit &U = us[o.second];
+      place(U.foff, (int64_t)(U.ra + U.rb) * U.c);
+    }
+  }
+  for (int64_t g = 0; g < nleaf; ++g) {
+    const int64_t sz = leaves[g].size;
+    place(leaves[g].dense_off, sz * sz);
+    for (int l = 0; l < Lv; ++l) {
+      KDesc &d = kd[g * Lv + l];
+      place(d.foff, sz * d.r);
+    }
+  }
+  if (cur != Fg) throw Error{HBI_ERR_NUMERIC, "internal layout error: factor store size"};
+  return out;
+}
+
 void build_factors(hbi_ctx *c, double tol) {
   const double tb0 = now_s();
   if (c->geo_leaf != c->leaf()) setup_cells(c);
@@ -956,16 +1019,14 @@ void build_factors(hbi_ctx *c, double tol) {
   c->Felems = Fg;
   const size_t esz = c->prec == HBI_F64 ? sizeof(double2) : sizeof(float2);
   HBI_HIP(c->F.alloc(esz * std::max<int64_t>(Fg, 1)));
-  for (auto &ch : chunks) {
-    if (ch.count == 0) continue;
-    if (c->prec == HBI_F64) {
-      HBI_HIP(hipMemcpyAsync(c->F.as<double2>() + ch.goff, ch.buf.p, sizeof(double2) * ch.count,
-                             hipMemcpyDeviceToDevice, c->stream));
-    } else {
-      HBI_HIP(launch_to_f32(ch.buf.as<double2>(), c->F.as<float2>() + ch.goff, ch.count, c->stream));
-    }
+  {
+    const std::vector<PlaceDesc> place = layout_store(chunks, Lv, nleaf, vd, kd, leaves, units, Fg);
+    DevBuf pd;
+    upload(pd, place);
+    HBI_HIP(launch_place_blocks(pd.as<PlaceDesc>(), (int64_t)place.size(), c->F.p,
+                                c->prec == HBI_F32, c->stream));
+    HBI_HIP(hipStreamSynchronize(c->stream));
   }
-  HBI_HIP(hipStreamSynchronize(c->stream));
   chunks.clear();
   upload(c->leaves_d, leaves);
   upload(c->vd_d, vd);
