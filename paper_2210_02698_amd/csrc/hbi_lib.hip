@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <functional>
 #include <limits>
 #include <memory>
 #include <string>
@@ -184,7 +186,6 @@ struct hbi_ctx {
   // build workspace; hc_cache holds the column side of every (cell, box)
   // pair during a build when it fits (hc_nbox boxes per cell, else empty)
   DevBuf ws, idx_d, hc_cache;
-  HostBuf stage_h;   // pinned staging of a batch's index upload
   int hc_nbox = 0;
   // factors and plan
   hbi_prec prec = HBI_F64;
@@ -355,8 +356,34 @@ static IdKernels id_kernels() {
 constexpr int32_t kEntryTileRows = 128;
 static int32_t entry_tile_cols(int dim) { return dim == 3 ? 32 : 16; }
 
+// One GPU batch of blocks.  prep() does all of its host-side set-up into a
+// pinned staging buffer without touching device memory; submit() sizes the
+// workspace, writes the device pointers, uploads and launches; finish()
+// waits and reads the ranks and pivots back.  Two staging buffers let the
+// host prepare batch j + 1 while the GPU runs batch j.
+struct Prepared {
+  const std::vector<BlockIn> *blocks = nullptr;
+  std::vector<BlockOut> *outs = nullptr;
+  std::function<void(int64_t, int64_t)> on_batch;   // after finish(), X still in the workspace
+  int64_t i0 = 0, i1 = 0, nb = 0;
+  int sbuf = 0;
+  bool id = false;
+  size_t ws_used = 0, idx_bytes = 0, up_bytes = 0;
+  size_t o_rows = 0, o_cols = 0, o_slot = 0, o_wc = 0, o_tl = 0, o_ro = 0, o_eb = 0, o_ib = 0,
+         o_sel = 0, o_piv = 0, o_rank = 0;
+  int64_t ncw = 0, ntiles = 0, po = 0;
+  int64_t nsel[3] = {0, 0, 0};
+  int nmax_g[3] = {1, 1, 1}, mmax_w = 1;
+  IdKernels idk = ID_AUTO;
+  double tol = 0;
+  std::vector<int64_t> wsoff, pivoff;
+  std::vector<int32_t> nslot;   // table slots per block of the batch
+  double t_submit = 0;
+};
+
 struct Batcher {
   hbi_ctx *c;
+  HostBuf stage[2];   // pinned staging: uploads and the rank/pivot read-back
   explicit Batcher(hbi_ctx *ctx) : c(ctx) {}
 
   // bytes of workspace a block needs
@@ -376,6 +403,71 @@ struct Batcher {
     return (int)slotbox.size();
   }
 
+  // Table slots of every block and the batch boundaries under the workspace
+  // budget; with `pairs`, blocks 2q and 2q+1 always go to the same batch.
+  struct Plan {
+    std::vector<std::vector<int32_t>> slots;
+    std::vector<int> nslot;
+    std::vector<std::pair<int64_t, int64_t>> batches;
+  };
+  Plan plan(const std::vector<BlockIn> &blocks, bool id, bool pairs) const {
+    Plan pl;
+    const int64_t nb = (int64_t)blocks.size();
+    const size_t budget = (size_t)c->wsbytes();
+    pl.slots.resize(nb);
+    pl.nslot.resize(nb);
+    parallel_for(nb, [&](int64_t a, int64_t b) {
+      for (int64_t i = a; i < b; ++i) pl.nslot[i] = count_slots(blocks[i], pl.slots[i]);
+    });
+    const int step = pairs ? 2 : 1;
+    int64_t i0 = 0;
+    while (i0 < nb) {
+      size_t used = 0;
+      int64_t i1 = i0;
+      while (i1 < nb) {
+        size_t need = 0;
+        for (int q = 0; q < step && i1 + q < nb; ++q)
+          need += ws_need(blocks[i1 + q].m, blocks[i1 + q].n, pl.nslot[i1 + q], id);
+        if (need > budget)
+          throw Error{HBI_ERR_OOM, "a single block (m=" + std::to_string(blocks[i1].m) + ", n=" +
+                                       std::to_string(blocks[i1].n) + ") exceeds the workspace"};
+        if (used + need > budget) break;
+        used += need;
+        i1 = std::min<int64_t>(nb, i1 + step);
+      }
+      pl.batches.push_back({i0, i1});
+      i0 = i1;
+    }
+    return pl;
+  }
+
+  // Runs batches handed out by next(P) (false when there are none left):
+  // batch j + 1 is prepared on the host while the GPU runs batch j.
+  template <class Next>
+  void pipeline(Next &&next) {
+    Prepared pa, pb;
+    Prepared *cur = &pa, *nxt = &pb;
+    int sb = 0;
+    cur->sbuf = sb;
+    try {
+      bool have = next(*cur);
+      while (have) {
+        submit(*cur);
+        sb ^= 1;
+        *nxt = Prepared();
+        nxt->sbuf = sb;
+        const bool have2 = next(*nxt);
+        finish(*cur);
+        std::swap(cur, nxt);
+        have = have2;
+      }
+    } catch (...) {
+      // no staging buffer or workspace may go while a copy or kernel uses it
+      (void)hipStreamSynchronize(c->stream);
+      throw;
+    }
+  }
+
   // Process blocks [0, nb) in as many GPU batches as the workspace needs.
   // id = true: evaluate into the workspace and run the ID, fill outs.
   // id = false: evaluate straight into blocks[i].out.
@@ -384,47 +476,34 @@ struct Batcher {
   template <class CB>
   void run(const std::vector<BlockIn> &blocks, bool id, double tol, std::vector<BlockOut> *outs,
            CB &&on_batch, bool pairs = false) {
-    const int64_t nb = (int64_t)blocks.size();
-    const size_t budget = (size_t)c->wsbytes();
-    std::vector<std::vector<int32_t>> slots(nb);
-    std::vector<int> nslot(nb);
-    parallel_for(nb, [&](int64_t a, int64_t b) {
-      for (int64_t i = a; i < b; ++i) nslot[i] = count_slots(blocks[i], slots[i]);
+    const Plan pl = plan(blocks, id, pairs);
+    size_t j = 0;
+    pipeline([&](Prepared &P) {
+      if (j == pl.batches.size()) return false;
+      prep(P, blocks, pl, pl.batches[j].first, pl.batches[j].second, id, tol);
+      ++j;
+      P.outs = outs;
+      P.on_batch = on_batch;
+      return true;
     });
-    int64_t i0 = 0;
-    while (i0 < nb) {
-      size_t used = 0;
-      int64_t i1 = i0;
-      // with `pairs`, blocks 2q and 2q+1 always go to the same batch
-      const int step = pairs ? 2 : 1;
-      while (i1 < nb) {
-        size_t need = 0;
-        for (int q = 0; q < step && i1 + q < nb; ++q)
-          need += ws_need(blocks[i1 + q].m, blocks[i1 + q].n, nslot[i1 + q], id);
-        if (need > budget)
-          throw Error{HBI_ERR_OOM, "a single block (m=" + std::to_string(blocks[i1].m) + ", n=" +
-                                       std::to_string(blocks[i1].n) + ") exceeds the workspace"};
-        if (used + need > budget) break;
-        used += need;
-        i1 = std::min<int64_t>(nb, i1 + step);
-      }
-      HBI_HIP(c->ws.reserve(used));   // grow-only; the previous batch has finished
-      run_batch(blocks, slots, nslot, i0, i1, id, tol, outs);
-      const double tc = now_s();
-      if (id) on_batch(i0, i1 - i0);
-      c->t_compact += now_s() - tc;
-      i0 = i1;
-    }
   }
 
-  void run_batch(const std::vector<BlockIn> &blocks, const std::vector<std::vector<int32_t>> &slots,
-                 const std::vector<int> &nslot, int64_t i0, int64_t i1, bool id, double tol,
-                 std::vector<BlockOut> *outs) {
+  // Host-side set-up of blocks [i0, i1) into staging buffer P.sbuf.
+  void prep(Prepared &P, const std::vector<BlockIn> &blocks, const Plan &pl, int64_t i0,
+            int64_t i1, bool id, double tol) {
     const double tb = now_s();
+    P.tol = tol;
+    P.blocks = &blocks;
+    P.i0 = i0; P.i1 = i1; P.id = id;
     const int64_t nb = i1 - i0;
+    P.nb = nb;
+    const auto &slots = pl.slots;
+    const auto &nslot = pl.nslot;
     // offsets of every block's rows, columns, slots and column-side work
-    std::vector<int64_t> ro(nb + 1, 0), co(nb + 1, 0), so(nb + 1, 0), wco(nb + 1, 0),
-        pivoff(nb + 1, 0), wsoff(nb + 1, 0), to(nb + 1, 0);
+    std::vector<int64_t> ro(nb + 1, 0), co(nb + 1, 0), so(nb + 1, 0), wco(nb + 1, 0), to(nb + 1, 0);
+    P.pivoff.assign(nb + 1, 0);
+    P.wsoff.assign(nb + 1, 0);
+    P.nslot.assign(nslot.begin() + i0, nslot.begin() + i1);
     for (int64_t q = 0; q < nb; ++q) {
       const BlockIn &b = blocks[i0 + q];
       const int ns = nslot[i0 + q];
@@ -432,18 +511,39 @@ struct Batcher {
       co[q + 1] = co[q] + b.n;
       so[q + 1] = so[q] + ns;
       wco[q + 1] = wco[q] + (int64_t)b.n * ns;
-      pivoff[q + 1] = pivoff[q] + (id ? b.n : 0);
-      size_t w = c->hc_cache.p ? 0 : align256((size_t)b.n * ns * 3 * c->NTb * sizeof(double));
-      if (id) w += align256((size_t)b.m * b.n * sizeof(double2)) +
-                   align256((size_t)std::min(b.m, b.n) * b.n * sizeof(double2));
-      wsoff[q + 1] = wsoff[q] + (int64_t)w;
+      P.pivoff[q + 1] = P.pivoff[q] + (id ? b.n : 0);
+      P.wsoff[q + 1] = P.wsoff[q] + (int64_t)ws_need(b.m, b.n, ns, id);
     }
-    const int64_t nrows = ro[nb], ncols = co[nb], nsl = so[nb], ncw = wco[nb], po = pivoff[nb];
+    P.ws_used = (size_t)P.wsoff[nb];
+    const int64_t nrows = ro[nb], ncols = co[nb], nsl = so[nb], ncw = wco[nb], po = P.pivoff[nb];
+    P.ncw = ncw;
+    P.po = po;
     // rows in slot order (counting sort) and the number of entry tiles
     // (kEntryTileRows rows of one slot x tcols columns) per block
     const int32_t tcols = entry_tile_cols(c->dim);
-    std::vector<int32_t> rord(nrows), rslot(nrows);
+    std::vector<int32_t> rslot(nrows);
     std::vector<int64_t> ntile(nb);
+    // ID kernel per block: on chip up to HBI_ID_ONCHIP_NMAX columns, the
+    // global-memory pivoted QR beyond; sel lists the groups.  (Group 1, the
+    // triangular factor on chip followed by the global pivoted QR of it for
+    // n <= 128, measured no faster than group 2 and is left empty.)
+    std::vector<int32_t> sel;
+    P.idk = id ? id_kernels() : ID_AUTO;
+    if (id) {
+      std::vector<int32_t> g[3];
+      for (int64_t q = 0; q < nb; ++q) {
+        const BlockIn &b = blocks[i0 + q];
+        const int k = P.idk != ID_AUTO || b.n > HBI_ID_ONCHIP_NMAX ? 2 : 0;
+        g[k].push_back((int32_t)q);
+        P.nmax_g[k] = std::max(P.nmax_g[k], (int)b.n);
+        if (k == 2) P.mmax_w = std::max(P.mmax_w, (int)b.m);
+      }
+      for (int k = 0; k < 3; ++k) {
+        P.nsel[k] = (int64_t)g[k].size();
+        sel.insert(sel.end(), g[k].begin(), g[k].end());
+      }
+    }
+    // the tile count needs the slot runs: first pass over the rows
     parallel_for(nb, [&](int64_t qa, int64_t qb) {
       std::vector<int32_t> cnt;
       for (int64_t q = qa; q < qb; ++q) {
@@ -457,86 +557,47 @@ struct Batcher {
           rs[i] = (int32_t)(std::find(sl.begin(), sl.end(), bx) - sl.begin());
           cnt[rs[i] + 1] += 1;
         }
-        for (int s2 = 0; s2 < ns; ++s2) cnt[s2 + 1] += cnt[s2];
         int64_t nt = 0;
         const int64_t cj = (b.n + tcols - 1) / tcols;
         for (int s2 = 0; s2 < ns; ++s2)
-          nt += (cnt[s2 + 1] - cnt[s2] + kEntryTileRows - 1) / kEntryTileRows * cj;
+          nt += (cnt[s2 + 1] + kEntryTileRows - 1) / kEntryTileRows * cj;
         ntile[q] = nt;
-        for (int32_t i = 0; i < b.m; ++i) rord[ro[q] + cnt[rs[i]]++] = i;
       }
     });
     for (int64_t q = 0; q < nb; ++q) to[q + 1] = to[q] + ntile[q];
     const int64_t ntiles = to[nb];
-    // ID kernel per block: on chip up to HBI_ID_ONCHIP_NMAX columns, the
-    // global-memory pivoted QR beyond; sel lists the groups.  (Group 1, the
-    // triangular factor on chip followed by the global pivoted QR of it for
-    // n <= 128, measured no faster than group 2 and is left empty.)
-    std::vector<int32_t> sel;
-    int64_t nsel[3] = {0, 0, 0};
-    int nmax_g[3] = {1, 1, 1}, mmax_w = 1;
-    const IdKernels idk = id ? id_kernels() : ID_AUTO;
-    if (id) {
-      std::vector<int32_t> g[3];
-      for (int64_t q = 0; q < nb; ++q) {
-        const BlockIn &b = blocks[i0 + q];
-        const int k = idk != ID_AUTO || b.n > HBI_ID_ONCHIP_NMAX ? 2 : 0;
-        g[k].push_back((int32_t)q);
-        nmax_g[k] = std::max(nmax_g[k], (int)b.n);
-        if (k == 2) mmax_w = std::max(mmax_w, (int)b.m);
-      }
-      for (int k = 0; k < 3; ++k) {
-        nsel[k] = (int64_t)g[k].size();
-        sel.insert(sel.end(), g[k].begin(), g[k].end());
-        c->nid_path[k] += nsel[k];
-      }
-    }
-    // one index upload from pinned host memory: rows, cols, slotbox, workc,
-    // tiles, rord, eb, ib, sel; then piv and rank come back
+    P.ntiles = ntiles;
+    // staging layout: rows, cols, slotbox, workc, tiles, rord, eb, ib, sel
+    // (uploaded), then piv and rank (read back)
     size_t off = 0;
     auto place = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
-    const size_t o_rows = place(nrows * 4), o_cols = place(ncols * 4), o_slot = place(nsl * 4),
-                 o_wc = place(ncw * 8), o_tl = place(ntiles * sizeof(ETile)),
-                 o_ro = place(nrows * 4), o_eb = place(nb * sizeof(EntryBlock)),
-                 o_ib = place(id ? nb * sizeof(IdBlock) : 0),
-                 o_sel = place(id ? (size_t)nb * 4 : 0), o_piv = place((size_t)po * 4),
-                 o_rank = place((size_t)nb * 4);
-    HBI_HIP(c->idx_d.reserve(off));
-    HBI_HIP(c->stage_h.reserve(o_piv));
-    char *ix = c->idx_d.as<char>();
-    char *st = c->stage_h.as<char>();
-    int32_t *rows = (int32_t *)(st + o_rows), *cols = (int32_t *)(st + o_cols),
-            *slotbox = (int32_t *)(st + o_slot), *workc = (int32_t *)(st + o_wc);
-    ETile *tiles = (ETile *)(st + o_tl);
-    EntryBlock *eb = (EntryBlock *)(st + o_eb);
-    IdBlock *ib = (IdBlock *)(st + o_ib);
-    std::memcpy(st + o_ro, rord.data(), nrows * 4);
-    if (id) std::memcpy(st + o_sel, sel.data(), sel.size() * 4);
-    char *ws = c->ws.as<char>();
+    P.o_rows = place(nrows * 4); P.o_cols = place(ncols * 4); P.o_slot = place(nsl * 4);
+    P.o_wc = place(ncw * 8); P.o_tl = place(ntiles * sizeof(ETile)); P.o_ro = place(nrows * 4);
+    P.o_eb = place(nb * sizeof(EntryBlock)); P.o_ib = place(id ? nb * sizeof(IdBlock) : 0);
+    P.o_sel = place(id ? (size_t)nb * 4 : 0); P.o_piv = place((size_t)po * 4);
+    P.o_rank = place((size_t)nb * 4);
+    P.idx_bytes = off;
+    P.up_bytes = P.o_piv;
+    HBI_HIP(stage[P.sbuf].reserve(off));
+    char *st = stage[P.sbuf].as<char>();
+    int32_t *rows = (int32_t *)(st + P.o_rows), *cols = (int32_t *)(st + P.o_cols),
+            *slotbox = (int32_t *)(st + P.o_slot), *workc = (int32_t *)(st + P.o_wc),
+            *rord = (int32_t *)(st + P.o_ro);
+    ETile *tiles = (ETile *)(st + P.o_tl);
+    if (id) std::memcpy(st + P.o_sel, sel.data(), sel.size() * 4);
     parallel_for(nb, [&](int64_t qa, int64_t qb) {
+      std::vector<int32_t> cnt;
       for (int64_t q = qa; q < qb; ++q) {
         const BlockIn &b = blocks[i0 + q];
         const std::vector<int32_t> &sl = slots[i0 + q];
         const int ns = nslot[i0 + q];
-        EntryBlock e{};
-        e.row_off = ro[q]; e.col_off = co[q]; e.slot_off = so[q];
-        e.m = b.m; e.n = b.n; e.nslot = ns;
-        size_t wso = (size_t)wsoff[q];
-        e.hc_off = (int64_t)(wso / sizeof(double));
-        if (!c->hc_cache.p) wso += align256((size_t)b.n * ns * 3 * c->NTb * sizeof(double));
-        if (id) {
-          IdBlock d{};
-          d.A = (double2 *)(ws + wso);
-          wso += align256((size_t)b.m * b.n * sizeof(double2));
-          d.X = (double2 *)(ws + wso);
-          d.m = b.m; d.n = b.n;
-          d.piv = (int32_t *)(ix + o_piv) + pivoff[q];
-          ib[q] = d;
-          e.out = d.A;
-        } else {
-          e.out = b.out;
-        }
-        eb[q] = e;
+        const int32_t *rs = rslot.data() + ro[q];
+        // rows in slot order
+        cnt.assign(ns + 1, 0);
+        for (int32_t i = 0; i < b.m; ++i) cnt[rs[i] + 1] += 1;
+        for (int s2 = 0; s2 < ns; ++s2) cnt[s2 + 1] += cnt[s2];
+        int32_t *rq = rord + ro[q];
+        for (int32_t i = 0; i < b.m; ++i) rq[cnt[rs[i]]++] = i;
         std::copy(b.rows, b.rows + b.m, rows + ro[q]);
         std::copy(b.cols, b.cols + b.n, cols + co[q]);
         std::copy(sl.begin(), sl.end(), slotbox + so[q]);
@@ -548,8 +609,6 @@ struct Batcher {
           }
         // tiles: slot runs of the sorted rows
         ETile *t = tiles + to[q];
-        const int32_t *rs = rslot.data() + ro[q];
-        const int32_t *rq = rord.data() + ro[q];
         int32_t r0 = 0;
         while (r0 < b.m) {
           const int s2 = rs[rq[r0]];
@@ -563,49 +622,98 @@ struct Batcher {
         }
       }
     });
+    for (int64_t q = 0; q < nb; ++q) c->entries_eval += (int64_t)blocks[i0 + q].m * blocks[i0 + q].n;
+    c->entry_slots += ntiles * kEntryTileRows * tcols;
+    for (int k = 0; k < 3; ++k) c->nid_path[k] += P.nsel[k];
     c->t_prep += now_s() - tb;   // host-side set-up of the batch
-    HBI_HIP(hipMemcpyAsync(ix, st, o_piv, hipMemcpyHostToDevice, c->stream));
-    const DevProblem P = c->devprob();
+  }
+
+  // Workspace and index buffer sized for P (the previous batch has
+  // finished), device pointers written into the staging copy of the block
+  // descriptors, upload and launches.
+  void submit(Prepared &P) {
+    P.t_submit = now_s();
+    const std::vector<BlockIn> &blocks = *P.blocks;
+    HBI_HIP(c->ws.reserve(P.ws_used));
+    HBI_HIP(c->idx_d.reserve(P.idx_bytes));
+    char *ix = c->idx_d.as<char>();
+    char *ws = c->ws.as<char>();
+    char *st = stage[P.sbuf].as<char>();
+    EntryBlock *eb = (EntryBlock *)(st + P.o_eb);
+    IdBlock *ib = (IdBlock *)(st + P.o_ib);
+    int64_t ro = 0, co = 0, so = 0;
+    for (int64_t q = 0; q < P.nb; ++q) {
+      const BlockIn &b = blocks[P.i0 + q];
+      const int32_t ns = P.nslot[q];
+      EntryBlock e{};
+      e.row_off = ro; e.col_off = co; e.slot_off = so;
+      e.m = b.m; e.n = b.n; e.nslot = ns;
+      size_t wso = (size_t)P.wsoff[q];
+      e.hc_off = (int64_t)(wso / sizeof(double));
+      if (!c->hc_cache.p) wso += align256((size_t)b.n * ns * 3 * c->NTb * sizeof(double));
+      if (P.id) {
+        IdBlock d{};
+        d.A = (double2 *)(ws + wso);
+        wso += align256((size_t)b.m * b.n * sizeof(double2));
+        d.X = (double2 *)(ws + wso);
+        d.m = b.m; d.n = b.n;
+        d.piv = (int32_t *)(ix + P.o_piv) + P.pivoff[q];
+        ib[q] = d;
+        e.out = d.A;
+      } else {
+        e.out = b.out;
+      }
+      eb[q] = e;
+      ro += b.m; co += b.n; so += ns;
+    }
+    HBI_HIP(hipMemcpyAsync(ix, st, P.up_bytes, hipMemcpyHostToDevice, c->stream));
+    const DevProblem Pr = c->devprob();
     const DevCells C = c->devcells();
     const DevTables T = c->devtables();
     const double *hcache = c->hc_cache.as<double>();
     if (!hcache)
-      HBI_HIP(launch_colside(P, C, T, (const EntryBlock *)(ix + o_eb),
-                             (const int32_t *)(ix + o_wc), ncw, (const int32_t *)(ix + o_cols),
-                             (const int32_t *)(ix + o_slot), c->ws.as<double>(), c->stream));
-    HBI_HIP(launch_entries(P, C, (const EntryBlock *)(ix + o_eb), (const ETile *)(ix + o_tl),
-                           ntiles, (const int32_t *)(ix + o_rows),
-                           (const int32_t *)(ix + o_ro), (const int32_t *)(ix + o_cols),
-                           c->ws.as<double>(), (const int32_t *)(ix + o_slot), hcache,
+      HBI_HIP(launch_colside(Pr, C, T, (const EntryBlock *)(ix + P.o_eb),
+                             (const int32_t *)(ix + P.o_wc), P.ncw, (const int32_t *)(ix + P.o_cols),
+                             (const int32_t *)(ix + P.o_slot), c->ws.as<double>(), c->stream));
+    HBI_HIP(launch_entries(Pr, C, (const EntryBlock *)(ix + P.o_eb), (const ETile *)(ix + P.o_tl),
+                           P.ntiles, (const int32_t *)(ix + P.o_rows),
+                           (const int32_t *)(ix + P.o_ro), (const int32_t *)(ix + P.o_cols),
+                           c->ws.as<double>(), (const int32_t *)(ix + P.o_slot), hcache,
                            c->hc_nbox, c->stream));
-    for (int64_t q = 0; q < nb; ++q) c->entries_eval += (int64_t)blocks[i0 + q].m * blocks[i0 + q].n;
-    c->entry_slots += ntiles * kEntryTileRows * tcols;
-    if (id) {
-      const IdBlock *ibd = (const IdBlock *)(ix + o_ib);
-      const int32_t *seld = (const int32_t *)(ix + o_sel);
-      int32_t *rankd = (int32_t *)(ix + o_rank);
-      HBI_HIP(launch_id_onchip(ibd, seld, nsel[0], nmax_g[0], tol, rankd, c->stream));
-      HBI_HIP(launch_id_onchip(ibd, seld + nsel[0], nsel[1], nmax_g[1], tol, rankd, c->stream));
-      if (idk == ID_BLOCKED)
-        HBI_HIP(launch_cpqr_blocked(ibd, seld + nsel[0] + nsel[1], nsel[2], nmax_g[2], mmax_w,
-                                    tol, rankd, c->stream));
+    if (P.id) {
+      const IdBlock *ibd = (const IdBlock *)(ix + P.o_ib);
+      const int32_t *seld = (const int32_t *)(ix + P.o_sel);
+      int32_t *rankd = (int32_t *)(ix + P.o_rank);
+      HBI_HIP(launch_id_onchip(ibd, seld, P.nsel[0], P.nmax_g[0], P.tol, rankd, c->stream));
+      HBI_HIP(launch_id_onchip(ibd, seld + P.nsel[0], P.nsel[1], P.nmax_g[1], P.tol, rankd, c->stream));
+      if (P.idk == ID_BLOCKED)
+        HBI_HIP(launch_cpqr_blocked(ibd, seld + P.nsel[0] + P.nsel[1], P.nsel[2], P.nmax_g[2],
+                                    P.mmax_w, P.tol, rankd, c->stream));
       else
-        HBI_HIP(launch_cpqr(ibd, seld + nsel[0] + nsel[1], nsel[2], nmax_g[2], mmax_w, tol,
-                            rankd, c->stream));
-      std::vector<int32_t> rank(nb), piv(po);
-      HBI_HIP(hipMemcpyAsync(rank.data(), ix + o_rank, nb * 4, hipMemcpyDeviceToHost, c->stream));
-      if (po) HBI_HIP(hipMemcpyAsync(piv.data(), ix + o_piv, po * 4, hipMemcpyDeviceToHost, c->stream));
-      HBI_HIP(hipStreamSynchronize(c->stream));
-      c->t_wait += now_s() - tb;
-      int64_t pp = 0;
-      for (int64_t q = 0; q < nb; ++q) {
-        BlockOut &o = (*outs)[i0 + q];
+        HBI_HIP(launch_cpqr(ibd, seld + P.nsel[0] + P.nsel[1], P.nsel[2], P.nmax_g[2], P.mmax_w,
+                            P.tol, rankd, c->stream));
+      // pivots and ranks back into the same staging buffer
+      HBI_HIP(hipMemcpyAsync(st + P.o_piv, ix + P.o_piv, P.idx_bytes - P.o_piv,
+                             hipMemcpyDeviceToHost, c->stream));
+    }
+  }
+
+  // Wait for P, take its ranks and pivots, then the caller's compaction.
+  void finish(Prepared &P) {
+    HBI_HIP(hipStreamSynchronize(c->stream));
+    c->t_wait += now_s() - P.t_submit;
+    if (P.id) {
+      const char *st = stage[P.sbuf].as<char>();
+      const IdBlock *ib = (const IdBlock *)(st + P.o_ib);
+      const int32_t *rank = (const int32_t *)(st + P.o_rank);
+      const int32_t *piv = (const int32_t *)(st + P.o_piv);
+      for (int64_t q = 0; q < P.nb; ++q) {
+        BlockOut &o = (*P.outs)[P.i0 + q];
         o.rank = rank[q];
         if (o.rank < 1 || o.rank > std::min(ib[q].m, ib[q].n))
           throw Error{HBI_ERR_NUMERIC, "interpolative decomposition returned an invalid rank"};
-        o.piv.assign(piv.begin() + pp, piv.begin() + pp + o.rank);
+        o.piv.assign(piv + P.pivoff[q], piv + P.pivoff[q] + o.rank);
         o.X = ib[q].X;
-        pp += ib[q].n;
         c->nid += 1;
         c->rank_max = std::max(c->rank_max, o.rank);
         c->rank_sum += o.rank;
@@ -620,9 +728,9 @@ struct Batcher {
         if (ib[q].n > 64) { c->id_work_wide += wk; c->nid_wide += 1; }
         if (ib[q].n > 128) c->id_work_128 += wk;
       }
-    } else {
-      HBI_HIP(hipStreamSynchronize(c->stream));
-      c->t_wait += now_s() - tb;
+      const double tc = now_s();
+      if (P.on_batch) P.on_batch(P.i0, P.nb);
+      c->t_compact += now_s() - tc;
     }
   }
 };
@@ -822,12 +930,31 @@ void build_factors(hbi_ctx *c, double tol) {
     std::vector<std::vector<int32_t>> skel_tmp(nblk);
     std::vector<int32_t> rank_tmp(nblk);
     std::vector<int64_t> foff_tmp(nblk);
+    // Blocks go to the GPU in chunks of CH: proxy rows and candidate columns
+    // on the host, then the chunk's batches.  The host builds chunk i + 1
+    // and prepares every next batch while the GPU runs the current one.
     const int64_t CH = 16384;
-    for (int64_t c0 = 0; c0 < nblk; c0 += CH) {
-      const int64_t c1 = std::min(nblk, c0 + CH);
+    struct ChunkJob {
+      int64_t c0 = 0, c1 = 0;
+      std::vector<std::vector<int32_t>> rows, cands;
+      std::vector<BlockIn> bin;
+      std::vector<int32_t> ncols;
+      std::vector<BlockOut> outs;
+      std::vector<int64_t> foff_local;
+      Batcher::Plan plan;
+      size_t next = 0, done = 0;
+    };
+    auto make_chunk = [&](int64_t c0) {
+      auto J = std::make_unique<ChunkJob>();
+      J->c0 = c0;
+      J->c1 = std::min(nblk, c0 + CH);
+      const int64_t n = J->c1 - c0;
       const double th = now_s();
-      std::vector<std::vector<int32_t>> rows(c1 - c0), cands(c1 - c0);
-      parallel_for(c1 - c0, [&](int64_t a, int64_t e) {
+      auto &rows = J->rows;
+      auto &cands = J->cands;
+      rows.resize(n);
+      cands.resize(n);
+      parallel_for(n, [&](int64_t a, int64_t e) {
         std::vector<int32_t> stamp(G.Nv, 0);
         int32_t tag = 0;
         for (int64_t q = a; q < e; ++q) {
@@ -853,30 +980,65 @@ void build_factors(hbi_ctx *c, double tol) {
         }
       });
       t_host += now_s() - th;
-      const double tg = now_s();
-      std::vector<BlockIn> bin(c1 - c0);
-      std::vector<int32_t> ncols(c1 - c0);
-      for (int64_t q = 0; q < c1 - c0; ++q) {
-        bin[q] = BlockIn{rows[q].data(), (int32_t)rows[q].size(), cands[q].data(),
-                         (int32_t)cands[q].size(), nullptr};
-        ncols[q] = (int32_t)cands[q].size();
-        if (ncols[q] > HBI_ID_NMAX)
+      J->bin.resize(n);
+      J->ncols.resize(n);
+      for (int64_t q = 0; q < n; ++q) {
+        J->bin[q] = BlockIn{rows[q].data(), (int32_t)rows[q].size(), cands[q].data(),
+                            (int32_t)cands[q].size(), nullptr};
+        J->ncols[q] = (int32_t)cands[q].size();
+        if (J->ncols[q] > HBI_ID_NMAX)
           throw Error{HBI_ERR_NUMERIC, "candidate set larger than the ID kernel supports"};
       }
-      std::vector<BlockOut> outs(c1 - c0);
-      std::vector<int64_t> foff_local(c1 - c0);
-      B.run(bin, true, tol, &outs, [&](int64_t first, int64_t cnt) {
-        compact(outs, first, cnt, ncols, foff_local, k > 0);
-      }, k > 0);
-      for (int64_t q = 0; q < c1 - c0; ++q) {
-        skel_tmp[c0 + q].resize(outs[q].rank);
-        for (int32_t r = 0; r < outs[q].rank; ++r) skel_tmp[c0 + q][r] = cands[q][outs[q].piv[r]];
-        rank_tmp[c0 + q] = outs[q].rank;
-        foff_tmp[c0 + q] = foff_local[q];
-        const int64_t e = (int64_t)outs[q].rank * ncols[q];
+      J->outs.resize(n);
+      J->foff_local.resize(n);
+      J->plan = B.plan(J->bin, true, k > 0);
+      return J;
+    };
+    auto chunk_done = [&](ChunkJob &J) {
+      for (int64_t q = 0; q < J.c1 - J.c0; ++q) {
+        const BlockOut &o = J.outs[q];
+        skel_tmp[J.c0 + q].resize(o.rank);
+        for (int32_t r = 0; r < o.rank; ++r) skel_tmp[J.c0 + q][r] = J.cands[q][o.piv[r]];
+        rank_tmp[J.c0 + q] = o.rank;
+        foff_tmp[J.c0 + q] = J.foff_local[q];
+        const int64_t e = (int64_t)o.rank * J.ncols[q];
         if (k == 0) c->nnz_v += e; else c->nnz_w += e;
       }
-      t_gpu += now_s() - tg;
+    };
+    {
+      std::deque<std::unique_ptr<ChunkJob>> live;   // chunks with batches not yet finished
+      std::vector<std::unique_ptr<ChunkJob>> finished;
+      // results of finished chunks into the level state, and their host
+      // arrays freed: done while the GPU runs the next batch
+      auto drain = [&]() {
+        for (auto &J : finished) chunk_done(*J);
+        finished.clear();
+      };
+      int64_t cnext = 0;
+      const double tg = now_s();
+      const double th0 = t_host;
+      B.pipeline([&](Prepared &P) {
+        drain();
+        if (live.empty() || live.back()->next == live.back()->plan.batches.size()) {
+          if (cnext >= nblk) return false;
+          live.push_back(make_chunk(cnext));
+          cnext = live.back()->c1;
+        }
+        ChunkJob *J = live.back().get();
+        const std::pair<int64_t, int64_t> bt = J->plan.batches[J->next++];
+        B.prep(P, J->bin, J->plan, bt.first, bt.second, true, tol);
+        P.outs = &J->outs;
+        P.on_batch = [&, J](int64_t first, int64_t cnt) {
+          compact(J->outs, first, cnt, J->ncols, J->foff_local, k > 0);
+          if (++J->done == J->plan.batches.size()) {
+            finished.push_back(std::move(live.front()));   // chunks finish in order
+            live.pop_front();
+          }
+        };
+        return true;
+      });
+      drain();
+      t_gpu += now_s() - tg - (t_host - th0);
     }
     // scatter into per-butterfly state (block index t * 2^(L-k) + j)
     for (int64_t q = 0; q < nblk; ++q) {
@@ -1015,7 +1177,8 @@ void build_factors(hbi_ctx *c, double tol) {
   const double tf = now_s();
   c->ws.release();
   c->idx_d.release();
-  c->stage_h.release();
+  B.stage[0].release();
+  B.stage[1].release();
   c->Felems = Fg;
   const size_t esz = c->prec == HBI_F64 ? sizeof(double2) : sizeof(float2);
   HBI_HIP(c->F.alloc(esz * std::max<int64_t>(Fg, 1)));
