@@ -71,7 +71,7 @@ def main():
     ap.add_argument("--oracle-rows", type=int, default=24)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=["bump", "batched", "3d"], default="bump",
+    ap.add_argument("--workload", choices=["bump", "batched", "3d", "sweep"], default="bump",
                     help="bump: the headline 1024^2 single-RHS apply; batched: 64 "
                          "constant-gradient problems with 1-256 RHS each; 3d: 64^3 sinusoid "
                          "with 32 RHS")
@@ -81,7 +81,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "one GPU only: the multi-GPU sharding is designed, not built; run with --gpus 1"}))
         sys.exit(2)
     if args.tol32 is None:
         args.tol32 = 1e-6 if args.workload == "3d" else 1e-5
@@ -248,17 +248,40 @@ def run_multi(args):
     import paper_2210_02698_amd as hbi
 
     dev = torch.device("cuda:0")
+    src, t_load, t_copy = None, 0.0, 0.0
     if args.workload == "batched":
         cases = hb_inputs.configs.c3(nprob=args.nprob)
         workload = (f"{len(cases)} 2D constant-gradient problems c(y)=1+g y, N_v in "
                     "{128^2, 256^2, 512^2}, 1-256 Gaussian-source RHS each, nI=13")
+    elif args.workload == "sweep":
+        # one table set (the HB ingredients do not depend on omega), operators
+        # at four frequencies built from it
+        import dataclasses
+        base = hb_inputs.configs.c4()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        src = hbi.Operator(base, device=0)
+        torch.cuda.synchronize()
+        t_load = time.perf_counter() - t0
+        cases = [(dataclasses.replace(base, omega=base.omega * f), 16,
+                  [hb_inputs.configs.CFG_SEED["c4"], 5, i])
+                 for i, f in enumerate((0.25, 0.5, 0.75, 1.0))]
+        workload = ("frequency sweep from one table set: 2D Gaussian-bump medium, 256x256 cells, "
+                    "tables 8x8 boxes x 8x8 nodes, omega = 16pi, 32pi, 48pi, 64pi, 16 RHS each")
     else:
         prob = hb_inputs.configs.c5()
         cases = [(prob, 32, [hb_inputs.configs.CFG_SEED["c5"], 0])]
         workload = "3D sinusoid n=1+0.2 sin2pi x sin2pi y sin2pi z, 64^3 cells, 32 RHS, nI=9"
     ops, S, t_build = [], [], 0.0
     for p, (prob, nrhs, seed) in enumerate(cases):
-        op = hbi.Operator(prob, device=0)
+        if src is not None:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            op = hbi.Operator.at_omega(src, prob.omega)
+            torch.cuda.synchronize()
+            t_copy += time.perf_counter() - t0
+        else:
+            op = hbi.Operator(prob, device=0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         op.build(tol=args.tol32, prec="f32")
@@ -286,7 +309,8 @@ def run_multi(args):
     flops = sum(8.0 * op.info()["nnz_total"] * c[1] for op, c in zip(ops, cases))
     # parity on sampled rows of a few problems
     errs = []
-    pick = [0] if len(cases) == 1 else sorted({0, len(cases) // 2, len(cases) - 1})
+    pick = ([0] if len(cases) == 1 else list(range(len(cases))) if src is not None
+            else sorted({0, len(cases) // 2, len(cases) - 1}))
     t_or, rows_done = 0.0, 0
     for p in pick:
         prob = cases[p][0]
@@ -319,6 +343,12 @@ def run_multi(args):
                          "sample": f"{rows_done} (row, RHS) outputs of the FP64 oracle on "
                                    f"problems {pick}, {t_or:.1f} s"},
     }
+    if src is not None:
+        line["sweep"] = {"omegas_over_pi": [round(c[0].omega / np.pi, 3) for c in cases],
+                         "table_load_s": round(t_load, 3),
+                         "table_copy_s_mean": round(t_copy / len(cases), 3),
+                         "rel_err_vs_oracle_per_omega": errs}
+        src.close()
     print(json.dumps(line), flush=True)
 
 

@@ -109,6 +109,18 @@ hbi_status hbi_set_stream(hbi_ctx *ctx, void *hip_stream);
  * earlier factors.  Synchronous. */
 hbi_status hbi_load_tables(hbi_ctx *ctx, const hbi_tables *t);
 
+/* Tables and cells of `src` at another angular frequency.  The HB
+ * ingredients tau, v0, v1 do not depend on omega (Sec. 2.2: tabulated once,
+ * reused for many frequencies), so a frequency sweep loads its tables once
+ * and gives every further context a device-to-device copy of them, with the
+ * cluster tree and per-cell data copied when the leaf sizes agree; only the
+ * self terms (App. A), which depend on omega, are evaluated again.  ctx and
+ * src are two contexts on the same device, or the same context (then only
+ * the frequency changes).  Drops the earlier factors of ctx; src keeps its
+ * own.  src must have tables (HBI_ERR_STATE otherwise); omega must be finite
+ * and > 0 (HBI_ERR_ARG).  Synchronous. */
+hbi_status hbi_load_tables_from(hbi_ctx *ctx, const hbi_ctx *src, double omega);
+
 /* Override compression parameters for later builds (NULL restores the
  * defaults). */
 hbi_status hbi_set_build_opts(hbi_ctx *ctx, const hbi_build_opts *opts);

@@ -52,6 +52,33 @@ class Operator:
         self._keep = []
         self.load(problem)
 
+    @classmethod
+    def at_omega(cls, src: "Operator", omega: float, stream=None) -> "Operator":
+        """A new operator with the tables and cells of ``src`` at angular
+        frequency ``omega`` (the HB ingredients do not depend on it; copied
+        on the device, only the self terms are evaluated again).  Build it
+        before applying."""
+        import torch
+        self = cls.__new__(cls)
+        self._lib = src._lib
+        self.device = src.device
+        self.dim, self.ncell, self.Nv, self.h = src.dim, src.ncell, src.Nv, src.h
+        self.prec = None
+        ctx = ctypes.c_void_p()
+        st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        _lib.check(self._lib.hbi_create(self.device.index, ctypes.c_void_p(st), ctypes.byref(ctx)))
+        self._ctx = ctx
+        self._keep = []
+        self._check(self._lib.hbi_load_tables_from(self._ctx, src._ctx, float(omega)))
+        return self
+
+    def set_omega(self, omega: float):
+        """Same tables and cells at angular frequency ``omega``; drops the
+        factors (build again before applying)."""
+        self._check(self._lib.hbi_load_tables_from(self._ctx, self._ctx, float(omega)))
+        self.prec = None
+        return self
+
     # -- marshalling helpers -------------------------------------------------
     def _check(self, status):
         _lib.check(status, self._ctx)

@@ -178,7 +178,7 @@ struct hbi_ctx {
   double origin[3] = {0, 0, 0}, h = 1, omega = 1, box_origin[3] = {0, 0, 0}, box_size = 1;
   std::vector<double> slow_nat;
   hbi_build_opts opts{};
-  int geo_leaf = -1;
+  int geo_leaf = -1, geo_band = -1;   // leaf size and band width the tree was built with
   Geometry geo;
   std::vector<int32_t> box_h;   // table box per tree position (host copy)
   // device cell data
@@ -289,11 +289,26 @@ template <class T> void upload(DevBuf &d, const std::vector<T> &h) {
 }
 
 // Geometry + per-cell device arrays for the current leaf size.
+// Self terms (App. A) of every cell at the context's omega.
+void eval_self_terms(hbi_ctx *c) {
+  const int64_t Nv = c->geo.Nv;
+  HBI_HIP(c->self_d.alloc(sizeof(double2) * Nv));
+  std::vector<double> gx, gw;
+  gauss_legendre01(32, gx, gw);
+  DevBuf gx_d, gw_d;
+  upload(gx_d, gx);
+  upload(gw_d, gw);
+  HBI_HIP(launch_self_terms(c->devprob(), c->slow_d.as<double>(), Nv, gx_d.as<double>(),
+                            gw_d.as<double>(), 32, c->self_d.as<double2>(), c->stream));
+  HBI_HIP(hipStreamSynchronize(c->stream));
+}
+
 void setup_cells(hbi_ctx *c) {
   const double t0 = now_s();
   c->geo.build(c->dim, c->ncell, c->leaf());
   c->geo.build_bands(c->band());
   c->geo_leaf = c->leaf();
+  c->geo_band = c->band();
   const int64_t Nv = c->geo.Nv;
   upload(c->perm_d, c->geo.perm);
   std::vector<double> slow_t(Nv);
@@ -302,18 +317,11 @@ void setup_cells(hbi_ctx *c) {
   HBI_HIP(c->xyz_d.alloc(sizeof(double) * 3 * Nv));
   HBI_HIP(c->lw_d.alloc(sizeof(double) * c->dim * c->nI * Nv));
   HBI_HIP(c->box_d.alloc(sizeof(int32_t) * Nv));
-  HBI_HIP(c->self_d.alloc(sizeof(double2) * Nv));
   const DevProblem P = c->devprob();
   HBI_HIP(launch_cell_setup(P, c->perm_d.as<int32_t>(), Nv, c->ncell, c->origin,
                             c->xyz_d.as<double>(), c->lw_d.as<double>(), c->box_d.as<int32_t>(),
                             c->stream));
-  std::vector<double> gx, gw;
-  gauss_legendre01(32, gx, gw);
-  DevBuf gx_d, gw_d;
-  upload(gx_d, gx);
-  upload(gw_d, gw);
-  HBI_HIP(launch_self_terms(P, c->slow_d.as<double>(), Nv, gx_d.as<double>(), gw_d.as<double>(),
-                            32, c->self_d.as<double2>(), c->stream));
+  eval_self_terms(c);
   c->box_h.resize(Nv);
   HBI_HIP(hipMemcpyAsync(c->box_h.data(), c->box_d.p, sizeof(int32_t) * Nv,
                          hipMemcpyDeviceToHost, c->stream));
@@ -838,7 +846,7 @@ std::vector<PlaceDesc> layout_store(const std::vector<Chunk> &chunks, int Lv, in
 
 void build_factors(hbi_ctx *c, double tol) {
   const double tb0 = now_s();
-  if (c->geo_leaf != c->leaf()) setup_cells(c);
+  if (c->geo_leaf != c->leaf() || c->geo_band != c->band()) setup_cells(c);
   HcCacheScope hc_scope{c};
   fill_hc_cache(c);
   Geometry &G = c->geo;
@@ -1762,6 +1770,62 @@ hbi_status hbi_load_tables(hbi_ctx *ctx, const hbi_tables *t) {
       upload(c->FT_d[k], tr);
     }
     setup_cells(c);
+    c->state = 1;
+  });
+}
+
+namespace {
+void copy_dev(DevBuf &dst, const DevBuf &src, hipStream_t st) {
+  HBI_HIP(dst.alloc(src.n));
+  if (src.n) HBI_HIP(hipMemcpyAsync(dst.p, src.p, src.n, hipMemcpyDeviceToDevice, st));
+}
+}  // namespace
+
+hbi_status hbi_load_tables_from(hbi_ctx *ctx, const hbi_ctx *src, double omega) {
+  if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
+  return guarded(ctx, [&]() {
+    HBI_REQUIRE(src, HBI_ERR_ARG, "src is NULL");
+    HBI_REQUIRE(std::isfinite(omega) && omega > 0, HBI_ERR_ARG, "omega must be finite and > 0");
+    HBI_REQUIRE(src->device == ctx->device, HBI_ERR_ARG, "src is on another device");
+    HBI_REQUIRE(src->state >= 1, HBI_ERR_STATE, "src has no tables");
+    hbi_ctx *c = ctx;
+    c->drop_factors();
+    if (c == src) {
+      c->omega = omega;
+      eval_self_terms(c);
+      c->state = 1;
+      return;
+    }
+    c->state = 0;
+    // tables are constant once loaded; src's stream may still run its own
+    // builds or applies, which only read them
+    HBI_HIP(hipStreamSynchronize(src->stream));
+    c->dim = src->dim; c->nterms = src->nterms; c->nI = src->nI;
+    c->NTb = src->NTb; c->NT = src->NT;
+    for (int a = 0; a < 3; ++a) {
+      c->ncell[a] = src->ncell[a]; c->nbox[a] = src->nbox[a];
+      c->origin[a] = src->origin[a]; c->box_origin[a] = src->box_origin[a];
+    }
+    c->h = src->h; c->box_size = src->box_size;
+    c->omega = omega;
+    c->slow_nat = src->slow_nat;
+    for (int k = 0; k < 3; ++k) copy_dev(c->FT_d[k], src->FT_d[k], c->stream);
+    if (src->geo_leaf == c->leaf() && src->geo_band == c->band()) {
+      // same cluster tree: copy it and the per-cell data
+      c->geo = src->geo;
+      c->geo_leaf = src->geo_leaf;
+      c->geo_band = src->geo_band;
+      copy_dev(c->perm_d, src->perm_d, c->stream);
+      copy_dev(c->slow_d, src->slow_d, c->stream);
+      copy_dev(c->xyz_d, src->xyz_d, c->stream);
+      copy_dev(c->lw_d, src->lw_d, c->stream);
+      copy_dev(c->box_d, src->box_d, c->stream);
+      c->box_h = src->box_h;
+      eval_self_terms(c);
+    } else {
+      setup_cells(c);
+    }
+    HBI_HIP(hipStreamSynchronize(c->stream));
     c->state = 1;
   });
 }

@@ -34,6 +34,12 @@ def test_rejected_calls_leave_context_usable():
     ctx2 = ctypes.c_void_p()
     assert lib.hbi_create(0, None, ctypes.byref(ctx2)) == _lib.HBI_OK
     assert lib.hbi_build(ctx2, 1e-7, 0) == _lib.HBI_ERR_STATE
+    # frequency sweep: a source without tables, a bad frequency, no source
+    assert lib.hbi_load_tables_from(ctx, ctx2, 1.0) == _lib.HBI_ERR_STATE
+    assert b"no tables" in lib.hbi_last_error(ctx)
+    assert lib.hbi_load_tables_from(ctx2, ctx, -1.0) == _lib.HBI_ERR_ARG
+    assert lib.hbi_load_tables_from(ctx2, ctx, float("nan")) == _lib.HBI_ERR_ARG
+    assert lib.hbi_load_tables_from(ctx2, None, 1.0) == _lib.HBI_ERR_ARG
     assert lib.hbi_destroy(ctx2) == _lib.HBI_OK
     # bad tables
     t = _lib.hbi_tables()

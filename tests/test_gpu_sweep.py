@@ -1,0 +1,114 @@
+"""Frequency sweep from one table set (hbi_load_tables_from).
+
+The HB ingredients tau, v0, v1 do not depend on omega (Sec. 2.2: computed
+once, reused for many frequencies), so operators at several frequencies are
+built from one loaded table set.  Checked here: a copy at the same omega is
+the same operator bit for bit; at other frequencies each operator matches
+the dense FP64 oracle at that frequency; the in-place change of omega equals
+the copy; the sweep's operators run together in one batched apply.
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+import hb_inputs
+import oracle
+from _hbi_util import ensure_built, requires_gpu
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    ensure_built()
+    import torch
+    return torch
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+_DENSE = {}
+
+
+def dense_at(prob, omega):
+    """The oracle's dense K of `prob` at angular frequency omega (cached)."""
+    if omega not in _DENSE:
+        _DENSE[omega] = oracle.dense(dataclasses.replace(prob, omega=omega))
+    return _DENSE[omega]
+
+
+def test_same_omega_is_the_same_operator(torch_mod):
+    torch = torch_mod
+    import paper_2210_02698_amd as hbi
+    prob = hb_inputs.configs.c2(64, nbox=4)
+    say("sweep copy at the same omega, bump 64^2")
+    a = hbi.Operator(prob, device=0).build(tol=1e-7, prec="f64")
+    b = hbi.Operator.at_omega(a, prob.omega).build(tol=1e-7, prec="f64")
+    s = torch.from_numpy(hb_inputs.complex_normal(prob.Nv, [21, 0])).to("cuda:0")
+    assert torch.equal(a.apply(s), b.apply(s))
+    assert torch.equal(a.apply_adjoint(s), b.apply_adjoint(s))
+    ia, ib = a.info(), b.info()
+    for k in ("nnz_total", "rank_max", "n_id", "L_v"):
+        assert ia[k] == ib[k], k
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("prec,tol,bound", [("f64", 1e-7, 1e-6), ("f32", 1e-5, 1e-4)])
+def test_sweep_matches_oracle_at_each_frequency(torch_mod, prec, tol, bound):
+    """Homogeneous 64^2 medium, tables loaded once at omega = 16 pi; operators
+    at 8 pi, 16 pi and 24 pi (16, 8 and 5.3 cells per wavelength) against the
+    dense oracle at each frequency; the in-place change of omega on the
+    loaded context gives the copy's operator bit for bit."""
+    torch = torch_mod
+    import paper_2210_02698_amd as hbi
+    base = hb_inputs.configs.c1()
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    src = hbi.Operator(base, device=0)
+    s_h = hb_inputs.complex_normal(base.Nv, [22, 0])
+    s = torch.from_numpy(s_h).to("cuda:0").to(dt)
+    for w in (8 * math.pi, 16 * math.pi, 24 * math.pi):
+        say(f"sweep {prec} omega {w / math.pi:.0f} pi")
+        op = hbi.Operator.at_omega(src, w).build(tol=tol, prec=prec)
+        u = op.apply(s).cpu().numpy().astype(np.complex128)
+        K = dense_at(base, w)
+        ref = K @ (s_h * base.h ** 2)
+        e = rel(u, ref)
+        say(f"  rel err {e:.2e}")
+        assert e < bound, (w, e)
+        # the same frequency set in place on a loaded context
+        src.set_omega(w).build(tol=tol, prec=prec)
+        assert torch.equal(src.apply(s), op.apply(s))
+        op.close()
+    src.close()
+
+
+def test_sweep_batched_apply(torch_mod):
+    """The sweep's operators (FP32 factors) in one batched call, 8 RHS each,
+    against their single-RHS applies (MFMA tiles: FP32 rounding order)."""
+    torch = torch_mod
+    import paper_2210_02698_amd as hbi
+    prob = hb_inputs.configs.c2(64, nbox=4)
+    say("sweep batched apply, bump 64^2, 3 frequencies x 8 RHS")
+    src = hbi.Operator(prob, device=0)
+    ops = [hbi.Operator.at_omega(src, prob.omega * f).build(tol=1e-5, prec="f32")
+           for f in (0.5, 0.75, 1.0)]
+    S = [torch.from_numpy(hb_inputs.complex_normal((8, prob.Nv), [23, i])).to("cuda:0")
+         .to(torch.complex64).t() for i in range(len(ops))]
+    U = hbi.apply_batched(ops, S)
+    for op, s, u in zip(ops, S, U):
+        for r in (0, 5):
+            ur = op.apply(s[:, r].contiguous())
+            e = (torch.linalg.norm(u[:, r] - ur) / torch.linalg.norm(ur)).item()
+            assert e < 2e-5, e
+    for op in ops:
+        op.close()
+    src.close()
