@@ -1,0 +1,38 @@
+"""Curve inclusions for the HB integrator (Sec. 3.1, domain with inclusion):
+a closed curve C discretised into N_s straight segments, given by their
+centres r^s_i, lengths w_i and the slowness n(r^s_i) of the medium there.
+Geometry only; none of the integrator's arithmetic."""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Curve:
+    centres: np.ndarray    # (N_s, 2) segment centres
+    w: np.ndarray          # (N_s,) segment lengths
+    slowness: np.ndarray   # (N_s,) n at the segment centres
+    name: str = ""
+
+    @property
+    def Ns(self) -> int:
+        return int(self.w.shape[0])
+
+
+def circle(prob, centre, radius, ns, name=None) -> Curve:
+    """The polygon of ns equal chords inscribed in the circle |r - centre| =
+    radius (vertices at angles 2 pi k / ns): segment centres are the chord
+    midpoints, lengths 2 radius sin(pi / ns)."""
+    if prob.dim != 2:
+        raise ValueError("curve inclusions are 2D")
+    c = np.asarray(centre, np.float64)
+    mid = (np.arange(ns, dtype=np.float64) + 0.5) * (2.0 * math.pi / ns)
+    rm = radius * math.cos(math.pi / ns)
+    P = c + rm * np.stack([np.cos(mid), np.sin(mid)], axis=1)
+    w = np.full(ns, 2.0 * radius * math.sin(math.pi / ns))
+    n = np.ascontiguousarray(prob.meta["medium"].slowness(P), dtype=np.float64)
+    return Curve(centres=np.ascontiguousarray(P), w=w, slowness=n,
+                 name=name or f"circle-c{tuple(c)}-r{radius}-ns{ns}")

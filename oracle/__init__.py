@@ -16,11 +16,13 @@ U = K (h^d s) (Sec. 3.1, eq. m_v2v), with
     (Appendix A: lemma eq. HankelIntegral2dlemma in 2D, Q_s of eq. e312 in
     3D).
 Every function is dense and O(N_v) per output row; nothing is compressed.
+``oracle.inclusion`` adds the curve inclusion of eq. m_v2v_inclu.
 """
 from .hb_oracle import (cheb_nodes, lagrange_1d, interp_weights, interpolate,
                         hb_terms, self_term, entries, apply, apply_adjoint,
                         dense)
+from . import inclusion
 
 __all__ = ["cheb_nodes", "lagrange_1d", "interp_weights", "interpolate",
            "hb_terms", "self_term", "entries", "apply", "apply_adjoint",
-           "dense"]
+           "dense", "inclusion"]

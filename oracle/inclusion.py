@@ -1,0 +1,97 @@
+"""Dense FP64 oracle of the HB integrator with a curve inclusion
+(Sec. 3.1, domain with inclusion; test infrastructure only).
+
+    U = (K^{v2v} + K^{s2v} (K^{s2s})^{-1} K^{v2s}) I,   I = h^d s
+                                                    (eq. m_v2v_inclu)
+with, for segment centres r^s_i of lengths w_i and cell centres r_j,
+    K^{v2s}_ij = g(r^s_i, r_j)                          (eq. m_v2s)
+    K^{s2v}_ij = g(r_i, r^s_j) w_j                      (eq. m_s2v)
+    K^{s2s}_ij = -g(r^s_i, r^s_j) w_j,  i != j          (eq. s2s)
+    K^{s2s}_ii = minus the integral of the leading HB term over segment i
+                 in its small-segment closed form
+                 -(i w_i / 4) [1 + (2i/pi)(log(e^gamma omega n_i w_i / 4) - 1)]
+where g is the HB ansatz evaluated from the tables (eq. babich, N = 1).
+The printed diagonal of eq. s2s lacks the factor i of the leading term
+(i/4) H0 and writes the Euler constant where e^gamma belongs; the reading
+above is the exact integral's small-argument expansion, pinned against
+quadrature in the tests.  The system K^{s2s} P = K^{v2s} I (eq. m_sie)
+enforces u^inc + u^sca = 0 at the segment centres.
+
+Pins (tests/test_inclusion_pins.py): the diagonal against quadrature of the
+segment integral; the whole operator, in a homogeneous medium where the
+ansatz is the exact Green's function, against the series solution of
+scattering by a disc with zero boundary values, converging as N_s grows;
+K^{s2v} against the transpose of K^{v2s} (symmetric tables).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .hb_oracle import apply as v2v_apply
+from .hb_oracle import apply_adjoint as v2v_apply_adjoint
+from .hb_oracle import hb_terms, interpolate
+
+
+def point_kernel(prob, Pr, Pc, skip_diagonal=False):
+    """g(r, r0) of the HB ansatz from the tables for observation points Pr
+    and source points Pc, complex128 (len(Pr), len(Pc)); with skip_diagonal
+    (Pr and Pc the same points) the diagonal is left 0."""
+    Pr = np.atleast_2d(np.asarray(Pr, np.float64))
+    Pc = np.atleast_2d(np.asarray(Pc, np.float64))
+    tau = np.sqrt(np.maximum(interpolate(prob, prob.tau2, Pr, Pc), 0.0))
+    if skip_diagonal:
+        np.fill_diagonal(tau, 1.0)
+    f0, f1 = hb_terms(prob.dim, prob.omega, tau)
+    K = interpolate(prob, prob.v0, Pr, Pc) * f0
+    if prob.nterms == 2:
+        K = K + interpolate(prob, prob.v1, Pr, Pc) * f1
+    if skip_diagonal:
+        np.fill_diagonal(K, 0.0)
+    return K
+
+
+def segment_self(prob, w, n):
+    """K^{s2s}_ii for a segment of length w where the slowness is n."""
+    w = np.asarray(w, np.float64)
+    L = np.euler_gamma + np.log(prob.omega * np.asarray(n, np.float64) * w / 4.0)
+    return -(1j * w / 4.0) * (1.0 + (2j / math.pi) * (L - 1.0))
+
+
+def v2s(prob, curve, cols=None):
+    """K^{v2s}[:, cols] (N_s x len(cols)); cols in natural cell order."""
+    cols = np.arange(prob.Nv) if cols is None else np.asarray(cols, np.int64)
+    return point_kernel(prob, curve.centres, prob.centres(cols))
+
+
+def s2v(prob, curve, rows=None):
+    """K^{s2v}[rows] (len(rows) x N_s)."""
+    rows = np.arange(prob.Nv) if rows is None else np.asarray(rows, np.int64)
+    return point_kernel(prob, prob.centres(rows), curve.centres) * curve.w[None, :]
+
+
+def s2s(prob, curve):
+    """K^{s2s} (N_s x N_s)."""
+    ns = curve.Ns
+    G = point_kernel(prob, curve.centres, curve.centres, skip_diagonal=True)
+    K = -G * curve.w[None, :]
+    K[np.arange(ns), np.arange(ns)] = segment_self(prob, curve.w, curve.slowness)
+    return K
+
+
+def apply(prob, curve, s, rows=None):
+    """U[rows] of eq. m_v2v_inclu for sources s ((N_v,) or (N_v, nrhs))."""
+    s = np.asarray(s, np.complex128)
+    I = s * prob.h ** prob.dim
+    P = np.linalg.solve(s2s(prob, curve), v2s(prob, curve) @ I)   # eq. m_sie, m_v2s
+    return v2v_apply(prob, s, rows) + s2v(prob, curve, rows) @ P  # eq. m_s2v
+
+
+def apply_adjoint(prob, curve, s, cols=None):
+    """(T^H s)[cols] for the total operator T = (K^{v2v} + K^{s2v}
+    (K^{s2s})^{-1} K^{v2s}) h^d of eq. m_v2v_inclu."""
+    s = np.asarray(s, np.complex128)
+    Q = np.linalg.solve(s2s(prob, curve).conj().T, s2v(prob, curve).conj().T @ s)
+    return v2v_apply_adjoint(prob, s, cols) + \
+        prob.h ** prob.dim * (v2s(prob, curve, cols).conj().T @ Q)
