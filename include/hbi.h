@@ -116,10 +116,29 @@ hbi_status hbi_load_tables(hbi_ctx *ctx, const hbi_tables *t);
  * cluster tree and per-cell data copied when the leaf sizes agree; only the
  * self terms (App. A), which depend on omega, are evaluated again.  ctx and
  * src are two contexts on the same device, or the same context (then only
- * the frequency changes).  Drops the earlier factors of ctx; src keeps its
- * own.  src must have tables (HBI_ERR_STATE otherwise); omega must be finite
+ * the frequency changes).  A curve inclusion of src (hbi_set_inclusion) is
+ * copied too.  Drops the earlier factors of ctx; src keeps its own.  src must have tables (HBI_ERR_STATE otherwise); omega must be finite
  * and > 0 (HBI_ERR_ARG).  Synchronous. */
 hbi_status hbi_load_tables_from(hbi_ctx *ctx, const hbi_ctx *src, double omega);
+
+/* A curve inclusion (Sec. 3.1, domain with inclusion; 2D): ns straight
+ * segments with centres (xy[2i], xy[2i+1]), lengths w[i] > 0 and slowness
+ * slowness[i] > 0 of the medium at the centres (host arrays, copied; the
+ * centres must lie in the table region; 0 <= ns <= 8192, ns = 0 removes the
+ * inclusion).  Later builds assemble, besides the volume factors, the dense
+ * array G[j, i] = g(r_j, r^s_i) over cells and segments (N_v x ns entries,
+ * read as K^{v2s} = G^T and K^{s2v} = G diag(w): the tables are symmetric)
+ * and the inverse of K^{s2s} (eq. s2s, by Gauss-Jordan elimination with row
+ * pivoting in FP64; HBI_ERR_NUMERIC if it is singular), both in the factors'
+ * precision.  hbi_apply and hbi_apply_adjoint then apply the total operator
+ * of eq. m_v2v_inclu, (K^{v2v} + K^{s2v} (K^{s2s})^{-1} K^{v2s}) h^d, and its
+ * conjugate transpose; hbi_apply_batched rejects such contexts.  The
+ * diagonal of K^{s2s} is -(i w/4)[1 + (2i/pi)(log(e^gamma omega n w/4) - 1)],
+ * minus the integral of the leading HB term over the segment.  Needs
+ * tables (HBI_ERR_STATE); drops the factors; hbi_load_tables removes the
+ * inclusion, hbi_load_tables_from copies the source's.  Synchronous. */
+hbi_status hbi_set_inclusion(hbi_ctx *ctx, int32_t ns, const double *xy, const double *w,
+                             const double *slowness);
 
 /* Override compression parameters for later builds (NULL restores the
  * defaults). */

@@ -6,6 +6,8 @@
 with, for segment centres r^s_i of lengths w_i and cell centres r_j,
     K^{v2s}_ij = g(r^s_i, r_j)                          (eq. m_v2s)
     K^{s2v}_ij = g(r_i, r^s_j) w_j                      (eq. m_s2v)
+                 (for a segment centre inside cell j, g is that cell's self
+                 term: the cell average of the leading HB term, App. A)
     K^{s2s}_ij = -g(r^s_i, r^s_j) w_j,  i != j          (eq. s2s)
     K^{s2s}_ii = minus the integral of the leading HB term over segment i
                  in its small-segment closed form
@@ -31,7 +33,7 @@ import numpy as np
 
 from .hb_oracle import apply as v2v_apply
 from .hb_oracle import apply_adjoint as v2v_apply_adjoint
-from .hb_oracle import hb_terms, interpolate
+from .hb_oracle import hb_terms, interpolate, self_term
 
 
 def point_kernel(prob, Pr, Pc, skip_diagonal=False):
@@ -59,16 +61,55 @@ def segment_self(prob, w, n):
     return -(1j * w / 4.0) * (1.0 + (2j / math.pi) * (L - 1.0))
 
 
+def containing_cell(prob, P):
+    """Natural index of the cell floor((x - origin)/h) (clamped) holding
+    each point."""
+    P = np.atleast_2d(np.asarray(P, np.float64))
+    nat = np.zeros(P.shape[0], np.int64)
+    stride = 1
+    for ax in range(prob.dim):
+        k = np.floor((P[:, ax] - prob.origin[ax]) / prob.h).astype(np.int64)
+        nat += np.clip(k, 0, prob.ncell[ax] - 1) * stride
+        stride *= prob.ncell[ax]
+    return nat
+
+
+def _segment_cell_kernel(prob, curve, cells):
+    """g between every segment centre and the cells `cells`
+    ((N_s, len(cells))).  A segment centre lying in a cell is paired with
+    that cell through the cell's self term (the cell average of the leading
+    HB term, App. A): the point value of the log-singular kernel at
+    sub-cell distances is not resolved by the tables (the paper is silent;
+    this is the reading)."""
+    with np.errstate(invalid="ignore", divide="ignore"):
+        G = point_kernel(prob, curve.centres, prob.centres(cells))
+    own = containing_cell(prob, curve.centres)
+    pos = {int(c): k for k, c in enumerate(cells)}
+    for i, c in enumerate(own):
+        if int(c) in pos:
+            G[i, pos[int(c)]] = self_term(prob, prob.slowness[c])
+    return G
+
+
 def v2s(prob, curve, cols=None):
     """K^{v2s}[:, cols] (N_s x len(cols)); cols in natural cell order."""
     cols = np.arange(prob.Nv) if cols is None else np.asarray(cols, np.int64)
-    return point_kernel(prob, curve.centres, prob.centres(cols))
+    return _segment_cell_kernel(prob, curve, cols)
 
 
 def s2v(prob, curve, rows=None):
-    """K^{s2v}[rows] (len(rows) x N_s)."""
+    """K^{s2v}[rows] (len(rows) x N_s): g(r_j, r^s_i) w_i, with the same
+    pairing of a segment centre and its cell as K^{v2s} (g is reciprocal for
+    symmetric tables)."""
     rows = np.arange(prob.Nv) if rows is None else np.asarray(rows, np.int64)
-    return point_kernel(prob, prob.centres(rows), curve.centres) * curve.w[None, :]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        G = point_kernel(prob, prob.centres(rows), curve.centres)
+    own = containing_cell(prob, curve.centres)
+    pos = {int(r): k for k, r in enumerate(rows)}
+    for i, c in enumerate(own):
+        if int(c) in pos:
+            G[pos[int(c)], i] = self_term(prob, prob.slowness[c])
+    return G * curve.w[None, :]
 
 
 def s2s(prob, curve):

@@ -107,6 +107,24 @@ class Operator:
         self._check(self._lib.hbi_load_tables(self._ctx, ctypes.byref(t)))
         self.prec = None
 
+    def set_inclusion(self, curve=None):
+        """A curve inclusion (Sec. 3.1): ``curve`` has ``centres`` (N_s, 2),
+        ``w`` (N_s,) and ``slowness`` (N_s,); None removes it.  Drops the
+        factors; after the next build, apply / apply_adjoint use the total
+        operator (K^{v2v} + K^{s2v} (K^{s2s})^{-1} K^{v2s}) h^d."""
+        if curve is None:
+            self._check(self._lib.hbi_set_inclusion(self._ctx, 0, None, None, None))
+        else:
+            xy = np.ascontiguousarray(curve.centres, dtype=np.float64)
+            w = np.ascontiguousarray(curve.w, dtype=np.float64)
+            n = np.ascontiguousarray(curve.slowness, dtype=np.float64)
+            if xy.shape != (w.size, 2) or n.shape != w.shape:
+                raise ValueError("curve: centres (N_s, 2), w and slowness (N_s,)")
+            self._check(self._lib.hbi_set_inclusion(self._ctx, int(w.size), _dptr(xy), _dptr(w),
+                                                    _dptr(n)))
+        self.prec = None
+        return self
+
     def set_stream(self, stream=None):
         import torch
         st = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream

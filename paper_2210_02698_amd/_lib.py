@@ -57,6 +57,10 @@ SIGNATURES = [
     ("hbi_set_stream", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("hbi_load_tables", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(hbi_tables)]),
     ("hbi_load_tables_from", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double]),
+    ("hbi_set_inclusion", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]),
     ("hbi_set_build_opts", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(hbi_build_opts)]),
     ("hbi_build", ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int]),
     ("hbi_apply", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,

@@ -1,0 +1,344 @@
+// HIP kernels of the curve inclusion (Sec. 3.1, domain with inclusion), 2D:
+//
+//   U = (K^{v2v} + K^{s2v} (K^{s2s})^{-1} K^{v2s}) h^d s      (eq. m_v2v_inclu)
+//
+// with K^{v2s}_ij = g(r^s_i, r_j), K^{s2v}_ij = g(r_i, r^s_j) w_j and
+// K^{s2s}_ij = -g(r^s_i, r^s_j) w_j off the diagonal (eq. m_v2s, m_s2v, s2s).
+// The tables are symmetric, so g is reciprocal and one dense array G,
+// G[j, i] = g(r_j, r^s_i) over cells j and segments i, serves both
+// K^{v2s} = G^T and K^{s2v} = G W.  G is stored in row chunks of `m` cells:
+// chunk q holds cells [q m, q m + m_q) as an m_q x N_s column-major block at
+// element offset q m N_s, so a segment's column within a chunk is contiguous.
+//
+//   k_point_setup           table box and Lagrange weights of every segment
+//                           centre, and the K^{s2s} self factor
+//   k_gj_pivot, k_gj_update, k_gj_unpermute
+//                           Gauss-Jordan inverse of K^{s2s} in FP64 with row
+//                           pivoting, in place
+//   k_inc_gather, k_inc_reduce, k_inc_small, k_inc_scatter
+//                           the inclusion term of one product (or of its
+//                           conjugate transpose), gathers only, fixed
+//                           summation order
+#include "hbi_kernels.h"
+#include "hbi_device.h"
+
+namespace hbi {
+
+namespace {
+constexpr double kPiI = 3.14159265358979323846;
+constexpr double kEulerGamma = 0.57721566490153286061;
+}  // namespace
+
+// Segment i sits at position p0 + i of the per-point arrays (after the
+// cells).  Its self factor sf_i is the value the entry kernels return on
+// the diagonal: K^{s2s}_ii = -w_i sf_i with
+//   -w_i sf_i = -(i w_i / 4) [1 + (2i/pi)(log(e^gamma omega n_i w_i / 4) - 1)],
+// minus the integral of the leading HB term (i/4) H0(omega n |t|) over the
+// segment, in its small-segment form (eq. s2s; the factor i of the leading
+// term and e^gamma are read into the printed formula).
+__global__ void k_point_setup(DevProblem P, const double *xy, const double *w,
+                              const double *slow, int32_t ns, int64_t p0, double *xyz,
+                              double *lw, int32_t *box, double2 *self) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  const int64_t p = p0 + i;
+  const double c[3] = {xy[2 * i], xy[2 * i + 1], 0.0};
+  for (int ax = 0; ax < 3; ++ax) xyz[p * 3 + ax] = c[ax];
+  box[p] = box_weights(P, c, lw + p * P.dim * P.nI);
+  const double L = kEulerGamma + log(P.omega * slow[i] * w[i] / 4.0);
+  self[p] = double2{-(L - 1.0) / (2.0 * kPiI), 0.25};
+}
+
+// ---------------------------------------------------------------------------
+// Gauss-Jordan inverse, column-major n x n complex A, in place.  Step k:
+// k_gj_pivot (one workgroup) picks the row p >= k with the largest |A[p,k]|
+// (lowest index on ties), swaps rows k and p, saves column k to colk,
+// replaces A[k,k] by 1/A[k,k] and scales the rest of row k by it;
+// k_gj_update subtracts colk[i] times row k from every other row i, and
+// sets A[i,k] = -colk[i] A[k,k].  Row k is only read in the update, column
+// k only written from colk, so the step has no read/write overlap.  After
+// the last step the columns are swapped back in reverse order.  A zero
+// pivot sets *status and leaves the remaining steps as no-ops.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_gj_pivot(double2 *A, int n, int k, int32_t *perm,
+                                                   double2 *colk, int32_t *status) {
+  __shared__ double sv[1024];
+  __shared__ int si[1024];
+  __shared__ double2 sinv;
+  __shared__ int sp;
+  if (*status) return;
+  const int t = threadIdx.x;
+  double best = -1.0;
+  int bi = n;
+  for (int i = k + t; i < n; i += blockDim.x) {
+    const double2 a = A[i + (int64_t)k * n];
+    const double m = a.x * a.x + a.y * a.y;
+    if (m > best) { best = m; bi = i; }
+  }
+  sv[t] = best;
+  si[t] = bi;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (t < o) {
+      const double b2 = sv[t + o];
+      const int i2 = si[t + o];
+      if (b2 > sv[t] || (b2 == sv[t] && i2 < si[t])) { sv[t] = b2; si[t] = i2; }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    sp = si[0];
+    perm[k] = sp;
+    if (!(sv[0] > 0.0)) *status = 1;
+  }
+  __syncthreads();
+  if (!(sv[0] > 0.0)) return;
+  const int p = sp;
+  if (p != k)
+    for (int j = t; j < n; j += blockDim.x) {
+      const double2 a = A[k + (int64_t)j * n], b = A[p + (int64_t)j * n];
+      A[k + (int64_t)j * n] = b;
+      A[p + (int64_t)j * n] = a;
+    }
+  __syncthreads();
+  for (int i = t; i < n; i += blockDim.x) colk[i] = A[i + (int64_t)k * n];
+  if (t == 0) {
+    const double2 a = A[k + (int64_t)k * n];
+    const double d = a.x * a.x + a.y * a.y;
+    sinv = double2{a.x / d, -a.y / d};
+  }
+  __syncthreads();
+  const double2 inv = sinv;
+  for (int j = t; j < n; j += blockDim.x) {
+    double2 &a = A[k + (int64_t)j * n];
+    a = j == k ? inv : cmul(a, inv);
+  }
+}
+
+__global__ void k_gj_update(double2 *A, int n, int k, const double2 *colk,
+                            const int32_t *status) {
+  if (*status) return;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int i = (int)(e % n), j = (int)(e / n);
+  if (i == k) return;
+  const double2 f = colk[i];
+  const double2 rk = A[k + (int64_t)j * n];
+  if (j == k) {
+    const double2 v = cmul(f, rk);
+    A[e] = double2{-v.x, -v.y};
+  } else {
+    const double2 v = cmul(f, rk);
+    A[e] = double2{A[e].x - v.x, A[e].y - v.y};
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_gj_unpermute(double2 *A, int n, const int32_t *perm,
+                                                       const int32_t *status) {
+  if (*status) return;
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = perm[k];
+    if (p != k)
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double2 a = A[i + (int64_t)k * n], b = A[i + (int64_t)p * n];
+        A[i + (int64_t)k * n] = b;
+        A[i + (int64_t)p * n] = a;
+      }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The inclusion term of one product.  Forward (CONJ = false), x = s:
+//   part[q][i] = hd sum_{j in chunk q} G[j, i] x_j        (K^{v2s} h^d s)
+//   z_i        = sum_q part[q][i]
+//   y_i        = w_i sum_k M[i, k] z_k                   (W (K^{s2s})^{-1} z)
+//   u_j       += sum_i G[j, i] y_i                        (K^{s2v} ...)
+// Adjoint (CONJ = true) with Ma = M^H:
+//   z_i = sum_j conj(G[j, i]) x_j,  y_i = sum_k Ma[i, k] w_k z_k,
+//   u_j += hd sum_i conj(G[j, i]) y_i.
+// ---------------------------------------------------------------------------
+template <typename R, bool CONJ>
+__global__ __launch_bounds__(256) void k_inc_gather(const cplx_t<R> *G, int64_t Nv, int32_t ns,
+                                                    int32_t m, const cplx_t<R> *x, R scale,
+                                                    cplx_t<R> *part) {
+  using C = cplx_t<R>;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int64_t q = blockIdx.x;
+  if (i >= ns) return;
+  const int64_t r0 = q * m;
+  const int mq = (int)(Nv - r0 < m ? Nv - r0 : m);
+  const C *col = G + r0 * ns + (int64_t)i * mq;
+  const C *xq = x + r0;
+  C acc{0, 0};
+  for (int j = lane; j < mq; j += 64) {
+    if (CONJ) cfmac(acc, col[j], xq[j]);
+    else cfma(acc, col[j], xq[j]);
+  }
+  acc.x = wave_sum(acc.x);
+  acc.y = wave_sum(acc.y);
+  if (lane == 0) part[q * ns + i] = C{acc.x * scale, acc.y * scale};
+}
+
+template <typename R>
+__global__ void k_inc_reduce(const cplx_t<R> *part, int64_t nchunk, int32_t ns, cplx_t<R> *z) {
+  using C = cplx_t<R>;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  C acc{0, 0};
+  for (int64_t q = 0; q < nchunk; ++q) {
+    const C v = part[q * ns + i];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  z[i] = acc;
+}
+
+// y_i = sum_k A[i + k ns] v_k with v = z (forward, y scaled by w_i after the
+// sum) or v = w z (adjoint); one thread per output, v staged in LDS.
+template <typename R, bool ADJ>
+__global__ __launch_bounds__(256) void k_inc_small(const cplx_t<R> *A, int32_t ns, const R *w,
+                                                   const cplx_t<R> *z, cplx_t<R> *y) {
+  using C = cplx_t<R>;
+  constexpr int KB = 1024;
+  __shared__ C vs[KB];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  C acc{0, 0};
+  for (int k0 = 0; k0 < ns; k0 += KB) {
+    const int kn = ns - k0 < KB ? ns - k0 : KB;
+    __syncthreads();
+    for (int k = threadIdx.x; k < kn; k += blockDim.x) {
+      const C v = z[k0 + k];
+      vs[k] = ADJ ? C{v.x * w[k0 + k], v.y * w[k0 + k]} : v;
+    }
+    __syncthreads();
+    if (i < ns)
+      for (int k = 0; k < kn; ++k) cfma(acc, A[i + (int64_t)(k0 + k) * ns], vs[k]);
+  }
+  if (i < ns) y[i] = ADJ ? acc : C{acc.x * w[i], acc.y * w[i]};
+}
+
+template <typename R, bool CONJ>
+__global__ __launch_bounds__(256) void k_inc_scatter(const cplx_t<R> *G, int64_t Nv, int32_t ns,
+                                                     int32_t m, const cplx_t<R> *y, R scale,
+                                                     cplx_t<R> *u) {
+  using C = cplx_t<R>;
+  constexpr int KB = 1024;
+  __shared__ C ys[KB];
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  // a workgroup's 256 cells lie in one chunk when m is a multiple of 256
+  const int64_t q = (blockIdx.x * (int64_t)blockDim.x) / m;
+  const int64_t r0 = q * m;
+  const int mq = (int)(Nv - r0 < m ? Nv - r0 : m);
+  const C *row = G + r0 * ns + (j - r0);
+  C acc{0, 0};
+  for (int i0 = 0; i0 < ns; i0 += KB) {
+    const int in = ns - i0 < KB ? ns - i0 : KB;
+    __syncthreads();
+    for (int k = threadIdx.x; k < in; k += blockDim.x) ys[k] = y[i0 + k];
+    __syncthreads();
+    if (j < Nv)
+      for (int k = 0; k < in; ++k) {
+        const C g = row[(int64_t)(i0 + k) * mq];
+        if (CONJ) cfmac(acc, g, ys[k]);
+        else cfma(acc, g, ys[k]);
+      }
+  }
+  if (j < Nv) {
+    const C o = u[j];
+    u[j] = C{o.x + scale * acc.x, o.y + scale * acc.y};
+  }
+}
+
+__global__ void k_scale_cols_neg(double2 *A, int32_t n, const double *w) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const double s = -w[e / n];
+  A[e] = double2{A[e].x * s, A[e].y * s};
+}
+
+// dst = src^H (column-major n x n)
+__global__ void k_conj_transpose(const double2 *src, int32_t n, double2 *dst) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int64_t i = e % n, j = e / n;
+  const double2 v = src[j + i * n];
+  dst[e] = double2{v.x, -v.y};
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_point_setup(const DevProblem &P, const double *xy, const double *w,
+                              const double *slow, int32_t ns, int64_t p0, double *xyz,
+                              double *lw, int32_t *box, double2 *self, hipStream_t st) {
+  if (ns <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_point_setup, dim3((ns + 255) / 256), dim3(256), 0, st, P, xy, w, slow,
+                     ns, p0, xyz, lw, box, self);
+  return hipGetLastError();
+}
+
+// -diag(w)-scaled columns, then the in-place Gauss-Jordan inverse.
+hipError_t launch_s2s_inverse(double2 *A, int32_t n, const double *w, int32_t *perm,
+                              double2 *colk, int32_t *status, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nn = (int64_t)n * n;
+  const int T = 256;
+  hipLaunchKernelGGL(k_scale_cols_neg, dim3((nn + T - 1) / T), dim3(T), 0, st, A, n, w);
+  for (int k = 0; k < n; ++k) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, st, A, n, k, perm, colk, status);
+    hipLaunchKernelGGL(k_gj_update, dim3((nn + T - 1) / T), dim3(T), 0, st, A, n, k, colk,
+                       status);
+  }
+  hipLaunchKernelGGL(k_gj_unpermute, dim3(1), dim3(1024), 0, st, A, n, perm, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_conj_transpose(const double2 *src, int32_t n, double2 *dst, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nn = (int64_t)n * n;
+  hipLaunchKernelGGL(k_conj_transpose, dim3((nn + 255) / 256), dim3(256), 0, st, src, n, dst);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_inclusion_apply(const InclusionPlan &ip, const void *x, void *u, R hd,
+                                  bool adjoint, hipStream_t st) {
+  using C = cplx_t<R>;
+  const C *G = (const C *)ip.G;
+  C *part = (C *)ip.part;
+  C *z = (C *)ip.z;
+  C *y = (C *)ip.y;
+  const R *w = (const R *)ip.w;
+  const int64_t nchunk = (ip.Nv + ip.m - 1) / ip.m;
+  const dim3 gg((unsigned)nchunk, (unsigned)((ip.ns + 3) / 4));
+  if (!adjoint) {
+    hipLaunchKernelGGL((k_inc_gather<R, false>), gg, dim3(256), 0, st, G, ip.Nv, ip.ns, ip.m,
+                       (const C *)x, hd, part);
+  } else {
+    hipLaunchKernelGGL((k_inc_gather<R, true>), gg, dim3(256), 0, st, G, ip.Nv, ip.ns, ip.m,
+                       (const C *)x, (R)1, part);
+  }
+  hipLaunchKernelGGL((k_inc_reduce<R>), dim3((ip.ns + 255) / 256), dim3(256), 0, st,
+                     (const C *)part, nchunk, ip.ns, z);
+  if (!adjoint) {
+    hipLaunchKernelGGL((k_inc_small<R, false>), dim3((ip.ns + 255) / 256), dim3(256), 0, st,
+                       (const C *)ip.M, ip.ns, w, (const C *)z, y);
+    hipLaunchKernelGGL((k_inc_scatter<R, false>), dim3((ip.Nv + 255) / 256), dim3(256), 0, st,
+                       G, ip.Nv, ip.ns, ip.m, (const C *)y, (R)1, (C *)u);
+  } else {
+    hipLaunchKernelGGL((k_inc_small<R, true>), dim3((ip.ns + 255) / 256), dim3(256), 0, st,
+                       (const C *)ip.MH, ip.ns, w, (const C *)z, y);
+    hipLaunchKernelGGL((k_inc_scatter<R, true>), dim3((ip.Nv + 255) / 256), dim3(256), 0, st,
+                       G, ip.Nv, ip.ns, ip.m, (const C *)y, hd, (C *)u);
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_inclusion_apply<double>(const InclusionPlan &, const void *, void *,
+                                                   double, bool, hipStream_t);
+template hipError_t launch_inclusion_apply<float>(const InclusionPlan &, const void *, void *,
+                                                  float, bool, hipStream_t);
+
+}  // namespace hbi

@@ -8,6 +8,7 @@
 #define HBI_ID_THREADS 1024
 #define HBI_ID_NMAX 4096   // largest candidate-column count an ID accepts
 #define HBI_ID_ONCHIP_NMAX 64   // largest column count of the on-chip ID kernel
+#define HBI_MAX_INCLUSION 8192  // segments of a curve inclusion
 
 // Problem constants visible to the kernels.
 struct DevProblem {
@@ -25,7 +26,23 @@ struct DevCells {
   const double2 *self;   // [Nv] self term K_ii
   const double *slow;    // [Nv] slowness
   const int32_t *perm;   // [Nv] tree position -> natural index
+  // With a curve inclusion, segment centres follow the cells as points
+  // Nv..Nv+ns-1 of xyz/lw/box/self, and cellof[p] is the position of the
+  // cell containing point p (p itself for a cell); null without one.
+  const int32_t *cellof;
 };
+
+// Which self value an entry (rp, cp) takes, or -1 for the HB value: the
+// diagonal, and a segment centre paired with the cell that contains it
+// (that cell's self term, the cell average of the leading HB term).
+__host__ __device__ inline int32_t self_index(const DevCells &C, int32_t rp, int32_t cp) {
+  if (rp == cp) return rp;
+  if (C.cellof) {
+    if (C.cellof[cp] == rp) return rp;
+    if (C.cellof[rp] == cp) return cp;
+  }
+  return -1;
+}
 
 struct DevTables {
   const double *FT[3];   // transposed tables FT[t][B*NT + A] = F_t[A*NT + B]

@@ -76,4 +76,24 @@ hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
                         const void *F, R hd, bool adjoint, hipStream_t st,
                         LaunchHook *hook = nullptr);
 
+// Curve inclusion (hbi_inclusion.hip).  G: chunked N_v x N_s array of
+// g(cell, segment); M = (K^{s2s})^{-1} and MH = M^H, column-major N_s x N_s;
+// w the segment lengths; part, z, y scratch of nchunk*N_s, N_s, N_s entries.
+// Element type complex64/complex128 (w float/double) as for the factors.
+struct InclusionPlan {
+  const void *G = nullptr, *M = nullptr, *MH = nullptr, *w = nullptr;
+  void *part = nullptr, *z = nullptr, *y = nullptr;
+  int64_t Nv = 0;
+  int32_t ns = 0, m = 0;
+};
+hipError_t launch_point_setup(const DevProblem &P, const double *xy, const double *w,
+                              const double *slow, int32_t ns, int64_t p0, double *xyz,
+                              double *lw, int32_t *box, double2 *self, hipStream_t st);
+hipError_t launch_s2s_inverse(double2 *A, int32_t n, const double *w, int32_t *perm,
+                              double2 *colk, int32_t *status, hipStream_t st);
+hipError_t launch_conj_transpose(const double2 *src, int32_t n, double2 *dst, hipStream_t st);
+template <typename R>
+hipError_t launch_inclusion_apply(const InclusionPlan &ip, const void *x, void *u, R hd,
+                                  bool adjoint, hipStream_t st);
+
 }  // namespace hbi

@@ -14,9 +14,6 @@ namespace hbi {
 
 // ---------------------------------------------------------------------------
 // Per-cell setup: centre, table box and 1D barycentric Lagrange weights.
-// First-kind Chebyshev nodes u_k = (1 + cos((2k+1)pi/(2nI)))/2 on [0,1]
-// have barycentric weights (-1)^k sin((2k+1)pi/(2nI)) (Berrut & Trefethen,
-// SIAM Rev. 2004); l_k(t) = (w_k/(t-u_k)) / sum_j w_j/(t-u_j).
 // ---------------------------------------------------------------------------
 __global__ void k_cell_setup(DevProblem P, const int32_t *perm, int64_t Nv,
                              int32_t ncx, int32_t ncy, double ox, double oy,
@@ -28,38 +25,9 @@ __global__ void k_cell_setup(DevProblem P, const int32_t *perm, int64_t Nv,
   double c[3];
   c[0] = ox + (ix + 0.5) * P.h;
   c[1] = oy + (iy + 0.5) * P.h;
-  c[2] = oz + (iz + 0.5) * P.h;
-  int32_t b = 0, stride = 1;
-  const int nI = P.nI;
-  for (int ax = 0; ax < P.dim; ++ax) {
-    xyz[p * 3 + ax] = c[ax];
-    const double rel = (c[ax] - P.box_origin[ax]) / P.box_size;
-    int bi = (int)floor(rel);
-    bi = bi < 0 ? 0 : (bi >= P.nbox[ax] ? P.nbox[ax] - 1 : bi);
-    b += bi * stride;
-    stride *= P.nbox[ax];
-    const double t = rel - bi;
-    double *w = lw + (p * P.dim + ax) * nI;
-    int hit = -1;
-    double den = 0.0;
-    for (int k = 0; k < nI; ++k) {
-      const double ang = (2.0 * k + 1.0) * kPi / (2.0 * nI);
-      const double u = 0.5 * (1.0 + cos(ang));
-      const double d = t - u;
-      if (d == 0.0) { hit = k; break; }
-      const double q = ((k & 1) ? -sin(ang) : sin(ang)) / d;
-      w[k] = q;
-      den += q;
-    }
-    if (hit >= 0) {
-      for (int k = 0; k < nI; ++k) w[k] = (k == hit) ? 1.0 : 0.0;
-    } else {
-      const double inv = 1.0 / den;
-      for (int k = 0; k < nI; ++k) w[k] *= inv;
-    }
-  }
-  if (P.dim == 2) xyz[p * 3 + 2] = 0.0;
-  box[p] = b;
+  c[2] = P.dim == 3 ? oz + (iz + 0.5) * P.h : 0.0;
+  for (int ax = 0; ax < 3; ++ax) xyz[p * 3 + ax] = c[ax];
+  box[p] = box_weights(P, c, lw + p * P.dim * P.nI);
 }
 
 // ---------------------------------------------------------------------------
@@ -344,9 +312,10 @@ __global__ __launch_bounds__(256, 2) void k_entries(
         if (cc >= T.nj) continue;
         const int j = T.j0 + cc;
         const int32_t cp = cols[B.col_off + j];
-        const double2 K = rp == cp ? C.self[rp]
-                                   : hb_value(D, P.nterms, P.omega, acc[r][c][0], acc[r][c][1],
-                                              acc[r][c][2]);
+        const int32_t si = self_index(C, rp, cp);
+        const double2 K = si >= 0 ? C.self[si]
+                                  : hb_value(D, P.nterms, P.omega, acc[r][c][0], acc[r][c][1],
+                                             acc[r][c][2]);
         B.out[i + (int64_t)j * B.m] = K;
       }
     }
@@ -369,8 +338,9 @@ __global__ __launch_bounds__(256, 2) void k_entries(
       if (rr < T.nr && cc < T.nj) {
         const int32_t rp = srp[rr];
         const int32_t cp = cols[B.col_off + T.j0 + cc];
-        if (rp == cp) {
-          const double2 sf = C.self[rp];
+        const int32_t si = self_index(C, rp, cp);
+        if (si >= 0) {
+          const double2 sf = C.self[si];
           ec0[e] = sf.x;
           ec1[e] = sf.y;
           cls[r][c] = 3;

@@ -196,6 +196,16 @@ struct hbi_ctx {
   ApplyPlan plan;
   int64_t ztotal = 0;
   DevBuf z_d;
+  // curve inclusion (2D): segments at positions [Nv, Nv + inc_ns) of the
+  // per-point arrays; inputs on the host and the device, and the dense
+  // operators built with the factors
+  int32_t inc_ns = 0;
+  std::vector<double> inc_xy, inc_w, inc_n;
+  DevBuf inc_xy_d, inc_w_d, inc_n_d;
+  DevBuf cellof_d;   // [Nv + inc_ns]: the cell containing each point (DevCells::cellof)
+  DevBuf inc_G, inc_M, inc_MH, inc_wf, inc_part, inc_z, inc_y;
+  InclusionPlan inc_plan;
+  double t_inc = 0;
   bool profiling = false;
   Profiler prof;
   // host copies of the apply plan (used to assemble batched work items)
@@ -226,6 +236,7 @@ struct hbi_ctx {
     DevCells C{};
     C.xyz = xyz_d.as<double>(); C.lw = lw_d.as<double>(); C.box = box_d.as<int32_t>();
     C.self = self_d.as<double2>(); C.slow = slow_d.as<double>(); C.perm = perm_d.as<int32_t>();
+    C.cellof = inc_ns ? cellof_d.as<int32_t>() : nullptr;
     return C;
   }
   DevTables devtables() const {
@@ -250,6 +261,8 @@ struct hbi_ctx {
   void drop_factors() {
     F.release(); Felems = 0; leaves_d.release(); vd_d.release(); kd_d.release();
     units_d.clear(); items_d.clear(); items_adj_d.clear(); plan = ApplyPlan();
+    inc_G.release(); inc_M.release(); inc_MH.release(); inc_wf.release();
+    inc_part.release(); inc_z.release(); inc_y.release(); inc_plan = InclusionPlan(); t_inc = 0;
     leaves_h.clear(); vd_h.clear(); kd_h.clear(); units_h.clear(); batch.reset(); ztotal = 0; z_d.release();
     nnz_v = nnz_w = nnz_k = nnz_d = entries_eval = nid = 0; rank_max = 0; rank_sum = 0;
     t_prep = t_wait = t_compact = 0; entry_slots = 0;
@@ -289,10 +302,12 @@ template <class T> void upload(DevBuf &d, const std::vector<T> &h) {
 }
 
 // Geometry + per-cell device arrays for the current leaf size.
-// Self terms (App. A) of every cell at the context's omega.
+// Self terms (App. A) of every cell at the context's omega, and the
+// per-point data of the inclusion's segments (their K^{s2s} self factor
+// depends on omega too).
 void eval_self_terms(hbi_ctx *c) {
   const int64_t Nv = c->geo.Nv;
-  HBI_HIP(c->self_d.alloc(sizeof(double2) * Nv));
+  HBI_HIP(c->self_d.alloc(sizeof(double2) * (Nv + c->inc_ns)));
   std::vector<double> gx, gw;
   gauss_legendre01(32, gx, gw);
   DevBuf gx_d, gw_d;
@@ -300,6 +315,10 @@ void eval_self_terms(hbi_ctx *c) {
   upload(gw_d, gw);
   HBI_HIP(launch_self_terms(c->devprob(), c->slow_d.as<double>(), Nv, gx_d.as<double>(),
                             gw_d.as<double>(), 32, c->self_d.as<double2>(), c->stream));
+  HBI_HIP(launch_point_setup(c->devprob(), c->inc_xy_d.as<double>(), c->inc_w_d.as<double>(),
+                             c->inc_n_d.as<double>(), c->inc_ns, Nv, c->xyz_d.as<double>(),
+                             c->lw_d.as<double>(), c->box_d.as<int32_t>(),
+                             c->self_d.as<double2>(), c->stream));
   HBI_HIP(hipStreamSynchronize(c->stream));
 }
 
@@ -314,16 +333,35 @@ void setup_cells(hbi_ctx *c) {
   std::vector<double> slow_t(Nv);
   for (int64_t p = 0; p < Nv; ++p) slow_t[p] = c->slow_nat[c->geo.perm[p]];
   upload(c->slow_d, slow_t);
-  HBI_HIP(c->xyz_d.alloc(sizeof(double) * 3 * Nv));
-  HBI_HIP(c->lw_d.alloc(sizeof(double) * c->dim * c->nI * Nv));
-  HBI_HIP(c->box_d.alloc(sizeof(int32_t) * Nv));
+  const int64_t np = Nv + c->inc_ns;   // cells, then the inclusion's segments
+  HBI_HIP(c->xyz_d.alloc(sizeof(double) * 3 * np));
+  HBI_HIP(c->lw_d.alloc(sizeof(double) * c->dim * c->nI * np));
+  HBI_HIP(c->box_d.alloc(sizeof(int32_t) * np));
   const DevProblem P = c->devprob();
   HBI_HIP(launch_cell_setup(P, c->perm_d.as<int32_t>(), Nv, c->ncell, c->origin,
                             c->xyz_d.as<double>(), c->lw_d.as<double>(), c->box_d.as<int32_t>(),
                             c->stream));
+  if (c->inc_ns > 0) {
+    // a segment centre belongs to the cell floor((x - origin) / h), clamped
+    std::vector<int32_t> cellof(np);
+    for (int64_t p = 0; p < Nv; ++p) cellof[p] = (int32_t)p;
+    for (int32_t i = 0; i < c->inc_ns; ++i) {
+      int64_t nat = 0, stride = 1;
+      for (int a = 0; a < 2; ++a) {
+        int64_t k = (int64_t)std::floor((c->inc_xy[2 * i + a] - c->origin[a]) / c->h);
+        k = std::min<int64_t>(std::max<int64_t>(k, 0), c->ncell[a] - 1);
+        nat += k * stride;
+        stride *= c->ncell[a];
+      }
+      cellof[Nv + i] = c->geo.ipos[nat];
+    }
+    upload(c->cellof_d, cellof);
+  } else {
+    c->cellof_d.release();
+  }
   eval_self_terms(c);
-  c->box_h.resize(Nv);
-  HBI_HIP(hipMemcpyAsync(c->box_h.data(), c->box_d.p, sizeof(int32_t) * Nv,
+  c->box_h.resize(np);
+  HBI_HIP(hipMemcpyAsync(c->box_h.data(), c->box_d.p, sizeof(int32_t) * np,
                          hipMemcpyDeviceToHost, c->stream));
   HBI_HIP(hipStreamSynchronize(c->stream));
   c->t_geo = now_s() - t0;
@@ -1299,6 +1337,114 @@ void build_factors(hbi_ctx *c, double tol) {
   c->t_build = now_s() - tb0;
 }
 
+// Dense operators of the curve inclusion (Sec. 3.1, eq. m_v2v_inclu):
+// G[j, i] = g(r_j, r^s_i) over cells j (natural order, chunks of kIncChunk
+// cells) and segments i, evaluated by the entry kernels with the segments as
+// points after the cells; K^{s2s} from g between segments, its columns
+// scaled by -w_j (self factors on the diagonal), inverted by Gauss-Jordan in
+// FP64.  Stored in the factors' precision.
+constexpr int32_t kIncChunk = 4096;   // cells per chunk of G (a multiple of 256)
+
+void build_inclusion(hbi_ctx *c) {
+  const double t0 = now_s();
+  const int64_t Nv = c->geo.Nv;
+  const int32_t ns = c->inc_ns;
+  const int32_t m = kIncChunk;
+  const int64_t nchunk = (Nv + m - 1) / m;
+  const bool f32 = c->prec == HBI_F32;
+  const size_t esz = f32 ? sizeof(float2) : sizeof(double2);
+  std::vector<int32_t> segpos(ns), rowpos(Nv);
+  for (int32_t i = 0; i < ns; ++i) segpos[i] = (int32_t)(Nv + i);
+  for (int64_t j = 0; j < Nv; ++j) rowpos[j] = c->geo.ipos[j];
+  HBI_HIP(c->inc_G.alloc(esz * (size_t)Nv * ns));
+  Batcher B(c);
+  {
+    // groups of chunks whose FP64 values fit a 1 GiB scratch
+    const int64_t per = (int64_t)m * ns * (int64_t)sizeof(double2);
+    const int64_t gch = std::max<int64_t>(1, ((int64_t)1 << 30) / per);
+    DevBuf scratch, pd_d;
+    HBI_HIP(scratch.alloc((size_t)std::min(nchunk, gch) * per));
+    for (int64_t g0 = 0; g0 < nchunk; g0 += gch) {
+      const int64_t g1 = std::min(nchunk, g0 + gch);
+      std::vector<BlockIn> bin;
+      std::vector<PlaceDesc> pd;
+      int64_t off = 0;
+      for (int64_t q = g0; q < g1; ++q) {
+        const int64_t r0 = q * m;
+        const int32_t mq = (int32_t)std::min<int64_t>(m, Nv - r0);
+        double2 *out = scratch.as<double2>() + off;
+        bin.push_back(BlockIn{rowpos.data() + r0, mq, segpos.data(), ns, out});
+        pd.push_back(PlaceDesc{out, r0 * ns, (int64_t)mq * ns});
+        off += (int64_t)mq * ns;
+      }
+      B.run(bin, false, 0.0, nullptr, [](int64_t, int64_t) {});
+      upload(pd_d, pd);
+      HBI_HIP(launch_place_blocks(pd_d.as<PlaceDesc>(), (int64_t)pd.size(), c->inc_G.p, f32,
+                                  c->stream));
+      HBI_HIP(hipStreamSynchronize(c->stream));
+    }
+  }
+  {
+    DevBuf S, SH, perm, colk, status, pd_d;
+    HBI_HIP(S.alloc(sizeof(double2) * (size_t)ns * ns));
+    HBI_HIP(SH.alloc(sizeof(double2) * (size_t)ns * ns));
+    HBI_HIP(perm.alloc(sizeof(int32_t) * ns));
+    HBI_HIP(colk.alloc(sizeof(double2) * ns));
+    HBI_HIP(status.alloc(sizeof(int32_t)));
+    HBI_HIP(hipMemsetAsync(status.p, 0, sizeof(int32_t), c->stream));
+    std::vector<BlockIn> bin{BlockIn{segpos.data(), ns, segpos.data(), ns, S.as<double2>()}};
+    B.run(bin, false, 0.0, nullptr, [](int64_t, int64_t) {});
+    HBI_HIP(launch_s2s_inverse(S.as<double2>(), ns, c->inc_w_d.as<double>(), perm.as<int32_t>(),
+                               colk.as<double2>(), status.as<int32_t>(), c->stream));
+    int32_t st = 0;
+    HBI_HIP(hipMemcpyAsync(&st, status.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HBI_HIP(hipStreamSynchronize(c->stream));
+    HBI_REQUIRE(st == 0, HBI_ERR_NUMERIC, "the surface-to-surface matrix is singular");
+    HBI_HIP(launch_conj_transpose(S.as<double2>(), ns, SH.as<double2>(), c->stream));
+    HBI_HIP(c->inc_M.alloc(esz * (size_t)ns * ns));
+    HBI_HIP(c->inc_MH.alloc(esz * (size_t)ns * ns));
+    std::vector<PlaceDesc> pd{PlaceDesc{S.as<double2>(), 0, (int64_t)ns * ns}};
+    upload(pd_d, pd);
+    HBI_HIP(launch_place_blocks(pd_d.as<PlaceDesc>(), 1, c->inc_M.p, f32, c->stream));
+    HBI_HIP(hipStreamSynchronize(c->stream));
+    pd[0].src = SH.as<double2>();
+    upload(pd_d, pd);
+    HBI_HIP(launch_place_blocks(pd_d.as<PlaceDesc>(), 1, c->inc_MH.p, f32, c->stream));
+    HBI_HIP(hipStreamSynchronize(c->stream));
+  }
+  if (f32) {
+    std::vector<float> wf(c->inc_w.begin(), c->inc_w.end());
+    upload(c->inc_wf, wf);
+  } else {
+    upload(c->inc_wf, c->inc_w);
+  }
+  HBI_HIP(c->inc_part.alloc(esz * (size_t)nchunk * ns));
+  HBI_HIP(c->inc_z.alloc(esz * (size_t)ns));
+  HBI_HIP(c->inc_y.alloc(esz * (size_t)ns));
+  InclusionPlan &ip = c->inc_plan;
+  ip.G = c->inc_G.p; ip.M = c->inc_M.p; ip.MH = c->inc_MH.p; ip.w = c->inc_wf.p;
+  ip.part = c->inc_part.p; ip.z = c->inc_z.p; ip.y = c->inc_y.p;
+  ip.Nv = Nv; ip.ns = ns; ip.m = m;
+  c->t_inc = now_s() - t0;
+}
+
+// The inclusion term of eq. m_v2v_inclu (or of its conjugate transpose),
+// added to u after the volume product of every column.
+void apply_inclusion(hbi_ctx *c, const void *s, void *u, int32_t nrhs, int64_t ld, bool adj) {
+  if (c->inc_ns == 0) return;
+  const size_t esz = c->prec == HBI_F64 ? 16 : 8;
+  for (int32_t r = 0; r < nrhs; ++r) {
+    const char *sc = (const char *)s + esz * (size_t)ld * r;
+    char *uc = (char *)u + esz * (size_t)ld * r;
+    if (c->prec == HBI_F64)
+      HBI_HIP(launch_inclusion_apply<double>(c->inc_plan, sc, uc, std::pow(c->h, c->dim), adj,
+                                             c->stream));
+    else
+      HBI_HIP(launch_inclusion_apply<float>(c->inc_plan, sc, uc, (float)std::pow(c->h, c->dim),
+                                            adj, c->stream));
+  }
+}
+
 bool overlap(const void *a, size_t na, const void *b, size_t nb) {
   const char *x = (const char *)a, *y = (const char *)b;
   return x < y + nb && y < x + na;
@@ -1704,6 +1850,14 @@ hbi_status hbi_set_stream(hbi_ctx *ctx, void *hip_stream) {
   return HBI_OK;
 }
 
+namespace {
+void clear_inclusion(hbi_ctx *c) {
+  c->inc_ns = 0;
+  c->inc_xy.clear(); c->inc_w.clear(); c->inc_n.clear();
+  c->inc_xy_d.release(); c->inc_w_d.release(); c->inc_n_d.release();
+}
+}  // namespace
+
 hbi_status hbi_load_tables(hbi_ctx *ctx, const hbi_tables *t) {
   if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
   return guarded(ctx, [&]() {
@@ -1734,6 +1888,7 @@ hbi_status hbi_load_tables(hbi_ctx *ctx, const hbi_tables *t) {
     hbi_ctx *c = ctx;
     c->drop_factors();
     c->state = 0;
+    clear_inclusion(c);
     c->dim = d;
     c->nterms = t->nterms;
     c->nI = t->nI;
@@ -1800,6 +1955,11 @@ hbi_status hbi_load_tables_from(hbi_ctx *ctx, const hbi_ctx *src, double omega) 
     // tables are constant once loaded; src's stream may still run its own
     // builds or applies, which only read them
     HBI_HIP(hipStreamSynchronize(src->stream));
+    c->inc_ns = src->inc_ns;
+    c->inc_xy = src->inc_xy; c->inc_w = src->inc_w; c->inc_n = src->inc_n;
+    copy_dev(c->inc_xy_d, src->inc_xy_d, c->stream);
+    copy_dev(c->inc_w_d, src->inc_w_d, c->stream);
+    copy_dev(c->inc_n_d, src->inc_n_d, c->stream);
     c->dim = src->dim; c->nterms = src->nterms; c->nI = src->nI;
     c->NTb = src->NTb; c->NT = src->NT;
     for (int a = 0; a < 3; ++a) {
@@ -1820,12 +1980,52 @@ hbi_status hbi_load_tables_from(hbi_ctx *ctx, const hbi_ctx *src, double omega) 
       copy_dev(c->xyz_d, src->xyz_d, c->stream);
       copy_dev(c->lw_d, src->lw_d, c->stream);
       copy_dev(c->box_d, src->box_d, c->stream);
+      copy_dev(c->cellof_d, src->cellof_d, c->stream);
       c->box_h = src->box_h;
       eval_self_terms(c);
     } else {
       setup_cells(c);
     }
     HBI_HIP(hipStreamSynchronize(c->stream));
+    c->state = 1;
+  });
+}
+
+hbi_status hbi_set_inclusion(hbi_ctx *ctx, int32_t ns, const double *xy, const double *w,
+                             const double *slowness) {
+  if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
+  return guarded(ctx, [&]() {
+    hbi_ctx *c = ctx;
+    HBI_REQUIRE(c->state >= 1, HBI_ERR_STATE, "inclusion before tables");
+    HBI_REQUIRE(c->dim == 2, HBI_ERR_ARG, "curve inclusions are 2D");
+    HBI_REQUIRE(ns >= 0 && ns <= HBI_MAX_INCLUSION, HBI_ERR_ARG, "ns must be in [0, 8192]");
+    if (ns > 0) {
+      HBI_REQUIRE(xy && w && slowness, HBI_ERR_ARG, "null segment array");
+      for (int32_t i = 0; i < ns; ++i) {
+        HBI_REQUIRE(std::isfinite(w[i]) && w[i] > 0, HBI_ERR_ARG, "segment lengths must be > 0");
+        HBI_REQUIRE(std::isfinite(slowness[i]) && slowness[i] > 0, HBI_ERR_ARG,
+                    "slowness must be finite and > 0");
+        for (int a = 0; a < 2; ++a) {
+          const double x = xy[2 * i + a];
+          const double blo = c->box_origin[a], bhi = blo + c->nbox[a] * c->box_size;
+          HBI_REQUIRE(std::isfinite(x) && x >= blo && x <= bhi, HBI_ERR_ARG,
+                      "segment centres lie outside the table region");
+        }
+      }
+    }
+    c->drop_factors();
+    c->state = 0;
+    clear_inclusion(c);
+    if (ns > 0) {
+      c->inc_ns = ns;
+      c->inc_xy.assign(xy, xy + 2 * (size_t)ns);
+      c->inc_w.assign(w, w + ns);
+      c->inc_n.assign(slowness, slowness + ns);
+      upload(c->inc_xy_d, c->inc_xy);
+      upload(c->inc_w_d, c->inc_w);
+      upload(c->inc_n_d, c->inc_n);
+    }
+    setup_cells(c);
     c->state = 1;
   });
 }
@@ -1851,6 +2051,10 @@ hbi_status hbi_build(hbi_ctx *ctx, double tol, hbi_prec prec) {
     ctx->prec = prec;
     ctx->tol = tol;
     build_factors(ctx, tol);
+    if (ctx->inc_ns > 0) {
+      build_inclusion(ctx);
+      ctx->t_build += ctx->t_inc;
+    }
     ctx->state = 2;
   });
 }
@@ -1862,6 +2066,7 @@ hbi_status hbi_apply(hbi_ctx *ctx, const void *s, void *u, int32_t nrhs, int64_t
       multi_apply(ctx, {ctx}, {s}, {u}, {nrhs}, {ld});
     else
       do_apply(ctx, s, u, nrhs, ld, false);
+    apply_inclusion(ctx, s, u, nrhs, ld, false);
   });
 }
 
@@ -1870,6 +2075,9 @@ hbi_status hbi_apply_batched(hbi_ctx *const *ctx, int32_t nprob, const void *con
   if (!ctx || nprob < 1 || !ctx[0]) { g_err = "ctx is NULL or nprob < 1"; return HBI_ERR_ARG; }
   return guarded(ctx[0], [&]() {
     HBI_REQUIRE(s && u && nrhs && ld, HBI_ERR_ARG, "null argument array");
+    for (int32_t p = 0; p < nprob; ++p)
+      HBI_REQUIRE(!ctx[p] || ctx[p]->inc_ns == 0, HBI_ERR_ARG,
+                  "operators with an inclusion are applied by hbi_apply");
     std::vector<hbi_ctx *> cs(ctx, ctx + nprob);
     std::vector<const void *> sv(s, s + nprob);
     std::vector<void *> uv(u, u + nprob);
@@ -1881,7 +2089,10 @@ hbi_status hbi_apply_batched(hbi_ctx *const *ctx, int32_t nprob, const void *con
 
 hbi_status hbi_apply_adjoint(hbi_ctx *ctx, const void *s, void *u, int32_t nrhs, int64_t ld) {
   if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
-  return guarded(ctx, [&]() { do_apply(ctx, s, u, nrhs, ld, true); });
+  return guarded(ctx, [&]() {
+    do_apply(ctx, s, u, nrhs, ld, true);
+    apply_inclusion(ctx, s, u, nrhs, ld, true);
+  });
 }
 
 hbi_status hbi_entries(hbi_ctx *ctx, const int32_t *rows, int32_t m, const int32_t *cols,
@@ -1973,7 +2184,8 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       "\"n_id_cols_gt64\": %lld, \"id_cmac_cols_gt64\": %.6e, \"id_cmac_cols_gt128\": %.6e, "
       "\"build_s\": %.6f, \"build_geometry_s\": %.6f, \"build_proxy_host_s\": %.6f, "
       "\"build_gpu_s\": %.6f, \"build_batch_host_setup_s\": %.6f, \"build_batch_total_s\": %.6f, "
-      "\"build_compact_s\": %.6f, \"build_finalize_s\": %.6f}",
+      "\"build_compact_s\": %.6f, \"build_finalize_s\": %.6f, "
+      "\"inclusion_ns\": %d, \"inclusion_bytes\": %lld, \"build_inclusion_s\": %.6f}",
       ctx->state, ctx->dim, (long long)Nv, ctx->geo.Lv, ctx->NT, ctx->nI,
       ctx->prec == HBI_F64 ? "f64" : "f32", ctx->tol, ctx->chi(), ctx->leaf(),
       (long long)ctx->nnz_v, (long long)ctx->nnz_w, (long long)ctx->nnz_k, (long long)ctx->nnz_d,
@@ -1986,7 +2198,8 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       ctx->nid ? ctx->id_n_sum / ctx->nid : 0.0, ctx->id_work, (long long)ctx->nid_wide,
       ctx->id_work_wide, ctx->id_work_128, ctx->t_build, ctx->t_geo, ctx->t_host, ctx->t_gpu, ctx->t_prep,
       ctx->t_wait, ctx->t_compact,
-      ctx->t_final);
+      ctx->t_final, ctx->inc_ns,
+      (long long)(ctx->inc_G.n + ctx->inc_M.n + ctx->inc_MH.n), ctx->t_inc);
   if (len < 0 || len >= cap) { ctx->err = "output buffer too small"; return HBI_ERR_ARG; }
   std::memcpy(json, buf, len + 1);
   return HBI_OK;

@@ -39,6 +39,7 @@ def test_null_context_is_an_argument_error(lib):
     assert lib.hbi_apply_adjoint(null, None, None, 1, 1) == _lib.HBI_ERR_ARG
     assert lib.hbi_load_tables(null, None) == _lib.HBI_ERR_ARG
     assert lib.hbi_load_tables_from(null, null, 1.0) == _lib.HBI_ERR_ARG
+    assert lib.hbi_set_inclusion(null, 0, None, None, None) == _lib.HBI_ERR_ARG
     assert lib.hbi_set_build_opts(null, None) == _lib.HBI_ERR_ARG
     assert lib.hbi_entries(null, None, 0, None, 0, None) == _lib.HBI_ERR_ARG
     assert lib.hbi_get_info(null, None, 0) == _lib.HBI_ERR_ARG
