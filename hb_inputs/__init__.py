@@ -19,11 +19,11 @@ from .media import (Homogeneous, ConstantGradient, GaussianBump, Sinusoid3D)
 from .tables import cheb_unit_nodes, node_coords, tabulate
 from .problem import HBProblem, make_problem
 from .rhs import complex_normal, gaussian_sources, point_sources
-from .curves import Curve, circle
+from .curves import Curve, circle, open_square
 from . import configs
 
 __all__ = [
     "Homogeneous", "ConstantGradient", "GaussianBump", "Sinusoid3D",
     "cheb_unit_nodes", "node_coords", "tabulate", "HBProblem", "make_problem",
-    "complex_normal", "gaussian_sources", "point_sources", "Curve", "circle", "configs",
+    "complex_normal", "gaussian_sources", "point_sources", "Curve", "circle", "open_square", "configs",
 ]

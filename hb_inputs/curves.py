@@ -36,3 +36,38 @@ def circle(prob, centre, radius, ns, name=None) -> Curve:
     n = np.ascontiguousarray(prob.meta["medium"].slowness(P), dtype=np.float64)
     return Curve(centres=np.ascontiguousarray(P), w=w, slowness=n,
                  name=name or f"circle-c{tuple(c)}-r{radius}-ns{ns}")
+
+
+def _polyline(prob, pts, w_target, name):
+    """Straight segments of length <= w_target along the open polyline pts
+    (each side split evenly)."""
+    P = np.asarray(pts, np.float64)
+    cs, ws = [], []
+    for a, b in zip(P[:-1], P[1:]):
+        L = float(np.linalg.norm(b - a))
+        k = max(1, int(math.ceil(L / w_target)))
+        t = (np.arange(k) + 0.5) / k
+        cs.append(a[None, :] + t[:, None] * (b - a)[None, :])
+        ws.append(np.full(k, L / k))
+    C = np.ascontiguousarray(np.concatenate(cs))
+    n = np.ascontiguousarray(prob.meta["medium"].slowness(C), dtype=np.float64)
+    return Curve(centres=C, w=np.concatenate(ws), slowness=n, name=name)
+
+
+def segment_length(prob, ppw):
+    """w = 2 pi / (omega n_max ppw): ppw segments per shortest local
+    wavelength (Sec. 5, inclusion examples)."""
+    return 2.0 * math.pi / (prob.omega * float(np.max(prob.slowness)) * ppw)
+
+
+def open_square(prob, centre, side, ppw, name=None) -> Curve:
+    """The outline of the square of this side centred at `centre` without
+    its top side (an open curve; Sec. 5, 2D examples with inclusion), cut
+    into segments of ppw per shortest wavelength."""
+    if prob.dim != 2:
+        raise ValueError("curve inclusions are 2D")
+    cx, cy = centre
+    a = side / 2.0
+    pts = [(cx - a, cy + a), (cx - a, cy - a), (cx + a, cy - a), (cx + a, cy + a)]
+    return _polyline(prob, pts, segment_length(prob, ppw),
+                     name or f"open-square-c{tuple(centre)}-s{side}-ppw{ppw}")

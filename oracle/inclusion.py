@@ -121,12 +121,17 @@ def s2s(prob, curve):
     return K
 
 
-def apply(prob, curve, s, rows=None):
+def apply(prob, curve, s, rows=None, chunk_entries=1 << 22):
     """U[rows] of eq. m_v2v_inclu for sources s ((N_v,) or (N_v, nrhs))."""
     s = np.asarray(s, np.complex128)
     I = s * prob.h ** prob.dim
-    P = np.linalg.solve(s2s(prob, curve), v2s(prob, curve) @ I)   # eq. m_sie, m_v2s
-    return v2v_apply(prob, s, rows) + s2v(prob, curve, rows) @ P  # eq. m_s2v
+    Uinc = np.zeros((curve.Ns,) + s.shape[1:], np.complex128)     # eq. m_v2s
+    step = max(1, chunk_entries // curve.Ns)
+    for a in range(0, prob.Nv, step):
+        cols = np.arange(a, min(prob.Nv, a + step))
+        Uinc += v2s(prob, curve, cols) @ I[cols]
+    P = np.linalg.solve(s2s(prob, curve), Uinc)                    # eq. m_sie
+    return v2v_apply(prob, s, rows) + s2v(prob, curve, rows) @ P   # eq. m_s2v
 
 
 def apply_adjoint(prob, curve, s, cols=None):

@@ -15,7 +15,7 @@
 //   k_gj_pivot, k_gj_update, k_gj_unpermute
 //                           Gauss-Jordan inverse of K^{s2s} in FP64 with row
 //                           pivoting, in place
-//   k_inc_gather, k_inc_reduce, k_inc_small, k_inc_scatter
+//   k_inc_gather, k_inc_reduce, k_inc_small(_sum), k_inc_scatter, k_inc_add
 //                           the inclusion term of one product (or of its
 //                           conjugate transpose), gathers only, fixed
 //                           summation order
@@ -196,59 +196,97 @@ __global__ void k_inc_reduce(const cplx_t<R> *part, int64_t nchunk, int32_t ns, 
 }
 
 // y_i = sum_k A[i + k ns] v_k with v = z (forward, y scaled by w_i after the
-// sum) or v = w z (adjoint); one thread per output, v staged in LDS.
+// sum) or v = w z (adjoint).  k_inc_small: partial sums over column block
+// kb = blockIdx.y of kIncCol columns, one thread per output row;
+// k_inc_small_sum adds the blocks in order.
+constexpr int kIncCol = 32;
+
 template <typename R, bool ADJ>
 __global__ __launch_bounds__(256) void k_inc_small(const cplx_t<R> *A, int32_t ns, const R *w,
-                                                   const cplx_t<R> *z, cplx_t<R> *y) {
+                                                   const cplx_t<R> *z, cplx_t<R> *part3) {
   using C = cplx_t<R>;
-  constexpr int KB = 1024;
-  __shared__ C vs[KB];
+  __shared__ C vs[kIncCol];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  C acc{0, 0};
-  for (int k0 = 0; k0 < ns; k0 += KB) {
-    const int kn = ns - k0 < KB ? ns - k0 : KB;
-    __syncthreads();
-    for (int k = threadIdx.x; k < kn; k += blockDim.x) {
-      const C v = z[k0 + k];
-      vs[k] = ADJ ? C{v.x * w[k0 + k], v.y * w[k0 + k]} : v;
-    }
-    __syncthreads();
-    if (i < ns)
-      for (int k = 0; k < kn; ++k) cfma(acc, A[i + (int64_t)(k0 + k) * ns], vs[k]);
+  const int k0 = blockIdx.y * kIncCol;
+  const int kn = ns - k0 < kIncCol ? ns - k0 : kIncCol;
+  if (threadIdx.x < kn) {
+    const C v = z[k0 + threadIdx.x];
+    vs[threadIdx.x] = ADJ ? C{v.x * w[k0 + threadIdx.x], v.y * w[k0 + threadIdx.x]} : v;
   }
-  if (i < ns) y[i] = ADJ ? acc : C{acc.x * w[i], acc.y * w[i]};
+  __syncthreads();
+  if (i >= ns) return;
+  C acc{0, 0};
+  const C *col = A + i + (int64_t)k0 * ns;
+#pragma unroll 8
+  for (int k = 0; k < kn; ++k) cfma(acc, col[(int64_t)k * ns], vs[k]);
+  part3[(int64_t)blockIdx.y * ns + i] = acc;
 }
+
+template <typename R, bool ADJ>
+__global__ void k_inc_small_sum(const cplx_t<R> *part3, int32_t ns, int32_t nkb, const R *w,
+                                cplx_t<R> *y) {
+  using C = cplx_t<R>;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  C acc{0, 0};
+  for (int b = 0; b < nkb; ++b) {
+    const C v = part3[(int64_t)b * ns + i];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  y[i] = ADJ ? acc : C{acc.x * w[i], acc.y * w[i]};
+}
+
+// Partial sums of u_j over segment block b = blockIdx.y (kIncSeg segments):
+// part2[b][j] = sum_{i in b} op(G[j, i]) y_i, loads issued 8 at a time.
+constexpr int kIncSeg = 256;
 
 template <typename R, bool CONJ>
 __global__ __launch_bounds__(256) void k_inc_scatter(const cplx_t<R> *G, int64_t Nv, int32_t ns,
-                                                     int32_t m, const cplx_t<R> *y, R scale,
-                                                     cplx_t<R> *u) {
+                                                     int32_t m, const cplx_t<R> *y,
+                                                     cplx_t<R> *part2) {
   using C = cplx_t<R>;
-  constexpr int KB = 1024;
-  __shared__ C ys[KB];
+  __shared__ C ys[kIncSeg];
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  // a workgroup's 256 cells lie in one chunk when m is a multiple of 256
-  const int64_t q = (blockIdx.x * (int64_t)blockDim.x) / m;
-  const int64_t r0 = q * m;
+  const int i0 = blockIdx.y * kIncSeg;
+  const int in = ns - i0 < kIncSeg ? ns - i0 : kIncSeg;
+  for (int k = threadIdx.x; k < in; k += blockDim.x) ys[k] = y[i0 + k];
+  __syncthreads();
+  if (j >= Nv) return;
+  const int64_t r0 = (j / m) * m;
   const int mq = (int)(Nv - r0 < m ? Nv - r0 : m);
-  const C *row = G + r0 * ns + (j - r0);
+  const C *row = G + r0 * ns + (j - r0) + (int64_t)i0 * mq;
   C acc{0, 0};
-  for (int i0 = 0; i0 < ns; i0 += KB) {
-    const int in = ns - i0 < KB ? ns - i0 : KB;
-    __syncthreads();
-    for (int k = threadIdx.x; k < in; k += blockDim.x) ys[k] = y[i0 + k];
-    __syncthreads();
-    if (j < Nv)
-      for (int k = 0; k < in; ++k) {
-        const C g = row[(int64_t)(i0 + k) * mq];
-        if (CONJ) cfmac(acc, g, ys[k]);
-        else cfma(acc, g, ys[k]);
+  constexpr int B = 8;
+  for (int k0 = 0; k0 < in; k0 += B) {
+    C g[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) g[b] = k0 + b < in ? row[(int64_t)(k0 + b) * mq] : C{0, 0};
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      if (k0 + b < in) {
+        if (CONJ) cfmac(acc, g[b], ys[k0 + b]);
+        else cfma(acc, g[b], ys[k0 + b]);
       }
+    }
   }
-  if (j < Nv) {
-    const C o = u[j];
-    u[j] = C{o.x + scale * acc.x, o.y + scale * acc.y};
+  part2[(int64_t)blockIdx.y * Nv + j] = acc;
+}
+
+// u_j += scale * sum_b part2[b][j], blocks in order.
+template <typename R>
+__global__ void k_inc_add(const cplx_t<R> *part2, int64_t Nv, int32_t nb, R scale, cplx_t<R> *u) {
+  using C = cplx_t<R>;
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= Nv) return;
+  C acc{0, 0};
+  for (int b = 0; b < nb; ++b) {
+    const C v = part2[(int64_t)b * Nv + j];
+    acc.x += v.x;
+    acc.y += v.y;
   }
+  const C o = u[j];
+  u[j] = C{o.x + scale * acc.x, o.y + scale * acc.y};
 }
 
 __global__ void k_scale_cols_neg(double2 *A, int32_t n, const double *w) {
@@ -322,17 +360,29 @@ hipError_t launch_inclusion_apply(const InclusionPlan &ip, const void *x, void *
   }
   hipLaunchKernelGGL((k_inc_reduce<R>), dim3((ip.ns + 255) / 256), dim3(256), 0, st,
                      (const C *)part, nchunk, ip.ns, z);
+  const int32_t nb = (ip.ns + kIncSeg - 1) / kIncSeg;
+  const dim3 gs((unsigned)((ip.Nv + 255) / 256), (unsigned)nb);
+  const int32_t nkb = (ip.ns + kIncCol - 1) / kIncCol;
+  const dim3 gm((unsigned)((ip.ns + 255) / 256), (unsigned)nkb);
+  C *part2 = (C *)ip.part2;
+  C *part3 = (C *)ip.part3;
   if (!adjoint) {
-    hipLaunchKernelGGL((k_inc_small<R, false>), dim3((ip.ns + 255) / 256), dim3(256), 0, st,
-                       (const C *)ip.M, ip.ns, w, (const C *)z, y);
-    hipLaunchKernelGGL((k_inc_scatter<R, false>), dim3((ip.Nv + 255) / 256), dim3(256), 0, st,
-                       G, ip.Nv, ip.ns, ip.m, (const C *)y, (R)1, (C *)u);
+    hipLaunchKernelGGL((k_inc_small<R, false>), gm, dim3(256), 0, st, (const C *)ip.M, ip.ns, w,
+                       (const C *)z, part3);
+    hipLaunchKernelGGL((k_inc_small_sum<R, false>), dim3((ip.ns + 255) / 256), dim3(256), 0, st,
+                       (const C *)part3, ip.ns, nkb, w, y);
+    hipLaunchKernelGGL((k_inc_scatter<R, false>), gs, dim3(256), 0, st, G, ip.Nv, ip.ns, ip.m,
+                       (const C *)y, part2);
   } else {
-    hipLaunchKernelGGL((k_inc_small<R, true>), dim3((ip.ns + 255) / 256), dim3(256), 0, st,
-                       (const C *)ip.MH, ip.ns, w, (const C *)z, y);
-    hipLaunchKernelGGL((k_inc_scatter<R, true>), dim3((ip.Nv + 255) / 256), dim3(256), 0, st,
-                       G, ip.Nv, ip.ns, ip.m, (const C *)y, hd, (C *)u);
+    hipLaunchKernelGGL((k_inc_small<R, true>), gm, dim3(256), 0, st, (const C *)ip.MH, ip.ns, w,
+                       (const C *)z, part3);
+    hipLaunchKernelGGL((k_inc_small_sum<R, true>), dim3((ip.ns + 255) / 256), dim3(256), 0, st,
+                       (const C *)part3, ip.ns, nkb, w, y);
+    hipLaunchKernelGGL((k_inc_scatter<R, true>), gs, dim3(256), 0, st, G, ip.Nv, ip.ns, ip.m,
+                       (const C *)y, part2);
   }
+  hipLaunchKernelGGL((k_inc_add<R>), dim3((unsigned)((ip.Nv + 255) / 256)), dim3(256), 0, st,
+                     (const C *)part2, ip.Nv, nb, adjoint ? hd : (R)1, (C *)u);
   return hipGetLastError();
 }
 

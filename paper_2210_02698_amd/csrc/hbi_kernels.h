@@ -78,11 +78,12 @@ hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
 
 // Curve inclusion (hbi_inclusion.hip).  G: chunked N_v x N_s array of
 // g(cell, segment); M = (K^{s2s})^{-1} and MH = M^H, column-major N_s x N_s;
-// w the segment lengths; part, z, y scratch of nchunk*N_s, N_s, N_s entries.
+// w the segment lengths; part, z, y, part2, part3 scratch of nchunk*N_s,
+// N_s, N_s, ceil(N_s/256)*N_v and ceil(N_s/32)*N_s entries.
 // Element type complex64/complex128 (w float/double) as for the factors.
 struct InclusionPlan {
   const void *G = nullptr, *M = nullptr, *MH = nullptr, *w = nullptr;
-  void *part = nullptr, *z = nullptr, *y = nullptr;
+  void *part = nullptr, *z = nullptr, *y = nullptr, *part2 = nullptr, *part3 = nullptr;
   int64_t Nv = 0;
   int32_t ns = 0, m = 0;
 };

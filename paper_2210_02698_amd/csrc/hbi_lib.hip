@@ -203,7 +203,7 @@ struct hbi_ctx {
   std::vector<double> inc_xy, inc_w, inc_n;
   DevBuf inc_xy_d, inc_w_d, inc_n_d;
   DevBuf cellof_d;   // [Nv + inc_ns]: the cell containing each point (DevCells::cellof)
-  DevBuf inc_G, inc_M, inc_MH, inc_wf, inc_part, inc_z, inc_y;
+  DevBuf inc_G, inc_M, inc_MH, inc_wf, inc_part, inc_z, inc_y, inc_part2, inc_part3;
   InclusionPlan inc_plan;
   double t_inc = 0;
   bool profiling = false;
@@ -262,7 +262,9 @@ struct hbi_ctx {
     F.release(); Felems = 0; leaves_d.release(); vd_d.release(); kd_d.release();
     units_d.clear(); items_d.clear(); items_adj_d.clear(); plan = ApplyPlan();
     inc_G.release(); inc_M.release(); inc_MH.release(); inc_wf.release();
-    inc_part.release(); inc_z.release(); inc_y.release(); inc_plan = InclusionPlan(); t_inc = 0;
+    inc_part.release(); inc_z.release(); inc_y.release(); inc_part2.release();
+    inc_part3.release();
+    inc_plan = InclusionPlan(); t_inc = 0;
     leaves_h.clear(); vd_h.clear(); kd_h.clear(); units_h.clear(); batch.reset(); ztotal = 0; z_d.release();
     nnz_v = nnz_w = nnz_k = nnz_d = entries_eval = nid = 0; rank_max = 0; rank_sum = 0;
     t_prep = t_wait = t_compact = 0; entry_slots = 0;
@@ -1421,9 +1423,12 @@ void build_inclusion(hbi_ctx *c) {
   HBI_HIP(c->inc_part.alloc(esz * (size_t)nchunk * ns));
   HBI_HIP(c->inc_z.alloc(esz * (size_t)ns));
   HBI_HIP(c->inc_y.alloc(esz * (size_t)ns));
+  HBI_HIP(c->inc_part2.alloc(esz * (size_t)Nv * ((ns + 255) / 256)));
+  HBI_HIP(c->inc_part3.alloc(esz * (size_t)ns * ((ns + 31) / 32)));
   InclusionPlan &ip = c->inc_plan;
   ip.G = c->inc_G.p; ip.M = c->inc_M.p; ip.MH = c->inc_MH.p; ip.w = c->inc_wf.p;
-  ip.part = c->inc_part.p; ip.z = c->inc_z.p; ip.y = c->inc_y.p;
+  ip.part = c->inc_part.p; ip.z = c->inc_z.p; ip.y = c->inc_y.p; ip.part2 = c->inc_part2.p;
+  ip.part3 = c->inc_part3.p;
   ip.Nv = Nv; ip.ns = ns; ip.m = m;
   c->t_inc = now_s() - t0;
 }
