@@ -180,7 +180,9 @@ def main():
             err = float(np.linalg.norm(ug - ref) / np.linalg.norm(ref))
         t_apply, prof = timed(op, s)
         esz = 16 if prec == "f64" else 8
-        fbytes = info["nnz_total"] * esz
+        # factor entries, and the transfer units' column orders the forward
+        # product gathers its inputs through (half of the index store)
+        fbytes = info["nnz_total"] * esz + info["index_bytes"] // 2
         vec_bytes = (2 * prob.Nv + 2 * info["z_entries"]) * esz
         results[prec] = dict(build_s=build_s, err=err, ms=t_apply * 1e3, info=info, prof=prof,
                              gcells=prob.Nv / t_apply / 1e9,

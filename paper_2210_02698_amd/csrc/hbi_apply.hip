@@ -131,40 +131,122 @@ __global__ __launch_bounds__(256) void k_vstage(const cplx_t<R> *s,
   }
 }
 
-// One wave per work item: rows [r0, r0 + 64) of a transfer unit (whole unit
-// when it has <= 64 rows).  Items are ordered by decreasing cost, and the
-// factor store holds the units in that order.  The unit's input skeleton
-// vector is staged in the wave's own LDS slice when it has at most WX
-// entries, so the streamed factor block is the only vector-memory traffic
-// of the loop; the waves of a workgroup do not wait for each other.
+// Rows [off, off + 64) of a compact transfer unit (all rows when it has at
+// most 32): row i of child a is X[i] + sum_m T_a[i, m] X[ra + m] with
+// X = xv + xoff the inputs in a's column order (xoff = 0), likewise for b
+// (xoff = c).  Per lane: T column stride rc, column count t, and the columns
+// grp, grp + G, ... when G > 1 lanes share a row.
+template <typename C, int B, typename XF>
+__device__ __forceinline__ void wstage_rows(const WItem &U, const C *__restrict__ Ta, int lane,
+                                            XF xv, C *z) {
+  const int ra = U.ra, rb = U.rb, c = U.c, Rt = ra + rb;
+  const int G = Rt <= 32 ? 64 / Rt : 1;
+  const int row = Rt <= 32 ? lane % Rt : U.off + lane;
+  const int grp = Rt <= 32 ? lane / Rt : 0;
+  const bool isb = row >= ra;
+  const int i = isb ? row - ra : row;
+  const int rc = isb ? rb : ra;
+  const int xo = (isb ? c : 0) + rc;
+  const C *T = (isb ? Ta + (int64_t)ra * (c - ra) : Ta) + i + (int64_t)grp * rc;
+  const int64_t tstep = (int64_t)G * rc;
+  const bool act = row < Rt && grp < G;
+  const int t = c - rc;
+  const int nt = act && t > grp ? (t - grp + G - 1) / G : 0;
+  C acc{0, 0};
+  for (int q0 = 0; q0 < nt; q0 += B) {
+    C mv[B], xq[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      if (q0 + u < nt) {
+        mv[u] = ldf(T + (q0 + u) * tstep);
+        xq[u] = xv(xo + grp + (q0 + u) * G);
+      } else {
+        mv[u] = C{0, 0};
+        xq[u] = C{0, 0};
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) cfma(acc, mv[u], xq[u]);
+  }
+  if (G > 1) {
+    // combine the G partial sums of each row (lanes row, row+Rt, ...)
+    C tot = acc;
+    for (int g = 1; g < G; ++g) {
+      const int src = lane + g * Rt;
+      const auto re = __shfl(acc.x, src < 64 ? src : lane, 64);
+      const auto im = __shfl(acc.y, src < 64 ? src : lane, 64);
+      if (src < 64) { tot.x += re; tot.y += im; }
+    }
+    acc = tot;
+  }
+  if (act && grp == 0) {
+    const C x0 = xv((isb ? c : 0) + i);
+    (isb ? z + U.zoutb : z + U.zouta)[i] = C{acc.x + x0.x, acc.y + x0.y};
+  }
+}
+
+// One wave per work item: rows [r0, r0 + 64) of a transfer unit, the pair
+// stacked a then b (the whole unit when it has <= 64 rows).  Items are
+// ordered by decreasing cost, and the factor store holds the units in that
+// order.  Row i of child a is x[ia[i]] + sum_m T_a[i, m] x[ia[ra + m]]
+// (X = [I, T] Pi^T), likewise for b with its own column order ib.  Both
+// gathered inputs are staged in the wave's own LDS slice when 2c <= WX, so
+// the streamed T blocks are the only vector-memory traffic of the loop; the
+// waves of a workgroup do not wait for each other.  Lanes are (row, column
+// group) for units of at most 32 rows and rows otherwise, as in wave_gemv.
 // (A persistent variant, each wave looping over items, measured slower.)
 template <typename R>
 __global__ __launch_bounds__(256) void k_wstage(const WItem *items, int64_t nitems,
-                                                const cplx_t<R> *F, cplx_t<R> *z) {
+                                                const uint16_t *fidx, const cplx_t<R> *F,
+                                                cplx_t<R> *z) {
   using C = cplx_t<R>;
-  constexpr int WX = sizeof(R) == 4 ? 512 : 256;
+  constexpr int WX = 512;   // LDS entries per wave: both permuted inputs, c <= WX / 2
   __shared__ C xs[4][WX];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t it = (int64_t)blockIdx.x * 4 + wave;
   if (it >= nitems) return;
   const WItem U = items[it];
-  C *za = z + U.zouta;
-  C *zb = z + U.zoutb;
-  const int ra = U.ra;
-  auto store = [&](int row, C v) {
-    if (row < ra) za[row] = v; else zb[row - ra] = v;
-  };
-  if (U.c <= WX) {
-    C *xw = xs[wave];
-    for (int i = lane; i < U.c; i += 64) xw[i] = z[U.zin + i];
+  const int c = U.c;
+  const uint16_t *ia = fidx + U.ioff;   // ia, then ib at ia + c
+  const C *zin = z + U.zin;
+  const bool lds = 2 * c <= WX;
+  C *xw = xs[wave];
+  if (lds) {
+    // the inputs in their own order and both column orders (three
+    // independent contiguous loads), then the two gathers within LDS:
+    // xw[0, c) = x[ia], xw[c, 2c) = x[ib]
+    uint16_t *iw = (uint16_t *)(xw + c);
+    for (int k = lane; k < c; k += 64) xw[k] = zin[k];
+    for (int k = lane; k < 2 * c; k += 64) iw[k] = ia[k];
     wave_lds_sync();
-    wave_gemv<C>(F + U.foff, ra + U.rb, U.c, lane, [&](int col) { return xw[col]; }, store, U.off,
-                 U.off + 64);
+    R ar[WX / 128], ai[WX / 128], br[WX / 128], bi[WX / 128];
+#pragma unroll
+    for (int u = 0; u < WX / 128; ++u) {
+      const int k = lane + 64 * u < c ? lane + 64 * u : 0;
+      const C va = xw[iw[k]], vb = xw[iw[c + k]];
+      ar[u] = va.x; ai[u] = va.y;
+      br[u] = vb.x; bi[u] = vb.y;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int u = 0; u < WX / 128; ++u) {
+      const int k = lane + 64 * u;
+      if (k < c) {
+        xw[k] = C{ar[u], ai[u]};
+        xw[c + k] = C{br[u], bi[u]};
+      }
+    }
+    wave_lds_sync();
+  }
+  const C *Ta = F + U.foff;
+  if (lds) {
+    // 8 loads in flight (FP32) or 4 (FP64) keep the registers within 8 (6)
+    // waves per SIMD
+    wstage_rows<C, sizeof(R) == 4 ? 8 : 4>(U, Ta, lane, [&](int k) { return xw[k]; }, z);
   } else {
-    const C *zin = z + U.zin;
-    wave_gemv<C>(F + U.foff, ra + U.rb, U.c, lane, [&](int col) { return zin[col]; }, store,
-                 U.off, U.off + 64);
+    // wide units (c > WX / 2, rare): inputs gathered from global memory
+    wstage_rows<C, 4>(U, Ta, lane, [&](int k) { return zin[ia[k]]; }, z);
   }
 }
 
@@ -247,27 +329,44 @@ __global__ __launch_bounds__(256) void k_final_adj(const cplx_t<R> *y,
   }
 }
 
+// Adjoint of a transfer unit, one lane per input column j of the window
+// [off, off + 64): column j of X_a is e_k when pa[j] = k < ra, and column
+// pa[j] - ra of T_a otherwise, so (X_a^H w_a)_j is w_a[k] or a conjugate
+// dot product with that column of T_a; child b adds the same way.
 template <typename R>
 __global__ __launch_bounds__(256) void k_wstage_adj(const WItem *items, int64_t nitems,
-                                                    const cplx_t<R> *F, cplx_t<R> *z) {
+                                                    const uint16_t *fidx, const cplx_t<R> *F,
+                                                    cplx_t<R> *z) {
   using C = cplx_t<R>;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t it = (int64_t)blockIdx.x * 4 + wave;
   if (it >= nitems) return;
   const WItem U = items[it];
-  const int ra = U.ra, Rt = U.ra + U.rb;
+  const int ra = U.ra, rb = U.rb, c = U.c;
+  const uint16_t *pa = fidx + U.ioff + 2 * (int64_t)c, *pb = pa + c;
   const C *wa = z + U.zouta, *wb = z + U.zoutb;
-  const C *M = F + U.foff;
-  const int c1 = U.off + 64 < U.c ? U.off + 64 : U.c;
+  const C *Ta = F + U.foff, *Tb = Ta + (int64_t)ra * (c - ra);
+  const int c1 = U.off + 64 < c ? U.off + 64 : c;
   const int col = U.off + lane;
   if (col < c1) {
     C acc{0, 0};
-    const C *cm = M + (int64_t)col * Rt;
-    batched_dot<LoadBatch<C>::value, true>(
-        acc, ra, [&](int i) { return ldf(cm + i); }, [&](int i) { return wa[i]; });
-    batched_dot<LoadBatch<C>::value, true>(
-        acc, Rt - ra, [&](int i) { return ldf(cm + ra + i); }, [&](int i) { return wb[i]; });
+    const int ka = pa[col], kb = pb[col];
+    if (ka < ra) {
+      acc = wa[ka];
+    } else {
+      const C *cm = Ta + (int64_t)(ka - ra) * ra;
+      batched_dot<LoadBatch<C>::value, true>(
+          acc, ra, [&](int i) { return ldf(cm + i); }, [&](int i) { return wa[i]; });
+    }
+    if (kb < rb) {
+      acc.x += wb[kb].x;
+      acc.y += wb[kb].y;
+    } else {
+      const C *cm = Tb + (int64_t)(kb - rb) * rb;
+      batched_dot<LoadBatch<C>::value, true>(
+          acc, rb, [&](int i) { return ldf(cm + i); }, [&](int i) { return wb[i]; });
+    }
     z[U.zin + col] = acc;
   }
 }
@@ -341,7 +440,7 @@ hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
       const int64_t ni = ap.nitems[k];
       pre("k_wstage", ap.w_elems[k], ap.w_idx[k]);
       hipLaunchKernelGGL((k_wstage<R>), dim3((ni + 3) / 4), dim3(256), 0, st,
-                         ap.items[k], ni, Fc, zc);
+                         ap.items[k], ni, ap.fidx, Fc, zc);
       post();
     }
     pre("k_final", ap.f_elems, ap.f_idx);
@@ -363,7 +462,7 @@ hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
       const int64_t ni = ap.nitems_adj[k];
       pre("k_wstage_adj", ap.w_elems[k], ap.w_idx[k]);
       hipLaunchKernelGGL((k_wstage_adj<R>), dim3((ni + 3) / 4), dim3(256), 0, st,
-                         ap.items_adj[k], ni, Fc, zc);
+                         ap.items_adj[k], ni, ap.fidx, Fc, zc);
       post();
     }
     pre("k_vstage_adj", ap.v_elems, ap.v_idx);

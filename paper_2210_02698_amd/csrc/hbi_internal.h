@@ -73,17 +73,26 @@ struct IdBlock {
 // Apply descriptors (element offsets into the factor store / z workspace).
 struct VDesc { int64_t foff; int64_t zout; int32_t r; int32_t pad; };
 struct KDesc { int64_t foff; int64_t zin; int32_t r; int32_t pad; };
+// A transfer unit: the interpolation matrices X_a (ra x c) and X_b (rb x c)
+// of a sibling pair over the same c candidate columns.  An interpolative
+// decomposition gives X = [I, T] Pi^T, so only T is stored: T_a (ra x ta,
+// ta = c - ra) at foff and T_b (rb x tb) at foff + ra ta, column-major.  The
+// index store holds at ioff four lists of c entries: ia (the skeleton
+// columns of a in pivot order, then its other columns in increasing order),
+// ib, and their inverses pa (pa[ia[k]] = k), pb.  Row i of X_a x is
+// x[ia[i]] + sum_m T_a[i, m] x[ia[ra + m]].
 struct WUnit {
-  int64_t foff;      // stacked [X_a; X_b], column-major (ra + rb) x c
+  int64_t foff;
   int64_t zin;       // c inputs (skeletons of nu_1 then nu_2)
   int64_t zouta, zoutb;
+  int64_t ioff;
   int32_t ra, rb, c, pad;
 };
-// Work item of a transfer stage: rows (forward) or columns (adjoint)
-// [off, off + 64) of a unit, with the unit's fields copied in so that a wave
-// needs one descriptor load.
+// Work item of a transfer stage: rows (forward, of the pair stacked a then
+// b) or columns (adjoint) [off, off + 64) of a unit, with the unit's fields
+// copied in so that a wave needs one descriptor load.
 struct WItem {
-  int64_t foff, zin, zouta, zoutb;
+  int64_t foff, zin, zouta, zoutb, ioff;
   int32_t ra, rb, c, off;
 };
 struct LeafInfo { int32_t start, size; int64_t dense_off; };

@@ -7,7 +7,15 @@
 namespace hbi {
 
 struct CopyDesc { const double2 *src; double2 *dst; int64_t count; };
-struct PairDesc { const double2 *xa, *xb; double2 *dst; int32_t ra, rb, c, pad; };
+// Compaction of a sibling pair's interpolation matrices: T_a = X_a[:, nsa]
+// (ra x (c - ra)) then T_b = X_b[:, nsb] at dst, column-major; nsa and nsb
+// list the non-skeleton columns (device, c - ra and c - rb entries).
+struct PairDesc {
+  const double2 *xa, *xb;
+  double2 *dst;
+  const uint16_t *nsa, *nsb;
+  int32_t ra, rb, c, pad;
+};
 struct PlaceDesc { const double2 *src; int64_t dst; int64_t count; };   // dst: element offset
 
 // Optional observer of apply launches (per-kernel event timing).
@@ -25,6 +33,7 @@ struct ApplyPlan {
   const int32_t *perm = nullptr;
   const VDesc *vd = nullptr;
   const KDesc *kd = nullptr;
+  const uint16_t *fidx = nullptr;   // index store of the transfer units
   std::vector<const WUnit *> units;   // index k = 1..Lmax
   std::vector<int64_t> nunits;
   std::vector<const WItem *> items, items_adj;   // index k

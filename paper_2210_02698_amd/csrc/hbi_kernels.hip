@@ -1366,16 +1366,24 @@ __global__ void k_copy_blocks(const CopyDesc *d, int64_t nb) {
 
 // Stack the interpolation matrices of a sibling pair, X_a (ra x c) and X_b
 // (rb x c), into one column-major (ra + rb) x c transfer block.
+// The non-skeleton columns of a sibling pair's interpolation matrices
+// X = [I, T] Pi^T (the skeleton columns are unit vectors and are not
+// stored): T_a = X_a[:, nsa], then T_b = X_b[:, nsb].
 __global__ void k_pack_pairs(const PairDesc *d, int64_t np) {
   const int64_t b = blockIdx.x;
   if (b >= np) return;
   const PairDesc p = d[b];
-  const int R = p.ra + p.rb;
-  const int64_t n = (int64_t)R * p.c;
+  const int ta = p.c - p.ra, tb = p.c - p.rb;
+  const int64_t na = (int64_t)p.ra * ta, n = na + (int64_t)p.rb * tb;
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-    const int col = (int)(i / R), row = (int)(i % R);
-    p.dst[i] = row < p.ra ? p.xa[row + (int64_t)col * p.ra]
-                          : p.xb[row - p.ra + (int64_t)col * p.rb];
+    if (i < na) {
+      const int m = (int)(i / p.ra), row = (int)(i % p.ra);
+      p.dst[i] = p.xa[row + (int64_t)p.nsa[m] * p.ra];
+    } else {
+      const int64_t e = i - na;
+      const int m = (int)(e / p.rb), row = (int)(e % p.rb);
+      p.dst[i] = p.xb[row + (int64_t)p.nsb[m] * p.rb];
+    }
   }
 }
 

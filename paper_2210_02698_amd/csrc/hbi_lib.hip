@@ -191,6 +191,7 @@ struct hbi_ctx {
   hbi_prec prec = HBI_F64;
   DevBuf F;
   int64_t Felems = 0;
+  DevBuf Fi;   // uint16 index store of the transfer units (WUnit)
   DevBuf leaves_d, vd_d, kd_d;
   std::vector<DevBuf> units_d, items_d, items_adj_d;
   ApplyPlan plan;
@@ -259,7 +260,7 @@ struct hbi_ctx {
     return std::min(hi, std::max(lo, (int64_t)(fr / 8)));
   }
   void drop_factors() {
-    F.release(); Felems = 0; leaves_d.release(); vd_d.release(); kd_d.release();
+    F.release(); Felems = 0; Fi.release(); leaves_d.release(); vd_d.release(); kd_d.release();
     units_d.clear(); items_d.clear(); items_adj_d.clear(); plan = ApplyPlan();
     inc_G.release(); inc_M.release(); inc_MH.release(); inc_wf.release();
     inc_part.release(); inc_z.release(); inc_y.release(); inc_part2.release();
@@ -790,10 +791,11 @@ struct LevelState {
   std::vector<int64_t> skel_off;   // into skel, size nblk+1
   std::vector<int32_t> skel;       // tree positions
   std::vector<int64_t> foff;
+  std::vector<int64_t> ioff;   // transfer blocks: the pair's index lists
   std::vector<int64_t> zoff;
   void reset(int64_t nblk) {
     rank.assign(nblk, 0); skel_off.assign(nblk + 1, 0); skel.clear();
-    foff.assign(nblk, 0); zoff.assign(nblk, 0);
+    foff.assign(nblk, 0); ioff.assign(nblk, -1); zoff.assign(nblk, 0);
   }
 };
 
@@ -869,7 +871,7 @@ std::vector<PlaceDesc> layout_store(const std::vector<Chunk> &chunks, int Lv, in
     });
     for (const auto &o : ord) {
       WUnit &U = us[o.second];
-      place(U.foff, (int64_t)(U.ra + U.rb) * U.c);
+      place(U.foff, (int64_t)U.ra * (U.c - U.ra) + (int64_t)U.rb * (U.c - U.rb));
     }
   }
   for (int64_t g = 0; g < nleaf; ++g) {
@@ -914,18 +916,23 @@ void build_factors(hbi_ctx *c, double tol) {
   double t_host = 0, t_gpu = 0;
 
   // Compact the X matrices of an ID batch into a new chunk.  Level 0 keeps
-  // each V_{tau,nu} (r x |nu|); higher levels stack the sibling pair
-  // (2t', j), (2t'+1, j) into one column-major transfer block [X_a; X_b].
+  // each V_{tau,nu} (r x |nu|); higher levels keep, for the sibling pair
+  // (2t', j), (2t'+1, j), the non-skeleton columns T_a then T_b of
+  // X = [I, T] Pi^T, and append the pair's column orders and their inverses
+  // (ia, ib, pa, pb) to the index store fi_h.
+  std::vector<uint16_t> fi_h;
   auto compact = [&](std::vector<BlockOut> &outs, int64_t first, int64_t cnt,
                      const std::vector<int32_t> &ncols, std::vector<int64_t> &foff_out,
-                     bool pairs) {
+                     std::vector<int64_t> &ioff_out, bool pairs) {
     int64_t tot = 0;
-    for (int64_t q = 0; q < cnt; ++q) tot += (int64_t)outs[first + q].rank * ncols[first + q];
+    for (int64_t q = 0; q < cnt; ++q)
+      tot += (int64_t)outs[first + q].rank *
+             (pairs ? ncols[first + q] - outs[first + q].rank : ncols[first + q]);
     Chunk ch;
-    HBI_HIP(ch.buf.alloc(sizeof(double2) * tot));
+    HBI_HIP(ch.buf.alloc(sizeof(double2) * std::max<int64_t>(tot, 1)));
     ch.goff = Fg;
     ch.count = tot;
-    DevBuf d_d;
+    DevBuf d_d, ns_d;
     int64_t o = 0;
     if (!pairs) {
       std::vector<CopyDesc> cd(cnt);
@@ -933,24 +940,58 @@ void build_factors(hbi_ctx *c, double tol) {
         const int64_t e = (int64_t)outs[first + q].rank * ncols[first + q];
         cd[q] = CopyDesc{outs[first + q].X, ch.buf.as<double2>() + o, e};
         foff_out[first + q] = Fg + o;
+        ioff_out[first + q] = -1;
         o += e;
       }
       upload(d_d, cd);
       HBI_HIP(launch_copy_blocks(d_d.as<CopyDesc>(), cnt, c->stream));
     } else {
       if (cnt % 2 != 0) throw Error{HBI_ERR_NUMERIC, "internal error: unpaired transfer block"};
-      std::vector<PairDesc> pd(cnt / 2);
+      const int64_t np = cnt / 2;
+      std::vector<PairDesc> pd(np);
+      std::vector<uint16_t> ns_h;        // non-skeleton lists for the pack kernel
+      std::vector<int64_t> nso(2 * np);
+      std::vector<uint16_t> ord, inv;
+      std::vector<uint8_t> mark;
       for (int64_t q = 0; q < cnt; q += 2) {
         const BlockOut &a = outs[first + q], &b = outs[first + q + 1];
         const int32_t cc = ncols[first + q];
         if (ncols[first + q + 1] != cc) throw Error{HBI_ERR_NUMERIC, "internal error: pair width"};
-        pd[q / 2] = PairDesc{a.X, b.X, ch.buf.as<double2>() + o, a.rank, b.rank, cc, 0};
+        const int64_t io = (int64_t)fi_h.size();
+        fi_h.resize(io + 4 * (int64_t)cc);
+        for (int h = 0; h < 2; ++h) {
+          const BlockOut &x = h ? b : a;
+          // column order: skeleton columns in pivot order, then the others
+          mark.assign(cc, 0);
+          ord.clear();
+          for (int32_t k = 0; k < x.rank; ++k) { ord.push_back((uint16_t)x.piv[k]); mark[x.piv[k]] = 1; }
+          for (int32_t j = 0; j < cc; ++j)
+            if (!mark[j]) ord.push_back((uint16_t)j);
+          if ((int32_t)ord.size() != cc)
+            throw Error{HBI_ERR_NUMERIC, "internal error: repeated pivot"};
+          inv.assign(cc, 0);
+          for (int32_t k = 0; k < cc; ++k) inv[ord[k]] = (uint16_t)k;
+          std::copy(ord.begin(), ord.end(), fi_h.begin() + io + (int64_t)h * cc);
+          std::copy(inv.begin(), inv.end(), fi_h.begin() + io + (int64_t)(2 + h) * cc);
+          nso[q + h] = (int64_t)ns_h.size();
+          ns_h.insert(ns_h.end(), ord.begin() + x.rank, ord.end());
+        }
+        const int64_t ea = (int64_t)a.rank * (cc - a.rank);
+        pd[q / 2] = PairDesc{a.X, b.X, ch.buf.as<double2>() + o, nullptr, nullptr,
+                             a.rank, b.rank, cc, 0};
         foff_out[first + q] = Fg + o;
-        foff_out[first + q + 1] = Fg + o + (int64_t)a.rank * cc;
-        o += (int64_t)(a.rank + b.rank) * cc;
+        foff_out[first + q + 1] = Fg + o + ea;
+        ioff_out[first + q] = io;
+        ioff_out[first + q + 1] = io;
+        o += ea + (int64_t)b.rank * (cc - b.rank);
+      }
+      upload(ns_d, ns_h);
+      for (int64_t q = 0; q < np; ++q) {
+        pd[q].nsa = ns_d.as<uint16_t>() + nso[2 * q];
+        pd[q].nsb = ns_d.as<uint16_t>() + nso[2 * q + 1];
       }
       upload(d_d, pd);
-      HBI_HIP(launch_pack_pairs(d_d.as<PairDesc>(), cnt / 2, c->stream));
+      HBI_HIP(launch_pack_pairs(d_d.as<PairDesc>(), np, c->stream));
     }
     HBI_HIP(hipStreamSynchronize(c->stream));
     Fg += tot;
@@ -977,7 +1018,7 @@ void build_factors(hbi_ctx *c, double tol) {
     // per-block skeleton staging (filled as batches finish)
     std::vector<std::vector<int32_t>> skel_tmp(nblk);
     std::vector<int32_t> rank_tmp(nblk);
-    std::vector<int64_t> foff_tmp(nblk);
+    std::vector<int64_t> foff_tmp(nblk), ioff_tmp(nblk);
     // Blocks go to the GPU in chunks of CH: proxy rows and candidate columns
     // on the host, then the chunk's batches.  The host builds chunk i + 1
     // and prepares every next batch while the GPU runs the current one.
@@ -988,7 +1029,7 @@ void build_factors(hbi_ctx *c, double tol) {
       std::vector<BlockIn> bin;
       std::vector<int32_t> ncols;
       std::vector<BlockOut> outs;
-      std::vector<int64_t> foff_local;
+      std::vector<int64_t> foff_local, ioff_local;
       Batcher::Plan plan;
       size_t next = 0, done = 0;
     };
@@ -1039,6 +1080,7 @@ void build_factors(hbi_ctx *c, double tol) {
       }
       J->outs.resize(n);
       J->foff_local.resize(n);
+      J->ioff_local.resize(n);
       J->plan = B.plan(J->bin, true, k > 0);
       return J;
     };
@@ -1049,8 +1091,9 @@ void build_factors(hbi_ctx *c, double tol) {
         for (int32_t r = 0; r < o.rank; ++r) skel_tmp[J.c0 + q][r] = J.cands[q][o.piv[r]];
         rank_tmp[J.c0 + q] = o.rank;
         foff_tmp[J.c0 + q] = J.foff_local[q];
-        const int64_t e = (int64_t)o.rank * J.ncols[q];
-        if (k == 0) c->nnz_v += e; else c->nnz_w += e;
+        ioff_tmp[J.c0 + q] = J.ioff_local[q];
+        if (k == 0) c->nnz_v += (int64_t)o.rank * J.ncols[q];
+        else c->nnz_w += (int64_t)o.rank * (J.ncols[q] - o.rank);
       }
     };
     {
@@ -1077,7 +1120,7 @@ void build_factors(hbi_ctx *c, double tol) {
         B.prep(P, J->bin, J->plan, bt.first, bt.second, true, tol);
         P.outs = &J->outs;
         P.on_batch = [&, J](int64_t first, int64_t cnt) {
-          compact(J->outs, first, cnt, J->ncols, J->foff_local, k > 0);
+          compact(J->outs, first, cnt, J->ncols, J->foff_local, J->ioff_local, k > 0);
           if (++J->done == J->plan.batches.size()) {
             finished.push_back(std::move(live.front()));   // chunks finish in order
             live.pop_front();
@@ -1095,6 +1138,7 @@ void build_factors(hbi_ctx *c, double tol) {
       const int64_t bi = (int64_t)bk.t * ((int64_t)1 << (L - k)) + bk.j;
       cur[bk.b].rank[bi] = rank_tmp[q];
       cur[bk.b].foff[bi] = foff_tmp[q];
+      cur[bk.b].ioff[bi] = ioff_tmp[q];
     }
     for (int64_t b = 0; b < nbf; ++b) {
       if (bfs[b].L < k) continue;
@@ -1132,11 +1176,13 @@ void build_factors(hbi_ctx *c, double tol) {
             U.ra = cs.rank[a]; U.rb = cs.rank[bb];
             U.c = ps.rank[in] + ps.rank[in + 1];
             U.foff = cs.foff[a];
+            U.ioff = cs.ioff[a];
             U.zin = ps.zoff[in];
             U.zouta = cs.zoff[a];
             U.zoutb = cs.zoff[bb];
             if (ps.zoff[in + 1] != ps.zoff[in] + ps.rank[in] ||
-                cs.foff[bb] != cs.foff[a] + (int64_t)U.ra * U.c)
+                cs.foff[bb] != cs.foff[a] + (int64_t)U.ra * (U.c - U.ra) ||
+                cs.ioff[bb] != cs.ioff[a] || U.ioff < 0)
               throw Error{HBI_ERR_NUMERIC, "internal layout error in the transfer stage"};
             units[k].push_back(U);
           }
@@ -1230,6 +1276,7 @@ void build_factors(hbi_ctx *c, double tol) {
   c->Felems = Fg;
   const size_t esz = c->prec == HBI_F64 ? sizeof(double2) : sizeof(float2);
   HBI_HIP(c->F.alloc(esz * std::max<int64_t>(Fg, 1)));
+  upload(c->Fi, fi_h);
   {
     const std::vector<PlaceDesc> place = layout_store(chunks, Lv, nleaf, vd, kd, leaves, units, Fg);
     DevBuf pd;
@@ -1256,6 +1303,7 @@ void build_factors(hbi_ctx *c, double tol) {
   c->plan.perm = c->perm_d.as<int32_t>();
   c->plan.vd = c->vd_d.as<VDesc>();
   c->plan.kd = c->kd_d.as<KDesc>();
+  c->plan.fidx = c->Fi.as<uint16_t>();
   c->plan.units.assign(Lmax + 1, nullptr);
   c->plan.nunits.assign(Lmax + 1, 0);
   c->items_d.clear();
@@ -1277,7 +1325,7 @@ void build_factors(hbi_ctx *c, double tol) {
       const WUnit &U = units[k][u];
       const int Rt = U.ra + U.rb;
       auto item = [&U](int32_t off) {
-        return WItem{U.foff, U.zin, U.zouta, U.zoutb, U.ra, U.rb, U.c, off};
+        return WItem{U.foff, U.zin, U.zouta, U.zoutb, U.ioff, U.ra, U.rb, U.c, off};
       };
       if (Rt <= 64) {
         fw.push_back({(int64_t)Rt * U.c, item(0)});
@@ -1328,8 +1376,12 @@ void build_factors(hbi_ctx *c, double tol) {
     ap.v_elems = ve; ap.v_idx = vi; ap.f_elems = fe; ap.f_idx = fi;
     for (int k = 1; k <= Lmax; ++k) {
       for (const WUnit &U : units[k])
-        ap.w_elems[k] += (double)(U.ra + U.rb) * U.c + U.c + U.ra + U.rb;
+        ap.w_elems[k] += (double)U.ra * (U.c - U.ra) + (double)U.rb * (U.c - U.rb) + U.c +
+                         U.ra + U.rb;
+      // descriptors, and the two column orders (uint16) a unit's inputs are
+      // gathered through
       ap.w_idx[k] = (double)sizeof(WItem) * ap.nitems[k];
+      for (const WUnit &U : units[k]) ap.w_idx[k] += 2.0 * sizeof(uint16_t) * U.c;
     }
   }
   HBI_HIP(c->z_d.alloc(esz * std::max<int64_t>(c->ztotal, 1)));
@@ -1649,15 +1701,19 @@ void build_items(BatchCache &B, int nb) {
         const char *F = c->F.as<char>();
         char *zb = ws + J.z_off * esz;
         const int ngrp = (J.Np / 16 + nb - 1) / nb;
-        for (const WUnit &U : c->units_h[k]) {
-          const int Rt = U.ra + U.rb;
-          for (int r0 = 0; r0 < Rt; r0 += 16)
-            for (int gq = 0; gq < ngrp; ++gq)
-              wi.push_back({(int64_t)U.c, MWItem{F + U.foff * esz, zb + U.zin * J.Np * esz,
-                                                 zb + U.zouta * J.Np * esz,
-                                                 zb + U.zoutb * J.Np * esz, U.ra, U.rb, U.c, r0,
-                                                 gq * nb, J.Np}});
-        }
+        const uint16_t *fidx = c->Fi.as<uint16_t>();
+        for (const WUnit &U : c->units_h[k])
+          for (int h = 0; h < 2; ++h) {
+            // child a, then child b (T_b after T_a, ib after ia)
+            const int32_t r = h ? U.rb : U.ra;
+            const int64_t toff = U.foff + (h ? (int64_t)U.ra * (U.c - U.ra) : 0);
+            const uint16_t *idx = fidx + U.ioff + (h ? U.c : 0);
+            char *zo = zb + (h ? U.zoutb : U.zouta) * J.Np * esz;
+            for (int r0 = 0; r0 < r; r0 += 16)
+              for (int gq = 0; gq < ngrp; ++gq)
+                wi.push_back({(int64_t)U.c, MWItem{F + toff * esz, idx, zb + U.zin * J.Np * esz,
+                                                   zo, r, U.c, r0, gq * nb, J.Np, 0}});
+          }
       }
       std::stable_sort(wi.begin(), wi.end(), [](const std::pair<int64_t, MWItem> &a,
                                                 const std::pair<int64_t, MWItem> &b) {
@@ -2182,7 +2238,7 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       "{\"state\": %d, \"dim\": %d, \"N_v\": %lld, \"L_v\": %d, \"NT\": %d, \"nI\": %d, "
       "\"prec\": \"%s\", \"tol\": %.3e, \"chi\": %.3f, \"leaf_size\": %d, "
       "\"nnz_v\": %lld, \"nnz_w\": %lld, \"nnz_k\": %lld, \"nnz_dense\": %lld, "
-      "\"nnz_total\": %lld, \"factor_bytes\": %lld, \"z_entries\": %lld, "
+      "\"nnz_total\": %lld, \"factor_bytes\": %lld, \"index_bytes\": %lld, \"z_entries\": %lld, "
       "\"n_id\": %lld, \"rank_max\": %d, \"rank_mean\": %.3f, \"entries_evaluated\": %lld, "
       "\"entry_tile_fill\": %.4f, \"n_id_onchip\": %lld, \"n_id_global\": %lld, "
       "\"id_rows_mean\": %.1f, \"id_rows_max\": %d, \"id_cols_mean\": %.1f, \"id_cmac\": %.6e, "
@@ -2194,7 +2250,8 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       ctx->state, ctx->dim, (long long)Nv, ctx->geo.Lv, ctx->NT, ctx->nI,
       ctx->prec == HBI_F64 ? "f64" : "f32", ctx->tol, ctx->chi(), ctx->leaf(),
       (long long)ctx->nnz_v, (long long)ctx->nnz_w, (long long)ctx->nnz_k, (long long)ctx->nnz_d,
-      (long long)ctx->Felems, (long long)(ctx->Felems * (int64_t)esz), (long long)ctx->ztotal,
+      (long long)ctx->Felems, (long long)(ctx->Felems * (int64_t)esz), (long long)ctx->Fi.n,
+      (long long)ctx->ztotal,
       (long long)ctx->nid, ctx->rank_max, ctx->nid ? ctx->rank_sum / ctx->nid : 0.0,
       (long long)ctx->entries_eval,
       ctx->entry_slots ? (double)ctx->entries_eval / (double)ctx->entry_slots : 0.0,

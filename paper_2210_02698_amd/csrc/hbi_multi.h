@@ -4,13 +4,16 @@
 
 namespace hbi {
 
-// Transfer-stage item: rows [r0, r0+16) x column tiles [jt, jt+NB) of the
-// stacked unit M ((ra+rb) x c, column-major).  Vector pointers are absolute.
+// Transfer-stage item: rows [r0, r0+16) x column tiles [jt, jt+NB) of one
+// child of a unit: z_out = X z_in with X = [I, T] Pi^T, T (r x (c - r),
+// column-major) and the child's column order idx (c entries: skeleton
+// columns, then the others).  Vector pointers are absolute.
 struct MWItem {
-  const void *M;
+  const void *T;
+  const uint16_t *idx;
   const void *zin;     // c x Np
-  void *za, *zb;       // ra x Np, rb x Np
-  int32_t ra, rb, c, r0, jt, Np;
+  void *zout;          // r x Np
+  int32_t r, c, r0, jt, Np, pad;
 };
 
 // V^0 item: rows [r0, r0+16) of V (r x sz) times the leaf's inputs.

@@ -46,12 +46,14 @@ template <> struct Mfma<double> {
 // for column tiles [jt0, jt0 + NB) of 16 columns each.  Four k-steps (16
 // columns of M) are loaded before their MFMAs are issued, so each wave keeps
 // 4 (1 + NB) loads in flight.
+// With `zrow` non-null, row kk of Z is zrow[kk] (a gather of the inputs).
 template <typename R, int NB>
 __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int ldm, int r0,
                                           int rows, int k, const cplx_t<R> *__restrict__ Z,
                                           int Np, int jt0, int lane,
                                           typename Mfma<R>::acc (&ar)[NB],
-                                          typename Mfma<R>::acc (&ai)[NB]) {
+                                          typename Mfma<R>::acc (&ai)[NB],
+                                          const uint16_t *zrow = nullptr) {
   using C = cplx_t<R>;
   constexpr int KU = 4;
   const int li = lane & 15, lk = lane >> 4;
@@ -68,9 +70,10 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
       const int kk = k0 + 4 * u + lk;
       const bool kok = kk < k;
       a[u] = (rok && kok) ? Mp[(int64_t)kk * ldm] : C{0, 0};
+      const int64_t zr = kok ? (zrow ? (int64_t)zrow[kk] : (int64_t)kk) : 0;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
-        b[u][nb] = (kok && nb < nbv) ? Zp[(int64_t)kk * Np + nb * 16] : C{0, 0};
+        b[u][nb] = (kok && nb < nbv) ? Zp[zr * Np + nb * 16] : C{0, 0};
     }
 #pragma unroll
     for (int u = 0; u < KU; ++u) {
@@ -87,7 +90,8 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
   }
 }
 
-// Transfer stage: one wave per (unit, 16-row tile, group of NB column tiles).
+// Transfer stage: one wave per (child of a unit, 16-row tile, group of NB
+// column tiles).
 template <typename R, int NB>
 __global__ __launch_bounds__(256) void k_wstage_mr(const MWItem *items, int64_t nitems) {
   using C = cplx_t<R>;
@@ -100,19 +104,26 @@ __global__ __launch_bounds__(256) void k_wstage_mr(const MWItem *items, int64_t 
   A ar[NB], ai[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) { ar[nb] = Mfma<R>::zero(); ai[nb] = Mfma<R>::zero(); }
-  const int Rt = W.ra + W.rb;
   const int jt0 = W.jt;
   const int nbv = (W.Np >> 4) - jt0 < NB ? (W.Np >> 4) - jt0 : NB;
-  tile_gemm<R, NB>((const C *)W.M, Rt, W.r0, Rt, W.c, (const C *)W.zin, W.Np, jt0, lane, ar, ai);
+  const C *Z = (const C *)W.zin;
+  // T times the non-skeleton inputs (rows idx[r..c) of Z)
+  tile_gemm<R, NB>((const C *)W.T, W.r, W.r0, W.r, W.c - W.r, Z, W.Np, jt0, lane, ar, ai,
+                   W.idx + W.r);
   const int li = lane & 15, lg = lane >> 4;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int row = W.r0 + Mfma<R>::row(lg, v);
-    if (row >= Rt) continue;
-    C *dst = row < W.ra ? (C *)W.za + (int64_t)row * W.Np : (C *)W.zb + (int64_t)(row - W.ra) * W.Np;
+    if (row >= W.r) continue;
+    // plus the skeleton input of the row (the identity part of X)
+    const C *zs = Z + (int64_t)W.idx[row] * W.Np;
+    C *dst = (C *)W.zout + (int64_t)row * W.Np;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
-      if (nb < nbv) dst[(jt0 + nb) * 16 + li] = C{ar[nb][v], ai[nb][v]};
+      if (nb < nbv) {
+        const C x0 = zs[(jt0 + nb) * 16 + li];
+        dst[(jt0 + nb) * 16 + li] = C{ar[nb][v] + x0.x, ai[nb][v] + x0.y};
+      }
   }
 }
 
