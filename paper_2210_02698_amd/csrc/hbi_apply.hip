@@ -95,14 +95,6 @@ __device__ __forceinline__ void wave_gemv(const C *__restrict__ M, int Rt, int c
   }
 }
 
-// Orders the LDS writes of a wave before its later LDS reads by other lanes
-// of the same wave (no other wave reads them).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // One workgroup (4 waves) per leaf; wave w handles the HODBF levels
 // l = w, w + 4, ... of the leaf.
 template <typename R>

@@ -73,6 +73,14 @@ __device__ inline int32_t box_weights(const DevProblem &P, const double c[3], do
   return b;
 }
 
+// Orders the LDS writes of a wave before its later LDS reads by other lanes
+// of the same wave (no other wave reads them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

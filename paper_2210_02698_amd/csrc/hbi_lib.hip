@@ -1702,7 +1702,17 @@ void build_items(BatchCache &B, int nb) {
         char *zb = ws + J.z_off * esz;
         const int ngrp = (J.Np / 16 + nb - 1) / nb;
         const uint16_t *fidx = c->Fi.as<uint16_t>();
-        for (const WUnit &U : c->units_h[k])
+        for (const WUnit &U : c->units_h[k]) {
+          if (U.ra + U.rb <= 32) {
+            // a small pair: stacked tiles, entries synthesised from T
+            for (int r0 = 0; r0 < U.ra + U.rb; r0 += 16)
+              for (int gq = 0; gq < ngrp; ++gq)
+                wi.push_back({(int64_t)U.c,
+                              MWItem{F + U.foff * esz, fidx + U.ioff, zb + U.zin * J.Np * esz,
+                                     zb + U.zouta * J.Np * esz, zb + U.zoutb * J.Np * esz, U.ra,
+                                     U.rb, U.c, r0, gq * nb, J.Np}});
+            continue;
+          }
           for (int h = 0; h < 2; ++h) {
             // child a, then child b (T_b after T_a, ib after ia)
             const int32_t r = h ? U.rb : U.ra;
@@ -1712,8 +1722,9 @@ void build_items(BatchCache &B, int nb) {
             for (int r0 = 0; r0 < r; r0 += 16)
               for (int gq = 0; gq < ngrp; ++gq)
                 wi.push_back({(int64_t)U.c, MWItem{F + toff * esz, idx, zb + U.zin * J.Np * esz,
-                                                   zo, r, U.c, r0, gq * nb, J.Np, 0}});
+                                                   zo, nullptr, r, -1, U.c, r0, gq * nb, J.Np}});
           }
+        }
       }
       std::stable_sort(wi.begin(), wi.end(), [](const std::pair<int64_t, MWItem> &a,
                                                 const std::pair<int64_t, MWItem> &b) {

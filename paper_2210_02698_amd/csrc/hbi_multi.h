@@ -4,16 +4,22 @@
 
 namespace hbi {
 
-// Transfer-stage item: rows [r0, r0+16) x column tiles [jt, jt+NB) of one
-// child of a unit: z_out = X z_in with X = [I, T] Pi^T, T (r x (c - r),
-// column-major) and the child's column order idx (c entries: skeleton
-// columns, then the others).  Vector pointers are absolute.
+// Transfer-stage item, column tiles [jt, jt+NB), z_out = X z_in with
+// X = [I, T] Pi^T (T column-major, r x (c - r)).  Two forms:
+//  * one child (rb < 0): rows [r0, r0+16) of X, T of the child at T, idx its
+//    column order (c entries: skeleton columns, then the others); B rows
+//    are gathered through idx and the skeleton rows added;
+//  * a unit of at most 32 rows (rb >= 0): rows [r0, r0+16) of the stacked
+//    [X_a; X_b], its entries synthesised from T_a (at T), T_b (after it) and
+//    the inverse orders pa, pb (idx: the unit's lists ia, ib, pa, pb), so a
+//    small pair shares tiles and its B rows are read in order.
+// Vector pointers are absolute.
 struct MWItem {
   const void *T;
   const uint16_t *idx;
   const void *zin;     // c x Np
-  void *zout;          // r x Np
-  int32_t r, c, r0, jt, Np, pad;
+  void *zout, *zoutb;  // r x Np (the child, or a), rb x Np (b)
+  int32_t r, rb, c, r0, jt, Np;
 };
 
 // V^0 item: rows [r0, r0+16) of V (r x sz) times the leaf's inputs.

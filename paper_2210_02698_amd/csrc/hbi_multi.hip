@@ -14,6 +14,8 @@
 // Np = nrhs rounded up to 16.  Factor blocks keep their single-RHS
 // column-major layout, so every factor entry is loaded once per 16-row
 // tile and reused for all Np right-hand sides.
+#include <type_traits>
+
 #include "hbi_device.h"
 #include "hbi_multi.h"
 
@@ -47,15 +49,18 @@ template <> struct Mfma<double> {
 // columns of M) are loaded before their MFMAs are issued, so each wave keeps
 // 4 (1 + NB) loads in flight.
 // With `zrow` non-null, row kk of Z is zrow[kk] (a gather of the inputs).
-template <typename R, int NB>
+// The A entries come from aload(row, kk) when given, else M[row + kk ldm].
+struct NoLoad {};
+template <typename R, int NB, typename AL = NoLoad>
 __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int ldm, int r0,
                                           int rows, int k, const cplx_t<R> *__restrict__ Z,
                                           int Np, int jt0, int lane,
                                           typename Mfma<R>::acc (&ar)[NB],
                                           typename Mfma<R>::acc (&ai)[NB],
-                                          const uint16_t *zrow = nullptr) {
+                                          const uint16_t *zrow = nullptr, AL aload = AL()) {
   using C = cplx_t<R>;
   constexpr int KU = 4;
+  constexpr bool synth = !std::is_same<AL, NoLoad>::value;
   const int li = lane & 15, lk = lane >> 4;
   const int row = r0 + li;
   const bool rok = row < rows;
@@ -69,7 +74,8 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
     for (int u = 0; u < KU; ++u) {
       const int kk = k0 + 4 * u + lk;
       const bool kok = kk < k;
-      a[u] = (rok && kok) ? Mp[(int64_t)kk * ldm] : C{0, 0};
+      if constexpr (synth) a[u] = (rok && kok) ? aload(row, kk) : C{0, 0};
+      else a[u] = (rok && kok) ? Mp[(int64_t)kk * ldm] : C{0, 0};
       const int64_t zr = kok ? (zrow ? (int64_t)zrow[kk] : (int64_t)kk) : 0;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
@@ -107,10 +113,35 @@ __global__ __launch_bounds__(256) void k_wstage_mr(const MWItem *items, int64_t 
   const int jt0 = W.jt;
   const int nbv = (W.Np >> 4) - jt0 < NB ? (W.Np >> 4) - jt0 : NB;
   const C *Z = (const C *)W.zin;
+  const int li = lane & 15, lg = lane >> 4;
+  if (W.rb >= 0) {
+    // a small unit as stacked 16-row tiles over all c inputs
+    const int ra = W.r, rb = W.rb, c = W.c;
+    const C *Ta = (const C *)W.T, *Tb = Ta + (int64_t)ra * (c - ra);
+    const uint16_t *pa = W.idx + 2 * (int64_t)c, *pb = pa + c;
+    auto aload = [&](int row, int kk) -> C {
+      const bool isb = row >= ra;
+      const int i = isb ? row - ra : row, rc = isb ? rb : ra;
+      const int p = (isb ? pb : pa)[kk];
+      if (p < rc) return C{p == i ? (R)1 : (R)0, (R)0};
+      return (isb ? Tb : Ta)[i + (int64_t)(p - rc) * rc];
+    };
+    tile_gemm<R, NB>(Ta, 0, W.r0, ra + rb, c, Z, W.Np, jt0, lane, ar, ai, nullptr, aload);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = W.r0 + Mfma<R>::row(lg, v);
+      if (row >= ra + rb) continue;
+      C *dst = row < ra ? (C *)W.zout + (int64_t)row * W.Np
+                        : (C *)W.zoutb + (int64_t)(row - ra) * W.Np;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        if (nb < nbv) dst[(jt0 + nb) * 16 + li] = C{ar[nb][v], ai[nb][v]};
+    }
+    return;
+  }
   // T times the non-skeleton inputs (rows idx[r..c) of Z)
   tile_gemm<R, NB>((const C *)W.T, W.r, W.r0, W.r, W.c - W.r, Z, W.Np, jt0, lane, ar, ai,
                    W.idx + W.r);
-  const int li = lane & 15, lg = lane >> 4;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int row = W.r0 + Mfma<R>::row(lg, v);
