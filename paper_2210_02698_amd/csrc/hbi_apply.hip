@@ -96,30 +96,40 @@ __device__ __forceinline__ void wave_gemv(const C *__restrict__ M, int Rt, int c
 }
 
 // One workgroup (4 waves) per leaf; wave w handles the HODBF levels
-// l = w, w + 4, ... of the leaf.
+// l = w, w + 4, ... of the leaf.  Each block is V = [I, T] Pi^T: the leaf's
+// inputs are permuted into the block's column order in the wave's LDS slice,
+// then row k is xp[k] + sum_m T[k, m] xp[r + m].
 template <typename R>
 __global__ __launch_bounds__(256) void k_vstage(const cplx_t<R> *s,
                                                 const LeafInfo *leaves,
                                                 const int32_t *perm,
                                                 const VDesc *vd, int Lv,
+                                                const uint16_t *fidx,
                                                 const cplx_t<R> *F,
                                                 cplx_t<R> *z, R hd) {
   using C = cplx_t<R>;
   __shared__ C xs[HBI_MAX_LEAF];
+  __shared__ C xp[4][HBI_MAX_LEAF];
   const int g = blockIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const LeafInfo lf = leaves[g];
-  if (threadIdx.x < lf.size) {
+  const int sz = lf.size;
+  if (threadIdx.x < sz) {
     const C v = s[perm[lf.start + threadIdx.x]];
     xs[threadIdx.x] = C{v.x * hd, v.y * hd};
   }
   __syncthreads();
+  C *xw = xp[wave];
   for (int l = wave; l < Lv; l += 4) {
     const VDesc d = vd[(int64_t)g * Lv + l];
+    wave_lds_sync();   // the previous block's reads of xw are done
+    if (lane < sz) xw[lane] = xs[fidx[d.ioff + lane]];
+    wave_lds_sync();
     C *zo = z + d.zout;
-    wave_gemv<C>(F + d.foff, d.r, lf.size, lane, [&](int col) { return xs[col]; },
-                 [&](int row, C v) { zo[row] = v; });
+    const int r = d.r;
+    wave_gemv<C>(F + d.foff, r, sz - r, lane, [&](int col) { return xw[r + col]; },
+                 [&](int row, C v) { zo[row] = C{v.x + xw[row].x, v.y + xw[row].y}; });
   }
 }
 
@@ -368,6 +378,7 @@ __global__ __launch_bounds__(256) void k_vstage_adj(const cplx_t<R> *y,
                                                     const LeafInfo *leaves,
                                                     const int32_t *perm,
                                                     const VDesc *vd, int Lv,
+                                                    const uint16_t *fidx,
                                                     const cplx_t<R> *F,
                                                     const cplx_t<R> *z,
                                                     cplx_t<R> *u, R hd) {
@@ -390,11 +401,18 @@ __global__ __launch_bounds__(256) void k_vstage_adj(const cplx_t<R> *y,
           acc, sz, [&](int row) { return ldf(Dc + row); }, [&](int row) { return ys[row]; });
     }
     for (int l = wave; l < Lv; l += 4) {
+      // column `lane` of V: e_p when p < r, else column p - r of T
       const VDesc d = vd[(int64_t)g * Lv + l];
-      const C *V = F + d.foff + (int64_t)lane * d.r;
       const C *w = z + d.zout;
-      batched_dot<LoadBatch<C>::value, true>(
-          acc, d.r, [&](int row) { return ldf(V + row); }, [&](int row) { return w[row]; });
+      const int p = fidx[d.ioff + sz + lane];
+      if (p < d.r) {
+        acc.x += w[p].x;
+        acc.y += w[p].y;
+      } else {
+        const C *V = F + d.foff + (int64_t)(p - d.r) * d.r;
+        batched_dot<LoadBatch<C>::value, true>(
+            acc, d.r, [&](int row) { return ldf(V + row); }, [&](int row) { return w[row]; });
+      }
     }
   }
   part[wave][lane] = acc;
@@ -423,7 +441,7 @@ hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
     if (ap.Lv > 0) {
       pre("k_vstage", ap.v_elems, ap.v_idx);
       hipLaunchKernelGGL((k_vstage<R>), dim3(ap.nleaf), dim3(256), 0, st, sc, ap.leaves,
-                         ap.perm, ap.vd, ap.Lv, Fc, zc, hd);
+                         ap.perm, ap.vd, ap.Lv, ap.fidx, Fc, zc, hd);
       post();
     }
     for (int k = 1; k <= ap.Lmax; ++k) {
@@ -459,7 +477,7 @@ hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
     }
     pre("k_vstage_adj", ap.v_elems, ap.v_idx);
     hipLaunchKernelGGL((k_vstage_adj<R>), dim3(ap.nleaf), dim3(256), 0, st, sc, ap.leaves,
-                       ap.perm, ap.vd, ap.Lv, Fc, (const C *)zc, uc, hd);
+                       ap.perm, ap.vd, ap.Lv, ap.fidx, Fc, (const C *)zc, uc, hd);
     post();
   }
   return hipGetLastError();

@@ -71,7 +71,11 @@ struct IdBlock {
 };
 
 // Apply descriptors (element offsets into the factor store / z workspace).
-struct VDesc { int64_t foff; int64_t zout; int32_t r; int32_t pad; };
+// V^0 block of a leaf and HODBF level: X = [I, T] Pi^T over the leaf's
+// cells; only T (r x (|nu| - r), column-major) is stored at foff, and the
+// index store holds at ioff the column order (skeleton cells in pivot
+// order, then the others ascending) and its inverse, |nu| entries each.
+struct VDesc { int64_t foff; int64_t zout; int64_t ioff; int32_t r; int32_t pad; };
 struct KDesc { int64_t foff; int64_t zin; int32_t r; int32_t pad; };
 // A transfer unit: the interpolation matrices X_a (ra x c) and X_b (rb x c)
 // of a sibling pair over the same c candidate columns.  An interpolative

@@ -856,7 +856,7 @@ std::vector<PlaceDesc> layout_store(const std::vector<Chunk> &chunks, int Lv, in
   for (int64_t g = 0; g < nleaf; ++g)
     for (int l = 0; l < Lv; ++l) {
       VDesc &d = vd[g * Lv + l];
-      place(d.foff, (int64_t)d.r * leaves[g].size);
+      place(d.foff, (int64_t)d.r * (leaves[g].size - d.r));
     }
   for (size_t k = 1; k < units.size(); ++k) {
     std::vector<WUnit> &us = units[k];
@@ -915,44 +915,68 @@ void build_factors(hbi_ctx *c, double tol) {
   c->ztotal = 0;
   double t_host = 0, t_gpu = 0;
 
-  // Compact the X matrices of an ID batch into a new chunk.  Level 0 keeps
-  // each V_{tau,nu} (r x |nu|); higher levels keep, for the sibling pair
-  // (2t', j), (2t'+1, j), the non-skeleton columns T_a then T_b of
-  // X = [I, T] Pi^T, and append the pair's column orders and their inverses
-  // (ia, ib, pa, pb) to the index store fi_h.
+  // Compact the X matrices of an ID batch into a new chunk: only the
+  // non-skeleton columns T of X = [I, T] Pi^T are kept.  Level 0 keeps T of
+  // each V_{tau,nu} and appends its column order and inverse (ia, pa) to the
+  // index store fi_h; higher levels keep, for the sibling pair (2t', j),
+  // (2t'+1, j), T_a then T_b, and append (ia, ib, pa, pb).
   std::vector<uint16_t> fi_h;
   auto compact = [&](std::vector<BlockOut> &outs, int64_t first, int64_t cnt,
                      const std::vector<int32_t> &ncols, std::vector<int64_t> &foff_out,
                      std::vector<int64_t> &ioff_out, bool pairs) {
     int64_t tot = 0;
     for (int64_t q = 0; q < cnt; ++q)
-      tot += (int64_t)outs[first + q].rank *
-             (pairs ? ncols[first + q] - outs[first + q].rank : ncols[first + q]);
+      tot += (int64_t)outs[first + q].rank * (ncols[first + q] - outs[first + q].rank);
     Chunk ch;
     HBI_HIP(ch.buf.alloc(sizeof(double2) * std::max<int64_t>(tot, 1)));
     ch.goff = Fg;
     ch.count = tot;
     DevBuf d_d, ns_d;
     int64_t o = 0;
+    // column order of one block (skeleton columns in pivot order, then the
+    // others ascending) and its inverse
+    std::vector<uint16_t> ord, inv;
+    std::vector<uint8_t> mark;
+    auto orders = [&](const BlockOut &x, int32_t cc) {
+      mark.assign(cc, 0);
+      ord.clear();
+      for (int32_t k = 0; k < x.rank; ++k) { ord.push_back((uint16_t)x.piv[k]); mark[x.piv[k]] = 1; }
+      for (int32_t j = 0; j < cc; ++j)
+        if (!mark[j]) ord.push_back((uint16_t)j);
+      if ((int32_t)ord.size() != cc) throw Error{HBI_ERR_NUMERIC, "internal error: repeated pivot"};
+      inv.assign(cc, 0);
+      for (int32_t k = 0; k < cc; ++k) inv[ord[k]] = (uint16_t)k;
+    };
     if (!pairs) {
-      std::vector<CopyDesc> cd(cnt);
+      // V^0 blocks: T of each, lists [ia, pa]
+      std::vector<PairDesc> pd(cnt);
+      std::vector<uint16_t> ns_h;
+      std::vector<int64_t> nso(cnt);
       for (int64_t q = 0; q < cnt; ++q) {
-        const int64_t e = (int64_t)outs[first + q].rank * ncols[first + q];
-        cd[q] = CopyDesc{outs[first + q].X, ch.buf.as<double2>() + o, e};
+        const BlockOut &x = outs[first + q];
+        const int32_t cc = ncols[first + q];
+        const int64_t io = (int64_t)fi_h.size();
+        orders(x, cc);
+        fi_h.insert(fi_h.end(), ord.begin(), ord.end());
+        fi_h.insert(fi_h.end(), inv.begin(), inv.end());
+        nso[q] = (int64_t)ns_h.size();
+        ns_h.insert(ns_h.end(), ord.begin() + x.rank, ord.end());
+        pd[q] = PairDesc{x.X, nullptr, ch.buf.as<double2>() + o, nullptr, nullptr, x.rank, 0,
+                         cc, 0};
         foff_out[first + q] = Fg + o;
-        ioff_out[first + q] = -1;
-        o += e;
+        ioff_out[first + q] = io;
+        o += (int64_t)x.rank * (cc - x.rank);
       }
-      upload(d_d, cd);
-      HBI_HIP(launch_copy_blocks(d_d.as<CopyDesc>(), cnt, c->stream));
+      upload(ns_d, ns_h);
+      for (int64_t q = 0; q < cnt; ++q) pd[q].nsa = ns_d.as<uint16_t>() + nso[q];
+      upload(d_d, pd);
+      HBI_HIP(launch_pack_pairs(d_d.as<PairDesc>(), cnt, c->stream));
     } else {
       if (cnt % 2 != 0) throw Error{HBI_ERR_NUMERIC, "internal error: unpaired transfer block"};
       const int64_t np = cnt / 2;
       std::vector<PairDesc> pd(np);
       std::vector<uint16_t> ns_h;        // non-skeleton lists for the pack kernel
       std::vector<int64_t> nso(2 * np);
-      std::vector<uint16_t> ord, inv;
-      std::vector<uint8_t> mark;
       for (int64_t q = 0; q < cnt; q += 2) {
         const BlockOut &a = outs[first + q], &b = outs[first + q + 1];
         const int32_t cc = ncols[first + q];
@@ -961,16 +985,7 @@ void build_factors(hbi_ctx *c, double tol) {
         fi_h.resize(io + 4 * (int64_t)cc);
         for (int h = 0; h < 2; ++h) {
           const BlockOut &x = h ? b : a;
-          // column order: skeleton columns in pivot order, then the others
-          mark.assign(cc, 0);
-          ord.clear();
-          for (int32_t k = 0; k < x.rank; ++k) { ord.push_back((uint16_t)x.piv[k]); mark[x.piv[k]] = 1; }
-          for (int32_t j = 0; j < cc; ++j)
-            if (!mark[j]) ord.push_back((uint16_t)j);
-          if ((int32_t)ord.size() != cc)
-            throw Error{HBI_ERR_NUMERIC, "internal error: repeated pivot"};
-          inv.assign(cc, 0);
-          for (int32_t k = 0; k < cc; ++k) inv[ord[k]] = (uint16_t)k;
+          orders(x, cc);
           std::copy(ord.begin(), ord.end(), fi_h.begin() + io + (int64_t)h * cc);
           std::copy(inv.begin(), inv.end(), fi_h.begin() + io + (int64_t)(2 + h) * cc);
           nso[q + h] = (int64_t)ns_h.size();
@@ -1092,8 +1107,8 @@ void build_factors(hbi_ctx *c, double tol) {
         rank_tmp[J.c0 + q] = o.rank;
         foff_tmp[J.c0 + q] = J.foff_local[q];
         ioff_tmp[J.c0 + q] = J.ioff_local[q];
-        if (k == 0) c->nnz_v += (int64_t)o.rank * J.ncols[q];
-        else c->nnz_w += (int64_t)o.rank * (J.ncols[q] - o.rank);
+        const int64_t e = (int64_t)o.rank * (J.ncols[q] - o.rank);
+        if (k == 0) c->nnz_v += e; else c->nnz_w += e;
       }
     };
     {
@@ -1163,7 +1178,7 @@ void build_factors(hbi_ctx *c, double tol) {
       if (k == 0) {
         for (int64_t j = 0; j < ((int64_t)1 << L); ++j) {
           const int64_t g = (bf.si << L) + j;
-          vd[g * Lv + (bf.lev - 1)] = VDesc{cs.foff[j], cs.zoff[j], cs.rank[j], 0};
+          vd[g * Lv + (bf.lev - 1)] = VDesc{cs.foff[j], cs.zoff[j], cs.ioff[j], cs.rank[j], 0};
         }
       } else {
         const LevelState &ps = prev[b];
@@ -1367,9 +1382,9 @@ void build_factors(hbi_ctx *c, double tol) {
       for (int l = 0; l < Lv; ++l) {
         const VDesc &v = vd[g * Lv + l];
         const KDesc &q = kd[g * Lv + l];
-        ve += (double)v.r * sz + v.r;
+        ve += (double)v.r * (sz - v.r) + v.r;
         fe += (double)q.r * sz + q.r;
-        vi += sizeof(VDesc);
+        vi += sizeof(VDesc) + sizeof(uint16_t) * sz;   // descriptor, column order
         fi += sizeof(KDesc);
       }
     }
@@ -1668,8 +1683,8 @@ void build_items(BatchCache &B, int nb) {
           const VDesc &d = c->vd_h[g * Lv + l];
           for (int r0 = 0; r0 < d.r; r0 += 16)
             for (int gq = 0; gq < ngrp; ++gq)
-              vi.push_back(MVItem{F + d.foff * esz, x, zb + d.zout * J.Np * esz, d.r, lf.size, r0,
-                                  gq * nb, J.Np, 0});
+              vi.push_back(MVItem{F + d.foff * esz, c->Fi.as<uint16_t>() + d.ioff, x,
+                                  zb + d.zout * J.Np * esz, d.r, lf.size, r0, gq * nb, J.Np, 0});
         }
         for (int r0 = 0; r0 < lf.size; r0 += 16)
           for (int gq = 0; gq < ngrp; ++gq)

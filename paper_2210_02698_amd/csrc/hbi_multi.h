@@ -22,9 +22,12 @@ struct MWItem {
   int32_t r, rb, c, r0, jt, Np;
 };
 
-// V^0 item: rows [r0, r0+16) of V (r x sz) times the leaf's inputs.
+// V^0 item: rows [r0, r0+16) of V = [I, T] Pi^T (T r x (sz - r) at T, the
+// column order idx: skeleton cells, then the others) times the leaf's
+// inputs.
 struct MVItem {
-  const void *V;
+  const void *T;
+  const uint16_t *idx;
   const void *x;       // sz x Np (tree-ordered input rows of the leaf)
   void *z;             // r x Np
   int32_t r, sz, r0, jt, Np, pad;

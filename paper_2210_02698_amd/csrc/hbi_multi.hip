@@ -172,16 +172,24 @@ __global__ __launch_bounds__(256) void k_vstage_mr(const MVItem *items, int64_t 
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) { ar[nb] = Mfma<R>::zero(); ai[nb] = Mfma<R>::zero(); }
   const int nbv = (W.Np >> 4) - W.jt < NB ? (W.Np >> 4) - W.jt : NB;
-  tile_gemm<R, NB>((const C *)W.V, W.r, W.r0, W.r, W.sz, (const C *)W.x, W.Np, W.jt, lane, ar, ai);
+  const C *X = (const C *)W.x;
+  // T times the non-skeleton inputs (rows idx[r..sz) of x)
+  tile_gemm<R, NB>((const C *)W.T, W.r, W.r0, W.r, W.sz - W.r, X, W.Np, W.jt, lane, ar, ai,
+                   W.idx + W.r);
   const int li = lane & 15, lg = lane >> 4;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int row = W.r0 + Mfma<R>::row(lg, v);
     if (row >= W.r) continue;
+    // plus the skeleton input of the row
+    const C *xs = X + (int64_t)W.idx[row] * W.Np;
     C *dst = (C *)W.z + (int64_t)row * W.Np;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
-      if (nb < nbv) dst[(W.jt + nb) * 16 + li] = C{ar[nb][v], ai[nb][v]};
+      if (nb < nbv) {
+        const C x0 = xs[(W.jt + nb) * 16 + li];
+        dst[(W.jt + nb) * 16 + li] = C{ar[nb][v] + x0.x, ai[nb][v] + x0.y};
+      }
   }
 }
 
