@@ -242,12 +242,24 @@ __global__ __launch_bounds__(256) void k_wstage(const WItem *items, int64_t nite
     wave_lds_sync();
   }
   const C *Ta = F + U.foff;
+  // wider units whose raw inputs and both column orders still fit the slice
+  const bool mid = !lds && c * (int)(sizeof(C) + 2 * sizeof(uint16_t)) <= WX * (int)sizeof(C);
+  if (mid) {
+    uint16_t *iw = (uint16_t *)(xw + c);
+    for (int k = lane; k < c; k += 64) xw[k] = zin[k];
+    for (int k = lane; k < 2 * c; k += 64) iw[k] = ia[k];
+    wave_lds_sync();
+  }
   if (lds) {
     // 8 loads in flight (FP32) or 4 (FP64) keep the registers within 8 (6)
     // waves per SIMD
     wstage_rows<C, sizeof(R) == 4 ? 8 : 4>(U, Ta, lane, [&](int k) { return xw[k]; }, z);
+  } else if (mid) {
+    // gathers through the column orders, both in LDS
+    const uint16_t *iw = (const uint16_t *)(xw + c);
+    wstage_rows<C, 4>(U, Ta, lane, [&](int k) { return xw[iw[k]]; }, z);
   } else {
-    // wide units (c > WX / 2, rare): inputs gathered from global memory
+    // the widest units: inputs gathered from global memory
     wstage_rows<C, 4>(U, Ta, lane, [&](int k) { return zin[ia[k]]; }, z);
   }
 }
