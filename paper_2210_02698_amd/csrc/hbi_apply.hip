@@ -133,18 +133,19 @@ __global__ __launch_bounds__(256) void k_vstage(const cplx_t<R> *s,
   }
 }
 
-// Rows [off, off + 64) of a compact transfer unit (all rows when it has at
+// Rows [off, off + wr) of a compact transfer unit (all rows when it has at
 // most 32): row i of child a is X[i] + sum_m T_a[i, m] X[ra + m] with
 // X = xv + xoff the inputs in a's column order (xoff = 0), likewise for b
 // (xoff = c).  Per lane: T column stride rc, column count t, and the columns
-// grp, grp + G, ... when G > 1 lanes share a row.
+// grp, grp + G, ... when G = 64 / wr > 1 lanes share a row.
 template <typename C, int B, typename XF>
 __device__ __forceinline__ void wstage_rows(const WItem &U, const C *__restrict__ Ta, int lane,
                                             XF xv, C *z) {
   const int ra = U.ra, rb = U.rb, c = U.c, Rt = ra + rb;
-  const int G = Rt <= 32 ? 64 / Rt : 1;
-  const int row = Rt <= 32 ? lane % Rt : U.off + lane;
-  const int grp = Rt <= 32 ? lane / Rt : 0;
+  const int wr = Rt <= 32 ? Rt : U.wr;   // rows of the window
+  const int G = 64 / wr;
+  const int row = (Rt <= 32 ? 0 : U.off) + lane % wr;
+  const int grp = lane / wr;
   const bool isb = row >= ra;
   const int i = isb ? row - ra : row;
   const int rc = isb ? rb : ra;
@@ -174,7 +175,7 @@ __device__ __forceinline__ void wstage_rows(const WItem &U, const C *__restrict_
     // combine the G partial sums of each row (lanes row, row+Rt, ...)
     C tot = acc;
     for (int g = 1; g < G; ++g) {
-      const int src = lane + g * Rt;
+      const int src = lane + g * wr;
       const auto re = __shfl(acc.x, src < 64 ? src : lane, 64);
       const auto im = __shfl(acc.y, src < 64 ? src : lane, 64);
       if (src < 64) { tot.x += re; tot.y += im; }

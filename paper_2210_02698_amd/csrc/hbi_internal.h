@@ -93,10 +93,13 @@ struct WUnit {
   int32_t ra, rb, c, pad;
 };
 // Work item of a transfer stage: rows (forward, of the pair stacked a then
-// b) or columns (adjoint) [off, off + 64) of a unit, with the unit's fields
-// copied in so that a wave needs one descriptor load.
+// b) [off, off + wr) or columns (adjoint) [off, off + 64) of a unit, with
+// the unit's fields copied in so that a wave needs one descriptor load.
+// Forward windows of wr = 16 rows (64 / wr lanes per row) serve the widest
+// units, whose rows are long.
 struct WItem {
   int64_t foff, zin, zouta, zoutb, ioff;
-  int32_t ra, rb, c, off;
+  int32_t ra, rb, c;
+  int16_t off, wr;
 };
 struct LeafInfo { int32_t start, size; int64_t dense_off; };

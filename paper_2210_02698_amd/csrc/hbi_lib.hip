@@ -863,8 +863,11 @@ std::vector<PlaceDesc> layout_store(const std::vector<Chunk> &chunks, int Lv, in
     // a unit's first forward item is its heaviest (64-row windows); items
     // of equal weight keep the unit order
     std::vector<std::pair<int64_t, int32_t>> ord(us.size());
-    for (size_t u = 0; u < us.size(); ++u)
-      ord[u] = {(int64_t)std::min(us[u].ra + us[u].rb, 64) * us[u].c, (int32_t)u};
+    for (size_t u = 0; u < us.size(); ++u) {
+      const int Rt = us[u].ra + us[u].rb;
+      const int wr = us[u].c > 256 && Rt > 32 ? 16 : 64;   // as the work items
+      ord[u] = {(int64_t)std::min(Rt, wr) * us[u].c, (int32_t)u};
+    }
     std::stable_sort(ord.begin(), ord.end(), [](const std::pair<int64_t, int32_t> &a,
                                                 const std::pair<int64_t, int32_t> &b) {
       return a.first > b.first;
@@ -1339,17 +1342,20 @@ void build_factors(hbi_ctx *c, double tol) {
     for (int32_t u = 0; u < (int32_t)units[k].size(); ++u) {
       const WUnit &U = units[k][u];
       const int Rt = U.ra + U.rb;
-      auto item = [&U](int32_t off) {
-        return WItem{U.foff, U.zin, U.zouta, U.zoutb, U.ioff, U.ra, U.rb, U.c, off};
+      auto item = [&U](int32_t off, int32_t wr) {
+        return WItem{U.foff, U.zin, U.zouta, U.zoutb, U.ioff, U.ra, U.rb, U.c, (int16_t)off,
+                     (int16_t)wr};
       };
-      if (Rt <= 64) {
-        fw.push_back({(int64_t)Rt * U.c, item(0)});
+      // units with long rows (c > 256) get 16-row windows, four lanes a row
+      const int wr = U.c > 256 && Rt > 32 ? 16 : 64;
+      if (Rt <= wr) {
+        fw.push_back({(int64_t)Rt * U.c, item(0, wr)});
       } else {
-        for (int r0 = 0; r0 < Rt; r0 += 64)
-          fw.push_back({(int64_t)std::min(64, Rt - r0) * U.c, item(r0)});
+        for (int r0 = 0; r0 < Rt; r0 += wr)
+          fw.push_back({(int64_t)std::min(wr, Rt - r0) * U.c, item(r0, wr)});
       }
       for (int c0 = 0; c0 < U.c; c0 += 64)
-        bw.push_back({(int64_t)std::min(64, U.c - c0) * Rt, item(c0)});
+        bw.push_back({(int64_t)std::min(64, U.c - c0) * Rt, item(c0, 64)});
     }
     auto order = [](std::vector<std::pair<int64_t, WItem>> &v) {
       std::stable_sort(v.begin(), v.end(), [](const std::pair<int64_t, WItem> &a,
