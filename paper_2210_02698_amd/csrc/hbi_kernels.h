@@ -6,7 +6,6 @@
 
 namespace hbi {
 
-struct CopyDesc { const double2 *src; double2 *dst; int64_t count; };
 // Compaction of a sibling pair's interpolation matrices: T_a = X_a[:, nsa]
 // (ra x (c - ra)) then T_b = X_b[:, nsb] at dst, column-major; nsa and nsb
 // list the non-skeleton columns (device, c - ra and c - rb entries).
@@ -75,7 +74,6 @@ hipError_t launch_id_onchip(const IdBlock *blks, const int32_t *sel, int64_t nb,
 // (falls back to launch_cpqr otherwise).
 hipError_t launch_cpqr_blocked(const IdBlock *blks, const int32_t *sel, int64_t nb, int nmax,
                                int mmax, double tol, int32_t *rank, hipStream_t st);
-hipError_t launch_copy_blocks(const CopyDesc *d, int64_t nb, hipStream_t st);
 hipError_t launch_pack_pairs(const PairDesc *d, int64_t np, hipStream_t st);
 hipError_t launch_place_blocks(const PlaceDesc *d, int64_t nb, void *F, bool f32,
                                hipStream_t st);

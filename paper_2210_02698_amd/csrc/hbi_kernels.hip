@@ -3,7 +3,7 @@
 //   hb_entry  k_cell_setup, k_self_terms, k_colside, k_colside_cells,
 //             k_entries
 //   bf_build  k_id_onchip, k_cpqr, k_cpqr_blocked (column-pivoted Householder
-//             QR + interpolation matrix), k_copy_blocks, k_pack_pairs,
+//             QR + interpolation matrix), k_pack_pairs,
 //             k_place_blocks
 // The apply kernels are in hbi_apply.hip, the multi-RHS ones in hbi_multi.hip.
 #include "hbi_kernels.h"
@@ -1356,19 +1356,9 @@ __global__ __launch_bounds__(HBI_ID_THREADS) void k_cpqr_blocked(const IdBlock *
   if (tid == 0) rank_out[blk] = r;
 }
 
-// Contiguous copies src[b] -> dst[b] of cnt[b] complex values.
-__global__ void k_copy_blocks(const CopyDesc *d, int64_t nb) {
-  const int64_t b = blockIdx.x;
-  if (b >= nb) return;
-  const CopyDesc c = d[b];
-  for (int64_t i = threadIdx.x; i < c.count; i += blockDim.x) c.dst[i] = c.src[i];
-}
-
-// Stack the interpolation matrices of a sibling pair, X_a (ra x c) and X_b
-// (rb x c), into one column-major (ra + rb) x c transfer block.
-// The non-skeleton columns of a sibling pair's interpolation matrices
-// X = [I, T] Pi^T (the skeleton columns are unit vectors and are not
-// stored): T_a = X_a[:, nsa], then T_b = X_b[:, nsb].
+// The non-skeleton columns of interpolation matrices X = [I, T] Pi^T (the
+// skeleton columns are unit vectors and are not stored): T_a = X_a[:, nsa],
+// then, for a sibling pair (rb > 0), T_b = X_b[:, nsb].
 __global__ void k_pack_pairs(const PairDesc *d, int64_t np) {
   const int64_t b = blockIdx.x;
   if (b >= np) return;
@@ -1560,12 +1550,6 @@ hipError_t launch_id_onchip(const IdBlock *blks, const int32_t *sel, int64_t nb,
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_id_onchip<8, 8, 2, 4>), dim3(nb), dim3(512), lds, st, blks, sel, tol, rank,
                      cap);
-  return hipGetLastError();
-}
-
-hipError_t launch_copy_blocks(const CopyDesc *d, int64_t nb, hipStream_t st) {
-  if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy_blocks, dim3(nb), dim3(256), 0, st, d, nb);
   return hipGetLastError();
 }
 
