@@ -138,30 +138,42 @@ __global__ __launch_bounds__(256) void k_vstage(const cplx_t<R> *s,
 // X = xv + xoff the inputs in a's column order (xoff = 0), likewise for b
 // (xoff = c).  Per lane: T column stride rc, column count t, and the columns
 // grp, grp + G, ... when G = 64 / wr > 1 lanes share a row.
-template <typename C, int B, typename XF>
-__device__ __forceinline__ void wstage_rows(const WItem &U, const C *__restrict__ Ta, int lane,
-                                            XF xv, C *z) {
+template <typename C> struct RowLane {
+  const C *T;        // the lane's first factor entry
+  int64_t tstep;     // between its successive entries
+  int nt, grp, G, wr, i, xo;
+  bool act, isb;
+};
+template <typename C>
+__device__ __forceinline__ RowLane<C> row_lane(const WItem &U, const C *__restrict__ Ta, int lane) {
+  RowLane<C> L;
   const int ra = U.ra, rb = U.rb, c = U.c, Rt = ra + rb;
-  const int wr = Rt <= 32 ? Rt : U.wr;   // rows of the window
-  const int G = 64 / wr;
-  const int row = (Rt <= 32 ? 0 : U.off) + lane % wr;
-  const int grp = lane / wr;
-  const bool isb = row >= ra;
-  const int i = isb ? row - ra : row;
-  const int rc = isb ? rb : ra;
-  const int xo = (isb ? c : 0) + rc;
-  const C *T = (isb ? Ta + (int64_t)ra * (c - ra) : Ta) + i + (int64_t)grp * rc;
-  const int64_t tstep = (int64_t)G * rc;
-  const bool act = row < Rt && grp < G;
+  L.wr = Rt <= 32 ? Rt : U.wr;   // rows of the window
+  L.G = 64 / L.wr;
+  const int row = (Rt <= 32 ? 0 : U.off) + lane % L.wr;
+  L.grp = lane / L.wr;
+  L.isb = row >= ra;
+  L.i = L.isb ? row - ra : row;
+  const int rc = L.isb ? rb : ra;
+  L.xo = (L.isb ? c : 0) + rc;
+  L.T = (L.isb ? Ta + (int64_t)ra * (c - ra) : Ta) + L.i + (int64_t)L.grp * rc;
+  L.tstep = (int64_t)L.G * rc;
+  L.act = row < Rt && L.grp < L.G;
   const int t = c - rc;
-  const int nt = act && t > grp ? (t - grp + G - 1) / G : 0;
+  L.nt = L.act && t > L.grp ? (t - L.grp + L.G - 1) / L.G : 0;
+  return L;
+}
+template <typename C, int B, typename XF>
+__device__ __forceinline__ void wstage_rows(const WItem &U, const RowLane<C> &L, int lane, XF xv,
+                                            C *z) {
+  const int nt = L.nt, G = L.G, grp = L.grp, xo = L.xo;
   C acc{0, 0};
   for (int q0 = 0; q0 < nt; q0 += B) {
     C mv[B], xq[B];
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       if (q0 + u < nt) {
-        mv[u] = ldf(T + (q0 + u) * tstep);
+        mv[u] = ldf(L.T + (q0 + u) * L.tstep);
         xq[u] = xv(xo + grp + (q0 + u) * G);
       } else {
         mv[u] = C{0, 0};
@@ -175,17 +187,43 @@ __device__ __forceinline__ void wstage_rows(const WItem &U, const C *__restrict_
     // combine the G partial sums of each row (lanes row, row+Rt, ...)
     C tot = acc;
     for (int g = 1; g < G; ++g) {
-      const int src = lane + g * wr;
+      const int src = lane + g * L.wr;
       const auto re = __shfl(acc.x, src < 64 ? src : lane, 64);
       const auto im = __shfl(acc.y, src < 64 ? src : lane, 64);
       if (src < 64) { tot.x += re; tot.y += im; }
     }
     acc = tot;
   }
-  if (act && grp == 0) {
-    const C x0 = xv((isb ? c : 0) + i);
-    (isb ? z + U.zoutb : z + U.zouta)[i] = C{acc.x + x0.x, acc.y + x0.y};
+  if (L.act && grp == 0) {
+    const C x0 = xv((L.isb ? U.c : 0) + L.i);
+    (L.isb ? z + U.zoutb : z + U.zouta)[L.i] = C{acc.x + x0.x, acc.y + x0.y};
   }
+}
+
+// xw[0, c) = zin[0, c) and iw[0, 2c) = io[0, 2c) for c <= 64 NX and
+// 2c <= 64 NI: every load is issued before the first LDS store, so the
+// wave waits on one round trip (a plain strided copy loop waits on each).
+template <int NX, int NI, typename C>
+__device__ __forceinline__ void stage_raw(C *xw, uint16_t *iw, const C *zin, const uint16_t *io,
+                                          int c, int lane) {
+  C xr[NX];
+  uint16_t ir[NI];
+#pragma unroll
+  for (int u = 0; u < NX; ++u) {
+    const int k = lane + 64 * u;
+    xr[u] = k < c ? zin[k] : C{0, 0};
+  }
+#pragma unroll
+  for (int u = 0; u < NI; ++u) {
+    const int k = lane + 64 * u;
+    ir[u] = k < 2 * c ? io[k] : uint16_t(0);
+  }
+#pragma unroll
+  for (int u = 0; u < NX; ++u)
+    if (lane + 64 * u < c) xw[lane + 64 * u] = xr[u];
+#pragma unroll
+  for (int u = 0; u < NI; ++u)
+    if (lane + 64 * u < 2 * c) iw[lane + 64 * u] = ir[u];
 }
 
 // One wave per work item: rows [r0, r0 + 64) of a transfer unit, the pair
@@ -215,13 +253,13 @@ __global__ __launch_bounds__(256) void k_wstage(const WItem *items, int64_t nite
   const C *zin = z + U.zin;
   const bool lds = 2 * c <= WX;
   C *xw = xs[wave];
+  const RowLane<C> L = row_lane(U, F + U.foff, lane);
   if (lds) {
     // the inputs in their own order and both column orders (three
     // independent contiguous loads), then the two gathers within LDS:
     // xw[0, c) = x[ia], xw[c, 2c) = x[ib]
     uint16_t *iw = (uint16_t *)(xw + c);
-    for (int k = lane; k < c; k += 64) xw[k] = zin[k];
-    for (int k = lane; k < 2 * c; k += 64) iw[k] = ia[k];
+    stage_raw<WX / 128, WX / 64>(xw, iw, zin, ia, c, lane);
     wave_lds_sync();
     R ar[WX / 128], ai[WX / 128], br[WX / 128], bi[WX / 128];
 #pragma unroll
@@ -241,27 +279,22 @@ __global__ __launch_bounds__(256) void k_wstage(const WItem *items, int64_t nite
       }
     }
     wave_lds_sync();
-  }
-  const C *Ta = F + U.foff;
-  // wider units whose raw inputs and both column orders still fit the slice
-  const bool mid = !lds && c * (int)(sizeof(C) + 2 * sizeof(uint16_t)) <= WX * (int)sizeof(C);
-  if (mid) {
-    uint16_t *iw = (uint16_t *)(xw + c);
-    for (int k = lane; k < c; k += 64) xw[k] = zin[k];
-    for (int k = lane; k < 2 * c; k += 64) iw[k] = ia[k];
-    wave_lds_sync();
-  }
-  if (lds) {
     // 8 loads in flight (FP32) or 4 (FP64) keep the registers within 8 (6)
     // waves per SIMD
-    wstage_rows<C, sizeof(R) == 4 ? 8 : 4>(U, Ta, lane, [&](int k) { return xw[k]; }, z);
-  } else if (mid) {
+    wstage_rows<C, sizeof(R) == 4 ? 8 : 4>(U, L, lane, [&](int k) { return xw[k]; }, z);
+    return;
+  }
+  // wider units whose raw inputs and both column orders still fit the slice
+  constexpr int CM = WX * (int)sizeof(C) / (int)(sizeof(C) + 2 * sizeof(uint16_t));
+  if (c <= CM) {
     // gathers through the column orders, both in LDS
-    const uint16_t *iw = (const uint16_t *)(xw + c);
-    wstage_rows<C, 4>(U, Ta, lane, [&](int k) { return xw[iw[k]]; }, z);
+    uint16_t *iw = (uint16_t *)(xw + c);
+    stage_raw<(CM + 63) / 64, (2 * CM + 63) / 64>(xw, iw, zin, ia, c, lane);
+    wave_lds_sync();
+    wstage_rows<C, 4>(U, L, lane, [&](int k) { return xw[iw[k]]; }, z);
   } else {
     // the widest units: inputs gathered from global memory
-    wstage_rows<C, 4>(U, Ta, lane, [&](int k) { return zin[ia[k]]; }, z);
+    wstage_rows<C, 4>(U, L, lane, [&](int k) { return zin[ia[k]]; }, z);
   }
 }
 
