@@ -43,13 +43,34 @@ template <> struct Mfma<double> {
   static __device__ __forceinline__ int row(int g, int v) { return g + 4 * v; }
 };
 
+// The descriptors carry generic pointers; loads and stores through these
+// helpers use global-memory instructions (flat ones would also wait on LDS
+// traffic and need a full address per lane).
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+template <typename C> __device__ __forceinline__ C ldg(const C *p, int64_t i) {
+  using E = decltype(C{}.x);
+  typedef E V __attribute__((ext_vector_type(2)));
+  const V v = ((gptr<const V>)p)[i];
+  return C{v[0], v[1]};
+}
+__device__ __forceinline__ int ldg16(const uint16_t *p, int64_t i) {
+  return ((gptr<const uint16_t>)p)[i];
+}
+template <typename C> __device__ __forceinline__ void stg(C *p, int64_t i, C v) {
+  using E = decltype(C{}.x);
+  typedef E V __attribute__((ext_vector_type(2)));
+  ((gptr<V>)p)[i] = V{v.x, v.y};
+}
+
 // Accumulate a 16-row tile of M (rows r0.., column-major, leading dimension
 // ldm, `rows` valid rows, `k` columns) times Z (k x Np, row stride Np),
 // for column tiles [jt0, jt0 + NB) of 16 columns each.  Four k-steps (16
 // columns of M) are loaded before their MFMAs are issued, so each wave keeps
-// 4 (1 + NB) loads in flight.
+// 4 (1 + NB) loads in flight; the index loads of the four steps (zrow, or
+// the A loader's) are issued first, so the gathers wait on one round trip.
 // With `zrow` non-null, row kk of Z is zrow[kk] (a gather of the inputs).
-// The A entries come from aload(row, kk) when given, else M[row + kk ldm].
+// The A entries come from aload.value(row, aload.index(row, kk)) when an
+// A loader is given, else M[row + kk ldm].
 struct NoLoad {};
 template <typename R, int NB, typename AL = NoLoad>
 __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int ldm, int r0,
@@ -64,22 +85,54 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
   const int li = lane & 15, lk = lane >> 4;
   const int row = r0 + li;
   const bool rok = row < rows;
-  const C *Mp = M + row;
-  const C *Zp = Z + jt0 * 16 + li;
+  const int zc = jt0 * 16 + li;
   // column tiles past Np (last group of a row) are never read
   const int nbv = (Np >> 4) - jt0 < NB ? (Np >> 4) - jt0 : NB;
   for (int k0 = 0; k0 < k; k0 += 4 * KU) {
     C a[KU], b[KU][NB];
+    int zr[KU], pa[KU];
+    // Out-of-range entries (rows, columns or column tiles) read entry 0
+    // (valid: rows, k >= 1) and are then replaced by zero, so that the
+    // loads need no branches.
 #pragma unroll
     for (int u = 0; u < KU; ++u) {
       const int kk = k0 + 4 * u + lk;
       const bool kok = kk < k;
-      if constexpr (synth) a[u] = (rok && kok) ? aload(row, kk) : C{0, 0};
-      else a[u] = (rok && kok) ? Mp[(int64_t)kk * ldm] : C{0, 0};
-      const int64_t zr = kok ? (zrow ? (int64_t)zrow[kk] : (int64_t)kk) : 0;
+      zr[u] = zrow ? ldg16(zrow, kok ? kk : 0) : kk;
+      if constexpr (synth) pa[u] = (rok && kok) ? aload.index(row, kk) : 0;
+    }
+    // then the loads that need no index (A, or B of a stacked tile), then
+    // the ones that do
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        b[u][nb] = (kok && nb < nbv) ? Zp[zr * Np + nb * 16] : C{0, 0};
+    for (int u = 0; u < KU; ++u) {
+      const int kk = k0 + 4 * u + lk;
+      const bool kok = kk < k;
+      if constexpr (synth) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const bool ok = kok && nb < nbv;
+          const C v = ldg(Z, (int64_t)(ok ? zr[u] : 0) * Np + zc + (ok ? nb * 16 : 0));
+          b[u][nb] = ok ? v : C{0, 0};
+        }
+      } else {
+        const C v = ldg(M, (rok && kok) ? row + (int64_t)kk * ldm : 0);
+        a[u] = (rok && kok) ? v : C{0, 0};
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const int kk = k0 + 4 * u + lk;
+      const bool kok = kk < k;
+      if constexpr (synth) {
+        a[u] = (rok && kok) ? aload.value(row, pa[u]) : C{0, 0};
+      } else {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const bool ok = kok && nb < nbv;
+          const C v = ldg(Z, (int64_t)(ok ? zr[u] : 0) * Np + zc + (ok ? nb * 16 : 0));
+          b[u][nb] = ok ? v : C{0, 0};
+        }
+      }
     }
 #pragma unroll
     for (int u = 0; u < KU; ++u) {
@@ -93,6 +146,59 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
         ai[nb] = Mfma<R>::op(a[u].y, b[u][nb].x, ai[nb]);
       }
     }
+  }
+}
+
+// A entries of a stacked compact unit (rows of child a, then of b, over
+// all c inputs): entry (row, kk) of X = [I, T] Pi^T is 1 or 0 when the
+// column's position p = pa[kk] (pb) is a skeleton, else T[i, p - r].
+template <typename R> struct StackedA {
+  const cplx_t<R> *Ta, *Tb;
+  const uint16_t *pa, *pb;
+  int ra, rb;
+  __device__ __forceinline__ int index(int row, int kk) const {
+    return row >= ra ? ldg16(pb, kk) : ldg16(pa, kk);
+  }
+  __device__ __forceinline__ cplx_t<R> value(int row, int p) const {
+    const bool isb = row >= ra;
+    const int i = isb ? row - ra : row, rc = isb ? rb : ra;
+    if (p < rc) return cplx_t<R>{p == i ? (R)1 : (R)0, (R)0};
+    return ldg(isb ? Tb : Ta, i + (int64_t)(p - rc) * rc);
+  }
+};
+
+// Rows [r0, r0 + 16) of Y = X Z for X = [I, T] Pi^T with T Z_rest already
+// in the accumulators: dst[row] = acc[row] + Z[idx[row]] for row < r.  The
+// four row indices are loaded first, then the inputs, then the stores.
+template <typename R, int NB>
+__device__ __forceinline__ void add_skeleton_rows(const uint16_t *idx, int r, int r0,
+                                                  const cplx_t<R> *Z, cplx_t<R> *dst, int Np,
+                                                  int jt0, int nbv, int lane,
+                                                  const typename Mfma<R>::acc (&ar)[NB],
+                                                  const typename Mfma<R>::acc (&ai)[NB]) {
+  using C = cplx_t<R>;
+  const int li = lane & 15, lg = lane >> 4;
+  int sr[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = r0 + Mfma<R>::row(lg, v);
+    sr[v] = ldg16(idx, row < r ? row : 0);   // idx[0] exists: r >= 1
+  }
+  C x0[4][NB];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      x0[v][nb] = nb < nbv ? ldg(Z, (int64_t)sr[v] * Np + (jt0 + nb) * 16 + li) : C{0, 0};
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = r0 + Mfma<R>::row(lg, v);
+    if (row >= r) continue;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      if (nb < nbv)
+        stg(dst, (int64_t)row * Np + (jt0 + nb) * 16 + li,
+            C{ar[nb][v] + x0[v][nb].x, ai[nb][v] + x0[v][nb].y});
   }
 }
 
@@ -117,16 +223,14 @@ __global__ __launch_bounds__(256) void k_wstage_mr(const MWItem *items, int64_t 
   if (W.rb >= 0) {
     // a small unit as stacked 16-row tiles over all c inputs
     const int ra = W.r, rb = W.rb, c = W.c;
-    const C *Ta = (const C *)W.T, *Tb = Ta + (int64_t)ra * (c - ra);
-    const uint16_t *pa = W.idx + 2 * (int64_t)c, *pb = pa + c;
-    auto aload = [&](int row, int kk) -> C {
-      const bool isb = row >= ra;
-      const int i = isb ? row - ra : row, rc = isb ? rb : ra;
-      const int p = (isb ? pb : pa)[kk];
-      if (p < rc) return C{p == i ? (R)1 : (R)0, (R)0};
-      return (isb ? Tb : Ta)[i + (int64_t)(p - rc) * rc];
-    };
-    tile_gemm<R, NB>(Ta, 0, W.r0, ra + rb, c, Z, W.Np, jt0, lane, ar, ai, nullptr, aload);
+    StackedA<R> aload;
+    aload.Ta = (const C *)W.T;
+    aload.Tb = aload.Ta + (int64_t)ra * (c - ra);
+    aload.pa = W.idx + 2 * (int64_t)c;
+    aload.pb = aload.pa + c;
+    aload.ra = ra;
+    aload.rb = rb;
+    tile_gemm<R, NB>(aload.Ta, 0, W.r0, ra + rb, c, Z, W.Np, jt0, lane, ar, ai, nullptr, aload);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = W.r0 + Mfma<R>::row(lg, v);
@@ -135,27 +239,15 @@ __global__ __launch_bounds__(256) void k_wstage_mr(const MWItem *items, int64_t 
                         : (C *)W.zoutb + (int64_t)(row - ra) * W.Np;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
-        if (nb < nbv) dst[(jt0 + nb) * 16 + li] = C{ar[nb][v], ai[nb][v]};
+        if (nb < nbv) stg(dst, (jt0 + nb) * 16 + li, C{ar[nb][v], ai[nb][v]});
     }
     return;
   }
   // T times the non-skeleton inputs (rows idx[r..c) of Z)
   tile_gemm<R, NB>((const C *)W.T, W.r, W.r0, W.r, W.c - W.r, Z, W.Np, jt0, lane, ar, ai,
                    W.idx + W.r);
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int row = W.r0 + Mfma<R>::row(lg, v);
-    if (row >= W.r) continue;
-    // plus the skeleton input of the row (the identity part of X)
-    const C *zs = Z + (int64_t)W.idx[row] * W.Np;
-    C *dst = (C *)W.zout + (int64_t)row * W.Np;
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-      if (nb < nbv) {
-        const C x0 = zs[(jt0 + nb) * 16 + li];
-        dst[(jt0 + nb) * 16 + li] = C{ar[nb][v] + x0.x, ai[nb][v] + x0.y};
-      }
-  }
+  // plus the skeleton input of each row (the identity part of X)
+  add_skeleton_rows<R, NB>(W.idx, W.r, W.r0, Z, (C *)W.zout, W.Np, jt0, nbv, lane, ar, ai);
 }
 
 // V^0 stage: one wave per (leaf, level, 16-row tile, column-tile group).
@@ -177,20 +269,8 @@ __global__ __launch_bounds__(256) void k_vstage_mr(const MVItem *items, int64_t 
   tile_gemm<R, NB>((const C *)W.T, W.r, W.r0, W.r, W.sz - W.r, X, W.Np, W.jt, lane, ar, ai,
                    W.idx + W.r);
   const int li = lane & 15, lg = lane >> 4;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int row = W.r0 + Mfma<R>::row(lg, v);
-    if (row >= W.r) continue;
-    // plus the skeleton input of the row
-    const C *xs = X + (int64_t)W.idx[row] * W.Np;
-    C *dst = (C *)W.z + (int64_t)row * W.Np;
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-      if (nb < nbv) {
-        const C x0 = xs[(W.jt + nb) * 16 + li];
-        dst[(W.jt + nb) * 16 + li] = C{ar[nb][v] + x0.x, ai[nb][v] + x0.y};
-      }
-  }
+  // plus the skeleton input of each row
+  add_skeleton_rows<R, NB>(W.idx, W.r, W.r0, X, (C *)W.z, W.Np, W.jt, nbv, lane, ar, ai);
 }
 
 // Final stage: one wave per (leaf, 16-row tile, column-tile group); the
@@ -225,7 +305,7 @@ __global__ __launch_bounds__(256) void k_final_mr(const MFItem *items, int64_t n
     C *dst = (C *)W.y + (int64_t)row * W.Np;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
-      if (nb < nbv) dst[(W.jt + nb) * 16 + li] = C{ar[nb][v], ai[nb][v]};
+      if (nb < nbv) stg(dst, (W.jt + nb) * 16 + li, C{ar[nb][v], ai[nb][v]});
   }
 }
 
