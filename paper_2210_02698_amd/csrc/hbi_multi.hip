@@ -69,8 +69,8 @@ template <typename C> __device__ __forceinline__ void stg(C *p, int64_t i, C v) 
 // 4 (1 + NB) loads in flight; the index loads of the four steps (zrow, or
 // the A loader's) are issued first, so the gathers wait on one round trip.
 // With `zrow` non-null, row kk of Z is zrow[kk] (a gather of the inputs).
-// The A entries come from aload.value(row, aload.index(row, kk)) when an
-// A loader is given, else M[row + kk ldm].
+// The A entries come from aload.value(row, aload.index(row, kk), valid)
+// when an A loader is given, else M[row + kk ldm].
 struct NoLoad {};
 template <typename R, int NB, typename AL = NoLoad>
 __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int ldm, int r0,
@@ -99,7 +99,7 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
       const int kk = k0 + 4 * u + lk;
       const bool kok = kk < k;
       zr[u] = zrow ? ldg16(zrow, kok ? kk : 0) : kk;
-      if constexpr (synth) pa[u] = (rok && kok) ? aload.index(row, kk) : 0;
+      if constexpr (synth) pa[u] = aload.index(row, (rok && kok) ? kk : 0);
     }
     // then the loads that need no index (A, or B of a stacked tile), then
     // the ones that do
@@ -124,7 +124,7 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
       const int kk = k0 + 4 * u + lk;
       const bool kok = kk < k;
       if constexpr (synth) {
-        a[u] = (rok && kok) ? aload.value(row, pa[u]) : C{0, 0};
+        a[u] = aload.value(row, pa[u], rok && kok);
       } else {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
@@ -151,19 +151,23 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
 
 // A entries of a stacked compact unit (rows of child a, then of b, over
 // all c inputs): entry (row, kk) of X = [I, T] Pi^T is 1 or 0 when the
-// column's position p = pa[kk] (pb) is a skeleton, else T[i, p - r].
+// column's position p = pa[kk] (pb) is a skeleton, else T[i, p - r].  The
+// load is issued either way, from `safe` (any valid entry) when no T entry
+// is wanted, and the value selected after it, so that it needs no branch.
 template <typename R> struct StackedA {
-  const cplx_t<R> *Ta, *Tb;
+  const cplx_t<R> *Ta, *Tb, *safe;
   const uint16_t *pa, *pb;
   int ra, rb;
   __device__ __forceinline__ int index(int row, int kk) const {
     return row >= ra ? ldg16(pb, kk) : ldg16(pa, kk);
   }
-  __device__ __forceinline__ cplx_t<R> value(int row, int p) const {
+  __device__ __forceinline__ cplx_t<R> value(int row, int p, bool ok) const {
     const bool isb = row >= ra;
     const int i = isb ? row - ra : row, rc = isb ? rb : ra;
-    if (p < rc) return cplx_t<R>{p == i ? (R)1 : (R)0, (R)0};
-    return ldg(isb ? Tb : Ta, i + (int64_t)(p - rc) * rc);
+    const bool t = ok && p >= rc;
+    const cplx_t<R> v = ldg(t ? (isb ? Tb : Ta) + i + (int64_t)(p - rc) * rc : safe, 0);
+    const R one = (ok && p == i) ? (R)1 : (R)0;
+    return t ? v : cplx_t<R>{one, (R)0};
   }
 };
 
@@ -226,6 +230,7 @@ __global__ __launch_bounds__(256) void k_wstage_mr(const MWItem *items, int64_t 
     StackedA<R> aload;
     aload.Ta = (const C *)W.T;
     aload.Tb = aload.Ta + (int64_t)ra * (c - ra);
+    aload.safe = Z;
     aload.pa = W.idx + 2 * (int64_t)c;
     aload.pb = aload.pa + c;
     aload.ra = ra;
