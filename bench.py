@@ -17,8 +17,10 @@ Per run:
      is the FP32 apply throughput in Gcell*RHS/s (the metric's rel. error
      bound is 1e-4); the FP64 figures are reported beside it.
   4. Roofline: per-kernel HIP-event durations recorded by the library on
-     its stream during the timed steps; algorithmic bytes from the factor
-     layout.
+     its stream over a second pass of the same number of applies, right
+     after the timed steps (which carry no per-kernel events); algorithmic
+     bytes from the factor layout; counted HBM traffic from the committed
+     counter record while the kernel source is the one it was taken with.
   5. CPU baseline: the oracle (as is) on a bounded sample of rows on the
      host, scaled to Gcell*RHS/s.
 """
@@ -75,7 +77,8 @@ def main():
                     default="bump",
                     help="bump: the headline 1024^2 single-RHS apply; batched: 64 "
                          "constant-gradient problems with 1-256 RHS each; 3d: 64^3 sinusoid "
-                         "with 32 RHS")
+                         "with 32 RHS; sweep: four frequencies from one table set, 16 RHS "
+                         "each; inclusion: 256^2 bump with an open-square curve inclusion")
     ap.add_argument("--nprob", type=int, default=64)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
