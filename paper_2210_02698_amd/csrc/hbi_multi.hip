@@ -64,10 +64,12 @@ template <typename C> __device__ __forceinline__ void stg(C *p, int64_t i, C v) 
 
 // Accumulate a 16-row tile of M (rows r0.., column-major, leading dimension
 // ldm, `rows` valid rows, `k` columns) times Z (k x Np, row stride Np),
-// for column tiles [jt0, jt0 + NB) of 16 columns each.  Four k-steps (16
-// columns of M) are loaded before their MFMAs are issued, so each wave keeps
-// 4 (1 + NB) loads in flight; the index loads of the four steps (zrow, or
-// the A loader's) are issued first, so the gathers wait on one round trip.
+// for column tiles [jt0, jt0 + NB) of 16 columns each.  KU k-steps (4 KU
+// columns of M; KU = 8 for NB = 1, else 4) are loaded before their MFMAs
+// are issued, so each wave keeps KU (1 + NB) loads in flight; the index
+// loads of those steps (zrow, or the A loader's) are issued first, so the
+// gathers wait on one round trip.  Steps past the last column issue loads
+// (clamped) but no MFMAs.
 // With `zrow` non-null, row kk of Z is zrow[kk] (a gather of the inputs).
 // The A entries come from aload.value(row, aload.index(row, kk), valid)
 // when an A loader is given, else M[row + kk ldm].
@@ -80,7 +82,7 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
                                           typename Mfma<R>::acc (&ai)[NB],
                                           const uint16_t *zrow = nullptr, AL aload = AL()) {
   using C = cplx_t<R>;
-  constexpr int KU = 4;
+  constexpr int KU = NB == 1 ? 8 : 4;   // registers allow twice the steps at NB = 1
   constexpr bool synth = !std::is_same<AL, NoLoad>::value;
   const int li = lane & 15, lk = lane >> 4;
   const int row = r0 + li;
@@ -136,6 +138,7 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
     }
 #pragma unroll
     for (int u = 0; u < KU; ++u) {
+      if (k0 + 4 * u >= k) break;   // wave-uniform: steps past the last column
       const R nai = -a[u].y;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
