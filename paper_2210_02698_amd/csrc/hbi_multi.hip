@@ -276,7 +276,6 @@ __global__ __launch_bounds__(256) void k_vstage_mr(const MVItem *items, int64_t 
   // T times the non-skeleton inputs (rows idx[r..sz) of x)
   tile_gemm<R, NB>((const C *)W.T, W.r, W.r0, W.r, W.sz - W.r, X, W.Np, W.jt, lane, ar, ai,
                    W.idx + W.r);
-  const int li = lane & 15, lg = lane >> 4;
   // plus the skeleton input of each row
   add_skeleton_rows<R, NB>(W.idx, W.r, W.r0, X, (C *)W.z, W.Np, W.jt, nbv, lane, ar, ai);
 }
