@@ -117,8 +117,9 @@ hbi_status hbi_load_tables(hbi_ctx *ctx, const hbi_tables *t);
  * self terms (App. A), which depend on omega, are evaluated again.  ctx and
  * src are two contexts on the same device, or the same context (then only
  * the frequency changes).  A curve inclusion of src (hbi_set_inclusion) is
- * copied too.  Drops the earlier factors of ctx; src keeps its own.  src must have tables (HBI_ERR_STATE otherwise); omega must be finite
- * and > 0 (HBI_ERR_ARG).  Synchronous. */
+ * copied too.  Drops the earlier factors of ctx; src keeps its own.  src
+ * must have tables (HBI_ERR_STATE otherwise); omega must be finite and > 0
+ * (HBI_ERR_ARG).  Synchronous. */
 hbi_status hbi_load_tables_from(hbi_ctx *ctx, const hbi_ctx *src, double omega);
 
 /* A curve inclusion (Sec. 3.1, domain with inclusion; 2D): ns straight
