@@ -172,8 +172,10 @@ hbi_status hbi_apply_adjoint(hbi_ctx *ctx, const void *s, void *u,
  * on ctx[0]'s stream.  The factor products of all problems become complex
  * GEMM tiles over the right-hand sides (16x16x4 MFMA), each stage of every
  * problem in one launch, and the whole call is captured once into a HIP
- * graph that later calls with the same contexts and nrhs replay (new
- * vector pointers are patched in).  On the first call the column-tile
+ * graph that later calls with the same contexts, builds and nrhs replay
+ * (new vector pointers are patched in; a context rebuilt since, or a new
+ * context at a freed one's address, makes the call capture again).  The
+ * graph is kept by ctx[0] until its next rebuild or hbi_destroy.  On the first call the column-tile
  * width is chosen by timing the candidates on the batch itself; choices are
  * kept for the process and in the JSON file named by HBI_TUNE_CACHE when
  * set.  Vector workspace is bounded by HBI_MULTI_BYTES (default 8 GiB);

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -29,6 +30,11 @@ using namespace hbi;
 namespace {
 
 thread_local std::string g_err;
+// Every successful build gets a new number: a cached batched-apply graph
+// names its contexts by address and by this number, so that it is never
+// replayed on factors that a rebuild (or a new context at the same
+// address) has replaced.
+std::atomic<uint64_t> g_build_gen{0};
 
 struct DevBuf {
   void *p = nullptr;
@@ -215,6 +221,7 @@ struct hbi_ctx {
   std::vector<KDesc> kd_h;
   std::vector<std::vector<WUnit>> units_h;
   std::shared_ptr<BatchCache> batch;
+  uint64_t build_gen = 0;   // g_build_gen of the current factors (0: none)
   // statistics
   double t_build = 0, t_geo = 0, t_host = 0, t_gpu = 0, t_final = 0;
   double t_prep = 0, t_wait = 0, t_compact = 0;   // inside t_gpu: batch host set-up, batch total, compaction
@@ -267,6 +274,7 @@ struct hbi_ctx {
     inc_part3.release();
     inc_plan = InclusionPlan(); t_inc = 0;
     leaves_h.clear(); vd_h.clear(); kd_h.clear(); units_h.clear(); batch.reset(); ztotal = 0; z_d.release();
+    build_gen = 0;
     nnz_v = nnz_w = nnz_k = nnz_d = entries_eval = nid = 0; rank_max = 0; rank_sum = 0;
     t_prep = t_wait = t_compact = 0; entry_slots = 0;
     nid_path[0] = nid_path[1] = nid_path[2] = 0;
@@ -1581,6 +1589,7 @@ struct MultiPass {
 
 struct BatchCache {
   std::vector<hbi_ctx *> ctxs;
+  std::vector<uint64_t> gens;   // build_gen of each context when captured
   std::vector<int32_t> nrhs;
   std::vector<const void *> s_ptr;
   std::vector<void *> u_ptr;
@@ -1595,6 +1604,8 @@ struct BatchCache {
   hipGraphExec_t gexec = nullptr;
   double tuned_ms = 0;
   ~BatchCache() {
+    // the graph may still run: its workspace and job tables go with it
+    if (gst) (void)hipStreamSynchronize(gst);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (e_in) (void)hipEventDestroy(e_in);
@@ -1839,11 +1850,18 @@ void multi_apply(hbi_ctx *c0, const std::vector<hbi_ctx *> &ctxs, const std::vec
     HBI_REQUIRE(ctxs[p]->device == c0->device, HBI_ERR_ARG, "batched problems on different devices");
     check_apply_args(ctxs[p], s[p], u[p], nrhs[p], ld[p]);
   }
+  std::vector<uint64_t> gens(ctxs.size());
+  for (size_t p = 0; p < ctxs.size(); ++p) gens[p] = ctxs[p]->build_gen;
   std::shared_ptr<BatchCache> B = c0->batch;
-  const bool same = B && B->ctxs == ctxs && B->nrhs == nrhs && B->prec == prec;
+  const bool same =
+      B && B->ctxs == ctxs && B->gens == gens && B->nrhs == nrhs && B->prec == prec;
   if (!same) {
+    // the previous graph, if any, finishes and frees its workspace first
+    B.reset();
+    c0->batch.reset();
     B = std::make_shared<BatchCache>();
     B->ctxs = ctxs;
+    B->gens = gens;
     B->nrhs = nrhs;
     B->prec = prec;
     B->s_ptr = s;
@@ -2148,6 +2166,7 @@ hbi_status hbi_build(hbi_ctx *ctx, double tol, hbi_prec prec) {
       build_inclusion(ctx);
       ctx->t_build += ctx->t_inc;
     }
+    ctx->build_gen = ++g_build_gen;
     ctx->state = 2;
   });
 }

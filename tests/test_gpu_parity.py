@@ -214,6 +214,32 @@ def test_apply_batched_uneven_problems(torch_mod, budget, monkeypatch):
         op.close()
 
 
+def test_apply_batched_after_a_member_is_rebuilt(torch_mod):
+    """The captured graph of a batched call is keyed on the builds of all of
+    its problems: after the second problem is rebuilt (new factor memory),
+    the same call with the same RHS counts captures again and matches
+    per-problem applies of the new factors."""
+    torch = torch_mod
+    ops, S = [], []
+    for side, g, nr in [(32, 0.3, 3), (40, 0.6, 5)]:
+        prob = hb_inputs.make_problem(ConstantGradient(1.0, (0.0, g)), 2, (side, side),
+                                      2 * math.pi * side / 8, nI=7)
+        ops.append(make_op(prob, tol=1e-6, prec="f32"))
+        S.append(to_dev(torch, hb_inputs.gaussian_sources(prob, nr, [4, side]), torch.complex64))
+    say("batched before and after rebuilding problem 1")
+    U = _batched(torch, ops, S, torch.complex64)
+    ops[1].build(tol=1e-4, prec="f32")
+    U2 = _batched(torch, ops, S, torch.complex64)
+    for p, (op, s) in enumerate(zip(ops, S)):
+        for r in range(s.shape[1]):
+            ref = op.apply(s[:, r].contiguous()).cpu().numpy()
+            assert rel(U2[p][:, r], ref) < 2e-5
+    assert np.array_equal(U[0], U2[0])
+    assert not np.array_equal(U[1], U2[1])   # other factors, other result
+    for op in ops:
+        op.close()
+
+
 @pytest.mark.parametrize("ncell", [(37, 29), (5, 7), (64, 1), (40, 40)])
 def test_ragged_and_degenerate_grids(torch_mod, ncell):
     """Uneven clusters (N_v not a power of two), a single leaf (N_v <= 64,
