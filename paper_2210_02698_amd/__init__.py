@@ -173,7 +173,7 @@ class Operator:
         nrhs = S.shape[1]
         ld = S.stride(1) if nrhs > 1 else self.Nv
         U = torch.empty((nrhs, self.Nv), dtype=self.dtype, device=self.device).t() \
-            if out is None else out.reshape(self.Nv, -1)
+            if out is None else _out_view(out, self.Nv, nrhs, ld, self.dtype, self.device, S)
         self.set_stream()
         self._check(fn(self._ctx, ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(U.data_ptr()),
                        nrhs, ld))
@@ -228,6 +228,35 @@ class Operator:
             pass
 
 
+def _out_view(u, nv, nrhs, ld, dtype, device, s=None):
+    """The caller's output buffer `u` as the nv x nrhs column-major view
+    (leading dimension ld) that the library writes, or an error: a buffer of
+    another type, size or layout would be written outside its bounds or
+    scrambled, and a reshaped copy would silently receive the result."""
+    if u.dtype != dtype or u.device != device:
+        raise ValueError(f"out must be {dtype} on {device}, got {u.dtype} on {u.device}")
+    if u.dim() == 1:
+        if nrhs != 1 or u.shape[0] != nv or u.stride(0) != 1:
+            raise ValueError(f"a 1-D out must hold {nv} contiguous entries for one RHS")
+        U = u.view(nv, 1)
+    elif u.dim() == 2:
+        if tuple(u.shape) != (nv, nrhs):
+            raise ValueError(f"out must be {nv} x {nrhs}, got {tuple(u.shape)}")
+        if u.stride(0) != 1 or (nrhs > 1 and u.stride(1) != ld):
+            raise ValueError(f"out must be column-major with leading dimension {ld}")
+        U = u
+    else:
+        raise ValueError("out must be 1-D or 2-D")
+    if s is not None:
+        esz = U.element_size()
+        a0, a1 = U.data_ptr(), U.data_ptr() + esz * (ld * (nrhs - 1) + nv)
+        b0 = s.data_ptr()
+        b1 = b0 + esz * ((s.stride(1) if s.dim() == 2 else nv) * (nrhs - 1) + nv)
+        if a0 < b1 and b0 < a1:
+            raise ValueError("out overlaps the input")
+    return U
+
+
 def apply_batched(ops, S, out=None):
     """u_p = K_p (h^d s_p) for every operator in `ops` in one library call
     (hbi_apply_batched): all problems' stages share launches and the call is
@@ -244,8 +273,14 @@ def apply_batched(ops, S, out=None):
     for op, s in zip(ops, Sc):
         if s.dtype != op.dtype or s.shape[0] != op.Nv or s.device != op.device:
             raise ValueError("right-hand side does not match its operator")
-    U = out if out is not None else [
-        torch.empty((s.shape[1], s.shape[0]), dtype=s.dtype, device=s.device).t() for s in Sc]
+    if out is not None:
+        if len(out) != n:
+            raise ValueError(f"out must hold {n} buffers")
+        U = [_out_view(u, s.shape[0], s.shape[1], s.shape[0], s.dtype, s.device, s)
+             for u, s in zip(out, Sc)]
+    else:
+        U = [torch.empty((s.shape[1], s.shape[0]), dtype=s.dtype, device=s.device).t()
+             for s in Sc]
     ctxs = (ctypes.c_void_p * n)(*[o._ctx.value for o in ops])
     sp = (ctypes.c_void_p * n)(*[s.data_ptr() for s in Sc])
     up = (ctypes.c_void_p * n)(*[u.data_ptr() for u in U])
