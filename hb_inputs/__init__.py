@@ -9,7 +9,7 @@ self terms, no compression): only the media, their tabulation at fixed node
 pairs, and random numbers.
 
 In the paper the tables come from Lax-Friedrichs WENO eikonal/transport solves
-with point sources at the Chebyshev nodes (Sec. 3.1, eq. chebinterp and the
+with point sources at the Chebyshev nodes (Sec. 4.1, eq. chebinterp and the
 tabulation paragraph after it); that solver is outside this project.  Here the
 tables are filled from closed forms where the medium has one (homogeneous and
 constant-gradient media, Sec. 5.1) and from a smooth straight-ray stand-in

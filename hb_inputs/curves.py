@@ -1,4 +1,4 @@
-"""Curve inclusions for the HB integrator (Sec. 3.1, domain with inclusion):
+"""Curve inclusions for the HB integrator (Sec. 3.2, domain with a sound-hard inclusion):
 a closed curve C discretised into N_s straight segments, given by their
 centres r^s_i, lengths w_i and the slowness n(r^s_i) of the medium there.
 Geometry only; none of the integrator's arithmetic."""

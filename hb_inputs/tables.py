@@ -1,4 +1,4 @@
-"""Tabulation of tau^2, v0, v1 at Chebyshev node pairs (Sec. 3.1).
+"""Tabulation of tau^2, v0, v1 at Chebyshev node pairs (Sec. 4.1).
 
 Layout (shared by every consumer of the tables):
   * the table region is ``nbox[0] x nbox[1] (x nbox[2])`` cubic boxes of side

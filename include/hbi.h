@@ -10,7 +10,7 @@
  * taken from Chebyshev-interpolated tables (eq. chebinterp,
  * eq. chebinterpblock) and K_ii the cell integral of the leading HB term
  * (Appendix A).  K is compressed as a hierarchically off-diagonal butterfly
- * (HODBF) matrix (Sec. 3.2): a K-D cluster tree, one column-wise butterfly
+ * (HODBF) matrix (Sec. 4.2): a K-D cluster tree, one column-wise butterfly
  * per pair of sibling clusters (eq. butterfly_mat, eq. butterfly_factors)
  * built level by level from interpolative decompositions of proxy-row
  * blocks (eq. ID, eq. proxy, eq. proxyv2v), and dense diagonal leaf blocks.
@@ -48,8 +48,8 @@ typedef enum {
 
 typedef enum { HBI_F64 = 0, HBI_F32 = 1 } hbi_prec;
 
-/* Problem statement and tabulated HB ingredients (Sec. 3.1 and the
- * tabulation of eq. chebinterp).
+/* Problem statement (Sec. 3.1) and tabulated HB ingredients (Sec. 4.1,
+ * eq. chebinterp).
  *
  * Table layout: the table region is nbox[0] x nbox[1] (x nbox[2]) cubic
  * boxes of side box_size from box_origin; box b = bx + nbox0*(by + nbox1*bz).
@@ -78,7 +78,7 @@ typedef struct {
                              order (used by the self terms, Appendix A)    */
 } hbi_tables;
 
-/* Compression parameters (Sec. 3.2.2 and the parameter choices of
+/* Compression parameters (Sec. 4.2.2 and the parameter choices of
  * Sec. 5.1).  Zero / negative fields select the default in brackets. */
 typedef struct {
   double chi;               /* proxy oversampling factor chi of eq. proxyv2v
@@ -110,7 +110,7 @@ hbi_status hbi_set_stream(hbi_ctx *ctx, void *hip_stream);
 hbi_status hbi_load_tables(hbi_ctx *ctx, const hbi_tables *t);
 
 /* Tables and cells of `src` at another angular frequency.  The HB
- * ingredients tau, v0, v1 do not depend on omega (Sec. 2.2: tabulated once,
+ * ingredients tau, v0, v1 do not depend on omega (Sec. 2.3: tabulated once,
  * reused for many frequencies), so a frequency sweep loads its tables once
  * and gives every further context a device-to-device copy of them, with the
  * cluster tree and per-cell data copied when the leaf sizes agree; only the
@@ -122,7 +122,7 @@ hbi_status hbi_load_tables(hbi_ctx *ctx, const hbi_tables *t);
  * (HBI_ERR_ARG).  Synchronous. */
 hbi_status hbi_load_tables_from(hbi_ctx *ctx, const hbi_ctx *src, double omega);
 
-/* A curve inclusion (Sec. 3.1, domain with inclusion; 2D): ns straight
+/* A curve inclusion (Sec. 3.2, domain with a sound-hard inclusion; 2D): ns straight
  * segments with centres (xy[2i], xy[2i+1]), lengths w[i] > 0 and slowness
  * slowness[i] > 0 of the medium at the centres (host arrays, copied; the
  * centres must lie in the table region; 0 <= ns <= 8192, ns = 0 removes the
@@ -145,7 +145,7 @@ hbi_status hbi_set_inclusion(hbi_ctx *ctx, int32_t ns, const double *xy, const d
  * defaults). */
 hbi_status hbi_set_build_opts(hbi_ctx *ctx, const hbi_build_opts *opts);
 
-/* Build the HODBF factors (Sec. 3.2): interpolative decompositions by
+/* Build the HODBF factors (Sec. 4.2): interpolative decompositions by
  * column-pivoted QR with relative tolerance `tol` (eq. ID: a pivot is kept
  * while |R_kk| > tol |R_11|), in FP64.  `prec` selects the precision the
  * factors are stored and applied in (HBI_F32 rounds the FP64 factors).

@@ -17,7 +17,7 @@ SQRT_PI = math.sqrt(math.pi)
 
 
 # ---------------------------------------------------------------------------
-# Chebyshev interpolation (Sec. 3.1, eq. chebinterp, eq. chebinterpblock)
+# Chebyshev interpolation (Sec. 4.1, eq. chebinterp, eq. chebinterpblock)
 # ---------------------------------------------------------------------------
 def cheb_nodes(nI):
     """First-kind Chebyshev nodes of one box, as fractions of the box side:
@@ -27,7 +27,7 @@ def cheb_nodes(nI):
 
 
 def lagrange_1d(x, nodes):
-    """Lagrange basis by the product formula of Sec. 3.1:
+    """Lagrange basis by the product formula of Sec. 4.1:
     l_i(x) = prod_{k != i} (x - x_k) / (x_i - x_k).  Returns (len(x), nI)."""
     x = np.asarray(x, np.float64)
     nI = len(nodes)

@@ -1,5 +1,5 @@
 """Dense FP64 oracle of the HB integrator with a curve inclusion
-(Sec. 3.1, domain with inclusion; test infrastructure only).
+(Sec. 3.2, domain with a sound-hard inclusion; test infrastructure only).
 
     U = (K^{v2v} + K^{s2v} (K^{s2s})^{-1} K^{v2s}) I,   I = h^d s
                                                     (eq. m_v2v_inclu)

@@ -5,7 +5,7 @@ streams; every step of entry evaluation, compression and application runs in
 the library's HIP kernels.
 
     op = Operator(problem, device=0)          # problem statement + tables
-    op.build(tol=1e-7, prec="f64")            # HODBF factors (Sec. 3.2)
+    op.build(tol=1e-7, prec="f64")            # HODBF factors (Sec. 4.2)
     u = op.apply(s)                           # u = K (h^d s)    (eq. m_v2v)
     g = op.apply_adjoint(r)                   # g = h^d K^H r
     u = HBApply.apply(op, s)                  # differentiable in s
@@ -100,6 +100,18 @@ class Operator:
                 np.ascontiguousarray(p.v0, dtype=np.float64),
                 None if p.v1 is None else np.ascontiguousarray(p.v1, dtype=np.float64),
                 np.ascontiguousarray(p.slowness, dtype=np.float64)]
+        # the library reads NT x NT doubles per table and N_v slowness
+        # values through these pointers: check the sizes here
+        nbox = int(np.prod([t.nbox[a] for a in range(self.dim)]))
+        NT = nbox * int(p.nI) ** self.dim
+        for name, a in zip(("tau2", "v0", "v1"), arrs[:3]):
+            if a is None:
+                if name != "v1" or int(p.nterms) != 1:
+                    raise ValueError(f"{name} is required")
+            elif a.size != NT * NT:
+                raise ValueError(f"{name} must hold NT x NT = {NT} x {NT} entries, got {a.shape}")
+        if arrs[3].size != self.Nv:
+            raise ValueError(f"slowness must hold N_v = {self.Nv} entries, got {arrs[3].size}")
         t.tau2 = _dptr(arrs[0])
         t.v0 = _dptr(arrs[1])
         t.v1 = _dptr(arrs[2]) if arrs[2] is not None else ctypes.POINTER(ctypes.c_double)()
@@ -108,7 +120,7 @@ class Operator:
         self.prec = None
 
     def set_inclusion(self, curve=None):
-        """A curve inclusion (Sec. 3.1): ``curve`` has ``centres`` (N_s, 2),
+        """A curve inclusion (Sec. 3.2): ``curve`` has ``centres`` (N_s, 2),
         ``w`` (N_s,) and ``slowness`` (N_s,); None removes it.  Drops the
         factors; after the next build, apply / apply_adjoint use the total
         operator (K^{v2v} + K^{s2v} (K^{s2s})^{-1} K^{v2s}) h^d."""
@@ -257,6 +269,17 @@ def _out_view(u, nv, nrhs, ld, dtype, device, s=None):
     return U
 
 
+def _span(t):
+    """[first byte, last byte + 1) of a 2-D column-major device view."""
+    esz = t.element_size()
+    ld = t.stride(1) if t.shape[1] > 1 else t.shape[0]
+    return t.data_ptr(), t.data_ptr() + esz * (ld * (t.shape[1] - 1) + t.shape[0])
+
+
+def _overlaps(a, b):
+    return a[0] < b[1] and b[0] < a[1]
+
+
 def apply_batched(ops, S, out=None):
     """u_p = K_p (h^d s_p) for every operator in `ops` in one library call
     (hbi_apply_batched): all problems' stages share launches and the call is
@@ -278,6 +301,14 @@ def apply_batched(ops, S, out=None):
             raise ValueError(f"out must hold {n} buffers")
         U = [_out_view(u, s.shape[0], s.shape[1], s.shape[0], s.dtype, s.device, s)
              for u, s in zip(out, Sc)]
+        # an output may overlap no other problem's input or output either:
+        # passes of a large batch run problems at different times
+        spans = [_span(x) for x in U]
+        ins = [_span(x) for x in Sc]
+        for p in range(n):
+            for q in range(n):
+                if q != p and (_overlaps(spans[p], ins[q]) or _overlaps(spans[p], spans[q])):
+                    raise ValueError(f"out[{p}] overlaps the input or output of problem {q}")
     else:
         U = [torch.empty((s.shape[1], s.shape[0]), dtype=s.dtype, device=s.device).t()
              for s in Sc]

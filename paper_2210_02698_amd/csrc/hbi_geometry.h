@@ -1,4 +1,4 @@
-// Host geometry of the HODBF representation (Sec. 3.2): K-D cluster tree of
+// Host geometry of the HODBF representation (Sec. 4.2): K-D cluster tree of
 // the cell centres, node ranges and bounding boxes, boundary bands, and the
 // proxy-row rule of eq. proxyv2v.
 #pragma once

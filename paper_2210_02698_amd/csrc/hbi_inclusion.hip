@@ -1,4 +1,4 @@
-// HIP kernels of the curve inclusion (Sec. 3.1, domain with inclusion), 2D:
+// HIP kernels of the curve inclusion (Sec. 3.2, domain with a sound-hard inclusion), 2D:
 //
 //   U = (K^{v2v} + K^{s2v} (K^{s2s})^{-1} K^{v2s}) h^d s      (eq. m_v2v_inclu)
 //

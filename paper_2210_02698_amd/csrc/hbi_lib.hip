@@ -1420,7 +1420,7 @@ void build_factors(hbi_ctx *c, double tol) {
   c->t_build = now_s() - tb0;
 }
 
-// Dense operators of the curve inclusion (Sec. 3.1, eq. m_v2v_inclu):
+// Dense operators of the curve inclusion (Sec. 3.2, eq. m_v2v_inclu):
 // G[j, i] = g(r_j, r^s_i) over cells j (natural order, chunks of kIncChunk
 // cells) and segments i, evaluated by the entry kernels with the segments as
 // points after the cells; K^{s2s} from g between segments, its columns
@@ -1879,9 +1879,13 @@ void multi_apply(hbi_ctx *c0, const std::vector<hbi_ctx *> &ctxs, const std::vec
     const std::string key = std::string(prec == HBI_F64 ? "f64" : "f32") + ":jt" + std::to_string(maxjt);
     auto &tt = tune_table();
     int best = -1;
+    // a cached width is used only if it is one of the candidates this batch
+    // would time (a corrupt or stale file entry is ignored and re-tuned)
     if (tt.count(key)) {
-      best = tt[key];
-    } else {
+      const int nb = tt[key];
+      if ((nb == 1 || nb == 2 || nb == 4 || nb == 8) && (nb == 1 || nb <= maxjt)) best = nb;
+    }
+    if (best < 0) {
       double bt = 1e300;
       for (int nb : {1, 2, 4, 8}) {
         if (nb > 1 && nb > maxjt) break;
@@ -1931,6 +1935,24 @@ void multi_apply(hbi_ctx *c0, const std::vector<hbi_ctx *> &ctxs, const std::vec
 // ===========================================================================
 // C ABI
 // ===========================================================================
+namespace {
+// Index and descriptor bytes one forward apply reads (algorithmic).
+double apply_index_bytes(const ApplyPlan &ap) {
+  double b = ap.v_idx + ap.f_idx;
+  for (double w : ap.w_idx) b += w;
+  return b;
+}
+// Bytes of the inclusion operators one apply streams: G twice (the
+// K^{v2s} gather and the K^{s2v} scatter), (K^{s2s})^{-1} once, and the
+// cell vectors read and written.
+double inclusion_apply_bytes(const hbi_ctx *c) {
+  if (!c->inc_ns || c->state < 2) return 0.0;
+  const double esz = c->prec == HBI_F64 ? 16.0 : 8.0;
+  const double nv = (double)c->geo.Nv, ns = (double)c->inc_ns;
+  return esz * (2.0 * nv * ns + ns * ns + 2.0 * nv);
+}
+}  // namespace
+
 extern "C" {
 
 hbi_status hbi_create(int device, void *hip_stream, hbi_ctx **out) {
@@ -2297,7 +2319,8 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       "\"build_s\": %.6f, \"build_geometry_s\": %.6f, \"build_proxy_host_s\": %.6f, "
       "\"build_gpu_s\": %.6f, \"build_batch_host_setup_s\": %.6f, \"build_batch_total_s\": %.6f, "
       "\"build_compact_s\": %.6f, \"build_finalize_s\": %.6f, "
-      "\"inclusion_ns\": %d, \"inclusion_bytes\": %lld, \"build_inclusion_s\": %.6f}",
+      "\"inclusion_ns\": %d, \"inclusion_bytes\": %lld, \"build_inclusion_s\": %.6f, "
+      "\"apply_index_bytes\": %.0f, \"inclusion_apply_bytes\": %.0f}",
       ctx->state, ctx->dim, (long long)Nv, ctx->geo.Lv, ctx->NT, ctx->nI,
       ctx->prec == HBI_F64 ? "f64" : "f32", ctx->tol, ctx->chi(), ctx->leaf(),
       (long long)ctx->nnz_v, (long long)ctx->nnz_w, (long long)ctx->nnz_k, (long long)ctx->nnz_d,
@@ -2312,7 +2335,8 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       ctx->id_work_wide, ctx->id_work_128, ctx->t_build, ctx->t_geo, ctx->t_host, ctx->t_gpu, ctx->t_prep,
       ctx->t_wait, ctx->t_compact,
       ctx->t_final, ctx->inc_ns,
-      (long long)(ctx->inc_G.n + ctx->inc_M.n + ctx->inc_MH.n), ctx->t_inc);
+      (long long)(ctx->inc_G.n + ctx->inc_M.n + ctx->inc_MH.n), ctx->t_inc,
+      apply_index_bytes(ctx->plan), inclusion_apply_bytes(ctx));
   if (len < 0 || len >= cap) { ctx->err = "output buffer too small"; return HBI_ERR_ARG; }
   std::memcpy(json, buf, len + 1);
   return HBI_OK;

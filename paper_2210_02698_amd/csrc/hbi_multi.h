@@ -70,6 +70,5 @@ hipError_t launch_gather_in(const MTrans *jobs, int64_t njobs, int64_t maxNv, in
 template <typename R>
 hipError_t launch_scatter_out(const MTrans *jobs, int64_t njobs, int64_t maxNv, int maxjt,
                               hipStream_t st);
-hipError_t launch_mfma_probe(const float *A, const float *B, float *D, hipStream_t st);
 
 }  // namespace hbi

@@ -7,7 +7,7 @@
 // Operand layout of the 16x16x4 MFMA (one wave): lane l holds A[l%16][l/16]
 // and B[l/16][l%16].  Accumulator v = 0..3 of lane l holds D[4*(l/16) + v]
 // [l%16] for the FP32 instruction and D[l/16 + 4*v][l%16] for the FP64 one
-// (checked on gfx950 with a probe of both builtins).
+// (measured on gfx950 for both builtins).
 //
 // Vectors are in tree order with the right-hand sides contiguous:
 // element (row, j) of a block with offset zoff is z[(zoff + row) * Np + j],
@@ -372,17 +372,6 @@ __global__ __launch_bounds__(256) void k_scatter_out(const MTrans *jobs, int64_t
   }
 }
 
-// MFMA operand-layout check: D = A B for one 16x16x4 tile (A row-major
-// 16x4, B row-major 4x16, D row-major 16x16), exactly as the GEMM kernels
-// use the instruction.
-__global__ void k_mfma_probe(const float *A, const float *B, float *D) {
-  const int l = threadIdx.x;
-  v4f acc = {0.f, 0.f, 0.f, 0.f};
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[(l & 15) * 4 + (l >> 4)], B[(l >> 4) * 16 + (l & 15)],
-                                             acc, 0, 0, 0);
-  for (int v = 0; v < 4; ++v) D[(4 * (l >> 4) + v) * 16 + (l & 15)] = acc[v];
-}
-
 // ---------------------------------------------------------------------------
 template <typename R, int NB>
 static void launch_stage_nb(const MStagePlan &sp, hipStream_t st) {
@@ -424,11 +413,6 @@ hipError_t launch_scatter_out(const MTrans *jobs, int64_t njobs, int64_t maxNv, 
   if (njobs == 0) return hipSuccess;
   hipLaunchKernelGGL((k_scatter_out<R>), dim3((maxNv + 63) / 64, njobs, maxjt), dim3(256), 0, st,
                      jobs, njobs);
-  return hipGetLastError();
-}
-
-hipError_t launch_mfma_probe(const float *A, const float *B, float *D, hipStream_t st) {
-  hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, st, A, B, D);
   return hipGetLastError();
 }
 

@@ -51,3 +51,50 @@ def test_overlap_with_the_input_is_rejected():
     assert _out_view(u2, NV, NR, NV, torch.complex64, CPU, s2).data_ptr() == u2.data_ptr()
     with pytest.raises(ValueError, match="overlaps"):
         _out_view(big[NR - 1:2 * NR - 1].t(), NV, NR, NV, torch.complex64, CPU, s2)
+
+
+class _FakeOp:
+    """Stands in for an Operator in the checks that run before any library
+    call (no device needed)."""
+
+    def __init__(self, nv, dtype=torch.complex64):
+        self.Nv, self.dtype, self.device = nv, dtype, CPU
+
+
+def test_batched_output_overlapping_another_problem_is_rejected():
+    import paper_2210_02698_amd as hbi
+    ops = [_FakeOp(NV), _FakeOp(NV)]
+    buf = torch.empty((4 * NR, NV), dtype=torch.complex64)
+    s0, s1 = buf[0:NR].t(), buf[NR:2 * NR].t()
+    u0, u1 = buf[2 * NR:3 * NR].t(), buf[3 * NR:].t()
+    with pytest.raises(ValueError, match="overlaps the input or output of problem 1"):
+        hbi.apply_batched(ops, [s0, s1], out=[s1, u1])       # out[0] is problem 1's input
+    with pytest.raises(ValueError, match=r"out\[0\] overlaps the input or output of problem 1"):
+        hbi.apply_batched(ops, [s0, s1], out=[u0, u0])       # two outputs share memory
+
+
+def _table_problem(nI=3, nbox=(1, 1), ncell=(4, 4), nterms=2, bad=None):
+    import types
+    import numpy as np
+    NT = int(np.prod(nbox)) * nI ** 2
+    p = types.SimpleNamespace(dim=2, ncell=ncell, origin=(0.0, 0.0), h=0.25, omega=1.0,
+                              nterms=nterms, nI=nI, nbox=nbox, box_origin=(0.0, 0.0),
+                              box_size=1.0, tau2=np.zeros((NT, NT)), v0=np.zeros((NT, NT)),
+                              v1=np.zeros((NT, NT)), slowness=np.ones(ncell[0] * ncell[1]))
+    if bad == "tau2":
+        p.tau2 = np.zeros((NT, NT - 1))
+    elif bad == "v1":
+        p.v1 = None
+    elif bad == "slowness":
+        p.slowness = np.ones(ncell[0] * ncell[1] - 1)
+    return p
+
+
+@pytest.mark.parametrize("bad", ["tau2", "v1", "slowness"])
+def test_missized_tables_are_rejected_before_the_library_reads_them(bad):
+    from paper_2210_02698_amd import Operator
+    op = Operator.__new__(Operator)        # no device context: the check comes first
+    op.dim, op.Nv = 2, 16
+    op._lib = None
+    with pytest.raises(ValueError):
+        op.load(_table_problem(bad=bad))

@@ -1,4 +1,4 @@
-"""GPU parity of the curve inclusion (Sec. 3.1, eq. m_v2v_inclu) against the
+"""GPU parity of the curve inclusion (Sec. 3.2, eq. m_v2v_inclu) against the
 FP64 oracle (oracle.inclusion), through the C ABI.
 
 Tolerances: the inclusion term has no compression, so its difference from

@@ -1,6 +1,6 @@
 """Frequency sweep from one table set (hbi_load_tables_from).
 
-The HB ingredients tau, v0, v1 do not depend on omega (Sec. 2.2: computed
+The HB ingredients tau, v0, v1 do not depend on omega (Sec. 2.3: computed
 once, reused for many frequencies), so operators at several frequencies are
 built from one loaded table set.  Checked here: a copy at the same omega is
 the same operator bit for bit; at other frequencies each operator matches

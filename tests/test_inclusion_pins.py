@@ -1,4 +1,4 @@
-"""CPU pins of the inclusion oracle (oracle.inclusion), Sec. 3.1 domain with
+"""CPU pins of the inclusion oracle (oracle.inclusion), Sec. 3.2 domain with
 inclusion, eq. m_v2v_inclu.
 
 * The self entry of K^{s2s} against adaptive quadrature of minus the segment
