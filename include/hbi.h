@@ -185,6 +185,27 @@ hbi_status hbi_apply_batched(hbi_ctx *const *ctx, int32_t nprob,
                              const void *const *s, void *const *u,
                              const int32_t *nrhs, const int64_t *ld);
 
+/* Bytes of the fixed per-device scratch array of hbi_apply_noalloc. */
+#define HBI_NOALLOC_SCRATCH_BYTES (128u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as hbi_apply, u = K (h^d s) for nrhs right-hand sides (same
+ * layout rules; the right-hand sides are applied one after another with the
+ * single-RHS kernels), with the per-level vectors z in a fixed scratch
+ * array of HBI_NOALLOC_SCRATCH_BYTES bytes that the library holds on every
+ * device it runs on until the process ends, instead of memory the library
+ * allocates.  Nothing is allocated or freed, and no per-kernel timing is
+ * recorded.  The scratch needed, "apply_scratch_bytes" of hbi_get_info,
+ * must fit that array (HBI_ERR_ARG otherwise, with the sizes in the
+ * message); contexts with a curve inclusion are rejected (HBI_ERR_ARG).
+ * Every call on a device shares that device's array and leaves its
+ * contents behind (no part of it needs to start at zero: a product writes
+ * every entry it reads first), so calls that overlap in time on one device
+ * (several streams, several threads) race and must be serialised by the
+ * caller.  Asynchronous on the context's stream. */
+hbi_status hbi_apply_noalloc(hbi_ctx *ctx, const void *s, void *u, int32_t nrhs, int64_t ld);
+
 /* hb_entry on its own: out[i + m*j] = K[rows[i], cols[j]] (natural cell
  * indices, host int32 arrays) as complex128 into the device array `out`
  * (column-major m x n), including the self term where rows[i] == cols[j].

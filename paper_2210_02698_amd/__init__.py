@@ -199,6 +199,12 @@ class Operator:
         """u = h^d K^H s."""
         return self._run(self._lib.hbi_apply_adjoint, s, out)
 
+    def apply_noalloc(self, s, out):
+        """u = K (h^d s) through hbi_apply_noalloc: the library allocates
+        nothing (its per-level vectors live in a fixed per-device scratch
+        array), so the caller gives the output buffer."""
+        return self._run(self._lib.hbi_apply_noalloc, s, out)
+
     def entries(self, rows, cols):
         """K[rows][:, cols] (natural indices) as a complex128 device tensor."""
         import torch

@@ -11,6 +11,7 @@
 #include <functional>
 #include <limits>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -35,6 +36,44 @@ thread_local std::string g_err;
 // replayed on factors that a rebuild (or a new context at the same
 // address) has replaced.
 std::atomic<uint64_t> g_build_gen{0};
+
+}  // namespace
+
+// Fixed per-device scratch of the allocation-free apply (hbi_apply_noalloc):
+// the per-level vectors z of the single-RHS product live here instead of in
+// memory the library allocates.  Host code never uses this name as an
+// address: the device address of each GPU's copy comes from
+// hipGetSymbolAddress, taken once per device when a context is created on
+// it, and kept in g_scratch below.
+static __device__ __align__(256) unsigned char scratch[HBI_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+struct ScratchSlot {
+  bool done = false;
+  hipError_t status = hipSuccess;
+  void *ptr = nullptr;
+};
+std::mutex g_scratch_mu;
+std::map<int, ScratchSlot> g_scratch;
+
+// The device address of `scratch` on `device` (the current device), looked
+// up once per device.
+void setup_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  ScratchSlot &sl = g_scratch[device];
+  if (sl.done) return;
+  sl.done = true;
+  void *ptr = nullptr;
+  sl.status = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (sl.status != hipSuccess) {
+    (void)hipGetLastError();
+    sl.ptr = nullptr;
+  } else {
+    sl.ptr = ptr;
+  }
+}
+
 
 struct DevBuf {
   void *p = nullptr;
@@ -113,6 +152,17 @@ struct Error {
   do {                               \
     if (!(cond)) throw Error{code, msg}; \
   } while (0)
+
+void *scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(device);
+  if (it == g_scratch.end() || !it->second.done)
+    throw Error{HBI_ERR_STATE, "scratch of this device not set up (no context created on it)"};
+  if (it->second.status != hipSuccess)
+    throw Error{HBI_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                 hipGetErrorString(it->second.status)};
+  return it->second.ptr;
+}
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -202,6 +252,7 @@ struct hbi_ctx {
   std::vector<DevBuf> units_d, items_d, items_adj_d;
   ApplyPlan plan;
   int64_t ztotal = 0;
+  int64_t zalloc = 0;   // entries of z_d (the per-level vectors of one single-RHS product)
   DevBuf z_d;
   // curve inclusion (2D): segments at positions [Nv, Nv + inc_ns) of the
   // per-point arrays; inputs on the host and the device, and the dense
@@ -273,7 +324,8 @@ struct hbi_ctx {
     inc_part.release(); inc_z.release(); inc_y.release(); inc_part2.release();
     inc_part3.release();
     inc_plan = InclusionPlan(); t_inc = 0;
-    leaves_h.clear(); vd_h.clear(); kd_h.clear(); units_h.clear(); batch.reset(); ztotal = 0; z_d.release();
+    leaves_h.clear(); vd_h.clear(); kd_h.clear(); units_h.clear(); batch.reset(); ztotal = 0; zalloc = 0;
+    z_d.release();
     build_gen = 0;
     nnz_v = nnz_w = nnz_k = nnz_d = entries_eval = nid = 0; rank_max = 0; rank_sum = 0;
     t_prep = t_wait = t_compact = 0; entry_slots = 0;
@@ -1413,7 +1465,8 @@ void build_factors(hbi_ctx *c, double tol) {
       for (const WUnit &U : units[k]) ap.w_idx[k] += 2.0 * sizeof(uint16_t) * U.c;
     }
   }
-  HBI_HIP(c->z_d.alloc(esz * std::max<int64_t>(c->ztotal, 1)));
+  c->zalloc = c->ztotal;
+  HBI_HIP(c->z_d.alloc(esz * std::max<int64_t>(c->zalloc, 1)));
   c->t_final = now_s() - tf;
   c->t_host = t_host;
   c->t_gpu = t_gpu;
@@ -1546,19 +1599,24 @@ void check_apply_args(hbi_ctx *c, const void *s, void *u, int32_t nrhs, int64_t 
   HBI_REQUIRE(!overlap(s, span, u, span), HBI_ERR_ARG, "s and u overlap");
 }
 
-void do_apply(hbi_ctx *c, const void *s, void *u, int32_t nrhs, int64_t ld, bool adj) {
+// The single-RHS product column by column, with the per-level vectors in z
+// (the context's own buffer unless another one is given; no profiling
+// events are recorded then).
+void do_apply(hbi_ctx *c, const void *s, void *u, int32_t nrhs, int64_t ld, bool adj,
+              void *zbuf = nullptr) {
   check_apply_args(c, s, u, nrhs, ld);
   const size_t esz = c->prec == HBI_F64 ? 16 : 8;
   c->prof.st = c->stream;
-  LaunchHook *hook = c->profiling ? &c->prof : nullptr;
+  LaunchHook *hook = c->profiling && !zbuf ? &c->prof : nullptr;
+  void *z = zbuf ? zbuf : c->z_d.p;
   for (int32_t r = 0; r < nrhs; ++r) {
     const char *sc = (const char *)s + esz * (size_t)ld * r;
     char *uc = (char *)u + esz * (size_t)ld * r;
     if (c->prec == HBI_F64) {
-      HBI_HIP(launch_apply<double>(c->plan, sc, uc, c->z_d.p, c->F.p, std::pow(c->h, c->dim), adj,
+      HBI_HIP(launch_apply<double>(c->plan, sc, uc, z, c->F.p, std::pow(c->h, c->dim), adj,
                                    c->stream, hook));
     } else {
-      HBI_HIP(launch_apply<float>(c->plan, sc, uc, c->z_d.p, c->F.p, (float)std::pow(c->h, c->dim),
+      HBI_HIP(launch_apply<float>(c->plan, sc, uc, z, c->F.p, (float)std::pow(c->h, c->dim),
                                   adj, c->stream, hook));
     }
   }
@@ -1963,6 +2021,7 @@ hbi_status hbi_create(int device, void *hip_stream, hbi_ctx **out) {
     HBI_HIP(hipGetDeviceCount(&n));
     HBI_REQUIRE(device >= 0 && device < n, HBI_ERR_ARG, "device index out of range");
     HBI_HIP(hipSetDevice(device));
+    setup_scratch(device);
     auto c = std::make_unique<hbi_ctx>();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
@@ -2221,6 +2280,23 @@ hbi_status hbi_apply_batched(hbi_ctx *const *ctx, int32_t nprob, const void *con
   });
 }
 
+hbi_status hbi_apply_noalloc(hbi_ctx *ctx, const void *s, void *u, int32_t nrhs, int64_t ld) {
+  if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
+  return guarded(ctx, [&]() {
+    HBI_REQUIRE(ctx->state == 2, HBI_ERR_STATE, "apply before build");
+    HBI_REQUIRE(ctx->inc_ns == 0, HBI_ERR_ARG,
+                "hbi_apply_noalloc applies the volume operator only (the context has a curve "
+                "inclusion)");
+    const size_t esz = ctx->prec == HBI_F64 ? 16 : 8;
+    const size_t need = esz * (size_t)std::max<int64_t>(ctx->zalloc, 1);
+    if (need > (size_t)HBI_NOALLOC_SCRATCH_BYTES)
+      throw Error{HBI_ERR_ARG, "hbi_apply_noalloc: the product needs " + std::to_string(need) +
+                                   " bytes of scratch, more than the fixed " +
+                                   std::to_string((size_t)HBI_NOALLOC_SCRATCH_BYTES) +
+                                   " bytes per device"};
+    do_apply(ctx, s, u, nrhs, ld, false, scratch_ptr(ctx->device));
+  });
+}
 hbi_status hbi_apply_adjoint(hbi_ctx *ctx, const void *s, void *u, int32_t nrhs, int64_t ld) {
   if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
   return guarded(ctx, [&]() {
@@ -2320,7 +2396,8 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       "\"build_gpu_s\": %.6f, \"build_batch_host_setup_s\": %.6f, \"build_batch_total_s\": %.6f, "
       "\"build_compact_s\": %.6f, \"build_finalize_s\": %.6f, "
       "\"inclusion_ns\": %d, \"inclusion_bytes\": %lld, \"build_inclusion_s\": %.6f, "
-      "\"apply_index_bytes\": %.0f, \"inclusion_apply_bytes\": %.0f}",
+      "\"apply_index_bytes\": %.0f, \"inclusion_apply_bytes\": %.0f, "
+      "\"apply_scratch_bytes\": %lld}",
       ctx->state, ctx->dim, (long long)Nv, ctx->geo.Lv, ctx->NT, ctx->nI,
       ctx->prec == HBI_F64 ? "f64" : "f32", ctx->tol, ctx->chi(), ctx->leaf(),
       (long long)ctx->nnz_v, (long long)ctx->nnz_w, (long long)ctx->nnz_k, (long long)ctx->nnz_d,
@@ -2336,7 +2413,8 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       ctx->t_wait, ctx->t_compact,
       ctx->t_final, ctx->inc_ns,
       (long long)(ctx->inc_G.n + ctx->inc_M.n + ctx->inc_MH.n), ctx->t_inc,
-      apply_index_bytes(ctx->plan), inclusion_apply_bytes(ctx));
+      apply_index_bytes(ctx->plan), inclusion_apply_bytes(ctx),
+      (long long)(ctx->zalloc * (int64_t)esz));
   if (len < 0 || len >= cap) { ctx->err = "output buffer too small"; return HBI_ERR_ARG; }
   std::memcpy(json, buf, len + 1);
   return HBI_OK;
