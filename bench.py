@@ -348,13 +348,11 @@ def gpu_bump(args, w, ref, cpu):
             err, row = rel_err(u.cpu().numpy()[rows], ref)
         t_apply, prof = timed_single(op, s, args.steps, args.warmup)
         esz = 16 if prec == "f64" else 8
-        # factor entries, and the transfer units' index lists the forward
-        # product reads (from the factor layout)
-        fbytes = info["nnz_total"] * esz + info["apply_index_bytes"]
-        vec_bytes = (2 * prob.Nv + 2 * info["z_entries"]) * esz
+        # algorithmic bytes of one product (from the factor layout): factor
+        # entries, vectors read and written, index lists and descriptors
         results[prec] = dict(build_s=build_s, err=err, row=row, ms=t_apply * 1e3, info=info,
                              prof=prof, gcells=prob.Nv / t_apply / 1e9,
-                             apply_gbs=(fbytes + vec_bytes) / t_apply / 1e9,
+                             apply_gbs=info["apply_bytes"] / t_apply / 1e9,
                              factor_bytes=info["nnz_total"] * esz)
         log(f"bump {prec} apply {t_apply * 1e3:.3f} ms err {err} row {row} prof {prof}")
         op.close()

@@ -133,169 +133,142 @@ __global__ __launch_bounds__(256) void k_vstage(const cplx_t<R> *s,
   }
 }
 
-// Rows [off, off + wr) of a compact transfer unit (all rows when it has at
-// most 32): row i of child a is X[i] + sum_m T_a[i, m] X[ra + m] with
-// X = xv + xoff the inputs in a's column order (xoff = 0), likewise for b
-// (xoff = c).  Per lane: T column stride rc, column count t, and the columns
-// grp, grp + G, ... when G = 64 / wr > 1 lanes share a row.
-template <typename C> struct RowLane {
-  const C *T;        // the lane's first factor entry
-  int64_t tstep;     // between its successive entries
-  int nt, grp, G, wr, i, xo;
-  bool act, isb;
-};
-template <typename C>
-__device__ __forceinline__ RowLane<C> row_lane(const WItem &U, const C *__restrict__ Ta, int lane) {
-  RowLane<C> L;
-  const int ra = U.ra, rb = U.rb, c = U.c, Rt = ra + rb;
-  L.wr = Rt <= 32 ? Rt : U.wr;   // rows of the window
-  L.G = 64 / L.wr;
-  const int row = (Rt <= 32 ? 0 : U.off) + lane % L.wr;
-  L.grp = lane / L.wr;
-  L.isb = row >= ra;
-  L.i = L.isb ? row - ra : row;
-  const int rc = L.isb ? rb : ra;
-  L.xo = (L.isb ? c : 0) + rc;
-  L.T = (L.isb ? Ta + (int64_t)ra * (c - ra) : Ta) + L.i + (int64_t)L.grp * rc;
-  L.tstep = (int64_t)L.G * rc;
-  L.act = row < Rt && L.grp < L.G;
-  const int t = c - rc;
-  L.nt = L.act && t > L.grp ? (t - L.grp + L.G - 1) / L.G : 0;
-  return L;
-}
-template <typename C, int B, typename XF>
-__device__ __forceinline__ void wstage_rows(const WItem &U, const RowLane<C> &L, int lane, XF xv,
-                                            C *z) {
-  const int nt = L.nt, G = L.G, grp = L.grp, xo = L.xo;
-  C acc{0, 0};
-  for (int q0 = 0; q0 < nt; q0 += B) {
-    C mv[B], xq[B];
+// One lane's share of a row of a column-major factor block: entries
+// T[0], T[step], ... (nt of them), streamed B at a time.  issue(q0) loads
+// entries q0 .. q0 + B - 1 (zero past nt), so the first batch can be issued
+// before the lane's inputs are ready.
+template <typename C, int B> struct RowStream {
+  const C *T;
+  int64_t step;
+  int nt;
+  C mv[B];
+  __device__ __forceinline__ void issue(int q0) {
 #pragma unroll
-    for (int u = 0; u < B; ++u) {
-      if (q0 + u < nt) {
-        mv[u] = ldf(L.T + (q0 + u) * L.tstep);
-        xq[u] = xv(xo + grp + (q0 + u) * G);
-      } else {
-        mv[u] = C{0, 0};
-        xq[u] = C{0, 0};
+    for (int u = 0; u < B; ++u) mv[u] = q0 + u < nt ? ldf(T + (int64_t)(q0 + u) * step) : C{0, 0};
+  }
+  // sum_q T[q step] x(q) in order of q; the first batch must have been issued
+  template <typename XF> __device__ __forceinline__ C dot(XF x) {
+    C acc{0, 0};
+    for (int q0 = 0; q0 < nt; q0 += B) {
+      if (q0 > 0) issue(q0);
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int q = q0 + u < nt ? q0 + u : nt - 1;   // padding entries are zero
+        cfma(acc, mv[u], x(q));
       }
     }
-#pragma unroll
-    for (int u = 0; u < B; ++u) cfma(acc, mv[u], xq[u]);
+    return acc;
   }
-  if (G > 1) {
-    // combine the G partial sums of each row (lanes row, row+Rt, ...)
-    C tot = acc;
-    for (int g = 1; g < G; ++g) {
-      const int src = lane + g * L.wr;
-      const auto re = __shfl(acc.x, src < 64 ? src : lane, 64);
-      const auto im = __shfl(acc.y, src < 64 ? src : lane, 64);
-      if (src < 64) { tot.x += re; tot.y += im; }
-    }
-    acc = tot;
+};
+
+// Lanes of a wave on rows [r0, r0 + wr) of a column-major block: lane l takes
+// row r0 + l % wr and the columns g, g + G, ... with g = l / wr, G = 64 / wr.
+// Sums the G partial sums of each row into its group-0 lane (a fixed tree
+// order, so results are bitwise repeatable).
+template <typename C>
+__device__ __forceinline__ C group_sum(C acc, int lane, int wr, int G) {
+  const int grp = lane / wr;
+  for (int off = 1; off < G; off <<= 1) {
+    const int src = lane + off * wr;
+    const auto re = __shfl(acc.x, src < 64 ? src : lane, 64);
+    const auto im = __shfl(acc.y, src < 64 ? src : lane, 64);
+    if ((grp & (2 * off - 1)) == 0 && grp + off < G) { acc.x += re; acc.y += im; }
   }
-  if (L.act && grp == 0) {
-    const C x0 = xv((L.isb ? U.c : 0) + L.i);
-    (L.isb ? z + U.zoutb : z + U.zouta)[L.i] = C{acc.x + x0.x, acc.y + x0.y};
-  }
+  return acc;
 }
 
-// xw[0, c) = zin[0, c) and iw[0, 2c) = io[0, 2c) for c <= 64 NX and
-// 2c <= 64 NI: every load is issued before the first LDS store, so the
-// wave waits on one round trip (a plain strided copy loop waits on each).
-template <int NX, int NI, typename C>
-__device__ __forceinline__ void stage_raw(C *xw, uint16_t *iw, const C *zin, const uint16_t *io,
-                                          int c, int lane) {
-  C xr[NX];
-  uint16_t ir[NI];
-#pragma unroll
-  for (int u = 0; u < NX; ++u) {
-    const int k = lane + 64 * u;
-    xr[u] = k < c ? zin[k] : C{0, 0};
-  }
-#pragma unroll
-  for (int u = 0; u < NI; ++u) {
-    const int k = lane + 64 * u;
-    ir[u] = k < 2 * c ? io[k] : uint16_t(0);
-  }
-#pragma unroll
-  for (int u = 0; u < NX; ++u)
-    if (lane + 64 * u < c) xw[lane + 64 * u] = xr[u];
-#pragma unroll
-  for (int u = 0; u < NI; ++u)
-    if (lane + 64 * u < 2 * c) iw[lane + 64 * u] = ir[u];
-}
-
-// One wave per work item: rows [r0, r0 + 64) of a transfer unit, the pair
-// stacked a then b (the whole unit when it has <= 64 rows).  Items are
-// ordered by decreasing cost, and the factor store holds the units in that
-// order.  Row i of child a is x[ia[i]] + sum_m T_a[i, m] x[ia[ra + m]]
-// (X = [I, T] Pi^T), likewise for b with its own column order ib.  Both
-// gathered inputs are staged in the wave's own LDS slice when 2c <= WX, so
-// the streamed T blocks are the only vector-memory traffic of the loop; the
-// waves of a workgroup do not wait for each other.  Lanes are (row, column
-// group) for units of at most 32 rows and rows otherwise, as in wave_gemv.
-// (A persistent variant, each wave looping over items, measured slower.)
-template <typename R>
-__global__ __launch_bounds__(256) void k_wstage(const WItem *items, int64_t nitems,
-                                                const uint16_t *fidx, const cplx_t<R> *F,
-                                                cplx_t<R> *z) {
+// Forward transfer stage: one wave per work item, rows [r0, r0 + wr) of a
+// unit (the pair stacked a then b; all rows when it has at most 32).  Row i
+// of child a is x[ia[i]] + sum_m T_a[i, m] x[ia[ra + m]] (X = [I, T] Pi^T),
+// likewise for b with its own column order ib.  Lanes take (row, column
+// group) as in group_sum.  A wave loads its descriptor, then at once the
+// unit's first 128 inputs and column-order words and the first batch of T,
+// so the factor stream is in flight while the inputs land in the wave's LDS
+// slice (raw inputs, then the orders ia, ib as 32-bit words).  PERM: the two
+// permuted input lists are then formed LDS to LDS and read directly;
+// otherwise each use reads its input through the order in LDS.  Units whose
+// slice would exceed cap_lds entries gather their inputs from global memory.
+// Items are ordered by decreasing cost, and the factor store holds the units
+// in that order.
+// Forward transfer stage.  Row i of child a of a unit is
+// x[ia[i]] + sum_m T_a[i, m] x[ia[ra + m]] (X = [I, T] Pi^T), likewise for b
+// with its own column order ib.  A work item is rows [r0, r0 + wr) of a unit
+// (the pair stacked a then b; all rows when it has at most 32), one wave,
+// lanes on (row, column group) as in group_sum.  A wave loads the item's
+// descriptor, then at once the unit's first 128 inputs and column-order
+// words and the first batch of T, so that the factor stream is in flight
+// while the raw inputs and the orders ia, ib (as 32-bit words) land in the
+// wave's LDS slice; each use then reads its input through the order in LDS.
+// Units whose inputs and orders would not fit cap_lds entries of the slice
+// gather their inputs from global memory.  Items are ordered by decreasing
+// cost, and the factor store holds the units in that order.  Measured and
+// dropped: the two permuted lists formed in LDS first (slower), persistent
+// waves looping over items with the next descriptor prefetched (slower),
+// the producers scattering their outputs straight into both consumer orders
+// (twice the output writes, scattered: slower).
+template <typename R, int B>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_wstage(
+    const WItem *items, int64_t nitems, const uint16_t *fidx, const cplx_t<R> *F,
+    cplx_t<R> *z, int cap_lds) {
   using C = cplx_t<R>;
-  constexpr int WX = 512;   // LDS entries per wave: both permuted inputs, c <= WX / 2
+  constexpr int WX = HBI_WSTAGE_LDS_BYTES / (int)sizeof(C);   // LDS entries per wave
+  constexpr int NS = 2;   // staging loads per lane issued before T
   __shared__ C xs[4][WX];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t it = (int64_t)blockIdx.x * 4 + wave;
   if (it >= nitems) return;
   const WItem U = items[it];
-  const int c = U.c;
-  const uint16_t *ia = fidx + U.ioff;   // ia, then ib at ia + c
+  const int ra = U.ra, rb = U.rb, c = U.c, Rt = ra + rb;
+  const int wr = Rt <= 32 ? Rt : U.wr;
+  const int G = 64 / wr;
+  const int r0 = Rt <= 32 ? 0 : U.off;
+  const int row = r0 + lane % wr, grp = lane / wr;
+  const bool act = row < Rt && row < r0 + wr && grp < G;
+  const bool isb = row >= ra;
+  const int i = isb ? row - ra : row;
+  const int rc = isb ? rb : ra;
+  const int t = c - rc;
+  const int ob = isb ? c : 0;          // this row's column order: ia or ib
+  const int j0 = ob + rc + grp;        // its first non-skeleton column position
+  const uint16_t *ia = fidx + U.ioff;  // ia, then ib at ia + c (4-byte aligned)
+  const uint32_t *ia32 = (const uint32_t *)ia;
   const C *zin = z + U.zin;
-  const bool lds = 2 * c <= WX;
-  C *xw = xs[wave];
-  const RowLane<C> L = row_lane(U, F + U.foff, lane);
-  if (lds) {
-    // the inputs in their own order and both column orders (three
-    // independent contiguous loads), then the two gathers within LDS:
-    // xw[0, c) = x[ia], xw[c, 2c) = x[ib]
-    uint16_t *iw = (uint16_t *)(xw + c);
-    stage_raw<WX / 128, WX / 64>(xw, iw, zin, ia, c, lane);
-    wave_lds_sync();
-    R ar[WX / 128], ai[WX / 128], br[WX / 128], bi[WX / 128];
+  RowStream<C, B> S;
+  S.T = F + U.foff + (isb ? (int64_t)ra * (c - ra) : 0) + i + (int64_t)grp * rc;
+  S.step = (int64_t)G * rc;
+  S.nt = act && t > grp ? (t - grp + G - 1) / G : 0;
+  const int cw = (4 * c + (int)sizeof(C) - 1) / (int)sizeof(C);   // entries the orders take
+  C acc, x0;
+  if (c + cw <= cap_lds) {
+    C *xw = xs[wave];
+    uint32_t *iw32 = (uint32_t *)(xw + c);
+    const uint16_t *iw = (const uint16_t *)iw32;
+    C xr[NS];
+    uint32_t ir[NS];
 #pragma unroll
-    for (int u = 0; u < WX / 128; ++u) {
-      const int k = lane + 64 * u < c ? lane + 64 * u : 0;
-      const C va = xw[iw[k]], vb = xw[iw[c + k]];
-      ar[u] = va.x; ai[u] = va.y;
-      br[u] = vb.x; bi[u] = vb.y;
-    }
-    wave_lds_sync();
-#pragma unroll
-    for (int u = 0; u < WX / 128; ++u) {
+    for (int u = 0; u < NS; ++u) {
       const int k = lane + 64 * u;
-      if (k < c) {
-        xw[k] = C{ar[u], ai[u]};
-        xw[c + k] = C{br[u], bi[u]};
-      }
+      xr[u] = k < c ? zin[k] : C{0, 0};
+      ir[u] = k < c ? ia32[k] : 0u;
+    }
+    S.issue(0);
+    for (int k = 64 * NS + lane; k < c; k += 64) { xw[k] = zin[k]; iw32[k] = ia32[k]; }
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int k = lane + 64 * u;
+      if (k < c) { xw[k] = xr[u]; iw32[k] = ir[u]; }
     }
     wave_lds_sync();
-    // 8 loads in flight (FP32) or 4 (FP64) keep the registers within 8 (6)
-    // waves per SIMD
-    wstage_rows<C, sizeof(R) == 4 ? 8 : 4>(U, L, lane, [&](int k) { return xw[k]; }, z);
-    return;
-  }
-  // wider units whose raw inputs and both column orders still fit the slice
-  constexpr int CM = WX * (int)sizeof(C) / (int)(sizeof(C) + 2 * sizeof(uint16_t));
-  if (c <= CM) {
-    // gathers through the column orders, both in LDS
-    uint16_t *iw = (uint16_t *)(xw + c);
-    stage_raw<(CM + 63) / 64, (2 * CM + 63) / 64>(xw, iw, zin, ia, c, lane);
-    wave_lds_sync();
-    wstage_rows<C, 4>(U, L, lane, [&](int k) { return xw[iw[k]]; }, z);
+    acc = S.dot([&](int q) { return xw[iw[j0 + q * G]]; });
+    x0 = xw[iw[ob + (act ? i : 0)]];
   } else {
-    // the widest units: inputs gathered from global memory
-    wstage_rows<C, 4>(U, L, lane, [&](int k) { return zin[ia[k]]; }, z);
+    S.issue(0);
+    acc = S.dot([&](int q) { return zin[ia[j0 + q * G]]; });
+    x0 = zin[ia[ob + (act ? i : 0)]];
   }
+  acc = group_sum(acc, lane, wr, G);
+  if (act && grp == 0) (isb ? z + U.zoutb : z + U.zouta)[i] = C{acc.x + x0.x, acc.y + x0.y};
 }
 
 // One workgroup (4 waves) per row leaf: wave w accumulates the K^L blocks
@@ -483,6 +456,8 @@ hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
     if (hook) hook->before(name, elems * esz + idx);
   };
   auto post = [&]() { if (hook) hook->after(); };
+  // factor loads per batch of the transfer stages (64 VGPRs: 8 waves/SIMD)
+  constexpr int WB = sizeof(R) == 4 ? 8 : 4;
   if (!adjoint) {
     if (ap.Lv > 0) {
       pre("k_vstage", ap.v_elems, ap.v_idx);
@@ -495,8 +470,8 @@ hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
       if (nu == 0) continue;
       const int64_t ni = ap.nitems[k];
       pre("k_wstage", ap.w_elems[k], ap.w_idx[k]);
-      hipLaunchKernelGGL((k_wstage<R>), dim3((ni + 3) / 4), dim3(256), 0, st,
-                         ap.items[k], ni, ap.fidx, Fc, zc);
+      hipLaunchKernelGGL((k_wstage<R, WB>), dim3((ni + 3) / 4), dim3(256), 0, st, ap.items[k],
+                         ni, ap.fidx, Fc, zc, ap.cap_lds);
       post();
     }
     pre("k_final", ap.f_elems, ap.f_idx);

@@ -37,6 +37,10 @@ struct ApplyPlan {
   std::vector<int64_t> nunits;
   std::vector<const WItem *> items, items_adj;   // index k
   std::vector<int64_t> nitems, nitems_adj;
+  // forward transfer items stage their inputs and column orders in the
+  // wave's LDS slice when they need at most cap_lds entries of it, else
+  // gather the inputs from global memory
+  int cap_lds = 0;
   // algorithmic traffic per launch, in complex elements and index bytes
   double v_elems = 0, v_idx = 0, f_elems = 0, f_idx = 0;
   std::vector<double> w_elems, w_idx;   // index k

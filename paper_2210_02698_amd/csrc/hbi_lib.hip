@@ -254,6 +254,10 @@ struct hbi_ctx {
   int64_t ztotal = 0;
   int64_t zalloc = 0;   // entries of z_d (the per-level vectors of one single-RHS product)
   DevBuf z_d;
+  // forward transfer items with inputs staged in LDS / gathered from global
+  // memory, and those on 16-row windows
+  int64_t wst_lds = 0, wst_global = 0, wst_wide = 0;
+  int32_t wst_cq[5] = {0, 0, 0, 0, 0};   // unit widths c: min, quartiles, max
   // curve inclusion (2D): segments at positions [Nv, Nv + inc_ns) of the
   // per-point arrays; inputs on the host and the device, and the dense
   // operators built with the factors
@@ -325,7 +329,7 @@ struct hbi_ctx {
     inc_part3.release();
     inc_plan = InclusionPlan(); t_inc = 0;
     leaves_h.clear(); vd_h.clear(); kd_h.clear(); units_h.clear(); batch.reset(); ztotal = 0; zalloc = 0;
-    z_d.release();
+    z_d.release(); wst_lds = wst_global = wst_wide = 0;
     build_gen = 0;
     nnz_v = nnz_w = nnz_k = nnz_d = entries_eval = nid = 0; rank_max = 0; rank_sum = 0;
     t_prep = t_wait = t_compact = 0; entry_slots = 0;
@@ -884,6 +888,19 @@ struct HcCacheScope {
   ~HcCacheScope() { c->hc_cache.release(); c->hc_nbox = 0; }
 };
 
+int env_int(const char *name, int def) {
+  const char *e = std::getenv(name);
+  if (!e || !*e) return def;
+  char *end = nullptr;
+  const long v = std::strtol(e, &end, 10);
+  return (end && *end == 0) ? (int)v : def;
+}
+
+// Units with more candidate columns than this get forward windows of 16
+// rows, four lanes a row (HBI_WSTAGE_WIDE_C, default 256).
+int wide_columns() { return env_int("HBI_WSTAGE_WIDE_C", 256); }
+int window_rows(const WUnit &U, int wide_c) { return U.c > wide_c && U.ra + U.rb > 32 ? 16 : 64; }
+
 // Final layout of the factor store.  The build leaves its blocks in chunks
 // in production order; the store places each block where its apply kernel
 // streams it, so that waves running at the same time read neighbouring
@@ -898,6 +915,7 @@ std::vector<PlaceDesc> layout_store(const std::vector<Chunk> &chunks, int Lv, in
                                     std::vector<VDesc> &vd, std::vector<KDesc> &kd,
                                     std::vector<LeafInfo> &leaves,
                                     std::vector<std::vector<WUnit>> &units, int64_t Fg) {
+  const int wide_c = wide_columns();
   // chunks are in store order (appended as the store grows)
   auto src = [&](int64_t off, int64_t n) -> const double2 * {
     auto it = std::upper_bound(chunks.begin(), chunks.end(), off,
@@ -925,7 +943,7 @@ std::vector<PlaceDesc> layout_store(const std::vector<Chunk> &chunks, int Lv, in
     std::vector<std::pair<int64_t, int32_t>> ord(us.size());
     for (size_t u = 0; u < us.size(); ++u) {
       const int Rt = us[u].ra + us[u].rb;
-      const int wr = us[u].c > 256 && Rt > 32 ? 16 : 64;   // as the work items
+      const int wr = window_rows(us[u], wide_c);   // as the work items
       ord[u] = {(int64_t)std::min(Rt, wr) * us[u].c, (int32_t)u};
     }
     std::stable_sort(ord.begin(), ord.end(), [](const std::pair<int64_t, int32_t> &a,
@@ -947,6 +965,131 @@ std::vector<PlaceDesc> layout_store(const std::vector<Chunk> &chunks, int Lv, in
   }
   if (cur != Fg) throw Error{HBI_ERR_NUMERIC, "internal layout error: factor store size"};
   return out;
+}
+
+// The apply plan of a finished build: descriptors on the device, the work
+// items of every transfer stage, and the algorithmic traffic of each launch.
+void make_apply_plan(hbi_ctx *c, std::vector<LeafInfo> &leaves, std::vector<VDesc> &vd,
+                     std::vector<KDesc> &kd, std::vector<std::vector<WUnit>> &units, int Lv,
+                     int Lmax) {
+  const int64_t nleaf = (int64_t)leaves.size();
+  const int wide_c = wide_columns();
+  // LDS entries of one forward wave for a unit of c columns: the raw inputs
+  // and both column orders (4 bytes per column)
+  const int esz = c->prec == HBI_F64 ? 16 : 8;
+  const int lds_max = HBI_WSTAGE_LDS_BYTES / esz;
+  const int cap_lds = std::max(0, std::min(env_int("HBI_WSTAGE_LDS_CAP", lds_max), lds_max));
+  auto slice = [&](int cc) { return cc + (4 * cc + esz - 1) / esz; };
+  for (int k = 1; k <= Lmax; ++k)
+    for (const WUnit &U : units[k])
+      if (U.ioff % 2 != 0) throw Error{HBI_ERR_NUMERIC, "internal layout error: index alignment"};
+  upload(c->leaves_d, leaves);
+  upload(c->vd_d, vd);
+  upload(c->kd_d, kd);
+  c->leaves_h = leaves;
+  c->vd_h = vd;
+  c->kd_h = kd;
+  c->units_h = units;
+  c->units_d.clear();
+  c->units_d.resize(Lmax + 1);
+  c->plan = ApplyPlan();
+  ApplyPlan &ap = c->plan;
+  ap.Lv = Lv;
+  ap.Lmax = Lv >= 1 ? Lmax : 0;
+  ap.nleaf = nleaf;
+  ap.leaves = c->leaves_d.as<LeafInfo>();
+  ap.perm = c->perm_d.as<int32_t>();
+  ap.vd = c->vd_d.as<VDesc>();
+  ap.kd = c->kd_d.as<KDesc>();
+  ap.fidx = c->Fi.as<uint16_t>();
+  ap.cap_lds = cap_lds;
+  ap.units.assign(Lmax + 1, nullptr);
+  ap.nunits.assign(Lmax + 1, 0);
+  c->items_d.clear();
+  c->items_d.resize(Lmax + 1);
+  c->items_adj_d.clear();
+  c->items_adj_d.resize(Lmax + 1);
+  ap.items.assign(Lmax + 1, nullptr);
+  ap.items_adj.assign(Lmax + 1, nullptr);
+  ap.nitems.assign(Lmax + 1, 0);
+  ap.nitems_adj.assign(Lmax + 1, 0);
+  ap.w_elems.assign(Lmax + 1, 0.0);
+  ap.w_idx.assign(Lmax + 1, 0.0);
+  c->wst_lds = c->wst_global = c->wst_wide = 0;
+  for (int k = 1; k <= Lmax; ++k) {
+    upload(c->units_d[k], units[k]);
+    ap.units[k] = c->units_d[k].as<WUnit>();
+    ap.nunits[k] = (int64_t)units[k].size();
+    // forward: windows of 64 (or 16) rows of every unit; adjoint: windows
+    // of 64 columns; heaviest first so the long items do not form the tail
+    std::vector<std::pair<int64_t, WItem>> fw, bw;
+    for (int32_t u = 0; u < (int32_t)units[k].size(); ++u) {
+      const WUnit &U = units[k][u];
+      const int Rt = U.ra + U.rb;
+      const int wr = window_rows(U, wide_c);
+      auto item = [&U](int32_t off, int32_t w) {
+        return WItem{U.foff, U.zin, U.zouta, U.zoutb, U.ioff, U.ra, U.rb, U.c, (int16_t)off,
+                     (int16_t)w};
+      };
+      for (int r0 = 0; r0 < Rt; r0 += wr) {
+        const int r1 = Rt <= 32 ? Rt : std::min(Rt, r0 + wr);
+        fw.push_back({(int64_t)(r1 - r0) * U.c, item(Rt <= 32 ? 0 : r0, wr)});
+        if (slice(U.c) <= cap_lds) ++c->wst_lds; else ++c->wst_global;
+        if (wr == 16) ++c->wst_wide;
+        if (Rt <= 32) break;
+      }
+      for (int c0 = 0; c0 < U.c; c0 += 64)
+        bw.push_back({(int64_t)std::min(64, U.c - c0) * Rt, item(c0, 64)});
+      // traffic of the unit: T of both children, its c inputs and Rt
+      // outputs; the two column orders the inputs are gathered through
+      ap.w_elems[k] += (double)U.ra * (U.c - U.ra) + (double)U.rb * (U.c - U.rb) + U.c + Rt;
+      ap.w_idx[k] += 2.0 * sizeof(uint16_t) * U.c;
+    }
+    auto order = [](std::vector<std::pair<int64_t, WItem>> &v) {
+      std::stable_sort(v.begin(), v.end(), [](const std::pair<int64_t, WItem> &a,
+                                              const std::pair<int64_t, WItem> &b) {
+        return a.first > b.first;
+      });
+      std::vector<WItem> out(v.size());
+      for (size_t q = 0; q < v.size(); ++q) out[q] = v[q].second;
+      return out;
+    };
+    upload(c->items_d[k], order(fw));
+    upload(c->items_adj_d[k], order(bw));
+    ap.items[k] = c->items_d[k].as<WItem>();
+    ap.items_adj[k] = c->items_adj_d[k].as<WItem>();
+    ap.nitems[k] = (int64_t)fw.size();
+    ap.nitems_adj[k] = (int64_t)bw.size();
+    ap.w_idx[k] += (double)sizeof(WItem) * ap.nitems[k];
+  }
+  {
+    std::vector<int32_t> cs;
+    for (int k = 1; k <= Lmax; ++k)
+      for (const WUnit &U : units[k]) cs.push_back(U.c);
+    std::sort(cs.begin(), cs.end());
+    for (int q = 0; q < 5; ++q)
+      c->wst_cq[q] = cs.empty() ? 0 : cs[std::min(cs.size() - 1, (size_t)(q * (cs.size() - 1) / 4))];
+  }
+  // traffic of the V^0 and final launches (complex elements + index bytes)
+  double ve = 0, vi = 0, fe = 0, fi = 0;
+  for (int64_t g = 0; g < nleaf; ++g) {
+    const double sz = leaves[g].size;
+    vi += sizeof(LeafInfo) + 4.0 * sz;
+    fi += sizeof(LeafInfo) + 4.0 * sz;
+    if (Lv > 0) ve += sz;                 // s read by the V stage
+    fe += sz * sz + 2.0 * sz;             // dense leaf, s read, u written
+    for (int l = 0; l < Lv; ++l) {
+      const VDesc &v = vd[g * Lv + l];
+      const KDesc &q = kd[g * Lv + l];
+      ve += (double)v.r * (sz - v.r) + v.r;
+      fe += (double)q.r * sz + q.r;
+      vi += sizeof(VDesc) + sizeof(uint16_t) * sz;   // descriptor, column order
+      fi += sizeof(KDesc);
+    }
+  }
+  ap.v_elems = ve; ap.v_idx = vi; ap.f_elems = fe; ap.f_idx = fi;
+  c->zalloc = c->ztotal;
+  HBI_HIP(c->z_d.alloc((size_t)esz * std::max<int64_t>(c->zalloc, 1)));
 }
 
 void build_factors(hbi_ctx *c, double tol) {
@@ -1364,109 +1507,7 @@ void build_factors(hbi_ctx *c, double tol) {
     HBI_HIP(hipStreamSynchronize(c->stream));
   }
   chunks.clear();
-  upload(c->leaves_d, leaves);
-  upload(c->vd_d, vd);
-  upload(c->kd_d, kd);
-  c->leaves_h = leaves;
-  c->vd_h = vd;
-  c->kd_h = kd;
-  c->units_h = units;
-  c->units_d.clear();
-  c->units_d.resize(Lmax + 1);
-  c->plan = ApplyPlan();
-  c->plan.Lv = Lv;
-  c->plan.Lmax = Lv >= 1 ? Lmax : 0;
-  c->plan.nleaf = nleaf;
-  c->plan.leaves = c->leaves_d.as<LeafInfo>();
-  c->plan.perm = c->perm_d.as<int32_t>();
-  c->plan.vd = c->vd_d.as<VDesc>();
-  c->plan.kd = c->kd_d.as<KDesc>();
-  c->plan.fidx = c->Fi.as<uint16_t>();
-  c->plan.units.assign(Lmax + 1, nullptr);
-  c->plan.nunits.assign(Lmax + 1, 0);
-  c->items_d.clear();
-  c->items_d.resize(Lmax + 1);
-  c->items_adj_d.clear();
-  c->items_adj_d.resize(Lmax + 1);
-  c->plan.items.assign(Lmax + 1, nullptr);
-  c->plan.items_adj.assign(Lmax + 1, nullptr);
-  c->plan.nitems.assign(Lmax + 1, 0);
-  c->plan.nitems_adj.assign(Lmax + 1, 0);
-  for (int k = 1; k <= Lmax; ++k) {
-    upload(c->units_d[k], units[k]);
-    c->plan.units[k] = c->units_d[k].as<WUnit>();
-    c->plan.nunits[k] = (int64_t)units[k].size();
-    // work items: 64-row (forward) / 64-column (adjoint) windows of every
-    // unit, heaviest first so the long items do not form the tail
-    std::vector<std::pair<int64_t, WItem>> fw, bw;
-    for (int32_t u = 0; u < (int32_t)units[k].size(); ++u) {
-      const WUnit &U = units[k][u];
-      const int Rt = U.ra + U.rb;
-      auto item = [&U](int32_t off, int32_t wr) {
-        return WItem{U.foff, U.zin, U.zouta, U.zoutb, U.ioff, U.ra, U.rb, U.c, (int16_t)off,
-                     (int16_t)wr};
-      };
-      // units with long rows (c > 256) get 16-row windows, four lanes a row
-      const int wr = U.c > 256 && Rt > 32 ? 16 : 64;
-      if (Rt <= wr) {
-        fw.push_back({(int64_t)Rt * U.c, item(0, wr)});
-      } else {
-        for (int r0 = 0; r0 < Rt; r0 += wr)
-          fw.push_back({(int64_t)std::min(wr, Rt - r0) * U.c, item(r0, wr)});
-      }
-      for (int c0 = 0; c0 < U.c; c0 += 64)
-        bw.push_back({(int64_t)std::min(64, U.c - c0) * Rt, item(c0, 64)});
-    }
-    auto order = [](std::vector<std::pair<int64_t, WItem>> &v) {
-      std::stable_sort(v.begin(), v.end(), [](const std::pair<int64_t, WItem> &a,
-                                              const std::pair<int64_t, WItem> &b) {
-        return a.first > b.first;
-      });
-      std::vector<WItem> out(v.size());
-      for (size_t q = 0; q < v.size(); ++q) out[q] = v[q].second;
-      return out;
-    };
-    upload(c->items_d[k], order(fw));
-    upload(c->items_adj_d[k], order(bw));
-    c->plan.items[k] = c->items_d[k].as<WItem>();
-    c->plan.items_adj[k] = c->items_adj_d[k].as<WItem>();
-    c->plan.nitems[k] = (int64_t)fw.size();
-    c->plan.nitems_adj[k] = (int64_t)bw.size();
-  }
-  // algorithmic traffic per launch (complex elements + index bytes)
-  {
-    ApplyPlan &ap = c->plan;
-    ap.w_elems.assign(Lmax + 1, 0.0);
-    ap.w_idx.assign(Lmax + 1, 0.0);
-    double ve = 0, vi = 0, fe = 0, fi = 0;
-    for (int64_t g = 0; g < nleaf; ++g) {
-      const double sz = leaves[g].size;
-      vi += sizeof(LeafInfo) + 4.0 * sz;
-      fi += sizeof(LeafInfo) + 4.0 * sz;
-      if (Lv > 0) ve += sz;                 // s read by the V stage
-      fe += sz * sz + 2.0 * sz;             // dense leaf, s read, u written
-      for (int l = 0; l < Lv; ++l) {
-        const VDesc &v = vd[g * Lv + l];
-        const KDesc &q = kd[g * Lv + l];
-        ve += (double)v.r * (sz - v.r) + v.r;
-        fe += (double)q.r * sz + q.r;
-        vi += sizeof(VDesc) + sizeof(uint16_t) * sz;   // descriptor, column order
-        fi += sizeof(KDesc);
-      }
-    }
-    ap.v_elems = ve; ap.v_idx = vi; ap.f_elems = fe; ap.f_idx = fi;
-    for (int k = 1; k <= Lmax; ++k) {
-      for (const WUnit &U : units[k])
-        ap.w_elems[k] += (double)U.ra * (U.c - U.ra) + (double)U.rb * (U.c - U.rb) + U.c +
-                         U.ra + U.rb;
-      // descriptors, and the two column orders (uint16) a unit's inputs are
-      // gathered through
-      ap.w_idx[k] = (double)sizeof(WItem) * ap.nitems[k];
-      for (const WUnit &U : units[k]) ap.w_idx[k] += 2.0 * sizeof(uint16_t) * U.c;
-    }
-  }
-  c->zalloc = c->ztotal;
-  HBI_HIP(c->z_d.alloc(esz * std::max<int64_t>(c->zalloc, 1)));
+  make_apply_plan(c, leaves, vd, kd, units, Lv, Lmax);
   c->t_final = now_s() - tf;
   c->t_host = t_host;
   c->t_gpu = t_gpu;
@@ -2000,6 +2041,13 @@ double apply_index_bytes(const ApplyPlan &ap) {
   for (double w : ap.w_idx) b += w;
   return b;
 }
+// Algorithmic bytes of one forward single-RHS product: factor entries,
+// vectors read and written, index lists, positions and descriptors.
+double apply_bytes(const ApplyPlan &ap, double esz) {
+  double e = ap.v_elems + ap.f_elems;
+  for (double w : ap.w_elems) e += w;
+  return e * esz + apply_index_bytes(ap);
+}
 // Bytes of the inclusion operators one apply streams: G twice (the
 // K^{v2s} gather and the K^{s2v} scatter), (K^{s2s})^{-1} once, and the
 // cell vectors read and written.
@@ -2397,7 +2445,9 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       "\"build_compact_s\": %.6f, \"build_finalize_s\": %.6f, "
       "\"inclusion_ns\": %d, \"inclusion_bytes\": %lld, \"build_inclusion_s\": %.6f, "
       "\"apply_index_bytes\": %.0f, \"inclusion_apply_bytes\": %.0f, "
-      "\"apply_scratch_bytes\": %lld}",
+      "\"apply_scratch_bytes\": %lld, \"apply_bytes\": %.0f, \"wstage_items_lds\": %lld, "
+      "\"wstage_items_global\": %lld, \"wstage_items_wide\": %lld, \"wstage_cap_lds\": %d, "
+      "\"wstage_form\": %d, \"wstage_c_quantiles\": [%d, %d, %d, %d, %d]}",
       ctx->state, ctx->dim, (long long)Nv, ctx->geo.Lv, ctx->NT, ctx->nI,
       ctx->prec == HBI_F64 ? "f64" : "f32", ctx->tol, ctx->chi(), ctx->leaf(),
       (long long)ctx->nnz_v, (long long)ctx->nnz_w, (long long)ctx->nnz_k, (long long)ctx->nnz_d,
@@ -2414,7 +2464,10 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       ctx->t_final, ctx->inc_ns,
       (long long)(ctx->inc_G.n + ctx->inc_M.n + ctx->inc_MH.n), ctx->t_inc,
       apply_index_bytes(ctx->plan), inclusion_apply_bytes(ctx),
-      (long long)(ctx->zalloc * (int64_t)esz));
+      (long long)(ctx->zalloc * (int64_t)esz), apply_bytes(ctx->plan, (double)esz),
+      (long long)ctx->wst_lds, (long long)ctx->wst_global, (long long)ctx->wst_wide,
+      ctx->plan.cap_lds, ctx->wst_cq[0], ctx->wst_cq[1], ctx->wst_cq[2],
+      ctx->wst_cq[3], ctx->wst_cq[4]);
   if (len < 0 || len >= cap) { ctx->err = "output buffer too small"; return HBI_ERR_ARG; }
   std::memcpy(json, buf, len + 1);
   return HBI_OK;

@@ -433,3 +433,58 @@ def test_inverse_source_gradient_bump256(torch_mod, prec):
             an = (np.conj(unit) * grad[j]).real
             assert abs(fd - an) <= 1e-3 * scale + 1e-4 * abs(fd), (j, unit, fd, an)
     op.close()
+
+
+@pytest.mark.parametrize("prec,tol,bound", [("f64", 1e-7, 1e-6), ("f32", 1e-5, 1e-4)])
+def test_transfer_stage_branches(torch_mod, monkeypatch, prec, tol, bound):
+    """The forward transfer stage has three kinds of work item: 64-row
+    windows whose inputs and column orders are staged in the wave's LDS
+    slice, the same with the inputs gathered from global memory (units
+    wider than the slice, HBI_WSTAGE_LDS_CAP entries), and
+    16-row windows with four lanes a row for units of more than
+    HBI_WSTAGE_WIDE_C columns.  Thresholds taken from the unit widths of the
+    default build make all of them occur on a 128^2 bump; the build
+    statistics count the items of each kind, and the product matches the
+    oracle and the default plan."""
+    torch = torch_mod
+    prob = hb_inputs.configs.c2(128, nbox=4)
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    s = hb_inputs.complex_normal(prob.Nv, [13, 5])
+    rows = np.sort(np.random.default_rng([13, 6]).choice(prob.Nv, 96, replace=False))
+    ref = oracle.apply(prob, s, rows)
+    say(f"transfer branches {prec} default plan")
+    op = make_op(prob, tol=tol, prec=prec)
+    info0 = op.info()
+    u0 = op.apply(to_dev(torch, s, dt)).cpu().numpy()
+    op.close()
+    assert info0["wstage_items_lds"] > 0 and info0["wstage_items_global"] == 0, info0
+    check(u0[rows], ref, bound, f"default plan {prec}")
+    # the median width goes to the global gathers, the widest quarter to
+    # 16-row windows
+    cq = info0["wstage_c_quantiles"]
+    esz = 16 if prec == "f64" else 8
+    per_c = 1 + 4.0 / esz     # slice entries per column: input and two orders
+    cap = int(per_c * cq[2]) - 1
+    wide = cq[3] - 1
+    monkeypatch.setenv("HBI_WSTAGE_LDS_CAP", str(cap))
+    monkeypatch.setenv("HBI_WSTAGE_WIDE_C", str(wide))
+    say(f"transfer branches {prec}: widths {cq}, cap {cap}, wide above {wide}")
+    op = make_op(prob, tol=tol, prec=prec)
+    info = op.info()
+    say(f"items: lds {info['wstage_items_lds']} global {info['wstage_items_global']} "
+        f"wide {info['wstage_items_wide']}")
+    assert info["wstage_cap_lds"] == cap
+    for kind in ("lds", "global", "wide"):
+        assert info[f"wstage_items_{kind}"] > 0, kind
+    assert info["nnz_total"] == info0["nnz_total"]
+    u = op.apply(to_dev(torch, s, dt)).cpu().numpy()
+    check(u[rows], ref, bound, f"forced branches {prec}")
+    # same factors, other work items: equal up to the order of the sums
+    assert rel(u, u0) < (1e-13 if prec == "f64" else 1e-5)
+    # the adjoint is untouched by the forward plan
+    y = hb_inputs.complex_normal(prob.Nv, [13, 7])
+    Kx = op.apply(to_dev(torch, s, dt)).cpu().numpy().astype(np.complex128)
+    KHy = op.apply_adjoint(to_dev(torch, y, dt)).cpu().numpy().astype(np.complex128)
+    lhs, rhs = np.vdot(y, Kx), np.vdot(KHy, s)
+    assert abs(lhs - rhs) <= (1e-12 if prec == "f64" else 1e-5) * abs(lhs)
+    op.close()
