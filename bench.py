@@ -25,7 +25,8 @@ the rows it computes are the parity references.  Also the C1 workload
 (2D homogeneous, 64^2 cells) as a full dense oracle apply and as a
 stored-dense K @ s product on all workers' cores.
 
---workload picks one workload alone (bump, batched, 3d, sweep, inclusion).
+--workload picks one workload alone (bump, batched, 3d, sweep, inclusion), or
+the complexity sweep (storage and build time over sizes).
 """
 from __future__ import annotations
 
@@ -615,6 +616,53 @@ def run_inclusion(args):
     op.close()
 
 
+def run_complexity(args):
+    """Storage and build time across sizes at 8 cells per wavelength: the 2D
+    Gaussian bump on 128^2 .. 1024^2 cells (FP64, tol 1e-7) and the 3D
+    sinusoid on 16^3 .. 64^3 cells (FP32, tol 1e-6), against the
+    O(N_v log^2 N_v) storage of the paper's complexity statement."""
+    import torch
+    import hb_inputs
+    import paper_2210_02698_amd as hbi
+    ensure_lib()
+    out = {"workload": "complexity sweep: storage and build time against N_v log2^2 N_v",
+           "2d": [], "3d": []}
+    cases = [("2d", s, hb_inputs.configs.c2(s), "f64", 1e-7) for s in (128, 256, 512, 1024)]
+    cases += [("3d", s, hb_inputs.configs.c5(s), "f32", 1e-6) for s in (16, 32, 48, 64)]
+    for kind, side, prob, prec, tol in cases:
+        op = hbi.Operator(prob, device=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op.build(tol=tol, prec=prec)
+        torch.cuda.synchronize()
+        bs = time.perf_counter() - t0
+        info = op.info()
+        op.close()
+        n = prob.Nv
+        l2 = math.log2(n) ** 2
+        rec = {"side": side, "N_v": n, "prec": prec, "tol": tol, "nnz_total": info["nnz_total"],
+               "nnz_per_cell": round(info["nnz_total"] / n, 2),
+               "nnz_per_cell_over_log2sq": round(info["nnz_total"] / n / l2, 4),
+               "build_s": round(bs, 3), "build_us_per_cell_over_log2sq": round(bs / n / l2 * 1e6, 5),
+               "rank_max": info["rank_max"], "rank_mean": info["rank_mean"]}
+        out[kind].append(rec)
+        log(f"complexity {kind} {side}: {rec}")
+        torch.cuda.empty_cache()
+    for kind in ("2d", "3d"):
+        r = out[kind]
+        # growth exponents between the smallest and largest size
+        a, b = r[0], r[-1]
+        out[kind + "_fit"] = {
+            "nnz_exponent": round(math.log(b["nnz_total"] / a["nnz_total"]) /
+                                  math.log(b["N_v"] / a["N_v"]), 4),
+            "build_exponent": round(math.log(b["build_s"] / a["build_s"]) /
+                                    math.log(b["N_v"] / a["N_v"]), 4),
+            "n_log2sq_exponent": round(math.log(b["N_v"] * math.log2(b["N_v"]) ** 2 /
+                                                (a["N_v"] * math.log2(a["N_v"]) ** 2)) /
+                                       math.log(b["N_v"] / a["N_v"]), 4)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -632,13 +680,15 @@ def main():
     ap.add_argument("--rows-3d", type=int, default=512)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=["all", "bump", "batched", "3d", "sweep", "inclusion"],
+    ap.add_argument("--workload", choices=["all", "bump", "batched", "3d", "sweep", "inclusion",
+                                           "complexity"],
                     default="all",
                     help="all: the headline bump line with the batched and 3d workloads beside "
                          "it; bump: the 1024^2 single-RHS apply alone; batched: 64 "
                          "constant-gradient problems with 1-256 RHS each; 3d: 64^3 sinusoid "
                          "with 32 RHS; sweep: four frequencies from one table set, 16 RHS "
-                         "each; inclusion: 256^2 bump with an open-square curve inclusion")
+                         "each; inclusion: 256^2 bump with an open-square curve inclusion; "
+                         "complexity: storage and build time over sizes")
     ap.add_argument("--nprob", type=int, default=64)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
@@ -652,6 +702,8 @@ def main():
         return run_inclusion(args)
     if args.workload == "sweep":
         return run_sweep(args)
+    if args.workload == "complexity":
+        return run_complexity(args)
 
     # CPU phase (no GPU touched yet): inputs, then the oracle on the pool
     want = {"all": ("bump", "batched", "3d", "c1")}.get(args.workload, (args.workload,))

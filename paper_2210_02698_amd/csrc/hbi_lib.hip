@@ -75,6 +75,15 @@ void setup_scratch(int device) {
 }
 
 
+// Test hook: with HBI_FAIL_ALLOC_BYTES=X set, every device allocation of at
+// least X bytes fails as out of memory (the error paths of HBI_ERR_OOM).
+bool forced_oom(size_t bytes) {
+  const char *e = std::getenv("HBI_FAIL_ALLOC_BYTES");
+  if (!e || !*e) return false;
+  const unsigned long long x = std::strtoull(e, nullptr, 10);
+  return x > 0 && bytes >= x;
+}
+
 struct DevBuf {
   void *p = nullptr;
   size_t n = 0;
@@ -95,6 +104,7 @@ struct DevBuf {
   hipError_t alloc(size_t bytes) {
     release();
     if (bytes == 0) return hipSuccess;
+    if (forced_oom(bytes)) return hipErrorOutOfMemory;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) { p = nullptr; (void)hipGetLastError(); return e; }
     n = bytes;
@@ -275,7 +285,7 @@ struct hbi_ctx {
   std::vector<VDesc> vd_h;
   std::vector<KDesc> kd_h;
   std::vector<std::vector<WUnit>> units_h;
-  std::shared_ptr<BatchCache> batch;
+  std::shared_ptr<BatchCache> batch, batch_adj;   // forward / adjoint graphs
   uint64_t build_gen = 0;   // g_build_gen of the current factors (0: none)
   // statistics
   double t_build = 0, t_geo = 0, t_host = 0, t_gpu = 0, t_final = 0;
@@ -328,7 +338,8 @@ struct hbi_ctx {
     inc_part.release(); inc_z.release(); inc_y.release(); inc_part2.release();
     inc_part3.release();
     inc_plan = InclusionPlan(); t_inc = 0;
-    leaves_h.clear(); vd_h.clear(); kd_h.clear(); units_h.clear(); batch.reset(); ztotal = 0; zalloc = 0;
+    leaves_h.clear(); vd_h.clear(); kd_h.clear(); units_h.clear(); batch.reset(); batch_adj.reset(); ztotal = 0;
+    zalloc = 0;
     z_d.release(); wst_lds = wst_global = wst_wide = 0;
     build_gen = 0;
     nnz_v = nnz_w = nnz_k = nnz_d = entries_eval = nid = 0; rank_max = 0; rank_sum = 0;
@@ -1694,6 +1705,7 @@ struct BatchCache {
   std::vector<void *> u_ptr;
   std::vector<int64_t> ld;
   int prec = 0, nb = 4;
+  bool adj = false;   // the conjugate-transpose product
   std::vector<MultiJob> jobs;
   std::vector<MultiPass> passes;
   DevBuf ws;
@@ -1872,6 +1884,96 @@ void build_items(BatchCache &B, int nb) {
   B.nb = nb;
 }
 
+// Work items of the adjoint product for `nb` column tiles per wave: the
+// K^L part, the transfer units from the top level down, then every leaf's
+// D^H and V^H parts (scaled by h^d); the inputs are gathered unscaled.
+void build_items_adj(BatchCache &B, int nb) {
+  const size_t esz = B.prec == HBI_F64 ? 16 : 8;
+  char *ws = B.ws.as<char>();
+  for (auto &P : B.passes) {
+    P.stages.clear();
+    P.bufs.clear();
+    P.jin.clear();
+    P.jout.clear();
+    P.maxNv = 0;
+    P.maxjt = 0;
+    int Lmax = 0;
+    std::vector<MFAItem> ki;
+    std::vector<MVAItem> li;
+    for (int q : P.jobs) {
+      const MultiJob &J = B.jobs[q];
+      hbi_ctx *c = J.c;
+      const char *F = c->F.as<char>();
+      char *xt = ws + J.xt_off * esz, *yt = ws + J.yt_off * esz, *zb = ws + J.z_off * esz;
+      const int Lv = c->geo.Lv;
+      Lmax = std::max(Lmax, c->plan.Lmax);
+      P.maxNv = std::max(P.maxNv, c->geo.Nv);
+      P.maxjt = std::max(P.maxjt, J.Np / 16);
+      const int ngrp = (J.Np / 16 + nb - 1) / nb;
+      const double hd = std::pow(c->h, c->dim);
+      for (int64_t g = 0; g < (int64_t)c->leaves_h.size(); ++g) {
+        const LeafInfo &lf = c->leaves_h[g];
+        const char *y = xt + (int64_t)lf.start * J.Np * esz;
+        for (int l = 0; l < Lv; ++l) {
+          const KDesc &d = c->kd_h[g * Lv + l];
+          for (int r0 = 0; r0 < d.r; r0 += 16)
+            for (int gq = 0; gq < ngrp; ++gq)
+              ki.push_back(MFAItem{F + d.foff * esz, y, zb + d.zin * J.Np * esz, d.r, lf.size, r0,
+                                   gq * nb, J.Np, 0});
+        }
+        for (int r0 = 0; r0 < lf.size; r0 += 16)
+          for (int gq = 0; gq < ngrp; ++gq)
+            li.push_back(MVAItem{F, c->Fi.as<uint16_t>(), y, yt + (int64_t)lf.start * J.Np * esz,
+                                 c->vd_d.as<VDesc>() + g * Lv, zb, lf.dense_off, hd, lf.size, Lv,
+                                 r0, gq * nb, J.Np, 0});
+      }
+      const size_t cofs = (size_t)J.j0 * esz;
+      P.jin.push_back(MTrans{(const char *)B.s_ptr[J.prob] + cofs * B.ld[J.prob], xt,
+                             c->perm_d.as<int32_t>(), c->geo.Nv, B.ld[J.prob], J.nrhs, J.Np, 1.0});
+      P.jout.push_back(MTrans{yt, (char *)B.u_ptr[J.prob] + cofs * B.ld[J.prob],
+                              c->perm_d.as<int32_t>(), c->geo.Nv, B.ld[J.prob], J.nrhs, J.Np, 1.0});
+    }
+    auto add_stage = [&](int kind, const void *data, size_t bytes, int64_t n) {
+      DevBuf d;
+      HBI_HIP(d.alloc(bytes));
+      if (bytes) HBI_HIP(hipMemcpy(d.p, data, bytes, hipMemcpyHostToDevice));
+      P.stages.push_back(MStagePlan{kind, nb, d.p, n});
+      P.bufs.push_back(std::move(d));
+    };
+    add_stage(3, ki.data(), ki.size() * sizeof(MFAItem), (int64_t)ki.size());
+    for (int k = Lmax; k >= 1; --k) {
+      std::vector<std::pair<int64_t, MWAItem>> wi;
+      for (int q : P.jobs) {
+        const MultiJob &J = B.jobs[q];
+        hbi_ctx *c = J.c;
+        if (k > c->plan.Lmax) continue;
+        const char *F = c->F.as<char>();
+        char *zb = ws + J.z_off * esz;
+        const int ngrp = (J.Np / 16 + nb - 1) / nb;
+        const uint16_t *fidx = c->Fi.as<uint16_t>();
+        for (const WUnit &U : c->units_h[k])
+          for (int r0 = 0; r0 < U.c; r0 += 16)
+            for (int gq = 0; gq < ngrp; ++gq)
+              wi.push_back({(int64_t)(U.ra + U.rb),
+                            MWAItem{F + U.foff * esz, fidx + U.ioff, zb + U.zin * J.Np * esz,
+                                    zb + U.zouta * J.Np * esz, zb + U.zoutb * J.Np * esz, U.ra,
+                                    U.rb, U.c, r0, gq * nb, J.Np}});
+      }
+      std::stable_sort(wi.begin(), wi.end(), [](const std::pair<int64_t, MWAItem> &a,
+                                                const std::pair<int64_t, MWAItem> &b) {
+        return a.first > b.first;
+      });
+      std::vector<MWAItem> w(wi.size());
+      for (size_t q = 0; q < wi.size(); ++q) w[q] = wi[q].second;
+      add_stage(4, w.data(), w.size() * sizeof(MWAItem), (int64_t)w.size());
+    }
+    add_stage(5, li.data(), li.size() * sizeof(MVAItem), (int64_t)li.size());
+    upload(P.jin_d, P.jin);
+    upload(P.jout_d, P.jout);
+  }
+  B.nb = nb;
+}
+
 void launch_passes(BatchCache &B, hipStream_t st) {
   for (auto &P : B.passes) {
     if (B.prec == HBI_F64) {
@@ -1941,7 +2043,7 @@ double time_passes(BatchCache &B, int reps) {
 
 void multi_apply(hbi_ctx *c0, const std::vector<hbi_ctx *> &ctxs, const std::vector<const void *> &s,
                  const std::vector<void *> &u, const std::vector<int32_t> &nrhs,
-                 const std::vector<int64_t> &ld) {
+                 const std::vector<int64_t> &ld, bool adj = false) {
   const int prec = ctxs[0]->prec;
   for (size_t p = 0; p < ctxs.size(); ++p) {
     HBI_REQUIRE(ctxs[p] && ctxs[p]->state == 2, HBI_ERR_STATE, "batched apply before build");
@@ -1951,14 +2053,16 @@ void multi_apply(hbi_ctx *c0, const std::vector<hbi_ctx *> &ctxs, const std::vec
   }
   std::vector<uint64_t> gens(ctxs.size());
   for (size_t p = 0; p < ctxs.size(); ++p) gens[p] = ctxs[p]->build_gen;
-  std::shared_ptr<BatchCache> B = c0->batch;
+  std::shared_ptr<BatchCache> &slot = adj ? c0->batch_adj : c0->batch;
+  std::shared_ptr<BatchCache> B = slot;
   const bool same =
       B && B->ctxs == ctxs && B->gens == gens && B->nrhs == nrhs && B->prec == prec;
   if (!same) {
     // the previous graph, if any, finishes and frees its workspace first
     B.reset();
-    c0->batch.reset();
+    slot.reset();
     B = std::make_shared<BatchCache>();
+    B->adj = adj;
     B->ctxs = ctxs;
     B->gens = gens;
     B->nrhs = nrhs;
@@ -1975,7 +2079,9 @@ void multi_apply(hbi_ctx *c0, const std::vector<hbi_ctx *> &ctxs, const std::vec
     // autotune the column-tile width on this batch (cached per process)
     int maxjt = 1;
     for (auto &J : B->jobs) maxjt = std::max(maxjt, J.Np / 16);
-    const std::string key = std::string(prec == HBI_F64 ? "f64" : "f32") + ":jt" + std::to_string(maxjt);
+    const std::string key = std::string(prec == HBI_F64 ? "f64" : "f32") + (adj ? ":adj" : "") +
+                            ":jt" + std::to_string(maxjt);
+    auto items = [&](int nb) { if (adj) build_items_adj(*B, nb); else build_items(*B, nb); };
     auto &tt = tune_table();
     int best = -1;
     // a cached width is used only if it is one of the candidates this batch
@@ -1988,7 +2094,7 @@ void multi_apply(hbi_ctx *c0, const std::vector<hbi_ctx *> &ctxs, const std::vec
       double bt = 1e300;
       for (int nb : {1, 2, 4, 8}) {
         if (nb > 1 && nb > maxjt) break;
-        build_items(*B, nb);
+        items(nb);
         const double t = time_passes(*B, 2);
         if (t < bt) { bt = t; best = nb; }
       }
@@ -1996,12 +2102,12 @@ void multi_apply(hbi_ctx *c0, const std::vector<hbi_ctx *> &ctxs, const std::vec
       tt[key] = best;
       save_tune_table();
     }
-    build_items(*B, best);
+    items(best);
     HBI_HIP(hipStreamBeginCapture(B->gst, hipStreamCaptureModeRelaxed));
     launch_passes(*B, B->gst);
     HBI_HIP(hipStreamEndCapture(B->gst, &B->graph));
     HBI_HIP(hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0));
-    c0->batch = B;
+    slot = B;
   } else if (B->s_ptr != s || B->u_ptr != u || B->ld != ld) {
     // new vector pointers: refresh the gather/scatter job tables
     HBI_HIP(hipStreamSynchronize(B->gst));
@@ -2348,7 +2454,10 @@ hbi_status hbi_apply_noalloc(hbi_ctx *ctx, const void *s, void *u, int32_t nrhs,
 hbi_status hbi_apply_adjoint(hbi_ctx *ctx, const void *s, void *u, int32_t nrhs, int64_t ld) {
   if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
   return guarded(ctx, [&]() {
-    do_apply(ctx, s, u, nrhs, ld, true);
+    if (nrhs >= 2 && !ctx->profiling)
+      multi_apply(ctx, {ctx}, {s}, {u}, {nrhs}, {ld}, true);
+    else
+      do_apply(ctx, s, u, nrhs, ld, true);
     apply_inclusion(ctx, s, u, nrhs, ld, true);
   });
 }
@@ -2447,7 +2556,8 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       "\"apply_index_bytes\": %.0f, \"inclusion_apply_bytes\": %.0f, "
       "\"apply_scratch_bytes\": %lld, \"apply_bytes\": %.0f, \"wstage_items_lds\": %lld, "
       "\"wstage_items_global\": %lld, \"wstage_items_wide\": %lld, \"wstage_cap_lds\": %d, "
-      "\"wstage_form\": %d, \"wstage_c_quantiles\": [%d, %d, %d, %d, %d]}",
+      "\"wstage_c_quantiles\": [%d, %d, %d, %d, %d], \"nnz_per_cell\": %.3f, "
+      "\"nnz_per_cell_over_log2sq\": %.5f}",
       ctx->state, ctx->dim, (long long)Nv, ctx->geo.Lv, ctx->NT, ctx->nI,
       ctx->prec == HBI_F64 ? "f64" : "f32", ctx->tol, ctx->chi(), ctx->leaf(),
       (long long)ctx->nnz_v, (long long)ctx->nnz_w, (long long)ctx->nnz_k, (long long)ctx->nnz_d,
@@ -2467,7 +2577,9 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       (long long)(ctx->zalloc * (int64_t)esz), apply_bytes(ctx->plan, (double)esz),
       (long long)ctx->wst_lds, (long long)ctx->wst_global, (long long)ctx->wst_wide,
       ctx->plan.cap_lds, ctx->wst_cq[0], ctx->wst_cq[1], ctx->wst_cq[2],
-      ctx->wst_cq[3], ctx->wst_cq[4]);
+      ctx->wst_cq[3], ctx->wst_cq[4], Nv ? (double)ctx->Felems / (double)Nv : 0.0,
+      Nv > 1 ? (double)ctx->Felems / (double)Nv / (std::log2((double)Nv) * std::log2((double)Nv))
+             : 0.0);
   if (len < 0 || len >= cap) { ctx->err = "output buffer too small"; return HBI_ERR_ARG; }
   std::memcpy(json, buf, len + 1);
   return HBI_OK;

@@ -45,6 +45,37 @@ struct MFItem {
   int32_t sz, Lv, r0, jt, Np, pad;
 };
 
+// Adjoint items (u = h^d K^H s), in the reverse order of the stages:
+// K^L part: z_l = (K^L)^H y_leaf, rows [r0, r0+16) of the r skeleton rows
+// (K column-major sz x r).
+struct MFAItem {
+  const void *K;
+  const void *y;       // sz x Np leaf inputs
+  void *z;             // r x Np
+  int32_t r, sz, r0, jt, Np, pad;
+};
+// A transfer unit: rows [r0, r0+16) of its c inputs, zin = X_a^H za + X_b^H zb
+// (T_a at T, T_b after it; idx: the unit's lists ia, ib, pa, pb).
+struct MWAItem {
+  const void *T;
+  const uint16_t *idx;
+  void *zin;           // c x Np
+  const void *za, *zb; // ra x Np, rb x Np
+  int32_t ra, rb, c, r0, jt, Np;
+};
+// Leaf part: rows [r0, r0+16) of u_leaf = scale (D^H y + sum_l V_l^H z_l).
+struct MVAItem {
+  const void *F;       // factor store (element offsets in vd, dense_off)
+  const uint16_t *fidx;
+  const void *y;       // sz x Np leaf inputs
+  void *u;             // sz x Np leaf outputs
+  const VDesc *vd;     // Lv descriptors of this leaf
+  const void *z;       // z base of the problem (offsets in vd are rows)
+  int64_t dense_off;
+  double scale;
+  int32_t sz, Lv, r0, jt, Np, pad;
+};
+
 // Gather / scatter between natural column-major vectors and tree-ordered
 // row-major blocks.
 struct MTrans {
@@ -57,7 +88,7 @@ struct MTrans {
 };
 
 struct MStagePlan {
-  int kind;            // 0 V, 1 W, 2 final
+  int kind;            // 0 V, 1 W, 2 final; adjoint: 3 K^L, 4 W, 5 leaf
   int nb;              // column tiles per wave
   const void *items;
   int64_t n;

@@ -80,7 +80,9 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
                                           int Np, int jt0, int lane,
                                           typename Mfma<R>::acc (&ar)[NB],
                                           typename Mfma<R>::acc (&ai)[NB],
-                                          const uint16_t *zrow = nullptr, AL aload = AL()) {
+                                          const uint16_t *zrow = nullptr, AL aload = AL(),
+                                          const cplx_t<R> *__restrict__ Z2 = nullptr,
+                                          int ksplit = 1 << 30) {
   using C = cplx_t<R>;
   constexpr int KU = NB == 1 ? 8 : 4;   // registers allow twice the steps at NB = 1
   constexpr bool synth = !std::is_same<AL, NoLoad>::value;
@@ -110,10 +112,14 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
       const int kk = k0 + 4 * u + lk;
       const bool kok = kk < k;
       if constexpr (synth) {
+        // rows at or past ksplit come from the second block (row - ksplit)
+        const bool second = Z2 && kok && kk >= ksplit;
+        const C *Zb = second ? Z2 : Z;
+        const int zrow_b = second ? zr[u] - ksplit : zr[u];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
           const bool ok = kok && nb < nbv;
-          const C v = ldg(Z, (int64_t)(ok ? zr[u] : 0) * Np + zc + (ok ? nb * 16 : 0));
+          const C v = ldg(Zb, (int64_t)(ok ? zrow_b : 0) * Np + zc + (ok ? nb * 16 : 0));
           b[u][nb] = ok ? v : C{0, 0};
         }
       } else {
@@ -171,6 +177,51 @@ template <typename R> struct StackedA {
     const cplx_t<R> v = ldg(t ? (isb ? Tb : Ta) + i + (int64_t)(p - rc) * rc : safe, 0);
     const R one = (ok && p == i) ? (R)1 : (R)0;
     return t ? v : cplx_t<R>{one, (R)0};
+  }
+};
+
+// A entries of a conjugate transpose: A[row][kk] = conj(M[kk + row ldm]).
+template <typename R> struct ConjTransA {
+  const cplx_t<R> *M;
+  int ldm;
+  __device__ __forceinline__ int index(int, int kk) const { return kk; }
+  __device__ __forceinline__ cplx_t<R> value(int row, int kk, bool ok) const {
+    const cplx_t<R> v = ldg(M, ok ? kk + (int64_t)row * ldm : 0);
+    return ok ? cplx_t<R>{v.x, -v.y} : cplx_t<R>{0, 0};
+  }
+};
+
+// A entries of [X_a; X_b]^H for a transfer unit (rows: its c input columns,
+// in their natural order; k: the ra rows of a, then the rb rows of b).  With
+// p = pa[row] (the column's position in a's order), X_a[k][row] is 1 when
+// p == k, T_a[k, p - ra] when p >= ra, else 0; likewise for b.  The lane's
+// positions pa[row], pb[row] are loaded once, before the tile.
+template <typename R> struct AdjStackedA {
+  const cplx_t<R> *Ta, *Tb, *safe;
+  int ra, rb, pja, pjb;
+  __device__ __forceinline__ int index(int, int kk) const { return kk; }
+  __device__ __forceinline__ cplx_t<R> value(int, int kk, bool ok) const {
+    const bool isb = kk >= ra;
+    const int k = isb ? kk - ra : kk, rc = isb ? rb : ra, p = isb ? pjb : pja;
+    const bool t = ok && p >= rc;
+    const cplx_t<R> v = ldg(t ? (isb ? Tb : Ta) + k + (int64_t)(p - rc) * rc : safe, 0);
+    const R one = (ok && p == k) ? (R)1 : (R)0;
+    return t ? cplx_t<R>{v.x, -v.y} : cplx_t<R>{one, (R)0};
+  }
+};
+
+// A entries of V^H for a V^0 block V = [I, T] Pi^T (r x sz): row j of V^H
+// (a cell of the leaf) has pv = the cell's position in the block's order;
+// V[k][j] is 1 when pv == k, T[k, pv - r] when pv >= r, else 0.
+template <typename R> struct AdjVA {
+  const cplx_t<R> *T, *safe;
+  int r, pj;
+  __device__ __forceinline__ int index(int, int kk) const { return kk; }
+  __device__ __forceinline__ cplx_t<R> value(int, int kk, bool ok) const {
+    const bool t = ok && pj >= r;
+    const cplx_t<R> v = ldg(t ? T + kk + (int64_t)(pj - r) * r : safe, 0);
+    const R one = (ok && pj == kk) ? (R)1 : (R)0;
+    return t ? cplx_t<R>{v.x, -v.y} : cplx_t<R>{one, (R)0};
   }
 };
 
@@ -316,6 +367,113 @@ __global__ __launch_bounds__(256) void k_final_mr(const MFItem *items, int64_t n
   }
 }
 
+// Stores rows [r0, r0 + 16) (those below `rows`) of the accumulators to
+// dst (row stride Np), times `scale`.
+template <typename R, int NB>
+__device__ __forceinline__ void store_tile(cplx_t<R> *dst, int r0, int rows, int Np, int jt,
+                                           int lane, R scale,
+                                           const typename Mfma<R>::acc (&ar)[NB],
+                                           const typename Mfma<R>::acc (&ai)[NB]) {
+  const int nbv = (Np >> 4) - jt < NB ? (Np >> 4) - jt : NB;
+  const int li = lane & 15, lg = lane >> 4;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = r0 + Mfma<R>::row(lg, v);
+    if (row >= rows) continue;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      if (nb < nbv)
+        stg(dst, (int64_t)row * Np + (jt + nb) * 16 + li,
+            cplx_t<R>{ar[nb][v] * scale, ai[nb][v] * scale});
+  }
+}
+
+// Adjoint, K^L part: z_l = (K^L_l)^H y_leaf for one (leaf, level, 16-row
+// tile of the r skeleton rows, column-tile group).
+template <typename R, int NB>
+__global__ __launch_bounds__(256) void k_final_adj_mr(const MFAItem *items, int64_t nitems) {
+  using C = cplx_t<R>;
+  using A = typename Mfma<R>::acc;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+  if (it >= nitems) return;
+  const MFAItem W = items[it];
+  A ar[NB], ai[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) { ar[nb] = Mfma<R>::zero(); ai[nb] = Mfma<R>::zero(); }
+  ConjTransA<R> aload{(const C *)W.K, W.sz};
+  tile_gemm<R, NB>(aload.M, 0, W.r0, W.r, W.sz, (const C *)W.y, W.Np, W.jt, lane, ar, ai,
+                   nullptr, aload);
+  store_tile<R, NB>((C *)W.z, W.r0, W.r, W.Np, W.jt, lane, (R)1, ar, ai);
+}
+
+// Adjoint of a transfer unit: rows [r0, r0 + 16) of its c inputs,
+// z_in = X_a^H w_a + X_b^H w_b as one product over the stacked ra + rb
+// outputs (w_a and w_b are separate blocks).
+template <typename R, int NB>
+__global__ __launch_bounds__(256) void k_wstage_adj_mr(const MWAItem *items, int64_t nitems) {
+  using C = cplx_t<R>;
+  using A = typename Mfma<R>::acc;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+  if (it >= nitems) return;
+  const MWAItem W = items[it];
+  A ar[NB], ai[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) { ar[nb] = Mfma<R>::zero(); ai[nb] = Mfma<R>::zero(); }
+  const int ra = W.ra, rb = W.rb, c = W.c;
+  const int row = W.r0 + (lane & 15);
+  const int rowc = row < c ? row : 0;
+  AdjStackedA<R> aload;
+  aload.Ta = (const C *)W.T;
+  aload.Tb = aload.Ta + (int64_t)ra * (c - ra);
+  aload.safe = aload.Ta;
+  aload.ra = ra;
+  aload.rb = rb;
+  // inverse orders pa, pb of the unit's index lists (ia, ib, pa, pb)
+  aload.pja = ldg16(W.idx, 2 * (int64_t)c + rowc);
+  aload.pjb = ldg16(W.idx, 3 * (int64_t)c + rowc);
+  tile_gemm<R, NB>(aload.Ta, 0, W.r0, c, ra + rb, (const C *)W.za, W.Np, W.jt, lane, ar, ai,
+                   nullptr, aload, (const C *)W.zb, ra);
+  store_tile<R, NB>((C *)W.zin, W.r0, c, W.Np, W.jt, lane, (R)1, ar, ai);
+}
+
+// Adjoint, leaf part: u_leaf = scale (D^H y_leaf + sum_l V_l^H z_l), rows
+// [r0, r0 + 16) of the leaf's cells, every level in a fixed order.
+template <typename R, int NB>
+__global__ __launch_bounds__(256) void k_vstage_adj_mr(const MVAItem *items, int64_t nitems) {
+  using C = cplx_t<R>;
+  using A = typename Mfma<R>::acc;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+  if (it >= nitems) return;
+  const MVAItem W = items[it];
+  A ar[NB], ai[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) { ar[nb] = Mfma<R>::zero(); ai[nb] = Mfma<R>::zero(); }
+  const C *F = (const C *)W.F;
+  const C *z = (const C *)W.z;
+  const int sz = W.sz;
+  const int row = W.r0 + (lane & 15);
+  const int rowc = row < sz ? row : 0;
+  ConjTransA<R> dl{F + W.dense_off, sz};
+  tile_gemm<R, NB>(dl.M, 0, W.r0, sz, sz, (const C *)W.y, W.Np, W.jt, lane, ar, ai, nullptr, dl);
+  for (int l = 0; l < W.Lv; ++l) {
+    const VDesc d = W.vd[l];
+    AdjVA<R> vl;
+    vl.T = F + d.foff;
+    vl.safe = F;
+    vl.r = d.r;
+    vl.pj = ldg16(W.fidx + d.ioff, sz + rowc);   // the cell's position in the order
+    tile_gemm<R, NB>(vl.T, 0, W.r0, sz, d.r, z + d.zout * W.Np, W.Np, W.jt, lane, ar, ai,
+                     nullptr, vl);
+  }
+  store_tile<R, NB>((C *)W.u, W.r0, sz, W.Np, W.jt, lane, (R)W.scale, ar, ai);
+}
+
 // s (natural order, column-major N_v x nrhs, leading dimension ld) ->
 // x (tree order, row stride Np), scaled by h^d; columns nrhs..Np-1 zeroed.
 // 64 tree positions x 16 columns per workgroup through LDS.
@@ -384,6 +542,15 @@ static void launch_stage_nb(const MStagePlan &sp, hipStream_t st) {
   if (sp.kind == 2 && sp.n)
     hipLaunchKernelGGL((k_final_mr<R, NB>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
                        (const MFItem *)sp.items, sp.n);
+  if (sp.kind == 3 && sp.n)
+    hipLaunchKernelGGL((k_final_adj_mr<R, NB>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
+                       (const MFAItem *)sp.items, sp.n);
+  if (sp.kind == 4 && sp.n)
+    hipLaunchKernelGGL((k_wstage_adj_mr<R, NB>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
+                       (const MWAItem *)sp.items, sp.n);
+  if (sp.kind == 5 && sp.n)
+    hipLaunchKernelGGL((k_vstage_adj_mr<R, NB>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
+                       (const MVAItem *)sp.items, sp.n);
 }
 
 template <typename R>

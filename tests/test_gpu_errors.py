@@ -73,3 +73,45 @@ def test_rejected_calls_leave_context_usable():
     assert np.linalg.norm(col - ref) / np.linalg.norm(ref) < 1e-6
     op32.close()
     op.close()
+
+
+def test_out_of_memory_is_reported_and_recovered(monkeypatch):
+    """Allocation failures, forced on the host (HBI_FAIL_ALLOC_BYTES: every
+    device allocation of at least that many bytes fails before any kernel of
+    the call is launched), come back as HBI_ERR_OOM with the failing call in
+    the message, for a build and for a batched apply; the context keeps its
+    tables, refuses to apply, and builds and applies normally once memory is
+    available again."""
+    ensure_built()
+    import torch
+    import paper_2210_02698_amd as hbi
+    from paper_2210_02698_amd import _lib
+    prob = hb_inputs.configs.c2(64, nbox=4)
+    s = torch.from_numpy(hb_inputs.complex_normal(prob.Nv, [71, 0])).to("cuda:0")
+    ref = hbi.Operator(prob, device=0).build(tol=1e-7)
+    u_ref = ref.apply(s).cpu().numpy()
+    op = hbi.Operator(prob, device=0)
+    print("[gpu-case] forced out of memory: build", flush=True)
+    monkeypatch.setenv("HBI_FAIL_ALLOC_BYTES", str(1 << 20))
+    with pytest.raises(hbi.HBIError) as ei:
+        op.build(tol=1e-7)
+    assert ei.value.status == _lib.HBI_ERR_OOM, ei.value
+    assert op.info()["state"] == 1
+    monkeypatch.delenv("HBI_FAIL_ALLOC_BYTES")
+    with pytest.raises(hbi.HBIError):
+        op.apply(s)               # no factors: the binding refuses
+    op.build(tol=1e-7)
+    assert np.array_equal(op.apply(s).cpu().numpy(), u_ref)
+    # a batched apply whose workspace cannot be allocated
+    print("[gpu-case] forced out of memory: batched apply", flush=True)
+    S = [s.reshape(-1, 1).repeat(1, 3).t().contiguous().t(), s.reshape(-1, 1)]
+    monkeypatch.setenv("HBI_FAIL_ALLOC_BYTES", str(1 << 16))
+    with pytest.raises(hbi.HBIError) as ei:
+        hbi.apply_batched([op, ref], S)
+    assert ei.value.status == _lib.HBI_ERR_OOM, ei.value
+    monkeypatch.delenv("HBI_FAIL_ALLOC_BYTES")
+    U = hbi.apply_batched([op, ref], S)
+    torch.cuda.synchronize()
+    assert np.allclose(U[1].cpu().numpy()[:, 0], u_ref, rtol=0, atol=1e-12 * np.abs(u_ref).max())
+    op.close()
+    ref.close()

@@ -162,6 +162,23 @@ def test_multi_rhs_matches_single(torch_mod, prec, nrhs):
     # replay of the captured graph gives identical results
     U2 = op.apply(to_dev(torch, S, dt).t()).cpu().numpy()
     assert np.array_equal(U, U2)
+    # the adjoint with several RHS (MFMA tiles of the conjugate-transposed
+    # factors) against the single-RHS adjoint, the oracle and the forward
+    # product (dot-product identity, all columns at once)
+    UA = op.apply_adjoint(to_dev(torch, S, dt).t()).cpu().numpy()
+    for r in range(0, nrhs, max(1, nrhs // 7)):
+        ua = op.apply_adjoint(to_dev(torch, S[r], dt)).cpu().numpy()
+        assert rel(UA[:, r], ua) < tol, (r, rel(UA[:, r], ua))
+    refa = oracle.apply_adjoint(prob, S.T.astype(np.complex128), rows)
+    check(UA[rows], refa, 1e-6 if prec == "f64" else 1e-4, f"multi rhs {prec} {nrhs} adjoint")
+    Y = hb_inputs.complex_normal((nrhs, prob.Nv), [7, nrhs, 1])
+    KX = U.astype(np.complex128)
+    KHY = op.apply_adjoint(to_dev(torch, Y, dt).t()).cpu().numpy().astype(np.complex128)
+    npdt = np.complex64 if prec == "f32" else np.complex128   # the values the GPU saw
+    Xr = S.T.astype(npdt).astype(np.complex128)
+    Yr = Y.T.astype(npdt).astype(np.complex128)
+    lhs, rhs_ = np.vdot(Yr, KX), np.vdot(KHY, Xr)
+    assert abs(lhs - rhs_) <= (1e-12 if prec == "f64" else 1e-5) * abs(lhs), (lhs, rhs_)
     op.close()
 
 
@@ -487,4 +504,27 @@ def test_transfer_stage_branches(torch_mod, monkeypatch, prec, tol, bound):
     KHy = op.apply_adjoint(to_dev(torch, y, dt)).cpu().numpy().astype(np.complex128)
     lhs, rhs = np.vdot(y, Kx), np.vdot(KHy, s)
     assert abs(lhs - rhs) <= (1e-12 if prec == "f64" else 1e-5) * abs(lhs)
+    op.close()
+
+
+def test_autograd_several_rhs(torch_mod):
+    """HBApply on an N_v x 3 block: the backward pass runs the MFMA adjoint
+    (several right-hand sides) and equals the dense adjoint column by
+    column."""
+    torch = torch_mod
+    import paper_2210_02698_amd as hbi
+    prob = hb_inputs.configs.c4(32)
+    say(f"autograd 3 RHS Nv={prob.Nv}")
+    op = make_op(prob, tol=1e-9)
+    S0 = np.asfortranarray(hb_inputs.complex_normal((prob.Nv, 3), [4, 9]))
+    D = hb_inputs.complex_normal((prob.Nv, 3), [4, 10])
+    s = torch.from_numpy(S0).to("cuda:0").requires_grad_(True)
+    u = hbi.HBApply.apply(op, s)
+    loss = (u - torch.from_numpy(D).to("cuda:0")).abs().pow(2).sum()
+    loss.backward()
+    grad = s.grad.cpu().numpy()
+    K = oracle.dense(prob)
+    hd = prob.h ** 2
+    ref = 2 * hd * (K.conj().T @ (K @ (S0 * hd) - D))
+    check(grad, ref, 1e-6, "autograd 3 RHS")
     op.close()
