@@ -15,7 +15,8 @@ tables are filled from closed forms where the medium has one (homogeneous and
 constant-gradient media, Sec. 5.1) and from a smooth straight-ray stand-in
 otherwise.
 """
-from .media import (Homogeneous, ConstantGradient, GaussianBump, Sinusoid3D)
+from .media import (Homogeneous, ConstantGradient, GaussianBump, Sinusoid3D, Sinusoid2D,
+                    n2_taylor, medium_grid, taylor_at)
 from .tables import cheb_unit_nodes, node_coords, tabulate
 from .problem import HBProblem, make_problem
 from .rhs import complex_normal, gaussian_sources, point_sources
@@ -23,7 +24,8 @@ from .curves import Curve, circle, open_square
 from . import configs
 
 __all__ = [
-    "Homogeneous", "ConstantGradient", "GaussianBump", "Sinusoid3D",
+    "Homogeneous", "ConstantGradient", "GaussianBump", "Sinusoid3D", "Sinusoid2D", "n2_taylor",
+    "medium_grid", "taylor_at",
     "cheb_unit_nodes", "node_coords", "tabulate", "HBProblem", "make_problem",
     "complex_normal", "gaussian_sources", "point_sources", "Curve", "circle", "open_square", "configs",
 ]

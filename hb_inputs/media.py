@@ -14,6 +14,7 @@ from __future__ import annotations
 import math
 from dataclasses import dataclass
 
+import mpmath
 import numpy as np
 
 _GL16_T, _GL16_W = np.polynomial.legendre.leggauss(16)
@@ -37,6 +38,9 @@ class Homogeneous:
     def slowness(self, P):
         P = np.asarray(P, dtype=np.float64)
         return np.full(P.shape[:-1], self.n0)
+
+    def slowness_mp(self, x, y):
+        return mpmath.mpf(self.n0)
 
     def ingredients(self, R, R0, d):
         R = np.asarray(R, np.float64)
@@ -121,6 +125,9 @@ class ConstantGradient:
     def slowness(self, P):
         return 1.0 / self.velocity(P)
 
+    def slowness_mp(self, x, y):
+        return 1 / (self.c0 + self.G[0] * x + self.G[1] * y)
+
     def tau(self, R, R0):
         R = np.asarray(R, np.float64)
         R0 = np.asarray(R0, np.float64)
@@ -186,6 +193,45 @@ class GaussianBump(_StraightRay):
         r2 = np.sum((P - c) ** 2, axis=-1)
         return 1.0 + self.amp * np.exp(-r2 / (2.0 * self.width ** 2))
 
+    def slowness_mp(self, x, y):
+        r2 = (x - self.centre[0]) ** 2 + (y - self.centre[1]) ** 2
+        return 1 + self.amp * mpmath.exp(-r2 / (2 * mpmath.mpf(self.width) ** 2))
+
+
+@dataclass(frozen=True)
+class Sinusoid2D(_StraightRay):
+    """n(x, y) = 1 / (1 + amp sin(pi (x + 0.05)) sin(pi y / 2)): the 2D
+    sinusoidal medium of the paper's numerical results (Sec. 5.1.1), whose
+    phase and HB coefficients have no closed form; its tables come from the
+    eikonal and transport solves (hbi_tabulate), the straight-ray stand-in
+    serving only as a placeholder."""
+    amp: float = 0.2
+    name: str = "sinusoid-2d"
+
+    def slowness(self, P):
+        P = np.asarray(P, np.float64)
+        return 1.0 / (1.0 + self.amp * np.sin(math.pi * (P[..., 0] + 0.05)) *
+                      np.sin(0.5 * math.pi * P[..., 1]))
+
+    def slowness_mp(self, x, y):
+        return 1 / (1 + self.amp * mpmath.sin(mpmath.pi * (x + mpmath.mpf("0.05"))) *
+                    mpmath.sin(mpmath.pi * y / 2))
+
+
+def n2_taylor(medium, r0, order=4, dps=40):
+    """Taylor coefficients of n(r)^2 about r0 (2D): S[i, j] is the coefficient
+    of (x - x0)^i (y - y0)^j, i + j <= order, from the medium's own
+    high-precision form (mpmath differentiation)."""
+    mpmath.mp.dps = dps
+    x0, y0 = (mpmath.mpf(float(c)) for c in r0[:2])
+    f = lambda x, y: medium.slowness_mp(x, y) ** 2
+    S = np.zeros((order + 1, order + 1))
+    for i in range(order + 1):
+        for j in range(order + 1 - i):
+            v = mpmath.diff(f, (x0, y0), (i, j))
+            S[i, j] = float(v) / (math.factorial(i) * math.factorial(j))
+    return S
+
 
 @dataclass(frozen=True)
 class Sinusoid3D(_StraightRay):
@@ -197,3 +243,21 @@ class Sinusoid3D(_StraightRay):
         P = np.asarray(P, np.float64)
         s = np.sin(2.0 * math.pi * P)
         return 1.0 + self.amp * s[..., 0] * s[..., 1] * s[..., 2]
+
+
+def medium_grid(medium, lo, hi, spacing, pad=4):
+    """n^2 of a 2D medium on a regular grid covering [lo - pad spacing,
+    hi + pad spacing] per axis: returns (n2[i, j], origin, spacing)."""
+    nx = int(math.ceil((hi[0] - lo[0]) / spacing)) + 2 * pad + 1
+    ny = int(math.ceil((hi[1] - lo[1]) / spacing)) + 2 * pad + 1
+    origin = (lo[0] - pad * spacing, lo[1] - pad * spacing)
+    X = origin[0] + spacing * np.arange(nx)[:, None] + 0.0 * np.arange(ny)[None, :]
+    Y = origin[1] + spacing * np.arange(ny)[None, :] + 0.0 * np.arange(nx)[:, None]
+    n = medium.slowness(np.stack([X, Y], axis=-1))
+    return n * n, origin, spacing
+
+
+def taylor_at(medium, P, order=4):
+    """(len(P), order + 1, order + 1) Taylor coefficients of n^2 about the
+    points P (n2_taylor at each)."""
+    return np.stack([n2_taylor(medium, p, order) for p in np.atleast_2d(P)])

@@ -185,6 +185,40 @@ hbi_status hbi_apply_batched(hbi_ctx *const *ctx, int32_t nprob,
                              const void *const *s, void *const *u,
                              const int32_t *nrhs, const int64_t *ld);
 
+/* A 2D medium for hbi_tabulate: n^2 on a regular grid, point (i, j) at
+ * origin + (i, j) * spacing, and the Taylor coefficients of n^2 about every
+ * table node. */
+typedef struct {
+  int32_t n[2];             /* grid points per axis (>= 6)                       */
+  double origin[2];
+  double spacing;           /* > 0                                                */
+  const double *n2;         /* host [n[0] * n[1]], n(r)^2, x fastest              */
+  const double *taylor;     /* host [NT * 25]: about node A, the coefficient of
+                               (x - x_A)^i (y - y_A)^j at [25 A + 5 i + j],
+                               i + j <= 4 (the other entries are ignored)       */
+} hbi_medium2d;
+
+/* The tables tau^2, v0, v1 of hbi_tables (Sec. 4.1: values at every pair of
+ * table nodes) computed from the medium, 2D: for every node as a point
+ * source, the factored eikonal (eq. faceik) and the transport recurrence
+ * (eq. equVs) for v0 and v1 on a grid of spacing h0 aligned with the node and
+ * covering the table region plus `margin` points on every side, by
+ * Lax-Friedrichs sweeping with fifth-order WENO derivatives (epsilon h0^2),
+ * Gauss-Seidel in the four orderings until the largest update of a round is
+ * below 1e-13, the unknowns held at their Taylor expansions (Sec. 2.2,
+ * truncation 6, 4, 2) within 5, 3 and 1 grid points of the node; then the 4 x 4 Lagrange cubic of the grid
+ * values at every other node.  The tables are symmetrised ((F + F^T) / 2)
+ * and written to the host arrays tau2, v0, v1 (NT x NT row-major, layout of
+ * hbi_tables).  The medium grid must cover every source grid with 3 more
+ * points (n^2 is interpolated by local quintics); nI 2..16, nbox >= 1,
+ * h0 > 0, margin >= 4 (HBI_ERR_ARG otherwise).  HBI_ERR_NUMERIC when a solve
+ * does not converge (the sweeps stop after 20000 rounds).  Needs a context
+ * for its device and stream only (tables and factors are untouched).
+ * Synchronous. */
+hbi_status hbi_tabulate(hbi_ctx *ctx, const hbi_medium2d *m, int32_t nI, const int32_t nbox[2],
+                        const double box_origin[2], double box_size, double h0, int32_t margin,
+                        double *tau2, double *v0, double *v1);
+
 /* Bytes of the fixed per-device scratch array of hbi_apply_noalloc. */
 #define HBI_NOALLOC_SCRATCH_BYTES (128u << 20)
 

@@ -24,7 +24,7 @@ import numpy as np
 from . import _lib
 from ._lib import HBIError, HBI_F32, HBI_F64
 
-__all__ = ["Operator", "HBApply", "HBIError", "load_library", "apply_batched"]
+__all__ = ["Operator", "HBApply", "HBIError", "load_library", "apply_batched", "tabulate"]
 
 
 def load_library():
@@ -326,6 +326,44 @@ def apply_batched(ops, S, out=None):
     ops[0].set_stream()
     _lib.check(lib.hbi_apply_batched(ctxs, n, sp, up, nr, ld), ops[0]._ctx)
     return U
+
+
+def tabulate(n2, origin, spacing, taylor, nI, nbox, box_origin, box_size, h0, margin=8,
+             device=0):
+    """Tables tau^2, v0, v1 (NT x NT each, the layout of hbi_tables) from the
+    eikonal and transport solves on the GPU (hbi_tabulate, 2D).  n2: the
+    medium's n^2 on a regular grid, array (nx, ny) indexed [i, j] at
+    origin + (i, j) spacing; taylor: (NT, 5, 5) Taylor coefficients of n^2
+    about every table node (entry [A, i, j] multiplies (x - x_A)^i
+    (y - y_A)^j)."""
+    import torch
+    lib = _lib.load()
+    n2 = np.asarray(n2, dtype=np.float64)
+    if n2.ndim != 2:
+        raise ValueError("n2 must be a 2D grid")
+    NT = int(nbox[0]) * int(nbox[1]) * int(nI) ** 2
+    tay = np.ascontiguousarray(taylor, dtype=np.float64)
+    if tay.shape != (NT, 5, 5):
+        raise ValueError(f"taylor must be ({NT}, 5, 5)")
+    grid = np.ascontiguousarray(n2.T)          # x fastest
+    m = _lib.hbi_medium2d()
+    m.n[0], m.n[1] = n2.shape
+    m.origin[0], m.origin[1] = float(origin[0]), float(origin[1])
+    m.spacing = float(spacing)
+    m.n2 = _dptr(grid)
+    m.taylor = _dptr(tay)
+    out = [np.empty((NT, NT)) for _ in range(3)]
+    nb = (ctypes.c_int32 * 2)(int(nbox[0]), int(nbox[1]))
+    bo = (ctypes.c_double * 2)(float(box_origin[0]), float(box_origin[1]))
+    ctx = ctypes.c_void_p()
+    st = torch.cuda.current_stream(torch.device("cuda", device)).cuda_stream
+    _lib.check(lib.hbi_create(device, ctypes.c_void_p(st), ctypes.byref(ctx)))
+    try:
+        _lib.check(lib.hbi_tabulate(ctx, ctypes.byref(m), int(nI), nb, bo, float(box_size),
+                                    float(h0), int(margin), *[_dptr(F) for F in out]), ctx)
+    finally:
+        lib.hbi_destroy(ctx)
+    return tuple(out)
 
 
 def _autograd_function():

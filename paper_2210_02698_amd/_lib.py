@@ -50,6 +50,12 @@ class HBIError(RuntimeError):
 
 _lib = None
 
+class hbi_medium2d(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 2), ("origin", ctypes.c_double * 2),
+                ("spacing", ctypes.c_double), ("n2", ctypes.POINTER(ctypes.c_double)),
+                ("taylor", ctypes.POINTER(ctypes.c_double))]
+
+
 # (name, restype, argtypes) for every function declared in include/hbi.h
 SIGNATURES = [
     ("hbi_create", ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
@@ -80,6 +86,12 @@ SIGNATURES = [
     ("hbi_get_profile", ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]),
     ("hbi_get_info", ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]),
     ("hbi_last_error", ctypes.c_char_p, [ctypes.c_void_p]),
+    ("hbi_tabulate", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(hbi_medium2d), ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]),
 ]
 
 

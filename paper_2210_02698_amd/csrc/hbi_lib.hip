@@ -20,6 +20,7 @@
 #include "hbi_internal.h"
 #include "hbi_kernels.h"
 #include "hbi_multi.h"
+#include "hbi_tabulate.h"
 
 #include <cstdlib>
 #include <fstream>
@@ -267,6 +268,7 @@ struct hbi_ctx {
   // forward transfer items with inputs staged in LDS / gathered from global
   // memory, and those on 16-row windows
   int64_t wst_lds = 0, wst_global = 0, wst_wide = 0;
+  int32_t tab_rounds_max = 0;   // largest sweep count of the last hbi_tabulate
   int32_t wst_cq[5] = {0, 0, 0, 0, 0};   // unit widths c: min, quartiles, max
   // curve inclusion (2D): segments at positions [Nv, Nv + inc_ns) of the
   // per-point arrays; inputs on the host and the device, and the dense
@@ -2140,6 +2142,216 @@ void multi_apply(hbi_ctx *c0, const std::vector<hbi_ctx *> &ctxs, const std::vec
 // ===========================================================================
 // C ABI
 // ===========================================================================
+// ---------------------------------------------------------------------------
+// Tables from the eikonal and transport solves (hbi_tabulate)
+// ---------------------------------------------------------------------------
+namespace tabgen {
+
+constexpr int DEG = 8;   // polynomials keep degrees <= DEG
+struct Poly {
+  double c[DEG + 1][DEG + 1] = {};   // c[i][j]: coefficient of x^i y^j
+};
+Poly hom(const Poly &A, int k) {
+  Poly B;
+  for (int i = 0; i <= k && i <= DEG; ++i)
+    if (k - i <= DEG) B.c[i][k - i] = A.c[i][k - i];
+  return B;
+}
+Poly mul(const Poly &A, const Poly &B) {
+  Poly C;
+  for (int i = 0; i <= DEG; ++i)
+    for (int j = 0; i + j <= DEG; ++j) {
+      if (A.c[i][j] == 0.0) continue;
+      for (int k = 0; i + j + k <= DEG; ++k)
+        for (int l = 0; i + j + k + l <= DEG; ++l) C.c[i + k][j + l] += A.c[i][j] * B.c[k][l];
+    }
+  return C;
+}
+Poly ddx(const Poly &A) {
+  Poly C;
+  for (int i = 1; i <= DEG; ++i)
+    for (int j = 0; j <= DEG; ++j) C.c[i - 1][j] = i * A.c[i][j];
+  return C;
+}
+Poly ddy(const Poly &A) {
+  Poly C;
+  for (int i = 0; i <= DEG; ++i)
+    for (int j = 1; j <= DEG; ++j) C.c[i][j - 1] = j * A.c[i][j];
+  return C;
+}
+void axpy(Poly &Y, double a, const Poly &X) {
+  for (int i = 0; i <= DEG; ++i)
+    for (int j = 0; j <= DEG; ++j) Y.c[i][j] += a * X.c[i][j];
+}
+Poly lap(const Poly &A) {
+  Poly L = ddx(ddx(A));
+  axpy(L, 1.0, ddy(ddy(A)));
+  return L;
+}
+Poly gdot(const Poly &A, const Poly &B) {
+  Poly G = mul(ddx(A), ddx(B));
+  axpy(G, 1.0, mul(ddy(A), ddy(B)));
+  return G;
+}
+
+// Homogeneous parts of tau^2 (T_0..T_6), v0 (B_0..B_4), v1 (C_0..C_2) about
+// a source from the Taylor coefficients S[i][j] of n^2 (i + j <= 4), by the
+// recursions of Sec. 2.2 (eq. recursiveT, eq. recursiveB, eq. C0, C1 and
+// recursiveC; d = 2), summed into TAB_PD x TAB_PD arrays.
+void taylor_sums(const double *S25, TabSource &src) {
+  const int PT = 6, PS = 4, PB = 4, PC = 2, d = 2;
+  Poly Sf;
+  for (int i = 0; i <= 4; ++i)
+    for (int j = 0; i + j <= 4; ++j) Sf.c[i][j] = S25[5 * i + j];
+  std::vector<Poly> Sk(PS + 1), T(PT + 1), B(PB + 1), C(PC + 1);
+  for (int k = 0; k <= PS; ++k) Sk[k] = hom(Sf, k);
+  const double S0 = Sk[0].c[0][0];
+  if (!(S0 > 0)) throw Error{HBI_ERR_ARG, "hbi_tabulate: n^2 must be positive at every node"};
+  T[2].c[2][0] = T[2].c[0][2] = S0;
+  for (int P = 3; P <= PT; ++P) {
+    Poly acc;
+    for (int k = 1; k <= P - 2; ++k)
+      if (k <= PS) axpy(acc, 1.0, mul(Sk[k], T[P - k]));
+    for (int k = 2; k <= P - 2; ++k) axpy(acc, -0.25, gdot(T[k + 1], T[P - k + 1]));
+    T[P] = hom(acc, P);
+    for (auto &row : T[P].c)
+      for (double &v : row) v /= (P - 1) * S0;
+  }
+  B[0].c[0][0] = 1.0 / (2.0 * std::sqrt(M_PI));   // n0^(d-2) / (2 pi^((d-1)/2)), d = 2
+  for (int P = 1; P <= PB; ++P) {
+    Poly acc;
+    for (int k = 1; k <= P - 1; ++k) axpy(acc, -1.0, gdot(B[k], T[P + 2 - k]));
+    for (int k = 0; k <= P - 1; ++k) {
+      axpy(acc, -0.5, mul(B[k], lap(T[P + 2 - k])));
+      axpy(acc, (double)d, mul(B[k], Sk[P - k]));
+    }
+    B[P] = hom(acc, P);
+    for (auto &row : B[P].c)
+      for (double &v : row) v /= 2.0 * P * S0;
+  }
+  for (int P = 0; P <= PC; ++P) {
+    Poly acc = lap(B[P + 2]);
+    for (auto &row : acc.c)
+      for (double &v : row) v *= 0.5;
+    for (int k = 1; k <= P - 1; ++k) axpy(acc, -1.0, gdot(C[k], T[P + 2 - k]));
+    for (int k = 0; k <= P - 1; ++k) {
+      axpy(acc, -0.5, mul(C[k], lap(T[P + 2 - k])));
+      axpy(acc, -(2.0 - d), mul(C[k], Sk[P - k]));
+    }
+    C[P] = hom(acc, P);
+    for (auto &row : C[P].c)
+      for (double &v : row) v /= 2.0 * (P + 1) * S0;
+  }
+  for (int a = 0; a < TAB_PD; ++a)
+    for (int b = 0; a + b < TAB_PD; ++b) {
+      double t = 0, v = 0, w = 0;
+      for (int k = 0; k <= PT; ++k) t += T[k].c[a][b];
+      for (int k = 0; k <= PB; ++k) v += B[k].c[a][b];
+      for (int k = 0; k <= PC; ++k) w += C[k].c[a][b];
+      src.T[a * TAB_PD + b] = t;
+      src.B[a * TAB_PD + b] = v;
+      src.C[a * TAB_PD + b] = w;
+    }
+  src.n0 = std::sqrt(S0);
+}
+
+void tabulate(hbi_ctx *c, const hbi_medium2d *m, int32_t nI, const int32_t nbox[2],
+              const double box_origin[2], double box_size, double h0, int32_t margin,
+              double *tau2, double *v0, double *v1) {
+  HBI_REQUIRE(m && nbox && box_origin && tau2 && v0 && v1 && m->n2 && m->taylor, HBI_ERR_ARG,
+              "hbi_tabulate: null argument");
+  HBI_REQUIRE(nI >= 2 && nI <= HBI_MAX_NI, HBI_ERR_ARG, "hbi_tabulate: nI must be in 2..16");
+  HBI_REQUIRE(nbox[0] >= 1 && nbox[1] >= 1 && box_size > 0 && h0 > 0 && margin >= 4,
+              HBI_ERR_ARG, "hbi_tabulate: bad nbox, box_size, h0 or margin");
+  HBI_REQUIRE(m->n[0] >= 6 && m->n[1] >= 6 && m->spacing > 0, HBI_ERR_ARG,
+              "hbi_tabulate: the medium grid needs >= 6 points per axis and spacing > 0");
+  const int64_t NT64 = (int64_t)nbox[0] * nbox[1] * nI * nI;
+  HBI_REQUIRE(NT64 <= 16384, HBI_ERR_ARG, "hbi_tabulate: more than 16384 table nodes");
+  const int32_t NT = (int32_t)NT64;
+  // nodes in table order (box b = bx + nbox0 by, node a = k1 + nI k2)
+  std::vector<double> nodes(2 * (size_t)NT);
+  for (int32_t b = 0; b < nbox[0] * nbox[1]; ++b)
+    for (int32_t a = 0; a < nI * nI; ++a) {
+      const int32_t q = b * nI * nI + a, bx = b % nbox[0], by = b / nbox[0];
+      const int32_t k1 = a % nI, k2 = a / nI;
+      nodes[2 * q] = box_origin[0] +
+                     (bx + 0.5 * (1.0 + std::cos((2.0 * k1 + 1.0) * M_PI / (2.0 * nI)))) * box_size;
+      nodes[2 * q + 1] = box_origin[1] +
+                         (by + 0.5 * (1.0 + std::cos((2.0 * k2 + 1.0) * M_PI / (2.0 * nI)))) * box_size;
+    }
+  const double lo[2] = {box_origin[0], box_origin[1]};
+  const double hi[2] = {box_origin[0] + nbox[0] * box_size, box_origin[1] + nbox[1] * box_size};
+  // source grids: aligned with the node, covering the region plus margin
+  std::vector<TabSource> src(NT);
+  int64_t npmax = 0;
+  for (int32_t q = 0; q < NT; ++q) {
+    TabSource &S = src[q];
+    const double x0 = nodes[2 * q], y0 = nodes[2 * q + 1];
+    const int32_t ia = (int32_t)std::floor((lo[0] - x0) / h0) - margin;
+    const int32_t ib = (int32_t)std::ceil((hi[0] - x0) / h0) + margin;
+    const int32_t ja = (int32_t)std::floor((lo[1] - y0) / h0) - margin;
+    const int32_t jb = (int32_t)std::ceil((hi[1] - y0) / h0) + margin;
+    S.h = h0;
+    S.nx = ib - ia + 1;
+    S.ny = jb - ja + 1;
+    S.i0 = -ia;
+    S.j0 = -ja;
+    S.gx0 = x0 + ia * h0;
+    S.gy0 = y0 + ja * h0;
+    HBI_REQUIRE((int64_t)S.nx * S.ny <= ((int64_t)1 << 24), HBI_ERR_ARG,
+                "hbi_tabulate: source grid larger than 2^24 points (h0 too small)");
+    // the quintic of the medium needs points -2 .. +3 around every grid point
+    const double fx0 = (S.gx0 - m->origin[0]) / m->spacing, fy0 = (S.gy0 - m->origin[1]) / m->spacing;
+    const double fx1 = (S.gx0 + (S.nx - 1) * h0 - m->origin[0]) / m->spacing;
+    const double fy1 = (S.gy0 + (S.ny - 1) * h0 - m->origin[1]) / m->spacing;
+    HBI_REQUIRE(std::floor(fx0) - 2 >= 0 && std::floor(fy0) - 2 >= 0 &&
+                    std::floor(fx1) + 3 <= m->n[0] - 1 && std::floor(fy1) + 3 <= m->n[1] - 1,
+                HBI_ERR_ARG, "hbi_tabulate: the medium grid does not cover the source grids");
+    taylor_sums(m->taylor + 25 * (size_t)q, S);
+    npmax = std::max<int64_t>(npmax, (int64_t)S.nx * S.ny);
+  }
+  const hipStream_t st = c->stream;
+  DevBuf n2d, nodes_d, tabs, stat_d, src_d, ws;
+  upload(n2d, std::vector<double>(m->n2, m->n2 + (size_t)m->n[0] * m->n[1]));
+  upload(nodes_d, nodes);
+  upload(src_d, src);
+  HBI_HIP(tabs.alloc(3 * sizeof(double) * (size_t)NT * NT));
+  HBI_HIP(stat_d.alloc(3 * sizeof(int32_t) * (size_t)NT));
+  TabMedium med{n2d.as<double>(), m->n[0], m->n[1], m->origin[0], m->origin[1], m->spacing};
+  const int64_t stride = 11 * npmax;
+  // sources in batches whose workspace fits about 2 GiB
+  const int64_t per = std::max<int64_t>(1, ((int64_t)2 << 30) / (stride * (int64_t)sizeof(double)));
+  const int32_t batch = (int32_t)std::min<int64_t>(NT, per);
+  HBI_HIP(ws.alloc(sizeof(double) * (size_t)stride * batch));
+  double *F0 = tabs.as<double>(), *F1 = F0 + (size_t)NT * NT, *F2 = F1 + (size_t)NT * NT;
+  for (int32_t s0 = 0; s0 < NT; s0 += batch) {
+    const int32_t nb = std::min(batch, NT - s0);
+    // column s0 + s of every table: offset the table pointers by s0 columns
+    HBI_HIP(launch_tabulate(src_d.as<TabSource>() + s0, nb, med, ws.as<double>(), stride,
+                            nodes_d.as<double>(), NT, F0 + s0, F1 + s0, F2 + s0,
+                            stat_d.as<int32_t>() + 3 * s0, 1e-13, 20000, st));
+    HBI_HIP(hipStreamSynchronize(st));
+  }
+  HBI_HIP(launch_tab_symmetrise(F0, F1, F2, NT, st));
+  std::vector<int32_t> status(3 * (size_t)NT);
+  HBI_HIP(hipMemcpyAsync(status.data(), stat_d.p, status.size() * sizeof(int32_t),
+                         hipMemcpyDeviceToHost, st));
+  HBI_HIP(hipMemcpyAsync(tau2, F0, sizeof(double) * (size_t)NT * NT, hipMemcpyDeviceToHost, st));
+  HBI_HIP(hipMemcpyAsync(v0, F1, sizeof(double) * (size_t)NT * NT, hipMemcpyDeviceToHost, st));
+  HBI_HIP(hipMemcpyAsync(v1, F2, sizeof(double) * (size_t)NT * NT, hipMemcpyDeviceToHost, st));
+  HBI_HIP(hipStreamSynchronize(st));
+  c->tab_rounds_max = 0;
+  for (int32_t q = 0; q < NT; ++q)
+    for (int e = 0; e < 3; ++e) {
+      if (status[3 * q + e] < 0)
+        throw Error{HBI_ERR_NUMERIC, "hbi_tabulate: the sweeps of node " + std::to_string(q) +
+                                         " (equation " + std::to_string(e) + ") did not converge"};
+      c->tab_rounds_max = std::max(c->tab_rounds_max, status[3 * q + e]);
+    }
+}
+
+}  // namespace tabgen
+
 namespace {
 // Index and descriptor bytes one forward apply reads (algorithmic).
 double apply_index_bytes(const ApplyPlan &ap) {
@@ -2431,6 +2643,15 @@ hbi_status hbi_apply_batched(hbi_ctx *const *ctx, int32_t nprob, const void *con
     std::vector<int32_t> nv(nrhs, nrhs + nprob);
     std::vector<int64_t> lv(ld, ld + nprob);
     multi_apply(ctx[0], cs, sv, uv, nv, lv);
+  });
+}
+
+hbi_status hbi_tabulate(hbi_ctx *ctx, const hbi_medium2d *m, int32_t nI, const int32_t nbox[2],
+                        const double box_origin[2], double box_size, double h0, int32_t margin,
+                        double *tau2, double *v0, double *v1) {
+  if (!ctx) { g_err = "ctx is NULL"; return HBI_ERR_ARG; }
+  return guarded(ctx, [&]() {
+    tabgen::tabulate(ctx, m, nI, nbox, box_origin, box_size, h0, margin, tau2, v0, v1);
   });
 }
 
