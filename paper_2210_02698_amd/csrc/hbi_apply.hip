@@ -177,19 +177,6 @@ __device__ __forceinline__ C group_sum(C acc, int lane, int wr, int G) {
   return acc;
 }
 
-// Forward transfer stage: one wave per work item, rows [r0, r0 + wr) of a
-// unit (the pair stacked a then b; all rows when it has at most 32).  Row i
-// of child a is x[ia[i]] + sum_m T_a[i, m] x[ia[ra + m]] (X = [I, T] Pi^T),
-// likewise for b with its own column order ib.  Lanes take (row, column
-// group) as in group_sum.  A wave loads its descriptor, then at once the
-// unit's first 128 inputs and column-order words and the first batch of T,
-// so the factor stream is in flight while the inputs land in the wave's LDS
-// slice (raw inputs, then the orders ia, ib as 32-bit words).  PERM: the two
-// permuted input lists are then formed LDS to LDS and read directly;
-// otherwise each use reads its input through the order in LDS.  Units whose
-// slice would exceed cap_lds entries gather their inputs from global memory.
-// Items are ordered by decreasing cost, and the factor store holds the units
-// in that order.
 // Forward transfer stage.  Row i of child a of a unit is
 // x[ia[i]] + sum_m T_a[i, m] x[ia[ra + m]] (X = [I, T] Pi^T), likewise for b
 // with its own column order ib.  A work item is rows [r0, r0 + wr) of a unit

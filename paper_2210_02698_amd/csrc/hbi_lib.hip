@@ -1782,6 +1782,50 @@ void plan_passes(BatchCache &B, const std::vector<int32_t> &nrhs) {
   HBI_HIP(B.ws.reserve(std::max<size_t>(wsmax, 256)));
 }
 
+// XCD-aware placement of one stage's work items (four per workgroup, one
+// per wave).  Workgroups are dispatched round-robin to the GPU's eight
+// XCDs (workgroup b to XCD b % 8), each with its own L2, so items that read
+// the same operands (a transfer unit's inputs and factors, a leaf's inputs)
+// are put on one XCD, in consecutive slots of its sequence of workgroups
+// b = 8 q + x: their repeated reads then hit that L2 instead of going to
+// memory once per XCD.  Groups are taken in decreasing `key` (the longest
+// items first) and each goes to the XCD with the least work so far; slots
+// left over are empty items (Np = 0).
+constexpr int kXcds = 8;
+
+template <typename It> struct ItemGroups {
+  std::vector<It> items;              // group g = items[start[g] .. start[g + 1])
+  std::vector<size_t> start{0};
+  std::vector<double> key, work;
+  void close(double k, double w) {
+    if (items.size() == start.back()) return;
+    start.push_back(items.size());
+    key.push_back(k);
+    work.push_back(w);
+  }
+};
+
+template <typename It> std::vector<It> xcd_place(const ItemGroups<It> &G) {
+  const size_t ng = G.key.size();
+  std::vector<size_t> order(ng);
+  for (size_t g = 0; g < ng; ++g) order[g] = g;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](size_t a, size_t b) { return G.key[a] > G.key[b]; });
+  std::vector<std::vector<It>> q(kXcds);
+  std::vector<double> load(kXcds, 0.0);
+  for (size_t g : order) {
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    q[x].insert(q[x].end(), G.items.begin() + G.start[g], G.items.begin() + G.start[g + 1]);
+    load[x] += G.work[g];
+  }
+  size_t nwg = 0;
+  for (auto &v : q) nwg = std::max(nwg, (v.size() + 3) / 4);
+  std::vector<It> out(nwg * kXcds * 4, It{});
+  for (int x = 0; x < kXcds; ++x)
+    for (size_t p = 0; p < q[x].size(); ++p) out[4 * (kXcds * (p / 4) + x) + p % 4] = q[x][p];
+  return out;
+}
+
 // Work items of every stage of every pass for `nb` column tiles per wave.
 void build_items(BatchCache &B, int nb) {
   const size_t esz = B.prec == HBI_F64 ? 16 : 8;
@@ -1794,8 +1838,8 @@ void build_items(BatchCache &B, int nb) {
     P.maxNv = 0;
     P.maxjt = 0;
     int Lmax = 0;
-    std::vector<MVItem> vi;
-    std::vector<MFItem> fi;
+    ItemGroups<MVItem> vi;
+    ItemGroups<MFItem> fi;
     for (int q : P.jobs) {
       const MultiJob &J = B.jobs[q];
       hbi_ctx *c = J.c;
@@ -1809,18 +1853,26 @@ void build_items(BatchCache &B, int nb) {
       for (int64_t g = 0; g < (int64_t)c->leaves_h.size(); ++g) {
         const LeafInfo &lf = c->leaves_h[g];
         const char *x = xt + (int64_t)lf.start * J.Np * esz;
-        for (int l = 0; l < Lv; ++l) {
-          const VDesc &d = c->vd_h[g * Lv + l];
-          for (int r0 = 0; r0 < d.r; r0 += 16)
-            for (int gq = 0; gq < ngrp; ++gq)
-              vi.push_back(MVItem{F + d.foff * esz, c->Fi.as<uint16_t>() + d.ioff, x,
-                                  zb + d.zout * J.Np * esz, d.r, lf.size, r0, gq * nb, J.Np, 0});
-        }
-        for (int r0 = 0; r0 < lf.size; r0 += 16)
-          for (int gq = 0; gq < ngrp; ++gq)
-            fi.push_back(MFItem{F, zb, x, yt + (int64_t)lf.start * J.Np * esz,
-                                c->kd_d.as<KDesc>() + g * Lv, lf.dense_off, lf.size, Lv, r0,
-                                gq * nb, J.Np, 0});
+        // one group per leaf: every item reads the leaf's inputs x
+        double vw = 0.0, fw = lf.size;
+        for (int gq = 0; gq < ngrp; ++gq)
+          for (int l = 0; l < Lv; ++l) {
+            const VDesc &d = c->vd_h[g * Lv + l];
+            for (int r0 = 0; r0 < d.r; r0 += 16) {
+              vi.items.push_back(MVItem{F + d.foff * esz, c->Fi.as<uint16_t>() + d.ioff, x,
+                                        zb + d.zout * J.Np * esz, d.r, lf.size, r0, gq * nb,
+                                        J.Np, 0});
+              vw += lf.size - d.r;
+            }
+          }
+        vi.close(lf.size, vw);
+        for (int l = 0; l < Lv; ++l) fw += c->kd_h[g * Lv + l].r;
+        for (int gq = 0; gq < ngrp; ++gq)
+          for (int r0 = 0; r0 < lf.size; r0 += 16)
+            fi.items.push_back(MFItem{F, zb, x, yt + (int64_t)lf.start * J.Np * esz,
+                                      c->kd_d.as<KDesc>() + g * Lv, lf.dense_off, lf.size, Lv, r0,
+                                      gq * nb, J.Np, 0});
+        fi.close(fw, fw * ((lf.size + 15) / 16) * ngrp);
       }
       const size_t cofs = (size_t)J.j0 * esz;
       P.jin.push_back(MTrans{(const char *)B.s_ptr[J.prob] + cofs * B.ld[J.prob], xt,
@@ -1836,9 +1888,10 @@ void build_items(BatchCache &B, int nb) {
       P.stages.push_back(MStagePlan{kind, nb, d.p, n});
       P.bufs.push_back(std::move(d));
     };
-    add_stage(0, vi.data(), vi.size() * sizeof(MVItem), (int64_t)vi.size());
+    const std::vector<MVItem> vp = xcd_place(vi);
+    add_stage(0, vp.data(), vp.size() * sizeof(MVItem), (int64_t)vp.size());
     for (int k = 1; k <= Lmax; ++k) {
-      std::vector<std::pair<int64_t, MWItem>> wi;
+      ItemGroups<MWItem> wi;
       for (int q : P.jobs) {
         const MultiJob &J = B.jobs[q];
         hbi_ctx *c = J.c;
@@ -1847,39 +1900,38 @@ void build_items(BatchCache &B, int nb) {
         char *zb = ws + J.z_off * esz;
         const int ngrp = (J.Np / 16 + nb - 1) / nb;
         const uint16_t *fidx = c->Fi.as<uint16_t>();
+        // one group per unit (its inputs and factors are read by every
+        // item), column-tile groups outermost
         for (const WUnit &U : c->units_h[k]) {
-          if (U.ra + U.rb <= 32) {
-            // a small pair: stacked tiles, entries synthesised from T
-            for (int r0 = 0; r0 < U.ra + U.rb; r0 += 16)
-              for (int gq = 0; gq < ngrp; ++gq)
-                wi.push_back({(int64_t)U.c,
-                              MWItem{F + U.foff * esz, fidx + U.ioff, zb + U.zin * J.Np * esz,
-                                     zb + U.zouta * J.Np * esz, zb + U.zoutb * J.Np * esz, U.ra,
-                                     U.rb, U.c, r0, gq * nb, J.Np}});
-            continue;
+          const size_t n0 = wi.items.size();
+          for (int gq = 0; gq < ngrp; ++gq) {
+            if (U.ra + U.rb <= 32) {
+              // a small pair: stacked tiles, entries synthesised from T
+              for (int r0 = 0; r0 < U.ra + U.rb; r0 += 16)
+                wi.items.push_back(MWItem{F + U.foff * esz, fidx + U.ioff, zb + U.zin * J.Np * esz,
+                                          zb + U.zouta * J.Np * esz, zb + U.zoutb * J.Np * esz,
+                                          U.ra, U.rb, U.c, r0, gq * nb, J.Np});
+              continue;
+            }
+            for (int h = 0; h < 2; ++h) {
+              // child a, then child b (T_b after T_a, ib after ia)
+              const int32_t r = h ? U.rb : U.ra;
+              const int64_t toff = U.foff + (h ? (int64_t)U.ra * (U.c - U.ra) : 0);
+              const uint16_t *idx = fidx + U.ioff + (h ? U.c : 0);
+              char *zo = zb + (h ? U.zoutb : U.zouta) * J.Np * esz;
+              for (int r0 = 0; r0 < r; r0 += 16)
+                wi.items.push_back(MWItem{F + toff * esz, idx, zb + U.zin * J.Np * esz, zo,
+                                          nullptr, r, -1, U.c, r0, gq * nb, J.Np});
+            }
           }
-          for (int h = 0; h < 2; ++h) {
-            // child a, then child b (T_b after T_a, ib after ia)
-            const int32_t r = h ? U.rb : U.ra;
-            const int64_t toff = U.foff + (h ? (int64_t)U.ra * (U.c - U.ra) : 0);
-            const uint16_t *idx = fidx + U.ioff + (h ? U.c : 0);
-            char *zo = zb + (h ? U.zoutb : U.zouta) * J.Np * esz;
-            for (int r0 = 0; r0 < r; r0 += 16)
-              for (int gq = 0; gq < ngrp; ++gq)
-                wi.push_back({(int64_t)U.c, MWItem{F + toff * esz, idx, zb + U.zin * J.Np * esz,
-                                                   zo, nullptr, r, -1, U.c, r0, gq * nb, J.Np}});
-          }
+          wi.close(U.c, (double)U.c * (wi.items.size() - n0));
         }
       }
-      std::stable_sort(wi.begin(), wi.end(), [](const std::pair<int64_t, MWItem> &a,
-                                                const std::pair<int64_t, MWItem> &b) {
-        return a.first > b.first;
-      });
-      std::vector<MWItem> w(wi.size());
-      for (size_t q = 0; q < wi.size(); ++q) w[q] = wi[q].second;
+      const std::vector<MWItem> w = xcd_place(wi);
       add_stage(1, w.data(), w.size() * sizeof(MWItem), (int64_t)w.size());
     }
-    add_stage(2, fi.data(), fi.size() * sizeof(MFItem), (int64_t)fi.size());
+    const std::vector<MFItem> fp = xcd_place(fi);
+    add_stage(2, fp.data(), fp.size() * sizeof(MFItem), (int64_t)fp.size());
     upload(P.jin_d, P.jin);
     upload(P.jout_d, P.jout);
   }
@@ -1900,8 +1952,8 @@ void build_items_adj(BatchCache &B, int nb) {
     P.maxNv = 0;
     P.maxjt = 0;
     int Lmax = 0;
-    std::vector<MFAItem> ki;
-    std::vector<MVAItem> li;
+    ItemGroups<MFAItem> ki;
+    ItemGroups<MVAItem> li;
     for (int q : P.jobs) {
       const MultiJob &J = B.jobs[q];
       hbi_ctx *c = J.c;
@@ -1916,18 +1968,26 @@ void build_items_adj(BatchCache &B, int nb) {
       for (int64_t g = 0; g < (int64_t)c->leaves_h.size(); ++g) {
         const LeafInfo &lf = c->leaves_h[g];
         const char *y = xt + (int64_t)lf.start * J.Np * esz;
-        for (int l = 0; l < Lv; ++l) {
-          const KDesc &d = c->kd_h[g * Lv + l];
-          for (int r0 = 0; r0 < d.r; r0 += 16)
-            for (int gq = 0; gq < ngrp; ++gq)
-              ki.push_back(MFAItem{F + d.foff * esz, y, zb + d.zin * J.Np * esz, d.r, lf.size, r0,
-                                   gq * nb, J.Np, 0});
-        }
-        for (int r0 = 0; r0 < lf.size; r0 += 16)
-          for (int gq = 0; gq < ngrp; ++gq)
-            li.push_back(MVAItem{F, c->Fi.as<uint16_t>(), y, yt + (int64_t)lf.start * J.Np * esz,
-                                 c->vd_d.as<VDesc>() + g * Lv, zb, lf.dense_off, hd, lf.size, Lv,
-                                 r0, gq * nb, J.Np, 0});
+        // one group per leaf: every item reads the leaf's inputs y
+        double kw = 0.0, lw = lf.size;
+        for (int gq = 0; gq < ngrp; ++gq)
+          for (int l = 0; l < Lv; ++l) {
+            const KDesc &d = c->kd_h[g * Lv + l];
+            for (int r0 = 0; r0 < d.r; r0 += 16) {
+              ki.items.push_back(MFAItem{F + d.foff * esz, y, zb + d.zin * J.Np * esz, d.r,
+                                         lf.size, r0, gq * nb, J.Np, 0});
+              kw += lf.size;
+            }
+          }
+        ki.close(lf.size, kw);
+        for (int l = 0; l < Lv; ++l) lw += c->vd_h[g * Lv + l].r;
+        for (int gq = 0; gq < ngrp; ++gq)
+          for (int r0 = 0; r0 < lf.size; r0 += 16)
+            li.items.push_back(MVAItem{F, c->Fi.as<uint16_t>(), y,
+                                       yt + (int64_t)lf.start * J.Np * esz,
+                                       c->vd_d.as<VDesc>() + g * Lv, zb, lf.dense_off, hd, lf.size,
+                                       Lv, r0, gq * nb, J.Np, 0});
+        li.close(lw, lw * ((lf.size + 15) / 16) * ngrp);
       }
       const size_t cofs = (size_t)J.j0 * esz;
       P.jin.push_back(MTrans{(const char *)B.s_ptr[J.prob] + cofs * B.ld[J.prob], xt,
@@ -1942,9 +2002,10 @@ void build_items_adj(BatchCache &B, int nb) {
       P.stages.push_back(MStagePlan{kind, nb, d.p, n});
       P.bufs.push_back(std::move(d));
     };
-    add_stage(3, ki.data(), ki.size() * sizeof(MFAItem), (int64_t)ki.size());
+    const std::vector<MFAItem> kp = xcd_place(ki);
+    add_stage(3, kp.data(), kp.size() * sizeof(MFAItem), (int64_t)kp.size());
     for (int k = Lmax; k >= 1; --k) {
-      std::vector<std::pair<int64_t, MWAItem>> wi;
+      ItemGroups<MWAItem> wi;
       for (int q : P.jobs) {
         const MultiJob &J = B.jobs[q];
         hbi_ctx *c = J.c;
@@ -1953,23 +2014,21 @@ void build_items_adj(BatchCache &B, int nb) {
         char *zb = ws + J.z_off * esz;
         const int ngrp = (J.Np / 16 + nb - 1) / nb;
         const uint16_t *fidx = c->Fi.as<uint16_t>();
-        for (const WUnit &U : c->units_h[k])
-          for (int r0 = 0; r0 < U.c; r0 += 16)
-            for (int gq = 0; gq < ngrp; ++gq)
-              wi.push_back({(int64_t)(U.ra + U.rb),
-                            MWAItem{F + U.foff * esz, fidx + U.ioff, zb + U.zin * J.Np * esz,
-                                    zb + U.zouta * J.Np * esz, zb + U.zoutb * J.Np * esz, U.ra,
-                                    U.rb, U.c, r0, gq * nb, J.Np}});
+        // one group per unit (every item reads its za, zb and factors)
+        for (const WUnit &U : c->units_h[k]) {
+          for (int gq = 0; gq < ngrp; ++gq)
+            for (int r0 = 0; r0 < U.c; r0 += 16)
+              wi.items.push_back(MWAItem{F + U.foff * esz, fidx + U.ioff, zb + U.zin * J.Np * esz,
+                                         zb + U.zouta * J.Np * esz, zb + U.zoutb * J.Np * esz,
+                                         U.ra, U.rb, U.c, r0, gq * nb, J.Np});
+          wi.close(U.ra + U.rb, (double)(U.ra + U.rb) * ((U.c + 15) / 16) * ngrp);
+        }
       }
-      std::stable_sort(wi.begin(), wi.end(), [](const std::pair<int64_t, MWAItem> &a,
-                                                const std::pair<int64_t, MWAItem> &b) {
-        return a.first > b.first;
-      });
-      std::vector<MWAItem> w(wi.size());
-      for (size_t q = 0; q < wi.size(); ++q) w[q] = wi[q].second;
+      const std::vector<MWAItem> w = xcd_place(wi);
       add_stage(4, w.data(), w.size() * sizeof(MWAItem), (int64_t)w.size());
     }
-    add_stage(5, li.data(), li.size() * sizeof(MVAItem), (int64_t)li.size());
+    const std::vector<MVAItem> lp = xcd_place(li);
+    add_stage(5, lp.data(), lp.size() * sizeof(MVAItem), (int64_t)lp.size());
     upload(P.jin_d, P.jin);
     upload(P.jout_d, P.jout);
   }

@@ -13,7 +13,8 @@ namespace hbi {
 //    [X_a; X_b], its entries synthesised from T_a (at T), T_b (after it) and
 //    the inverse orders pa, pb (idx: the unit's lists ia, ib, pa, pb), so a
 //    small pair shares tiles and its B rows are read in order.
-// Vector pointers are absolute.
+// Vector pointers are absolute.  In every item kind Np = 0 marks an empty
+// slot (the wave returns at once).
 struct MWItem {
   const void *T;
   const uint16_t *idx;

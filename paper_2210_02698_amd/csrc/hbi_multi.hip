@@ -64,17 +64,26 @@ template <typename C> __device__ __forceinline__ void stg(C *p, int64_t i, C v) 
 
 // Accumulate a 16-row tile of M (rows r0.., column-major, leading dimension
 // ldm, `rows` valid rows, `k` columns) times Z (k x Np, row stride Np),
-// for column tiles [jt0, jt0 + NB) of 16 columns each.  KU k-steps (4 KU
-// columns of M; KU = 8 for NB = 1, else 4) are loaded before their MFMAs
-// are issued, so each wave keeps KU (1 + NB) loads in flight; the index
-// loads of those steps (zrow, or the A loader's) are issued first, so the
-// gathers wait on one round trip.  Steps past the last column issue loads
-// (clamped) but no MFMAs.
+// for column tiles [jt0, jt0 + NB) of 16 columns each.
 // With `zrow` non-null, row kk of Z is zrow[kk] (a gather of the inputs).
 // The A entries come from aload.value(row, aload.index(row, kk), valid)
-// when an A loader is given, else M[row + kk ldm].
+// when an A loader is given, else M[row + kk ldm]; rows at or past ksplit
+// come from Z2 (row - ksplit).
+//
+// The k columns go in chunks of KU MFMA k-steps (4 KU columns), software
+// pipelined two deep: while the MFMAs of chunk i run, the data loads of
+// chunk i + 1 (A entries and B rows) and the index loads of chunk i + 2
+// (zrow, or the A loader's) are in flight, so a wave waits on memory only
+// when the MFMAs cannot cover a round trip.  Loads of chunks past the end
+// read clamped, valid addresses and are zeroed; so are out-of-range rows,
+// columns and column tiles, whose MFMAs then add zeros (a wave-uniform
+// branch around them would split the loop into blocks and let the compiler
+// sink each load into the block that uses it).  An empty asm statement
+// with a memory clobber after each batch of loads keeps them there.
 struct NoLoad {};
-template <typename R, int NB, typename AL = NoLoad>
+__device__ __forceinline__ void load_fence() { __asm__ volatile("" ::: "memory"); }
+
+template <typename R, int NB, typename AL = NoLoad, bool GATHER = false>
 __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int ldm, int r0,
                                           int rows, int k, const cplx_t<R> *__restrict__ Z,
                                           int Np, int jt0, int lane,
@@ -84,7 +93,8 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
                                           const cplx_t<R> *__restrict__ Z2 = nullptr,
                                           int ksplit = 1 << 30) {
   using C = cplx_t<R>;
-  constexpr int KU = NB == 1 ? 8 : 4;   // registers allow twice the steps at NB = 1
+  constexpr int KU = NB == 1 ? 4 : NB == 2 ? 2 : 1;   // k-steps per chunk
+  constexpr int STEP = 4 * KU;                        // columns per chunk
   constexpr bool synth = !std::is_same<AL, NoLoad>::value;
   const int li = lane & 15, lk = lane >> 4;
   const int row = r0 + li;
@@ -92,69 +102,70 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
   const int zc = jt0 * 16 + li;
   // column tiles past Np (last group of a row) are never read
   const int nbv = (Np >> 4) - jt0 < NB ? (Np >> 4) - jt0 : NB;
-  for (int k0 = 0; k0 < k; k0 += 4 * KU) {
-    C a[KU], b[KU][NB];
-    int zr[KU], pa[KU];
-    // Out-of-range entries (rows, columns or column tiles) read entry 0
-    // (valid: rows, k >= 1) and are then replaced by zero, so that the
-    // loads need no branches.
+  struct Idx { int zr[KU], pa[KU]; };
+  struct Dat { C a[KU], b[KU][NB]; };
+  auto load_idx = [&](int k0, Idx &I) {
 #pragma unroll
     for (int u = 0; u < KU; ++u) {
       const int kk = k0 + 4 * u + lk;
       const bool kok = kk < k;
-      zr[u] = zrow ? ldg16(zrow, kok ? kk : 0) : kk;
-      if constexpr (synth) pa[u] = aload.index(row, (rok && kok) ? kk : 0);
+      if constexpr (GATHER) I.zr[u] = ldg16(zrow, kok ? kk : 0);
+      else I.zr[u] = kk;
+      if constexpr (synth) I.pa[u] = aload.index(row, (rok && kok) ? kk : 0);
     }
-    // then the loads that need no index (A, or B of a stacked tile), then
-    // the ones that do
+  };
+  auto load_dat = [&](int k0, const Idx &I, Dat &D) {
 #pragma unroll
     for (int u = 0; u < KU; ++u) {
       const int kk = k0 + 4 * u + lk;
       const bool kok = kk < k;
-      if constexpr (synth) {
-        // rows at or past ksplit come from the second block (row - ksplit)
-        const bool second = Z2 && kok && kk >= ksplit;
-        const C *Zb = second ? Z2 : Z;
-        const int zrow_b = second ? zr[u] - ksplit : zr[u];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const bool ok = kok && nb < nbv;
-          const C v = ldg(Zb, (int64_t)(ok ? zrow_b : 0) * Np + zc + (ok ? nb * 16 : 0));
-          b[u][nb] = ok ? v : C{0, 0};
-        }
-      } else {
-        const C v = ldg(M, (rok && kok) ? row + (int64_t)kk * ldm : 0);
-        a[u] = (rok && kok) ? v : C{0, 0};
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < KU; ++u) {
-      const int kk = k0 + 4 * u + lk;
-      const bool kok = kk < k;
-      if constexpr (synth) {
-        a[u] = aload.value(row, pa[u], rok && kok);
-      } else {
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const bool ok = kok && nb < nbv;
-          const C v = ldg(Z, (int64_t)(ok ? zr[u] : 0) * Np + zc + (ok ? nb * 16 : 0));
-          b[u][nb] = ok ? v : C{0, 0};
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < KU; ++u) {
-      if (k0 + 4 * u >= k) break;   // wave-uniform: steps past the last column
-      const R nai = -a[u].y;
+      const bool second = Z2 && kok && kk >= ksplit;
+      const C *Zb = second ? Z2 : Z;
+      const int zrb = second ? I.zr[u] - ksplit : I.zr[u];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        if (nb >= nbv) break;   // wave-uniform: no MFMAs on padding tiles
-        ar[nb] = Mfma<R>::op(a[u].x, b[u][nb].x, ar[nb]);
-        ar[nb] = Mfma<R>::op(nai, b[u][nb].y, ar[nb]);
-        ai[nb] = Mfma<R>::op(a[u].x, b[u][nb].y, ai[nb]);
-        ai[nb] = Mfma<R>::op(a[u].y, b[u][nb].x, ai[nb]);
+        const bool ok = kok && nb < nbv;
+        const C v = ldg(Zb, (int64_t)(ok ? zrb : 0) * Np + zc + (ok ? nb * 16 : 0));
+        D.b[u][nb] = ok ? v : C{0, 0};
+      }
+      if constexpr (synth) {
+        D.a[u] = aload.value(row, I.pa[u], rok && kok);
+      } else {
+        const C v = ldg(M, (rok && kok) ? row + (int64_t)kk * ldm : 0);
+        D.a[u] = (rok && kok) ? v : C{0, 0};
       }
     }
+  };
+  auto mma = [&](const Dat &D) {
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const R nai = -D.a[u].y;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        ar[nb] = Mfma<R>::op(D.a[u].x, D.b[u][nb].x, ar[nb]);
+        ar[nb] = Mfma<R>::op(nai, D.b[u][nb].y, ar[nb]);
+        ai[nb] = Mfma<R>::op(D.a[u].x, D.b[u][nb].y, ai[nb]);
+        ai[nb] = Mfma<R>::op(D.a[u].y, D.b[u][nb].x, ai[nb]);
+      }
+    }
+  };
+  // Loads complete in issue order, so the index loads of a chunk are issued
+  // before the data loads of the chunk ahead of it: using the indices then
+  // never waits for data loads.  One chunk per iteration (a single exit
+  // keeps the accumulators in place); the buffers rotate at its end.
+  Idx In, Inn;
+  Dat Dc, Dn;
+  load_idx(0, In);
+  load_idx(STEP, Inn);
+  load_dat(0, In, Dc);
+  load_fence();
+  for (int k0 = 0; k0 < k; k0 += STEP) {
+    In = Inn;
+    load_idx(k0 + 2 * STEP, Inn);
+    load_dat(k0 + STEP, In, Dn);
+    load_fence();
+    mma(Dc);
+    Dc = Dn;
   }
 }
 
@@ -271,6 +282,7 @@ __global__ __launch_bounds__(256) void k_wstage_mr(const MWItem *items, int64_t 
   const int64_t it = (int64_t)blockIdx.x * 4 + wave;
   if (it >= nitems) return;
   const MWItem W = items[it];
+  if (W.Np == 0) return;   // a free slot of the XCD placement
   A ar[NB], ai[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) { ar[nb] = Mfma<R>::zero(); ai[nb] = Mfma<R>::zero(); }
@@ -303,8 +315,8 @@ __global__ __launch_bounds__(256) void k_wstage_mr(const MWItem *items, int64_t 
     return;
   }
   // T times the non-skeleton inputs (rows idx[r..c) of Z)
-  tile_gemm<R, NB>((const C *)W.T, W.r, W.r0, W.r, W.c - W.r, Z, W.Np, jt0, lane, ar, ai,
-                   W.idx + W.r);
+  tile_gemm<R, NB, NoLoad, true>((const C *)W.T, W.r, W.r0, W.r, W.c - W.r, Z, W.Np, jt0, lane,
+                                 ar, ai, W.idx + W.r);
   // plus the skeleton input of each row (the identity part of X)
   add_skeleton_rows<R, NB>(W.idx, W.r, W.r0, Z, (C *)W.zout, W.Np, jt0, nbv, lane, ar, ai);
 }
@@ -319,14 +331,15 @@ __global__ __launch_bounds__(256) void k_vstage_mr(const MVItem *items, int64_t 
   const int64_t it = (int64_t)blockIdx.x * 4 + wave;
   if (it >= nitems) return;
   const MVItem W = items[it];
+  if (W.Np == 0) return;   // a free slot of the XCD placement
   A ar[NB], ai[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) { ar[nb] = Mfma<R>::zero(); ai[nb] = Mfma<R>::zero(); }
   const int nbv = (W.Np >> 4) - W.jt < NB ? (W.Np >> 4) - W.jt : NB;
   const C *X = (const C *)W.x;
   // T times the non-skeleton inputs (rows idx[r..sz) of x)
-  tile_gemm<R, NB>((const C *)W.T, W.r, W.r0, W.r, W.sz - W.r, X, W.Np, W.jt, lane, ar, ai,
-                   W.idx + W.r);
+  tile_gemm<R, NB, NoLoad, true>((const C *)W.T, W.r, W.r0, W.r, W.sz - W.r, X, W.Np, W.jt,
+                                 lane, ar, ai, W.idx + W.r);
   // plus the skeleton input of each row
   add_skeleton_rows<R, NB>(W.idx, W.r, W.r0, X, (C *)W.z, W.Np, W.jt, nbv, lane, ar, ai);
 }
@@ -343,6 +356,7 @@ __global__ __launch_bounds__(256) void k_final_mr(const MFItem *items, int64_t n
   const int64_t it = (int64_t)blockIdx.x * 4 + wave;
   if (it >= nitems) return;
   const MFItem W = items[it];
+  if (W.Np == 0) return;   // a free slot of the XCD placement
   A ar[NB], ai[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) { ar[nb] = Mfma<R>::zero(); ai[nb] = Mfma<R>::zero(); }
@@ -399,6 +413,7 @@ __global__ __launch_bounds__(256) void k_final_adj_mr(const MFAItem *items, int6
   const int64_t it = (int64_t)blockIdx.x * 4 + wave;
   if (it >= nitems) return;
   const MFAItem W = items[it];
+  if (W.Np == 0) return;   // a free slot of the XCD placement
   A ar[NB], ai[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) { ar[nb] = Mfma<R>::zero(); ai[nb] = Mfma<R>::zero(); }
@@ -420,6 +435,7 @@ __global__ __launch_bounds__(256) void k_wstage_adj_mr(const MWAItem *items, int
   const int64_t it = (int64_t)blockIdx.x * 4 + wave;
   if (it >= nitems) return;
   const MWAItem W = items[it];
+  if (W.Np == 0) return;   // a free slot of the XCD placement
   A ar[NB], ai[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) { ar[nb] = Mfma<R>::zero(); ai[nb] = Mfma<R>::zero(); }
@@ -451,6 +467,7 @@ __global__ __launch_bounds__(256) void k_vstage_adj_mr(const MVAItem *items, int
   const int64_t it = (int64_t)blockIdx.x * 4 + wave;
   if (it >= nitems) return;
   const MVAItem W = items[it];
+  if (W.Np == 0) return;   // a free slot of the XCD placement
   A ar[NB], ai[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) { ar[nb] = Mfma<R>::zero(); ai[nb] = Mfma<R>::zero(); }
