@@ -12,6 +12,9 @@ Default run (`python bench.py`), one JSON line:
     call (MFMA tiles, replayed HIP graph).
   * "3d": 3D sinusoid n = 1 + 0.2 sin 2pi x sin 2pi y sin 2pi z on 64^3
     cells, 32 RHS, FP32 factors at tol 1e-6, MFMA tiles.
+  * "tables": the tau^2, v0, v1 tables of the paper's 2D sinusoidal medium
+    (13 x 13 Chebyshev nodes, h0 = 0.01) from the eikonal and transport
+    solves (hbi_tabulate), in source nodes per second.
 
 Each workload: build seconds (wall time of hbi_build), the relative L2
 error against the FP64 CPU oracle on seeded rows (and the worst row), W
@@ -25,7 +28,7 @@ the rows it computes are the parity references.  Also the C1 workload
 (2D homogeneous, 64^2 cells) as a full dense oracle apply and as a
 stored-dense K @ s product on all workers' cores.
 
---workload picks one workload alone (bump, batched, 3d, sweep, inclusion), or
+--workload picks one workload alone (bump, batched, 3d, tables, sweep, inclusion), or
 the complexity sweep (storage and build time over sizes).
 """
 from __future__ import annotations
@@ -85,6 +88,19 @@ def _oracle_task(args):
     import oracle
     prob, S = _JOBS[key]
     return key, rows, oracle.apply(prob, S, rows)
+
+
+def _table_task(args):
+    key, rows = args
+    import numpy as np
+    import hb_inputs
+    from oracle import hb_tables as ht
+    med, P, h0, lo, hi = _JOBS[key]
+    out = []
+    for b in rows:
+        r = ht.solve_source(med.slowness, hb_inputs.n2_taylor(med, P[b]), P[b], lo, hi, h0)
+        out.append(float(sum(r[5])))
+    return key, rows, np.array(out)
 
 
 def _dense_task(args):
@@ -285,6 +301,17 @@ def cpu_phase(work, args):
                                 f"FP64 oracle, {W} worker processes, {dt:.1f} s wall",
                       "cpu": info}
         log(f"cpu: 3d {outs} outputs in {dt:.1f}s")
+    if "tables" in work:
+        w = work["tables"]
+        res, dt = run_pool(split_rows("tables", w["sample"], 1), _table_task, W)
+        n = len(w["sample"])
+        base["tables"] = {"value": n / dt, "unit": "sources/s", "cores": min(W, n),
+                          "kind": "oracle",
+                          "sample": f"{n} seeded source nodes of the 169, each solved by the "
+                                    f"table oracle (C sweeps, one thread per source), "
+                                    f"{min(W, n)} worker processes, {dt:.1f} s wall",
+                          "cpu": info}
+        log(f"cpu: tables {n} sources in {dt:.1f}s")
     if "c1" in work:
         w = work["c1"]
         prob = w["prob"]
@@ -541,6 +568,65 @@ def run_sweep(args):
     print(json.dumps(line), flush=True)
 
 
+TAB_FLOPS_PER_UPDATE = 290   # FP64 operations of one sweep point update (two WENO5
+                             # one-sided derivatives per axis, the numerical Hamiltonian)
+FP64_VALU_PEAK_TFLOPS = 78.6
+
+
+def prepare_tables(args):
+    """Inputs of the table generation: the paper's 2D sinusoidal medium
+    (Sec. 5.1) with its table sizes, nI = 13 nodes per axis on the unit square
+    and h0 = 0.01; n^2 on a grid of spacing h0/4 and its Taylor coefficients
+    at the 169 nodes."""
+    import numpy as np
+    import hb_inputs
+    from oracle import hb_tables as ht
+    med = hb_inputs.Sinusoid2D()
+    nI, h0, margin = 13, 0.01, 8
+    lo, hi = (0.0, 0.0), (1.0, 1.0)
+    t0 = time.time()
+    P = hb_inputs.node_coords(2, nI, (1, 1), lo, 1.0)
+    taylor = hb_inputs.taylor_at(med, P)
+    n2, org, sp = hb_inputs.medium_grid(med, lo, hi, h0 / 4, pad=4 * (margin + 4))
+    log(f"tables: inputs {time.time() - t0:.1f}s")
+    _JOBS["tables"] = (med, ht.node_coords(nI, (1, 1), lo, 1.0), h0, lo, hi)
+    sample = np.sort(np.random.default_rng([13, 1]).choice(P.shape[0], 16, replace=False))
+    return dict(med=med, nI=nI, h0=h0, margin=margin, n2=n2, org=org, sp=sp, taylor=taylor,
+                NT=P.shape[0], sample=sample)
+
+
+def gpu_tables(args, w, cpu):
+    """hbi_tabulate on the prepared inputs: wall time per call (inputs host to
+    device, the 169 sources' solves, tables back), the solves' kernel time
+    and point updates from hbi_get_info."""
+    import torch
+    import paper_2210_02698_amd as hbi
+    run = lambda: hbi.tabulate(w["n2"], w["org"], w["sp"], w["taylor"], w["nI"], (1, 1),
+                               (0.0, 0.0), 1.0, w["h0"], w["margin"], info=True)
+    run()                                   # warm-up
+    steps = max(1, min(args.steps, 3))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        *_, st = run()
+    t = (time.perf_counter() - t0) / steps
+    achieved = st["tab_point_updates"] * TAB_FLOPS_PER_UPDATE / st["tab_s"] / 1e12
+    return {"value": round(w["NT"] / t, 3), "unit": "sources/s", "ms_per_step": round(t * 1e3, 2),
+            "steps": steps, "dtype": "f64",
+            "config": {"workload": "2D sinusoidal medium n = 1/(1 + 0.2 sin(pi(x+0.05)) "
+                                   "sin(pi y/2)), 13x13 Chebyshev source nodes, h0 = 0.01 "
+                                   "(117^2-point grids), tau^2 / v0 / v1 tables",
+                       "NT": w["NT"], "h0": w["h0"], "margin": w["margin"]},
+            "solve_s": round(st["tab_s"], 4), "rounds_max": st["tab_rounds_max"],
+            "point_updates": st["tab_point_updates"],
+            "roofline": {"bound": "alu", "kernel": "k_tab_source",
+                         "achieved": round(achieved, 4), "peak": FP64_VALU_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 5),
+                         "flops_per_point_update": TAB_FLOPS_PER_UPDATE, "traffic": None},
+            "parity": "tests/test_gpu_tabulate.py (tables against the oracle to 1e-8)",
+            "cpu_baseline": cpu}
+
+
 def run_inclusion(args):
     """Total field with a curve inclusion (eq. m_v2v_inclu): 2D Gaussian bump
     256^2 at omega = 64 pi, an open square of side 0.8 centred in the domain
@@ -680,13 +766,15 @@ def main():
     ap.add_argument("--rows-3d", type=int, default=512)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=["all", "bump", "batched", "3d", "sweep", "inclusion",
-                                           "complexity"],
+    ap.add_argument("--workload", choices=["all", "bump", "batched", "3d", "tables", "sweep",
+                                           "inclusion", "complexity"],
                     default="all",
                     help="all: the headline bump line with the batched and 3d workloads beside "
                          "it; bump: the 1024^2 single-RHS apply alone; batched: 64 "
                          "constant-gradient problems with 1-256 RHS each; 3d: 64^3 sinusoid "
-                         "with 32 RHS; sweep: four frequencies from one table set, 16 RHS "
+                         "with 32 RHS; tables: the tau^2/v0/v1 tables of the 2D sinusoidal "
+                         "medium from the eikonal and transport solves; sweep: four "
+                         "frequencies from one table set, 16 RHS "
                          "each; inclusion: 256^2 bump with an open-square curve inclusion; "
                          "complexity: storage and build time over sizes")
     ap.add_argument("--nprob", type=int, default=64)
@@ -706,7 +794,8 @@ def main():
         return run_complexity(args)
 
     # CPU phase (no GPU touched yet): inputs, then the oracle on the pool
-    want = {"all": ("bump", "batched", "3d", "c1")}.get(args.workload, (args.workload,))
+    want = {"all": ("bump", "batched", "3d", "tables", "c1")}.get(args.workload,
+                                                                   (args.workload,))
     work = {}
     if "bump" in want:
         work["bump"] = prepare_bump(args)
@@ -714,6 +803,8 @@ def main():
         work["batched"] = prepare_batched(args)
     if "3d" in want:
         work["3d"] = prepare_3d(args)
+    if "tables" in want:
+        work["tables"] = prepare_tables(args)
     if "c1" in want and not args.no_cpu:
         work["c1"] = prepare_c1()
     refs, base = ({}, {}) if args.no_cpu else cpu_phase(work, args)
@@ -755,6 +846,18 @@ def main():
             if "fp64" in line:
                 # the FP32 many-RHS apply against the FP64 single-RHS apply
                 obj["speedup_over_fp64_single_rhs"] = round(obj["value"] / line["fp64"]["value"], 2)
+    if "tables" in work:
+        obj = gpu_tables(args, work["tables"], base.get("tables"))
+        if line is None:
+            line = {"metric": "HB table generation sources/s (eikonal and transport solves)",
+                    "value": obj["value"], "unit": obj["unit"], "n_gpus": 1,
+                    "steps": obj["steps"], "warmup": 1, "ms_per_step": obj["ms_per_step"],
+                    "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                    "dtype": obj["dtype"], "data": "synthetic (the paper's medium in closed form)",
+                    "config": dict(obj["config"], parallelism="single GPU"),
+                    "roofline": obj["roofline"], "cpu_baseline": obj["cpu_baseline"]}
+        else:
+            line["tables"] = obj
     if "c1" in base:
         line["cpu_dense_c1"] = base["c1"]
     print(json.dumps(line), flush=True)

@@ -329,13 +329,15 @@ def apply_batched(ops, S, out=None):
 
 
 def tabulate(n2, origin, spacing, taylor, nI, nbox, box_origin, box_size, h0, margin=8,
-             device=0):
+             device=0, info=False):
     """Tables tau^2, v0, v1 (NT x NT each, the layout of hbi_tables) from the
     eikonal and transport solves on the GPU (hbi_tabulate, 2D).  n2: the
     medium's n^2 on a regular grid, array (nx, ny) indexed [i, j] at
     origin + (i, j) spacing; taylor: (NT, 5, 5) Taylor coefficients of n^2
     about every table node (entry [A, i, j] multiplies (x - x_A)^i
-    (y - y_A)^j)."""
+    (y - y_A)^j).  With info=True the solve counters of hbi_get_info
+    (tab_sources, tab_rounds_max, tab_point_updates, tab_s) come back as a
+    fourth value."""
     import torch
     lib = _lib.load()
     n2 = np.asarray(n2, dtype=np.float64)
@@ -361,9 +363,15 @@ def tabulate(n2, origin, spacing, taylor, nI, nbox, box_origin, box_size, h0, ma
     try:
         _lib.check(lib.hbi_tabulate(ctx, ctypes.byref(m), int(nI), nb, bo, float(box_size),
                                     float(h0), int(margin), *[_dptr(F) for F in out]), ctx)
+        if info:
+            buf = ctypes.create_string_buffer(1 << 14)
+            _lib.check(lib.hbi_get_info(ctx, buf, len(buf)), ctx)
+            d = json.loads(buf.value.decode())
+            stats = {k: d[k] for k in ("tab_sources", "tab_rounds_max", "tab_point_updates",
+                                       "tab_s")}
     finally:
         lib.hbi_destroy(ctx)
-    return tuple(out)
+    return (*out, stats) if info else tuple(out)
 
 
 def _autograd_function():

@@ -268,7 +268,10 @@ struct hbi_ctx {
   // forward transfer items with inputs staged in LDS / gathered from global
   // memory, and those on 16-row windows
   int64_t wst_lds = 0, wst_global = 0, wst_wide = 0;
-  int32_t tab_rounds_max = 0;   // largest sweep count of the last hbi_tabulate
+  // the last hbi_tabulate: sources, largest sweep count, point updates (rounds
+  // x four orderings x updated points, over every equation), solve time
+  int32_t tab_sources = 0, tab_rounds_max = 0;
+  double tab_point_updates = 0, tab_s = 0;
   int32_t wst_cq[5] = {0, 0, 0, 0, 0};   // unit widths c: min, quartiles, max
   // curve inclusion (2D): segments at positions [Nv, Nv + inc_ns) of the
   // per-point arrays; inputs on the host and the device, and the dense
@@ -2383,10 +2386,11 @@ void tabulate(hbi_ctx *c, const hbi_medium2d *m, int32_t nI, const int32_t nbox[
   const int32_t batch = (int32_t)std::min<int64_t>(NT, per);
   HBI_HIP(ws.alloc(sizeof(double) * (size_t)stride * batch));
   double *F0 = tabs.as<double>(), *F1 = F0 + (size_t)NT * NT, *F2 = F1 + (size_t)NT * NT;
+  const double t0 = now_s();
   for (int32_t s0 = 0; s0 < NT; s0 += batch) {
     const int32_t nb = std::min(batch, NT - s0);
     // column s0 + s of every table: offset the table pointers by s0 columns
-    HBI_HIP(launch_tabulate(src_d.as<TabSource>() + s0, nb, med, ws.as<double>(), stride,
+    HBI_HIP(launch_tabulate(src_d.as<TabSource>() + s0, nb, med, ws.as<double>(), stride, npmax,
                             nodes_d.as<double>(), NT, F0 + s0, F1 + s0, F2 + s0,
                             stat_d.as<int32_t>() + 3 * s0, 1e-13, 20000, st));
     HBI_HIP(hipStreamSynchronize(st));
@@ -2399,13 +2403,20 @@ void tabulate(hbi_ctx *c, const hbi_medium2d *m, int32_t nI, const int32_t nbox[
   HBI_HIP(hipMemcpyAsync(v0, F1, sizeof(double) * (size_t)NT * NT, hipMemcpyDeviceToHost, st));
   HBI_HIP(hipMemcpyAsync(v1, F2, sizeof(double) * (size_t)NT * NT, hipMemcpyDeviceToHost, st));
   HBI_HIP(hipStreamSynchronize(st));
+  c->tab_s = now_s() - t0;
+  c->tab_sources = NT;
   c->tab_rounds_max = 0;
+  c->tab_point_updates = 0;
   for (int32_t q = 0; q < NT; ++q)
     for (int e = 0; e < 3; ++e) {
       if (status[3 * q + e] < 0)
         throw Error{HBI_ERR_NUMERIC, "hbi_tabulate: the sweeps of node " + std::to_string(q) +
                                          " (equation " + std::to_string(e) + ") did not converge"};
       c->tab_rounds_max = std::max(c->tab_rounds_max, status[3 * q + e]);
+      // held points: the (2 P - 1)^2 square, P = 6, 4, 2 (inside the grid)
+      const int64_t held = (int64_t)(11 - 4 * e) * (11 - 4 * e);
+      c->tab_point_updates +=
+          4.0 * status[3 * q + e] * (double)((int64_t)src[q].nx * src[q].ny - held);
     }
 }
 
@@ -2818,7 +2829,7 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
   if (!json || cap <= 0) { ctx->err = "null or empty output buffer"; return HBI_ERR_ARG; }
   const int64_t Nv = ctx->geo.Nv;
   const size_t esz = ctx->prec == HBI_F64 ? 16 : 8;
-  char buf[4096];
+  char buf[8192];
   const int len = std::snprintf(
       buf, sizeof buf,
       "{\"state\": %d, \"dim\": %d, \"N_v\": %lld, \"L_v\": %d, \"NT\": %d, \"nI\": %d, "
@@ -2837,7 +2848,8 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       "\"apply_scratch_bytes\": %lld, \"apply_bytes\": %.0f, \"wstage_items_lds\": %lld, "
       "\"wstage_items_global\": %lld, \"wstage_items_wide\": %lld, \"wstage_cap_lds\": %d, "
       "\"wstage_c_quantiles\": [%d, %d, %d, %d, %d], \"nnz_per_cell\": %.3f, "
-      "\"nnz_per_cell_over_log2sq\": %.5f}",
+      "\"nnz_per_cell_over_log2sq\": %.5f, \"tab_sources\": %d, \"tab_rounds_max\": %d, "
+      "\"tab_point_updates\": %.0f, \"tab_s\": %.6f}",
       ctx->state, ctx->dim, (long long)Nv, ctx->geo.Lv, ctx->NT, ctx->nI,
       ctx->prec == HBI_F64 ? "f64" : "f32", ctx->tol, ctx->chi(), ctx->leaf(),
       (long long)ctx->nnz_v, (long long)ctx->nnz_w, (long long)ctx->nnz_k, (long long)ctx->nnz_d,
@@ -2859,7 +2871,8 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       ctx->plan.cap_lds, ctx->wst_cq[0], ctx->wst_cq[1], ctx->wst_cq[2],
       ctx->wst_cq[3], ctx->wst_cq[4], Nv ? (double)ctx->Felems / (double)Nv : 0.0,
       Nv > 1 ? (double)ctx->Felems / (double)Nv / (std::log2((double)Nv) * std::log2((double)Nv))
-             : 0.0);
+             : 0.0,
+      ctx->tab_sources, ctx->tab_rounds_max, ctx->tab_point_updates, ctx->tab_s);
   if (len < 0 || len >= cap) { ctx->err = "output buffer too small"; return HBI_ERR_ARG; }
   std::memcpy(json, buf, len + 1);
   return HBI_OK;
