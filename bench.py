@@ -855,6 +855,8 @@ def main():
                     "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
                     "dtype": obj["dtype"], "data": "synthetic (the paper's medium in closed form)",
                     "config": dict(obj["config"], parallelism="single GPU"),
+                    "solve_s": obj["solve_s"], "rounds_max": obj["rounds_max"],
+                    "point_updates": obj["point_updates"], "parity": obj["parity"],
                     "roofline": obj["roofline"], "cpu_baseline": obj["cpu_baseline"]}
         else:
             line["tables"] = obj
