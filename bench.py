@@ -6,7 +6,9 @@ Default run (`python bench.py`), one JSON line:
     n = 1, omega = 256 pi), piecewise Chebyshev tables (8 x 8 boxes x 8 x 8
     nodes), one seeded complex N(0,1) right-hand side.  FP64 factors at tol
     1e-7 and FP32 factors (FP64 build, rounded) at tol 1e-5; `value` is the
-    FP32 apply in Gcell*RHS/s, the FP64 figures are reported beside it.
+    FP32 apply in Gcell*RHS/s, the FP64 figures are reported beside it, and
+    the conjugate-transpose product (hbi_apply_adjoint) of both is timed the
+    same way and checked against the oracle's h^d K^H s on 128 columns.
   * "batched": 64 constant-gradient problems c(y) = 1 + g y of 128^2, 256^2
     or 512^2 cells with 1-256 Gaussian-source RHS each, FP32, one batched
     call (MFMA tiles, replayed HIP graph).
@@ -88,6 +90,13 @@ def _oracle_task(args):
     import oracle
     prob, S = _JOBS[key]
     return key, rows, oracle.apply(prob, S, rows)
+
+
+def _oracle_adj_task(args):
+    key, rows = args
+    import oracle
+    prob, S = _JOBS[key]
+    return key, rows, oracle.apply_adjoint(prob, S, rows)
 
 
 def _table_task(args):
@@ -276,6 +285,10 @@ def cpu_phase(work, args):
                                   f"extrapolates to {dt * w['prob'].Nv / n / 3600:.2f} h",
                         "cpu": info}
         log(f"cpu: bump {n} rows on {W} workers in {dt:.1f}s")
+        ra = w["rows"][::4]
+        res, dta = run_pool(split_rows("bump", ra, 4), _oracle_adj_task, W)
+        refs["bump_adj"] = res["bump"][1]
+        log(f"cpu: bump adjoint {len(ra)} columns in {dta:.1f}s")
     if "batched" in work:
         w = work["batched"]
         tasks = []
@@ -349,7 +362,7 @@ def cpu_phase(work, args):
     return refs, base
 
 
-def gpu_bump(args, w, ref, cpu):
+def gpu_bump(args, w, ref, cpu, ref_adj=None):
     import numpy as np
     import torch
     import paper_2210_02698_amd as hbi
@@ -375,13 +388,33 @@ def gpu_bump(args, w, ref, cpu):
         if ref is not None:
             err, row = rel_err(u.cpu().numpy()[rows], ref)
         t_apply, prof = timed_single(op, s, args.steps, args.warmup)
+        # the conjugate-transpose product (bf_adjoint): same factors, same
+        # bytes, gathers only; checked against the oracle's h^d K^H s
+        ua = op.apply_adjoint(s)
+        torch.cuda.synchronize()
+        aerr = arow = None
+        if ref_adj is not None:
+            aerr, arow = rel_err(ua.cpu().numpy()[rows[::4]], ref_adj)
+        for _ in range(args.warmup):
+            op.apply_adjoint(s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            op.apply_adjoint(s)
+        torch.cuda.synchronize()
+        t_adj = (time.perf_counter() - t0) / args.steps
+        log(f"bump {prec} adjoint {t_adj * 1e3:.3f} ms err {aerr} row {arow}")
         esz = 16 if prec == "f64" else 8
         # algorithmic bytes of one product (from the factor layout): factor
         # entries, vectors read and written, index lists and descriptors
         results[prec] = dict(build_s=build_s, err=err, row=row, ms=t_apply * 1e3, info=info,
                              prof=prof, gcells=prob.Nv / t_apply / 1e9,
                              apply_gbs=info["apply_bytes"] / t_apply / 1e9,
-                             factor_bytes=info["nnz_total"] * esz)
+                             factor_bytes=info["nnz_total"] * esz,
+                             adj={"value": round(prob.Nv / t_adj / 1e9, 6),
+                                  "ms_per_step": round(t_adj * 1e3, 4),
+                                  "apply_achieved_GBs": round(info["apply_bytes"] / t_adj / 1e9, 1),
+                                  "rel_err_vs_oracle": aerr, "row_max_err_vs_oracle": arow})
         log(f"bump {prec} apply {t_apply * 1e3:.3f} ms err {err} row {row} prof {prof}")
         op.close()
         del op
@@ -423,6 +456,7 @@ def gpu_bump(args, w, ref, cpu):
                      "traffic": measured_traffic(dom) if args.n_side == 1024 else None,
                      "algorithmic_bytes_per_launch": round(kd["bytes"] / kd["launches"])},
         "cpu_baseline": cpu,
+        "adjoint": dict(head["adj"], oracle_columns=len(rows[::4])),
     }
     if "f64" in results:
         r = results["f64"]
@@ -430,7 +464,7 @@ def gpu_bump(args, w, ref, cpu):
                         "rel_err_vs_oracle": r["err"], "row_max_err_vs_oracle": r["row"],
                         "build_s": round(r["build_s"], 3),
                         "apply_achieved_GBs": round(r["apply_gbs"], 1),
-                        "factor_bytes": r["factor_bytes"]}
+                        "factor_bytes": r["factor_bytes"], "adjoint": r["adj"]}
         line["fp32_speedup_over_fp64"] = round(r["ms"] / head["ms"], 3)
     return line
 
@@ -824,7 +858,8 @@ def main():
         del a, b
     line = None
     if "bump" in work:
-        line = gpu_bump(args, work["bump"], refs.get("bump"), base.get("bump"))
+        line = gpu_bump(args, work["bump"], refs.get("bump"), base.get("bump"),
+                        refs.get("bump_adj"))
     for kind in ("batched", "3d"):
         if kind not in work:
             continue

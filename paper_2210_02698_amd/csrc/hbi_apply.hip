@@ -3,6 +3,8 @@
 //
 //   bf_apply  k_vstage, k_wstage, k_final             (u = K h^d s)
 //   adjoint   k_final_adj, k_wstage_adj, k_vstage_adj  (u = h^d K^H s)
+#include <type_traits>
+
 #include "hbi_kernels.h"
 #include "hbi_device.h"
 
@@ -308,7 +310,69 @@ __global__ __launch_bounds__(256) void k_final(const cplx_t<R> *s,
 
 // ---------------------------------------------------------------------------
 // Adjoint: the same factors read as conjugate transposes, stages reversed.
+// Every product is a set of conjugate dot products down contiguous columns
+// of a column-major block.  A wave takes four columns at a time: slot
+// g = lane / 16 one column, lane r16 = lane % 16 of the slot the rows r16,
+// r16 + 16, ..., so each load instruction reads four contiguous column
+// segments; the 16 partial sums of a slot are added by DPP row shifts (a
+// fixed order), leaving the column's result in the slot's lane 15.
 // ---------------------------------------------------------------------------
+template <int CTRL> __device__ __forceinline__ float dpp_row(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_row(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+// Sum over each row of 16 lanes, complete in the row's lane 15 (row_shr 1,
+// 2, 4, 8 with zero fill: a prefix sum within the row).
+template <typename C> __device__ __forceinline__ C row16_sum(C v) {
+  v.x += dpp_row<0x111>(v.x); v.y += dpp_row<0x111>(v.y);
+  v.x += dpp_row<0x112>(v.x); v.y += dpp_row<0x112>(v.y);
+  v.x += dpp_row<0x114>(v.x); v.y += dpp_row<0x114>(v.y);
+  v.x += dpp_row<0x118>(v.x); v.y += dpp_row<0x118>(v.y);
+  return v;
+}
+
+// This lane's share of sum_{i < R} conj(col[i]) w[i]: rows r16, r16 + 16,
+// ...; the first four of them use wr[0..3] (w at those rows, loaded once by
+// the caller), later ones read w.  Loads issued four at a time, predicated.
+template <typename C>
+__device__ __forceinline__ C col_share(const C *col, int R, int r16, const C (&wr)[4],
+                                       const C *w) {
+  C acc{0, 0};
+  {
+    C mv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) mv[u] = r16 + 16 * u < R ? ldf(col + r16 + 16 * u) : C{0, 0};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) cfmac(acc, mv[u], wr[u]);
+  }
+  for (int k0 = r16 + 64; k0 < R; k0 += 64) {
+    C mv[4], wv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = k0 + 16 * u;
+      mv[u] = i < R ? ldf(col + i) : C{0, 0};
+      wv[u] = i < R ? w[i] : C{0, 0};
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) cfmac(acc, mv[u], wv[u]);
+  }
+  return acc;
+}
+// w at this lane's first four rows (zero past R)
+template <typename C>
+__device__ __forceinline__ void load_w4(C (&wr)[4], const C *w, int R, int r16) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) wr[u] = r16 + 16 * u < R ? w[r16 + 16 * u] : C{0, 0};
+}
+
+// K^L part: z_l = (K^L_l)^H y_leaf for every level of a row leaf (one
+// workgroup; wave w takes levels w, w + 4, ...); K^L_l is sz x r, column q
+// contiguous.
 template <typename R>
 __global__ __launch_bounds__(256) void k_final_adj(const cplx_t<R> *y,
                                                    const LeafInfo *leaves,
@@ -321,33 +385,71 @@ __global__ __launch_bounds__(256) void k_final_adj(const cplx_t<R> *y,
   const int g = blockIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
+  const int slot = lane >> 4, r16 = lane & 15;
   const LeafInfo lf = leaves[g];
   const int sz = lf.size;
   if (threadIdx.x < sz) ys[threadIdx.x] = y[perm[lf.start + threadIdx.x]];
   __syncthreads();
+  C yr[4];
+  load_w4(yr, ys, sz, r16);
   for (int l = wave; l < Lv; l += 4) {
     const KDesc d = kd[(int64_t)g * Lv + l];
-    if (lane < d.r) {
-      const C *K = F + d.foff + (int64_t)lane * sz;
-      C acc{0, 0};
-      batched_dot<LoadBatch<C>::value, true>(
-          acc, sz, [&](int row) { return ldf(K + row); }, [&](int row) { return ys[row]; });
-      z[d.zin + lane] = acc;
+    // eight columns per pass, two column groups in flight
+    for (int q0 = 0; q0 < d.r; q0 += 8) {
+      const int q1 = q0 + slot, q2 = q0 + 4 + slot;
+      const C *K = F + d.foff;
+      C a1 = col_share(K + (int64_t)(q1 < d.r ? q1 : d.r - 1) * sz, sz, r16, yr, ys);
+      C a2 = col_share(K + (int64_t)(q2 < d.r ? q2 : d.r - 1) * sz, sz, r16, yr, ys);
+      a1 = row16_sum(a1);
+      a2 = row16_sum(a2);
+      if (r16 == 15 && q1 < d.r) z[d.zin + q1] = a1;
+      if (r16 == 15 && q2 < d.r) z[d.zin + q2] = a2;
     }
   }
 }
 
-// Adjoint of a transfer unit, one lane per input column j of the window
-// [off, off + 64): column j of X_a is e_k when pa[j] = k < ra, and column
-// pa[j] - ra of T_a otherwise, so (X_a^H w_a)_j is w_a[k] or a conjugate
-// dot product with that column of T_a; child b adds the same way.
+// Passes of the two adjoint kernels below for blocks of at most 16 U rows:
+// U rows per lane and NT groups of four columns per pass (4 NT columns),
+// all their loads in flight before the sums.  col(t) is the slot's column
+// position in group t (its T column is pos - r when pos >= r).
+template <int U, int NT, typename C, typename POS>
+__device__ __forceinline__ void adj_pass(const C *T, int r, int r16, const C (&wr)[4], POS pos,
+                                         C (&out)[NT]) {
+  int pp[NT];
+  C tv[NT][U];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) pp[t] = pos(t);
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = r16 + 16 * u;
+      tv[t][u] = pp[t] >= r && i < r ? ldf(T + (int64_t)(pp[t] - r) * r + i) : C{0, 0};
+    }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    C acc{0, 0};
+#pragma unroll
+    for (int u = 0; u < U; ++u) cfmac(acc, tv[t][u], wr[u]);
+    out[t] = row16_sum(acc);
+  }
+}
+
+// Adjoint of a transfer unit for the inputs j of the window [off, off + 64):
+// column j of X_a is e_k when pa[j] = k < ra, and column pa[j] - ra of T_a
+// otherwise (ra contiguous entries), so (X_a^H w_a)_j is w_a[k] or a
+// conjugate dot product with that column; child b adds the same way.  Four
+// inputs at a time, one per slot; the results gather in the wave's LDS
+// slice and are stored together.
 template <typename R>
 __global__ __launch_bounds__(256) void k_wstage_adj(const WItem *items, int64_t nitems,
                                                     const uint16_t *fidx, const cplx_t<R> *F,
                                                     cplx_t<R> *z) {
   using C = cplx_t<R>;
+  __shared__ C res[4][64];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
+  const int slot = lane >> 4, r16 = lane & 15;
   const int64_t it = (int64_t)blockIdx.x * 4 + wave;
   if (it >= nitems) return;
   const WItem U = items[it];
@@ -355,30 +457,68 @@ __global__ __launch_bounds__(256) void k_wstage_adj(const WItem *items, int64_t 
   const uint16_t *pa = fidx + U.ioff + 2 * (int64_t)c, *pb = pa + c;
   const C *wa = z + U.zouta, *wb = z + U.zoutb;
   const C *Ta = F + U.foff, *Tb = Ta + (int64_t)ra * (c - ra);
-  const int c1 = U.off + 64 < c ? U.off + 64 : c;
-  const int col = U.off + lane;
-  if (col < c1) {
-    C acc{0, 0};
-    const int ka = pa[col], kb = pb[col];
-    if (ka < ra) {
-      acc = wa[ka];
-    } else {
-      const C *cm = Ta + (int64_t)(ka - ra) * ra;
-      batched_dot<LoadBatch<C>::value, true>(
-          acc, ra, [&](int i) { return ldf(cm + i); }, [&](int i) { return wa[i]; });
+  const int nw = c - U.off < 64 ? c - U.off : 64;   // inputs of this window
+  // the window's inverse orders, one input per lane
+  const int jl = U.off + (lane < nw ? lane : 0);
+  const int ka_l = pa[jl], kb_l = pb[jl];
+  C war[4], wbr[4];
+  load_w4(war, wa, ra, r16);
+  load_w4(wbr, wb, rb, r16);
+  // blocks of at most 32 rows: two rows per lane, 16 inputs per pass with
+  // all their column loads in flight (one row per lane and 32 inputs per
+  // pass measured slower: twice the registers, half the waves)
+  auto fast = [&](auto Uc) {
+    constexpr int Uv = decltype(Uc)::value, NT = 4;
+    for (int q0 = 0; q0 < nw; q0 += 4 * NT) {
+      int ka[NT], kb[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int jw = q0 + 4 * t + slot < nw ? q0 + 4 * t + slot : nw - 1;
+        ka[t] = __shfl(ka_l, jw, 64);
+        kb[t] = __shfl(kb_l, jw, 64);
+      }
+      C sa[NT], sb[NT];
+      adj_pass<Uv, NT>(Ta, ra, r16, war, [&](int t) { return ka[t]; }, sa);
+      adj_pass<Uv, NT>(Tb, rb, r16, wbr, [&](int t) { return kb[t]; }, sb);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int q = q0 + 4 * t + slot;
+        if (r16 == 15 && q < nw) {
+          const C xa = ka[t] < ra ? wa[ka[t]] : sa[t];
+          const C xb = kb[t] < rb ? wb[kb[t]] : sb[t];
+          res[wave][q] = C{xa.x + xb.x, xa.y + xb.y};
+        }
+      }
     }
-    if (kb < rb) {
-      acc.x += wb[kb].x;
-      acc.y += wb[kb].y;
-    } else {
-      const C *cm = Tb + (int64_t)(kb - rb) * rb;
-      batched_dot<LoadBatch<C>::value, true>(
-          acc, rb, [&](int i) { return ldf(cm + i); }, [&](int i) { return wb[i]; });
+    wave_lds_sync();
+    if (lane < nw) z[U.zin + U.off + lane] = res[wave][lane];
+  };
+  if (ra <= 32 && rb <= 32) return fast(std::integral_constant<int, 2>());
+  for (int q0 = 0; q0 < nw; q0 += 4) {
+    const int jw = q0 + slot < nw ? q0 + slot : nw - 1;   // window position of this slot
+    const int ka = __shfl(ka_l, jw, 64), kb = __shfl(kb_l, jw, 64);
+    // a skeleton column has no T column: zero rows, no loads (T may be empty)
+    C acc = col_share(Ta + (int64_t)(ka >= ra ? ka - ra : 0) * ra, ka >= ra ? ra : 0, r16, war,
+                      wa);
+    C accb = col_share(Tb + (int64_t)(kb >= rb ? kb - rb : 0) * rb, kb >= rb ? rb : 0, r16, wbr,
+                       wb);
+    acc = row16_sum(acc);
+    accb = row16_sum(accb);
+    if (r16 == 15 && q0 + slot < nw) {
+      const C xa = ka < ra ? wa[ka] : acc;
+      const C xb = kb < rb ? wb[kb] : accb;
+      res[wave][q0 + slot] = C{xa.x + xb.x, xa.y + xb.y};
     }
-    z[U.zin + col] = acc;
   }
+  wave_lds_sync();
+  if (lane < nw) z[U.zin + U.off + lane] = res[wave][lane];
 }
 
+// Leaf part of the adjoint: u_leaf = hd (D^H y_leaf + sum_l V_l^H z_l), one
+// workgroup per leaf: wave 0 the dense block (column-major sz x sz), wave w
+// the levels w, w + 4, ...; column j of V_l = [I, T] Pi^T is e_p when the
+// cell's position p < r, else column p - r of T (r contiguous entries).
+// Per-wave sums in LDS, added over the waves in a fixed order.
 template <typename R>
 __global__ __launch_bounds__(256) void k_vstage_adj(const cplx_t<R> *y,
                                                     const LeafInfo *leaves,
@@ -394,34 +534,73 @@ __global__ __launch_bounds__(256) void k_vstage_adj(const cplx_t<R> *y,
   const int g = blockIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
+  const int slot = lane >> 4, r16 = lane & 15;
   const LeafInfo lf = leaves[g];
   const int sz = lf.size;
   if (threadIdx.x < sz) ys[threadIdx.x] = y[perm[lf.start + threadIdx.x]];
+  part[wave][lane] = C{0, 0};
   __syncthreads();
-  C acc{0, 0};
-  if (lane < sz) {
-    if (wave == 0) {
-      // dense leaf: (D^H y)[col], column `lane` of D is contiguous
-      const C *Dc = F + lf.dense_off + (int64_t)lane * sz;
-      batched_dot<LoadBatch<C>::value, true>(
-          acc, sz, [&](int row) { return ldf(Dc + row); }, [&](int row) { return ys[row]; });
+  if (wave == 0) {
+    // dense leaf: (D^H y)[col], column col of D contiguous
+    C yr[4];
+    load_w4(yr, ys, sz, r16);
+    for (int q0 = 0; q0 < sz; q0 += 8) {
+      const int q1 = q0 + slot, q2 = q0 + 4 + slot;
+      C a1 = col_share(F + lf.dense_off + (int64_t)(q1 < sz ? q1 : sz - 1) * sz, sz, r16, yr, ys);
+      C a2 = col_share(F + lf.dense_off + (int64_t)(q2 < sz ? q2 : sz - 1) * sz, sz, r16, yr, ys);
+      a1 = row16_sum(a1);
+      a2 = row16_sum(a2);
+      if (r16 == 15 && q1 < sz) part[0][q1] = a1;
+      if (r16 == 15 && q2 < sz) part[0][q2] = a2;
     }
-    for (int l = wave; l < Lv; l += 4) {
-      // column `lane` of V: e_p when p < r, else column p - r of T
-      const VDesc d = vd[(int64_t)g * Lv + l];
-      const C *w = z + d.zout;
-      const int p = fidx[d.ioff + sz + lane];
-      if (p < d.r) {
-        acc.x += w[p].x;
-        acc.y += w[p].y;
-      } else {
-        const C *V = F + d.foff + (int64_t)(p - d.r) * d.r;
-        batched_dot<LoadBatch<C>::value, true>(
-            acc, d.r, [&](int row) { return ldf(V + row); }, [&](int row) { return w[row]; });
+  }
+  for (int l = wave; l < Lv; l += 4) {
+    const VDesc d = vd[(int64_t)g * Lv + l];
+    const C *w = z + d.zout;
+    const int p_l = fidx[d.ioff + sz + (lane < sz ? lane : 0)];   // position of cell `lane`
+    C wr[4];
+    load_w4(wr, w, d.r, r16);
+    // blocks of at most 32 rows: two rows per lane, 16 cells per pass with
+    // all their column loads in flight
+    auto fast = [&](auto Uc) {
+      constexpr int Uv = decltype(Uc)::value, NT = 4;
+      for (int q0 = 0; q0 < sz; q0 += 4 * NT) {
+        int pp[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int jw = q0 + 4 * t + slot < sz ? q0 + 4 * t + slot : sz - 1;
+          pp[t] = __shfl(p_l, jw, 64);
+        }
+        C sv[NT];
+        adj_pass<Uv, NT>(F + d.foff, d.r, r16, wr, [&](int t) { return pp[t]; }, sv);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int q = q0 + 4 * t + slot;
+          if (r16 == 15 && q < sz) {
+            const C x = pp[t] < d.r ? w[pp[t]] : sv[t];
+            C &tt = part[wave][q];
+            tt.x += x.x;
+            tt.y += x.y;
+          }
+        }
+      }
+    };
+    if (d.r <= 32) { fast(std::integral_constant<int, 2>()); continue; }
+    for (int q0 = 0; q0 < sz; q0 += 4) {
+      const int jw = q0 + slot < sz ? q0 + slot : sz - 1;
+      const int p = __shfl(p_l, jw, 64);
+      // a skeleton cell has no T column: zero rows, no loads (T may be empty)
+      C acc = col_share(F + d.foff + (int64_t)(p >= d.r ? p - d.r : 0) * d.r, p >= d.r ? d.r : 0,
+                        r16, wr, w);
+      acc = row16_sum(acc);
+      if (r16 == 15 && q0 + slot < sz) {
+        const C x = p < d.r ? w[p] : acc;
+        C &t = part[wave][q0 + slot];
+        t.x += x.x;
+        t.y += x.y;
       }
     }
   }
-  part[wave][lane] = acc;
   __syncthreads();
   if (threadIdx.x < sz) {
     C t = part[0][threadIdx.x];
