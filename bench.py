@@ -14,6 +14,9 @@ Default run (`python bench.py`), one JSON line:
     call (MFMA tiles, replayed HIP graph).
   * "3d": 3D sinusoid n = 1 + 0.2 sin 2pi x sin 2pi y sin 2pi z on 64^3
     cells, 32 RHS, FP32 factors at tol 1e-6, MFMA tiles.
+  * "gradient": inverse-source gradient steps on the 256^2 bump (512
+    receivers; forward apply, loss, backward through hbi_apply_adjoint),
+    FP32 and FP64, each gradient against the dense FP64 oracle's.
   * "tables": the tau^2, v0, v1 tables of the paper's 2D sinusoidal medium
     (13 x 13 Chebyshev nodes, h0 = 0.01) from the eikonal and transport
     solves (hbi_tabulate), in source nodes per second.
@@ -314,6 +317,25 @@ def cpu_phase(work, args):
                                 f"FP64 oracle, {W} worker processes, {dt:.1f} s wall",
                       "cpu": info}
         log(f"cpu: 3d {outs} outputs in {dt:.1f}s")
+    if "grad" in work:
+        w = work["grad"]
+        prob = w["prob"]
+        hd = prob.h ** prob.dim
+        t0 = time.perf_counter()
+        res, _ = run_pool(split_rows("grad", w["P"], 32), _dense_task, W)
+        KP = res["grad"][1]
+        d = KP @ (w["s_true"] * hd)
+        r = KP @ (w["s0"] * hd) - d
+        g = 2 * hd * (KP.conj().T @ r)
+        dt = time.perf_counter() - t0
+        refs["grad"] = {"d": d, "grad": g}
+        base["grad"] = {"value": prob.Nv / dt / 1e9, "unit": "Gcell/s (gradient steps)",
+                        "cores": W, "kind": "oracle",
+                        "sample": f"one full gradient: the {len(w['P'])} receiver rows of K by "
+                                  f"the dense FP64 oracle on {W} worker processes, then "
+                                  f"K[P] h^d s - d and 2 h^d K[P]^H r, {dt:.1f} s wall",
+                        "cpu": info}
+        log(f"cpu: gradient in {dt:.1f}s")
     if "tables" in work:
         w = work["tables"]
         res, dt = run_pool(split_rows("tables", w["sample"], 1), _table_task, W)
@@ -602,6 +624,81 @@ def run_sweep(args):
     print(json.dumps(line), flush=True)
 
 
+def prepare_gradient(args):
+    """The differentiation workload: Gaussian bump on 256^2 cells (omega =
+    64 pi), P = 512 seeded receiver cells, data d = P K h^d s_true from 20
+    seeded point sources, loss ||P K h^d s - d||^2 at a seeded complex
+    N(0,1) s; its gradient is 2 h^d K[P]^H (K[P] h^d s - d)."""
+    import numpy as np
+    import hb_inputs
+    prob = hb_inputs.configs.c4()
+    seed = hb_inputs.configs.CFG_SEED["c4"]
+    g = np.random.default_rng([seed, 0])
+    P = np.sort(g.choice(prob.Nv, 512, replace=False))
+    _, s_true = hb_inputs.point_sources(prob, 20, [seed, 1])
+    s0 = hb_inputs.complex_normal(prob.Nv, [seed, 2], dtype=np.complex64).astype(np.complex128)
+    _JOBS["grad"] = (prob, None)
+    return dict(prob=prob, P=P, s_true=s_true, s0=s0)
+
+
+def gpu_gradient(args, w, ref, cpu):
+    """Gradient steps through HBApply (forward apply, loss on the receivers,
+    backward = hbi_apply_adjoint), FP32 (tol 1e-5) and FP64 (tol 1e-7)
+    factors; each step's gradient against the dense FP64 oracle's."""
+    import numpy as np
+    import torch
+    import paper_2210_02698_amd as hbi
+    prob, P = w["prob"], w["P"]
+    hd = prob.h ** prob.dim
+    dev = torch.device("cuda:0")
+    out = {}
+    for prec, tol in (("f32", args.tol32), ("f64", args.tol64)):
+        dt = torch.complex64 if prec == "f32" else torch.complex128
+        op = hbi.Operator(prob, device=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op.build(tol=tol, prec=prec)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        Pd = torch.from_numpy(P).to(dev)
+        dd = torch.from_numpy(ref["d"]).to(dev).to(dt)
+        s0 = torch.from_numpy(w["s0"]).to(dev).to(dt)
+
+        def step():
+            s = s0.detach().clone().requires_grad_(True)
+            u = hbi.HBApply.apply(op, s)
+            loss = (u[Pd] - dd).abs().pow(2).sum()
+            loss.backward()
+            return s.grad
+
+        grad = step()
+        torch.cuda.synchronize()
+        g_h = grad.cpu().numpy().astype(np.complex128)
+        err = float(np.linalg.norm(g_h - ref["grad"]) / np.linalg.norm(ref["grad"]))
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / args.steps
+        log(f"gradient {prec}: {t * 1e3:.3f} ms per step, rel err {err:.2e}")
+        out[prec] = {"value": round(prob.Nv / t / 1e9, 6), "ms_per_step": round(t * 1e3, 4),
+                     "rel_err_vs_oracle": err, "build_s": round(build_s, 3), "tol": tol}
+        op.close()
+    head = out["f32"]
+    return {"value": head["value"], "unit": "Gcell/s (gradient steps)",
+            "ms_per_step": head["ms_per_step"], "steps": args.steps, "warmup": args.warmup,
+            "dtype": "c64 (fp32 factors; fp64 build)",
+            "config": {"workload": "inverse-source gradient: 2D Gaussian bump 256x256, omega=64pi, "
+                                   "512 receivers, loss ||P K h^d s - d||^2, gradient by the "
+                                   "adjoint apply",
+                       "N_v": prob.Nv, "receivers": len(P)},
+            "rel_err_vs_oracle": head["rel_err_vs_oracle"], "build_s": head["build_s"],
+            "fp64": out["f64"], "cpu_baseline": cpu}
+
+
 TAB_FLOPS_PER_UPDATE = 290   # FP64 operations of one sweep point update (two WENO5
                              # one-sided derivatives per axis, the numerical Hamiltonian)
 FP64_VALU_PEAK_TFLOPS = 78.6
@@ -800,13 +897,14 @@ def main():
     ap.add_argument("--rows-3d", type=int, default=512)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=["all", "bump", "batched", "3d", "tables", "sweep",
-                                           "inclusion", "complexity"],
+    ap.add_argument("--workload", choices=["all", "bump", "batched", "3d", "grad", "tables",
+                                           "sweep", "inclusion", "complexity"],
                     default="all",
                     help="all: the headline bump line with the batched and 3d workloads beside "
                          "it; bump: the 1024^2 single-RHS apply alone; batched: 64 "
                          "constant-gradient problems with 1-256 RHS each; 3d: 64^3 sinusoid "
-                         "with 32 RHS; tables: the tau^2/v0/v1 tables of the 2D sinusoidal "
+                         "with 32 RHS; grad: inverse-source gradient steps on the 256^2 bump; "
+                         "tables: the tau^2/v0/v1 tables of the 2D sinusoidal "
                          "medium from the eikonal and transport solves; sweep: four "
                          "frequencies from one table set, 16 RHS "
                          "each; inclusion: 256^2 bump with an open-square curve inclusion; "
@@ -828,7 +926,7 @@ def main():
         return run_complexity(args)
 
     # CPU phase (no GPU touched yet): inputs, then the oracle on the pool
-    want = {"all": ("bump", "batched", "3d", "tables", "c1")}.get(args.workload,
+    want = {"all": ("bump", "batched", "3d", "grad", "tables", "c1")}.get(args.workload,
                                                                    (args.workload,))
     work = {}
     if "bump" in want:
@@ -837,6 +935,8 @@ def main():
         work["batched"] = prepare_batched(args)
     if "3d" in want:
         work["3d"] = prepare_3d(args)
+    if "grad" in want:
+        work["grad"] = prepare_gradient(args)
     if "tables" in want:
         work["tables"] = prepare_tables(args)
     if "c1" in want and not args.no_cpu:
@@ -881,6 +981,19 @@ def main():
             if "fp64" in line:
                 # the FP32 many-RHS apply against the FP64 single-RHS apply
                 obj["speedup_over_fp64_single_rhs"] = round(obj["value"] / line["fp64"]["value"], 2)
+    if "grad" in work and "grad" in refs:
+        obj = gpu_gradient(args, work["grad"], refs["grad"], base.get("grad"))
+        if line is None:
+            line = {"metric": "inverse-source gradient steps (Gcell/s)", "value": obj["value"],
+                    "unit": obj["unit"], "n_gpus": 1, "steps": obj["steps"],
+                    "warmup": obj["warmup"], "ms_per_step": obj["ms_per_step"],
+                    "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                    "dtype": obj["dtype"], "data": "synthetic (seeded inputs; stand-in tables)",
+                    "config": dict(obj["config"], parallelism="single GPU"),
+                    "rel_err_vs_oracle": obj["rel_err_vs_oracle"], "fp64": obj["fp64"],
+                    "roofline": None, "cpu_baseline": obj["cpu_baseline"]}
+        else:
+            line["gradient"] = obj
     if "tables" in work:
         obj = gpu_tables(args, work["tables"], base.get("tables"))
         if line is None:
