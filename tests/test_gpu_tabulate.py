@@ -94,3 +94,45 @@ def test_integrator_on_solved_tables():
     rows = np.sort(np.random.default_rng([91, 1]).choice(prob.Nv, 128, replace=False))
     check(u[rows], oracle.apply(prob, s, rows), 1e-6, "product on solved tables")
     op.close()
+
+
+def test_tables_of_several_boxes_match_oracle():
+    """Piecewise tables: 2 x 1 boxes of nI = 4 nodes on [0, 2] x [0, 1]
+    (constant gradient, h0 = 1/16); every source's grid covers both boxes,
+    and the table layout (box-major, node k1 + nI k2) matches the oracle's."""
+    med = hb_inputs.ConstantGradient(1.0, (0.0, 0.7))
+    say("tabulate constant-gradient 2x1 boxes nI=4 h0=1/16")
+    got = gpu_tables(med, 4, (2, 1), (0.0, 0.0), 1.0, 1 / 16)
+    ref = oracle_tables(med, 4, (2, 1), (0.0, 0.0), 1.0, 1 / 16)
+    for label, g, r in zip(("tau2", "v0", "v1"), got, ref):
+        assert g.shape == (32, 32)
+        e = np.abs(g - r).max() / np.abs(r).max()
+        say(f"2x1 boxes {label}: max |gpu - oracle| / max|oracle| = {e:.2e}")
+        assert e < 1e-8, (label, e)
+
+
+def test_tabulate_rejects_bad_arguments():
+    """Argument errors come back as HBI_ERR_ARG before any solve: a node
+    count outside 2..16, a margin below 4, a medium grid that does not cover
+    the source grids, and n^2 <= 0 at a node."""
+    import paper_2210_02698_amd as hbi
+    ensure_built()
+    med = hb_inputs.Homogeneous(1.0)
+    n2, org, sp = hb_inputs.medium_grid(med, (0.0, 0.0), (1.0, 1.0), 1 / 64, pad=4 * 12)
+    P = hb_inputs.node_coords(2, 3, (1, 1), (0.0, 0.0), 1.0)
+    tay = hb_inputs.taylor_at(med, P)
+
+    def run(nI=3, taylor=tay, n2=n2, margin=8, h0=1 / 16):
+        return hbi.tabulate(n2, org, sp, taylor, nI, (1, 1), (0.0, 0.0), 1.0, h0, margin)
+
+    run()   # the valid call
+    with pytest.raises(hbi.HBIError, match="nI must be in 2..16"):
+        run(nI=1, taylor=tay[:1])
+    with pytest.raises(hbi.HBIError, match="bad nbox, box_size, h0 or margin"):
+        run(margin=3)
+    with pytest.raises(hbi.HBIError, match="does not cover the source grids"):
+        run(n2=n2[40:-40, 40:-40])
+    bad = tay.copy()
+    bad[4, 0, 0] = -1.0
+    with pytest.raises(hbi.HBIError, match="n\\^2 must be positive"):
+        run(taylor=bad)
