@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhbi.so")
 
 HIP_SOURCES = ["hbi_kernels.hip", "hbi_apply.hip", "hbi_multi.hip", "hbi_inclusion.hip",
-               "hbi_tabulate.hip", "hbi_lib.hip"]
+               "hbi_s2v.hip", "hbi_tabulate.hip", "hbi_lib.hip"]
 CPP_SOURCES = ["hbi_geometry.cpp"]
 
 

@@ -136,14 +136,17 @@ void proxy_rows(const Geometry &G, int64_t nd, const int32_t *cand, int ncand,
     out.resize(size);
     for (int64_t i = 0; i < size; ++i) out[i] = a + (int32_t)i;
   };
-  if (nf >= size || nd >= (int64_t)G.band_off.size() - 1) { all_rows(); return; }
+  if (nf >= size || (pp.band && nd >= (int64_t)G.band_off.size() - 1)) { all_rows(); return; }
   auto add = [&](int32_t p) {
     if (stamp[p] != tag) { stamp[p] = tag; out.push_back(p); }
   };
   // f_tau: half over the boundary band, half over the whole node
-  const int64_t b0 = G.band_off[nd], nb_all = G.band_off[nd + 1] - b0;
-  const int64_t nb = std::min<int64_t>(nb_all, (nf + 1) / 2);
-  for (int64_t q = 0; q < nb; ++q) add(G.band[b0 + (q * nb_all) / nb]);
+  int64_t nb = 0;
+  if (pp.band) {
+    const int64_t b0 = G.band_off[nd], nb_all = G.band_off[nd + 1] - b0;
+    nb = std::min<int64_t>(nb_all, (nf + 1) / 2);
+    for (int64_t q = 0; q < nb; ++q) add(G.band[b0 + (q * nb_all) / nb]);
+  }
   const int64_t nu = nf - nb;
   for (int64_t q = 0; q < nu; ++q) add(a + (int32_t)((q * size + size / 2) / nu));
   // nearest-neighbour rows: cells of the node within `radius` of a candidate

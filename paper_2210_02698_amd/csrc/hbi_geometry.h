@@ -41,14 +41,17 @@ struct Geometry {
 struct ProxyParams {
   double chi = 20.0;
   double radius = 10.0;   // neighbour radius in cells
+  bool band = true;       // half of the uniform rows over the boundary band
 };
 
 // Proxy rows of eq. proxyv2v for row node `nd` and candidate columns `cand`
-// (tree positions): the cells of the node within `radius` cells of a
-// candidate, plus ceil(chi*|cand|) cells spread uniformly, half over the
-// node's boundary band and half over the whole node.  Falls back to all
-// cells of the node when that is not smaller.  Output ascending.  `stamp`
-// is per-thread scratch of size Nv with values < `tag`.
+// (tree positions; for segment columns, the cells that hold them): the
+// cells of the node within `radius` cells of a candidate, plus
+// ceil(chi*|cand|) cells spread uniformly, half over the node's boundary
+// band and half over the whole node (all over the whole node without
+// `band`, the rule for the cells x segments butterfly, Sec. 4.2).  Falls
+// back to all cells of the node when that is not smaller.  Output
+// ascending.  `stamp` is per-thread scratch of size Nv with values < `tag`.
 void proxy_rows(const Geometry &G, int64_t nd, const int32_t *cand, int ncand,
                 const ProxyParams &pp, std::vector<int32_t> &out,
                 std::vector<int32_t> &stamp, int32_t tag);

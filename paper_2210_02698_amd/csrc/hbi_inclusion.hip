@@ -4,11 +4,12 @@
 //
 // with K^{v2s}_ij = g(r^s_i, r_j), K^{s2v}_ij = g(r_i, r^s_j) w_j and
 // K^{s2s}_ij = -g(r^s_i, r^s_j) w_j off the diagonal (eq. m_v2s, m_s2v, s2s).
-// The tables are symmetric, so g is reciprocal and one dense array G,
+// The tables are symmetric, so g is reciprocal and one operator G,
 // G[j, i] = g(r_j, r^s_i) over cells j and segments i, serves both
-// K^{v2s} = G^T and K^{s2v} = G W.  G is stored in row chunks of `m` cells:
-// chunk q holds cells [q m, q m + m_q) as an m_q x N_s column-major block at
-// element offset q m N_s, so a segment's column within a chunk is contiguous.
+// K^{v2s} = G^T and K^{s2v} = G W.  G is a single butterfly (hbi_s2v.hip),
+// or, kept dense for comparison, stored in row chunks of `m` cells: chunk q
+// holds cells [q m, q m + m_q) as an m_q x N_s column-major block at element
+// offset q m N_s, so a segment's column within a chunk is contiguous.
 //
 //   k_point_setup           table box and Lagrange weights of every segment
 //                           centre, and the K^{s2s} self factor
@@ -18,7 +19,8 @@
 //   k_inc_gather, k_inc_reduce, k_inc_small(_sum), k_inc_scatter, k_inc_add
 //                           the inclusion term of one product (or of its
 //                           conjugate transpose), gathers only, fixed
-//                           summation order
+//                           summation order (with a butterfly G, only the
+//                           K^{s2s} step k_inc_small(_sum) runs here)
 #include "hbi_kernels.h"
 #include "hbi_device.h"
 
@@ -349,6 +351,27 @@ hipError_t launch_inclusion_apply(const InclusionPlan &ip, const void *x, void *
   C *z = (C *)ip.z;
   C *y = (C *)ip.y;
   const R *w = (const R *)ip.w;
+  const int32_t nkb = (ip.ns + kIncCol - 1) / kIncCol;
+  const dim3 gm((unsigned)((ip.ns + 255) / 256), (unsigned)nkb);
+  C *part3 = (C *)ip.part3;
+  if (ip.bf) {
+    // z = h^d G^T x (forward) or G^H x (adjoint), then the K^{s2s} step, then
+    // u += G y (forward) or h^d conj(G) y (adjoint)
+    hipError_t e = launch_s2v<R>(*ip.bf, x, z, adjoint ? (R)1 : hd, true, adjoint, st);
+    if (e != hipSuccess) return e;
+    if (!adjoint) {
+      hipLaunchKernelGGL((k_inc_small<R, false>), gm, dim3(256), 0, st, (const C *)ip.M, ip.ns, w,
+                         (const C *)z, part3);
+      hipLaunchKernelGGL((k_inc_small_sum<R, false>), dim3((ip.ns + 255) / 256), dim3(256), 0,
+                         st, (const C *)part3, ip.ns, nkb, w, y);
+    } else {
+      hipLaunchKernelGGL((k_inc_small<R, true>), gm, dim3(256), 0, st, (const C *)ip.MH, ip.ns, w,
+                         (const C *)z, part3);
+      hipLaunchKernelGGL((k_inc_small_sum<R, true>), dim3((ip.ns + 255) / 256), dim3(256), 0,
+                         st, (const C *)part3, ip.ns, nkb, w, y);
+    }
+    return launch_s2v<R>(*ip.bf, y, u, adjoint ? hd : (R)1, false, adjoint, st);
+  }
   const int64_t nchunk = (ip.Nv + ip.m - 1) / ip.m;
   const dim3 gg((unsigned)nchunk, (unsigned)((ip.ns + 3) / 4));
   if (!adjoint) {
@@ -362,10 +385,7 @@ hipError_t launch_inclusion_apply(const InclusionPlan &ip, const void *x, void *
                      (const C *)part, nchunk, ip.ns, z);
   const int32_t nb = (ip.ns + kIncSeg - 1) / kIncSeg;
   const dim3 gs((unsigned)((ip.Nv + 255) / 256), (unsigned)nb);
-  const int32_t nkb = (ip.ns + kIncCol - 1) / kIncCol;
-  const dim3 gm((unsigned)((ip.ns + 255) / 256), (unsigned)nkb);
   C *part2 = (C *)ip.part2;
-  C *part3 = (C *)ip.part3;
   if (!adjoint) {
     hipLaunchKernelGGL((k_inc_small<R, false>), gm, dim3(256), 0, st, (const C *)ip.M, ip.ns, w,
                        (const C *)z, part3);

@@ -87,12 +87,47 @@ hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
                         const void *F, R hd, bool adjoint, hipStream_t st,
                         LaunchHook *hook = nullptr);
 
-// Curve inclusion (hbi_inclusion.hip).  G: chunked N_v x N_s array of
-// g(cell, segment); M = (K^{s2s})^{-1} and MH = M^H, column-major N_s x N_s;
+// Single butterfly of the inclusion's cells x segments matrix G (hbi_s2v.hip):
+// V^0 over the segment leaves, W^1..W^L over the units of each level, K^L
+// over the cell nodes of depth L.  Offsets are elements of the factor store
+// F (T blocks column major), of the index store idx, and of the skeleton
+// vector z.
+struct S2VLeaf {
+  int64_t foff, ioff, zoff;   // T (r x (n - r)); idx: column order, inverse (n each)
+  int32_t r, n, lo, pad;      // rank, segments [lo, lo + n)
+};
+struct S2VNode {
+  int64_t foff, zoff;         // K (size x r, column major); skeleton vector
+  int32_t start, size, r, pad;   // cells at tree positions [start, start + size)
+};
+struct S2VPlan {
+  int L = 0;
+  const void *F = nullptr;
+  const uint16_t *idx = nullptr;
+  const int32_t *perm = nullptr;   // tree position -> natural cell index
+  const S2VLeaf *leaves = nullptr;
+  const S2VNode *nodes = nullptr;
+  int64_t nleaf = 0, nnode = 0;
+  std::vector<const WUnit *> units;   // index k = 1..L
+  std::vector<int64_t> nunits;
+  std::vector<int32_t> rows_max, cols_max;   // largest ra + rb and c of level k
+  void *z = nullptr;
+  int32_t size_max = 0, rmax_node = 0;
+};
+// transpose = false: y (cells, natural order) += scale op(G) x (segments);
+// transpose = true: y (segments) = scale op(G)^T x (cells); op = conj or not.
+template <typename R>
+hipError_t launch_s2v(const S2VPlan &p, const void *x, void *y, R scale, bool transpose,
+                      bool conj, hipStream_t st);
+
+// Curve inclusion (hbi_inclusion.hip).  G: the butterfly bf, or (bf null) a
+// chunked N_v x N_s array of g(cell, segment); M = (K^{s2s})^{-1} and MH = M^H,
+// column-major N_s x N_s;
 // w the segment lengths; part, z, y, part2, part3 scratch of nchunk*N_s,
 // N_s, N_s, ceil(N_s/256)*N_v and ceil(N_s/32)*N_s entries.
 // Element type complex64/complex128 (w float/double) as for the factors.
 struct InclusionPlan {
+  const S2VPlan *bf = nullptr;   // G as a butterfly (then G is not used)
   const void *G = nullptr, *M = nullptr, *MH = nullptr, *w = nullptr;
   void *part = nullptr, *z = nullptr, *y = nullptr, *part2 = nullptr, *part3 = nullptr;
   int64_t Nv = 0;

@@ -282,6 +282,13 @@ struct hbi_ctx {
   DevBuf cellof_d;   // [Nv + inc_ns]: the cell containing each point (DevCells::cellof)
   DevBuf inc_G, inc_M, inc_MH, inc_wf, inc_part, inc_z, inc_y, inc_part2, inc_part3;
   InclusionPlan inc_plan;
+  // G as a single butterfly (the default; HBI_INCLUSION_DENSE=1 keeps G dense)
+  DevBuf s2v_F, s2v_idx, s2v_leaves, s2v_nodes, s2v_z;
+  std::vector<DevBuf> s2v_units;
+  S2VPlan s2v_plan;
+  int s2v_L = -1;
+  int64_t s2v_entries = 0, s2v_ztotal = 0;
+  int32_t s2v_rank_max = 0;
   double t_inc = 0;
   bool profiling = false;
   Profiler prof;
@@ -343,6 +350,9 @@ struct hbi_ctx {
     inc_part.release(); inc_z.release(); inc_y.release(); inc_part2.release();
     inc_part3.release();
     inc_plan = InclusionPlan(); t_inc = 0;
+    s2v_F.release(); s2v_idx.release(); s2v_leaves.release(); s2v_nodes.release();
+    s2v_z.release(); s2v_units.clear(); s2v_plan = S2VPlan();
+    s2v_L = -1; s2v_entries = s2v_ztotal = 0; s2v_rank_max = 0;
     leaves_h.clear(); vd_h.clear(); kd_h.clear(); units_h.clear(); batch.reset(); batch_adj.reset(); ztotal = 0;
     zalloc = 0;
     z_d.release(); wst_lds = wst_global = wst_wide = 0;
@@ -1530,6 +1540,325 @@ void build_factors(hbi_ctx *c, double tol) {
   c->t_build = now_s() - tb0;
 }
 
+// The inclusion's G[j, i] = g(r_j, r^s_i) (cells j, segments i) as a single
+// butterfly (Sec. 4.2: K^{s2v} compressed as one butterfly of
+// L = min(L_v, L_s) levels, rows on the cell tree, columns on a tree of the
+// segments; proxy rows by eq. proxyv2v with the uniform rows spread over the
+// whole node).  The segment tree halves index ranges of the segments (they
+// follow the curve) down to leaves of at most kSegLeaf segments.  Level k
+// holds the blocks (t, j) of cell node t at depth k and segment node j at
+// depth L - k (block index t 2^(L-k) + j): level 0 takes a leaf's segments
+// as candidate columns, level k > 0 the skeletons of (t/2, 2j) and
+// (t/2, 2j + 1), and level L all rows of its node; K^L then holds every
+// cell of a depth-L node against that node's skeleton.  Factors are
+// rounded to the context's precision like the volume ones.
+constexpr int32_t kSegLeaf = 8;
+
+// The inclusion term passes through (K^{s2s})^{-1}, which amplifies the
+// compression error of G by its condition number; G's butterfly is small
+// next to the volume factors, so it is compressed kIncTolFactor times
+// tighter than the build tolerance (HBI_INCLUSION_TOL sets it outright).
+constexpr double kIncTolFactor = 0.01;
+double inclusion_tol(const hbi_ctx *c) {
+  const char *e = std::getenv("HBI_INCLUSION_TOL");
+  if (e && std::atof(e) > 0 && std::atof(e) < 1) return std::atof(e);
+  return c->tol * kIncTolFactor;
+}
+
+void build_s2v(hbi_ctx *c, double tol) {
+  const Geometry &G = c->geo;
+  const int32_t ns = c->inc_ns;
+  const int64_t Nv = G.Nv;
+  int Ls = 0;
+  while ((((int64_t)ns + ((int64_t)1 << Ls) - 1) >> Ls) > kSegLeaf) ++Ls;
+  const int L = std::min(G.Lv, Ls);
+  auto seg_lo = [&](int l, int64_t i) { return (int32_t)((i * ns) >> l); };
+  // the cell holding each segment centre (the proxy rule's neighbours)
+  std::vector<int32_t> segcell(ns);
+  for (int32_t i = 0; i < ns; ++i) {
+    int64_t nat = 0, stride = 1;
+    for (int a = 0; a < 2; ++a) {
+      int64_t k = (int64_t)std::floor((c->inc_xy[2 * i + a] - c->origin[a]) / c->h);
+      k = std::min<int64_t>(std::max<int64_t>(k, 0), c->ncell[a] - 1);
+      nat += k * stride;
+      stride *= c->ncell[a];
+    }
+    segcell[i] = G.ipos[nat];
+  }
+  ProxyParams pp;
+  pp.chi = c->chi();
+  pp.radius = c->radius();
+  pp.band = false;
+  // the volume operator's ID statistics are kept apart
+  const int64_t s_nid = c->nid, s_nw = c->nid_wide;
+  const int32_t s_rmax = c->rank_max, s_mmax = c->id_m_max;
+  const double s_rsum = c->rank_sum, s_msum = c->id_m_sum, s_nsum = c->id_n_sum,
+               s_w = c->id_work, s_ww = c->id_work_wide, s_w128 = c->id_work_128;
+  const int64_t s_path[3] = {c->nid_path[0], c->nid_path[1], c->nid_path[2]};
+
+  struct Lev {
+    std::vector<int32_t> rank, skel;
+    std::vector<int64_t> soff, zoff, foff, ioff;
+  };
+  Lev prev, cur;
+  std::vector<Chunk> chunks;
+  int64_t Fg = 0, ztot = 0;
+  std::vector<uint16_t> ih;
+  std::vector<S2VLeaf> leaves((size_t)1 << L);
+  std::vector<std::vector<WUnit>> units(L + 1);
+  Batcher B(c);
+  std::vector<int32_t> stamp(Nv, 0);
+  int32_t tag = 0, rmax = 0;
+  std::vector<uint16_t> ord, inv;
+  std::vector<uint8_t> mark;
+  auto orders = [&](const BlockOut &x, int32_t n) {
+    mark.assign(n, 0);
+    ord.clear();
+    for (int32_t k = 0; k < x.rank; ++k) { ord.push_back((uint16_t)x.piv[k]); mark[x.piv[k]] = 1; }
+    for (int32_t j = 0; j < n; ++j)
+      if (!mark[j]) ord.push_back((uint16_t)j);
+    if ((int32_t)ord.size() != n) throw Error{HBI_ERR_NUMERIC, "internal error: repeated pivot"};
+    inv.assign(n, 0);
+    for (int32_t k = 0; k < n; ++k) inv[ord[k]] = (uint16_t)k;
+  };
+  for (int k = 0; k <= L; ++k) {
+    const int64_t nt = (int64_t)1 << k, nj = (int64_t)1 << (L - k), nblk = nt * nj;
+    // processing order: level 0 by leaf, higher levels the sibling pairs
+    // (2t', j), (2t' + 1, j) side by side (they share their candidates)
+    std::vector<int64_t> bi(nblk);
+    {
+      int64_t q = 0;
+      if (k == 0) {
+        for (int64_t j = 0; j < nj; ++j) bi[q++] = j;
+      } else {
+        for (int64_t tp = 0; tp < nt / 2; ++tp)
+          for (int64_t j = 0; j < nj; ++j)
+            for (int h = 0; h < 2; ++h) bi[q++] = (2 * tp + h) * nj + j;
+      }
+    }
+    std::vector<std::vector<int32_t>> cand(nblk), rows(nblk), colpt(nblk);
+    std::vector<BlockIn> bin(nblk);
+    std::vector<int32_t> cells;
+    for (int64_t q = 0; q < nblk; ++q) {
+      const int64_t b = bi[q], t = b / nj, j = b % nj;
+      std::vector<int32_t> &cd = cand[q];
+      if (k == 0) {
+        for (int32_t i = seg_lo(L, j); i < seg_lo(L, j + 1); ++i) cd.push_back(i);
+      } else {
+        const int64_t in = (t >> 1) * (2 * nj) + 2 * j;
+        cd.assign(prev.skel.begin() + prev.soff[in], prev.skel.begin() + prev.soff[in + 2]);
+      }
+      if ((int64_t)cd.size() > HBI_ID_NMAX)
+        throw Error{HBI_ERR_NUMERIC, "inclusion candidate set larger than the ID kernel supports"};
+      const int64_t nd = Geometry::node(k, t);
+      if (k == L) {
+        rows[q].resize(G.nend[nd] - G.nstart[nd]);
+        for (size_t i = 0; i < rows[q].size(); ++i) rows[q][i] = G.nstart[nd] + (int32_t)i;
+      } else {
+        cells.resize(cd.size());
+        for (size_t i = 0; i < cd.size(); ++i) cells[i] = segcell[cd[i]];
+        proxy_rows(G, nd, cells.data(), (int)cells.size(), pp, rows[q], stamp, ++tag);
+      }
+      colpt[q].resize(cd.size());
+      for (size_t i = 0; i < cd.size(); ++i) colpt[q][i] = (int32_t)(Nv + cd[i]);
+      bin[q] = BlockIn{rows[q].data(), (int32_t)rows[q].size(), colpt[q].data(),
+                       (int32_t)cd.size(), nullptr};
+    }
+    cur.rank.assign(nblk, 0);
+    cur.foff.assign(nblk, 0);
+    cur.ioff.assign(nblk, 0);
+    std::vector<BlockOut> outs(nblk);
+    // each batch's T blocks packed into a chunk of the store, while its
+    // interpolation matrices are still in the workspace
+    B.run(bin, true, tol, &outs, [&](int64_t first, int64_t cnt) {
+      const bool pairs = k > 0;
+      if (pairs && (first % 2 || cnt % 2))
+        throw Error{HBI_ERR_NUMERIC, "internal error: unpaired inclusion block"};
+      int64_t tot = 0;
+      for (int64_t q = first; q < first + cnt; ++q)
+        tot += (int64_t)outs[q].rank * ((int64_t)cand[q].size() - outs[q].rank);
+      Chunk ch;
+      HBI_HIP(ch.buf.alloc(sizeof(double2) * std::max<int64_t>(tot, 1)));
+      ch.goff = Fg;
+      ch.count = tot;
+      std::vector<PairDesc> pd;
+      std::vector<uint16_t> nsl;
+      std::vector<int64_t> nso;
+      int64_t o = 0;
+      for (int64_t q = first; q < first + cnt; q += pairs ? 2 : 1) {
+        const int64_t io = (int64_t)ih.size();
+        const int32_t n = (int32_t)cand[q].size();
+        PairDesc d{outs[q].X, nullptr, ch.buf.as<double2>() + o, nullptr, nullptr, outs[q].rank,
+                   0, n, 0};
+        if (!pairs) {
+          orders(outs[q], n);
+          ih.insert(ih.end(), ord.begin(), ord.end());
+          ih.insert(ih.end(), inv.begin(), inv.end());
+          nso.push_back((int64_t)nsl.size());
+          nsl.insert(nsl.end(), ord.begin() + outs[q].rank, ord.end());
+          nso.push_back(-1);
+        } else {
+          if ((int32_t)cand[q + 1].size() != n)
+            throw Error{HBI_ERR_NUMERIC, "internal error: inclusion pair width"};
+          ih.resize(io + 4 * (int64_t)n);
+          for (int h = 0; h < 2; ++h) {
+            orders(outs[q + h], n);
+            std::copy(ord.begin(), ord.end(), ih.begin() + io + (int64_t)h * n);
+            std::copy(inv.begin(), inv.end(), ih.begin() + io + (int64_t)(2 + h) * n);
+            nso.push_back((int64_t)nsl.size());
+            nsl.insert(nsl.end(), ord.begin() + outs[q + h].rank, ord.end());
+          }
+          d.xb = outs[q + 1].X;
+          d.rb = outs[q + 1].rank;
+        }
+        for (int h = 0; h < (pairs ? 2 : 1); ++h) {
+          const int64_t b = bi[q + h];
+          cur.rank[b] = outs[q + h].rank;
+          cur.foff[b] = Fg + o;
+          cur.ioff[b] = io;
+          o += (int64_t)outs[q + h].rank * (n - outs[q + h].rank);
+          rmax = std::max(rmax, outs[q + h].rank);
+        }
+        pd.push_back(d);
+      }
+      DevBuf ns_d, pd_d;
+      upload(ns_d, nsl);
+      for (size_t e = 0; e < pd.size(); ++e) {
+        pd[e].nsa = ns_d.as<uint16_t>() + nso[2 * e];
+        if (pairs) pd[e].nsb = ns_d.as<uint16_t>() + nso[2 * e + 1];
+      }
+      upload(pd_d, pd);
+      HBI_HIP(launch_pack_pairs(pd_d.as<PairDesc>(), (int64_t)pd.size(), c->stream));
+      HBI_HIP(hipStreamSynchronize(c->stream));
+      Fg += tot;
+      chunks.push_back(std::move(ch));
+    }, k > 0);
+    // skeletons and vector offsets in block order
+    cur.soff.assign(nblk + 1, 0);
+    for (int64_t b = 0; b < nblk; ++b) cur.soff[b + 1] = cur.soff[b] + cur.rank[b];
+    cur.skel.assign(cur.soff[nblk], 0);
+    for (int64_t q = 0; q < nblk; ++q) {
+      const int64_t b = bi[q];
+      for (int32_t r = 0; r < outs[q].rank; ++r) cur.skel[cur.soff[b] + r] = cand[q][outs[q].piv[r]];
+    }
+    cur.zoff.assign(nblk, 0);
+    for (int64_t b = 0; b < nblk; ++b) { cur.zoff[b] = ztot; ztot += cur.rank[b]; }
+    if (k == 0) {
+      for (int64_t j = 0; j < nj; ++j)
+        leaves[j] = S2VLeaf{cur.foff[j], cur.ioff[j], cur.zoff[j], cur.rank[j],
+                            seg_lo(L, j + 1) - seg_lo(L, j), seg_lo(L, j), 0};
+    } else {
+      for (int64_t tp = 0; tp < nt / 2; ++tp)
+        for (int64_t j = 0; j < nj; ++j) {
+          const int64_t a = (2 * tp) * nj + j, bb = a + nj, in = tp * (2 * nj) + 2 * j;
+          WUnit U{};
+          U.ra = cur.rank[a];
+          U.rb = cur.rank[bb];
+          U.c = prev.rank[in] + prev.rank[in + 1];
+          U.foff = cur.foff[a];
+          U.ioff = cur.ioff[a];
+          U.zin = prev.zoff[in];
+          U.zouta = cur.zoff[a];
+          U.zoutb = cur.zoff[bb];
+          if (prev.zoff[in + 1] != prev.zoff[in] + prev.rank[in] ||
+              cur.foff[bb] != cur.foff[a] + (int64_t)U.ra * (U.c - U.ra) || cur.ioff[bb] != U.ioff)
+            throw Error{HBI_ERR_NUMERIC, "internal layout error in the inclusion butterfly"};
+          units[k].push_back(U);
+        }
+    }
+    std::swap(prev, cur);
+  }
+  // K^L: every cell of a depth-L node against the node's skeleton
+  std::vector<S2VNode> nodes((size_t)1 << L);
+  int32_t size_max = 0, rmax_node = 0;
+  {
+    int64_t tot = 0;
+    for (int64_t t = 0; t < ((int64_t)1 << L); ++t) {
+      const int64_t nd = Geometry::node(L, t);
+      tot += (int64_t)(G.nend[nd] - G.nstart[nd]) * prev.rank[t];
+    }
+    Chunk ch;
+    HBI_HIP(ch.buf.alloc(sizeof(double2) * std::max<int64_t>(tot, 1)));
+    ch.goff = Fg;
+    ch.count = tot;
+    std::vector<std::vector<int32_t>> rws(nodes.size()), cls(nodes.size());
+    std::vector<BlockIn> bin(nodes.size());
+    int64_t o = 0;
+    for (int64_t t = 0; t < (int64_t)nodes.size(); ++t) {
+      const int64_t nd = Geometry::node(L, t);
+      const int32_t sz = G.nend[nd] - G.nstart[nd], r = prev.rank[t];
+      rws[t].resize(sz);
+      for (int32_t i = 0; i < sz; ++i) rws[t][i] = G.nstart[nd] + i;
+      cls[t].resize(r);
+      for (int32_t i = 0; i < r; ++i) cls[t][i] = (int32_t)(Nv + prev.skel[prev.soff[t] + i]);
+      bin[t] = BlockIn{rws[t].data(), sz, cls[t].data(), r, ch.buf.as<double2>() + o};
+      nodes[t] = S2VNode{Fg + o, prev.zoff[t], G.nstart[nd], sz, r, 0};
+      size_max = std::max(size_max, sz);
+      rmax_node = std::max(rmax_node, r);
+      o += (int64_t)sz * r;
+    }
+    B.run(bin, false, tol, nullptr, [](int64_t, int64_t) {});
+    Fg += tot;
+    chunks.push_back(std::move(ch));
+  }
+  c->nid = s_nid; c->nid_wide = s_nw; c->rank_max = s_rmax; c->id_m_max = s_mmax;
+  c->rank_sum = s_rsum; c->id_m_sum = s_msum; c->id_n_sum = s_nsum; c->id_work = s_w;
+  c->id_work_wide = s_ww; c->id_work_128 = s_w128;
+  for (int q = 0; q < 3; ++q) c->nid_path[q] = s_path[q];
+  // the store: chunks in order, rounded to the context's precision
+  const bool f32 = c->prec == HBI_F32;
+  const size_t esz = f32 ? sizeof(float2) : sizeof(double2);
+  HBI_HIP(c->s2v_F.alloc(esz * std::max<int64_t>(Fg, 1)));
+  {
+    std::vector<PlaceDesc> pd;
+    for (const Chunk &ch : chunks)
+      if (ch.count) pd.push_back(PlaceDesc{ch.buf.as<double2>(), ch.goff, ch.count});
+    DevBuf pd_d;
+    upload(pd_d, pd);
+    HBI_HIP(launch_place_blocks(pd_d.as<PlaceDesc>(), (int64_t)pd.size(), c->s2v_F.p, f32,
+                                c->stream));
+    HBI_HIP(hipStreamSynchronize(c->stream));
+  }
+  chunks.clear();
+  if (ih.empty()) ih.push_back(0);
+  upload(c->s2v_idx, ih);
+  upload(c->s2v_leaves, leaves);
+  upload(c->s2v_nodes, nodes);
+  c->s2v_units.clear();
+  S2VPlan &P = c->s2v_plan;
+  P = S2VPlan();
+  P.L = L;
+  P.F = c->s2v_F.p;
+  P.idx = c->s2v_idx.as<uint16_t>();
+  P.perm = c->perm_d.as<int32_t>();
+  P.leaves = c->s2v_leaves.as<S2VLeaf>();
+  P.nodes = c->s2v_nodes.as<S2VNode>();
+  P.nleaf = (int64_t)leaves.size();
+  P.nnode = (int64_t)nodes.size();
+  P.units.assign(L + 1, nullptr);
+  P.nunits.assign(L + 1, 0);
+  P.rows_max.assign(L + 1, 0);
+  P.cols_max.assign(L + 1, 0);
+  for (int k = 1; k <= L; ++k) {
+    c->s2v_units.emplace_back();
+    upload(c->s2v_units.back(), units[k]);
+    P.units[k] = c->s2v_units.back().as<WUnit>();
+    P.nunits[k] = (int64_t)units[k].size();
+    for (const WUnit &U : units[k]) {
+      P.rows_max[k] = std::max(P.rows_max[k], U.ra + U.rb);
+      P.cols_max[k] = std::max(P.cols_max[k], U.c);
+    }
+  }
+  HBI_HIP(c->s2v_z.alloc(esz * std::max<int64_t>(ztot, 1)));
+  P.z = c->s2v_z.p;
+  P.size_max = size_max;
+  P.rmax_node = rmax_node;
+  c->s2v_L = L;
+  c->s2v_entries = Fg;
+  c->s2v_rank_max = rmax;
+  c->s2v_ztotal = ztot;
+}
+
 // Dense operators of the curve inclusion (Sec. 3.2, eq. m_v2v_inclu):
 // G[j, i] = g(r_j, r^s_i) over cells j (natural order, chunks of kIncChunk
 // cells) and segments i, evaluated by the entry kernels with the segments as
@@ -1549,9 +1878,11 @@ void build_inclusion(hbi_ctx *c) {
   std::vector<int32_t> segpos(ns), rowpos(Nv);
   for (int32_t i = 0; i < ns; ++i) segpos[i] = (int32_t)(Nv + i);
   for (int64_t j = 0; j < Nv; ++j) rowpos[j] = c->geo.ipos[j];
-  HBI_HIP(c->inc_G.alloc(esz * (size_t)Nv * ns));
+  const bool dense = env_int("HBI_INCLUSION_DENSE", 0) != 0;
+  if (!dense) build_s2v(c, inclusion_tol(c));
+  else HBI_HIP(c->inc_G.alloc(esz * (size_t)Nv * ns));
   Batcher B(c);
-  {
+  if (dense) {
     // groups of chunks whose FP64 values fit a 1 GiB scratch
     const int64_t per = (int64_t)m * ns * (int64_t)sizeof(double2);
     const int64_t gch = std::max<int64_t>(1, ((int64_t)1 << 30) / per);
@@ -1611,12 +1942,15 @@ void build_inclusion(hbi_ctx *c) {
   } else {
     upload(c->inc_wf, c->inc_w);
   }
-  HBI_HIP(c->inc_part.alloc(esz * (size_t)nchunk * ns));
+  if (dense) {
+    HBI_HIP(c->inc_part.alloc(esz * (size_t)nchunk * ns));
+    HBI_HIP(c->inc_part2.alloc(esz * (size_t)Nv * ((ns + 255) / 256)));
+  }
   HBI_HIP(c->inc_z.alloc(esz * (size_t)ns));
   HBI_HIP(c->inc_y.alloc(esz * (size_t)ns));
-  HBI_HIP(c->inc_part2.alloc(esz * (size_t)Nv * ((ns + 255) / 256)));
   HBI_HIP(c->inc_part3.alloc(esz * (size_t)ns * ((ns + 31) / 32)));
   InclusionPlan &ip = c->inc_plan;
+  ip.bf = dense ? nullptr : &c->s2v_plan;
   ip.G = c->inc_G.p; ip.M = c->inc_M.p; ip.MH = c->inc_MH.p; ip.w = c->inc_wf.p;
   ip.part = c->inc_part.p; ip.z = c->inc_z.p; ip.y = c->inc_y.p; ip.part2 = c->inc_part2.p;
   ip.part3 = c->inc_part3.p;
@@ -2439,10 +2773,15 @@ double apply_bytes(const ApplyPlan &ap, double esz) {
 // Bytes of the inclusion operators one apply streams: G twice (the
 // K^{v2s} gather and the K^{s2v} scatter), (K^{s2s})^{-1} once, and the
 // cell vectors read and written.
+// With G as a butterfly: its factors twice (the transposed and the forward
+// product), (K^{s2s})^{-1} once, the cell vectors read and written, and the
+// index store twice.
 double inclusion_apply_bytes(const hbi_ctx *c) {
   if (!c->inc_ns || c->state < 2) return 0.0;
   const double esz = c->prec == HBI_F64 ? 16.0 : 8.0;
   const double nv = (double)c->geo.Nv, ns = (double)c->inc_ns;
+  if (c->inc_plan.bf)
+    return esz * (2.0 * (double)c->s2v_entries + ns * ns + 2.0 * nv) + 2.0 * (double)c->s2v_idx.n;
   return esz * (2.0 * nv * ns + ns * ns + 2.0 * nv);
 }
 }  // namespace
@@ -2844,6 +3183,8 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       "\"build_gpu_s\": %.6f, \"build_batch_host_setup_s\": %.6f, \"build_batch_total_s\": %.6f, "
       "\"build_compact_s\": %.6f, \"build_finalize_s\": %.6f, "
       "\"inclusion_ns\": %d, \"inclusion_bytes\": %lld, \"build_inclusion_s\": %.6f, "
+      "\"inclusion_bf_levels\": %d, \"inclusion_bf_entries\": %lld, "
+      "\"inclusion_bf_rank_max\": %d, "
       "\"apply_index_bytes\": %.0f, \"inclusion_apply_bytes\": %.0f, "
       "\"apply_scratch_bytes\": %lld, \"apply_bytes\": %.0f, \"wstage_items_lds\": %lld, "
       "\"wstage_items_global\": %lld, \"wstage_items_wide\": %lld, \"wstage_cap_lds\": %d, "
@@ -2864,7 +3205,10 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       ctx->id_work_wide, ctx->id_work_128, ctx->t_build, ctx->t_geo, ctx->t_host, ctx->t_gpu, ctx->t_prep,
       ctx->t_wait, ctx->t_compact,
       ctx->t_final, ctx->inc_ns,
-      (long long)(ctx->inc_G.n + ctx->inc_M.n + ctx->inc_MH.n), ctx->t_inc,
+      (long long)(ctx->inc_G.n + ctx->inc_M.n + ctx->inc_MH.n + ctx->s2v_F.n + ctx->s2v_idx.n +
+                  ctx->s2v_z.n),
+      ctx->t_inc, ctx->inc_plan.bf ? ctx->s2v_L : -1, (long long)ctx->s2v_entries,
+      ctx->s2v_rank_max,
       apply_index_bytes(ctx->plan), inclusion_apply_bytes(ctx),
       (long long)(ctx->zalloc * (int64_t)esz), apply_bytes(ctx->plan, (double)esz),
       (long long)ctx->wst_lds, (long long)ctx->wst_global, (long long)ctx->wst_wide,
