@@ -126,12 +126,17 @@ hbi_status hbi_load_tables_from(hbi_ctx *ctx, const hbi_ctx *src, double omega);
  * segments with centres (xy[2i], xy[2i+1]), lengths w[i] > 0 and slowness
  * slowness[i] > 0 of the medium at the centres (host arrays, copied; the
  * centres must lie in the table region; 0 <= ns <= 8192, ns = 0 removes the
- * inclusion).  Later builds assemble, besides the volume factors, the dense
- * array G[j, i] = g(r_j, r^s_i) over cells and segments (N_v x ns entries,
- * read as K^{v2s} = G^T and K^{s2v} = G diag(w): the tables are symmetric)
+ * inclusion; the segments are taken in the given order, which should follow
+ * the curve).  Later builds assemble, besides the volume factors, the
+ * operator G[j, i] = g(r_j, r^s_i) over cells and segments (read as
+ * K^{v2s} = G^T and K^{s2v} = G diag(w): the tables are symmetric) as a
+ * single butterfly (Sec. 4.2: L = min(L_v, L_s) levels over the cell tree
+ * and a halving tree of the segment indices with leaves of at most 8
+ * segments, compressed at tol / 100; O(N_v) entries instead of N_v x ns),
  * and the inverse of K^{s2s} (eq. s2s, by Gauss-Jordan elimination with row
  * pivoting in FP64; HBI_ERR_NUMERIC if it is singular), both in the factors'
- * precision.  hbi_apply and hbi_apply_adjoint then apply the total operator
+ * precision.  With the environment variable HBI_INCLUSION_DENSE=1 at build
+ * time G is kept dense instead (N_v x ns entries), for comparison.  hbi_apply and hbi_apply_adjoint then apply the total operator
  * of eq. m_v2v_inclu, (K^{v2v} + K^{s2v} (K^{s2s})^{-1} K^{v2s}) h^d, and its
  * conjugate transpose; hbi_apply_batched rejects such contexts.  The
  * diagonal of K^{s2s} is -(i w/4)[1 + (2i/pi)(log(e^gamma omega n w/4) - 1)],
