@@ -78,6 +78,11 @@ hipError_t launch_id_onchip(const IdBlock *blks, const int32_t *sel, int64_t nb,
 // (falls back to launch_cpqr otherwise).
 hipError_t launch_cpqr_blocked(const IdBlock *blks, const int32_t *sel, int64_t nb, int nmax,
                                int mmax, double tol, int32_t *rank, hipStream_t st);
+// Tall blocks (m >= n, every selected one): k_gram forms G = A^H A in X's
+// space, k_pchol the pivoted Cholesky factorisation of G (the pivots and R of
+// the column-pivoted QR of A) and X; nmax = their largest n.
+hipError_t launch_id_gram(const IdBlock *blks, const int32_t *sel, int64_t nb, int nmax,
+                          double tol, int32_t *rank, hipStream_t st);
 hipError_t launch_pack_pairs(const PairDesc *d, int64_t np, hipStream_t st);
 hipError_t launch_place_blocks(const PlaceDesc *d, int64_t nb, void *F, bool f32,
                                hipStream_t st);

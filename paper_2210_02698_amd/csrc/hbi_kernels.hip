@@ -1472,6 +1472,191 @@ hipError_t launch_entries(const DevProblem &P, const DevCells &C, const EntryBlo
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Interpolative decomposition of a tall block (m >= n) from its Gram matrix.
+// The column-pivoted QR of A and the pivoted Cholesky factorisation of
+// G = A^H A choose the same pivots and the same R in exact arithmetic (the
+// remaining column norms of the QR are the square roots of the remaining
+// diagonal of the Cholesky factorisation), so A is read once, by an MFMA
+// product, instead of once per pivot step:
+//   k_gram   G = A^H A (n x n, row major, in X's space, which holds
+//            min(m, n) n >= n^2 entries), FP64 16x16x4 MFMA tiles of the
+//            upper triangle, mirrored;
+//   k_pchol  left-looking pivoted Cholesky of G with the pivot rule and
+//            stopping test of k_cpqr (largest remaining norm, stop once it
+//            is at most tol |R_00|): the rows of R, row major in A's space
+//            (A is not needed any more), then X = R11^-1 [R11 R12] written
+//            as k_cpqr writes it.
+// Rounding: the Gram matrix squares the condition number.  A remaining
+// diagonal entry carries an absolute error of about eps |a_j|^2, which can
+// swap pivots that are within rounding of each other and keep columns of
+// norm up to about sqrt(n eps) |A| (a rank that much larger at most); the
+// interpolation residual stays at about eps times the skeleton's condition
+// number.
+// ---------------------------------------------------------------------------
+constexpr int kGramWG = 8;   // workgroups per block in k_gram
+
+__global__ __launch_bounds__(256) void k_gram(const IdBlock *blks, const int32_t *sel) {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  const int blk = sel[blockIdx.x / kGramWG];
+  const int part = blockIdx.x % kGramWG;
+  const IdBlock B = blks[blk];
+  const int m = B.m, n = B.n;
+  const int nt = (n + 15) / 16, ntri = nt * (nt + 1) / 2;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  double2 *G = B.X;
+  constexpr int KS = 4;   // MFMA k-steps whose loads are issued together
+  for (int t = part * 4 + wave; t < ntri; t += kGramWG * 4) {
+    int I = 0, rem = t;
+    while (rem >= nt - I) { rem -= nt - I; ++I; }
+    const int J = I + rem;
+    const int ci = I * 16 + li, cj = J * 16 + li;
+    const bool oi = ci < n, oj = cj < n;
+    const double2 *ai = B.A + (int64_t)(oi ? ci : 0) * m;
+    const double2 *aj = B.A + (int64_t)(oj ? cj : 0) * m;
+    v4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < m; k0 += 4 * KS) {
+      double2 x[KS], y[KS];
+#pragma unroll
+      for (int q = 0; q < KS; ++q) {
+        const int k = k0 + 4 * q + lk;
+        const int kc = k < m ? k : 0;
+        x[q] = ai[kc];
+        y[q] = aj[kc];
+        if (!(oi && k < m)) x[q] = double2{0.0, 0.0};
+        if (!(oj && k < m)) y[q] = double2{0.0, 0.0};
+      }
+#pragma unroll
+      for (int q = 0; q < KS; ++q) {
+        // conj(x) y
+        re = __builtin_amdgcn_mfma_f64_16x16x4f64(x[q].x, y[q].x, re, 0, 0, 0);
+        re = __builtin_amdgcn_mfma_f64_16x16x4f64(x[q].y, y[q].y, re, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f64_16x16x4f64(x[q].x, y[q].y, im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f64_16x16x4f64(-x[q].y, y[q].x, im, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = I * 16 + lk + 4 * v, col = J * 16 + li;
+      if (row < n && col < n) {
+        G[(int64_t)row * n + col] = double2{re[v], im[v]};
+        if (I != J) G[(int64_t)col * n + row] = double2{re[v], -im[v]};
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(HBI_ID_THREADS) void k_pchol(const IdBlock *blks, const int32_t *sel,
+                                                           double tol, int32_t *rank_out) {
+  extern __shared__ double lds_pc[];
+  constexpr int T = HBI_ID_THREADS, NW = T / 64;
+  __shared__ double red_v[NW];
+  __shared__ int red_i[NW];
+  __shared__ int sh_stop, sh_rank, sh_p;
+  __shared__ double sh_nrm, sh_r11;
+  const int blk = sel[blockIdx.x];
+  const IdBlock B = blks[blk];
+  const int n = B.n;
+  const double2 *G = B.X;
+  double2 *R = B.A;                                  // row k of R at R + k n
+  double2 *rp = (double2 *)lds_pc;                   // n: R[l][p], l < k
+  double *d = lds_pc + 2 * (int64_t)n;               // n: remaining diagonal
+  int *colmap = (int *)(d + n);                      // n: pivot order
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j = tid; j < n; j += T) {
+    d[j] = fmax(G[(int64_t)j * n + j].x, 0.0);
+    colmap[j] = j;
+  }
+  if (tid == 0) { sh_rank = n; sh_r11 = 0.0; }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    // largest remaining diagonal over positions [k, n) (lowest position on ties)
+    double bv = -1.0;
+    int bq = n;
+    for (int q = k + tid; q < n; q += T) {
+      const double v = d[colmap[q]];
+      if (v > bv) { bv = v; bq = q; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o, 64);
+      const int oq = __shfl_xor(bq, o, 64);
+      if (ov > bv || (ov == bv && oq < bq)) { bv = ov; bq = oq; }
+    }
+    if (lane == 0) { red_v[wave] = bv; red_i[wave] = bq; }
+    __syncthreads();
+    if (tid == 0) {
+      double v = red_v[0];
+      int q = red_i[0];
+      for (int w2 = 1; w2 < NW; ++w2)
+        if (red_v[w2] > v || (red_v[w2] == v && red_i[w2] < q)) { v = red_v[w2]; q = red_i[w2]; }
+      const double nrm = sqrt(fmax(v, 0.0));
+      if (k == 0) sh_r11 = nrm;
+      const int stop = (q >= n) || (nrm == 0.0) || (k > 0 && nrm <= tol * sh_r11);
+      sh_stop = stop;
+      if (stop) {
+        sh_rank = k > 0 ? k : 1;
+      } else {
+        const int t = colmap[k];
+        colmap[k] = colmap[q];
+        colmap[q] = t;
+        sh_p = colmap[k];
+        sh_nrm = nrm;
+      }
+    }
+    __syncthreads();
+    if (sh_stop) break;
+    const int p = sh_p;
+    const double nrm = sh_nrm, inv = 1.0 / nrm;
+    for (int l = tid; l < k; l += T) rp[l] = R[(int64_t)l * n + p];
+    if (tid == 0) R[(int64_t)k * n + p] = double2{nrm, 0.0};
+    __syncthreads();
+    // row k over the remaining columns: (G[p][j] - sum_l conj(R[l][p]) R[l][j]) / R_kk
+    for (int q = k + 1 + tid; q < n; q += T) {
+      const int j = colmap[q];
+      double2 acc = G[(int64_t)p * n + j];
+      int l = 0;
+      for (; l + 4 <= k; l += 4) {
+        double2 rv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) rv[u] = R[(int64_t)(l + u) * n + j];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double2 a = rp[l + u];
+          acc.x -= a.x * rv[u].x + a.y * rv[u].y;
+          acc.y -= a.x * rv[u].y - a.y * rv[u].x;
+        }
+      }
+      for (; l < k; ++l) {
+        const double2 a = rp[l], b = R[(int64_t)l * n + j];
+        acc.x -= a.x * b.x + a.y * b.y;
+        acc.y -= a.x * b.y - a.y * b.x;
+      }
+      const double2 rkj = double2{acc.x * inv, acc.y * inv};
+      R[(int64_t)k * n + j] = rkj;
+      d[j] = fmax(d[j] - (rkj.x * rkj.x + rkj.y * rkj.y), 0.0);
+    }
+    __syncthreads();
+  }
+  const int r = sh_rank;
+  const bool zero = !(sh_r11 > 0.0);
+  double2 *X = B.X;   // G is not read any more
+  for (int idx = tid; idx < r * r; idx += T) {
+    const int q = idx / r, i = idx % r;
+    X[i + (int64_t)colmap[q] * r] = double2{i == q ? 1.0 : 0.0, 0.0};
+  }
+  for (int q = tid; q < r; q += T) B.piv[q] = colmap[q];
+  auto Rat = [R, colmap, n](int i, int l) { return R[(int64_t)i * n + colmap[l]]; };
+  for (int q = r + tid; q < n; q += T) {
+    const int col = colmap[q];
+    double2 *xo = X + (int64_t)col * r;
+    for (int i = 0; i < r; ++i) xo[i] = R[(int64_t)i * n + col];
+    solve_upper(Rat, xo, r, zero);
+  }
+  if (tid == 0) rank_out[blk] = r;
+}
+
 static hipError_t lds_limit(int *ldsmax) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -1550,6 +1735,26 @@ hipError_t launch_id_onchip(const IdBlock *blks, const int32_t *sel, int64_t nb,
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_id_onchip<8, 8, 2, 4>), dim3(nb), dim3(512), lds, st, blks, sel, tol, rank,
                      cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_id_gram(const IdBlock *blks, const int32_t *sel, int64_t nb, int nmax,
+                          double tol, int32_t *rank, hipStream_t st) {
+  if (nb == 0) return hipSuccess;
+  int ldsmax = 65536;
+  hipError_t e = lds_limit(&ldsmax);
+  if (e != hipSuccess) return e;
+  // rp (16 B), d (8 B) and colmap (4 B) per column
+  const size_t lds = (size_t)28 * nmax + 64;
+  if (lds > (size_t)ldsmax) return hipErrorInvalidValue;
+  if (lds > 65536) {
+    e = hipFuncSetAttribute((const void *)k_pchol, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_gram, dim3((unsigned)(nb * kGramWG)), dim3(256), 0, st, blks, sel);
+  hipLaunchKernelGGL(k_pchol, dim3((unsigned)nb), dim3(HBI_ID_THREADS), lds, st, blks, sel, tol,
+                     rank);
   return hipGetLastError();
 }
 

@@ -304,7 +304,7 @@ struct hbi_ctx {
   double t_prep = 0, t_wait = 0, t_compact = 0;   // inside t_gpu: batch host set-up, batch total, compaction
   int64_t nnz_v = 0, nnz_w = 0, nnz_k = 0, nnz_d = 0, entries_eval = 0, nid = 0;
   int64_t entry_slots = 0;   // entry-tile capacity launched (fill = entries_eval / entry_slots)
-  int64_t nid_path[3] = {0, 0, 0};   // IDs per kernel group (on chip, unused, global)
+  int64_t nid_path[3] = {0, 0, 0};   // IDs per kernel group (on chip, Gram matrix, global QR)
   int32_t rank_max = 0, id_m_max = 0;
   double rank_sum = 0, id_m_sum = 0, id_n_sum = 0, id_work = 0, id_work_wide = 0, id_work_128 = 0;
   int64_t nid_wide = 0;
@@ -477,16 +477,29 @@ struct BlockOut {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Widest block of the Gram-matrix ID path: its per-column LDS (28 B) within
+// a workgroup's share.
+static int id_gram_nmax() { return 4096; }
+// Smallest build tolerance of the Gram-matrix ID path.  Forming A^H A costs
+// the remaining column norms an absolute error of about sqrt(k eps) |a_j|
+// after k steps (1.5e-7 of the column at k = 100): at tol >= 1e-6 the
+// stopping test and the pivots it keeps stay above that; tighter builds
+// (the FP64 ones) keep the pivoted QR of A itself.
+constexpr double kGramMinTol = 1e-6;
+
 // Which kernels decompose the blocks (HBI_ID_KERNEL, for comparisons):
 // by default blocks of at most HBI_ID_ONCHIP_NMAX columns on chip and wider
 // ones by the global-memory pivoted QR (k_cpqr); "global" sends every block
 // to k_cpqr, "blocked" every block to its panel form (k_cpqr_blocked, which
 // measured slower than k_cpqr on the 2D and 3D workloads).
-enum IdKernels { ID_AUTO = 0, ID_GLOBAL = 1, ID_BLOCKED = 2 };
+// "cpqr" keeps the default's on-chip kernel for narrow blocks but sends
+// every wider block to k_cpqr instead of the Gram-matrix path.
+enum IdKernels { ID_AUTO = 0, ID_GLOBAL = 1, ID_BLOCKED = 2, ID_CPQR = 3 };
 static IdKernels id_kernels() {
   const char *e = std::getenv("HBI_ID_KERNEL");
   if (e && std::strcmp(e, "global") == 0) return ID_GLOBAL;
   if (e && std::strcmp(e, "blocked") == 0) return ID_BLOCKED;
+  if (e && std::strcmp(e, "cpqr") == 0) return ID_CPQR;
   return ID_AUTO;
 }
 
@@ -662,17 +675,20 @@ struct Batcher {
     const int32_t tcols = entry_tile_cols(c->dim);
     std::vector<int32_t> rslot(nrows);
     std::vector<int64_t> ntile(nb);
-    // ID kernel per block: on chip up to HBI_ID_ONCHIP_NMAX columns, the
-    // global-memory pivoted QR beyond; sel lists the groups.  (Group 1, the
-    // triangular factor on chip followed by the global pivoted QR of it for
-    // n <= 128, measured no faster than group 2 and is left empty.)
+    // ID kernel per block: on chip up to HBI_ID_ONCHIP_NMAX columns (group
+    // 0); wider blocks with at least as many rows as columns through their
+    // Gram matrix (group 1), the others by the global-memory pivoted QR
+    // (group 2); sel lists the groups.
     std::vector<int32_t> sel;
     P.idk = id ? id_kernels() : ID_AUTO;
     if (id) {
       std::vector<int32_t> g[3];
+      const int gram_nmax = id_gram_nmax();
       for (int64_t q = 0; q < nb; ++q) {
         const BlockIn &b = blocks[i0 + q];
-        const int k = P.idk != ID_AUTO || b.n > HBI_ID_ONCHIP_NMAX ? 2 : 0;
+        int k = (P.idk == ID_AUTO || P.idk == ID_CPQR) && b.n <= HBI_ID_ONCHIP_NMAX ? 0 : 2;
+        if (k == 2 && P.idk == ID_AUTO && tol >= kGramMinTol && b.m >= b.n && b.n <= gram_nmax)
+          k = 1;
         g[k].push_back((int32_t)q);
         P.nmax_g[k] = std::max(P.nmax_g[k], (int)b.n);
         if (k == 2) P.mmax_w = std::max(P.mmax_w, (int)b.m);
@@ -824,7 +840,7 @@ struct Batcher {
       const int32_t *seld = (const int32_t *)(ix + P.o_sel);
       int32_t *rankd = (int32_t *)(ix + P.o_rank);
       HBI_HIP(launch_id_onchip(ibd, seld, P.nsel[0], P.nmax_g[0], P.tol, rankd, c->stream));
-      HBI_HIP(launch_id_onchip(ibd, seld + P.nsel[0], P.nsel[1], P.nmax_g[1], P.tol, rankd, c->stream));
+      HBI_HIP(launch_id_gram(ibd, seld + P.nsel[0], P.nsel[1], P.nmax_g[1], P.tol, rankd, c->stream));
       if (P.idk == ID_BLOCKED)
         HBI_HIP(launch_cpqr_blocked(ibd, seld + P.nsel[0] + P.nsel[1], P.nsel[2], P.nmax_g[2],
                                     P.mmax_w, P.tol, rankd, c->stream));
@@ -3176,7 +3192,7 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       "\"nnz_v\": %lld, \"nnz_w\": %lld, \"nnz_k\": %lld, \"nnz_dense\": %lld, "
       "\"nnz_total\": %lld, \"factor_bytes\": %lld, \"index_bytes\": %lld, \"z_entries\": %lld, "
       "\"n_id\": %lld, \"rank_max\": %d, \"rank_mean\": %.3f, \"entries_evaluated\": %lld, "
-      "\"entry_tile_fill\": %.4f, \"n_id_onchip\": %lld, \"n_id_global\": %lld, "
+      "\"entry_tile_fill\": %.4f, \"n_id_onchip\": %lld, \"n_id_global\": %lld, \"n_id_gram\": %lld, "
       "\"id_rows_mean\": %.1f, \"id_rows_max\": %d, \"id_cols_mean\": %.1f, \"id_cmac\": %.6e, "
       "\"n_id_cols_gt64\": %lld, \"id_cmac_cols_gt64\": %.6e, \"id_cmac_cols_gt128\": %.6e, "
       "\"build_s\": %.6f, \"build_geometry_s\": %.6f, \"build_proxy_host_s\": %.6f, "
@@ -3199,7 +3215,7 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       (long long)ctx->nid, ctx->rank_max, ctx->nid ? ctx->rank_sum / ctx->nid : 0.0,
       (long long)ctx->entries_eval,
       ctx->entry_slots ? (double)ctx->entries_eval / (double)ctx->entry_slots : 0.0,
-      (long long)ctx->nid_path[0], (long long)ctx->nid_path[2],
+      (long long)ctx->nid_path[0], (long long)ctx->nid_path[2], (long long)ctx->nid_path[1],
       ctx->nid ? ctx->id_m_sum / ctx->nid : 0.0, ctx->id_m_max,
       ctx->nid ? ctx->id_n_sum / ctx->nid : 0.0, ctx->id_work, (long long)ctx->nid_wide,
       ctx->id_work_wide, ctx->id_work_128, ctx->t_build, ctx->t_geo, ctx->t_host, ctx->t_gpu, ctx->t_prep,

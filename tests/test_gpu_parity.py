@@ -307,13 +307,16 @@ def test_3d_apply_sampled_rows(torch_mod):
 @pytest.mark.parametrize("prec,tol,bound", [("f64", 1e-7, 1e-6), ("f32", 1e-5, 1e-4)])
 def test_id_kernels_agree(torch_mod, monkeypatch, prec, tol, bound):
     """By default blocks of at most 64 candidate columns are decomposed on
-    chip (pivoted QR of the triangular factor of the block) and wider ones by
-    the global-memory pivoted QR; HBI_ID_KERNEL=global sends every block to
-    the global-memory kernel and =blocked to its panel (deferred-update) form.  The
-    last two builds also turn the per-cell column-side cache off
-    (HBI_HC_CACHE_BYTES=0), so entries come from the per-block column side.
-    All three operators agree with the oracle and with each other to the
-    compression tolerance, with nearly the same ranks."""
+    chip (pivoted QR of the triangular factor of the block) and wider ones,
+    at tol >= 1e-6 and with at least as many rows as columns, through their
+    Gram matrix (pivoted Cholesky), the rest by the global-memory pivoted
+    QR; HBI_ID_KERNEL=cpqr sends every wide block to the global-memory
+    pivoted QR, =global every block, and =blocked every block to its panel
+    (deferred-update) form.  The last two builds also turn the per-cell
+    column-side cache off (HBI_HC_CACHE_BYTES=0), so entries come from the
+    per-block column side.  All four operators agree with the oracle and
+    with each other to the compression tolerance, with nearly the same
+    ranks."""
     torch = torch_mod
     prob = hb_inputs.configs.c2(128)
     dt = torch.complex128 if prec == "f64" else torch.complex64
@@ -321,9 +324,10 @@ def test_id_kernels_agree(torch_mod, monkeypatch, prec, tol, bound):
     rows = np.random.default_rng(6).choice(prob.Nv, 64, replace=False)
     ref = oracle.apply(prob, s, rows)
     out = {}
-    for kind in ("auto", "global", "blocked"):
+    for kind in ("auto", "cpqr", "global", "blocked"):
         if kind != "auto":
             monkeypatch.setenv("HBI_ID_KERNEL", kind)
+        if kind in ("global", "blocked"):
             monkeypatch.setenv("HBI_HC_CACHE_BYTES", "0")
         say(f"id kernel {kind} {prec} tol {tol}")
         op = make_op(prob, tol=tol, prec=prec)
@@ -333,15 +337,49 @@ def test_id_kernels_agree(torch_mod, monkeypatch, prec, tol, bound):
         say(f"{kind} rank mean {out[kind][1]['rank_mean']:.3f}")
         op.close()
     info = out["auto"][1]
-    say(f"auto paths: on chip {info['n_id_onchip']}, global {info['n_id_global']}")
-    assert info["n_id_onchip"] > 0 and info["n_id_global"] > 0, info
+    say(f"auto paths: on chip {info['n_id_onchip']}, Gram {info['n_id_gram']}, "
+        f"global {info['n_id_global']}")
+    assert info["n_id_onchip"] > 0, info
+    if tol >= 1e-6:
+        assert info["n_id_gram"] > 0, info
+    else:
+        assert info["n_id_gram"] == 0 and info["n_id_global"] > 0, info
+    assert out["cpqr"][1]["n_id_gram"] == 0 and out["cpqr"][1]["n_id_global"] > 0
     assert out["global"][1]["n_id_onchip"] == 0
-    for kind in ("global", "blocked"):
+    for kind in ("cpqr", "global", "blocked"):
         d = rel(out["auto"][0], out[kind][0])
         say(f"auto vs {kind} {d:.3e}")
         assert d < bound, (kind, d)
         r1, r2 = out["auto"][1]["rank_mean"], out[kind][1]["rank_mean"]
         assert abs(r1 - r2) <= 0.02 * r2, (kind, r1, r2)
+
+
+def test_gram_id_in_3d(torch_mod, monkeypatch):
+    """The 3D sinusoid at 32^3 cells, FP32 at tol 1e-6: the wide blocks go
+    through their Gram matrix; the operator matches the oracle on sampled
+    rows and the one built with the pivoted QR of every wide block to the
+    tolerance, with ranks within 3 %."""
+    torch = torch_mod
+    prob = hb_inputs.configs.c5(32, nI=9)
+    s = hb_inputs.complex_normal(prob.Nv, [13, 0])
+    rows = np.sort(np.random.default_rng(13).choice(prob.Nv, 48, replace=False))
+    ref = oracle.apply(prob, s, rows)
+    out = {}
+    for kind in ("auto", "cpqr"):
+        if kind == "cpqr":
+            monkeypatch.setenv("HBI_ID_KERNEL", "cpqr")
+        say(f"3d id path {kind}")
+        op = make_op(prob, tol=1e-6, prec="f32")
+        u = op.apply(to_dev(torch, s, torch.complex64)).cpu().numpy().astype(np.complex128)
+        out[kind] = (u, op.info())
+        check(u[rows], ref, 1e-4, f"3d {kind}")
+        op.close()
+    ia, ic = out["auto"][1], out["cpqr"][1]
+    say(f"Gram IDs {ia['n_id_gram']}, rank mean {ia['rank_mean']:.2f} vs {ic['rank_mean']:.2f}, "
+        f"build {ia['build_s']:.2f} s vs {ic['build_s']:.2f} s")
+    assert ia["n_id_gram"] > 0 and ic["n_id_gram"] == 0
+    assert abs(ia["rank_mean"] - ic["rank_mean"]) <= 0.03 * ic["rank_mean"]
+    assert rel(out["auto"][0], out["cpqr"][0]) < 1e-4
 
 
 def test_small_build_workspace_many_batches(torch_mod):
