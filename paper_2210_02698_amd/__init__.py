@@ -219,7 +219,7 @@ class Operator:
         return out.t()
 
     def info(self) -> dict:
-        buf = ctypes.create_string_buffer(8192)
+        buf = ctypes.create_string_buffer(16384)
         self._check(self._lib.hbi_get_info(self._ctx, buf, len(buf)))
         return json.loads(buf.value.decode())
 

@@ -200,8 +200,9 @@ __global__ void k_inc_reduce(const cplx_t<R> *part, int64_t nchunk, int32_t ns, 
 // y_i = sum_k A[i + k ns] v_k with v = z (forward, y scaled by w_i after the
 // sum) or v = w z (adjoint).  k_inc_small: partial sums over column block
 // kb = blockIdx.y of kIncCol columns, one thread per output row;
-// k_inc_small_sum adds the blocks in order.
-constexpr int kIncCol = 32;
+// k_inc_small_sum adds the blocks in order (256-column blocks keep that sum
+// short: with 32 it was a few hundred terms per row on 32 workgroups).
+constexpr int kIncCol = 256;
 
 template <typename R, bool ADJ>
 __global__ __launch_bounds__(256) void k_inc_small(const cplx_t<R> *A, int32_t ns, const R *w,

@@ -115,9 +115,15 @@ struct S2VPlan {
   int64_t nleaf = 0, nnode = 0;
   std::vector<const WUnit *> units;   // index k = 1..L
   std::vector<int64_t> nunits;
-  std::vector<int32_t> rows_max, cols_max;   // largest ra + rb and c of level k
+  // work items (descriptor index, first of four outputs) of the wave-per-
+  // output kernels: rows of level k's units, their inputs (transposed), and
+  // the skeleton columns of the K^L nodes (transposed)
+  std::vector<const int2 *> witems, wtitems;   // index k
+  std::vector<int64_t> nwitems, nwtitems;
+  const int2 *ktitems = nullptr;
+  int64_t nktitems = 0;
   void *z = nullptr;
-  int32_t size_max = 0, rmax_node = 0;
+  int32_t size_max = 0;
 };
 // transpose = false: y (cells, natural order) += scale op(G) x (segments);
 // transpose = true: y (segments) = scale op(G)^T x (cells); op = conj or not.
@@ -129,7 +135,7 @@ hipError_t launch_s2v(const S2VPlan &p, const void *x, void *y, R scale, bool tr
 // chunked N_v x N_s array of g(cell, segment); M = (K^{s2s})^{-1} and MH = M^H,
 // column-major N_s x N_s;
 // w the segment lengths; part, z, y, part2, part3 scratch of nchunk*N_s,
-// N_s, N_s, ceil(N_s/256)*N_v and ceil(N_s/32)*N_s entries.
+// N_s, N_s, ceil(N_s/256)*N_v and ceil(N_s/256)*N_s entries.
 // Element type complex64/complex128 (w float/double) as for the factors.
 struct InclusionPlan {
   const S2VPlan *bf = nullptr;   // G as a butterfly (then G is not used)

@@ -1786,7 +1786,7 @@ void build_s2v(hbi_ctx *c, double tol) {
   }
   // K^L: every cell of a depth-L node against the node's skeleton
   std::vector<S2VNode> nodes((size_t)1 << L);
-  int32_t size_max = 0, rmax_node = 0;
+  int32_t size_max = 0;
   {
     int64_t tot = 0;
     for (int64_t t = 0; t < ((int64_t)1 << L); ++t) {
@@ -1810,7 +1810,6 @@ void build_s2v(hbi_ctx *c, double tol) {
       bin[t] = BlockIn{rws[t].data(), sz, cls[t].data(), r, ch.buf.as<double2>() + o};
       nodes[t] = S2VNode{Fg + o, prev.zoff[t], G.nstart[nd], sz, r, 0};
       size_max = std::max(size_max, sz);
-      rmax_node = std::max(rmax_node, r);
       o += (int64_t)sz * r;
     }
     B.run(bin, false, tol, nullptr, [](int64_t, int64_t) {});
@@ -1853,22 +1852,44 @@ void build_s2v(hbi_ctx *c, double tol) {
   P.nnode = (int64_t)nodes.size();
   P.units.assign(L + 1, nullptr);
   P.nunits.assign(L + 1, 0);
-  P.rows_max.assign(L + 1, 0);
-  P.cols_max.assign(L + 1, 0);
+  P.witems.assign(L + 1, nullptr);
+  P.wtitems.assign(L + 1, nullptr);
+  P.nwitems.assign(L + 1, 0);
+  P.nwtitems.assign(L + 1, 0);
+  // four outputs per workgroup: (descriptor, first output)
+  auto quads = [](std::vector<int2> &v, int32_t d, int32_t n) {
+    for (int32_t o = 0; o < n; o += 4) v.push_back(int2{d, o});
+  };
   for (int k = 1; k <= L; ++k) {
+    std::vector<int2> wi, wti;
+    for (size_t u = 0; u < units[k].size(); ++u) {
+      quads(wi, (int32_t)u, units[k][u].ra + units[k][u].rb);
+      quads(wti, (int32_t)u, units[k][u].c);
+    }
     c->s2v_units.emplace_back();
     upload(c->s2v_units.back(), units[k]);
     P.units[k] = c->s2v_units.back().as<WUnit>();
     P.nunits[k] = (int64_t)units[k].size();
-    for (const WUnit &U : units[k]) {
-      P.rows_max[k] = std::max(P.rows_max[k], U.ra + U.rb);
-      P.cols_max[k] = std::max(P.cols_max[k], U.c);
-    }
+    c->s2v_units.emplace_back();
+    upload(c->s2v_units.back(), wi);
+    P.witems[k] = c->s2v_units.back().as<int2>();
+    P.nwitems[k] = (int64_t)wi.size();
+    c->s2v_units.emplace_back();
+    upload(c->s2v_units.back(), wti);
+    P.wtitems[k] = c->s2v_units.back().as<int2>();
+    P.nwtitems[k] = (int64_t)wti.size();
+  }
+  {
+    std::vector<int2> kti;
+    for (size_t t = 0; t < nodes.size(); ++t) quads(kti, (int32_t)t, nodes[t].r);
+    c->s2v_units.emplace_back();
+    upload(c->s2v_units.back(), kti);
+    P.ktitems = c->s2v_units.back().as<int2>();
+    P.nktitems = (int64_t)kti.size();
   }
   HBI_HIP(c->s2v_z.alloc(esz * std::max<int64_t>(ztot, 1)));
   P.z = c->s2v_z.p;
   P.size_max = size_max;
-  P.rmax_node = rmax_node;
   c->s2v_L = L;
   c->s2v_entries = Fg;
   c->s2v_rank_max = rmax;
@@ -1964,7 +1985,7 @@ void build_inclusion(hbi_ctx *c) {
   }
   HBI_HIP(c->inc_z.alloc(esz * (size_t)ns));
   HBI_HIP(c->inc_y.alloc(esz * (size_t)ns));
-  HBI_HIP(c->inc_part3.alloc(esz * (size_t)ns * ((ns + 31) / 32)));
+  HBI_HIP(c->inc_part3.alloc(esz * (size_t)ns * ((ns + 255) / 256)));
   InclusionPlan &ip = c->inc_plan;
   ip.bf = dense ? nullptr : &c->s2v_plan;
   ip.G = c->inc_G.p; ip.M = c->inc_M.p; ip.MH = c->inc_MH.p; ip.w = c->inc_wf.p;
@@ -3184,7 +3205,16 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
   if (!json || cap <= 0) { ctx->err = "null or empty output buffer"; return HBI_ERR_ARG; }
   const int64_t Nv = ctx->geo.Nv;
   const size_t esz = ctx->prec == HBI_F64 ? 16 : 8;
-  char buf[8192];
+  // algorithmic bytes of each forward transfer launch (levels 1..L_max)
+  std::string wl = "[";
+  for (size_t k = 1; k < ctx->plan.w_elems.size(); ++k) {
+    char t[32];
+    std::snprintf(t, sizeof t, "%s%.0f", k > 1 ? ", " : "",
+                  ctx->plan.w_elems[k] * (double)esz + ctx->plan.w_idx[k]);
+    wl += t;
+  }
+  wl += "]";
+  char buf[12288];
   const int len = std::snprintf(
       buf, sizeof buf,
       "{\"state\": %d, \"dim\": %d, \"N_v\": %lld, \"L_v\": %d, \"NT\": %d, \"nI\": %d, "
@@ -3206,7 +3236,7 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       "\"wstage_items_global\": %lld, \"wstage_items_wide\": %lld, \"wstage_cap_lds\": %d, "
       "\"wstage_c_quantiles\": [%d, %d, %d, %d, %d], \"nnz_per_cell\": %.3f, "
       "\"nnz_per_cell_over_log2sq\": %.5f, \"tab_sources\": %d, \"tab_rounds_max\": %d, "
-      "\"tab_point_updates\": %.0f, \"tab_s\": %.6f}",
+      "\"tab_point_updates\": %.0f, \"tab_s\": %.6f, \"wstage_bytes_per_level\": %s}",
       ctx->state, ctx->dim, (long long)Nv, ctx->geo.Lv, ctx->NT, ctx->nI,
       ctx->prec == HBI_F64 ? "f64" : "f32", ctx->tol, ctx->chi(), ctx->leaf(),
       (long long)ctx->nnz_v, (long long)ctx->nnz_w, (long long)ctx->nnz_k, (long long)ctx->nnz_d,
@@ -3232,7 +3262,7 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       ctx->wst_cq[3], ctx->wst_cq[4], Nv ? (double)ctx->Felems / (double)Nv : 0.0,
       Nv > 1 ? (double)ctx->Felems / (double)Nv / (std::log2((double)Nv) * std::log2((double)Nv))
              : 0.0,
-      ctx->tab_sources, ctx->tab_rounds_max, ctx->tab_point_updates, ctx->tab_s);
+      ctx->tab_sources, ctx->tab_rounds_max, ctx->tab_point_updates, ctx->tab_s, wl.c_str());
   if (len < 0 || len >= cap) { ctx->err = "output buffer too small"; return HBI_ERR_ARG; }
   std::memcpy(json, buf, len + 1);
   return HBI_OK;

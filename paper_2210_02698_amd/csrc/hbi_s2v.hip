@@ -18,7 +18,8 @@
 // element, sums in a fixed order: results are bitwise repeatable.  The
 // transfer and K^L-transposed kernels give each output a wave (lanes over
 // its sum), so that a sum of a few hundred terms is not one lane's chain of
-// dependent loads.
+// dependent loads; their workgroups (four outputs each) come from exact
+// item lists, not a grid sized for the largest unit.
 #include "hbi_kernels.h"
 #include "hbi_device.h"
 
@@ -52,11 +53,13 @@ __global__ __launch_bounds__(64) void k_s2v_v(const S2VLeaf *lv, const cplx_t<R>
 // zin[ia[ra + m]], the lanes taking m = lane, lane + 64, ... and their
 // partial sums added in a fixed tree.
 template <typename R, bool CONJ>
-__global__ __launch_bounds__(256) void k_s2v_w(const WUnit *units, const cplx_t<R> *F,
-                                               const uint16_t *idx, cplx_t<R> *z) {
+__global__ __launch_bounds__(256) void k_s2v_w(const WUnit *units, const int2 *items,
+                                               const cplx_t<R> *F, const uint16_t *idx,
+                                               cplx_t<R> *z) {
   using C = cplx_t<R>;
-  const WUnit U = units[blockIdx.x];
-  const int ii = blockIdx.y * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int2 it = items[blockIdx.x];
+  const WUnit U = units[it.x];
+  const int ii = it.y + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (ii >= U.ra + U.rb) return;
   const C *zin = z + U.zin;
   const bool b = ii >= U.ra;
@@ -106,18 +109,39 @@ __global__ __launch_bounds__(256) void k_s2v_k(const S2VNode *nodes, const cplx_
 }
 
 // K^L, transposed: z[zoff + k] = scale sum_p K[p, k] x[perm[start + p]], one
-// wave per skeleton column k (lane-strided partial sums, then a fixed tree).
+// wave per skeleton column k (lane-strided partial sums, then a fixed tree);
+// a workgroup's four columns share the node's inputs, gathered once into
+// LDS when they fit (kKtLds entries).
+constexpr int kKtLds = 2048;
 template <typename R, bool CONJ>
-__global__ __launch_bounds__(256) void k_s2v_kt(const S2VNode *nodes, const cplx_t<R> *F,
-                                                const int32_t *perm, const cplx_t<R> *x, R scale,
-                                                cplx_t<R> *z) {
+__global__ __launch_bounds__(256) void k_s2v_kt(const S2VNode *nodes, const int2 *items,
+                                                const cplx_t<R> *F, const int32_t *perm,
+                                                const cplx_t<R> *x, R scale, cplx_t<R> *z) {
   using C = cplx_t<R>;
-  const S2VNode d = nodes[blockIdx.x];
-  const int k = blockIdx.y * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  __shared__ C xs[kKtLds];
+  const int2 it = items[blockIdx.x];
+  const S2VNode d = nodes[it.x];
+  const bool lds = d.size <= kKtLds;
+  if (lds)
+    for (int p = threadIdx.x; p < d.size; p += 256) xs[p] = x[perm[d.start + p]];
+  __syncthreads();
+  const int k = it.y + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (k >= d.r) return;
   const C *K = F + d.foff + (int64_t)k * d.size;
   C acc{0, 0};
-  for (int p = lane; p < d.size; p += 64) fma_op<CONJ>(acc, K[p], x[perm[d.start + p]]);
+  if (lds) {
+    int p = lane;
+    for (; p + 192 < d.size; p += 256) {
+      C kv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) kv[u] = K[p + 64 * u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) fma_op<CONJ>(acc, kv[u], xs[p + 64 * u]);
+    }
+    for (; p < d.size; p += 64) fma_op<CONJ>(acc, K[p], xs[p]);
+  } else {
+    for (int p = lane; p < d.size; p += 64) fma_op<CONJ>(acc, K[p], x[perm[d.start + p]]);
+  }
   acc.x = wave_sum(acc.x);
   acc.y = wave_sum(acc.y);
   if (lane == 0) z[d.zoff + k] = C{scale * acc.x, scale * acc.y};
@@ -128,11 +152,13 @@ __global__ __launch_bounds__(256) void k_s2v_kt(const S2VNode *nodes, const cplx
 // unit vector e_p when p < ra, else column p - ra of T_a (likewise for b).
 // The lanes take the rows i = lane, lane + 64, ...
 template <typename R, bool CONJ>
-__global__ __launch_bounds__(256) void k_s2v_wt(const WUnit *units, const cplx_t<R> *F,
-                                                const uint16_t *idx, cplx_t<R> *z) {
+__global__ __launch_bounds__(256) void k_s2v_wt(const WUnit *units, const int2 *items,
+                                                const cplx_t<R> *F, const uint16_t *idx,
+                                                cplx_t<R> *z) {
   using C = cplx_t<R>;
-  const WUnit U = units[blockIdx.x];
-  const int q = blockIdx.y * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int2 it = items[blockIdx.x];
+  const WUnit U = units[it.x];
+  const int q = it.y + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (q >= U.c) return;
   const uint16_t *pa = idx + U.ioff + 2 * (int64_t)U.c, *pb = pa + U.c;
   const C *Ta = F + U.foff, *Tb = Ta + (int64_t)U.ra * (U.c - U.ra);
@@ -187,9 +213,9 @@ static void s2v_forward(const S2VPlan &p, const cplx_t<R> *x, cplx_t<R> *y, R sc
   hipLaunchKernelGGL((k_s2v_v<R, CONJ>), dim3((unsigned)p.nleaf), dim3(64), 0, st, p.leaves, F,
                      p.idx, x, z);
   for (int k = 1; k <= p.L; ++k)
-    if (p.nunits[k])
-      hipLaunchKernelGGL((k_s2v_w<R, CONJ>), dim3((unsigned)p.nunits[k], (p.rows_max[k] + 3) / 4),
-                         dim3(256), 0, st, p.units[k], F, p.idx, z);
+    if (p.nwitems[k])
+      hipLaunchKernelGGL((k_s2v_w<R, CONJ>), dim3((unsigned)p.nwitems[k]), dim3(256), 0, st,
+                         p.units[k], p.witems[k], F, p.idx, z);
   hipLaunchKernelGGL((k_s2v_k<R, CONJ>), dim3((unsigned)p.nnode, (p.size_max + 255) / 256),
                      dim3(256), 0, st, p.nodes, F, p.perm, (const C *)z, scale, y);
 }
@@ -200,12 +226,12 @@ static void s2v_transpose(const S2VPlan &p, const cplx_t<R> *x, cplx_t<R> *y, R 
   using C = cplx_t<R>;
   const C *F = (const C *)p.F;
   C *z = (C *)p.z;
-  hipLaunchKernelGGL((k_s2v_kt<R, CONJ>), dim3((unsigned)p.nnode, (p.rmax_node + 3) / 4),
-                     dim3(256), 0, st, p.nodes, F, p.perm, x, scale, z);
+  hipLaunchKernelGGL((k_s2v_kt<R, CONJ>), dim3((unsigned)p.nktitems), dim3(256), 0, st, p.nodes,
+                     p.ktitems, F, p.perm, x, scale, z);
   for (int k = p.L; k >= 1; --k)
-    if (p.nunits[k])
-      hipLaunchKernelGGL((k_s2v_wt<R, CONJ>), dim3((unsigned)p.nunits[k], (p.cols_max[k] + 3) / 4),
-                         dim3(256), 0, st, p.units[k], F, p.idx, z);
+    if (p.nwtitems[k])
+      hipLaunchKernelGGL((k_s2v_wt<R, CONJ>), dim3((unsigned)p.nwtitems[k]), dim3(256), 0, st,
+                         p.units[k], p.wtitems[k], F, p.idx, z);
   hipLaunchKernelGGL((k_s2v_vt<R, CONJ>), dim3((unsigned)p.nleaf), dim3(64), 0, st, p.leaves, F,
                      p.idx, (const C *)z, y);
 }
@@ -215,8 +241,9 @@ hipError_t launch_s2v(const S2VPlan &p, const void *x, void *y, R scale, bool tr
                       bool conj, hipStream_t st) {
   using C = cplx_t<R>;
   if (p.nleaf <= 0 || p.nnode <= 0 || (int)p.units.size() != p.L + 1 ||
-      (int)p.nunits.size() != p.L + 1 || (int)p.rows_max.size() != p.L + 1 ||
-      (int)p.cols_max.size() != p.L + 1 || p.size_max <= 0 || p.rmax_node <= 0)
+      (int)p.nunits.size() != p.L + 1 || (int)p.witems.size() != p.L + 1 ||
+      (int)p.wtitems.size() != p.L + 1 || (int)p.nwitems.size() != p.L + 1 ||
+      (int)p.nwtitems.size() != p.L + 1 || p.size_max <= 0 || p.nktitems <= 0)
     return hipErrorInvalidValue;
   if (!transpose) {
     if (conj) s2v_forward<R, true>(p, (const C *)x, (C *)y, scale, st);

@@ -218,3 +218,28 @@ def test_inclusion_butterfly_storage_and_accuracy(torch_mod):
             assert e < 1e-4
         op.close()
     assert ent[256] < 5 * ent[128], ent
+
+
+@pytest.mark.parametrize("ns,levels", [(5, 0), (16, 1), (40, 3)])
+def test_inclusion_butterfly_few_segments(torch_mod, ns, levels):
+    """Degenerate butterflies of G: 5 segments give L = 0 (one
+    interpolative decomposition of all cells against the leaf, then K^L over
+    every cell), 16 segments L = 1 (one transfer level), 40 segments L = 3;
+    the inclusion term and its adjoint match the oracle in FP64."""
+    torch = torch_mod
+    import paper_2210_02698_amd as hbi
+    prob = hb_inputs.configs.c1()
+    curve = hb_inputs.circle(prob, (0.45, 0.55), 0.1, ns)
+    say(f"inclusion butterfly ns={ns}")
+    plain = hbi.Operator(prob, device=0).build(tol=1e-7)
+    op = hbi.Operator(prob, device=0).set_inclusion(curve).build(tol=1e-7)
+    assert op.info()["inclusion_bf_levels"] == levels
+    s_h = hb_inputs.complex_normal(prob.Nv, [35, ns])
+    s = torch.from_numpy(s_h).to("cuda:0")
+    u = op.apply(s).cpu().numpy() - plain.apply(s).cpu().numpy()
+    assert rel(u, _inclusion_term(prob, curve, s_h)) < 1e-8
+    g = op.apply_adjoint(s).cpu().numpy() - plain.apply_adjoint(s).cpu().numpy()
+    Q = np.linalg.solve(inc.s2s(prob, curve).conj().T, inc.s2v(prob, curve).conj().T @ s_h)
+    assert rel(g, prob.h ** 2 * (inc.v2s(prob, curve).conj().T @ Q)) < 1e-8
+    plain.close()
+    op.close()
