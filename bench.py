@@ -932,8 +932,9 @@ def main():
                          "each; inclusion: 1024^2 bump with an open-square curve inclusion; "
                          "complexity: storage and build time over sizes")
     ap.add_argument("--nprob", type=int, default=64)
-    ap.add_argument("--calib-copy-mb", type=int, default=0,
-                    help="run one device copy of this many MiB first (HBM counter calibration)")
+    ap.add_argument("--calib-copy-mb", type=str, default="",
+                    help="run device copies of these many MiB first, comma-separated (HBM "
+                         "counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -969,8 +970,8 @@ def main():
     # GPU phase
     import torch
     ensure_lib()
-    if args.calib_copy_mb:
-        n = args.calib_copy_mb << 20
+    for mb in [int(x) for x in args.calib_copy_mb.split(",") if x.strip()]:
+        n = mb << 20
         a = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
