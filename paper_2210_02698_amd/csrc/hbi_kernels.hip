@@ -1488,11 +1488,11 @@ hipError_t launch_entries(const DevProblem &P, const DevCells &C, const EntryBlo
 //            (A is not needed any more), then X = R11^-1 [R11 R12] written
 //            as k_cpqr writes it.
 // Rounding: the Gram matrix squares the condition number.  A remaining
-// diagonal entry carries an absolute error of about eps |a_j|^2, which can
-// swap pivots that are within rounding of each other and keep columns of
-// norm up to about sqrt(n eps) |A| (a rank that much larger at most); the
-// interpolation residual stays at about eps times the skeleton's condition
-// number.
+// diagonal entry carries an absolute error of about eps |a_j|^2 per step,
+// which can swap pivots that are within rounding of each other and keep
+// columns of norm up to about sqrt(k eps) |A|; the interpolation residual
+// stays at about eps times the skeleton's condition number.  The caller
+// takes this path only for tolerances where that was measured harmless.
 // ---------------------------------------------------------------------------
 constexpr int kGramWG = 8;   // workgroups per block in k_gram
 
