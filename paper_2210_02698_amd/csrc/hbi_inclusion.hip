@@ -13,9 +13,11 @@
 //
 //   k_point_setup           table box and Lagrange weights of every segment
 //                           centre, and the K^{s2s} self factor
-//   k_gj_pivot, k_gj_update, k_gj_unpermute
+//   k_gj_pivot(_panel), k_gj_update(_panel), k_gj_copy_rows,
+//   k_gj_block_update, k_gj_unpermute
 //                           Gauss-Jordan inverse of K^{s2s} in FP64 with row
-//                           pivoting, in place
+//                           pivoting, in place, by panels of 32 columns whose
+//                           update of the rest is an MFMA GEMM
 //   k_inc_gather, k_inc_reduce, k_inc_small(_sum), k_inc_scatter, k_inc_add
 //                           the inclusion term of one product (or of its
 //                           conjugate transpose), gathers only, fixed
@@ -132,6 +134,139 @@ __global__ void k_gj_update(double2 *A, int n, int k, const double2 *colk,
   } else {
     const double2 v = cmul(f, rk);
     A[e] = double2{A[e].x - v.x, A[e].y - v.y};
+  }
+}
+
+// Blocked form: the pivot steps of a panel of up to kGjPanel columns
+// [j0, j0 + jb) swap whole rows but scale and eliminate only inside the
+// panel (k_gj_pivot_panel, k_gj_update_panel), which leaves in the panel
+// columns the panel's own Gauss-Jordan result Pn: A11^-1 on the pivot rows
+// j0.., -A21 A11^-1 on the others.  The rest of the matrix then takes the
+// whole panel at once: with S its pivot rows (copied to Sb first),
+// A[:, rest] = (A[:, rest], pivot rows zeroed) + Pn S, a complex GEMM of
+// rank jb on FP64 MFMA tiles (k_gj_block_update).  This is the same
+// elimination as the column-by-column form, its row updates regrouped.
+constexpr int kGjPanel = 32;
+
+__global__ __launch_bounds__(1024) void k_gj_pivot_panel(double2 *A, int n, int k, int j0, int jb,
+                                                         int32_t *perm, double2 *colk,
+                                                         int32_t *status) {
+  __shared__ double sv[1024];
+  __shared__ int si[1024];
+  __shared__ double2 sinv;
+  __shared__ int sp;
+  if (*status) return;
+  const int t = threadIdx.x;
+  double best = -1.0;
+  int bi = n;
+  for (int i = k + t; i < n; i += blockDim.x) {
+    const double2 a = A[i + (int64_t)k * n];
+    const double m = a.x * a.x + a.y * a.y;
+    if (m > best) { best = m; bi = i; }
+  }
+  sv[t] = best;
+  si[t] = bi;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (t < o) {
+      const double b2 = sv[t + o];
+      const int i2 = si[t + o];
+      if (b2 > sv[t] || (b2 == sv[t] && i2 < si[t])) { sv[t] = b2; si[t] = i2; }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    sp = si[0];
+    perm[k] = sp;
+    if (!(sv[0] > 0.0)) *status = 1;
+  }
+  __syncthreads();
+  if (!(sv[0] > 0.0)) return;
+  const int p = sp;
+  if (p != k)
+    for (int j = t; j < n; j += blockDim.x) {
+      const double2 a = A[k + (int64_t)j * n], b = A[p + (int64_t)j * n];
+      A[k + (int64_t)j * n] = b;
+      A[p + (int64_t)j * n] = a;
+    }
+  __syncthreads();
+  for (int i = t; i < n; i += blockDim.x) colk[i] = A[i + (int64_t)k * n];
+  if (t == 0) {
+    const double2 a = A[k + (int64_t)k * n];
+    const double d = a.x * a.x + a.y * a.y;
+    sinv = double2{a.x / d, -a.y / d};
+  }
+  __syncthreads();
+  const double2 inv = sinv;
+  for (int j = j0 + t; j < j0 + jb; j += blockDim.x) {
+    double2 &a = A[k + (int64_t)j * n];
+    a = j == k ? inv : cmul(a, inv);
+  }
+}
+
+__global__ void k_gj_update_panel(double2 *A, int n, int k, int j0, int jb, const double2 *colk,
+                                  const int32_t *status) {
+  if (*status) return;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * jb) return;
+  const int i = (int)(e % n), j = j0 + (int)(e / n);
+  if (i == k) return;
+  const double2 f = colk[i];
+  const double2 rk = A[k + (int64_t)j * n];
+  double2 &a = A[i + (int64_t)j * n];
+  const double2 v = cmul(f, rk);
+  a = j == k ? double2{-v.x, -v.y} : double2{a.x - v.x, a.y - v.y};
+}
+
+// Sb[q][j] = A[j0 + q][j] for the columns outside the panel (0 inside it),
+// q < jb, row-major jb x n.
+__global__ void k_gj_copy_rows(const double2 *A, int n, int j0, int jb, double2 *Sb,
+                               const int32_t *status) {
+  if (*status) return;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * jb) return;
+  const int q = (int)(e / n), j = (int)(e % n);
+  Sb[e] = (j >= j0 && j < j0 + jb) ? double2{0.0, 0.0} : A[(j0 + q) + (int64_t)j * n];
+}
+
+// One wave per 16 x 16 tile of A outside the panel, computed transposed so
+// that a lane's four results are 16 consecutive rows of a column: tile
+// (rows i0.., columns c0..) = (pivot rows zeroed) + (Sb^T Pn^T)^T.
+__global__ __launch_bounds__(256) void k_gj_block_update(double2 *A, int n, int j0, int jb,
+                                                         const double2 *Sb,
+                                                         const int32_t *status) {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  if (*status) return;
+  const int nt = (n + 15) / 16;
+  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= (int64_t)nt * nt) return;
+  const int it = (int)(t % nt), ct = (int)(t / nt);
+  const int c0 = ct * 16, i0 = it * 16;
+  if (c0 >= j0 && c0 < j0 + jb) return;   // panel columns: tiles never straddle (j0 % 16 == 0)
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int col = c0 + li, row = i0 + li;
+  const bool cok = col < n, rok = row < n;
+  v4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < jb; k0 += 4) {
+    const int q = k0 + lk;
+    const bool qok = q < jb;
+    double2 s = Sb[(int64_t)(qok ? q : 0) * n + (cok ? col : 0)];
+    double2 pn = A[(rok ? row : 0) + (int64_t)(j0 + (qok ? q : 0)) * n];
+    if (!(qok && cok)) s = double2{0.0, 0.0};
+    if (!(qok && rok)) pn = double2{0.0, 0.0};
+    // (S^T)[col][q] * (Pn^T)[q][row]
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(s.x, pn.x, re, 0, 0, 0);
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(-s.y, pn.y, re, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(s.x, pn.y, im, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(s.y, pn.x, im, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int j = c0 + lk + 4 * v, i = i0 + li;
+    if (j >= n || i >= n) continue;
+    double2 &a = A[i + (int64_t)j * n];
+    const double2 o = (i >= j0 && i < j0 + jb) ? double2{0.0, 0.0} : a;
+    a = double2{o.x + re[v], o.y + im[v]};
   }
 }
 
@@ -320,17 +455,39 @@ hipError_t launch_point_setup(const DevProblem &P, const double *xy, const doubl
   return hipGetLastError();
 }
 
-// -diag(w)-scaled columns, then the in-place Gauss-Jordan inverse.
+// -diag(w)-scaled columns, then the in-place Gauss-Jordan inverse, by
+// panels of kGjPanel columns (Sb: kGjPanel x n scratch) or, with Sb null,
+// column by column.
 hipError_t launch_s2s_inverse(double2 *A, int32_t n, const double *w, int32_t *perm,
-                              double2 *colk, int32_t *status, hipStream_t st) {
+                              double2 *colk, double2 *Sb, int32_t *status, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const int64_t nn = (int64_t)n * n;
   const int T = 256;
   hipLaunchKernelGGL(k_scale_cols_neg, dim3((nn + T - 1) / T), dim3(T), 0, st, A, n, w);
-  for (int k = 0; k < n; ++k) {
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, st, A, n, k, perm, colk, status);
-    hipLaunchKernelGGL(k_gj_update, dim3((nn + T - 1) / T), dim3(T), 0, st, A, n, k, colk,
-                       status);
+  if (!Sb) {
+    for (int k = 0; k < n; ++k) {
+      hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, st, A, n, k, perm, colk, status);
+      hipLaunchKernelGGL(k_gj_update, dim3((nn + T - 1) / T), dim3(T), 0, st, A, n, k, colk,
+                         status);
+    }
+  } else {
+    const int nt = (n + 15) / 16;
+    const int64_t ntile = (int64_t)nt * nt;
+    for (int j0 = 0; j0 < n; j0 += kGjPanel) {
+      const int jb = n - j0 < kGjPanel ? n - j0 : kGjPanel;
+      const int64_t np = (int64_t)n * jb;
+      for (int k = j0; k < j0 + jb; ++k) {
+        hipLaunchKernelGGL(k_gj_pivot_panel, dim3(1), dim3(1024), 0, st, A, n, k, j0, jb, perm,
+                           colk, status);
+        hipLaunchKernelGGL(k_gj_update_panel, dim3((np + T - 1) / T), dim3(T), 0, st, A, n, k, j0,
+                           jb, colk, status);
+      }
+      if (jb == n) break;
+      hipLaunchKernelGGL(k_gj_copy_rows, dim3((np + T - 1) / T), dim3(T), 0, st, A, n, j0, jb,
+                         Sb, status);
+      hipLaunchKernelGGL(k_gj_block_update, dim3((unsigned)((ntile + 3) / 4)), dim3(256), 0, st,
+                         A, n, j0, jb, Sb, status);
+    }
   }
   hipLaunchKernelGGL(k_gj_unpermute, dim3(1), dim3(1024), 0, st, A, n, perm, status);
   return hipGetLastError();

@@ -148,7 +148,7 @@ hipError_t launch_point_setup(const DevProblem &P, const double *xy, const doubl
                               const double *slow, int32_t ns, int64_t p0, double *xyz,
                               double *lw, int32_t *box, double2 *self, hipStream_t st);
 hipError_t launch_s2s_inverse(double2 *A, int32_t n, const double *w, int32_t *perm,
-                              double2 *colk, int32_t *status, hipStream_t st);
+                              double2 *colk, double2 *Sb, int32_t *status, hipStream_t st);
 hipError_t launch_conj_transpose(const double2 *src, int32_t n, double2 *dst, hipStream_t st);
 template <typename R>
 hipError_t launch_inclusion_apply(const InclusionPlan &ip, const void *x, void *u, R hd,

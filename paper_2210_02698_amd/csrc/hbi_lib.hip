@@ -1955,8 +1955,13 @@ void build_inclusion(hbi_ctx *c) {
     }
   }
   {
-    DevBuf S, SH, perm, colk, status, pd_d;
+    DevBuf S, SH, perm, colk, status, pd_d, Sb;
     HBI_HIP(S.alloc(sizeof(double2) * (size_t)ns * ns));
+    // panel rows of the blocked inverse (32 x ns); HBI_S2S_INVERSE=columns
+    // keeps the column-by-column form
+    const char *iv = std::getenv("HBI_S2S_INVERSE");
+    const bool blocked = !(iv && std::strcmp(iv, "columns") == 0);
+    if (blocked) HBI_HIP(Sb.alloc(sizeof(double2) * (size_t)32 * ns));
     HBI_HIP(SH.alloc(sizeof(double2) * (size_t)ns * ns));
     HBI_HIP(perm.alloc(sizeof(int32_t) * ns));
     HBI_HIP(colk.alloc(sizeof(double2) * ns));
@@ -1965,7 +1970,8 @@ void build_inclusion(hbi_ctx *c) {
     std::vector<BlockIn> bin{BlockIn{segpos.data(), ns, segpos.data(), ns, S.as<double2>()}};
     B.run(bin, false, 0.0, nullptr, [](int64_t, int64_t) {});
     HBI_HIP(launch_s2s_inverse(S.as<double2>(), ns, c->inc_w_d.as<double>(), perm.as<int32_t>(),
-                               colk.as<double2>(), status.as<int32_t>(), c->stream));
+                               colk.as<double2>(), blocked ? Sb.as<double2>() : nullptr,
+                               status.as<int32_t>(), c->stream));
     int32_t st = 0;
     HBI_HIP(hipMemcpyAsync(&st, status.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     HBI_HIP(hipStreamSynchronize(c->stream));
