@@ -98,9 +98,14 @@ __device__ __forceinline__ void wave_gemv(const C *__restrict__ M, int Rt, int c
 }
 
 // One workgroup (4 waves) per leaf; wave w handles the HODBF levels
-// l = w, w + 4, ... of the leaf.  Each block is V = [I, T] Pi^T: the leaf's
-// inputs are permuted into the block's column order in the wave's LDS slice,
-// then row k is xp[k] + sum_m T[k, m] xp[r + m].
+// l = w, w + 4, ... of the leaf (at most kVq of them).  Each block is
+// V = [I, T] Pi^T: the leaf's inputs are permuted into the block's column
+// order in the wave's LDS slice, then row k is xp[k] + sum_m T[k, m]
+// xp[r + m].  A wave loads the descriptors and column orders of all its
+// blocks at once, while the leaf's inputs are gathered, so that each block
+// then waits only for its own factor stream (one block after another, each
+// waited on three dependent loads).
+constexpr int kVq = 8;   // blocks per wave: L_v <= 4 kVq
 template <typename R>
 __global__ __launch_bounds__(256) void k_vstage(const cplx_t<R> *s,
                                                 const LeafInfo *leaves,
@@ -117,16 +122,26 @@ __global__ __launch_bounds__(256) void k_vstage(const cplx_t<R> *s,
   const int lane = threadIdx.x & 63;
   const LeafInfo lf = leaves[g];
   const int sz = lf.size;
+  const int nq = wave < Lv ? (Lv - wave + 3) / 4 : 0;
+  VDesc dq[kVq];
+  int ix[kVq];
+#pragma unroll
+  for (int q = 0; q < kVq; ++q)
+    if (q < nq) dq[q] = vd[(int64_t)g * Lv + wave + 4 * q];
+#pragma unroll
+  for (int q = 0; q < kVq; ++q) ix[q] = (q < nq && lane < sz) ? fidx[dq[q].ioff + lane] : 0;
   if (threadIdx.x < sz) {
     const C v = s[perm[lf.start + threadIdx.x]];
     xs[threadIdx.x] = C{v.x * hd, v.y * hd};
   }
   __syncthreads();
   C *xw = xp[wave];
-  for (int l = wave; l < Lv; l += 4) {
-    const VDesc d = vd[(int64_t)g * Lv + l];
+#pragma unroll
+  for (int q = 0; q < kVq; ++q) {
+    if (q >= nq) break;
+    const VDesc d = dq[q];
     wave_lds_sync();   // the previous block's reads of xw are done
-    if (lane < sz) xw[lane] = xs[fidx[d.ioff + lane]];
+    if (lane < sz) xw[lane] = xs[ix[q]];
     wave_lds_sync();
     C *zo = z + d.zout;
     const int r = d.r;
@@ -624,6 +639,7 @@ hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
   auto post = [&]() { if (hook) hook->after(); };
   // factor loads per batch of the transfer stages (64 VGPRs: 8 waves/SIMD)
   constexpr int WB = sizeof(R) == 4 ? 8 : 4;
+  if (ap.Lv > 4 * kVq) return hipErrorInvalidValue;   // N_v < 2^31 keeps L_v <= 25
   if (!adjoint) {
     if (ap.Lv > 0) {
       pre("k_vstage", ap.v_elems, ap.v_idx);

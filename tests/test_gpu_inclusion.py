@@ -243,3 +243,25 @@ def test_inclusion_butterfly_few_segments(torch_mod, ns, levels):
     assert rel(g, prob.h ** 2 * (inc.v2s(prob, curve).conj().T @ Q)) < 1e-8
     plain.close()
     op.close()
+
+
+def test_blocked_and_column_inverse_agree(torch_mod, monkeypatch):
+    """The inverse of K^{s2s} by 32-column panels (an MFMA update of the rest
+    per panel, the default) and column by column give the same operator to
+    rounding: 200 segments, 7 panels, the last one partial; FP64."""
+    torch = torch_mod
+    import paper_2210_02698_amd as hbi
+    prob, centre, R, ns = CASES["bump-64"]()
+    curve = hb_inputs.circle(prob, centre, R, ns)
+    s = torch.from_numpy(hb_inputs.complex_normal(prob.Nv, [36, 0])).to("cuda:0")
+    u = {}
+    for mode in ("panels", "columns"):
+        if mode == "columns":
+            monkeypatch.setenv("HBI_S2S_INVERSE", "columns")
+        say(f"K^s2s inverse by {mode}")
+        op = hbi.Operator(prob, device=0).set_inclusion(curve).build(tol=1e-7)
+        u[mode] = op.apply(s).cpu().numpy()
+        op.close()
+    d = rel(u["panels"], u["columns"])
+    say(f"panels vs columns {d:.2e}")
+    assert d < 1e-12, d
