@@ -2442,9 +2442,9 @@ void launch_passes(BatchCache &B, hipStream_t st) {
   }
 }
 
-// Tuned column-tile width per (precision, widest column-tile count),
-// shared by every batch of the process and optionally kept in the JSON
-// file named by HBI_TUNE_CACHE.
+// Tuned column-tile width per (architecture, precision, direction, widest
+// column-tile count, rank bucket), shared by every batch of the process and
+// optionally kept in the JSON file named by HBI_TUNE_CACHE.
 std::map<std::string, int> &tune_table() {
   static std::map<std::string, int> t;
   static bool loaded = false;
@@ -2527,10 +2527,23 @@ void multi_apply(hbi_ctx *c0, const std::vector<hbi_ctx *> &ctxs, const std::vec
     HBI_HIP(hipStreamWaitEvent(B->gst, B->e_in, 0));
     plan_passes(*B, nrhs);
     // autotune the column-tile width on this batch (cached per process)
+    // key: architecture, precision, direction, widest column-tile count and
+    // the rank bucket (power of two >= the largest transfer unit's rows)
     int maxjt = 1;
     for (auto &J : B->jobs) maxjt = std::max(maxjt, J.Np / 16);
-    const std::string key = std::string(prec == HBI_F64 ? "f64" : "f32") + (adj ? ":adj" : "") +
-                            ":jt" + std::to_string(maxjt);
+    int rmax = 1;
+    for (hbi_ctx *cc : ctxs)
+      if (cc)
+        for (const auto &lev : cc->units_h)
+          for (const WUnit &U : lev) rmax = std::max(rmax, U.ra + U.rb);
+    int rbucket = 16;
+    while (rbucket < rmax) rbucket *= 2;
+    hipDeviceProp_t prop;
+    HBI_HIP(hipGetDeviceProperties(&prop, c0->device));
+    std::string arch(prop.gcnArchName);
+    arch = arch.substr(0, arch.find(':'));
+    const std::string key = arch + ":" + (prec == HBI_F64 ? "f64" : "f32") + (adj ? ":adj" : "") +
+                            ":jt" + std::to_string(maxjt) + ":r" + std::to_string(rbucket);
     auto items = [&](int nb) { if (adj) build_items_adj(*B, nb); else build_items(*B, nb); };
     auto &tt = tune_table();
     int best = -1;
