@@ -857,17 +857,26 @@ def run_complexity(args):
     """Storage and build time across sizes at 8 cells per wavelength: the 2D
     Gaussian bump on 128^2 .. 1024^2 cells (FP64, tol 1e-7) and the 3D
     sinusoid on 16^3 .. 64^3 cells (FP32, tol 1e-6), against the
-    O(N_v log^2 N_v) storage of the paper's complexity statement."""
+    O(N_v log^2 N_v) storage of the paper's complexity statement; and the
+    single butterfly of the open-square inclusion (20 segments per
+    wavelength, FP32 at tol 1e-5) on the same 2D sizes, against the O(N_v)
+    storage stated for K^{s2v} (Sec. 4.2)."""
     import torch
     import hb_inputs
     import paper_2210_02698_amd as hbi
     ensure_lib()
-    out = {"workload": "complexity sweep: storage and build time against N_v log2^2 N_v",
-           "2d": [], "3d": []}
+    out = {"workload": "complexity sweep: storage and build time against N_v log2^2 N_v; "
+                       "the inclusion butterfly's storage against N_v",
+           "2d": [], "3d": [], "inclusion": []}
     cases = [("2d", s, hb_inputs.configs.c2(s), "f64", 1e-7) for s in (128, 256, 512, 1024)]
     cases += [("3d", s, hb_inputs.configs.c5(s), "f32", 1e-6) for s in (16, 32, 48, 64)]
+    cases += [("inclusion", s, hb_inputs.configs.c2(s), "f32", 1e-5) for s in (128, 256, 512, 1024)]
     for kind, side, prob, prec, tol in cases:
         op = hbi.Operator(prob, device=0)
+        curve = None
+        if kind == "inclusion":
+            curve = hb_inputs.open_square(prob, (0.5, 0.5), 0.8, 20)
+            op.set_inclusion(curve)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         op.build(tol=tol, prec=prec)
@@ -877,14 +886,31 @@ def run_complexity(args):
         op.close()
         n = prob.Nv
         l2 = math.log2(n) ** 2
-        rec = {"side": side, "N_v": n, "prec": prec, "tol": tol, "nnz_total": info["nnz_total"],
-               "nnz_per_cell": round(info["nnz_total"] / n, 2),
-               "nnz_per_cell_over_log2sq": round(info["nnz_total"] / n / l2, 4),
-               "build_s": round(bs, 3), "build_us_per_cell_over_log2sq": round(bs / n / l2 * 1e6, 5),
-               "rank_max": info["rank_max"], "rank_mean": info["rank_mean"]}
+        if kind == "inclusion":
+            ent = info["inclusion_bf_entries"]
+            rec = {"side": side, "N_v": n, "N_s": curve.Ns, "prec": prec, "tol": tol,
+                   "levels": info["inclusion_bf_levels"], "bf_entries": ent,
+                   "bf_entries_per_cell": round(ent / n, 2),
+                   "dense_G_entries": n * curve.Ns, "rank_max": info["inclusion_bf_rank_max"],
+                   "build_inclusion_s": round(info["build_inclusion_s"], 3)}
+        else:
+            rec = {"side": side, "N_v": n, "prec": prec, "tol": tol,
+                   "nnz_total": info["nnz_total"],
+                   "nnz_per_cell": round(info["nnz_total"] / n, 2),
+                   "nnz_per_cell_over_log2sq": round(info["nnz_total"] / n / l2, 4),
+                   "build_s": round(bs, 3),
+                   "build_us_per_cell_over_log2sq": round(bs / n / l2 * 1e6, 5),
+                   "rank_max": info["rank_max"], "rank_mean": info["rank_mean"]}
         out[kind].append(rec)
         log(f"complexity {kind} {side}: {rec}")
         torch.cuda.empty_cache()
+    r = out["inclusion"]
+    a, b = r[0], r[-1]
+    out["inclusion_fit"] = {
+        "bf_entries_exponent": round(math.log(b["bf_entries"] / a["bf_entries"]) /
+                                     math.log(b["N_v"] / a["N_v"]), 4),
+        "dense_G_exponent": round(math.log(b["dense_G_entries"] / a["dense_G_entries"]) /
+                                  math.log(b["N_v"] / a["N_v"]), 4)}
     for kind in ("2d", "3d"):
         r = out[kind]
         # growth exponents between the smallest and largest size
