@@ -125,7 +125,7 @@ hbi_status hbi_load_tables_from(hbi_ctx *ctx, const hbi_ctx *src, double omega);
 /* A curve inclusion (Sec. 3.2, domain with a sound-hard inclusion; 2D): ns straight
  * segments with centres (xy[2i], xy[2i+1]), lengths w[i] > 0 and slowness
  * slowness[i] > 0 of the medium at the centres (host arrays, copied; the
- * centres must lie in the table region; 0 <= ns <= 8192, ns = 0 removes the
+ * centres must lie in the table region; 0 <= ns <= 32768, ns = 0 removes the
  * inclusion; the segments are taken in the given order, which should follow
  * the curve).  Later builds assemble, besides the volume factors, the
  * operator G[j, i] = g(r_j, r^s_i) over cells and segments (read as

@@ -8,7 +8,7 @@
 #define HBI_ID_THREADS 1024
 #define HBI_ID_NMAX 4096   // largest candidate-column count an ID accepts
 #define HBI_ID_ONCHIP_NMAX 64   // largest column count of the on-chip ID kernel
-#define HBI_MAX_INCLUSION 8192  // segments of a curve inclusion
+#define HBI_MAX_INCLUSION 32768  // segments of a curve inclusion
 #define HBI_WSTAGE_LDS_BYTES 4096   // LDS of one forward transfer-stage wave
 
 // Problem constants visible to the kernels.

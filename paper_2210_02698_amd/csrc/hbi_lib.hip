@@ -1912,6 +1912,7 @@ void build_s2v(hbi_ctx *c, double tol) {
 // scaled by -w_j (self factors on the diagonal), inverted by Gauss-Jordan in
 // FP64.  Stored in the factors' precision.
 constexpr int32_t kIncChunk = 4096;   // cells per chunk of G (a multiple of 256)
+constexpr int32_t kS2sChunk = 512;    // columns per block of the K^{s2s} entries
 
 void build_inclusion(hbi_ctx *c) {
   const double t0 = now_s();
@@ -1967,7 +1968,12 @@ void build_inclusion(hbi_ctx *c) {
     HBI_HIP(colk.alloc(sizeof(double2) * ns));
     HBI_HIP(status.alloc(sizeof(int32_t)));
     HBI_HIP(hipMemsetAsync(status.p, 0, sizeof(int32_t), c->stream));
-    std::vector<BlockIn> bin{BlockIn{segpos.data(), ns, segpos.data(), ns, S.as<double2>()}};
+    // K^{s2s} entries in column chunks (each chunk's column side then needs
+    // a bounded workspace whatever N_s is)
+    std::vector<BlockIn> bin;
+    for (int32_t j0 = 0; j0 < ns; j0 += kS2sChunk)
+      bin.push_back(BlockIn{segpos.data(), ns, segpos.data() + j0, std::min(kS2sChunk, ns - j0),
+                            S.as<double2>() + (int64_t)j0 * ns});
     B.run(bin, false, 0.0, nullptr, [](int64_t, int64_t) {});
     HBI_HIP(launch_s2s_inverse(S.as<double2>(), ns, c->inc_w_d.as<double>(), perm.as<int32_t>(),
                                colk.as<double2>(), blocked ? Sb.as<double2>() : nullptr,
@@ -3030,7 +3036,8 @@ hbi_status hbi_set_inclusion(hbi_ctx *ctx, int32_t ns, const double *xy, const d
     hbi_ctx *c = ctx;
     HBI_REQUIRE(c->state >= 1, HBI_ERR_STATE, "inclusion before tables");
     HBI_REQUIRE(c->dim == 2, HBI_ERR_ARG, "curve inclusions are 2D");
-    HBI_REQUIRE(ns >= 0 && ns <= HBI_MAX_INCLUSION, HBI_ERR_ARG, "ns must be in [0, 8192]");
+    HBI_REQUIRE(ns >= 0 && ns <= HBI_MAX_INCLUSION, HBI_ERR_ARG,
+                "ns must be in [0, " + std::to_string(HBI_MAX_INCLUSION) + "]");
     if (ns > 0) {
       HBI_REQUIRE(xy && w && slowness, HBI_ERR_ARG, "null segment array");
       for (int32_t i = 0; i < ns; ++i) {

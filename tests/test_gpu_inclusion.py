@@ -168,7 +168,7 @@ def test_inclusion_rejected_calls(torch_mod):
     assert lib.hbi_set_inclusion(op._ctx, 16, P(xy), P(bad), P(n)) == _lib.HBI_ERR_ARG
     far = xy.copy(); far[5, 0] = 7.0
     assert lib.hbi_set_inclusion(op._ctx, 16, P(far), P(w), P(n)) == _lib.HBI_ERR_ARG
-    assert lib.hbi_set_inclusion(op._ctx, 9000, P(xy), P(w), P(n)) == _lib.HBI_ERR_ARG
+    assert lib.hbi_set_inclusion(op._ctx, 40000, P(xy), P(w), P(n)) == _lib.HBI_ERR_ARG
     ctx2 = ctypes.c_void_p()
     assert lib.hbi_create(0, None, ctypes.byref(ctx2)) == _lib.HBI_OK
     assert lib.hbi_set_inclusion(ctx2, 16, P(xy), P(w), P(n)) == _lib.HBI_ERR_STATE
