@@ -49,6 +49,16 @@ template <typename C> __device__ __forceinline__ C ldf(const C *p) {
   const V v = __builtin_nontemporal_load((const V *)p);
   return C{v[0], v[1]};
 }
+// Factor load with the non-temporal hint or without it.  Measured on the
+// 1024^2 FP32 apply: the short per-wave streams of the FP32 transfer stages
+// and of the adjoint's K^L stage run 3 % and 12 % faster with plain loads,
+// while the leaf stages and every FP64 stage are faster with the hint.
+template <bool NTL, typename C> __device__ __forceinline__ C ldx(const C *p) {
+  if constexpr (NTL) return ldf(p);
+  else return *p;
+}
+// FP32 transfer stages and adjoint K^L stage: plain loads
+template <typename R> struct PlainF32 { static constexpr bool nt = sizeof(R) != 4; };
 
 // y[0..R) = M x for a column-major R x c matrix M streamed by one wave.
 // Lane l works on row l % R of column group l / R (G = 64 / R groups when
@@ -104,7 +114,10 @@ __device__ __forceinline__ void wave_gemv(const C *__restrict__ M, int Rt, int c
 // xp[r + m].  A wave loads the descriptors and column orders of all its
 // blocks at once, while the leaf's inputs are gathered, so that each block
 // then waits only for its own factor stream (one block after another, each
-// waited on three dependent loads).
+// waited on three dependent loads).  Batches of 8 instead of 16 entries per
+// lane (7 or 8 waves per SIMD instead of 5) measured the same; issuing the
+// next block's first batch before the current block is consumed took 124
+// registers (4 waves per SIMD) and was 7 % slower.
 constexpr int kVq = 8;   // blocks per wave: L_v <= 4 kVq
 template <typename R>
 __global__ __launch_bounds__(256) void k_vstage(const cplx_t<R> *s,
@@ -154,14 +167,15 @@ __global__ __launch_bounds__(256) void k_vstage(const cplx_t<R> *s,
 // T[0], T[step], ... (nt of them), streamed B at a time.  issue(q0) loads
 // entries q0 .. q0 + B - 1 (zero past nt), so the first batch can be issued
 // before the lane's inputs are ready.
-template <typename C, int B> struct RowStream {
+template <typename C, int B, bool NTL> struct RowStream {
   const C *T;
   int64_t step;
   int nt;
   C mv[B];
   __device__ __forceinline__ void issue(int q0) {
 #pragma unroll
-    for (int u = 0; u < B; ++u) mv[u] = q0 + u < nt ? ldf(T + (int64_t)(q0 + u) * step) : C{0, 0};
+    for (int u = 0; u < B; ++u)
+      mv[u] = q0 + u < nt ? ldx<NTL>(T + (int64_t)(q0 + u) * step) : C{0, 0};
   }
   // sum_q T[q step] x(q) in order of q; the first batch must have been issued
   template <typename XF> __device__ __forceinline__ C dot(XF x) {
@@ -209,7 +223,10 @@ __device__ __forceinline__ C group_sum(C acc, int lane, int wr, int G) {
 // dropped: the two permuted lists formed in LDS first (slower), persistent
 // waves looping over items with the next descriptor prefetched (slower),
 // the producers scattering their outputs straight into both consumer orders
-// (twice the output writes, scattered: slower).
+// (twice the output writes, scattered: slower).  Factor batches of 4 to 16
+// entries per lane, 2 to 6 staging loads per lane issued ahead and 5 to 8
+// waves per SIMD all ran within 5 % of each other (this configuration the
+// fastest), so the stage is not bound by the loads one wave keeps in flight.
 template <typename R, int B>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_wstage(
     const WItem *items, int64_t nitems, const uint16_t *fidx, const cplx_t<R> *F,
@@ -238,7 +255,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
   const uint16_t *ia = fidx + U.ioff;  // ia, then ib at ia + c (4-byte aligned)
   const uint32_t *ia32 = (const uint32_t *)ia;
   const C *zin = z + U.zin;
-  RowStream<C, B> S;
+  RowStream<C, B, PlainF32<R>::nt> S;
   S.T = F + U.foff + (isb ? (int64_t)ra * (c - ra) : 0) + i + (int64_t)grp * rc;
   S.step = (int64_t)G * rc;
   S.nt = act && t > grp ? (t - grp + G - 1) / G : 0;
@@ -354,14 +371,14 @@ template <typename C> __device__ __forceinline__ C row16_sum(C v) {
 // This lane's share of sum_{i < R} conj(col[i]) w[i]: rows r16, r16 + 16,
 // ...; the first four of them use wr[0..3] (w at those rows, loaded once by
 // the caller), later ones read w.  Loads issued four at a time, predicated.
-template <typename C>
+template <bool NTL = true, typename C>
 __device__ __forceinline__ C col_share(const C *col, int R, int r16, const C (&wr)[4],
                                        const C *w) {
   C acc{0, 0};
   {
     C mv[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) mv[u] = r16 + 16 * u < R ? ldf(col + r16 + 16 * u) : C{0, 0};
+    for (int u = 0; u < 4; ++u) mv[u] = r16 + 16 * u < R ? ldx<NTL>(col + r16 + 16 * u) : C{0, 0};
 #pragma unroll
     for (int u = 0; u < 4; ++u) cfmac(acc, mv[u], wr[u]);
   }
@@ -370,7 +387,7 @@ __device__ __forceinline__ C col_share(const C *col, int R, int r16, const C (&w
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int i = k0 + 16 * u;
-      mv[u] = i < R ? ldf(col + i) : C{0, 0};
+      mv[u] = i < R ? ldx<NTL>(col + i) : C{0, 0};
       wv[u] = i < R ? w[i] : C{0, 0};
     }
 #pragma unroll
@@ -413,8 +430,9 @@ __global__ __launch_bounds__(256) void k_final_adj(const cplx_t<R> *y,
     for (int q0 = 0; q0 < d.r; q0 += 8) {
       const int q1 = q0 + slot, q2 = q0 + 4 + slot;
       const C *K = F + d.foff;
-      C a1 = col_share(K + (int64_t)(q1 < d.r ? q1 : d.r - 1) * sz, sz, r16, yr, ys);
-      C a2 = col_share(K + (int64_t)(q2 < d.r ? q2 : d.r - 1) * sz, sz, r16, yr, ys);
+      constexpr bool nt = PlainF32<R>::nt;
+      C a1 = col_share<nt>(K + (int64_t)(q1 < d.r ? q1 : d.r - 1) * sz, sz, r16, yr, ys);
+      C a2 = col_share<nt>(K + (int64_t)(q2 < d.r ? q2 : d.r - 1) * sz, sz, r16, yr, ys);
       a1 = row16_sum(a1);
       a2 = row16_sum(a2);
       if (r16 == 15 && q1 < d.r) z[d.zin + q1] = a1;
