@@ -227,17 +227,18 @@ __device__ __forceinline__ C group_sum(C acc, int lane, int wr, int G) {
 // entries per lane, 2 to 6 staging loads per lane issued ahead and 5 to 8
 // waves per SIMD all ran within 5 % of each other (this configuration the
 // fastest), so the stage is not bound by the loads one wave keeps in flight.
+// Each wave is a workgroup of its own (1-2 % faster than four per
+// workgroup: a finished wave's slot and LDS are not held by the others).
 template <typename R, int B>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_wstage(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_wstage(
     const WItem *items, int64_t nitems, const uint16_t *fidx, const cplx_t<R> *F,
     cplx_t<R> *z, int cap_lds) {
   using C = cplx_t<R>;
-  constexpr int WX = HBI_WSTAGE_LDS_BYTES / (int)sizeof(C);   // LDS entries per wave
+  constexpr int WX = HBI_WSTAGE_LDS_BYTES / (int)sizeof(C);   // LDS entries of the wave
   constexpr int NS = 2;   // staging loads per lane issued before T
-  __shared__ C xs[4][WX];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+  __shared__ C xs[WX];
+  const int lane = threadIdx.x;
+  const int64_t it = blockIdx.x;
   if (it >= nitems) return;
   const WItem U = items[it];
   const int ra = U.ra, rb = U.rb, c = U.c, Rt = ra + rb;
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
   const int cw = (4 * c + (int)sizeof(C) - 1) / (int)sizeof(C);   // entries the orders take
   C acc, x0;
   if (c + cw <= cap_lds) {
-    C *xw = xs[wave];
+    C *xw = xs;
     uint32_t *iw32 = (uint32_t *)(xw + c);
     const uint16_t *iw = (const uint16_t *)iw32;
     C xr[NS];
@@ -473,17 +474,17 @@ __device__ __forceinline__ void adj_pass(const C *T, int r, int r16, const C (&w
 // otherwise (ra contiguous entries), so (X_a^H w_a)_j is w_a[k] or a
 // conjugate dot product with that column; child b adds the same way.  Four
 // inputs at a time, one per slot; the results gather in the wave's LDS
-// slice and are stored together.
+// slice and are stored together.  One wave per workgroup (3 % faster than
+// four).
 template <typename R>
-__global__ __launch_bounds__(256) void k_wstage_adj(const WItem *items, int64_t nitems,
-                                                    const uint16_t *fidx, const cplx_t<R> *F,
-                                                    cplx_t<R> *z) {
+__global__ __launch_bounds__(64) void k_wstage_adj(const WItem *items, int64_t nitems,
+                                                   const uint16_t *fidx, const cplx_t<R> *F,
+                                                   cplx_t<R> *z) {
   using C = cplx_t<R>;
-  __shared__ C res[4][64];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
+  __shared__ C res[64];
+  const int lane = threadIdx.x;
   const int slot = lane >> 4, r16 = lane & 15;
-  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t it = blockIdx.x;
   if (it >= nitems) return;
   const WItem U = items[it];
   const int ra = U.ra, rb = U.rb, c = U.c;
@@ -519,12 +520,12 @@ __global__ __launch_bounds__(256) void k_wstage_adj(const WItem *items, int64_t 
         if (r16 == 15 && q < nw) {
           const C xa = ka[t] < ra ? wa[ka[t]] : sa[t];
           const C xb = kb[t] < rb ? wb[kb[t]] : sb[t];
-          res[wave][q] = C{xa.x + xb.x, xa.y + xb.y};
+          res[q] = C{xa.x + xb.x, xa.y + xb.y};
         }
       }
     }
     wave_lds_sync();
-    if (lane < nw) z[U.zin + U.off + lane] = res[wave][lane];
+    if (lane < nw) z[U.zin + U.off + lane] = res[lane];
   };
   if (ra <= 32 && rb <= 32) return fast(std::integral_constant<int, 2>());
   for (int q0 = 0; q0 < nw; q0 += 4) {
@@ -540,11 +541,11 @@ __global__ __launch_bounds__(256) void k_wstage_adj(const WItem *items, int64_t 
     if (r16 == 15 && q0 + slot < nw) {
       const C xa = ka < ra ? wa[ka] : acc;
       const C xb = kb < rb ? wb[kb] : accb;
-      res[wave][q0 + slot] = C{xa.x + xb.x, xa.y + xb.y};
+      res[q0 + slot] = C{xa.x + xb.x, xa.y + xb.y};
     }
   }
   wave_lds_sync();
-  if (lane < nw) z[U.zin + U.off + lane] = res[wave][lane];
+  if (lane < nw) z[U.zin + U.off + lane] = res[lane];
 }
 
 // Leaf part of the adjoint: u_leaf = hd (D^H y_leaf + sum_l V_l^H z_l), one
@@ -670,7 +671,7 @@ hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
       if (nu == 0) continue;
       const int64_t ni = ap.nitems[k];
       pre("k_wstage", ap.w_elems[k], ap.w_idx[k]);
-      hipLaunchKernelGGL((k_wstage<R, WB>), dim3((ni + 3) / 4), dim3(256), 0, st, ap.items[k],
+      hipLaunchKernelGGL((k_wstage<R, WB>), dim3(ni), dim3(64), 0, st, ap.items[k],
                          ni, ap.fidx, Fc, zc, ap.cap_lds);
       post();
     }
@@ -692,7 +693,7 @@ hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
       if (nu == 0) continue;
       const int64_t ni = ap.nitems_adj[k];
       pre("k_wstage_adj", ap.w_elems[k], ap.w_idx[k]);
-      hipLaunchKernelGGL((k_wstage_adj<R>), dim3((ni + 3) / 4), dim3(256), 0, st,
+      hipLaunchKernelGGL((k_wstage_adj<R>), dim3(ni), dim3(64), 0, st,
                          ap.items_adj[k], ni, ap.fidx, Fc, zc);
       post();
     }
