@@ -185,7 +185,12 @@ hbi_status hbi_apply_adjoint(hbi_ctx *ctx, const void *s, void *u,
  * kept for the process and in the JSON file named by HBI_TUNE_CACHE when
  * set.  Vector workspace is bounded by HBI_MULTI_BYTES (default 8 GiB);
  * larger batches run as several passes inside the same graph.  hbi_apply
- * with nrhs >= 2 uses the same path for one problem. */
+ * with nrhs >= 2 uses the same path for one problem.  With the environment
+ * variable HBI_BATCHED_PERSISTENT=1 (read when a batch is planned) the call
+ * is instead one persistent cooperative kernel launch per call: its
+ * workgroups walk every pass's gather, stages and scatter in order with a
+ * grid-wide barrier between them, with results identical to the graph's;
+ * hbi_get_info counts these launches in "batched_persistent_launches". */
 hbi_status hbi_apply_batched(hbi_ctx *const *ctx, int32_t nprob,
                              const void *const *s, void *const *u,
                              const int32_t *nrhs, const int64_t *ld);

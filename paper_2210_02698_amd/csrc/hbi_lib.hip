@@ -272,6 +272,8 @@ struct hbi_ctx {
   // x four orderings x updated points, over every equation), solve time
   int32_t tab_sources = 0, tab_rounds_max = 0;
   double tab_point_updates = 0, tab_s = 0;
+  // batched products issued by this context as one persistent launch
+  int64_t n_persistent = 0;
   int32_t wst_cq[5] = {0, 0, 0, 0, 0};   // unit widths c: min, quartiles, max
   // curve inclusion (2D): segments at positions [Nv, Nv + inc_ns) of the
   // per-point arrays; inputs on the host and the device, and the dense
@@ -2110,6 +2112,10 @@ struct BatchCache {
   hipEvent_t e_in = nullptr, e_out = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  // one persistent cooperative launch instead of the graph
+  bool persistent = false;
+  int pgrid = 0, nphase = 0;
+  DevBuf phases_d;
   double tuned_ms = 0;
   ~BatchCache() {
     // the graph may still run: its workspace and job tables go with it
@@ -2511,8 +2517,9 @@ void multi_apply(hbi_ctx *c0, const std::vector<hbi_ctx *> &ctxs, const std::vec
   for (size_t p = 0; p < ctxs.size(); ++p) gens[p] = ctxs[p]->build_gen;
   std::shared_ptr<BatchCache> &slot = adj ? c0->batch_adj : c0->batch;
   std::shared_ptr<BatchCache> B = slot;
-  const bool same =
-      B && B->ctxs == ctxs && B->gens == gens && B->nrhs == nrhs && B->prec == prec;
+  const bool persistent = env_int("HBI_BATCHED_PERSISTENT", 0) != 0;
+  const bool same = B && B->ctxs == ctxs && B->gens == gens && B->nrhs == nrhs &&
+                    B->prec == prec && B->persistent == persistent;
   if (!same) {
     // the previous graph, if any, finishes and frees its workspace first
     B.reset();
@@ -2572,10 +2579,27 @@ void multi_apply(hbi_ctx *c0, const std::vector<hbi_ctx *> &ctxs, const std::vec
       save_tune_table();
     }
     items(best);
-    HBI_HIP(hipStreamBeginCapture(B->gst, hipStreamCaptureModeRelaxed));
-    launch_passes(*B, B->gst);
-    HBI_HIP(hipStreamEndCapture(B->gst, &B->graph));
-    HBI_HIP(hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0));
+    B->persistent = persistent;
+    if (persistent) {
+      // the passes' gathers, stages and scatters as the phases of one launch
+      std::vector<MPhase> ph;
+      for (auto &P : B->passes) {
+        const int nx = (int)((P.maxNv + 63) / 64);
+        ph.push_back(MPhase{6, nx, P.maxjt, P.jin_d.p, (int64_t)P.jin.size()});
+        for (auto &sp : P.stages)
+          if (sp.n) ph.push_back(MPhase{sp.kind, 0, 0, sp.items, sp.n});
+        ph.push_back(MPhase{7, nx, P.maxjt, P.jout_d.p, (int64_t)P.jout.size()});
+      }
+      upload(B->phases_d, ph);
+      B->nphase = (int)ph.size();
+      if (prec == HBI_F64) HBI_HIP(persistent_grid<double>(best, c0->device, &B->pgrid));
+      else HBI_HIP(persistent_grid<float>(best, c0->device, &B->pgrid));
+    } else {
+      HBI_HIP(hipStreamBeginCapture(B->gst, hipStreamCaptureModeRelaxed));
+      launch_passes(*B, B->gst);
+      HBI_HIP(hipStreamEndCapture(B->gst, &B->graph));
+      HBI_HIP(hipGraphInstantiate(&B->gexec, B->graph, nullptr, nullptr, 0));
+    }
     slot = B;
   } else if (B->s_ptr != s || B->u_ptr != u || B->ld != ld) {
     // new vector pointers: refresh the gather/scatter job tables
@@ -2599,7 +2623,14 @@ void multi_apply(hbi_ctx *c0, const std::vector<hbi_ctx *> &ctxs, const std::vec
   }
   HBI_HIP(hipEventRecord(B->e_in, c0->stream));
   HBI_HIP(hipStreamWaitEvent(B->gst, B->e_in, 0));
-  HBI_HIP(hipGraphLaunch(B->gexec, B->gst));
+  if (B->persistent) {
+    const MPhase *ph = B->phases_d.as<MPhase>();
+    if (prec == HBI_F64) HBI_HIP(launch_multi_persistent<double>(ph, B->nphase, B->nb, B->pgrid, B->gst));
+    else HBI_HIP(launch_multi_persistent<float>(ph, B->nphase, B->nb, B->pgrid, B->gst));
+    ++c0->n_persistent;
+  } else {
+    HBI_HIP(hipGraphLaunch(B->gexec, B->gst));
+  }
   HBI_HIP(hipEventRecord(B->e_out, B->gst));
   HBI_HIP(hipStreamWaitEvent(c0->stream, B->e_out, 0));
 }
@@ -3271,7 +3302,8 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       "\"wstage_items_global\": %lld, \"wstage_items_wide\": %lld, \"wstage_cap_lds\": %d, "
       "\"wstage_c_quantiles\": [%d, %d, %d, %d, %d], \"nnz_per_cell\": %.3f, "
       "\"nnz_per_cell_over_log2sq\": %.5f, \"tab_sources\": %d, \"tab_rounds_max\": %d, "
-      "\"tab_point_updates\": %.0f, \"tab_s\": %.6f, \"wstage_bytes_per_level\": %s}",
+      "\"tab_point_updates\": %.0f, \"tab_s\": %.6f, \"batched_persistent_launches\": %lld, "
+      "\"wstage_bytes_per_level\": %s}",
       ctx->state, ctx->dim, (long long)Nv, ctx->geo.Lv, ctx->NT, ctx->nI,
       ctx->prec == HBI_F64 ? "f64" : "f32", ctx->tol, ctx->chi(), ctx->leaf(),
       (long long)ctx->nnz_v, (long long)ctx->nnz_w, (long long)ctx->nnz_k, (long long)ctx->nnz_d,
@@ -3297,7 +3329,8 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       ctx->wst_cq[3], ctx->wst_cq[4], Nv ? (double)ctx->Felems / (double)Nv : 0.0,
       Nv > 1 ? (double)ctx->Felems / (double)Nv / (std::log2((double)Nv) * std::log2((double)Nv))
              : 0.0,
-      ctx->tab_sources, ctx->tab_rounds_max, ctx->tab_point_updates, ctx->tab_s, wl.c_str());
+      ctx->tab_sources, ctx->tab_rounds_max, ctx->tab_point_updates, ctx->tab_s,
+      (long long)ctx->n_persistent, wl.c_str());
   if (len < 0 || len >= cap) { ctx->err = "output buffer too small"; return HBI_ERR_ARG; }
   std::memcpy(json, buf, len + 1);
   return HBI_OK;

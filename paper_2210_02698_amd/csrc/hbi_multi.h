@@ -95,7 +95,23 @@ struct MStagePlan {
   int64_t n;
 };
 
+// One phase of the persistent batched product: a stage (kind 0..5, as in
+// MStagePlan, n work items) or a gather (6) / scatter (7) over n jobs, nx
+// blocks of 64 tree positions and maxjt column tiles each.
+struct MPhase {
+  int kind;
+  int nx, maxjt;
+  const void *items;
+  int64_t n;
+};
+
 template <typename R> hipError_t launch_multi_stage(const MStagePlan &sp, hipStream_t st);
+// Co-resident workgroups of the persistent kernel for column-tile width nb
+// (a multiple of 8), and its cooperative launch over device phases.
+template <typename R> hipError_t persistent_grid(int nb, int device, int *grid);
+template <typename R>
+hipError_t launch_multi_persistent(const MPhase *phases, int nphase, int nb, int grid,
+                                   hipStream_t st);
 template <typename R>
 hipError_t launch_gather_in(const MTrans *jobs, int64_t njobs, int64_t maxNv, int maxjt,
                             hipStream_t st);

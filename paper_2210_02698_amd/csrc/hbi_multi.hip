@@ -16,6 +16,8 @@
 // tile and reused for all Np right-hand sides.
 #include <type_traits>
 
+#include <hip/hip_cooperative_groups.h>
+
 #include "hbi_device.h"
 #include "hbi_multi.h"
 
@@ -274,12 +276,12 @@ __device__ __forceinline__ void add_skeleton_rows(const uint16_t *idx, int r, in
 // Transfer stage: one wave per (child of a unit, 16-row tile, group of NB
 // column tiles).
 template <typename R, int NB>
-__global__ __launch_bounds__(256) void k_wstage_mr(const MWItem *items, int64_t nitems) {
+__device__ __forceinline__ void b_wstage_mr(const MWItem *items, int64_t nitems, int64_t bid) {
   using C = cplx_t<R>;
   using A = typename Mfma<R>::acc;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t it = bid * 4 + wave;
   if (it >= nitems) return;
   const MWItem W = items[it];
   if (W.Np == 0) return;   // a free slot of the XCD placement
@@ -320,15 +322,19 @@ __global__ __launch_bounds__(256) void k_wstage_mr(const MWItem *items, int64_t 
   // plus the skeleton input of each row (the identity part of X)
   add_skeleton_rows<R, NB>(W.idx, W.r, W.r0, Z, (C *)W.zout, W.Np, jt0, nbv, lane, ar, ai);
 }
+template <typename R, int NB>
+__global__ __launch_bounds__(256) void k_wstage_mr(const MWItem *items, int64_t nitems) {
+  b_wstage_mr<R, NB>(items, nitems, blockIdx.x);
+}
 
 // V^0 stage: one wave per (leaf, level, 16-row tile, column-tile group).
 template <typename R, int NB>
-__global__ __launch_bounds__(256) void k_vstage_mr(const MVItem *items, int64_t nitems) {
+__device__ __forceinline__ void b_vstage_mr(const MVItem *items, int64_t nitems, int64_t bid) {
   using C = cplx_t<R>;
   using A = typename Mfma<R>::acc;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t it = bid * 4 + wave;
   if (it >= nitems) return;
   const MVItem W = items[it];
   if (W.Np == 0) return;   // a free slot of the XCD placement
@@ -343,17 +349,21 @@ __global__ __launch_bounds__(256) void k_vstage_mr(const MVItem *items, int64_t 
   // plus the skeleton input of each row
   add_skeleton_rows<R, NB>(W.idx, W.r, W.r0, X, (C *)W.z, W.Np, W.jt, nbv, lane, ar, ai);
 }
+template <typename R, int NB>
+__global__ __launch_bounds__(256) void k_vstage_mr(const MVItem *items, int64_t nitems) {
+  b_vstage_mr<R, NB>(items, nitems, blockIdx.x);
+}
 
 // Final stage: one wave per (leaf, 16-row tile, column-tile group); the
 // dense leaf block and every level's K^L accumulate into the same tiles in
 // a fixed order.
 template <typename R, int NB>
-__global__ __launch_bounds__(256) void k_final_mr(const MFItem *items, int64_t nitems) {
+__device__ __forceinline__ void b_final_mr(const MFItem *items, int64_t nitems, int64_t bid) {
   using C = cplx_t<R>;
   using A = typename Mfma<R>::acc;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t it = bid * 4 + wave;
   if (it >= nitems) return;
   const MFItem W = items[it];
   if (W.Np == 0) return;   // a free slot of the XCD placement
@@ -380,6 +390,10 @@ __global__ __launch_bounds__(256) void k_final_mr(const MFItem *items, int64_t n
       if (nb < nbv) stg(dst, (W.jt + nb) * 16 + li, C{ar[nb][v], ai[nb][v]});
   }
 }
+template <typename R, int NB>
+__global__ __launch_bounds__(256) void k_final_mr(const MFItem *items, int64_t nitems) {
+  b_final_mr<R, NB>(items, nitems, blockIdx.x);
+}
 
 // Stores rows [r0, r0 + 16) (those below `rows`) of the accumulators to
 // dst (row stride Np), times `scale`.
@@ -405,12 +419,12 @@ __device__ __forceinline__ void store_tile(cplx_t<R> *dst, int r0, int rows, int
 // Adjoint, K^L part: z_l = (K^L_l)^H y_leaf for one (leaf, level, 16-row
 // tile of the r skeleton rows, column-tile group).
 template <typename R, int NB>
-__global__ __launch_bounds__(256) void k_final_adj_mr(const MFAItem *items, int64_t nitems) {
+__device__ __forceinline__ void b_final_adj_mr(const MFAItem *items, int64_t nitems, int64_t bid) {
   using C = cplx_t<R>;
   using A = typename Mfma<R>::acc;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t it = bid * 4 + wave;
   if (it >= nitems) return;
   const MFAItem W = items[it];
   if (W.Np == 0) return;   // a free slot of the XCD placement
@@ -422,17 +436,21 @@ __global__ __launch_bounds__(256) void k_final_adj_mr(const MFAItem *items, int6
                    nullptr, aload);
   store_tile<R, NB>((C *)W.z, W.r0, W.r, W.Np, W.jt, lane, (R)1, ar, ai);
 }
+template <typename R, int NB>
+__global__ __launch_bounds__(256) void k_final_adj_mr(const MFAItem *items, int64_t nitems) {
+  b_final_adj_mr<R, NB>(items, nitems, blockIdx.x);
+}
 
 // Adjoint of a transfer unit: rows [r0, r0 + 16) of its c inputs,
 // z_in = X_a^H w_a + X_b^H w_b as one product over the stacked ra + rb
 // outputs (w_a and w_b are separate blocks).
 template <typename R, int NB>
-__global__ __launch_bounds__(256) void k_wstage_adj_mr(const MWAItem *items, int64_t nitems) {
+__device__ __forceinline__ void b_wstage_adj_mr(const MWAItem *items, int64_t nitems, int64_t bid) {
   using C = cplx_t<R>;
   using A = typename Mfma<R>::acc;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t it = bid * 4 + wave;
   if (it >= nitems) return;
   const MWAItem W = items[it];
   if (W.Np == 0) return;   // a free slot of the XCD placement
@@ -455,16 +473,20 @@ __global__ __launch_bounds__(256) void k_wstage_adj_mr(const MWAItem *items, int
                    nullptr, aload, (const C *)W.zb, ra);
   store_tile<R, NB>((C *)W.zin, W.r0, c, W.Np, W.jt, lane, (R)1, ar, ai);
 }
+template <typename R, int NB>
+__global__ __launch_bounds__(256) void k_wstage_adj_mr(const MWAItem *items, int64_t nitems) {
+  b_wstage_adj_mr<R, NB>(items, nitems, blockIdx.x);
+}
 
 // Adjoint, leaf part: u_leaf = scale (D^H y_leaf + sum_l V_l^H z_l), rows
 // [r0, r0 + 16) of the leaf's cells, every level in a fixed order.
 template <typename R, int NB>
-__global__ __launch_bounds__(256) void k_vstage_adj_mr(const MVAItem *items, int64_t nitems) {
+__device__ __forceinline__ void b_vstage_adj_mr(const MVAItem *items, int64_t nitems, int64_t bid) {
   using C = cplx_t<R>;
   using A = typename Mfma<R>::acc;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t it = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t it = bid * 4 + wave;
   if (it >= nitems) return;
   const MVAItem W = items[it];
   if (W.Np == 0) return;   // a free slot of the XCD placement
@@ -490,17 +512,21 @@ __global__ __launch_bounds__(256) void k_vstage_adj_mr(const MVAItem *items, int
   }
   store_tile<R, NB>((C *)W.u, W.r0, sz, W.Np, W.jt, lane, (R)W.scale, ar, ai);
 }
+template <typename R, int NB>
+__global__ __launch_bounds__(256) void k_vstage_adj_mr(const MVAItem *items, int64_t nitems) {
+  b_vstage_adj_mr<R, NB>(items, nitems, blockIdx.x);
+}
 
 // s (natural order, column-major N_v x nrhs, leading dimension ld) ->
 // x (tree order, row stride Np), scaled by h^d; columns nrhs..Np-1 zeroed.
 // 64 tree positions x 16 columns per workgroup through LDS.
 template <typename R>
-__global__ __launch_bounds__(256) void k_gather_in(const MTrans *jobs, int64_t njobs) {
+__device__ __forceinline__ void b_gather_in(const MTrans *jobs, int64_t bx, int by, int bz,
+                                            cplx_t<R> (*tile)[17]) {
   using C = cplx_t<R>;
-  __shared__ C tile[64][17];
-  const MTrans J = jobs[blockIdx.y];
-  const int64_t p0 = (int64_t)blockIdx.x * 64;
-  const int jt = blockIdx.z;
+  const MTrans J = jobs[by];
+  const int64_t p0 = bx * 64;
+  const int jt = bz;
   if (p0 >= J.Nv || jt * 16 >= J.Np) return;
   const int t = threadIdx.x;
   // read: column j fastest-varying over threads' positions
@@ -522,15 +548,20 @@ __global__ __launch_bounds__(256) void k_gather_in(const MTrans *jobs, int64_t n
     if (p < J.Nv) ((C *)J.dst)[p * J.Np + jt * 16 + j] = tile[pl][j];
   }
 }
+template <typename R>
+__global__ __launch_bounds__(256) void k_gather_in(const MTrans *jobs, int64_t njobs) {
+  __shared__ cplx_t<R> tile[64][17];
+  b_gather_in<R>(jobs, blockIdx.x, blockIdx.y, blockIdx.z, tile);
+}
 
 // y (tree order, row stride Np) -> u (natural order, column-major, ld).
 template <typename R>
-__global__ __launch_bounds__(256) void k_scatter_out(const MTrans *jobs, int64_t njobs) {
+__device__ __forceinline__ void b_scatter_out(const MTrans *jobs, int64_t bx, int by, int bz,
+                                              cplx_t<R> (*tile)[17]) {
   using C = cplx_t<R>;
-  __shared__ C tile[64][17];
-  const MTrans J = jobs[blockIdx.y];
-  const int64_t p0 = (int64_t)blockIdx.x * 64;
-  const int jt = blockIdx.z;
+  const MTrans J = jobs[by];
+  const int64_t p0 = bx * 64;
+  const int jt = bz;
   if (p0 >= J.Nv || jt * 16 >= J.Np) return;
   const int t = threadIdx.x;
   for (int q = t; q < 64 * 16; q += 256) {
@@ -544,6 +575,47 @@ __global__ __launch_bounds__(256) void k_scatter_out(const MTrans *jobs, int64_t
     const int64_t p = p0 + pl;
     const int col = jt * 16 + j;
     if (p < J.Nv && col < J.nrhs) ((C *)J.dst)[J.perm[p] + (int64_t)col * J.ld] = tile[pl][j];
+  }
+}
+template <typename R>
+__global__ __launch_bounds__(256) void k_scatter_out(const MTrans *jobs, int64_t njobs) {
+  __shared__ cplx_t<R> tile[64][17];
+  b_scatter_out<R>(jobs, blockIdx.x, blockIdx.y, blockIdx.z, tile);
+}
+
+// The whole batched product in one persistent launch: the workgroups walk
+// the phases (gather, every stage, scatter, pass after pass) in order, each
+// taking the units b, b + gridDim.x, ... of a phase (workgroup b keeps XCD
+// b % 8 since gridDim.x is a multiple of 8, so the XCD placement of the work
+// items holds), and wait at a grid-wide barrier between phases.  Launched
+// cooperatively: every workgroup is resident, so the barrier cannot wait on
+// a workgroup that has not started.
+template <typename R, int NB>
+__global__ __launch_bounds__(256) void k_multi_persistent(const MPhase *phases, int nphase) {
+  __shared__ cplx_t<R> tile[64][17];
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  for (int q = 0; q < nphase; ++q) {
+    const MPhase P = phases[q];
+    const bool trans = P.kind >= 6;
+    const int64_t nu = trans ? (int64_t)P.nx * P.n * P.maxjt : (P.n + 3) / 4;
+    for (int64_t u = blockIdx.x; u < nu; u += gridDim.x) {
+      switch (P.kind) {
+        case 0: b_vstage_mr<R, NB>((const MVItem *)P.items, P.n, u); break;
+        case 1: b_wstage_mr<R, NB>((const MWItem *)P.items, P.n, u); break;
+        case 2: b_final_mr<R, NB>((const MFItem *)P.items, P.n, u); break;
+        case 3: b_final_adj_mr<R, NB>((const MFAItem *)P.items, P.n, u); break;
+        case 4: b_wstage_adj_mr<R, NB>((const MWAItem *)P.items, P.n, u); break;
+        case 5: b_vstage_adj_mr<R, NB>((const MVAItem *)P.items, P.n, u); break;
+        default: {
+          const int64_t bx = u % P.nx, rest = u / P.nx;
+          const int by = (int)(rest % P.n), bz = (int)(rest / P.n);
+          if (P.kind == 6) b_gather_in<R>((const MTrans *)P.items, bx, by, bz, tile);
+          else b_scatter_out<R>((const MTrans *)P.items, bx, by, bz, tile);
+          __syncthreads();   // the tile is reused by the next unit
+        }
+      }
+    }
+    grid.sync();
   }
 }
 
@@ -600,6 +672,43 @@ hipError_t launch_scatter_out(const MTrans *jobs, int64_t njobs, int64_t maxNv, 
   return hipGetLastError();
 }
 
+template <typename R> static const void *persistent_kernel(int nb) {
+  switch (nb) {
+    case 1: return (const void *)k_multi_persistent<R, 1>;
+    case 2: return (const void *)k_multi_persistent<R, 2>;
+    case 4: return (const void *)k_multi_persistent<R, 4>;
+    case 8: return (const void *)k_multi_persistent<R, 8>;
+    default: return nullptr;
+  }
+}
+
+template <typename R> hipError_t persistent_grid(int nb, int device, int *grid) {
+  const void *k = persistent_kernel<R>(nb);
+  if (!k) return hipErrorInvalidValue;
+  int per_cu = 0, ncu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, 0);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) return e;
+  const int g = per_cu * ncu - (per_cu * ncu) % 8;
+  if (g < 8) return hipErrorInvalidConfiguration;
+  *grid = g;
+  return hipSuccess;
+}
+
+template <typename R>
+hipError_t launch_multi_persistent(const MPhase *phases, int nphase, int nb, int grid,
+                                   hipStream_t st) {
+  const void *k = persistent_kernel<R>(nb);
+  if (!k || grid < 8 || grid % 8) return hipErrorInvalidValue;
+  void *args[] = {(void *)&phases, (void *)&nphase};
+  return hipLaunchCooperativeKernel(k, dim3(grid), dim3(256), args, 0, st);
+}
+
+template hipError_t persistent_grid<float>(int, int, int *);
+template hipError_t persistent_grid<double>(int, int, int *);
+template hipError_t launch_multi_persistent<float>(const MPhase *, int, int, int, hipStream_t);
+template hipError_t launch_multi_persistent<double>(const MPhase *, int, int, int, hipStream_t);
 template hipError_t launch_multi_stage<float>(const MStagePlan &, hipStream_t);
 template hipError_t launch_multi_stage<double>(const MStagePlan &, hipStream_t);
 template hipError_t launch_gather_in<float>(const MTrans *, int64_t, int64_t, int, hipStream_t);
