@@ -208,7 +208,8 @@ __device__ __forceinline__ C group_sum(C acc, int lane, int wr, int G) {
   return acc;
 }
 
-// Forward transfer stage.  Row i of child a of a unit is
+// Forward transfer stage (FP64; FP32 runs k_wstage_pair below, the same
+// work with rows in pairs).  Row i of child a of a unit is
 // x[ia[i]] + sum_m T_a[i, m] x[ia[ra + m]] (X = [I, T] Pi^T), likewise for b
 // with its own column order ib.  A work item is rows [r0, r0 + wr) of a unit
 // (the pair stacked a then b; all rows when it has at most 32), one wave,
@@ -225,8 +226,9 @@ __device__ __forceinline__ C group_sum(C acc, int lane, int wr, int G) {
 // the producers scattering their outputs straight into both consumer orders
 // (twice the output writes, scattered: slower).  Factor batches of 4 to 16
 // entries per lane, 2 to 6 staging loads per lane issued ahead and 5 to 8
-// waves per SIMD all ran within 5 % of each other (this configuration the
-// fastest), so the stage is not bound by the loads one wave keeps in flight.
+// waves per SIMD all ran within 5 % of each other in FP32 (this
+// configuration the fastest), so the stage is not bound by the loads one
+// wave keeps in flight.
 // Each wave is a workgroup of its own (1-2 % faster than four per
 // workgroup: a finished wave's slot and LDS are not held by the others).
 template <typename R, int B>
@@ -291,6 +293,117 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void
   }
   acc = group_sum(acc, lane, wr, G);
   if (act && grp == 0) (isb ? z + U.zoutb : z + U.zouta)[i] = C{acc.x + x0.x, acc.y + x0.y};
+}
+
+// FP32 forward transfer stage with row pairs: lane (p, g) takes rows i and
+// i + 1 of one child (pairs never straddle the two children) and the
+// columns g, g + G, ... (G = 64 / pairs), loading both entries of a column
+// with one 16-byte load, so a wave issues half the factor-load
+// instructions of k_wstage for the same bytes.  The pair's second entry of
+// an odd child is the next column's first (or, for the last column, the
+// entry after the block, inside the store's two spare entries) and is not
+// used.  Staging and column orders as in k_wstage.  The stage's waves spend
+// much of their life ready but waiting for issue behind the others' memory
+// instructions: the pairs took it from 63.8 to 58.7 us per launch on the
+// 1024^2 bump; staging the inputs and orders with 16-byte loads as well
+// measured slower (59.6 us), as did 8 pairs per batch (spills).
+template <int B>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_wstage_pair(
+    const WItem *items, int64_t nitems, const uint16_t *fidx, const cplx_t<float> *F,
+    cplx_t<float> *z, int cap_lds) {
+  using C = cplx_t<float>;
+  typedef float F4 __attribute__((ext_vector_type(4), aligned(8)));
+  constexpr int WX = HBI_WSTAGE_LDS_BYTES / (int)sizeof(C);
+  constexpr int NS = 2;
+  __shared__ C xs[WX];
+  const int lane = threadIdx.x;
+  const int64_t it = blockIdx.x;
+  if (it >= nitems) return;
+  const WItem U = items[it];
+  const int ra = U.ra, rb = U.rb, c = U.c, Rt = ra + rb;
+  const int wr = Rt <= 32 ? Rt : U.wr;
+  const int r0 = Rt <= 32 ? 0 : U.off;
+  const int r1 = r0 + wr < Rt ? r0 + wr : Rt;        // window [r0, r1) of the stacked rows
+  // the window's rows of child a, [a0, a1), and of child b, [b0, b1) (local)
+  const int a0 = r0 < ra ? r0 : ra, a1 = r1 < ra ? r1 : ra;
+  const int b0 = (r0 > ra ? r0 : ra) - ra, b1 = r1 > ra ? r1 - ra : 0;
+  const int npa = (a1 - a0 + 1) >> 1, npb = (b1 - b0 + 1) >> 1, P = npa + npb;
+  const int G = 64 / P;
+  const int pr = lane % P, grp = lane / P;
+  const bool isb = pr >= npa;
+  const int i = isb ? b0 + 2 * (pr - npa) : a0 + 2 * pr;   // first row, local to the child
+  const int iend = isb ? b1 : a1;
+  const bool act = grp < G;
+  const bool two = i + 1 < iend;                     // the pair's second row is in the window
+  const int rc = isb ? rb : ra;
+  const int t = c - rc;
+  const int ob = isb ? c : 0;
+  const int j0 = ob + rc + grp;
+  const uint16_t *ia = fidx + U.ioff;
+  const uint32_t *ia32 = (const uint32_t *)ia;
+  const C *zin = z + U.zin;
+  const C *T = F + U.foff + (isb ? (int64_t)ra * (c - ra) : 0) + i + (int64_t)grp * rc;
+  const int64_t step = (int64_t)G * rc;
+  const int nt = act && t > grp ? (t - grp + G - 1) / G : 0;
+  F4 mv[B];
+  auto issue = [&](int q0) {
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      mv[u] = q0 + u < nt ? *(const F4 *)(T + (int64_t)(q0 + u) * step) : F4{0, 0, 0, 0};
+  };
+  auto dot = [&](auto xat, C &acc0, C &acc1) {
+    acc0 = C{0, 0};
+    acc1 = C{0, 0};
+    for (int q0 = 0; q0 < nt; q0 += B) {
+      if (q0 > 0) issue(q0);
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int q = q0 + u < nt ? q0 + u : nt - 1;   // padding entries are zero
+        const C x = xat(q);
+        cfma(acc0, C{mv[u][0], mv[u][1]}, x);
+        cfma(acc1, C{mv[u][2], mv[u][3]}, x);
+      }
+    }
+  };
+  const int cw = (4 * c + (int)sizeof(C) - 1) / (int)sizeof(C);
+  C acc0, acc1, x0, x1;
+  const int i1 = two ? i + 1 : i;
+  if (c + cw <= cap_lds) {
+    C *xw = xs;
+    uint32_t *iw32 = (uint32_t *)(xw + c);
+    const uint16_t *iw = (const uint16_t *)iw32;
+    C xr[NS];
+    uint32_t ir[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int k = lane + 64 * u;
+      xr[u] = k < c ? zin[k] : C{0, 0};
+      ir[u] = k < c ? ia32[k] : 0u;
+    }
+    issue(0);
+    for (int k = 64 * NS + lane; k < c; k += 64) { xw[k] = zin[k]; iw32[k] = ia32[k]; }
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int k = lane + 64 * u;
+      if (k < c) { xw[k] = xr[u]; iw32[k] = ir[u]; }
+    }
+    wave_lds_sync();
+    dot([&](int q) { return xw[iw[j0 + q * G]]; }, acc0, acc1);
+    x0 = xw[iw[ob + (act ? i : 0)]];
+    x1 = xw[iw[ob + (act ? i1 : 0)]];
+  } else {
+    issue(0);
+    dot([&](int q) { return zin[ia[j0 + q * G]]; }, acc0, acc1);
+    x0 = zin[ia[ob + (act ? i : 0)]];
+    x1 = zin[ia[ob + (act ? i1 : 0)]];
+  }
+  acc0 = group_sum(acc0, lane, P, G);
+  acc1 = group_sum(acc1, lane, P, G);
+  if (act && grp == 0) {
+    C *zo = isb ? z + U.zoutb : z + U.zouta;
+    zo[i] = C{acc0.x + x0.x, acc0.y + x0.y};
+    if (two) zo[i + 1] = C{acc1.x + x1.x, acc1.y + x1.y};
+  }
 }
 
 // One workgroup (4 waves) per row leaf: wave w accumulates the K^L blocks
@@ -656,8 +769,8 @@ hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
     if (hook) hook->before(name, elems * esz + idx);
   };
   auto post = [&]() { if (hook) hook->after(); };
-  // factor loads per batch of the transfer stages (64 VGPRs: 8 waves/SIMD)
-  constexpr int WB = sizeof(R) == 4 ? 8 : 4;
+  // factor loads per batch of the FP64 transfer stage (64 VGPRs: 8 waves/SIMD)
+  constexpr int WB = 4;
   if (ap.Lv > 4 * kVq) return hipErrorInvalidValue;   // N_v < 2^31 keeps L_v <= 25
   if (!adjoint) {
     if (ap.Lv > 0) {
@@ -670,9 +783,14 @@ hipError_t launch_apply(const ApplyPlan &ap, const void *s, void *u, void *z,
       const int64_t nu = ap.nunits[k];
       if (nu == 0) continue;
       const int64_t ni = ap.nitems[k];
-      pre("k_wstage", ap.w_elems[k], ap.w_idx[k]);
-      hipLaunchKernelGGL((k_wstage<R, WB>), dim3(ni), dim3(64), 0, st, ap.items[k],
-                         ni, ap.fidx, Fc, zc, ap.cap_lds);
+      pre(sizeof(R) == 4 ? "k_wstage_pair" : "k_wstage", ap.w_elems[k], ap.w_idx[k]);
+      // FP32: rows in pairs, one 16-byte factor load per pair and column
+      if constexpr (sizeof(R) == 4)
+        hipLaunchKernelGGL((k_wstage_pair<4>), dim3(ni), dim3(64), 0, st, ap.items[k], ni,
+                           ap.fidx, Fc, zc, ap.cap_lds);
+      else
+        hipLaunchKernelGGL((k_wstage<R, WB>), dim3(ni), dim3(64), 0, st, ap.items[k],
+                           ni, ap.fidx, Fc, zc, ap.cap_lds);
       post();
     }
     pre("k_final", ap.f_elems, ap.f_idx);

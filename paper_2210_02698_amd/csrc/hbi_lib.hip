@@ -1549,7 +1549,9 @@ void build_factors(hbi_ctx *c, double tol) {
   B.stage[1].release();
   c->Felems = Fg;
   const size_t esz = c->prec == HBI_F64 ? sizeof(double2) : sizeof(float2);
-  HBI_HIP(c->F.alloc(esz * std::max<int64_t>(Fg, 1)));
+  // two spare entries: the FP32 transfer stage loads rows in pairs, which
+  // reads at most one entry past a block
+  HBI_HIP(c->F.alloc(esz * (std::max<int64_t>(Fg, 1) + 2)));
   upload(c->Fi, fi_h);
   {
     const std::vector<PlaceDesc> place = layout_store(chunks, Lv, nleaf, vd, kd, leaves, units, Fg);
