@@ -64,6 +64,26 @@ template <typename C> __device__ __forceinline__ void stg(C *p, int64_t i, C v) 
   ((gptr<V>)p)[i] = V{v.x, v.y};
 }
 
+// Workspace column of lane li in column tile nb of the group [jt, jt + NB)
+// (nbv tiles of it exist).  With NB >= 2 a full pair of tiles (2m, 2m + 1)
+// takes the 32 columns jt*16 + 32m + [0, 32) interleaved, tile 2m the even
+// ones and 2m + 1 the odd ones, so that one 16-byte load brings a lane's B
+// entries of both; a pair with one tile takes its 16 columns in order.
+// Every load and store of the tiles' columns goes through this map, and
+// each output column is computed from the same input column, so the
+// numbers do not depend on it.
+template <int NB> __device__ __forceinline__ int tcol(int jt, int nb, int li, int nbv) {
+  if (NB >= 2 && (nb | 1) < nbv) return jt * 16 + 32 * (nb >> 1) + 2 * li + (nb & 1);
+  return (jt + nb) * 16 + li;
+}
+template <typename C> __device__ __forceinline__ void ldg2(const C *p, int64_t i, C &e0, C &e1) {
+  using E = decltype(C{}.x);
+  typedef E V __attribute__((ext_vector_type(4)));
+  const V v = ((gptr<const V>)(p + i))[0];
+  e0 = C{v[0], v[1]};
+  e1 = C{v[2], v[3]};
+}
+
 // Accumulate a 16-row tile of M (rows r0.., column-major, leading dimension
 // ldm, `rows` valid rows, `k` columns) times Z (k x Np, row stride Np),
 // for column tiles [jt0, jt0 + NB) of 16 columns each.
@@ -124,11 +144,27 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
       const bool second = Z2 && kok && kk >= ksplit;
       const C *Zb = second ? Z2 : Z;
       const int zrb = second ? I.zr[u] - ksplit : I.zr[u];
+      if constexpr (NB >= 2 && sizeof(R) == 4) {
+        // one 16-byte load per pair of tiles (tcol's interleaved columns);
+        // a pair with one tile loads the aligned pair of columns holding
+        // the lane's column and keeps its half
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const bool ok = kok && nb < nbv;
-        const C v = ldg(Zb, (int64_t)(ok ? zrb : 0) * Np + zc + (ok ? nb * 16 : 0));
-        D.b[u][nb] = ok ? v : C{0, 0};
+        for (int nb = 0; nb < NB; nb += 2) {
+          const bool full = nb + 1 < nbv;
+          const bool ok0 = kok && nb < nbv, ok1 = kok && full;
+          const int col = full ? jt0 * 16 + 16 * nb + 2 * li : (jt0 + nb) * 16 + (li & ~1);
+          C e0, e1;
+          ldg2(Zb, (int64_t)(ok0 ? zrb : 0) * Np + (ok0 ? col : 0), e0, e1);
+          D.b[u][nb] = ok0 ? (full || !(li & 1) ? e0 : e1) : C{0, 0};
+          D.b[u][nb + 1] = ok1 ? e1 : C{0, 0};
+        }
+      } else {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const bool ok = kok && nb < nbv;
+          const C v = ldg(Zb, (int64_t)(ok ? zrb : 0) * Np + (ok ? tcol<NB>(jt0, nb, li, nbv) : zc));
+          D.b[u][nb] = ok ? v : C{0, 0};
+        }
       }
       if constexpr (synth) {
         D.a[u] = aload.value(row, I.pa[u], rok && kok);
@@ -260,7 +296,7 @@ __device__ __forceinline__ void add_skeleton_rows(const uint16_t *idx, int r, in
   for (int v = 0; v < 4; ++v)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
-      x0[v][nb] = nb < nbv ? ldg(Z, (int64_t)sr[v] * Np + (jt0 + nb) * 16 + li) : C{0, 0};
+      x0[v][nb] = nb < nbv ? ldg(Z, (int64_t)sr[v] * Np + tcol<NB>(jt0, nb, li, nbv)) : C{0, 0};
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int row = r0 + Mfma<R>::row(lg, v);
@@ -268,7 +304,7 @@ __device__ __forceinline__ void add_skeleton_rows(const uint16_t *idx, int r, in
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
       if (nb < nbv)
-        stg(dst, (int64_t)row * Np + (jt0 + nb) * 16 + li,
+        stg(dst, (int64_t)row * Np + tcol<NB>(jt0, nb, li, nbv),
             C{ar[nb][v] + x0[v][nb].x, ai[nb][v] + x0[v][nb].y});
   }
 }
@@ -312,7 +348,7 @@ __device__ __forceinline__ void b_wstage_mr(const MWItem *items, int64_t nitems,
                         : (C *)W.zoutb + (int64_t)(row - ra) * W.Np;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
-        if (nb < nbv) stg(dst, (jt0 + nb) * 16 + li, C{ar[nb][v], ai[nb][v]});
+        if (nb < nbv) stg(dst, tcol<NB>(jt0, nb, li, nbv), C{ar[nb][v], ai[nb][v]});
     }
     return;
   }
@@ -387,7 +423,7 @@ __device__ __forceinline__ void b_final_mr(const MFItem *items, int64_t nitems, 
     C *dst = (C *)W.y + (int64_t)row * W.Np;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
-      if (nb < nbv) stg(dst, (W.jt + nb) * 16 + li, C{ar[nb][v], ai[nb][v]});
+      if (nb < nbv) stg(dst, tcol<NB>(W.jt, nb, li, nbv), C{ar[nb][v], ai[nb][v]});
   }
 }
 template <typename R, int NB>
@@ -411,7 +447,7 @@ __device__ __forceinline__ void store_tile(cplx_t<R> *dst, int r0, int rows, int
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
       if (nb < nbv)
-        stg(dst, (int64_t)row * Np + (jt + nb) * 16 + li,
+        stg(dst, (int64_t)row * Np + tcol<NB>(jt, nb, li, nbv),
             cplx_t<R>{ar[nb][v] * scale, ai[nb][v] * scale});
   }
 }
