@@ -525,19 +525,21 @@ def gpu_many(args, kind, w, refs, cpu, tol):
     t, U = timed_batched(ops, S, args.steps, args.warmup)
     # the same batch as one persistent cooperative launch per call (the
     # library's opt-in mode) beside the graph replay timed above
-    prev = os.environ.get("HBI_BATCHED_PERSISTENT")
-    os.environ["HBI_BATCHED_PERSISTENT"] = "1"
-    try:
-        tp, Up = timed_batched(ops, S, args.steps, args.warmup)
-        p_same = all(bool(torch.equal(a, b)) for a, b in zip(U, Up))
-    finally:
-        if prev is None:
-            os.environ.pop("HBI_BATCHED_PERSISTENT")
-        else:
-            os.environ["HBI_BATCHED_PERSISTENT"] = prev
-    del Up
-    log(f"{kind}: persistent launch {tp * 1e3:.3f} ms per step, graph {t * 1e3:.3f}, "
-        f"bitwise equal {p_same}")
+    tp = p_same = None
+    if not args.no_persistent:
+        prev = os.environ.get("HBI_BATCHED_PERSISTENT")
+        os.environ["HBI_BATCHED_PERSISTENT"] = "1"
+        try:
+            tp, Up = timed_batched(ops, S, args.steps, args.warmup)
+            p_same = all(bool(torch.equal(a, b)) for a, b in zip(U, Up))
+        finally:
+            if prev is None:
+                os.environ.pop("HBI_BATCHED_PERSISTENT")
+            else:
+                os.environ["HBI_BATCHED_PERSISTENT"] = prev
+        del Up
+        log(f"{kind}: persistent launch {tp * 1e3:.3f} ms per step, graph {t * 1e3:.3f}, "
+            f"bitwise equal {p_same}")
     cells = sum(c[0].Nv * c[1] for c in cases)
     nnz = [op.info()["nnz_total"] for op in ops]
     flops = sum(8.0 * n * c[1] for n, c in zip(nnz, cases))
@@ -562,9 +564,9 @@ def gpu_many(args, kind, w, refs, cpu, tol):
                         "achieved": round(achieved, 2), "peak": MFMA_F32_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / MFMA_F32_PEAK_TFLOPS, 4),
                         "flops_per_step": flops, "traffic": None},
-           "persistent_launch": {"ms_per_step": round(tp * 1e3, 4),
-                                 "value": round(cells / tp / 1e9, 6),
-                                 "bitwise_equal_to_graph": p_same},
+           "persistent_launch": None if tp is None else {
+               "ms_per_step": round(tp * 1e3, 4), "value": round(cells / tp / 1e9, 6),
+               "bitwise_equal_to_graph": p_same},
            "cpu_baseline": cpu}
     log(f"{kind}: {out['value']} Gcell*RHS/s {out['ms_per_step']} ms err {out['rel_err_vs_oracle_max']}")
     for op in ops:
@@ -963,6 +965,10 @@ def main():
     ap.add_argument("--rows-3d", type=int, default=512)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="skip the persistent-launch timing of the batched and 3d "
+                         "workloads (profiled runs: rocprofv3 can crash at exit "
+                         "after a cooperative launch)")
     ap.add_argument("--workload", choices=["all", "bump", "batched", "3d", "grad", "tables",
                                            "sweep", "inclusion", "complexity"],
                     default="all",
