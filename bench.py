@@ -523,6 +523,9 @@ def gpu_many(args, kind, w, refs, cpu, tol):
         if p % 16 == 0 or p == len(cases) - 1:
             log(f"{kind}: problem {p} N_v={prob.Nv} nrhs={nrhs} build total {t_build:.1f}s")
     t, U = timed_batched(ops, S, args.steps, args.warmup)
+    info0 = ops[0].info()
+    tile = {"nb": info0.get("batched_tile_nb"), "ku": info0.get("batched_tile_ku")}
+    log(f"{kind}: tuned tile {tile}")
     # the same batch as one persistent cooperative launch per call (the
     # library's opt-in mode) beside the graph replay timed above
     tp = p_same = None
@@ -564,6 +567,7 @@ def gpu_many(args, kind, w, refs, cpu, tol):
                         "achieved": round(achieved, 2), "peak": MFMA_F32_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / MFMA_F32_PEAK_TFLOPS, 4),
                         "flops_per_step": flops, "traffic": None},
+           "tuned_tile": tile,
            "persistent_launch": None if tp is None else {
                "ms_per_step": round(tp * 1e3, 4), "value": round(cells / tp / 1e9, 6),
                "bitwise_equal_to_graph": p_same},

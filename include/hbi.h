@@ -181,9 +181,11 @@ hbi_status hbi_apply_adjoint(hbi_ctx *ctx, const void *s, void *u,
  * (new vector pointers are patched in; a context rebuilt since, or a new
  * context at a freed one's address, makes the call capture again).  The
  * graph is kept by ctx[0] until its next rebuild or hbi_destroy.  On the first call the column-tile
- * width is chosen by timing the candidates on the batch itself; choices are
- * kept for the process and in the JSON file named by HBI_TUNE_CACHE when
- * set.  Vector workspace is bounded by HBI_MULTI_BYTES (default 8 GiB);
+ * width, then the MFMA k-steps whose loads are issued together, are chosen
+ * by timing the candidates on the batch itself (hbi_get_info of ctx[0]:
+ * "batched_tile_nb", "batched_tile_ku", 0 for the width's default); choices
+ * are kept for the process and in the JSON file named by HBI_TUNE_CACHE
+ * when set.  Vector workspace is bounded by HBI_MULTI_BYTES (default 8 GiB);
  * larger batches run as several passes inside the same graph.  hbi_apply
  * with nrhs >= 2 uses the same path for one problem.  With the environment
  * variable HBI_BATCHED_PERSISTENT=1 (read when a batch is planned) the call

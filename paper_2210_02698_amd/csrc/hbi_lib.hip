@@ -2105,7 +2105,7 @@ struct BatchCache {
   std::vector<const void *> s_ptr;
   std::vector<void *> u_ptr;
   std::vector<int64_t> ld;
-  int prec = 0, nb = 4;
+  int prec = 0, nb = 4, ku = 0;   // column-tile width, k-steps per chunk (0: default)
   bool adj = false;   // the conjugate-transpose product
   std::vector<MultiJob> jobs;
   std::vector<MultiPass> passes;
@@ -2561,14 +2561,29 @@ void multi_apply(hbi_ctx *c0, const std::vector<hbi_ctx *> &ctxs, const std::vec
                             ":jt" + std::to_string(maxjt) + ":r" + std::to_string(rbucket);
     auto items = [&](int nb) { if (adj) build_items_adj(*B, nb); else build_items(*B, nb); };
     auto &tt = tune_table();
-    int best = -1;
-    // a cached width is used only if it is one of the candidates this batch
+    // the tuned choice is kept as nb * 16 + ku (ku = 0: the width's default
+    // k-steps per chunk; entries written before the k-step knob are nb alone)
+    auto set_ku = [&](int ku) {
+      for (auto &P : B->passes)
+        for (auto &sp : P.stages) sp.ku = ku;
+    };
+    auto valid = [&](int nb, int ku) {
+      if (!(nb == 1 || nb == 2 || nb == 4 || nb == 8) || (nb > 1 && nb > maxjt)) return false;
+      if (ku == 0) return true;
+      for (int k : multi_ku_candidates(nb))
+        if (k == ku) return true;
+      return false;
+    };
+    int best = -1, best_ku = 0;
+    // a cached choice is used only if it is one of the candidates this batch
     // would time (a corrupt or stale file entry is ignored and re-tuned)
     if (tt.count(key)) {
-      const int nb = tt[key];
-      if ((nb == 1 || nb == 2 || nb == 4 || nb == 8) && (nb == 1 || nb <= maxjt)) best = nb;
+      const int v = tt[key];
+      const int nb = v < 16 ? v : v / 16, ku = v < 16 ? 0 : v % 16;
+      if (valid(nb, ku)) { best = nb; best_ku = ku; }
     }
     if (best < 0) {
+      // the width at its default k-steps, then the k-steps at that width
       double bt = 1e300;
       for (int nb : {1, 2, 4, 8}) {
         if (nb > 1 && nb > maxjt) break;
@@ -2576,11 +2591,21 @@ void multi_apply(hbi_ctx *c0, const std::vector<hbi_ctx *> &ctxs, const std::vec
         const double t = time_passes(*B, 2);
         if (t < bt) { bt = t; best = nb; }
       }
+      items(best);
+      const std::vector<int> kus = multi_ku_candidates(best);
+      for (size_t q = 1; q < kus.size(); ++q) {
+        set_ku(kus[q]);
+        const double t = time_passes(*B, 2);
+        if (t < bt) { bt = t; best_ku = kus[q]; }
+      }
       B->tuned_ms = bt;
-      tt[key] = best;
+      tt[key] = best * 16 + best_ku;
       save_tune_table();
     }
     items(best);
+    // the persistent kernel runs every width at its default k-steps
+    set_ku(persistent ? 0 : best_ku);
+    B->ku = persistent ? 0 : best_ku;
     B->persistent = persistent;
     if (persistent) {
       // the passes' gathers, stages and scatters as the phases of one launch
@@ -3305,7 +3330,7 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       "\"wstage_c_quantiles\": [%d, %d, %d, %d, %d], \"nnz_per_cell\": %.3f, "
       "\"nnz_per_cell_over_log2sq\": %.5f, \"tab_sources\": %d, \"tab_rounds_max\": %d, "
       "\"tab_point_updates\": %.0f, \"tab_s\": %.6f, \"batched_persistent_launches\": %lld, "
-      "\"wstage_bytes_per_level\": %s}",
+      "\"batched_tile_nb\": %d, \"batched_tile_ku\": %d, \"wstage_bytes_per_level\": %s}",
       ctx->state, ctx->dim, (long long)Nv, ctx->geo.Lv, ctx->NT, ctx->nI,
       ctx->prec == HBI_F64 ? "f64" : "f32", ctx->tol, ctx->chi(), ctx->leaf(),
       (long long)ctx->nnz_v, (long long)ctx->nnz_w, (long long)ctx->nnz_k, (long long)ctx->nnz_d,
@@ -3332,7 +3357,8 @@ hbi_status hbi_get_info(const hbi_ctx *cctx, char *json, int64_t cap) {
       Nv > 1 ? (double)ctx->Felems / (double)Nv / (std::log2((double)Nv) * std::log2((double)Nv))
              : 0.0,
       ctx->tab_sources, ctx->tab_rounds_max, ctx->tab_point_updates, ctx->tab_s,
-      (long long)ctx->n_persistent, wl.c_str());
+      (long long)ctx->n_persistent, ctx->batch ? ctx->batch->nb : -1,
+      ctx->batch ? ctx->batch->ku : -1, wl.c_str());
   if (len < 0 || len >= cap) { ctx->err = "output buffer too small"; return HBI_ERR_ARG; }
   std::memcpy(json, buf, len + 1);
   return HBI_OK;

@@ -1,5 +1,7 @@
 // Work items and launchers of the multi-right-hand-side (MFMA) apply.
 #pragma once
+
+#include <vector>
 #include "hbi_internal.h"
 
 namespace hbi {
@@ -93,7 +95,19 @@ struct MStagePlan {
   int nb;              // column tiles per wave
   const void *items;
   int64_t n;
+  int ku = 0;          // MFMA k-steps per load chunk (0: the default for nb)
 };
+// k-steps per chunk that launch_multi_stage accepts for a column-tile
+// width, the default first
+inline std::vector<int> multi_ku_candidates(int nb) {
+  switch (nb) {
+    case 1: return {4, 8, 2};
+    case 2: return {2, 4, 1};
+    case 4: return {1, 2};
+    case 8: return {1};
+    default: return {};
+  }
+}
 
 // One phase of the persistent batched product: a stage (kind 0..5, as in
 // MStagePlan, n work items) or a gather (6) / scatter (7) over n jobs, nx

@@ -105,7 +105,7 @@ template <typename C> __device__ __forceinline__ void ldg2(const C *p, int64_t i
 struct NoLoad {};
 __device__ __forceinline__ void load_fence() { __asm__ volatile("" ::: "memory"); }
 
-template <typename R, int NB, typename AL = NoLoad, bool GATHER = false>
+template <typename R, int NB, int KUT = 0, typename AL = NoLoad, bool GATHER = false>
 __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int ldm, int r0,
                                           int rows, int k, const cplx_t<R> *__restrict__ Z,
                                           int Np, int jt0, int lane,
@@ -115,7 +115,8 @@ __device__ __forceinline__ void tile_gemm(const cplx_t<R> *__restrict__ M, int l
                                           const cplx_t<R> *__restrict__ Z2 = nullptr,
                                           int ksplit = 1 << 30) {
   using C = cplx_t<R>;
-  constexpr int KU = NB == 1 ? 4 : NB == 2 ? 2 : 1;   // k-steps per chunk
+  // k-steps per chunk: KUT, or by default 4 / 2 / 1 for NB = 1 / 2 / more
+  constexpr int KU = KUT ? KUT : NB == 1 ? 4 : NB == 2 ? 2 : 1;
   constexpr int STEP = 4 * KU;                        // columns per chunk
   constexpr bool synth = !std::is_same<AL, NoLoad>::value;
   const int li = lane & 15, lk = lane >> 4;
@@ -311,7 +312,7 @@ __device__ __forceinline__ void add_skeleton_rows(const uint16_t *idx, int r, in
 
 // Transfer stage: one wave per (child of a unit, 16-row tile, group of NB
 // column tiles).
-template <typename R, int NB>
+template <typename R, int NB, int KUT = 0>
 __device__ __forceinline__ void b_wstage_mr(const MWItem *items, int64_t nitems, int64_t bid) {
   using C = cplx_t<R>;
   using A = typename Mfma<R>::acc;
@@ -339,7 +340,7 @@ __device__ __forceinline__ void b_wstage_mr(const MWItem *items, int64_t nitems,
     aload.pb = aload.pa + c;
     aload.ra = ra;
     aload.rb = rb;
-    tile_gemm<R, NB>(aload.Ta, 0, W.r0, ra + rb, c, Z, W.Np, jt0, lane, ar, ai, nullptr, aload);
+    tile_gemm<R, NB, KUT>(aload.Ta, 0, W.r0, ra + rb, c, Z, W.Np, jt0, lane, ar, ai, nullptr, aload);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = W.r0 + Mfma<R>::row(lg, v);
@@ -353,18 +354,18 @@ __device__ __forceinline__ void b_wstage_mr(const MWItem *items, int64_t nitems,
     return;
   }
   // T times the non-skeleton inputs (rows idx[r..c) of Z)
-  tile_gemm<R, NB, NoLoad, true>((const C *)W.T, W.r, W.r0, W.r, W.c - W.r, Z, W.Np, jt0, lane,
+  tile_gemm<R, NB, KUT, NoLoad, true>((const C *)W.T, W.r, W.r0, W.r, W.c - W.r, Z, W.Np, jt0, lane,
                                  ar, ai, W.idx + W.r);
   // plus the skeleton input of each row (the identity part of X)
   add_skeleton_rows<R, NB>(W.idx, W.r, W.r0, Z, (C *)W.zout, W.Np, jt0, nbv, lane, ar, ai);
 }
-template <typename R, int NB>
+template <typename R, int NB, int KUT = 0>
 __global__ __launch_bounds__(256) void k_wstage_mr(const MWItem *items, int64_t nitems) {
-  b_wstage_mr<R, NB>(items, nitems, blockIdx.x);
+  b_wstage_mr<R, NB, KUT>(items, nitems, blockIdx.x);
 }
 
 // V^0 stage: one wave per (leaf, level, 16-row tile, column-tile group).
-template <typename R, int NB>
+template <typename R, int NB, int KUT = 0>
 __device__ __forceinline__ void b_vstage_mr(const MVItem *items, int64_t nitems, int64_t bid) {
   using C = cplx_t<R>;
   using A = typename Mfma<R>::acc;
@@ -380,20 +381,20 @@ __device__ __forceinline__ void b_vstage_mr(const MVItem *items, int64_t nitems,
   const int nbv = (W.Np >> 4) - W.jt < NB ? (W.Np >> 4) - W.jt : NB;
   const C *X = (const C *)W.x;
   // T times the non-skeleton inputs (rows idx[r..sz) of x)
-  tile_gemm<R, NB, NoLoad, true>((const C *)W.T, W.r, W.r0, W.r, W.sz - W.r, X, W.Np, W.jt,
+  tile_gemm<R, NB, KUT, NoLoad, true>((const C *)W.T, W.r, W.r0, W.r, W.sz - W.r, X, W.Np, W.jt,
                                  lane, ar, ai, W.idx + W.r);
   // plus the skeleton input of each row
   add_skeleton_rows<R, NB>(W.idx, W.r, W.r0, X, (C *)W.z, W.Np, W.jt, nbv, lane, ar, ai);
 }
-template <typename R, int NB>
+template <typename R, int NB, int KUT = 0>
 __global__ __launch_bounds__(256) void k_vstage_mr(const MVItem *items, int64_t nitems) {
-  b_vstage_mr<R, NB>(items, nitems, blockIdx.x);
+  b_vstage_mr<R, NB, KUT>(items, nitems, blockIdx.x);
 }
 
 // Final stage: one wave per (leaf, 16-row tile, column-tile group); the
 // dense leaf block and every level's K^L accumulate into the same tiles in
 // a fixed order.
-template <typename R, int NB>
+template <typename R, int NB, int KUT = 0>
 __device__ __forceinline__ void b_final_mr(const MFItem *items, int64_t nitems, int64_t bid) {
   using C = cplx_t<R>;
   using A = typename Mfma<R>::acc;
@@ -409,10 +410,10 @@ __device__ __forceinline__ void b_final_mr(const MFItem *items, int64_t nitems, 
   const C *F = (const C *)W.F;
   const C *z = (const C *)W.z;
   const int sz = W.sz;
-  tile_gemm<R, NB>(F + W.dense_off, sz, W.r0, sz, sz, (const C *)W.x, W.Np, W.jt, lane, ar, ai);
+  tile_gemm<R, NB, KUT>(F + W.dense_off, sz, W.r0, sz, sz, (const C *)W.x, W.Np, W.jt, lane, ar, ai);
   for (int l = 0; l < W.Lv; ++l) {
     const KDesc d = W.kd[l];
-    tile_gemm<R, NB>(F + d.foff, sz, W.r0, sz, d.r, z + d.zin * W.Np, W.Np, W.jt, lane, ar, ai);
+    tile_gemm<R, NB, KUT>(F + d.foff, sz, W.r0, sz, d.r, z + d.zin * W.Np, W.Np, W.jt, lane, ar, ai);
   }
   const int nbv = (W.Np >> 4) - W.jt < NB ? (W.Np >> 4) - W.jt : NB;
   const int li = lane & 15, lg = lane >> 4;
@@ -426,9 +427,9 @@ __device__ __forceinline__ void b_final_mr(const MFItem *items, int64_t nitems, 
       if (nb < nbv) stg(dst, tcol<NB>(W.jt, nb, li, nbv), C{ar[nb][v], ai[nb][v]});
   }
 }
-template <typename R, int NB>
+template <typename R, int NB, int KUT = 0>
 __global__ __launch_bounds__(256) void k_final_mr(const MFItem *items, int64_t nitems) {
-  b_final_mr<R, NB>(items, nitems, blockIdx.x);
+  b_final_mr<R, NB, KUT>(items, nitems, blockIdx.x);
 }
 
 // Stores rows [r0, r0 + 16) (those below `rows`) of the accumulators to
@@ -454,7 +455,7 @@ __device__ __forceinline__ void store_tile(cplx_t<R> *dst, int r0, int rows, int
 
 // Adjoint, K^L part: z_l = (K^L_l)^H y_leaf for one (leaf, level, 16-row
 // tile of the r skeleton rows, column-tile group).
-template <typename R, int NB>
+template <typename R, int NB, int KUT = 0>
 __device__ __forceinline__ void b_final_adj_mr(const MFAItem *items, int64_t nitems, int64_t bid) {
   using C = cplx_t<R>;
   using A = typename Mfma<R>::acc;
@@ -468,19 +469,19 @@ __device__ __forceinline__ void b_final_adj_mr(const MFAItem *items, int64_t nit
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) { ar[nb] = Mfma<R>::zero(); ai[nb] = Mfma<R>::zero(); }
   ConjTransA<R> aload{(const C *)W.K, W.sz};
-  tile_gemm<R, NB>(aload.M, 0, W.r0, W.r, W.sz, (const C *)W.y, W.Np, W.jt, lane, ar, ai,
+  tile_gemm<R, NB, KUT>(aload.M, 0, W.r0, W.r, W.sz, (const C *)W.y, W.Np, W.jt, lane, ar, ai,
                    nullptr, aload);
   store_tile<R, NB>((C *)W.z, W.r0, W.r, W.Np, W.jt, lane, (R)1, ar, ai);
 }
-template <typename R, int NB>
+template <typename R, int NB, int KUT = 0>
 __global__ __launch_bounds__(256) void k_final_adj_mr(const MFAItem *items, int64_t nitems) {
-  b_final_adj_mr<R, NB>(items, nitems, blockIdx.x);
+  b_final_adj_mr<R, NB, KUT>(items, nitems, blockIdx.x);
 }
 
 // Adjoint of a transfer unit: rows [r0, r0 + 16) of its c inputs,
 // z_in = X_a^H w_a + X_b^H w_b as one product over the stacked ra + rb
 // outputs (w_a and w_b are separate blocks).
-template <typename R, int NB>
+template <typename R, int NB, int KUT = 0>
 __device__ __forceinline__ void b_wstage_adj_mr(const MWAItem *items, int64_t nitems, int64_t bid) {
   using C = cplx_t<R>;
   using A = typename Mfma<R>::acc;
@@ -505,18 +506,18 @@ __device__ __forceinline__ void b_wstage_adj_mr(const MWAItem *items, int64_t ni
   // inverse orders pa, pb of the unit's index lists (ia, ib, pa, pb)
   aload.pja = ldg16(W.idx, 2 * (int64_t)c + rowc);
   aload.pjb = ldg16(W.idx, 3 * (int64_t)c + rowc);
-  tile_gemm<R, NB>(aload.Ta, 0, W.r0, c, ra + rb, (const C *)W.za, W.Np, W.jt, lane, ar, ai,
+  tile_gemm<R, NB, KUT>(aload.Ta, 0, W.r0, c, ra + rb, (const C *)W.za, W.Np, W.jt, lane, ar, ai,
                    nullptr, aload, (const C *)W.zb, ra);
   store_tile<R, NB>((C *)W.zin, W.r0, c, W.Np, W.jt, lane, (R)1, ar, ai);
 }
-template <typename R, int NB>
+template <typename R, int NB, int KUT = 0>
 __global__ __launch_bounds__(256) void k_wstage_adj_mr(const MWAItem *items, int64_t nitems) {
-  b_wstage_adj_mr<R, NB>(items, nitems, blockIdx.x);
+  b_wstage_adj_mr<R, NB, KUT>(items, nitems, blockIdx.x);
 }
 
 // Adjoint, leaf part: u_leaf = scale (D^H y_leaf + sum_l V_l^H z_l), rows
 // [r0, r0 + 16) of the leaf's cells, every level in a fixed order.
-template <typename R, int NB>
+template <typename R, int NB, int KUT = 0>
 __device__ __forceinline__ void b_vstage_adj_mr(const MVAItem *items, int64_t nitems, int64_t bid) {
   using C = cplx_t<R>;
   using A = typename Mfma<R>::acc;
@@ -535,7 +536,7 @@ __device__ __forceinline__ void b_vstage_adj_mr(const MVAItem *items, int64_t ni
   const int row = W.r0 + (lane & 15);
   const int rowc = row < sz ? row : 0;
   ConjTransA<R> dl{F + W.dense_off, sz};
-  tile_gemm<R, NB>(dl.M, 0, W.r0, sz, sz, (const C *)W.y, W.Np, W.jt, lane, ar, ai, nullptr, dl);
+  tile_gemm<R, NB, KUT>(dl.M, 0, W.r0, sz, sz, (const C *)W.y, W.Np, W.jt, lane, ar, ai, nullptr, dl);
   for (int l = 0; l < W.Lv; ++l) {
     const VDesc d = W.vd[l];
     AdjVA<R> vl;
@@ -543,14 +544,14 @@ __device__ __forceinline__ void b_vstage_adj_mr(const MVAItem *items, int64_t ni
     vl.safe = F;
     vl.r = d.r;
     vl.pj = ldg16(W.fidx + d.ioff, sz + rowc);   // the cell's position in the order
-    tile_gemm<R, NB>(vl.T, 0, W.r0, sz, d.r, z + d.zout * W.Np, W.Np, W.jt, lane, ar, ai,
+    tile_gemm<R, NB, KUT>(vl.T, 0, W.r0, sz, d.r, z + d.zout * W.Np, W.Np, W.jt, lane, ar, ai,
                      nullptr, vl);
   }
   store_tile<R, NB>((C *)W.u, W.r0, sz, W.Np, W.jt, lane, (R)W.scale, ar, ai);
 }
-template <typename R, int NB>
+template <typename R, int NB, int KUT = 0>
 __global__ __launch_bounds__(256) void k_vstage_adj_mr(const MVAItem *items, int64_t nitems) {
-  b_vstage_adj_mr<R, NB>(items, nitems, blockIdx.x);
+  b_vstage_adj_mr<R, NB, KUT>(items, nitems, blockIdx.x);
 }
 
 // s (natural order, column-major N_v x nrhs, leading dimension ld) ->
@@ -656,35 +657,41 @@ __global__ __launch_bounds__(256) void k_multi_persistent(const MPhase *phases, 
 }
 
 // ---------------------------------------------------------------------------
-template <typename R, int NB>
+template <typename R, int NB, int KUT>
 static void launch_stage_nb(const MStagePlan &sp, hipStream_t st) {
   if (sp.kind == 0 && sp.n)
-    hipLaunchKernelGGL((k_vstage_mr<R, NB>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_vstage_mr<R, NB, KUT>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
                        (const MVItem *)sp.items, sp.n);
   if (sp.kind == 1 && sp.n)
-    hipLaunchKernelGGL((k_wstage_mr<R, NB>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_wstage_mr<R, NB, KUT>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
                        (const MWItem *)sp.items, sp.n);
   if (sp.kind == 2 && sp.n)
-    hipLaunchKernelGGL((k_final_mr<R, NB>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_final_mr<R, NB, KUT>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
                        (const MFItem *)sp.items, sp.n);
   if (sp.kind == 3 && sp.n)
-    hipLaunchKernelGGL((k_final_adj_mr<R, NB>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_final_adj_mr<R, NB, KUT>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
                        (const MFAItem *)sp.items, sp.n);
   if (sp.kind == 4 && sp.n)
-    hipLaunchKernelGGL((k_wstage_adj_mr<R, NB>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_wstage_adj_mr<R, NB, KUT>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
                        (const MWAItem *)sp.items, sp.n);
   if (sp.kind == 5 && sp.n)
-    hipLaunchKernelGGL((k_vstage_adj_mr<R, NB>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_vstage_adj_mr<R, NB, KUT>), dim3((sp.n + 3) / 4), dim3(256), 0, st,
                        (const MVAItem *)sp.items, sp.n);
 }
 
 template <typename R>
 hipError_t launch_multi_stage(const MStagePlan &sp, hipStream_t st) {
-  switch (sp.nb) {
-    case 1: launch_stage_nb<R, 1>(sp, st); break;
-    case 2: launch_stage_nb<R, 2>(sp, st); break;
-    case 4: launch_stage_nb<R, 4>(sp, st); break;
-    case 8: launch_stage_nb<R, 8>(sp, st); break;
+  // (column-tile width, k-steps per chunk); ku = 0 is the width's default
+  switch (sp.nb * 16 + sp.ku) {
+    case 16 + 0: case 16 + 4: launch_stage_nb<R, 1, 4>(sp, st); break;
+    case 16 + 8: launch_stage_nb<R, 1, 8>(sp, st); break;
+    case 16 + 2: launch_stage_nb<R, 1, 2>(sp, st); break;
+    case 32 + 0: case 32 + 2: launch_stage_nb<R, 2, 2>(sp, st); break;
+    case 32 + 4: launch_stage_nb<R, 2, 4>(sp, st); break;
+    case 32 + 1: launch_stage_nb<R, 2, 1>(sp, st); break;
+    case 64 + 0: case 64 + 1: launch_stage_nb<R, 4, 1>(sp, st); break;
+    case 64 + 2: launch_stage_nb<R, 4, 2>(sp, st); break;
+    case 128 + 0: case 128 + 1: launch_stage_nb<R, 8, 1>(sp, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
