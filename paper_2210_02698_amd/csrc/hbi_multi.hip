@@ -14,6 +14,11 @@
 // Np = nrhs rounded up to 16.  Factor blocks keep their single-RHS
 // column-major layout, so every factor entry is loaded once per 16-row
 // tile and reused for all Np right-hand sides.
+//
+// Each stage is one launch (the host replays them from a HIP graph), or all
+// of them are phases of k_multi_persistent, one cooperative launch.  The
+// column-tile width NB and the k-steps per load chunk are template
+// parameters that the host tunes per batch.
 #include <type_traits>
 
 #include <hip/hip_cooperative_groups.h>
